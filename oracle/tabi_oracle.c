@@ -1,0 +1,894 @@
+/*
+ * TABI oracle: a plain CPU implementation of the packing method of
+ * "TABI: Tight and Balanced Interactive Atlas Packing" (Gu, Vining, Sheffer,
+ * Eurographics 2026).
+ *
+ * TEST INFRASTRUCTURE ONLY.  The GPU library never links, loads or calls this
+ * file; only the tests, the smoke check and the benchmark's CPU-baseline leg do.
+ *
+ * The method is a heuristic, so this file is the algorithm itself, written
+ * step by step in the paper's order:
+ *   chart AABB and 90-degree turn ............ Sec. 3.1, Sec. 4.3
+ *   local-AABB slices ......................... Sec. 4.1.1, App. A (local AABBs)
+ *   chart orientation (reflections) .......... Sec. 4.1.1, App. A (orientations)
+ *   approximate OBB over 8 directions ......... Sec. 4.1.1, App. A (OBBs)
+ *   sort by height ............................ Sec. 3.1, Sec. 4.3
+ *   per-texel TopEdge/BottomEdge (and the row-wise Left/Right analogue)
+ *                                              App. A (Parallel Pushing), Fig. pushing
+ *   horizontal compacting distance ............ Sec. 4.1.2, Alg. 2
+ *   interlock flags (CannotMoveAbove) ........ Sec. 4.1.3, App. A (Interlocking)
+ *   fold, push, correct, update, score ....... Alg. 2, Alg. 1, Alg. 3
+ *   knees: detection and location update ..... Sec. 4.2, App. A, Alg. 4
+ *   t_opt tail rows ........................... Sec. 4.4
+ *   scale search over k/64 .................... Sec. 3.1, Sec. 4.3, Sec. 5
+ *
+ * Where the paper leaves a choice open (rounding direction, ties, the exact
+ * tail rule, gutters, pairs beyond neighbours) the reading used is stated at
+ * the point of use.
+ */
+#include "tabi_oracle.h"
+
+#include <limits.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef __int128 i128;
+
+#define QS 16384  /* Q8 (1/256 texel) times the 64 scale steps: texel = k*u/16384 */
+
+/* floor(a/b) and ceil(a/b) for b != 0 */
+static int64_t fdiv64(int64_t a, int64_t b) {
+  int64_t q = a / b, r = a % b;
+  if (r != 0 && ((r < 0) != (b < 0))) q--;
+  return q;
+}
+static int64_t cdiv64(int64_t a, int64_t b) { return -fdiv64(-a, b); }
+static i128 fdiv128(i128 a, i128 b) {
+  i128 q = a / b, r = a % b;
+  if (r != 0 && ((r < 0) != (b < 0))) q--;
+  return q;
+}
+static i128 cdiv128(i128 a, i128 b) { return -fdiv128(-a, b); }
+static int64_t mini64(int64_t a, int64_t b) { return a < b ? a : b; }
+static int64_t maxi64(int64_t a, int64_t b) { return a > b ? a : b; }
+
+/* ------------------------------------------------------------------------ */
+/* Quality presets: number of local AABBs and t_opt (Sec. 5 ablations:
+ * K in {2,5,10}, t_opt in {5,2,1,0}%; the paper's default is K=10 with
+ * t_opt = 0% up to 10,000 charts and 1% above).                             */
+void orc_quality(int32_t quality, int32_t n, int32_t* K, int32_t* topt) {
+  if (quality == 0) { *K = 2; *topt = 5; }
+  else if (quality == 1) { *K = 5; *topt = 2; }
+  else { *K = 10; *topt = (n > 10000) ? 1 : 0; }
+}
+
+/* ------------------------------------------------------------------------ */
+/* The 8 box directions m*pi/16, m = 0..7 (App. A: eight evenly spaced
+ * rotations in [0, 7pi/16]), as integer vectors 2^14 (cos, sin) rounded.   */
+static void direction(int m, int64_t* C, int64_t* S) {
+  *C = llround(16384.0 * cos((double)m * M_PI / 16.0));
+  *S = llround(16384.0 * sin((double)m * M_PI / 16.0));
+}
+
+/* Range [lo, hi] of the value axis b over the part of the closed polygon
+ * whose slab axis a lies in the slab K*a in [j*E, (j+1)*E].  The extreme
+ * values over polygon-inside-slab lie on the boundary clipped to the slab:
+ * edge endpoints inside it, and crossings of edges with the two slab lines.
+ * Rounded outward to whole Q8 units.                                        */
+static void slice_range(const int64_t* A, const int64_t* B, int nv, int64_t E, int K, int j,
+                        int64_t* lo, int64_t* hi) {
+  int64_t L = (int64_t)j * E, R = (int64_t)(j + 1) * E;
+  int64_t l = INT64_MAX, h = INT64_MIN;
+  for (int i = 0; i < nv; ++i) {
+    int i2 = (i + 1) % nv;
+    int64_t a1 = (int64_t)K * A[i], a2 = (int64_t)K * A[i2];
+    int64_t b1 = B[i], b2 = B[i2];
+    if (L <= a1 && a1 <= R) { l = mini64(l, b1); h = maxi64(h, b1); }
+    for (int s = 0; s < 2; ++s) {
+      int64_t line = s ? R : L;
+      if ((a1 < line && line < a2) || (a2 < line && line < a1)) {
+        /* b at the crossing = b1 + (b2-b1)*(line-a1)/(a2-a1) */
+        int64_t num = b1 * (a2 - a1) + (b2 - b1) * (line - a1);
+        int64_t den = a2 - a1;
+        l = mini64(l, fdiv64(num, den));
+        h = maxi64(h, cdiv64(num, den));
+      }
+    }
+  }
+  *lo = l;
+  *hi = h;
+}
+
+int orc_prep_chart(const int32_t* xy, int32_t nv, int32_t K, orc_chart* ch) {
+  memset(ch, 0, sizeof(*ch));
+  ch->K = K;
+  if (nv < 3) return 0;
+  int64_t xmin = INT64_MAX, ymin = INT64_MAX, xmax = INT64_MIN, ymax = INT64_MIN;
+  for (int i = 0; i < nv; ++i) {
+    int64_t x = xy[2 * i], y = xy[2 * i + 1];
+    if (x <= -(1 << 22) || x >= (1 << 22) || y <= -(1 << 22) || y >= (1 << 22)) return 0;
+    xmin = mini64(xmin, x); xmax = maxi64(xmax, x);
+    ymin = mini64(ymin, y); ymax = maxi64(ymax, y);
+  }
+  int64_t w0 = xmax - xmin, h0 = ymax - ymin;
+  if (w0 == 0 || h0 == 0) return 0;
+  ch->xmin = xmin;
+  ch->ymin = ymin;
+
+  /* 90-degree turn so that the box is at least as tall as wide (Sec. 3.1).
+   * Clockwise in y-down coordinates: (u, v) -> (h0 - v, u).  No turn when
+   * the box is square. */
+  int64_t* u = (int64_t*)malloc(sizeof(int64_t) * nv);
+  int64_t* v = (int64_t*)malloc(sizeof(int64_t) * nv);
+  ch->rot = w0 > h0;
+  for (int i = 0; i < nv; ++i) {
+    int64_t u0 = xy[2 * i] - xmin, v0 = xy[2 * i + 1] - ymin;
+    if (ch->rot) { u[i] = h0 - v0; v[i] = u0; }
+    else { u[i] = u0; v[i] = v0; }
+  }
+  int64_t W = ch->rot ? h0 : w0, H = ch->rot ? w0 : h0;
+  ch->W = W;
+  ch->H = H;
+
+  /* twice the area (shoelace) */
+  i128 s = 0;
+  for (int i = 0; i < nv; ++i) {
+    int i2 = (i + 1) % nv;
+    s += (i128)u[i] * v[i2] - (i128)u[i2] * v[i];
+  }
+  ch->area2 = (int64_t)(s < 0 ? -s : s);
+
+  /* local AABBs: K equal slices along x (giving top/bottom bounds) and along
+   * y (giving left/right bounds) (Sec. 4.1.1, App. A) */
+  for (int j = 0; j < K; ++j) slice_range(u, v, nv, W, K, j, &ch->ylo[j], &ch->yhi[j]);
+  for (int j = 0; j < K; ++j) slice_range(v, u, nv, H, K, j, &ch->xlo[j], &ch->xhi[j]);
+
+  /* orientation (App. A, "Computing Chart Orientations").  Empty area above
+   * the top boundary vs below the bottom boundary: reflect vertically when
+   * the top one is larger. */
+  int64_t top_area = 0, bot_area = 0;
+  for (int j = 0; j < K; ++j) { top_area += ch->ylo[j]; bot_area += H - ch->yhi[j]; }
+  if (top_area > bot_area) {
+    ch->flipy = 1;
+    for (int j = 0; j < K; ++j) {
+      int64_t lo = H - ch->yhi[j], hi = H - ch->ylo[j];
+      ch->ylo[j] = lo; ch->yhi[j] = hi;
+    }
+    for (int j = 0; j < K / 2; ++j) {
+      int64_t t;
+      t = ch->xlo[j]; ch->xlo[j] = ch->xlo[K - 1 - j]; ch->xlo[K - 1 - j] = t;
+      t = ch->xhi[j]; ch->xhi[j] = ch->xhi[K - 1 - j]; ch->xhi[K - 1 - j] = t;
+    }
+  }
+  /* Left vs right empty area; reflect horizontally when left exceeds right by
+   * more than 10% of the AABB area (areas in units of H/K: 10*(L-R) > K*W).
+   * When they differ by at most that much, compare the bottom empty area left
+   * of the midline with the part right of it (a middle slice, for odd K, is
+   * shared equally and cancels). */
+  int64_t L = 0, R = 0;
+  for (int j = 0; j < K; ++j) { L += ch->xlo[j]; R += W - ch->xhi[j]; }
+  int64_t diff = L - R;
+  if (10 * diff > (int64_t)K * W) {
+    ch->flipx = 1;
+  } else if (10 * (diff < 0 ? -diff : diff) <= (int64_t)K * W) {
+    int half = K / 2;
+    int64_t bl = 0, br = 0;
+    for (int j = 0; j < half; ++j) bl += H - ch->yhi[j];
+    for (int j = K - half; j < K; ++j) br += H - ch->yhi[j];
+    if (bl > br) ch->flipx = 1;
+  }
+  if (ch->flipx) {
+    for (int j = 0; j < K / 2; ++j) {
+      int64_t t;
+      t = ch->ylo[j]; ch->ylo[j] = ch->ylo[K - 1 - j]; ch->ylo[K - 1 - j] = t;
+      t = ch->yhi[j]; ch->yhi[j] = ch->yhi[K - 1 - j]; ch->yhi[K - 1 - j] = t;
+    }
+    for (int j = 0; j < K; ++j) {
+      int64_t lo = W - ch->xhi[j], hi = W - ch->xlo[j];
+      ch->xlo[j] = lo; ch->xhi[j] = hi;
+    }
+  }
+
+  /* approximate OBB of the chart as it will be packed: the minimum-area box
+   * over the 8 directions (App. A), areas compared exactly; ties keep the
+   * smaller m.  An axis-aligned winner adds nothing to the AABB. */
+  for (int i = 0; i < nv; ++i) {
+    if (ch->flipx) u[i] = W - u[i];
+    if (ch->flipy) v[i] = H - v[i];
+  }
+  int best = -1;
+  i128 best_ext = 0, best_N = 1;
+  int64_t bC = 0, bS = 0, ba = 0, bb = 0, be = 0, bf = 0;
+  for (int m = 0; m < 8; ++m) {
+    int64_t C, S;
+    direction(m, &C, &S);
+    int64_t a = INT64_MAX, b = INT64_MIN, e = INT64_MAX, f = INT64_MIN;
+    for (int i = 0; i < nv; ++i) {
+      int64_t p = C * u[i] + S * v[i], q = -S * u[i] + C * v[i];
+      a = mini64(a, p); b = maxi64(b, p);
+      e = mini64(e, q); f = maxi64(f, q);
+    }
+    i128 ext = (i128)(b - a) * (i128)(f - e);
+    i128 N = (i128)C * C + (i128)S * S;
+    if (best < 0 || ext * best_N < best_ext * N) {
+      best = m; best_ext = ext; best_N = N;
+      bC = C; bS = S; ba = a; bb = b; be = e; bf = f;
+    }
+  }
+  ch->obb_m = best;
+  ch->obb = best != 0;
+  ch->C = bC; ch->S = bS; ch->a = ba; ch->b = bb; ch->e = be; ch->f = bf;
+  free(u);
+  free(v);
+  ch->valid = 1;
+  return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-texel profiles at scale k/64 (App. A, "Parallel Pushing Algorithm").
+ *
+ * Texel coverage: a chart covers texel (i, j) when the open unit square
+ * (i, i+1) x (j, j+1) meets the polygon interior; a chart then spans
+ * w = ceil(k W / 16384) columns and h = ceil(k H / 16384) rows.
+ *
+ * TopEdge(i) is the tightest of three lower bounds on the chart's v inside
+ * the open column (i, i+1): the x-slices overlapping it, the y-slices whose
+ * u-range reaches into it, and the OBB's top boundary over the column.  The
+ * paper takes the largest per texel; rounding is outward (floor for a top,
+ * ceil for a bottom) so that separation is never violated.  Left/Right per
+ * row are the same construction with the axes exchanged.                    */
+
+/* OBB boundary evaluations.  The box is a <= p <= b, e <= q <= f with
+ * p = C u + S v and q = -S u + C v (C, S > 0).  In scaled coordinates
+ * U = k u / 16384, V = k v / 16384 its top boundary is
+ *   top(U) = max( (k a - 16384 C U) / (16384 S), (k e + 16384 S U) / (16384 C) ),
+ * the max of a decreasing and an increasing line, so its minimum over a column
+ * is at one of the column's ends or at the box's top corner (p = a, q = e) if
+ * that lies inside.  Bottom, left and right boundaries are analogous. */
+
+/* value of a line (n0 + n1 * U) / den at U = num_u / den_u, floored or ceiled */
+static i128 line_at(i128 n0, i128 n1, i128 den, i128 num_u, i128 den_u, int ceil_) {
+  i128 num = n0 * den_u + n1 * num_u;
+  i128 d = den * den_u;
+  return ceil_ ? cdiv128(num, d) : fdiv128(num, d);
+}
+
+static void obb_column(const orc_chart* ch, int64_t k, int64_t i, int64_t* To, int64_t* Bo) {
+  i128 C = ch->C, S = ch->S, N = C * C + S * S, K = k;
+  /* column [i, ub], ub = min(i+1, kW/16384) as a rational num/den */
+  i128 ub_n, ub_d;
+  if ((i128)QS * (i + 1) <= K * ch->W) { ub_n = i + 1; ub_d = 1; }
+  else { ub_n = K * ch->W; ub_d = QS; }
+  /* top(U) = max( (k a - 16384 C U) / (16384 S), (k e + 16384 S U) / (16384 C) ) */
+  i128 t_i = line_at(K * ch->a, -(i128)QS * C, (i128)QS * S, i, 1, 0);
+  i128 t2 = line_at(K * ch->e, (i128)QS * S, (i128)QS * C, i, 1, 0);
+  if (t2 > t_i) t_i = t2;
+  i128 t_u = line_at(K * ch->a, -(i128)QS * C, (i128)QS * S, ub_n, ub_d, 0);
+  t2 = line_at(K * ch->e, (i128)QS * S, (i128)QS * C, ub_n, ub_d, 0);
+  if (t2 > t_u) t_u = t2;
+  i128 top = t_i < t_u ? t_i : t_u;
+  /* top corner (p = a, q = e): U = k (C a - S e) / (16384 N) */
+  i128 cu = K * (C * ch->a - S * ch->e);
+  if (cu * ub_d >= (i128)QS * N * i * ub_d && cu * ub_d <= (i128)QS * N * ub_n) {
+    i128 cv = fdiv128(K * (S * ch->a + C * ch->e), (i128)QS * N);
+    if (cv < top) top = cv;
+  }
+  /* bottom(U) = min( (k b - 16384 C U) / (16384 S), (k f + 16384 S U) / (16384 C) ) */
+  i128 b_i = line_at(K * ch->b, -(i128)QS * C, (i128)QS * S, i, 1, 1);
+  i128 b2 = line_at(K * ch->f, (i128)QS * S, (i128)QS * C, i, 1, 1);
+  if (b2 < b_i) b_i = b2;
+  i128 b_u = line_at(K * ch->b, -(i128)QS * C, (i128)QS * S, ub_n, ub_d, 1);
+  b2 = line_at(K * ch->f, (i128)QS * S, (i128)QS * C, ub_n, ub_d, 1);
+  if (b2 < b_u) b_u = b2;
+  i128 bot = b_i > b_u ? b_i : b_u;
+  /* bottom corner (p = b, q = f) */
+  cu = K * (C * ch->b - S * ch->f);
+  if (cu * ub_d >= (i128)QS * N * i * ub_d && cu * ub_d <= (i128)QS * N * ub_n) {
+    i128 cv = cdiv128(K * (S * ch->b + C * ch->f), (i128)QS * N);
+    if (cv > bot) bot = cv;
+  }
+  *To = (int64_t)top;
+  *Bo = (int64_t)bot;
+}
+
+static void obb_row(const orc_chart* ch, int64_t k, int64_t j, int64_t* Lo, int64_t* Ro) {
+  i128 C = ch->C, S = ch->S, N = C * C + S * S, K = k;
+  i128 vb_n, vb_d;
+  if ((i128)QS * (j + 1) <= K * ch->H) { vb_n = j + 1; vb_d = 1; }
+  else { vb_n = K * ch->H; vb_d = QS; }
+  /* left(V) = max( (k a - 16384 S V) / (16384 C), (16384 C V - k f) / (16384 S) ) */
+  i128 l_j = line_at(K * ch->a, -(i128)QS * S, (i128)QS * C, j, 1, 0);
+  i128 l2 = line_at(-K * ch->f, (i128)QS * C, (i128)QS * S, j, 1, 0);
+  if (l2 > l_j) l_j = l2;
+  i128 l_v = line_at(K * ch->a, -(i128)QS * S, (i128)QS * C, vb_n, vb_d, 0);
+  l2 = line_at(-K * ch->f, (i128)QS * C, (i128)QS * S, vb_n, vb_d, 0);
+  if (l2 > l_v) l_v = l2;
+  i128 left = l_j < l_v ? l_j : l_v;
+  /* left corner (p = a, q = f): V = k (S a + C f) / (16384 N), U = k (C a - S f) / (16384 N) */
+  i128 cv = K * (S * ch->a + C * ch->f);
+  if (cv * vb_d >= (i128)QS * N * j * vb_d && cv * vb_d <= (i128)QS * N * vb_n) {
+    i128 cu = fdiv128(K * (C * ch->a - S * ch->f), (i128)QS * N);
+    if (cu < left) left = cu;
+  }
+  /* right(V) = min( (k b - 16384 S V) / (16384 C), (16384 C V - k e) / (16384 S) ) */
+  i128 r_j = line_at(K * ch->b, -(i128)QS * S, (i128)QS * C, j, 1, 1);
+  i128 r2 = line_at(-K * ch->e, (i128)QS * C, (i128)QS * S, j, 1, 1);
+  if (r2 < r_j) r_j = r2;
+  i128 r_v = line_at(K * ch->b, -(i128)QS * S, (i128)QS * C, vb_n, vb_d, 1);
+  r2 = line_at(-K * ch->e, (i128)QS * C, (i128)QS * S, vb_n, vb_d, 1);
+  if (r2 < r_v) r_v = r2;
+  i128 right = r_j > r_v ? r_j : r_v;
+  /* right corner (p = b, q = e) */
+  cv = K * (S * ch->b + C * ch->e);
+  if (cv * vb_d >= (i128)QS * N * j * vb_d && cv * vb_d <= (i128)QS * N * vb_n) {
+    i128 cu = cdiv128(K * (C * ch->b - S * ch->e), (i128)QS * N);
+    if (cu > right) right = cu;
+  }
+  *Lo = (int64_t)left;
+  *Ro = (int64_t)right;
+}
+
+void orc_profiles(const orc_chart* ch, int32_t k, int32_t* w_out, int32_t* h_out,
+                  int32_t* top, int32_t* bot, int32_t* left, int32_t* right) {
+  const int64_t W = ch->W, H = ch->H, K = ch->K, kk = k;
+  int64_t w = cdiv64(kk * W, QS), h = cdiv64(kk * H, QS);
+  *w_out = (int32_t)w;
+  *h_out = (int32_t)h;
+  for (int64_t i = 0; i < w; ++i) {
+    int64_t T = INT64_MIN, B = INT64_MAX;
+    /* x-slices whose scaled closed range meets the open column (i, i+1) */
+    int64_t tx = INT64_MAX, bx = INT64_MIN;
+    for (int64_t j = 0; j < K; ++j) {
+      if (j * W * kk < QS * K * (i + 1) && (j + 1) * W * kk > QS * K * i) {
+        tx = mini64(tx, fdiv64(ch->ylo[j] * kk, QS));
+        bx = maxi64(bx, cdiv64(ch->yhi[j] * kk, QS));
+      }
+    }
+    /* y-slices whose u-range reaches into the open column */
+    int64_t ty = INT64_MAX, by = INT64_MIN;
+    for (int64_t j = 0; j < K; ++j) {
+      if (ch->xlo[j] * kk < QS * (i + 1) && ch->xhi[j] * kk > QS * i) {
+        ty = mini64(ty, fdiv64(j * H * kk, QS * K));
+        by = maxi64(by, cdiv64((j + 1) * H * kk, QS * K));
+      }
+    }
+    T = maxi64(tx, ty);
+    B = mini64(bx, by);
+    if (ch->obb) {
+      int64_t to, bo;
+      obb_column(ch, kk, i, &to, &bo);
+      T = maxi64(T, to);
+      B = mini64(B, bo);
+    }
+    top[i] = (int32_t)T;
+    bot[i] = (int32_t)B;
+  }
+  for (int64_t j = 0; j < h; ++j) {
+    int64_t ly = INT64_MAX, ry = INT64_MIN;
+    for (int64_t s = 0; s < K; ++s) {
+      if (s * H * kk < QS * K * (j + 1) && (s + 1) * H * kk > QS * K * j) {
+        ly = mini64(ly, fdiv64(ch->xlo[s] * kk, QS));
+        ry = maxi64(ry, cdiv64(ch->xhi[s] * kk, QS));
+      }
+    }
+    int64_t lx = INT64_MAX, rx = INT64_MIN;
+    for (int64_t s = 0; s < K; ++s) {
+      if (ch->ylo[s] * kk < QS * (j + 1) && ch->yhi[s] * kk > QS * j) {
+        lx = mini64(lx, fdiv64(s * W * kk, QS * K));
+        rx = maxi64(rx, cdiv64((s + 1) * W * kk, QS * K));
+      }
+    }
+    int64_t Lf = maxi64(ly, lx), Rf = mini64(ry, rx);
+    if (ch->obb) {
+      int64_t lo, ro;
+      obb_row(ch, kk, j, &lo, &ro);
+      Lf = maxi64(Lf, lo);
+      Rf = mini64(Rf, ro);
+    }
+    left[j] = (int32_t)Lf;
+    right[j] = (int32_t)Rf;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sorting (Sec. 3.1): height descending; ties by width descending, then by
+ * input index.                                                              */
+static const orc_chart* g_sort_charts;
+static int cmp_order(const void* pa, const void* pb) {
+  int ia = *(const int*)pa, ib = *(const int*)pb;
+  const orc_chart *a = &g_sort_charts[ia], *b = &g_sort_charts[ib];
+  if (a->H != b->H) return a->H > b->H ? -1 : 1;
+  if (a->W != b->W) return a->W > b->W ? -1 : 1;
+  return ia < ib ? -1 : (ia > ib ? 1 : 0);
+}
+
+/* Largest k in 1..64 whose scaled charts' total area fits the atlas:
+ * sum(area2) * k^2 <= 2^29 * W * H  (area2 in Q8^2; a pack is overlap free,
+ * so no larger k can succeed). 0 if even k = 1 is too big.                  */
+static int area_bound(const orc_chart* ch, int n, int Wa, int Ha) {
+  i128 s = 0;
+  for (int c = 0; c < n; ++c) s += ch[c].area2;
+  int khi = 0;
+  for (int k = 1; k <= 64; ++k)
+    if (s * k * k <= ((i128)1 << 29) * Wa * Ha) khi = k;
+  return khi;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-scale data: dilated profiles, compacting distances.                   */
+typedef struct {
+  int n, Wd, Hd, Wa, Ha, p, topt;
+  int32_t *wd, *hd, *h;
+  int64_t* Hq;                       /* unscaled Q8 heights, for knees */
+  int32_t **topd, **botd, **leftd, **rightd;
+  int32_t* cd;
+} kdata;
+
+static void free_kdata(kdata* D) {
+  for (int c = 0; c < D->n; ++c) {
+    free(D->topd[c]); free(D->botd[c]); free(D->leftd[c]); free(D->rightd[c]);
+  }
+  free(D->topd); free(D->botd); free(D->leftd); free(D->rightd);
+  free(D->wd); free(D->hd); free(D->h); free(D->Hq); free(D->cd);
+}
+
+/* Gutters: a chart's footprint is grown by [0,p] x [0,p] toward +x,+y and
+ * footprints may not share a texel.  Two grown footprints are disjoint exactly
+ * when at least p empty texels separate the charts; the grown atlas is
+ * (W+p) x (H+p), so charts may touch the atlas edges (Sec. 5: gutters between
+ * charts, none along the 4 atlas edges).                                     */
+static void build_kdata(kdata* D, const orc_chart* ch, const int* perm, int n, int k,
+                        int Wa, int Ha, int p, int topt) {
+  D->n = n; D->Wa = Wa; D->Ha = Ha; D->p = p; D->topt = topt;
+  D->Wd = Wa + p; D->Hd = Ha + p;
+  D->wd = calloc(n + 1, sizeof(int32_t)); D->hd = calloc(n + 1, sizeof(int32_t));
+  D->h = calloc(n + 1, sizeof(int32_t)); D->Hq = calloc(n + 1, sizeof(int64_t));
+  D->cd = calloc(n + 1, sizeof(int32_t));
+  D->topd = calloc(n + 1, sizeof(int32_t*)); D->botd = calloc(n + 1, sizeof(int32_t*));
+  D->leftd = calloc(n + 1, sizeof(int32_t*)); D->rightd = calloc(n + 1, sizeof(int32_t*));
+  for (int c = 0; c < n; ++c) {
+    const orc_chart* q = &ch[perm[c]];
+    int64_t w = cdiv64((int64_t)k * q->W, QS), h = cdiv64((int64_t)k * q->H, QS);
+    int32_t* top = malloc(sizeof(int32_t) * w);
+    int32_t* bot = malloc(sizeof(int32_t) * w);
+    int32_t* lft = malloc(sizeof(int32_t) * h);
+    int32_t* rgt = malloc(sizeof(int32_t) * h);
+    int32_t ww, hh;
+    orc_profiles(q, k, &ww, &hh, top, bot, lft, rgt);
+    int wd = ww + p, hd = hh + p;
+    D->wd[c] = wd; D->hd[c] = hd; D->h[c] = hh; D->Hq[c] = q->H;
+    D->topd[c] = malloc(sizeof(int32_t) * wd); D->botd[c] = malloc(sizeof(int32_t) * wd);
+    D->leftd[c] = malloc(sizeof(int32_t) * hd); D->rightd[c] = malloc(sizeof(int32_t) * hd);
+    for (int i = 0; i < wd; ++i) {
+      int lo = i - p < 0 ? 0 : i - p, hi = i < ww - 1 ? i : ww - 1;
+      int32_t t = INT32_MAX, b = INT32_MIN;
+      for (int s = lo; s <= hi; ++s) { if (top[s] < t) t = top[s]; if (bot[s] > b) b = bot[s]; }
+      D->topd[c][i] = t;
+      D->botd[c][i] = b + p;
+    }
+    for (int j = 0; j < hd; ++j) {
+      int lo = j - p < 0 ? 0 : j - p, hi = j < hh - 1 ? j : hh - 1;
+      int32_t l = INT32_MAX, r = INT32_MIN;
+      for (int s = lo; s <= hi; ++s) { if (lft[s] < l) l = lft[s]; if (rgt[s] > r) r = rgt[s]; }
+      D->leftd[c][j] = l;
+      D->rightd[c][j] = r + p;
+    }
+    free(top); free(bot); free(lft); free(rgt);
+  }
+  /* Horizontal compacting distance between sorted neighbours (Sec. 4.1.2):
+   * with both charts top-aligned, the largest leftward slide of the second
+   * that keeps every shared row apart, measured on the per-row tightest
+   * proxy bounds. */
+  D->cd[0] = 0;
+  for (int c = 1; c < n; ++c) {
+    int rows = D->hd[c - 1] < D->hd[c] ? D->hd[c - 1] : D->hd[c];
+    int32_t best = INT32_MAX;
+    for (int j = 0; j < rows; ++j) {
+      int32_t g = D->wd[c - 1] - D->rightd[c - 1][j] + D->leftd[c][j];
+      if (g < best) best = g;
+    }
+    D->cd[c] = best;
+  }
+}
+
+/* Interlock flags (Sec. 4.1.3, App. A "Detecting Interlocking Charts"),
+ * for A and a later chart B whose grown box starts d texels to the right of
+ * A's.  B "cannot move above A" when some row j >= 1 of B starts left of where
+ * A ends in some row above j (then raising B by 1..j texels may make them
+ * meet); symmetrically for A.  Flags are conservative: any upward shift that
+ * could bring the two proxies together sets the flag.  No shared column, no
+ * flag. */
+int orc_interlock(const int32_t* rightA, int32_t hdA, int32_t wdA,
+                  const int32_t* leftB, int32_t hdB, int32_t d) {
+  if (d >= wdA) return 0;
+  int flags = 0;
+  int32_t pm = rightA[0];
+  for (int j = 1; j < hdB; ++j) {
+    if (d + leftB[j] < pm) { flags |= 1; break; }
+    if (j < hdA && rightA[j] > pm) pm = rightA[j];
+  }
+  int32_t pn = leftB[0];
+  for (int j = 1; j < hdA; ++j) {
+    if (rightA[j] > d + pn) { flags |= 2; break; }
+    if (j < hdB && leftB[j] < pn) pn = leftB[j];
+  }
+  return flags;
+}
+
+/* CorrectYOffsets (Alg. 1): for each constrained pair (A, B, flags), while
+ * some chart sits above a chart it may not move above, move it down to that
+ * chart's offset (offsets grow downward).  Offsets only increase, so the loop
+ * ends at the least solution above the pushed offsets. */
+void orc_correct(int32_t m, const int32_t* pa, int32_t* y) {
+  int violation;
+  do {
+    violation = 0;
+    for (int q = 0; q < m; ++q) {
+      int A = pa[3 * q], B = pa[3 * q + 1], fl = pa[3 * q + 2];
+      if ((fl & 1) && y[B] < y[A]) { y[B] = y[A]; violation = 1; }
+      if ((fl & 2) && y[A] < y[B]) { y[A] = y[B]; violation = 1; }
+    }
+  } while (violation);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Row folding (Alg. 2): from the row's first chart, lay charts left to right;
+ * a chart is included while its grown box ends inside the folding width;
+ * the first that does not fit ends the row.  With horizontal compacting the
+ * next chart starts compactingDistance earlier.                             */
+static int fold_row(const kdata* D, int rs, int width, int hc, int32_t* X) {
+  int64_t x = 0;
+  int cnt = 0;
+  for (int c = rs; c < D->n; ++c) {
+    if (x + D->wd[c] > width) break;
+    X[cnt++] = (int32_t)x;
+    x = x + D->wd[c] - ((hc && c + 1 < D->n) ? D->cd[c + 1] : 0);
+  }
+  return cnt;
+}
+
+enum { LR = 0, RL = 1 };
+
+typedef struct {
+  int R0, R1, dir, hc, cnt, knee;
+  int32_t *X, *xa, *y, *Fp;
+  int64_t whole, region;
+} config;
+
+/* Push, correct, update and score one row configuration (Alg. 3 inner loop).
+ * Right-to-left rows place each chart mirrored inside its own box (so its
+ * profiles read backwards) at R1 - X - w'. */
+static void evaluate(const kdata* D, const int32_t* F, int rs, config* g) {
+  int cnt = g->cnt;
+  for (int t = 0; t < cnt; ++t) {
+    int c = rs + t;
+    g->xa[t] = g->dir == LR ? g->R0 + g->X[t] : g->R1 - g->X[t] - D->wd[c];
+  }
+  /* push: each chart rises until it touches the frontline */
+  for (int t = 0; t < cnt; ++t) {
+    int c = rs + t, wd = D->wd[c];
+    int32_t y = INT32_MIN;
+    for (int i = 0; i < wd; ++i) {
+      int32_t tp = g->dir == LR ? D->topd[c][i] : D->topd[c][wd - 1 - i];
+      int32_t v = F[g->xa[t] + i] - tp;
+      if (v > y) y = v;
+    }
+    g->y[t] = y;
+  }
+  /* correct (Alg. 1): charts that may not move above a compacted neighbour
+   * are moved down to it until no such pair is out of order.  Every pair
+   * whose grown boxes share columns is checked, not only direct neighbours:
+   * a narrow chart between two others can let the outer two share columns. */
+  if (g->hc) {
+    int cap = 16, m = 0;
+    int32_t* pa = malloc(sizeof(int32_t) * cap * 3);
+    for (int A = 0; A < cnt; ++A) {
+      for (int Bt = A + 1; Bt < cnt; ++Bt) {
+        int d = g->X[Bt] - g->X[A];
+        if (d >= D->wd[rs + A]) break;
+        int fl = orc_interlock(D->rightd[rs + A], D->hd[rs + A], D->wd[rs + A],
+                               D->leftd[rs + Bt], D->hd[rs + Bt], d);
+        if (!fl) continue;
+        if (m == cap) { cap *= 2; pa = realloc(pa, sizeof(int32_t) * cap * 3); }
+        pa[3 * m] = A; pa[3 * m + 1] = Bt; pa[3 * m + 2] = fl; ++m;
+      }
+    }
+    orc_correct(m, pa, g->y);
+    free(pa);
+  }
+  /* update a private copy of the frontline with the charts' bottoms */
+  memcpy(g->Fp, F, sizeof(int32_t) * D->Wd);
+  for (int t = 0; t < cnt; ++t) {
+    int c = rs + t, wd = D->wd[c];
+    for (int i = 0; i < wd; ++i) {
+      int32_t bt = g->dir == LR ? D->botd[c][i] : D->botd[c][wd - 1 - i];
+      int32_t v = g->y[t] + bt;
+      if (v > g->Fp[g->xa[t] + i]) g->Fp[g->xa[t] + i] = v;
+    }
+  }
+  /* scores: deepest frontline texel overall, and inside the folding region */
+  int64_t s = INT64_MIN, r = INT64_MIN;
+  for (int x = 0; x < D->Wd; ++x) {
+    if (g->Fp[x] > s) s = g->Fp[x];
+    if (x >= g->R0 && x < g->R1 && g->Fp[x] > r) r = g->Fp[x];
+  }
+  g->whole = s;
+  g->region = r;
+}
+
+typedef struct { int active, dir, left, right; } knee_t;
+
+/* Knee update (Alg. 4): the concavity wall moves to the nearest texel of the
+ * knee chart whose frontline is at least as deep as the frontline just past
+ * the wall.  A wall probe outside the atlas ends the knee.                  */
+static void update_knee(knee_t* kn, const int32_t* F, int Wd) {
+  if (kn->dir == LR) {
+    int probe = kn->right;
+    if (probe < 0 || probe >= Wd) { kn->active = 0; return; }
+    int32_t h0 = F[probe];
+    int nl = kn->left - 1;
+    for (int x = kn->left; x < kn->right; ++x)
+      if (F[x] >= h0 && x > nl) nl = x;
+    kn->right = nl + 1;
+  } else {
+    int probe = kn->left - 1;
+    if (probe < 0 || probe >= Wd) { kn->active = 0; return; }
+    int32_t h0 = F[probe];
+    int nl = kn->right;
+    for (int x = kn->left; x < kn->right; ++x)
+      if (F[x] >= h0 && x < nl) nl = x;
+    kn->left = nl;
+  }
+}
+
+/* Knee detection (Sec. 4.2, App. A): the largest drop in unscaled height
+ * between consecutive charts of the row that is at least 10% of the atlas
+ * height and at least 20% of the taller chart; ties go to the first pair.
+ * The knee is the taller chart's grown span in the atlas.                   */
+static knee_t find_knee(const kdata* D, int rs, const config* g) {
+  knee_t kn = {0, 0, 0, 0};
+  int64_t best = -1;
+  for (int t = 0; t + 1 < g->cnt; ++t) {
+    int c = rs + t;
+    int64_t dl = D->Hq[c] - D->Hq[c + 1];
+    if (10 * dl >= 256 * (int64_t)D->Ha && 5 * dl >= D->Hq[c] && dl > best) {
+      best = dl;
+      kn.active = 1;
+      kn.dir = g->dir;
+      kn.left = g->xa[t];
+      kn.right = g->xa[t] + D->wd[c];
+    }
+  }
+  return kn;
+}
+
+static void config_alloc(config* g, int n, int Wd) {
+  g->X = malloc(sizeof(int32_t) * (n + 1));
+  g->xa = malloc(sizeof(int32_t) * (n + 1));
+  g->y = malloc(sizeof(int32_t) * (n + 1));
+  g->Fp = malloc(sizeof(int32_t) * Wd);
+}
+static void config_free(config* g) { free(g->X); free(g->xa); free(g->y); free(g->Fp); }
+
+/* Full packing at one scale (Alg. 3).  Positions (sorted order) into xs, ys,
+ * mirror flags into mir.  Returns 1 when every chart is placed without the
+ * frontline passing the (grown) atlas height.                               */
+static int pack_scale(const kdata* D, int32_t* xs, int32_t* ys, uint8_t* mir, int* rows_out) {
+  int n = D->n, Wd = D->Wd, Hd = D->Hd;
+  int32_t* F = calloc(Wd, sizeof(int32_t));
+  int32_t* Xoff = malloc(sizeof(int32_t) * (n + 1));
+  int32_t* Xon = malloc(sizeof(int32_t) * (n + 1));
+  config full[2], kc[2];
+  for (int d = 0; d < 2; ++d) { config_alloc(&full[d], n, Wd); config_alloc(&kc[d], n, Wd); }
+  knee_t kn = {0, 0, 0, 0};
+  int tail = 0, trow = 0, rs = 0, rows = 0, ok = 1;
+  while (rs < n) {
+    if (kn.active) update_knee(&kn, F, Wd);
+    /* t_opt (Sec. 4.4): once no knee is pending and the row's tallest chart
+     * is shorter than t_opt of the atlas height, the remaining rows are full
+     * width, compacted, in the fixed 1 left-to-right : 2 right-to-left
+     * alternation, without per-row configuration search. */
+    if (!tail && !kn.active && 100 * (int64_t)D->h[rs] < (int64_t)D->topt * D->Ha) tail = 1;
+    config* ch;
+    int knee_used = 0;
+    if (tail) {
+      ch = &full[0];
+      ch->R0 = 0; ch->R1 = Wd; ch->hc = 1; ch->knee = 0;
+      ch->dir = (trow % 3 == 0) ? LR : RL;
+      ++trow;
+      ch->cnt = fold_row(D, rs, Wd, 1, ch->X);
+      if (ch->cnt == 0) { ok = 0; break; }
+      evaluate(D, F, rs, ch);
+    } else {
+      int coff = fold_row(D, rs, Wd, 0, Xoff);
+      int con = fold_row(D, rs, Wd, 1, Xon);
+      if (con == 0) { ok = 0; break; }   /* first chart wider than the atlas */
+      /* compaction is used when it fits more charts in the row */
+      int hc = con > coff;
+      for (int d = 0; d < 2; ++d) {
+        config* g = &full[d];
+        g->R0 = 0; g->R1 = Wd; g->dir = d; g->hc = hc; g->knee = 0;
+        g->cnt = hc ? con : coff;
+        memcpy(g->X, hc ? Xon : Xoff, sizeof(int32_t) * g->cnt);
+        evaluate(D, F, rs, g);
+      }
+      /* direction: smaller maximal frontline height, ties left-to-right */
+      ch = full[RL].whole < full[LR].whole ? &full[RL] : &full[LR];
+      if (kn.active) {
+        int R0 = kn.dir == LR ? kn.right : 0;
+        int R1 = kn.dir == LR ? Wd : kn.left;
+        int koff = fold_row(D, rs, R1 - R0, 0, Xoff);
+        int kon = fold_row(D, rs, R1 - R0, 1, Xon);
+        if (kon > 0) {
+          int khc = kon > koff;
+          for (int d = 0; d < 2; ++d) {
+            config* g = &kc[d];
+            g->R0 = R0; g->R1 = R1; g->dir = d; g->hc = khc; g->knee = 1;
+            g->cnt = khc ? kon : koff;
+            memcpy(g->X, khc ? Xon : Xoff, sizeof(int32_t) * g->cnt);
+            evaluate(D, F, rs, g);
+          }
+          /* inside the knee region the direction is judged on the region */
+          config* kb = kc[RL].region < kc[LR].region ? &kc[RL] : &kc[LR];
+          /* the knee fold wins only if it is strictly lower overall */
+          if (kb->whole < ch->whole) { ch = kb; knee_used = 1; }
+        }
+      }
+    }
+    /* commit */
+    memcpy(F, ch->Fp, sizeof(int32_t) * Wd);
+    for (int t = 0; t < ch->cnt; ++t) {
+      xs[rs + t] = ch->xa[t];
+      ys[rs + t] = ch->y[t];
+      mir[rs + t] = (uint8_t)(ch->dir == RL);
+    }
+    ++rows;
+    if (!tail && !knee_used) kn = find_knee(D, rs, ch);
+    if (ch->whole > Hd) { ok = 0; break; }
+    rs += ch->cnt;
+  }
+  for (int d = 0; d < 2; ++d) { config_free(&full[d]); config_free(&kc[d]); }
+  free(F); free(Xoff); free(Xon);
+  if (rows_out) *rows_out = rows;
+  return ok;
+}
+
+/* ------------------------------------------------------------------------ */
+static int check_args(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                      int32_t Ha, int32_t p, int32_t q) {
+  if (n < 0 || (n > 0 && (!xy || !offsets))) return -1;
+  if (Wa <= 0 || Ha <= 0 || p < 0 || Wa + p > 16384 || Ha + p > 16384) return -1;
+  if (q < 0 || q > 2) return -1;
+  if (n > 0 && offsets[0] != 0) return -1;
+  for (int c = 0; c < n; ++c)
+    if (offsets[c + 1] < offsets[c]) return -1;
+  return 0;
+}
+
+static int prep_all(const int32_t* xy, const int32_t* offsets, int n, int K, orc_chart* ch) {
+  int ok = 1;
+  for (int c = 0; c < n; ++c) {
+    int nv = offsets[c + 1] - offsets[c];
+    if (!orc_prep_chart(xy + 2 * (int64_t)offsets[c], nv, K, &ch[c])) ok = 0;
+  }
+  return ok;
+}
+
+static void sort_charts(const orc_chart* ch, int n, int* perm) {
+  for (int c = 0; c < n; ++c) perm[c] = c;
+  g_sort_charts = ch;
+  qsort(perm, n, sizeof(int), cmp_order);
+}
+
+int tabi_oracle_pack(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                     int32_t Ha, int32_t p, int32_t q, int32_t* out_xy, uint8_t* out_orient,
+                     float* out_scale, int32_t* out_k) {
+  if (check_args(xy, offsets, n, Wa, Ha, p, q)) return -1;
+  int K, topt;
+  orc_quality(q, n, &K, &topt);
+  if (n == 0) { *out_scale = 1.0f; if (out_k) *out_k = 64; return 0; }
+  orc_chart* ch = calloc(n, sizeof(orc_chart));
+  for (int c = 0; c < n; ++c) { out_xy[2 * c] = -1; out_xy[2 * c + 1] = -1; out_orient[c] = 0; }
+  if (!prep_all(xy, offsets, n, K, ch)) {
+    free(ch);
+    *out_scale = -1.0f;
+    if (out_k) *out_k = -1;
+    return 0;
+  }
+  int* perm = malloc(sizeof(int) * n);
+  sort_charts(ch, n, perm);
+  int khi = area_bound(ch, n, Wa, Ha);
+  int32_t* xs = malloc(sizeof(int32_t) * n);
+  int32_t* ys = malloc(sizeof(int32_t) * n);
+  uint8_t* mir = malloc(n);
+  int kstar = 0;
+  /* Scale search (Sec. 3.1, 4.3): the largest k/64 whose packing succeeds. */
+  for (int k = khi; k >= 1; --k) {
+    kdata D;
+    build_kdata(&D, ch, perm, n, k, Wa, Ha, p, topt);
+    int ok = pack_scale(&D, xs, ys, mir, NULL);
+    free_kdata(&D);
+    if (ok) { kstar = k; break; }
+  }
+  if (kstar > 0) {
+    for (int t = 0; t < n; ++t) {
+      int c = perm[t];
+      out_xy[2 * c] = xs[t];
+      out_xy[2 * c + 1] = ys[t];
+      out_orient[c] = (uint8_t)(ch[c].rot | (ch[c].flipx << 1) | (ch[c].flipy << 2) | (mir[t] << 3));
+    }
+  }
+  *out_scale = (float)kstar / 64.0f;
+  if (out_k) *out_k = kstar;
+  free(xs); free(ys); free(mir); free(perm); free(ch);
+  return 0;
+}
+
+int tabi_oracle_feasible(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                         int32_t Ha, int32_t p, int32_t q, int32_t k, int32_t* out_xy,
+                         uint8_t* out_orient, int32_t* rows_out) {
+  if (check_args(xy, offsets, n, Wa, Ha, p, q) || k < 1 || k > 64) return -1;
+  int K, topt;
+  orc_quality(q, n, &K, &topt);
+  if (n == 0) return 1;
+  orc_chart* ch = calloc(n, sizeof(orc_chart));
+  if (!prep_all(xy, offsets, n, K, ch)) { free(ch); return -1; }
+  int* perm = malloc(sizeof(int) * n);
+  sort_charts(ch, n, perm);
+  int32_t* xs = malloc(sizeof(int32_t) * n);
+  int32_t* ys = malloc(sizeof(int32_t) * n);
+  uint8_t* mir = calloc(n, 1);
+  for (int t = 0; t < n; ++t) { xs[t] = -1; ys[t] = -1; }
+  kdata D;
+  build_kdata(&D, ch, perm, n, k, Wa, Ha, p, topt);
+  int ok = pack_scale(&D, xs, ys, mir, rows_out);
+  free_kdata(&D);
+  for (int t = 0; t < n; ++t) {
+    int c = perm[t];
+    out_xy[2 * c] = xs[t];
+    out_xy[2 * c + 1] = ys[t];
+    out_orient[c] = (uint8_t)(ch[c].rot | (ch[c].flipx << 1) | (ch[c].flipy << 2) | (mir[t] << 3));
+  }
+  free(xs); free(ys); free(mir); free(perm); free(ch);
+  return ok;
+}
+
+int tabi_oracle_order(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                      int32_t Ha, int32_t q, int32_t* perm_out, int32_t* k_hi) {
+  if (check_args(xy, offsets, n, Wa, Ha, 0, q)) return -1;
+  int K, topt;
+  orc_quality(q, n, &K, &topt);
+  orc_chart* ch = calloc(n > 0 ? n : 1, sizeof(orc_chart));
+  if (!prep_all(xy, offsets, n, K, ch)) { free(ch); return -1; }
+  int* perm = malloc(sizeof(int) * (n > 0 ? n : 1));
+  sort_charts(ch, n, perm);
+  for (int t = 0; t < n; ++t) perm_out[t] = perm[t];
+  *k_hi = n ? area_bound(ch, n, Wa, Ha) : 64;
+  free(perm); free(ch);
+  return 0;
+}
+
+int tabi_oracle_pairs(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t p,
+                      int32_t q, int32_t k, int32_t* cd, uint8_t* flags) {
+  if (check_args(xy, offsets, n, 1, 1, p, q) || k < 1 || k > 64) return -1;
+  int K, topt;
+  orc_quality(q, n, &K, &topt);
+  if (n == 0) return 0;
+  orc_chart* ch = calloc(n, sizeof(orc_chart));
+  if (!prep_all(xy, offsets, n, K, ch)) { free(ch); return -1; }
+  int* perm = malloc(sizeof(int) * n);
+  sort_charts(ch, n, perm);
+  kdata D;
+  build_kdata(&D, ch, perm, n, k, 1, 1, p, topt);
+  cd[0] = 0;
+  flags[0] = 0;
+  for (int c = 1; c < n; ++c) {
+    cd[c] = D.cd[c];
+    flags[c] = (uint8_t)orc_interlock(D.rightd[c - 1], D.hd[c - 1], D.wd[c - 1], D.leftd[c],
+                                      D.hd[c], D.wd[c - 1] - D.cd[c]);
+  }
+  free_kdata(&D);
+  free(perm); free(ch);
+  return 0;
+}

@@ -1,0 +1,295 @@
+"""Seeded synthetic chart sets shaped like the paper's packing workloads.
+
+The paper packs UV-unwrapped and texture-space-shading chart sets into square
+power-of-two atlases with 1-pixel gutters (Sec. 5, "Experimental Setup"); those
+datasets are not redistributable, so every input here is synthetic: star-shaped
+polygons, concave L/U shapes and near-rectangular lightmap quads with
+log-normal areas, quantised to fixed point (1/256 texel, "Q8").
+
+This module holds no packing arithmetic.  It only draws inputs, and it is the
+one module shared by the oracle-side tests and the GPU-side tests / benchmark.
+"""
+from __future__ import annotations
+
+import dataclasses
+import functools
+import math
+
+import numpy as np
+
+Q8 = 256  # fixed-point units per texel for input vertex coordinates
+
+
+@dataclasses.dataclass(frozen=True)
+class AtlasInput:
+    """One packing problem: charts as a CSR of Q8 polygons plus the atlas."""
+
+    xy: np.ndarray        # int32[2V], interleaved x,y in Q8, y grows downward
+    offsets: np.ndarray   # int32[n+1] CSR vertex offsets
+    atlas_w: int
+    atlas_h: int
+    padding: int
+    quality: int
+
+    @property
+    def n(self) -> int:
+        return int(self.offsets.shape[0] - 1)
+
+    @property
+    def total_verts(self) -> int:
+        return int(self.offsets[-1])
+
+    def chart(self, c: int) -> np.ndarray:
+        a, b = int(self.offsets[c]), int(self.offsets[c + 1])
+        return self.xy[2 * a:2 * b].reshape(-1, 2)
+
+
+# Workload recipes.  'mix' entries: (shape, fraction, min_verts, max_verts, max_aspect)
+CONFIGS = {
+    # 64 stars into 512^2, padding 2
+    "stars64": dict(W=512, H=512, p=2, n=64, sigma=0.8, fill=0.6, q=2,
+                  mix=[("star", 1.0, 8, 24, 4.0)]),
+    # 2,000 charts into 2048^2, padding 2: 70% stars, 30% L/U, area 120% of atlas
+    "mixed2k": dict(W=2048, H=2048, p=2, n=2000, sigma=1.2, fill=1.2, q=2,
+                   mix=[("star", 0.7, 8, 64, 8.0), ("lu", 0.3, 6, 8, 8.0)]),
+    # 20,000 lightmap-style charts into 4096^2, padding 1
+    "lightmap20k": dict(W=4096, H=4096, p=1, n=20000, sigma=1.5, fill=1.5, q=2,
+                  mix=[("quad", 0.9, 4, 8, 16.0), ("star", 0.1, 16, 48, 4.0)]),
+}
+CONFIG_INDEX = {"stars64": 1, "mixed2k": 2, "lightmap20k": 3, "batch": 4, "serve": 5}
+
+
+def config_seed(name: str, instance: int) -> int:
+    """seed = 1000 * config number + instance (instance 0 is the timed input)."""
+    return 1000 * CONFIG_INDEX[name] + int(instance)
+
+
+# --------------------------------------------------------------------------
+# exact integer validity test of a quantised polygon
+# --------------------------------------------------------------------------
+def _orient(ax, ay, bx, by, cx, cy):
+    return np.sign((bx - ax) * (cy - ay) - (by - ay) * (cx - ax))
+
+
+def polygon_is_simple(P: np.ndarray) -> bool:
+    """True iff the closed integer polygon P (m x 2) has >= 3 distinct
+    consecutive vertices, no zero-length edge and no two edges that touch
+    except consecutive edges at their shared vertex (and those do not fold
+    back onto each other)."""
+    P = np.asarray(P, dtype=np.int64)
+    m = P.shape[0]
+    if m < 3:
+        return False
+    Q = np.roll(P, -1, axis=0)
+    if np.any(np.all(P == Q, axis=1)):
+        return False
+    ax, ay = P[:, 0][:, None], P[:, 1][:, None]
+    bx, by = Q[:, 0][:, None], Q[:, 1][:, None]
+    cx, cy = P[:, 0][None, :], P[:, 1][None, :]
+    dx, dy = Q[:, 0][None, :], Q[:, 1][None, :]
+    d1 = _orient(ax, ay, bx, by, cx, cy)
+    d2 = _orient(ax, ay, bx, by, dx, dy)
+    d3 = _orient(cx, cy, dx, dy, ax, ay)
+    d4 = _orient(cx, cy, dx, dy, bx, by)
+    proper = (d1 * d2 < 0) & (d3 * d4 < 0)
+
+    def on_seg(px, py, qx, qy, rx, ry):  # r on segment pq given collinear
+        return ((np.minimum(px, qx) <= rx) & (rx <= np.maximum(px, qx)) &
+                (np.minimum(py, qy) <= ry) & (ry <= np.maximum(py, qy)))
+
+    touch = ((d1 == 0) & on_seg(ax, ay, bx, by, cx, cy)) | \
+            ((d2 == 0) & on_seg(ax, ay, bx, by, dx, dy)) | \
+            ((d3 == 0) & on_seg(cx, cy, dx, dy, ax, ay)) | \
+            ((d4 == 0) & on_seg(cx, cy, dx, dy, bx, by))
+    hit = proper | touch
+    idx = np.arange(m)
+    same = idx[:, None] == idx[None, :]
+    nxt = (idx[:, None] + 1) % m == idx[None, :]
+    prv = (idx[None, :] + 1) % m == idx[:, None]
+    bad = hit & ~same & ~nxt & ~prv
+    if np.any(bad):
+        return False
+    # consecutive edges must not fold back (collinear with opposite direction)
+    R = np.roll(P, -2, axis=0)
+    e1 = Q - P
+    e2 = R - Q
+    cross = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]
+    dot = e1[:, 0] * e2[:, 0] + e1[:, 1] * e2[:, 1]
+    if np.any((cross == 0) & (dot < 0)):
+        return False
+    if m == 3 and np.all(cross == 0):
+        return False
+    return True
+
+
+def _shoelace(P: np.ndarray) -> float:
+    x, y = P[:, 0], P[:, 1]
+    return 0.5 * abs(float(np.dot(x, np.roll(y, -1)) - np.dot(np.roll(x, -1), y)))
+
+
+# --------------------------------------------------------------------------
+# shape primitives (float, unit-ish size; scaled to the target area later)
+# --------------------------------------------------------------------------
+def _rot(P, phi):
+    c, s = math.cos(phi), math.sin(phi)
+    return P @ np.array([[c, s], [-s, c]])
+
+
+def _star(rng, m, amax):
+    ang = 2.0 * np.pi * (np.arange(m) + rng.uniform(-0.3, 0.3, m)) / m
+    ang.sort()
+    r = 1.0 + rng.uniform(-0.4, 0.4, m)
+    P = np.stack([r * np.cos(ang), r * np.sin(ang)], axis=1)
+    a = rng.uniform(1.0, amax)
+    P[:, 0] *= math.sqrt(a)
+    P[:, 1] /= math.sqrt(a)
+    return _rot(P, rng.uniform(0.0, np.pi))
+
+
+def _lu(rng, amax):
+    a = rng.uniform(1.0, amax)
+    w, h = math.sqrt(a), 1.0 / math.sqrt(a)
+    fx, fy = rng.uniform(0.3, 0.7, 2)
+    if rng.uniform() < 0.5:   # L: rectangle minus a corner block
+        P = np.array([[0, 0], [w, 0], [w, h * fy], [w * fx, h * fy], [w * fx, h], [0, h]], float)
+    else:                     # U: rectangle minus a centred notch
+        nw = w * fx
+        x0 = 0.5 * (w - nw)
+        P = np.array([[0, 0], [x0, 0], [x0, h * fy], [x0 + nw, h * fy], [x0 + nw, 0],
+                      [w, 0], [w, h], [0, h]], float)
+    t = rng.integers(0, 4)
+    P = _rot(P, t * np.pi / 2)
+    if rng.uniform() < 0.5:
+        P[:, 0] = -P[:, 0]
+        P = P[::-1].copy()
+    if rng.uniform() < 0.5:
+        P = _rot(P, rng.uniform(0.0, np.pi))
+    return P
+
+
+def _quad(rng, mv, amax):
+    a = rng.uniform(1.0, amax)
+    w, h = math.sqrt(a), 1.0 / math.sqrt(a)
+    short = min(w, h)
+    corners = np.array([[0, 0], [w, 0], [w, h], [0, h]], float)
+    corners += rng.uniform(-0.05, 0.05, corners.shape) * short
+    extra = int(rng.integers(0, mv - 4 + 1))
+    pts = []
+    per_edge = np.zeros(4, int)
+    for _ in range(extra):
+        per_edge[rng.integers(0, 4)] += 1
+    for e in range(4):
+        p0, p1 = corners[e], corners[(e + 1) % 4]
+        pts.append(p0)
+        if per_edge[e]:
+            ts = np.sort(rng.uniform(0.15, 0.85, per_edge[e]))
+            d = p1 - p0
+            nrm = np.array([-d[1], d[0]]) / (np.hypot(*d) + 1e-30)
+            for t in ts:
+                pts.append(p0 + t * d + nrm * rng.uniform(-0.02, 0.02) * short)
+    P = np.array(pts)
+    return _rot(P, rng.uniform(-np.pi / 18, np.pi / 18))
+
+
+def _draw_shape(rng, kind, vmin, vmax, amax):
+    if kind == "star":
+        return _star(rng, int(rng.integers(vmin, vmax + 1)), amax)
+    if kind == "lu":
+        return _lu(rng, amax)
+    if kind == "quad":
+        return _quad(rng, vmax, amax)
+    raise ValueError(kind)
+
+
+def _quantise(P_float, area_tex, rng, place_w, place_h):
+    """Scale a float shape to area_tex texel^2, place it at a random spot and
+    round to Q8.  Returns None if the result is degenerate or not simple."""
+    A = _shoelace(P_float)
+    if A <= 0:
+        return None
+    P = P_float * math.sqrt(area_tex / A)
+    P -= P.min(axis=0)
+    off = np.array([rng.uniform(0, place_w), rng.uniform(0, place_h)])
+    Q = np.rint((P + off) * Q8).astype(np.int64)
+    ext = Q.max(axis=0) - Q.min(axis=0)
+    if ext.min() < 4 or np.abs(Q).max() >= (1 << 21):
+        return None
+    if not polygon_is_simple(Q):
+        return None
+    return Q
+
+
+def generate_charts(n, W, H, sigma, fill, mix, seed):
+    """n charts with log-normal areas summing to fill*W*H texel^2."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    areas = np.exp(sigma * rng.standard_normal(n))
+    areas *= fill * W * H / areas.sum()
+    fracs = np.array([m[1] for m in mix], float)
+    kinds = rng.choice(len(mix), size=n, p=fracs / fracs.sum())
+    polys = []
+    for i in range(n):
+        kind, _, vmin, vmax, amax = mix[kinds[i]]
+        for _attempt in range(64):
+            Q = _quantise(_draw_shape(rng, kind, vmin, vmax, amax), areas[i], rng, W, H)
+            if Q is not None:
+                break
+        else:  # pragma: no cover - vanishingly rare
+            raise RuntimeError("could not draw a valid chart")
+        polys.append(Q)
+    return polys
+
+
+def pack_csr(polys):
+    offs = np.zeros(len(polys) + 1, np.int32)
+    offs[1:] = np.cumsum([p.shape[0] for p in polys])
+    xy = np.concatenate([p.reshape(-1) for p in polys]).astype(np.int32) if polys \
+        else np.zeros(0, np.int32)
+    return xy, offs
+
+
+@functools.lru_cache(maxsize=64)
+def make_input(name: str, instance: int = 0, quality: int | None = None,
+               n: int | None = None) -> AtlasInput:
+    """A named workload ('small', 'medium', 'large'); n overrides the chart
+    count (same recipe) for reduced-size parity cases."""
+    cfg = CONFIGS[name]
+    nn = cfg["n"] if n is None else int(n)
+    seed = config_seed(name, instance) + (0 if n is None else 7919 * nn)
+    polys = generate_charts(nn, cfg["W"], cfg["H"], cfg["sigma"], cfg["fill"] * nn / cfg["n"]
+                            if n is not None else cfg["fill"], cfg["mix"], seed)
+    xy, offs = pack_csr(polys)
+    return AtlasInput(xy, offs, cfg["W"], cfg["H"], cfg["p"],
+                      cfg["q"] if quality is None else int(quality))
+
+
+def make_custom(n, W, H, p, q, sigma, fill, mix, seed) -> AtlasInput:
+    polys = generate_charts(n, W, H, sigma, fill, mix, seed)
+    xy, offs = pack_csr(polys)
+    return AtlasInput(xy, offs, W, H, p, q)
+
+
+def make_batch(count: int = 256, seed: int = 4000, nmin: int = 50, nmax: int = 5000):
+    """Independent atlases with side drawn from {512,1024,2048} and chart counts
+    uniform in [nmin, nmax], each drawn with the 2,000-chart recipe (70% stars,
+    30% L/U, sigma 1.2, area 120% of the atlas)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sides = rng.choice([512, 1024, 2048], size=count)
+    ns = rng.integers(nmin, nmax + 1, size=count)
+    mix = CONFIGS["mixed2k"]["mix"]
+    out = []
+    for a in range(count):
+        out.append(make_custom(int(ns[a]), int(sides[a]), int(sides[a]), 2, 2, 1.2, 1.2, mix,
+                               seed * 1000 + a))
+    return out
+
+
+def rect_input(n, a_q8, b_q8, W, H, p, q=2, seed=0, jitter_xy=True) -> AtlasInput:
+    """n identical axis-aligned a x b rectangles (Q8 sides), at random offsets."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    polys = []
+    for _ in range(n):
+        ox, oy = (rng.integers(0, 1 << 18, 2) if jitter_xy else (0, 0))
+        polys.append(np.array([[ox, oy], [ox + a_q8, oy], [ox + a_q8, oy + b_q8],
+                               [ox, oy + b_q8]], np.int64))
+    xy, offs = pack_csr(polys)
+    return AtlasInput(xy, offs, W, H, p, q)

@@ -1,0 +1,577 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+The oracle implements a heuristic, so its choices (which row configuration
+wins, where knees fall) cannot be pinned by a closed form; what can be pinned
+is checked here, each by code independent of the oracle:
+
+* safety: brute-force rasterised layouts have no overlapping grown footprints
+  and stay inside the atlas (Sec. 5 "Robustness": overlap free, gutters kept);
+* proxy soundness: every covered texel lies inside the per-texel profiles,
+  and exact rectangles give exact profiles (App. A, "Parallel Pushing");
+* local-AABB slices equal exact rational clipping, rounded outward (Sec. 4.1.1);
+* the OBB contains the chart and is the smallest of the 8 boxes (App. A);
+* compacting distance = first collision of sliding proxy footprints minus one
+  (Sec. 4.1.2) and real rasters never collide at that distance;
+* interlock flags are set whenever an upward shift makes proxies meet (App. A);
+* the correction loop reaches the least fixpoint (Alg. 1);
+* closed forms for a single chart and for identical rectangles (Sec. 3.1 search);
+* knee thresholds at +-1 Q8 unit (App. A "Knee Detection Parameters");
+* L2 stretch of the output transform is exactly 64/k (Sec. 5);
+* early-exit search equals the full 64-scale sweep (Sec. 4.3);
+* translation invariance and bitwise determinism.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2602_07782_amd import synth
+
+T = 16384
+
+
+# ---------------------------------------------------------------------------
+# helpers (independent of the oracle)
+# ---------------------------------------------------------------------------
+def final_frame(P, rec):
+    """Vertices of a chart in its final local frame, from the oracle's turn /
+    reflection bits (the output contract)."""
+    P = np.asarray(P, np.int64)
+    u = P[:, 0] - P[:, 0].min()
+    v = P[:, 1] - P[:, 1].min()
+    w0, h0 = int(u.max()), int(v.max())
+    if rec.rot:
+        u, v = h0 - v, u
+        W, H = h0, w0
+    else:
+        W, H = w0, h0
+    if rec.flipx:
+        u = W - u
+    if rec.flipy:
+        v = H - v
+    return u, v, W, H
+
+
+def small_input(seed, n=None, W=None, p=None, q=None):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 24)) if n is None else n
+    W = int(rng.choice([32, 64, 96, 128])) if W is None else W
+    p = int(rng.integers(0, 4)) if p is None else p
+    q = int(rng.integers(0, 3)) if q is None else q
+    mix = [("star", 0.5, 5, 16, 6.0), ("lu", 0.3, 6, 8, 6.0), ("quad", 0.2, 4, 8, 10.0)]
+    return synth.make_custom(n, W, W, p, q, float(rng.uniform(0.3, 1.5)),
+                             float(rng.uniform(0.2, 1.2)), mix, 90000 + seed)
+
+
+def clip_slab(poly, axis, lo, hi):
+    """Sutherland-Hodgman clip of a polygon (list of Fraction pairs) to
+    lo <= coord[axis] <= hi."""
+    def clip(pts, keep, inter):
+        out = []
+        m = len(pts)
+        for i in range(m):
+            a, b = pts[i], pts[(i + 1) % m]
+            ka, kb = keep(a), keep(b)
+            if ka:
+                out.append(a)
+            if ka != kb:
+                out.append(inter(a, b))
+        return out
+
+    def inter_at(c):
+        def f(a, b):
+            t = (c - a[axis]) / (b[axis] - a[axis])
+            return (a[0] + t * (b[0] - a[0]), a[1] + t * (b[1] - a[1]))
+        return f
+    pts = clip(poly, lambda P: P[axis] >= lo, inter_at(lo))
+    pts = clip(pts, lambda P: P[axis] <= hi, inter_at(hi))
+    return pts
+
+
+def dilate(mask, p):
+    h, w = mask.shape
+    out = np.zeros((h + p, w + p), bool)
+    for dj in range(p + 1):
+        for di in range(p + 1):
+            out[dj:dj + h, di:di + w] |= mask.astype(bool)
+    return out
+
+
+def row_footprint(left, right, w):
+    """Mask filled between the row profiles."""
+    h = len(left)
+    m = np.zeros((h, w), bool)
+    for j in range(h):
+        m[j, left[j]:right[j]] = True
+    return m
+
+
+def hulls(mask):
+    L, R = [], []
+    for j in range(mask.shape[0]):
+        nz = np.nonzero(mask[j])[0]
+        L.append(int(nz.min()))
+        R.append(int(nz.max()) + 1)
+    return np.array(L), np.array(R)
+
+
+def chart_raster(chk, u, v, k, w, h):
+    mask, outside = chk.raster(k * u, k * v, 0, 0, w, h)
+    assert outside == 0
+    return mask.astype(bool)
+
+
+# ---------------------------------------------------------------------------
+# P1: safety of whole layouts
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(60))
+def test_small_random_layouts_are_safe(orc, chk, seed):
+    inp = small_input(seed)
+    xy, ori, sc, k = orc.pack(inp)
+    assert k >= 1 and sc == k / 64
+    st = chk.check_layout(inp, xy, ori, k)
+    assert st["overlap"] == 0 and st["outside"] == 0 and st["empty"] == 0, st
+
+
+@pytest.mark.parametrize("inst", [0, 1, 2])
+def test_stars64_layouts_are_safe(orc, chk, inst):
+    inp = synth.make_input("stars64", inst)
+    xy, ori, sc, k = orc.pack(inp)
+    st = chk.check_layout(inp, xy, ori, k)
+    assert st["overlap"] == 0 and st["outside"] == 0, st
+
+
+@pytest.mark.parametrize("q", [0, 2])
+def test_mixed2k_layout_is_safe(orc, chk, q):
+    base = synth.make_input("mixed2k", 0)
+    inp = synth.AtlasInput(base.xy, base.offsets, base.atlas_w, base.atlas_h, base.padding, q)
+    xy, ori, sc, k = orc.pack(inp)
+    assert 1 <= k <= 58
+    st = chk.check_layout(inp, xy, ori, k)
+    assert st["overlap"] == 0 and st["outside"] == 0 and st["empty"] == 0, st
+
+
+@pytest.mark.slow
+def test_lightmap20k_layout_is_safe(orc, chk):
+    inp = synth.make_input("lightmap20k", 0)
+    xy, ori, sc, k = orc.pack(inp)
+    st = chk.check_layout(inp, xy, ori, k)
+    assert st["overlap"] == 0 and st["outside"] == 0 and st["empty"] == 0, st
+
+
+def test_infeasible_scales_place_safely_too(orc, chk):
+    """Partial layouts of failing scales are still overlap free (every row is
+    committed with the same rules); only the height bound is exceeded."""
+    inp = synth.make_input("stars64", 3)
+    _, _, _, kstar = orc.pack(inp)
+    for k in range(kstar + 1, min(64, kstar + 4) + 1):
+        ok, xy, ori, rows = orc.feasible(inp, k)
+        placed = xy[:, 0] >= 0
+        sub = synth.AtlasInput(*synth.pack_csr([inp.chart(c) for c in np.nonzero(placed)[0]]),
+                               inp.atlas_w, 10 * inp.atlas_h, inp.padding, inp.quality)
+        st = chk.check_layout(sub, xy[placed], ori[placed], k)
+        assert st["overlap"] == 0, (k, st)
+
+
+# ---------------------------------------------------------------------------
+# P2: per-texel profiles bound the rasterised chart
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(40))
+def test_profiles_contain_raster(orc, chk, seed):
+    rng = np.random.default_rng(seed)
+    inp = small_input(1000 + seed, n=6)
+    K = [2, 5, 10][seed % 3]
+    for c in range(inp.n):
+        P = inp.chart(c)
+        rec = orc.prep_chart(P, K)
+        assert rec.valid
+        u, v, W, H = final_frame(P, rec)
+        assert (W, H) == (rec.W, rec.H) and H >= W
+        for k in rng.integers(1, 65, 3):
+            k = int(k)
+            top, bot, left, right = orc.profiles(rec, k)
+            w, h = len(top), len(left)
+            assert w == -(-k * W // T) and h == -(-k * H // T)
+            m = chart_raster(chk, u, v, k, w, h)
+            assert np.all(top < bot) and np.all(left < right)
+            assert np.all(top >= 0) and np.all(bot <= h) and np.all(left >= 0) and np.all(right <= w)
+            jj, ii = np.nonzero(m)
+            assert np.all(top[ii] <= jj) and np.all(jj < bot[ii])
+            assert np.all(left[jj] <= ii) and np.all(ii < right[jj])
+            # every column and row of the box is covered somewhere
+            assert m.any(axis=0).all() and m.any(axis=1).all()
+
+
+@pytest.mark.parametrize("a,b,k", [(256 * 5, 256 * 9, 64), (1000, 2000, 64), (777, 1531, 17),
+                                   (256 * 7, 256 * 7, 32), (300, 4000, 5)])
+def test_rectangle_profiles_are_exact(orc, chk, a, b, k):
+    P = np.array([[10, 20], [10 + a, 20], [10 + a, 20 + b], [10, 20 + b]])
+    for K in (2, 5, 10):
+        rec = orc.prep_chart(P, K)
+        assert rec.obb == 0  # axis-aligned rectangle: the AABB is the best box
+        top, bot, left, right = orc.profiles(rec, k)
+        u, v, W, H = final_frame(P, rec)
+        m = chart_raster(chk, u, v, k, len(top), len(left))
+        assert m.all()
+        assert np.all(top == 0) and np.all(bot == len(left))
+        assert np.all(left == 0) and np.all(right == len(top))
+
+
+# ---------------------------------------------------------------------------
+# P3: local-AABB slices = exact clipping rounded outward
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(25))
+def test_slices_equal_exact_clipping(orc, seed):
+    inp = small_input(2000 + seed, n=5)
+    K = [2, 5, 10][seed % 3]
+    for c in range(inp.n):
+        P = inp.chart(c)
+        rec = orc.prep_chart(P, K)
+        u, v, W, H = final_frame(P, rec)
+        poly = [(Fraction(int(a)), Fraction(int(b))) for a, b in zip(u, v)]
+        for j in range(K):
+            cl = clip_slab(poly, 0, Fraction(j * W, K), Fraction((j + 1) * W, K))
+            vs = [pt[1] for pt in cl]
+            assert rec.ylo[j] == math.floor(min(vs)) and rec.yhi[j] == math.ceil(max(vs))
+            cl = clip_slab(poly, 1, Fraction(j * H, K), Fraction((j + 1) * H, K))
+            us = [pt[0] for pt in cl]
+            assert rec.xlo[j] == math.floor(min(us)) and rec.xhi[j] == math.ceil(max(us))
+
+
+# ---------------------------------------------------------------------------
+# P4: OBB contains the chart and is the smallest candidate
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(20))
+def test_obb_contains_and_is_minimal(orc, seed):
+    inp = small_input(3000 + seed, n=8)
+    for c in range(inp.n):
+        P = inp.chart(c)
+        rec = orc.prep_chart(P, 10)
+        u, v, W, H = final_frame(P, rec)
+        m = rec.obb_m
+        # the direction is (cos, sin) of m*pi/16 to 2^-14
+        assert abs(rec.C / T - math.cos(m * math.pi / 16)) < 1e-4
+        assert abs(rec.S / T - math.sin(m * math.pi / 16)) < 1e-4
+        C, S = int(rec.C), int(rec.S)
+        pp = C * u + S * v
+        qq = -S * u + C * v
+        assert pp.min() == rec.a and pp.max() == rec.b and qq.min() == rec.e and qq.max() == rec.f
+        best = Fraction((rec.b - rec.a) * (rec.f - rec.e), C * C + S * S)
+        for mm in range(8):
+            Cm = round(T * math.cos(mm * math.pi / 16))
+            Sm = round(T * math.sin(mm * math.pi / 16))
+            p2 = Cm * u + Sm * v
+            q2 = -Sm * u + Cm * v
+            area = Fraction(int(p2.max() - p2.min()) * int(q2.max() - q2.min()), Cm * Cm + Sm * Sm)
+            assert best <= area
+        assert rec.obb == (m != 0)
+
+
+# ---------------------------------------------------------------------------
+# P5 / P6: compaction distance and interlock flags against sliding footprints
+# ---------------------------------------------------------------------------
+def _pair_data(orc, inp, K, k):
+    perm, _ = orc.order(inp)
+    cd, fl = orc.pairs(inp, k)
+    recs = [orc.prep_chart(inp.chart(c), K) for c in range(inp.n)]
+    return perm, cd, fl, recs
+
+
+@pytest.mark.parametrize("seed", range(15))
+def test_compaction_distance_is_first_collision_minus_one(orc, chk, seed):
+    inp = small_input(4000 + seed, n=10)
+    K, _ = orc.quality(inp.quality, inp.n)
+    p = inp.padding
+    rng = np.random.default_rng(seed)
+    for k in (int(x) for x in rng.integers(8, 65, 2)):
+        perm, cd, fl, recs = _pair_data(orc, inp, K, k)
+        for t in range(1, inp.n):
+            A, B = recs[perm[t - 1]], recs[perm[t]]
+            tA, bA, lA, rA = orc.profiles(A, k)
+            tB, bB, lB, rB = orc.profiles(B, k)
+            fa = dilate(row_footprint(lA, rA, len(tA)), p)
+            fb = dilate(row_footprint(lB, rB, len(tB)), p)
+            wdA = fa.shape[1]
+            rows = min(fa.shape[0], fb.shape[0])
+
+            def collide(shift):  # B's box starts at wdA - shift
+                x = wdA - shift
+                for j in range(rows):
+                    a = np.nonzero(fa[j])[0]
+                    b = np.nonzero(fb[j])[0] + x
+                    if np.intersect1d(a, b).size:
+                        return True
+                return False
+            c = int(cd[t])
+            assert 0 <= c < wdA
+            assert not collide(c) and collide(c + 1)
+            # the real rasters, grown, are apart at that distance too
+            uA, vA, _, _ = final_frame(inp.chart(perm[t - 1]), A)
+            uB, vB, _, _ = final_frame(inp.chart(perm[t]), B)
+            ra = dilate(chart_raster(chk, uA, vA, k, len(tA), len(lA)), p)
+            rb = dilate(chart_raster(chk, uB, vB, k, len(tB), len(lB)), p)
+            x = wdA - c
+            H = max(ra.shape[0], rb.shape[0])
+            Wt = x + rb.shape[1]
+            g = np.zeros((H, max(Wt, ra.shape[1])), int)
+            g[:ra.shape[0], :ra.shape[1]] += ra
+            g[:rb.shape[0], x:x + rb.shape[1]] += rb
+            assert g.max() <= 1
+
+
+@pytest.mark.parametrize("seed", range(15))
+def test_interlock_flags_are_sound(orc, seed):
+    inp = small_input(5000 + seed, n=10)
+    K, _ = orc.quality(inp.quality, inp.n)
+    p = inp.padding
+    k = 64 - 3 * (seed % 10)
+    perm, cd, fl, recs = _pair_data(orc, inp, K, k)
+    for t in range(1, inp.n):
+        A, B = recs[perm[t - 1]], recs[perm[t]]
+        tA, _, lA, rA = orc.profiles(A, k)
+        tB, _, lB, rB = orc.profiles(B, k)
+        LA, RA = hulls(dilate(row_footprint(lA, rA, len(tA)), p))
+        LB, RB = hulls(dilate(row_footprint(lB, rB, len(tB)), p))
+        d = len(tA) + p - int(cd[t])
+        hA, hB = len(LA), len(LB)
+
+        def meet(ja, jb):
+            return max(LA[ja], d + LB[jb]) < min(RA[ja], d + RB[jb])
+        b_up = any(meet(jb - dl, jb) for dl in range(1, hA + hB) for jb in range(hB)
+                   if 0 <= jb - dl < hA)
+        a_up = any(meet(ja, ja - dl) for dl in range(1, hA + hB) for ja in range(hA)
+                   if 0 <= ja - dl < hB)
+        if int(cd[t]) == 0:
+            assert fl[t] == 0
+        if b_up:
+            assert fl[t] & 1, (t, k)
+        if a_up:
+            assert fl[t] & 2, (t, k)
+
+
+def test_interlock_hand_cases(orc):
+    # two full rectangles side by side, no shared column: nothing restricted
+    assert orc.interlock(np.full(5, 4), 4, np.zeros(5, np.int32), 4) == 0
+    # B's lower rows reach under A's top-right overhang: B may not rise
+    rightA = np.array([6, 2, 2, 2])
+    leftB = np.array([3, 0, 0, 0])  # row 0 starts at 3, rows below start at 0
+    assert orc.interlock(rightA, 6, leftB, 3) & 1
+    # mirror case: A's lower rows reach under B's overhang: A may not rise
+    rightA = np.array([2, 5, 5, 5])
+    leftB = np.array([0, 3, 3, 3])
+    assert orc.interlock(rightA, 5, leftB, 2) & 2
+
+
+# ---------------------------------------------------------------------------
+# P7: correction reaches the least fixpoint
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(30))
+def test_correction_is_least_fixpoint(orc, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 40))
+    m = int(rng.integers(0, 3 * n))
+    pa = []
+    for _ in range(m):
+        A = int(rng.integers(0, n - 1))
+        B = int(rng.integers(A + 1, n))
+        pa.append((A, B, int(rng.integers(1, 4))))
+    y0 = rng.integers(0, 100, n)
+    y = orc.correct(np.array(pa, np.int32).reshape(-1, 3), y0)
+    # edge u -> v means y[v] >= y[u]
+    adj = [[] for _ in range(n)]
+    for A, B, f in pa:
+        if f & 1:
+            adj[A].append(B)
+        if f & 2:
+            adj[B].append(A)
+    want = y0.copy()
+    for s in range(n):
+        seen, stack = {s}, [s]
+        while stack:
+            x = stack.pop()
+            for z in adj[x]:
+                if z not in seen:
+                    seen.add(z)
+                    stack.append(z)
+        for z in seen:
+            want[z] = max(want[z], y0[s])
+    assert np.array_equal(y, want)
+
+
+# ---------------------------------------------------------------------------
+# P8 / P9 / P13: closed forms
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(30))
+def test_single_chart_closed_form(orc, seed):
+    rng = np.random.default_rng(seed)
+    inp0 = small_input(6000 + seed, n=1)
+    Wa, Ha = int(rng.integers(4, 200)), int(rng.integers(4, 200))
+    p = int(rng.integers(0, 4))
+    inp = synth.AtlasInput(inp0.xy, inp0.offsets, Wa, Ha, p, int(rng.integers(0, 3)))
+    P = inp.chart(0)
+    ext = P.max(axis=0) - P.min(axis=0)
+    W, H = sorted(int(e) for e in ext)
+    ks = [k for k in range(1, 65) if -(-k * W // T) <= Wa and -(-k * H // T) <= Ha]
+    xy, ori, sc, k = orc.pack(inp)
+    assert k == (max(ks) if ks else 0)
+    if k:
+        assert tuple(xy[0]) == (0, 0)
+        # feasibility is monotone here
+        assert all(orc.feasible(inp, kk)[0] == (kk <= k) for kk in range(1, 65))
+
+
+@pytest.mark.parametrize("a,b,n,Wa,Ha,p", [
+    (256 * 3, 256 * 5, 37, 40, 40, 1), (1000, 1900, 50, 64, 90, 2), (2048, 2048, 64, 64, 64, 0),
+    (256 * 6, 256 * 6, 36, 36, 36, 0), (700, 3000, 25, 50, 128, 3), (512, 512, 9, 9, 9, 1)])
+def test_identical_rectangles_closed_form(orc, a, b, n, Wa, Ha, p):
+    inp = synth.rect_input(n, a, b, Wa, Ha, p, q=2, seed=n)
+    Wd, Hd = Wa + p, Ha + p
+
+    def fits(k):
+        w, h = -(-k * a // T), -(-k * b // T)
+        M = Wd // (w + p)
+        return M >= 1 and -(-n // M) * (h + p) <= Hd
+    ks = [k for k in range(1, 65) if fits(k)]
+    want = max(ks) if ks else 0
+    xy, ori, sc, k = orc.pack(inp)
+    assert k == want
+    if k:
+        w, h = -(-k * a // T), -(-k * b // T)
+        M = Wd // (w + p)
+        perm, _ = orc.order(inp)
+        assert np.array_equal(perm, np.arange(n))  # equal keys: input order
+        for t in range(n):
+            assert tuple(xy[t]) == ((t % M) * (w + p), (t // M) * (h + p))
+        assert all(orc.feasible(inp, kk)[0] == fits(kk) for kk in range(1, 65))
+
+
+def test_exact_tiling_reaches_full_scale(orc, chk):
+    # 6 x 4 tiling of 10x15 texel rectangles with 2-texel gutters: W' = 6*12, H' = 4*17
+    inp = synth.rect_input(24, 2560, 3840, 6 * 12 - 2, 4 * 17 - 2, 2)
+    xy, ori, sc, k = orc.pack(inp)
+    assert k == 64 and sc == 1.0
+    st = chk.check_layout(inp, xy, ori, k)
+    assert st["overlap"] == 0 and st["outside"] == 0
+
+
+# ---------------------------------------------------------------------------
+# P10: knee thresholds (>= 10% of atlas height and >= 20% of the taller chart)
+# ---------------------------------------------------------------------------
+def _knee_input(tall_h_q8, short_h_q8, Ha):
+    polys = [np.array([[0, 0], [20 * 256, 0], [20 * 256, tall_h_q8], [0, tall_h_q8]])]
+    for i in range(30):
+        ox = 1000 * (i + 1)
+        polys.append(np.array([[ox, 0], [ox + 10 * 256, 0], [ox + 10 * 256, short_h_q8],
+                               [ox, short_h_q8]]))
+    xy, off = synth.pack_csr(polys)
+    return synth.AtlasInput(xy, off, 100, Ha, 0, 2)
+
+
+@pytest.mark.parametrize("short_h,knee", [(48 * 256, True), (48 * 256 + 1, False)])
+def test_knee_relative_threshold(orc, short_h, knee):
+    # drop 60 -> 48 texels is exactly 20% of the taller chart (and 12% of H)
+    inp = _knee_input(60 * 256, short_h, 100)
+    ok, xy, ori, rows = orc.feasible(inp, 64)
+    first_of_row1 = 9  # row 0 holds the tall chart and 8 short ones (20 + 8*10 = 100)
+    assert (int(xy[first_of_row1][0]) == 20) == knee
+
+
+@pytest.mark.parametrize("Ha,knee", [(120, True), (121, False)])
+def test_knee_absolute_threshold(orc, Ha, knee):
+    # drop of 12 texels: 10% of 120 (knee) but less than 10% of 121 (none)
+    inp = _knee_input(40 * 256, 28 * 256, Ha)
+    ok, xy, ori, rows = orc.feasible(inp, 64)
+    assert (int(xy[9][0]) == 20) == knee
+
+
+# ---------------------------------------------------------------------------
+# P11: L2 stretch of the output transform is 64/k exactly
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(10))
+def test_stretch_equals_scale(orc, chk, seed):
+    inp = small_input(7000 + seed)
+    xy, ori, sc, k = orc.pack(inp)
+    polys = chk.atlas_polygons(inp, xy, ori, k)
+    for c in range(inp.n):
+        S = inp.chart(c).astype(np.float64) / 256.0   # input texels
+        A = polys[c].astype(np.float64) / T           # atlas texels
+        for i in range(len(S) - 2):
+            s0, s1, s2 = S[i], S[i + 1], S[i + 2]
+            a0, a1, a2 = A[i], A[i + 1], A[i + 2]
+            Ma = np.stack([a1 - a0, a2 - a0], 1)
+            if abs(np.linalg.det(Ma)) < 1e-9:
+                continue
+            Ms = np.stack([s1 - s0, s2 - s0], 1)
+            J = Ms @ np.linalg.inv(Ma)  # atlas -> input
+            sv = np.linalg.svd(J, compute_uv=False)
+            l2 = math.sqrt((sv[0] ** 2 + sv[1] ** 2) / 2)
+            assert abs(l2 - 64.0 / k) < 1e-9 * (64.0 / k)
+            assert abs(sv[0] - sv[1]) < 1e-9 * sv[0]  # a similarity: no shear
+
+
+# ---------------------------------------------------------------------------
+# P12: search = full sweep; the area prune never removes a feasible scale
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(8))
+def test_search_equals_full_sweep(orc, seed):
+    inp = small_input(8000 + seed, n=12)
+    _, khi = orc.order(inp)
+    feas = [orc.feasible(inp, k)[0] for k in range(1, 65)]
+    best = max([k for k in range(1, 65) if feas[k - 1]], default=0)
+    assert orc.pack(inp)[3] == best
+    assert not any(feas[k - 1] for k in range(khi + 1, 65))
+
+
+# ---------------------------------------------------------------------------
+# P14: translation invariance, determinism; degenerate and edge inputs
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(6))
+def test_translation_invariance_and_determinism(orc, seed):
+    inp = small_input(9000 + seed)
+    r1 = orc.pack(inp)
+    r2 = orc.pack(inp)
+    assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1]) and r1[3] == r2[3]
+    rng = np.random.default_rng(seed)
+    polys = [inp.chart(c) + rng.integers(-5000, 5000, 2) for c in range(inp.n)]
+    xy, off = synth.pack_csr(polys)
+    r3 = orc.pack(synth.AtlasInput(xy, off, inp.atlas_w, inp.atlas_h, inp.padding, inp.quality))
+    assert np.array_equal(r1[0], r3[0]) and np.array_equal(r1[1], r3[1]) and r1[3] == r3[3]
+
+
+def test_edge_inputs(orc):
+    empty = synth.AtlasInput(np.zeros(0, np.int32), np.zeros(1, np.int32), 64, 64, 1, 2)
+    assert orc.pack(empty)[2] == 1.0
+    two = synth.AtlasInput(np.array([0, 0, 100, 100], np.int32), np.array([0, 2], np.int32),
+                           64, 64, 1, 2)
+    xy, ori, sc, k = orc.pack(two)
+    assert sc == -1.0 and np.all(xy == -1)
+    flat = synth.AtlasInput(np.array([0, 0, 100, 0, 200, 0], np.int32), np.array([0, 3], np.int32),
+                            64, 64, 1, 2)
+    assert orc.pack(flat)[2] == -1.0
+    huge = synth.AtlasInput(np.array([0, 0, 1 << 22, 0, 0, 100], np.int32),
+                            np.array([0, 3], np.int32), 64, 64, 1, 2)
+    assert orc.pack(huge)[2] == -1.0
+    big = synth.rect_input(1, 100 * 256, 100 * 256, 1, 1, 0)
+    xy, ori, sc, k = orc.pack(big)
+    assert sc == 0.0 and k == 0 and np.all(xy == -1)
+    for bad in [dict(atlas_w=0), dict(padding=-1), dict(quality=3), dict(atlas_w=16384, padding=1)]:
+        d = dict(xy=two.xy, offsets=two.offsets, atlas_w=64, atlas_h=64, padding=1, quality=2)
+        d.update(bad)
+        with pytest.raises(ValueError):
+            orc.pack(synth.AtlasInput(**d))
+
+
+def test_tail_rows_follow_one_to_two_alternation(orc):
+    """t_opt tail (Sec. 4.4): identical small rectangles, q=0 (t_opt = 5%):
+    every row is a tail row; directions go L, R, R, L, R, R ..."""
+    n, a, b = 60, 256 * 2, 256 * 3
+    inp = synth.rect_input(n, a, b, 20, 200, 0, q=0, seed=1)
+    ok, xy, ori, rows = orc.feasible(inp, 64)
+    assert ok
+    M = 10
+    for r in range(6):
+        mirrored = bool(ori[r * M] & 8)
+        assert mirrored == (r % 3 != 0)
