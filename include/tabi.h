@@ -1,0 +1,145 @@
+/*
+ * tabi.h - C ABI of the MI355X TABI atlas packer.
+ *
+ * Packs 2D polygon charts into a fixed-size texture atlas following
+ * "TABI: Tight and Balanced Interactive Atlas Packing" (Gu, Vining, Sheffer,
+ * Eurographics 2026).  The problem (Sec. 4, "Method", first paragraph): charts
+ * are polygons in texel units, the atlas has fixed dimensions; the output is
+ * one scale for all charts plus, per chart, a rigid transform (quarter turn,
+ * reflections, translation) such that no two charts nor their gutters overlap.
+ * The scale is the largest of the 64 factors k/64 whose packing succeeds
+ * (Sec. 5, "Experimental Setup"; Sec. 4.3).
+ *
+ * Conventions shared by every entry point
+ *  - Vertex coordinates are int32 fixed point with 8 fractional bits ("Q8",
+ *    1/256 texel); y grows downward.  Chart c is one simple polygon loop given
+ *    by vertices [offsets[c], offsets[c+1]) of the interleaved array xy.
+ *  - All arrays passed to tabi_pack / tabi_pack_many are DEVICE pointers owned
+ *    by the caller.  The library never frees or retains them.
+ *  - The functions are asynchronous and ordered on `stream` (0 = the null
+ *    stream).  Work space is taken from, and returned to, the device's
+ *    stream-ordered memory pool on the same stream; calls on different streams
+ *    are independent.
+ *  - The return value reports only errors the host can see.  Conditions found
+ *    on the device are written into out_scale (see tabi_pack).
+ *  - Gutters: `padding` is the minimum number of empty texels between two
+ *    charts (the paper's 1-pixel gutters around charts correspond to
+ *    padding = 2).  Charts may touch the atlas edges.
+ *  - quality selects the paper's quality/speed knob (Sec. 5 ablations):
+ *      0: 2 local AABBs per axis, t_opt = 5 %
+ *      1: 5 local AABBs per axis, t_opt = 2 %
+ *      2: 10 local AABBs per axis, t_opt = 0 % up to 10,000 charts, 1 % above
+ *         (the paper's default).
+ */
+#ifndef TABI_H
+#define TABI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* tabi_stream_t; /* a hipStream_t */
+
+enum {
+  TABI_OK = 0,
+  TABI_EINVAL = -1, /* bad argument: null pointer, n < 0 or n > TABI_MAX_CHARTS,
+                       atlas side < 1, side + padding > 16384, padding < 0,
+                       quality not in {0,1,2}, count < 0 */
+  TABI_ENOMEM = -2, /* the device memory pool could not supply the work space */
+  TABI_EHIP = -3    /* a HIP runtime call failed (launch, memory); see tabi_last_hip_error */
+};
+
+#define TABI_MAX_CHARTS 262144 /* charts per atlas */
+
+typedef struct {
+  const int32_t* xy;      /* device int32[2*total_verts]: x0,y0,x1,y1,... in Q8 */
+  const int32_t* offsets; /* device int32[n+1]: CSR vertex offsets, offsets[0] = 0 */
+  int32_t total_verts;    /* V = offsets[n] */
+} tabi_charts;
+
+/* Pack n charts into an atlas_w x atlas_h texel atlas (Alg. 3 for every
+ * candidate scale, largest success returned; Sec. 4.3).
+ *
+ * Outputs (device memory, written before the stream reaches the end of the call):
+ *   out_xy[2c], out_xy[2c+1]: texel column X and row Y of the top-left corner
+ *       of chart c's box in the atlas.
+ *   out_orient[c]: bit0 quarter turn applied first, (u,v) -> (h0 - v, u) in
+ *       the chart's box (h0 its input height); bit1 mirror in x inside the box;
+ *       bit2 mirror in y inside the box; bit3 mirror in x inside the scaled
+ *       texel box (rows placed right to left).  With s = k/64 the atlas
+ *       position of a chart point, in texels, is (X + s*u', Y + s*v') where
+ *       (u', v') is the point after bits 0-2, and bit3 then maps
+ *       s*u' -> ceil(s*W') - s*u' (W' the box width after bit0).
+ *   out_scale[0]: k/64 for the chosen k >= 1 (exact);
+ *        0.0f if no scale fits (out_xy filled with -1);
+ *       -1.0f if some chart is degenerate: fewer than 3 vertices, zero width
+ *             or height, or a coordinate with |x| >= 2^22 (out_xy filled with -1).
+ * Errors: TABI_EINVAL, TABI_ENOMEM, TABI_EHIP (nothing is written then). */
+int tabi_pack(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+              int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
+              float* out_scale, tabi_stream_t stream);
+
+/* Pack `count` independent atlases in one set of launches.  Charts of all
+ * atlases form one CSR (xy, vert_offsets over all charts); atlas a owns charts
+ * [atlas_offsets[a], atlas_offsets[a+1]) and has size atlas_wh[2a] x
+ * atlas_wh[2a+1] texels (device int32 arrays).  out_xy / out_orient are
+ * indexed by global chart index, out_scale by atlas.  Same per-atlas semantics
+ * as tabi_pack; padding and quality are shared. */
+int tabi_pack_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
+                   int32_t count, const int32_t* atlas_wh, int32_t padding, int32_t quality,
+                   int32_t* out_xy, uint8_t* out_orient, float* out_scale,
+                   tabi_stream_t stream);
+
+/* ---- diagnostics (same conventions; device pointers) ------------------- */
+
+/* Sorted chart order (Sec. 3.1: height descending, then width descending,
+ * then input index) and the largest candidate scale k_top (total chart area
+ * and the largest chart must fit the atlas at k_top / 64).
+ * perm[t] = input index of the t-th chart; khi[0] = k_top, or -1 if a chart
+ * is degenerate. */
+int tabi_debug_order(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+                     int32_t padding, int32_t quality, int32_t* perm, int32_t* khi,
+                     tabi_stream_t stream);
+
+/* Horizontal compacting distance and interlock flags of each sorted neighbour
+ * pair (c-1, c) at scale k/64 (Sec. 4.1.2, App. A): cd[c] in texels and
+ * flags[c] (bit0: c may not move above c-1; bit1: c-1 may not move above c);
+ * cd[0] = flags[0] = 0.  Indexed by sorted position. */
+int tabi_debug_pairs(const tabi_charts* charts, int32_t n, int32_t padding, int32_t quality,
+                     int32_t k, int32_t* cd, uint8_t* flags, tabi_stream_t stream);
+
+/* Fold-and-push at the single scale k/64 (Alg. 3).  feasible[0] = 1 if every
+ * chart was placed within the atlas height, 0 if a row overflowed or a chart
+ * is wider than the atlas; out_xy / out_orient as in tabi_pack for the charts
+ * placed before the scan stopped, -1 / 0 for the rest; rows[0] = number of
+ * rows committed. */
+int tabi_debug_feasible(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+                        int32_t padding, int32_t quality, int32_t k, int32_t* out_xy,
+                        uint8_t* out_orient, int32_t* feasible, int32_t* rows,
+                        tabi_stream_t stream);
+
+/* Text for a return code; last HIP error string seen by the library. */
+const char* tabi_strerror(int code);
+const char* tabi_last_hip_error(void);
+
+/* Stage timing (host side).  When enabled, the calling process brackets each
+ * stage of later tabi_pack / tabi_pack_many calls with a pair of HIP events on
+ * the call's stream.  Stages, in order: 0 chart proxies (prep), 1 sort and
+ * scale bound, 2 per-scale set-up, 3 neighbour pairs, 4 fold-and-push, 5 scale
+ * selection.  tabi_timing_read waits for the recorded events and writes the
+ * summed milliseconds and the number of bracketed launches per stage since
+ * the last reset (arrays of nstages entries, either may be NULL). */
+int tabi_timing_enable(int on);
+int tabi_timing_read(double* ms, int32_t* launches, int32_t nstages);
+void tabi_timing_reset(void);
+
+/* Device shared memory (bytes) the packing kernel will use for an atlas of
+ * width atlas_w + padding and n charts (host only; no device work). */
+int64_t tabi_pack_lds_bytes(int32_t n, int32_t atlas_w, int32_t padding);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TABI_H */

@@ -848,7 +848,8 @@ int tabi_oracle_feasible(const int32_t* xy, const int32_t* offsets, int32_t n, i
     int c = perm[t];
     out_xy[2 * c] = xs[t];
     out_xy[2 * c + 1] = ys[t];
-    out_orient[c] = (uint8_t)(ch[c].rot | (ch[c].flipx << 1) | (ch[c].flipy << 2) | (mir[t] << 3));
+    /* charts not reached before the scan stopped: no transform reported */
+    out_orient[c] = xs[t] < 0 ? 0 : (uint8_t)(ch[c].rot | (ch[c].flipx << 1) | (ch[c].flipy << 2) | (mir[t] << 3));
   }
   free(xs); free(ys); free(mir); free(perm); free(ch);
   return ok;

@@ -61,7 +61,7 @@ int tabi_oracle_pack(const int32_t* xy, const int32_t* offsets, int32_t n,
 
 /* Fold-and-push at one scale (Alg. 3).  Returns 1 if every chart is placed
  * without overflow, 0 otherwise, -1 on bad arguments.  Positions / orientation
- * of the charts placed so far are written in input order (others -1 / 0);
+ * of the charts placed so far are written in input order (others -1 and 0);
  * rows_out (optional) receives the number of committed rows. */
 int tabi_oracle_feasible(const int32_t* xy, const int32_t* offsets, int32_t n,
                          int32_t atlas_w, int32_t atlas_h, int32_t padding, int32_t quality,

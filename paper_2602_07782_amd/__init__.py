@@ -1,0 +1,202 @@
+"""MI355X (gfx950) implementation of TABI atlas packing.
+
+Thin ctypes binding over the C ABI in ``include/tabi.h``.  Every step of the
+packing path runs in the HIP kernels of ``libtabi_hip.so``; this module only
+allocates output tensors with PyTorch (device memory and streams) and passes
+raw pointers.  There is no CPU fallback: without the built library every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtabi_hip.so")
+
+TABI_OK, TABI_EINVAL, TABI_ENOMEM, TABI_EHIP = 0, -1, -2, -3
+ERRORS = {TABI_EINVAL: "invalid argument", TABI_ENOMEM: "out of device memory",
+          TABI_EHIP: "HIP runtime error"}
+
+
+class TabiError(RuntimeError):
+    def __init__(self, code, detail=""):
+        super().__init__(f"tabi error {code}: {ERRORS.get(code, 'unknown')} {detail}".strip())
+        self.code = code
+
+
+class Charts(ctypes.Structure):
+    _fields_ = [("xy", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("total_verts", ctypes.c_int32)]
+
+
+_lib = None
+EXPORTS = ["tabi_pack", "tabi_pack_many", "tabi_debug_order", "tabi_debug_pairs",
+           "tabi_debug_feasible", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
+           "tabi_timing_enable", "tabi_timing_read", "tabi_timing_reset"]
+STAGES = ["prep", "sort", "setup", "pairs", "pack", "select"]
+
+
+def lib():
+    """Load libtabi_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2602_07782_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32 = ctypes.c_void_p, ctypes.c_int32
+        L.tabi_pack.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, i32, vp, vp, vp, vp]
+        L.tabi_pack_many.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp]
+        L.tabi_debug_order.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, i32, vp, vp, vp]
+        L.tabi_debug_pairs.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, vp, vp, vp]
+        L.tabi_debug_feasible.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, i32, i32,
+                                          vp, vp, vp, vp, vp]
+        L.tabi_strerror.restype = ctypes.c_char_p
+        L.tabi_last_hip_error.restype = ctypes.c_char_p
+        L.tabi_pack_lds_bytes.argtypes = [i32, i32, i32]
+        L.tabi_pack_lds_bytes.restype = ctypes.c_int64
+        L.tabi_timing_enable.argtypes = [ctypes.c_int]
+        L.tabi_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int32), i32]
+        L.tabi_timing_reset.restype = None
+        _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _check(rc):
+    if rc != TABI_OK:
+        detail = lib().tabi_last_hip_error().decode() if rc == TABI_EHIP else ""
+        raise TabiError(rc, detail)
+
+
+def _dev_i32(a, device):
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device, dtype=torch.int32)
+    else:
+        import numpy as np
+        t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).to(device)
+    return t.contiguous()
+
+
+def _charts(xy, offsets):
+    n = int(offsets.numel()) - 1
+    c = Charts(_ptr(xy).value, _ptr(offsets).value, int(xy.numel() // 2))
+    return c, n
+
+
+def pack(xy, offsets, atlas_w, atlas_h, padding, quality, stream=None, device="cuda"):
+    """tabi_pack.  xy: int32[2V] (Q8), offsets: int32[n+1] (device tensors or
+    arrays).  Returns (out_xy int32[n,2], out_orient uint8[n], out_scale
+    float32[1]) on the device; enqueued on `stream` (default: current)."""
+    torch = _torch()
+    xy = _dev_i32(xy, device)
+    offsets = _dev_i32(offsets, device)
+    ch, n = _charts(xy, offsets)
+    out_xy = torch.empty((max(n, 0), 2), dtype=torch.int32, device=xy.device)
+    out_or = torch.empty(max(n, 0), dtype=torch.uint8, device=xy.device)
+    out_sc = torch.empty(1, dtype=torch.float32, device=xy.device)
+    _check(lib().tabi_pack(ctypes.byref(ch), n, int(atlas_w), int(atlas_h), int(padding),
+                           int(quality), _ptr(out_xy), _ptr(out_or), _ptr(out_sc), _stream(stream)))
+    return out_xy, out_or, out_sc
+
+
+def pack_into(xy, offsets, n, atlas_w, atlas_h, padding, quality, out_xy, out_orient, out_scale,
+              stream=None):
+    """tabi_pack on caller-provided device tensors (no allocation here)."""
+    ch = Charts(_ptr(xy).value, _ptr(offsets).value, int(xy.numel() // 2))
+    _check(lib().tabi_pack(ctypes.byref(ch), int(n), int(atlas_w), int(atlas_h), int(padding),
+                           int(quality), _ptr(out_xy), _ptr(out_orient), _ptr(out_scale),
+                           _stream(stream)))
+
+
+def pack_many(xy, vert_offsets, atlas_offsets, atlas_wh, padding, quality, stream=None,
+              device="cuda"):
+    """tabi_pack_many over a flattened batch.  Returns (out_xy int32[N,2],
+    out_orient uint8[N], out_scale float32[count])."""
+    torch = _torch()
+    xy = _dev_i32(xy, device)
+    vert_offsets = _dev_i32(vert_offsets, device)
+    atlas_offsets = _dev_i32(atlas_offsets, device)
+    atlas_wh = _dev_i32(atlas_wh, device)
+    count = int(atlas_offsets.numel()) - 1
+    N = int(vert_offsets.numel()) - 1
+    out_xy = torch.empty((N, 2), dtype=torch.int32, device=xy.device)
+    out_or = torch.empty(N, dtype=torch.uint8, device=xy.device)
+    out_sc = torch.empty(count, dtype=torch.float32, device=xy.device)
+    _check(lib().tabi_pack_many(_ptr(xy), _ptr(vert_offsets), _ptr(atlas_offsets), count,
+                                _ptr(atlas_wh), int(padding), int(quality), _ptr(out_xy),
+                                _ptr(out_or), _ptr(out_sc), _stream(stream)))
+    return out_xy, out_or, out_sc
+
+
+def debug_order(xy, offsets, atlas_w, atlas_h, padding, quality, stream=None, device="cuda"):
+    torch = _torch()
+    xy = _dev_i32(xy, device)
+    offsets = _dev_i32(offsets, device)
+    ch, n = _charts(xy, offsets)
+    perm = torch.empty(n, dtype=torch.int32, device=xy.device)
+    khi = torch.empty(1, dtype=torch.int32, device=xy.device)
+    _check(lib().tabi_debug_order(ctypes.byref(ch), n, int(atlas_w), int(atlas_h), int(padding),
+                                  int(quality), _ptr(perm), _ptr(khi), _stream(stream)))
+    return perm, khi
+
+
+def debug_pairs(xy, offsets, padding, quality, k, stream=None, device="cuda"):
+    torch = _torch()
+    xy = _dev_i32(xy, device)
+    offsets = _dev_i32(offsets, device)
+    ch, n = _charts(xy, offsets)
+    cd = torch.empty(n, dtype=torch.int32, device=xy.device)
+    fl = torch.empty(n, dtype=torch.uint8, device=xy.device)
+    _check(lib().tabi_debug_pairs(ctypes.byref(ch), n, int(padding), int(quality), int(k),
+                                  _ptr(cd), _ptr(fl), _stream(stream)))
+    return cd, fl
+
+
+def debug_feasible(xy, offsets, atlas_w, atlas_h, padding, quality, k, stream=None,
+                   device="cuda"):
+    torch = _torch()
+    xy = _dev_i32(xy, device)
+    offsets = _dev_i32(offsets, device)
+    ch, n = _charts(xy, offsets)
+    out_xy = torch.empty((n, 2), dtype=torch.int32, device=xy.device)
+    out_or = torch.empty(n, dtype=torch.uint8, device=xy.device)
+    feas = torch.empty(1, dtype=torch.int32, device=xy.device)
+    rows = torch.empty(1, dtype=torch.int32, device=xy.device)
+    _check(lib().tabi_debug_feasible(ctypes.byref(ch), n, int(atlas_w), int(atlas_h),
+                                     int(padding), int(quality), int(k), _ptr(out_xy),
+                                     _ptr(out_or), _ptr(feas), _ptr(rows), _stream(stream)))
+    return out_xy, out_or, feas, rows
+
+
+def timing_enable(on=True):
+    lib().tabi_timing_enable(1 if on else 0)
+
+
+def timing_reset():
+    lib().tabi_timing_reset()
+
+
+def timing_read():
+    """{stage: (total_ms, launches)} since the last reset (waits for events)."""
+    ms = (ctypes.c_double * len(STAGES))()
+    n = (ctypes.c_int32 * len(STAGES))()
+    _check(lib().tabi_timing_read(ms, n, len(STAGES)))
+    return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}

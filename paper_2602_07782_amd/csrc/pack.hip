@@ -1,0 +1,565 @@
+// Fold-and-push at one candidate scale per workgroup (Alg. 3), and the scale
+// selection.
+//
+// One workgroup (8 wavefronts) owns one (atlas, scale) pair and walks its rows
+// in order.  The committed frontline lives in LDS.  Per row:
+//   1. knee update (Alg. 4)            block max/min over the knee span
+//   2. folding (Alg. 2)                wavefront prefix sums of chart advances,
+//                                      first overflow by ballot; folds with
+//                                      and without compaction and at full and
+//                                      knee width come from the same two scans
+//   3. staging                         grown TopEdge/BottomEdge of the row's
+//                                      candidate charts into LDS (int16)
+//   4. push                            every texel of every configuration:
+//                                      frontline - TopEdge, segmented max per
+//                                      chart across the wavefront, one LDS
+//                                      atomic per chart segment
+//   5. correction (Alg. 1)             per configuration one wavefront: forward
+//                                      and backward segmented max scans over the
+//                                      interlock chain, plus the rare pairs that
+//                                      share columns without being neighbours
+//   6. scores                          max over texels of offset + BottomEdge;
+//                                      no private frontline copy is needed since
+//                                      max(F, updates) = max(max F, max updates)
+//   7. selection (Sec. 4.2 "Placing Rows") and commit, knee detection.
+// All threads keep the per-row scalars in registers and compute them
+// identically from LDS, so only data arrays and reductions cross threads.
+#include "tabi_internal.h"
+#include "pairs_dev.h"
+
+namespace tabi {
+
+constexpr int PACK_NT = 512;
+constexpr int PACK_WAVES = PACK_NT / WAVE;
+constexpr int LRCAP = 256;  // pairs per row that share columns without being neighbours
+enum { DIR_LR = 0, DIR_RL = 1 };
+
+__device__ inline void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// largest t in [0, cand) with Xoff[t] <= e
+__device__ inline int find_chart(const int32_t* Xoff, int cand, int e) {
+  int lo = 0, hi = cand - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (Xoff[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// segmented max toward the first lane of each run of equal t
+__device__ inline int32_t seg_max_to_head(int32_t v, int t) {
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int32_t vd = __shfl_down(v, o);
+    int td = __shfl_down(t, o);
+    if (lane_id() + o < WAVE && td == t) v = max(v, vd);
+  }
+  return v;
+}
+
+// CorrectYOffsets (Alg. 1) for one configuration, one wavefront.  Chain links
+// come from the neighbour flags; fl[t] holds the flags of (t-1, t).
+__device__ void correct_offsets(int32_t* y, int cnt, const uint8_t* fl, const int32_t (*lr)[3],
+                                int lrn) {
+  const int lane = lane_id();
+  for (;;) {
+    int32_t carry = -BIG;
+    for (int t0 = 0; t0 < cnt; t0 += WAVE) {  // y[t] >= y[t-1] where bit0 of fl[t]
+      const int t = t0 + lane;
+      int32_t v = t < cnt ? y[t] : -BIG;
+      int head = !(t >= 1 && t < cnt && (fl[t] & 1));
+#pragma unroll
+      for (int o = 1; o < WAVE; o <<= 1) {
+        int32_t vu = __shfl_up(v, o);
+        int hu = __shfl_up(head, o);
+        if (lane >= o && !head) { v = max(v, vu); head |= hu; }
+      }
+      if (!head) v = max(v, carry);
+      if (t < cnt) y[t] = v;
+      carry = __shfl(v, WAVE - 1);
+    }
+    wsync();
+    carry = -BIG;
+    for (int r0 = 0; r0 < cnt; r0 += WAVE) {  // y[t] >= y[t+1] where bit1 of fl[t+1]
+      const int r = r0 + lane, t = cnt - 1 - r;
+      int32_t v = r < cnt ? y[t] : -BIG;
+      int head = !(r >= 1 && r < cnt && (fl[t + 1] & 2));
+#pragma unroll
+      for (int o = 1; o < WAVE; o <<= 1) {
+        int32_t vu = __shfl_up(v, o);
+        int hu = __shfl_up(head, o);
+        if (lane >= o && !head) { v = max(v, vu); head |= hu; }
+      }
+      if (!head) v = max(v, carry);
+      if (r < cnt) y[t] = v;
+      carry = __shfl(v, WAVE - 1);
+    }
+    wsync();
+    int changed = 0;
+    for (int q0 = 0; q0 < lrn; q0 += WAVE) {
+      const int q = q0 + lane;
+      if (q < lrn) {
+        const int A = lr[q][0], C = lr[q][1], f = lr[q][2];
+        if (C < cnt) {
+          const int32_t ya = y[A], yc = y[C];
+          if ((f & 1) && yc < ya) { atomicMax(&y[C], ya); changed = 1; }
+          if ((f & 2) && ya < yc) { atomicMax(&y[A], yc); changed = 1; }
+        }
+      }
+    }
+    const bool any = ballot64(changed) != 0;
+    wsync();
+    if (!any) break;
+  }
+}
+
+__device__ inline int32_t block_reduce_max(int32_t v, int32_t* red) {
+  v = wave_max(v);
+  __syncthreads();
+  if (lane_id() == 0) red[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  int32_t r = red[0];
+#pragma unroll
+  for (int i = 1; i < PACK_WAVES; ++i) r = max(r, red[i]);
+  return r;
+}
+__device__ inline int32_t block_reduce_min(int32_t v, int32_t* red) {
+  v = wave_min(v);
+  __syncthreads();
+  if (lane_id() == 0) red[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  int32_t r = red[0];
+#pragma unroll
+  for (int i = 1; i < PACK_WAVES; ++i) r = min(r, red[i]);
+  return r;
+}
+
+__global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, int RC, int SC) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t s_cnt[4];
+  __shared__ int32_t s_red[PACK_WAVES * 6];
+  __shared__ int64_t s_red64[PACK_WAVES];
+  __shared__ int32_t s_lrn, s_lrover;
+  __shared__ int32_t s_lr[LRCAP][3];
+
+  const int s = blockIdx.x, a = blockIdx.y;
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+  const AtlasDesc d = w.desc[a];
+  const int k = slot_k(P, d, round, s);
+  const bool run = P.fixed_k > 0 ? (k >= 1 && !d.bad) : (!d.done && d.ktop >= 1 && k >= 1);
+  if (!run) {
+    if (tid == 0) { w.feas[a * P.B + s] = -1; w.rows[a * P.B + s] = 0; }
+    return;
+  }
+  const int n = d.n, Wd = d.Wa + P.p, Hd = d.Ha + P.p, Ha = d.Ha, p = P.p, K = P.K;
+  const int topt = P.q == 0 ? 5 : (P.q == 1 ? 2 : (n > 10000 ? 1 : 0));
+  const size_t slot = (size_t)s * P.N + d.c0;
+  int32_t* F = reinterpret_cast<int32_t*>(smem);
+  int32_t* Xoff = F + Wd;
+  int32_t* Xon = Xoff + (RC + 1);
+  int32_t* Y = Xon + (RC + 1);
+  int16_t* stT = reinterpret_cast<int16_t*>(Y + 4 * RC);
+  int16_t* stB = stT + SC;
+  const unsigned char* kcb = w.kc + slot * P.stride;
+  const Chart* ch = w.srecs + d.c0;
+  const int32_t* cdv = w.cd + slot;
+  const uint8_t* flv = w.fl + slot;
+  int32_t* xs = w.xs + slot;
+  int32_t* ys = w.ys + slot;
+  uint8_t* mir = w.mir + slot;
+  auto KV = [&](int c) { return kview(kcb + (size_t)c * P.stride, K); };
+
+  for (int x = tid; x < Wd; x += PACK_NT) F[x] = 0;
+  for (int t = tid; t < n; t += PACK_NT) { xs[t] = -1; ys[t] = -1; mir[t] = 0; }
+
+  // per-row state, identical in every thread
+  int rs = 0, rows = 0, feasible = 1, tail = 0, trow = 0;
+  int kn = 0, kdir = 0, kl = 0, kr = 0;
+  int32_t fmax = 0;
+
+  for (;;) {
+    __syncthreads();
+    if (rs >= n) break;
+    // ---- 1. knee location update (Alg. 4)
+    if (kn) {
+      const int probe = kdir == DIR_LR ? kr : kl - 1;
+      if (probe < 0 || probe >= Wd) {
+        kn = 0;
+      } else {
+        const int32_t h0 = F[probe];
+        if (kdir == DIR_LR) {
+          int32_t best = kl - 1;
+          for (int x = kl + tid; x < kr; x += PACK_NT) if (F[x] >= h0) best = max(best, x);
+          best = block_reduce_max(best, s_red);
+          kr = best + 1;
+        } else {
+          int32_t best = kr;
+          for (int x = kl + tid; x < kr; x += PACK_NT) if (F[x] >= h0) best = min(best, x);
+          best = block_reduce_min(best, s_red);
+          kl = best;
+        }
+      }
+    }
+    // ---- t_opt switch (Sec. 4.4)
+    if (!tail && !kn && 100 * (int64_t)KV(rs).hd->h < (int64_t)topt * Ha) tail = 1;
+    // ---- 2. folding (Alg. 2), wavefront 0
+    const int kw = kn ? (kdir == DIR_LR ? Wd - kr : kl) : 0;
+    if (wv == 0) {
+      int cfo = -1, cfn = -1, cko = -1, ckn = -1;
+      int xo = 0, xn = 0;
+      for (int t0 = 0; cfn < 0; t0 += WAVE) {
+        const int t = t0 + lane, c = rs + t;
+        int wd = Wd + 1, cdn = 0;
+        if (c < n) {
+          wd = KV(c).hd->w + p;
+          if (c + 1 < n) cdn = cdv[c + 1];
+        }
+        const int ao = wd, an = wd - cdn;
+        const int io = wave_incl_sum(ao), in = wave_incl_sum(an);
+        const int Xo = xo + io - ao, Xn = xn + in - an;
+        if (t <= RC) { Xoff[t] = Xo; Xon[t] = Xn; }
+        const uint64_t bfo = ballot64(Xo + wd > Wd), bfn = ballot64(Xn + wd > Wd);
+        const uint64_t bko = ballot64(Xo + wd > kw), bkn = ballot64(Xn + wd > kw);
+        if (cfo < 0 && bfo) cfo = t0 + __builtin_ctzll(bfo);
+        if (cfn < 0 && bfn) cfn = t0 + __builtin_ctzll(bfn);
+        if (cko < 0 && bko) cko = t0 + __builtin_ctzll(bko);
+        if (ckn < 0 && bkn) ckn = t0 + __builtin_ctzll(bkn);
+        xo += __shfl(io, WAVE - 1);
+        xn += __shfl(in, WAVE - 1);
+      }
+      if (lane == 0) {
+        s_cnt[0] = cfo; s_cnt[1] = cfn; s_cnt[2] = cko; s_cnt[3] = ckn;
+        s_lrn = 0; s_lrover = 0;
+      }
+    }
+    __syncthreads();
+    const int cfo = s_cnt[0], cfn = s_cnt[1], cko = s_cnt[2], ckn = s_cnt[3];
+    if (cfn == 0) { feasible = 0; break; }  // a chart wider than the atlas
+    if (cfn > RC) { feasible = -2; break; }   // cannot happen: advances are >= 1
+    // ---- configurations: direction x compaction x (full | knee) (Sec. 4.2)
+    int ncfg, c_cnt[4], c_hc[4], c_dir[4], c_R0[4], c_R1[4];
+    if (tail) {
+      ncfg = 1;
+      c_cnt[0] = cfn; c_hc[0] = 1; c_dir[0] = (trow % 3 == 0) ? DIR_LR : DIR_RL;
+      c_R0[0] = 0; c_R1[0] = Wd;
+      ++trow;
+    } else {
+      const int hc = cfn > cfo, cnt = hc ? cfn : cfo;
+      ncfg = 2;
+      c_cnt[0] = c_cnt[1] = cnt; c_hc[0] = c_hc[1] = hc;
+      c_dir[0] = DIR_LR; c_dir[1] = DIR_RL;
+      c_R0[0] = c_R0[1] = 0; c_R1[0] = c_R1[1] = Wd;
+      if (kn && ckn > 0) {
+        const int khc = ckn > cko, kc = khc ? ckn : cko;
+        ncfg = 4;
+        c_cnt[2] = c_cnt[3] = kc; c_hc[2] = c_hc[3] = khc;
+        c_dir[2] = DIR_LR; c_dir[3] = DIR_RL;
+        c_R0[2] = c_R0[3] = kdir == DIR_LR ? kr : 0;
+        c_R1[2] = c_R1[3] = kdir == DIR_LR ? Wd : kl;
+      }
+    }
+    for (int j = ncfg; j < 4; ++j) { c_cnt[j] = 0; c_hc[j] = 0; c_dir[j] = 0; c_R0[j] = 0; c_R1[j] = 0; }
+    const int cand = cfn;
+    int cmax = 0, anyhc = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { cmax = max(cmax, c_cnt[j]); anyhc |= c_hc[j]; }
+    const int E = Xoff[cand], Eall = Xoff[cmax];
+    const bool staged = E <= SC;
+    // ---- 3. staging, offset init, neighbour-free pairs that share columns
+    if (staged) {
+      for (int e = tid; e < E; e += PACK_NT) {
+        const int t = find_chart(Xoff, cand, e);
+        int32_t tp, bt;
+        column_bounds_grown(KV(rs + t), ch[rs + t], K, k, p, e - Xoff[t], tp, bt);
+        stT[e] = (int16_t)tp;
+        stB[e] = (int16_t)bt;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      for (int t = tid; t < c_cnt[j]; t += PACK_NT) Y[j * RC + t] = -BIG;
+    if (anyhc) {
+      for (int A = tid; A + 2 < cand; A += PACK_NT) {
+        const int wdA = Xoff[A + 1] - Xoff[A];
+        for (int C = A + 2; C < cand && Xon[C] - Xon[A] < wdA; ++C) {
+          const int q = atomicAdd(&s_lrn, 1);
+          if (q < LRCAP) { s_lr[q][0] = A; s_lr[q][1] = C; s_lr[q][2] = 0; }
+          else s_lrover = 1;
+        }
+      }
+    }
+    __syncthreads();
+    const int lrn = min(s_lrn, LRCAP);
+    if (s_lrover) { feasible = -2; break; }
+    for (int q = wv; q < lrn; q += PACK_WAVES) {
+      const int A = s_lr[q][0], C = s_lr[q][1];
+      const int f = pair_flags(KV(rs + A), ch[rs + A], KV(rs + C), ch[rs + C], K, k, p,
+                               Xon[C] - Xon[A]);
+      if (lane == 0) s_lr[q][2] = f;
+    }
+    __syncthreads();
+    // ---- 4. push every configuration against the committed frontline
+    for (int e0 = wv * WAVE; e0 < Eall; e0 += PACK_NT) {
+      const int e = e0 + lane;
+      const bool valid = e < Eall;
+      const int t = valid ? find_chart(Xoff, cand, e) : -1;
+      const int i = valid ? e - Xoff[t] : 0;
+      int32_t tp = 0;
+      if (valid) {
+        if (staged) tp = stT[e];
+        else { int32_t bt; column_bounds_grown(KV(rs + t), ch[rs + t], K, k, p, i, tp, bt); }
+      }
+      const bool head = lane == 0 || __shfl_up(t, 1) != t;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j >= ncfg) break;
+        int32_t v = -BIG;
+        if (valid && t < c_cnt[j]) {
+          const int X = c_hc[j] ? Xon[t] : Xoff[t];
+          const int col = c_dir[j] == DIR_LR ? c_R0[j] + X + i : c_R1[j] - 1 - X - i;
+          v = F[col] - tp;
+        }
+        v = seg_max_to_head(v, t);
+        if (head && v > -BIG) atomicMax(&Y[j * RC + t], v);
+      }
+    }
+    __syncthreads();
+    // ---- 5. correction, one wavefront per compacted configuration
+    if (wv < ncfg) {
+      const int cnt = wv == 0 ? c_cnt[0] : wv == 1 ? c_cnt[1] : wv == 2 ? c_cnt[2] : c_cnt[3];
+      const int hc = wv == 0 ? c_hc[0] : wv == 1 ? c_hc[1] : wv == 2 ? c_hc[2] : c_hc[3];
+      if (hc) correct_offsets(Y + wv * RC, cnt, flv + rs, s_lr, lrn);
+    }
+    __syncthreads();
+    // ---- 6. scores
+    int32_t M[4] = {-BIG, -BIG, -BIG, -BIG};
+    for (int e0 = wv * WAVE; e0 < Eall; e0 += PACK_NT) {
+      const int e = e0 + lane;
+      if (e < Eall) {
+        const int t = find_chart(Xoff, cand, e);
+        int32_t bt;
+        if (staged) bt = stB[e];
+        else { int32_t tp; column_bounds_grown(KV(rs + t), ch[rs + t], K, k, p, e - Xoff[t], tp, bt); }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (t < c_cnt[j]) M[j] = max(M[j], Y[j * RC + t] + bt);
+      }
+    }
+    int32_t fr = -BIG;
+    if (ncfg == 4)
+      for (int x = c_R0[2] + tid; x < c_R1[2]; x += PACK_NT) fr = max(fr, F[x]);
+    {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) M[j] = wave_max(M[j]);
+      fr = wave_max(fr);
+      if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s_red[wv * 6 + j] = M[j];
+        s_red[wv * 6 + 4] = fr;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int32_t m = -BIG;
+        for (int q = 0; q < PACK_WAVES; ++q) m = max(m, s_red[q * 6 + j]);
+        M[j] = m;
+      }
+      int32_t f2 = -BIG;
+      for (int q = 0; q < PACK_WAVES; ++q) f2 = max(f2, s_red[q * 6 + 4]);
+      fr = f2;
+    }
+    // ---- 7. selection: lower maximal height wins, ties left to right; the
+    // knee fold only if strictly lower over the whole frontline
+    int win = 0, knee_used = 0;
+    int32_t whole[4], region[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { whole[j] = max(fmax, M[j]); region[j] = max(fr, M[j]); }
+    if (!tail) {
+      win = whole[1] < whole[0] ? 1 : 0;
+      if (ncfg == 4) {
+        const int kb = region[3] < region[2] ? 3 : 2;
+        if (whole[kb] < whole[win]) { win = kb; knee_used = 1; }
+      }
+    }
+    const int w_cnt = win == 0 ? c_cnt[0] : win == 1 ? c_cnt[1] : win == 2 ? c_cnt[2] : c_cnt[3];
+    const int w_hc = win == 0 ? c_hc[0] : win == 1 ? c_hc[1] : win == 2 ? c_hc[2] : c_hc[3];
+    const int w_dir = win == 0 ? c_dir[0] : win == 1 ? c_dir[1] : win == 2 ? c_dir[2] : c_dir[3];
+    const int w_R0 = win == 0 ? c_R0[0] : win == 1 ? c_R0[1] : win == 2 ? c_R0[2] : c_R0[3];
+    const int w_R1 = win == 0 ? c_R1[0] : win == 1 ? c_R1[1] : win == 2 ? c_R1[2] : c_R1[3];
+    const int32_t w_score = win == 0 ? whole[0] : win == 1 ? whole[1] : win == 2 ? whole[2] : whole[3];
+    const int32_t* Yw = Y + win * RC;
+    __syncthreads();  // everyone has read the reductions and Y before commit
+    // ---- commit: frontline update, placements
+    const int Ew = Xoff[w_cnt];
+    for (int e = tid; e < Ew; e += PACK_NT) {
+      const int t = find_chart(Xoff, cand, e);
+      const int i = e - Xoff[t];
+      int32_t bt;
+      if (staged) bt = stB[e];
+      else { int32_t tp; column_bounds_grown(KV(rs + t), ch[rs + t], K, k, p, i, tp, bt); }
+      const int X = w_hc ? Xon[t] : Xoff[t];
+      const int col = w_dir == DIR_LR ? w_R0 + X + i : w_R1 - 1 - X - i;
+      atomicMax(&F[col], Yw[t] + bt);
+    }
+    for (int t = tid; t < w_cnt; t += PACK_NT) {
+      const int X = w_hc ? Xon[t] : Xoff[t];
+      const int wd = Xoff[t + 1] - Xoff[t];
+      xs[rs + t] = w_dir == DIR_LR ? w_R0 + X : w_R1 - X - wd;
+      ys[rs + t] = Yw[t];
+      mir[rs + t] = (uint8_t)(w_dir == DIR_RL);
+    }
+    // knee detection on a row folded at full width (Sec. 4.2; App. A): the
+    // largest drop in unscaled height between consecutive charts that is at
+    // least 10% of the atlas height and 20% of the taller chart; first wins
+    if (!tail && !knee_used) {
+      int64_t best = -1;
+      for (int t = tid; t + 1 < w_cnt; t += PACK_NT) {
+        const int64_t h1 = ch[rs + t].H, h2 = ch[rs + t + 1].H, dl = h1 - h2;
+        if (10 * dl >= 256 * (int64_t)Ha && 5 * dl >= h1) {
+          const int64_t key = (dl << 20) | (int64_t)((1 << 20) - 1 - t);
+          best = key > best ? key : best;
+        }
+      }
+      best = wave_max64(best);
+      if (lane == 0) s_red64[wv] = best;
+      __syncthreads();
+      int64_t b = s_red64[0];
+      for (int q = 1; q < PACK_WAVES; ++q) b = s_red64[q] > b ? s_red64[q] : b;
+      if (b >= 0) {
+        const int t = (1 << 20) - 1 - (int)(b & ((1 << 20) - 1));
+        const int X = w_hc ? Xon[t] : Xoff[t];
+        const int wd = Xoff[t + 1] - Xoff[t];
+        kn = 1;
+        kdir = w_dir;
+        kl = w_dir == DIR_LR ? w_R0 + X : w_R1 - X - wd;
+        kr = kl + wd;
+      } else {
+        kn = 0;
+      }
+    }
+    fmax = max(fmax, w_score);
+    ++rows;
+    if (w_score > Hd) { feasible = 0; break; }
+    rs += w_cnt;
+  }
+  if (tid == 0) {
+    w.feas[a * P.B + s] = feasible;
+    w.rows[a * P.B + s] = rows;
+  }
+}
+
+// Largest feasible scale of this round per atlas; outputs in input order.
+__global__ __launch_bounds__(256) void k_select(Params P, Work w, int round, int last_round,
+                                                int32_t* out_xy, uint8_t* out_orient,
+                                                float* out_scale) {
+  __shared__ int s_best, s_limit, s_more;
+  const int a = blockIdx.x;
+  const AtlasDesc d = w.desc[a];
+  if (d.done) return;
+  if (threadIdx.x == 0) {
+    int best = -1, limit = 0;
+    if (!d.bad && d.n > 0 && d.ktop >= 1) {
+      for (int s = 0; s < P.B; ++s) {
+        const int f = w.feas[a * P.B + s];
+        if (f == -2) limit = 1;
+        if (f == 1 && best < 0) best = s;
+      }
+    }
+    s_best = best;
+    s_limit = limit;
+    // more candidate scales remain for a later round
+    s_more = !d.bad && d.n > 0 && d.ktop >= 1 && best < 0 && !limit && !last_round &&
+             slot_k(P, d, round, P.B - 1) > 1;
+  }
+  __syncthreads();
+  const int best = s_best;
+  if (s_more) return;
+  float scale;
+  int kstar = 0;
+  if (d.bad) scale = -1.0f;
+  else if (d.n == 0) { scale = 1.0f; kstar = 64; }
+  else if (s_limit) scale = -2.0f;
+  else if (best >= 0) { kstar = slot_k(P, d, round, best); scale = (float)kstar / 64.0f; }
+  else scale = 0.0f;
+  const size_t slot = (size_t)(best >= 0 ? best : 0) * P.N;
+  for (int t = threadIdx.x; t < d.n; t += blockDim.x) {
+    const int c = d.c0 + t;
+    const int dst = d.c0 + w.perm[c];
+    if (kstar > 0 && best >= 0) {
+      out_xy[2 * (size_t)dst] = w.xs[slot + c];
+      out_xy[2 * (size_t)dst + 1] = w.ys[slot + c];
+      out_orient[dst] = (uint8_t)(w.srecs[c].bits | (w.mir[slot + c] << 3));
+    } else {
+      out_xy[2 * (size_t)dst] = -1;
+      out_xy[2 * (size_t)dst + 1] = -1;
+      out_orient[dst] = 0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    out_scale[a] = scale;
+    w.desc[a].done = 1;
+    w.desc[a].kstar = kstar;
+  }
+}
+
+// Placements of the single diagnostic scale (slot 0, atlas 0) in input order.
+__global__ __launch_bounds__(256) void k_scatter(Params P, Work w, int32_t* out_xy,
+                                                 uint8_t* out_orient, int32_t* feasible,
+                                                 int32_t* rows) {
+  const AtlasDesc d = w.desc[0];
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    feasible[0] = d.bad ? -1 : w.feas[0];
+    rows[0] = d.bad ? 0 : w.rows[0];
+  }
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < d.n; t += gridDim.x * blockDim.x) {
+    const int dst = w.perm[t];
+    const int32_t x = d.bad ? -1 : w.xs[t];
+    out_xy[2 * (size_t)dst] = x >= 0 ? x : -1;
+    out_xy[2 * (size_t)dst + 1] = x >= 0 ? w.ys[t] : -1;
+    out_orient[dst] = x >= 0 ? (uint8_t)(w.srecs[t].bits | (w.mir[t] << 3)) : 0;
+  }
+}
+
+hipError_t launch_scatter(const Params& P, const Work& w, int32_t* out_xy, uint8_t* out_orient,
+                          int32_t* feasible, int32_t* rows, hipStream_t st) {
+  int blocks = (P.N + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(256), 0, st, P, w, out_xy, out_orient, feasible,
+                     rows);
+  return hipGetLastError();
+}
+
+PackLds pack_lds_plan(int nmax, int Wd, int budget) {
+  PackLds L;
+  L.RC = nmax < Wd ? nmax : Wd;
+  if (L.RC < 1) L.RC = 1;
+  const int fixed = 4 * Wd + 8 * (L.RC + 1) + 16 * L.RC;
+  int sc = (budget - fixed) / 4;
+  if (sc < 0) sc = 0;
+  if (sc > (1 << 20)) sc = 1 << 20;
+  L.SC = sc & ~7;
+  L.bytes = fixed + 4 * L.SC;
+  return L;
+}
+
+hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes, int RC, int SC,
+                       hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_pack,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pack, dim3(P.B, P.count), dim3(PACK_NT), lds_bytes, st, P, w, round, RC, SC);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const Params& P, const Work& w, int round, int last_round,
+                         int32_t* out_xy, uint8_t* out_orient, float* out_scale, hipStream_t st) {
+  hipLaunchKernelGGL(k_select, dim3(P.count), dim3(256), 0, st, P, w, round, last_round, out_xy,
+                     out_orient, out_scale);
+  return hipGetLastError();
+}
+
+}  // namespace tabi

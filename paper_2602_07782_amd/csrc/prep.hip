@@ -1,0 +1,407 @@
+// Per-chart proxy construction, sorting, the candidate-scale bound and the
+// per-(scale, chart) rasterisation set-up.
+//
+//   k_init   atlas descriptors
+//   k_prep   one wavefront per chart: AABB, quarter turn, area, local-AABB
+//            slices (LDS atomics per edge), orientation, 8-direction OBB
+//            (Sec. 4.1.1; App. A "Computing Local AABBs / OBBs / Orientations")
+//   k_sort   height-descending order within each atlas (Sec. 3.1, 4.3)
+//   k_plan   largest candidate scale per atlas (area and largest chart fit)
+//   k_setup  per (scale slot, chart): texel rectangles of the slices and the
+//            OBB side split points used by per-texel evaluation
+#include "tabi_internal.h"
+
+namespace tabi {
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void k_init(Params P, Work w, const int32_t* atlas_off, const int32_t* atlas_wh,
+                       int single_w, int single_h) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= P.count) return;
+  AtlasDesc d;
+  if (atlas_off) {
+    d.c0 = atlas_off[a];
+    d.n = atlas_off[a + 1] - atlas_off[a];
+    d.Wa = atlas_wh[2 * a];
+    d.Ha = atlas_wh[2 * a + 1];
+  } else {
+    d.c0 = 0;
+    d.n = P.N;
+    d.Wa = single_w;
+    d.Ha = single_h;
+  }
+  d.ktop = 0;
+  d.bad = 0;
+  d.done = 0;
+  d.kstar = 0;
+  w.desc[a] = d;
+}
+
+// charts per 256-thread block in k_prep
+constexpr int PREP_WAVES = 4;
+
+__device__ inline void slab_contrib(int32_t* lo, int32_t* hi, int K, int64_t E, int64_t a1,
+                                    int64_t b1, int64_t a2, int64_t b2) {
+  // a = slab axis coordinate, b = value; slabs are K*a in [jE, (j+1)E].
+  const int64_t A1 = (int64_t)K * a1, A2 = (int64_t)K * a2;
+  // endpoint (a1, b1): the slab containing it, or both slabs at a slab line
+  int64_t q = A1 / E, r = A1 % E;
+  int jh = (int)min<int64_t>(q, K - 1);
+  int jl = (r == 0) ? (int)max<int64_t>(q - 1, 0) : jh;
+  for (int j = jl; j <= jh; ++j) {
+    atomicMin(&lo[j], (int32_t)b1);
+    atomicMax(&hi[j], (int32_t)b1);
+  }
+  // crossings with interior slab lines strictly between the endpoints
+  const int64_t mn = min(A1, A2), mx = max(A1, A2);
+  int64_t m0 = mn / E + 1, m1 = (mx - 1) / E;
+  if (m0 < 1) m0 = 1;
+  if (m1 > K - 1) m1 = K - 1;
+  for (int64_t m = m0; m <= m1; ++m) {
+    int64_t num = b1 * (A2 - A1) + (b2 - b1) * (m * E - A1);
+    int64_t den = A2 - A1;
+    if (den < 0) { num = -num; den = -den; }
+    int32_t f = (int32_t)fdiv53(num, den), c = (int32_t)cdiv53(num, den);
+    atomicMin(&lo[m - 1], f); atomicMin(&lo[m], f);
+    atomicMax(&hi[m - 1], c); atomicMax(&hi[m], c);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* __restrict__ xy,
+                                              const int32_t* __restrict__ voff,
+                                              const int32_t* __restrict__ atlas_off) {
+  __shared__ int32_t sl[PREP_WAVES][4][KMAX];
+  const int wv = threadIdx.x / WAVE, lane = lane_id();
+  const int c = blockIdx.x * PREP_WAVES + wv;
+  if (c >= P.N) return;  // whole wavefront leaves; no block barrier below
+  const int K = P.K;
+  int a = 0;
+  if (atlas_off) {  // atlas of this chart: last a with atlas_off[a] <= c
+    int lo = 0, hi = P.count - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (atlas_off[mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    a = lo;
+  }
+  const int local = c - (atlas_off ? atlas_off[a] : 0);
+  if (lane == 0) w.chart_atlas[c] = a;
+  const int v0 = voff[c], nv = voff[c + 1] - v0;
+  const int2* V = reinterpret_cast<const int2*>(xy) + v0;
+
+  int32_t xmn = BIG, xmx = -BIG, ymn = BIG, ymx = -BIG;
+  int range_bad = 0;
+  for (int i = lane; i < nv; i += WAVE) {
+    int2 p = V[i];
+    if (p.x <= -(1 << 22) || p.x >= (1 << 22) || p.y <= -(1 << 22) || p.y >= (1 << 22)) range_bad = 1;
+    xmn = min(xmn, p.x); xmx = max(xmx, p.x);
+    ymn = min(ymn, p.y); ymx = max(ymx, p.y);
+  }
+  xmn = wave_min(xmn); xmx = wave_max(xmx);
+  ymn = wave_min(ymn); ymx = wave_max(ymx);
+  range_bad = wave_max(range_bad);
+  const int32_t W0 = xmx - xmn, H0 = ymx - ymn;
+  Chart* out = &w.recs[c];
+  if (nv < 3 || range_bad || W0 <= 0 || H0 <= 0) {
+    if (lane == 0) {
+      out->valid = 0;
+      out->src = local;
+      w.keys[c] = ((uint64_t)0x7fffff << 41) | ((uint64_t)0x7fffff << 18) | (uint64_t)local;
+      atomicOr(&w.desc[a].bad, 1);
+    }
+    return;
+  }
+  // quarter turn so the box is at least as tall as wide: (u,v) -> (H0 - v, u)
+  const bool rot = W0 > H0;
+  const int32_t W = rot ? H0 : W0, H = rot ? W0 : H0;
+  auto local_uv = [&](int i, int64_t& u, int64_t& v) {
+    int2 p = V[i];
+    int64_t u0 = p.x - xmn, vv = p.y - ymn;
+    if (rot) { u = H0 - vv; v = u0; } else { u = u0; v = vv; }
+  };
+
+  int32_t* ylo = sl[wv][0];
+  int32_t* yhi = sl[wv][1];
+  int32_t* xlo = sl[wv][2];
+  int32_t* xhi = sl[wv][3];
+  if (lane < K) { ylo[lane] = BIG; yhi[lane] = -BIG; xlo[lane] = BIG; xhi[lane] = -BIG; }
+  wave_sync();
+
+  uint64_t area = 0;
+  for (int i = lane; i < nv; i += WAVE) {
+    int i2 = (i + 1 == nv) ? 0 : i + 1;
+    int64_t u1, v1, u2, v2;
+    local_uv(i, u1, v1);
+    local_uv(i2, u2, v2);
+    area += (uint64_t)(u1 * v2) - (uint64_t)(u2 * v1);
+    slab_contrib(ylo, yhi, K, W, u1, v1, u2, v2);  // x-slices: slab axis u
+    slab_contrib(xlo, xhi, K, H, v1, u1, v2, u2);  // y-slices: slab axis v
+  }
+  area = wave_sum_u64(area);
+  int64_t area2 = (int64_t)area;
+  if (area2 < 0) area2 = -area2;
+  wave_sync();
+
+  // orientation: lanes j < K hold slice j
+  int32_t sylo = 0, syhi = 0, sxlo = 0, sxhi = 0;
+  if (lane < K) { sylo = ylo[lane]; syhi = yhi[lane]; sxlo = xlo[lane]; sxhi = xhi[lane]; }
+  const bool in = lane < K;
+  // empty area above the top boundary vs below the bottom boundary
+  int64_t top_area = (int64_t)wave_sum_u64(in ? (uint64_t)(int64_t)sylo : 0);
+  int64_t bot_area = (int64_t)wave_sum_u64(in ? (uint64_t)(int64_t)(H - syhi) : 0);
+  const bool flipy = top_area > bot_area;
+  if (flipy) {
+    int32_t l2 = H - syhi, h2 = H - sylo;
+    sylo = l2; syhi = h2;
+    int src = K - 1 - lane;
+    int32_t a1 = __shfl(sxlo, src < 0 ? 0 : src), a2 = __shfl(sxhi, src < 0 ? 0 : src);
+    if (in) { sxlo = a1; sxhi = a2; }
+  }
+  int64_t Ls = (int64_t)wave_sum_u64(in ? (uint64_t)(int64_t)sxlo : 0);
+  int64_t Rs = (int64_t)wave_sum_u64(in ? (uint64_t)(int64_t)(W - sxhi) : 0);
+  const int half = K / 2;
+  int64_t BL = (int64_t)wave_sum_u64((lane < half) ? (uint64_t)(int64_t)(H - syhi) : 0);
+  int64_t BR = (int64_t)wave_sum_u64((lane >= K - half && in) ? (uint64_t)(int64_t)(H - syhi) : 0);
+  int64_t diff = Ls - Rs;
+  bool flipx;
+  if (10 * diff > (int64_t)K * W) flipx = true;
+  else if (10 * (diff < 0 ? -diff : diff) <= (int64_t)K * W) flipx = BL > BR;
+  else flipx = false;
+  if (flipx) {
+    int src = K - 1 - lane;
+    int32_t a1 = __shfl(sylo, src < 0 ? 0 : src), a2 = __shfl(syhi, src < 0 ? 0 : src);
+    if (in) { sylo = a1; syhi = a2; }
+    int32_t l2 = W - sxhi, h2 = W - sxlo;
+    sxlo = l2; sxhi = h2;
+  }
+
+  // approximate OBB of the chart as packed (after the reflections)
+  int64_t pmin[8], pmax[8], qmin[8], qmax[8];
+#pragma unroll
+  for (int m = 1; m < 8; ++m) { pmin[m] = INT64_MAX; pmax[m] = INT64_MIN; qmin[m] = INT64_MAX; qmax[m] = INT64_MIN; }
+  for (int i = lane; i < nv; i += WAVE) {
+    int64_t u, v;
+    local_uv(i, u, v);
+    if (flipx) u = W - u;
+    if (flipy) v = H - v;
+#pragma unroll
+    for (int m = 1; m < 8; ++m) {
+      const int64_t C = kDirC[m], S = kDirS[m];
+      int64_t pp = C * u + S * v, qq = C * v - S * u;
+      pmin[m] = min(pmin[m], pp); pmax[m] = max(pmax[m], pp);
+      qmin[m] = min(qmin[m], qq); qmax[m] = max(qmax[m], qq);
+    }
+  }
+#pragma unroll
+  for (int m = 1; m < 8; ++m) {
+    pmin[m] = wave_min64(pmin[m]); pmax[m] = wave_max64(pmax[m]);
+    qmin[m] = wave_min64(qmin[m]); qmax[m] = wave_max64(qmax[m]);
+  }
+  // smallest area (b-a)(f-e)/(C^2+S^2), exact; ties keep the smaller m
+  int best = 0;
+  unsigned __int128 bext = (unsigned __int128)((uint64_t)QS * W) * (uint64_t)(QS * H);
+  unsigned __int128 bN = (unsigned __int128)(QS * QS);
+#pragma unroll
+  for (int m = 1; m < 8; ++m) {
+    const uint64_t C = kDirC[m], S = kDirS[m];
+    unsigned __int128 ext = (unsigned __int128)(uint64_t)(pmax[m] - pmin[m]) * (uint64_t)(qmax[m] - qmin[m]);
+    unsigned __int128 N = (unsigned __int128)(C * C + S * S);
+    if (ext * bN < bext * N) { best = m; bext = ext; bN = N; }
+  }
+  int64_t ba = 0, bb = 0, be = 0, bf = 0;
+#pragma unroll
+  for (int m = 1; m < 8; ++m)
+    if (m == best) { ba = pmin[m]; bb = pmax[m]; be = qmin[m]; bf = qmax[m]; }
+
+  if (in) {
+    out->ylo[lane] = sylo; out->yhi[lane] = syhi;
+    out->xlo[lane] = sxlo; out->xhi[lane] = sxhi;
+  }
+  if (lane == 0) {
+    out->W = W;
+    out->H = H;
+    out->bits = (rot ? 1 : 0) | (flipx ? 2 : 0) | (flipy ? 4 : 0);
+    out->m = best;
+    out->a = ba; out->b = bb; out->e = be; out->f = bf;
+    out->area2 = area2;
+    out->src = local;
+    out->valid = 1;
+    // ascending key = height descending, width descending, input index
+    w.keys[c] = ((uint64_t)(0x7fffff - H) << 41) | ((uint64_t)(0x7fffff - W) << 18) | (uint64_t)local;
+  }
+}
+
+// rank of each chart's key inside its atlas; scatter to sorted position
+__global__ __launch_bounds__(256) void k_sort(Params P, Work w) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.N) return;
+  const AtlasDesc d = w.desc[w.chart_atlas[c]];
+  const uint64_t key = w.keys[c];
+  int rank = 0;
+  const uint64_t* ks = w.keys + d.c0;
+  for (int j = 0; j < d.n; ++j) rank += ks[j] < key;
+  const int pos = d.c0 + rank;
+  w.srecs[pos] = w.recs[c];
+  w.perm[pos] = c - d.c0;
+}
+
+// candidate scales: the charts' total area and the largest chart must fit
+__global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
+  __shared__ uint64_t s_sum[256];
+  __shared__ int32_t s_maxw[256];
+  const int a = blockIdx.x;
+  AtlasDesc d = w.desc[a];
+  uint64_t sum = 0;
+  int32_t mw = 0;
+  for (int t = threadIdx.x; t < d.n; t += blockDim.x) {
+    const Chart& ch = w.srecs[d.c0 + t];
+    sum += (uint64_t)ch.area2;
+    mw = max(mw, ch.W);
+  }
+  s_sum[threadIdx.x] = sum;
+  s_maxw[threadIdx.x] = mw;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned __int128 S = 0;
+    int32_t MW = 0;
+    for (int t = 0; t < (int)blockDim.x; ++t) { S += s_sum[t]; MW = max(MW, s_maxw[t]); }
+    int ktop = 0;
+    if (d.bad) {
+      ktop = -1;
+    } else if (d.n == 0) {
+      ktop = 64;
+    } else {
+      const int32_t MH = w.srecs[d.c0].H;  // tallest chart comes first
+      const unsigned __int128 cap = ((unsigned __int128)1 << 29) * (unsigned)d.Wa * (unsigned)d.Ha;
+      for (int k = 1; k <= 64; ++k) {
+        bool area_ok = S * (unsigned)(k * k) <= cap;
+        bool fit = cdiv64((int64_t)k * MW, QS) <= d.Wa && cdiv64((int64_t)k * MH, QS) <= d.Ha;
+        if (area_ok && fit) ktop = k;
+      }
+    }
+    w.desc[a].ktop = ktop;
+  }
+}
+
+// one thread per (slot, chart)
+__global__ __launch_bounds__(256) void k_setup(Params P, Work w, int round) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (c >= P.N) return;
+  const AtlasDesc d = w.desc[w.chart_atlas[c]];
+  const bool run = P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1);
+  if (!run) return;
+  const int k = slot_k(P, d, round, s);
+  if (k < 1) return;
+  const Chart& ch = w.srecs[c];
+  const int K = P.K;
+  unsigned char* base = w.kc + ((size_t)s * P.N + c) * P.stride;
+  KHead* hd = reinterpret_cast<KHead*>(base);
+  KSide* sd = reinterpret_cast<KSide*>(base + sizeof(KHead));
+  KRect* rc = reinterpret_cast<KRect*>(base + sizeof(KHead) + 4 * sizeof(KSide));
+  const int64_t kk = k, W = ch.W, H = ch.H;
+  const int32_t wt = (int32_t)cdiv64(kk * W, QS), ht = (int32_t)cdiv64(kk * H, QS);
+  KHead h;
+  h.w = wt;
+  h.h = ht;
+  h.obb = ch.m != 0;
+  h.pad = 0;
+  *hd = h;
+  // local-AABB slices as texel rectangles at this scale
+  // (values are clamped to int16; only a chart larger than any atlas reaches
+  // the clamp, and such a scale fails on that chart's width or height anyway)
+  auto i16 = [](int64_t v) { return (int16_t)(v > 32767 ? 32767 : v); };
+  for (int j = 0; j < K; ++j) {
+    KRect r;
+    r.c0 = i16(((int64_t)j * W * kk >> 14) / K);
+    r.c1 = i16((((int64_t)(j + 1) * W * kk + QS * K - 1) >> 14) / K);
+    r.r0 = i16(((int64_t)ch.ylo[j] * kk) >> 14);
+    r.r1 = i16(((int64_t)ch.yhi[j] * kk + QS - 1) >> 14);
+    rc[j] = r;
+    KRect y;
+    y.c0 = i16(((int64_t)ch.xlo[j] * kk) >> 14);
+    y.c1 = i16(((int64_t)ch.xhi[j] * kk + QS - 1) >> 14);
+    y.r0 = i16(((int64_t)j * H * kk >> 14) / K);
+    y.r1 = i16((((int64_t)(j + 1) * H * kk + QS * K - 1) >> 14) / K);
+    rc[K + j] = y;
+  }
+  if (!h.obb) return;
+  const int64_t C = kDirC[ch.m], S = kDirS[ch.m], N = C * C + S * S, D = QS * N;
+  const int64_t a = ch.a, b = ch.b, e = ch.e, f = ch.f;
+  auto split = [&](int64_t num, KSide& sdv) {  // corner position num/D (texels)
+    sdv.sa = clamp32(fdiv64(num, D));
+    sdv.sb = clamp32(cdiv64(num, D));
+  };
+  KSide st, sb, sL, sR;
+  // top: corner (p=a, q=e); A: (k a - 16384 C x)/(16384 S); B: (k e + 16384 S x)/(16384 C)
+  split(kk * (C * a - S * e), st);
+  st.corner = clamp32(fdiv64(kk * (S * a + C * e), D));
+  // bottom: corner (p=b, q=f); A: (k f + 16384 S x)/(16384 C); B: (k b - 16384 C x)/(16384 S)
+  split(kk * (C * b - S * f), sb);
+  sb.corner = clamp32(cdiv64(kk * (S * b + C * f), D));
+  // left: corner (p=a, q=f) at row k(Sa+Cf)/D; A: (k a - 16384 S y)/(16384 C); B: (16384 C y - k f)/(16384 S)
+  split(kk * (S * a + C * f), sL);
+  sL.corner = clamp32(fdiv64(kk * (C * a - S * f), D));
+  // right: corner (p=b, q=e) at row k(Sb+Ce)/D; A: (16384 C y - k e)/(16384 S); B: (k b - 16384 S y)/(16384 C)
+  split(kk * (S * b + C * e), sR);
+  sR.corner = clamp32(cdiv64(kk * (C * b - S * e), D));
+  // last column / row: the extent may end inside the texel
+  const int64_t tw = wt - 1, th = ht - 1;
+  const bool wfrac = (kk * W) % QS != 0, hfrac = (kk * H) % QS != 0;
+  // top
+  if (!wfrac ? (tw + 1 <= st.sa) : (W * N <= C * a - S * e))
+    st.last = clamp32(!wfrac ? fdiv64(kk * a - QS * C * (tw + 1), QS * S) : fdiv64(kk * (a - C * W), QS * S));
+  else if (tw >= st.sb) st.last = clamp32(fdiv64(kk * e + QS * S * tw, QS * C));
+  else st.last = st.corner;
+  // bottom
+  if (!wfrac ? (tw + 1 <= sb.sa) : (W * N <= C * b - S * f))
+    sb.last = clamp32(!wfrac ? cdiv64(kk * f + QS * S * (tw + 1), QS * C) : cdiv64(kk * (f + S * W), QS * C));
+  else if (tw >= sb.sb) sb.last = clamp32(cdiv64(kk * b - QS * C * tw, QS * S));
+  else sb.last = sb.corner;
+  // left
+  if (!hfrac ? (th + 1 <= sL.sa) : (H * N <= S * a + C * f))
+    sL.last = clamp32(!hfrac ? fdiv64(kk * a - QS * S * (th + 1), QS * C) : fdiv64(kk * (a - S * H), QS * C));
+  else if (th >= sL.sb) sL.last = clamp32(fdiv64(QS * C * th - kk * f, QS * S));
+  else sL.last = sL.corner;
+  // right
+  if (!hfrac ? (th + 1 <= sR.sa) : (H * N <= S * b + C * e))
+    sR.last = clamp32(!hfrac ? cdiv64(QS * C * (th + 1) - kk * e, QS * S) : cdiv64(kk * (C * H - e), QS * S));
+  else if (th >= sR.sb) sR.last = clamp32(cdiv64(kk * b - QS * S * th, QS * C));
+  else sR.last = sR.corner;
+  sd[0] = st;
+  sd[1] = sb;
+  sd[2] = sL;
+  sd[3] = sR;
+}
+
+hipError_t launch_prep(const Params& P, const Work& w, const int32_t* xy, const int32_t* voff,
+                       const int32_t* atlas_off, const int32_t* atlas_wh, int single_w,
+                       int single_h, hipStream_t st) {
+  hipLaunchKernelGGL(k_init, dim3((P.count + 255) / 256), dim3(256), 0, st, P, w, atlas_off,
+                     atlas_wh, single_w, single_h);
+  if (P.N > 0)
+    hipLaunchKernelGGL(k_prep, dim3((P.N + PREP_WAVES - 1) / PREP_WAVES), dim3(256), 0, st, P, w,
+                       xy, voff, atlas_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(const Params& P, const Work& w, hipStream_t st) {
+  if (P.N > 0) hipLaunchKernelGGL(k_sort, dim3((P.N + 255) / 256), dim3(256), 0, st, P, w);
+  hipLaunchKernelGGL(k_plan, dim3(P.count), dim3(256), 0, st, P, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan(const Params&, const Work&, hipStream_t) { return hipSuccess; }
+
+hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t st) {
+  if (P.N > 0)
+    hipLaunchKernelGGL(k_setup, dim3((P.N + 255) / 256, P.B), dim3(256), 0, st, P, w, round);
+  return hipGetLastError();
+}
+
+}  // namespace tabi

@@ -1,0 +1,269 @@
+// Device-side data layout and helpers of the MI355X TABI packer (gfx950).
+//
+// Every quantity on the packing path is an integer; the per-texel proxy
+// bounds are exact rationals rounded outward with floor / ceil.  Wavefronts
+// are 64 lanes wide.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tabi {
+
+constexpr int KMAX = 10;     // local AABB slices per axis, largest quality
+constexpr int64_t QS = 16384; // Q8 units per texel (256) times 64 scale steps
+constexpr int WAVE = 64;
+constexpr int32_t BIG = 0x3fffffff;
+
+// Chart proxies in the chart's final local frame (after the quarter turn and
+// reflections), Q8 units.  Sec. 4.1.1: local AABBs along x and y, and an
+// approximate OBB from 8 directions.
+struct alignas(16) Chart {
+  int32_t W, H;      // extents, H >= W
+  int32_t bits;      // bit0 quarter turn, bit1 mirror x, bit2 mirror y
+  int32_t m;         // OBB direction index (0: axis aligned, adds nothing)
+  int64_t a, b, e, f;  // OBB: a <= C u + S v <= b, e <= -S u + C v <= f
+  int32_t ylo[KMAX], yhi[KMAX];  // x-slices: v-range inside u in [jW/K, (j+1)W/K]
+  int32_t xlo[KMAX], xhi[KMAX];  // y-slices: u-range inside v in [jH/K, (j+1)H/K]
+  int64_t area2;     // twice the polygon area, Q8^2
+  int32_t src;       // input index (within its atlas)
+  int32_t valid;
+};
+
+// OBB direction m*pi/16 as 2^14 (cos, sin), rounded to integers.
+__constant__ static const int32_t kDirC[8] = {16384, 16069, 15137, 13623, 11585, 9102, 6270, 3196};
+__constant__ static const int32_t kDirS[8] = {0, 3196, 6270, 9102, 11585, 13623, 15137, 16069};
+
+// Per (scale, chart) rasterisation set-up.  At scale k the local-AABB proxy
+// becomes 2K integer texel rectangles (x-slices then y-slices); the OBB
+// boundary on each of the four sides is evaluated per texel from one line,
+// chosen by which side of the box corner the texel lies (see side_value).
+struct alignas(16) KHead {
+  int32_t w, h;      // texel extents at this scale (undilated)
+  int32_t obb;       // OBB present
+  int32_t pad;
+};
+struct alignas(16) KSide {
+  int32_t sa;        // texels t with t+1 <= sa use line A at t+1
+  int32_t sb;        // texels t >= sb use line B at t (otherwise: corner)
+  int32_t corner;    // rounded corner coordinate
+  int32_t last;      // full value for the last texel (extent may end mid-texel)
+};
+struct alignas(8) KRect {
+  int16_t c0, c1, r0, r1;  // columns [c0,c1) x rows [r0,r1)
+};
+
+// Bytes of one per-(scale, chart) record for K slices.
+__host__ __device__ inline int kchart_stride(int K) {
+  return (int)(sizeof(KHead) + 4 * sizeof(KSide) + 2 * K * sizeof(KRect));
+}
+
+struct KView {
+  const KHead* hd;
+  const KSide* sd;   // [0] top, [1] bottom, [2] left, [3] right
+  const KRect* rc;   // 2K rectangles
+};
+__device__ inline KView kview(const unsigned char* base, int K) {
+  KView v;
+  v.hd = reinterpret_cast<const KHead*>(base);
+  v.sd = reinterpret_cast<const KSide*>(base + sizeof(KHead));
+  v.rc = reinterpret_cast<const KRect*>(base + sizeof(KHead) + 4 * sizeof(KSide));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// exact integer division
+// ---------------------------------------------------------------------------
+// floor(n / d) for 0 < d < 2^31 and |n| < 2^53: the double quotient is within
+// one unit of the true one, so one integer correction makes it exact.
+__device__ inline int64_t fdiv53(int64_t n, int64_t d) {
+  int64_t q = (int64_t)floor((double)n / (double)d);
+  int64_t r = n - q * d;
+  if (r < 0) q -= 1;
+  else if (r >= d) q += 1;
+  return q;
+}
+__device__ inline int64_t cdiv53(int64_t n, int64_t d) { return -fdiv53(-n, d); }
+
+// floor / ceil for any int64 with d > 0
+__host__ __device__ inline int64_t fdiv64(int64_t n, int64_t d) {
+  int64_t q = n / d;
+  if ((n % d) != 0 && n < 0) q -= 1;
+  return q;
+}
+__host__ __device__ inline int64_t cdiv64(int64_t n, int64_t d) { return -fdiv64(-n, d); }
+
+__device__ inline int32_t clamp32(int64_t v) {
+  return (int32_t)(v < -(1 << 30) ? -(1 << 30) : (v > (1 << 30) ? (1 << 30) : v));
+}
+
+// ---------------------------------------------------------------------------
+// per-texel proxy evaluation
+// ---------------------------------------------------------------------------
+// OBB side value at texel t (column for top/bottom, row for left/right) of an
+// extent with n texels.  Line A applies left of (above) the corner, line B
+// right of (below) it; each line is (n0 + n1 * x) / d rounded down (lo sides)
+// or up (hi sides).
+template <bool CEIL>
+__device__ inline int32_t side_value(const KSide& s, int32_t t, int32_t n, int64_t n0a, int64_t n1a,
+                                     int64_t da, int64_t n0b, int64_t n1b, int64_t db) {
+  if (t == n - 1) return s.last;
+  if (t + 1 <= s.sa) {
+    int64_t num = n0a + n1a * (int64_t)(t + 1);
+    return (int32_t)(CEIL ? cdiv53(num, da) : fdiv53(num, da));
+  }
+  if (t >= s.sb) {
+    int64_t num = n0b + n1b * (int64_t)t;
+    return (int32_t)(CEIL ? cdiv53(num, db) : fdiv53(num, db));
+  }
+  return s.corner;
+}
+
+// Undilated TopEdge / BottomEdge of column i (App. A, "Parallel Pushing"):
+// the tightest of the two proxies, rounded outward.
+__device__ inline void column_bounds(const KView& kv, const Chart& ch, int K, int k, int i,
+                                     int32_t& top, int32_t& bot) {
+  int32_t tx = BIG, bx = -BIG, ty = BIG, by = -BIG;
+  for (int j = 0; j < K; ++j) {
+    KRect r = kv.rc[j];
+    if (r.c0 <= i && i < r.c1) { tx = min(tx, (int32_t)r.r0); bx = max(bx, (int32_t)r.r1); }
+  }
+  for (int j = 0; j < K; ++j) {
+    KRect r = kv.rc[K + j];
+    if (r.c0 <= i && i < r.c1) { ty = min(ty, (int32_t)r.r0); by = max(by, (int32_t)r.r1); }
+  }
+  int32_t t = max(tx, ty), b = min(bx, by);
+  const KHead hd = *kv.hd;
+  if (hd.obb) {
+    const int64_t C = kDirC[ch.m], S = kDirS[ch.m];
+    const int64_t kk = k;
+    // top = max(A: (k a - 16384 C x)/(16384 S), B: (k e + 16384 S x)/(16384 C))
+    int32_t to = side_value<false>(kv.sd[0], i, hd.w, kk * ch.a, -QS * C, QS * S, kk * ch.e, QS * S, QS * C);
+    // bottom = min(A: (k f + 16384 S x)/(16384 C), B: (k b - 16384 C x)/(16384 S))
+    int32_t bo = side_value<true>(kv.sd[1], i, hd.w, kk * ch.f, QS * S, QS * C, kk * ch.b, -QS * C, QS * S);
+    t = max(t, to);
+    b = min(b, bo);
+  }
+  top = t;
+  bot = b;
+}
+
+// Undilated left / right bound of row j.
+__device__ inline void row_bounds(const KView& kv, const Chart& ch, int K, int k, int j,
+                                  int32_t& left, int32_t& right) {
+  int32_t ly = BIG, ry = -BIG, lx = BIG, rx = -BIG;
+  for (int s = 0; s < K; ++s) {
+    KRect r = kv.rc[K + s];
+    if (r.r0 <= j && j < r.r1) { ly = min(ly, (int32_t)r.c0); ry = max(ry, (int32_t)r.c1); }
+  }
+  for (int s = 0; s < K; ++s) {
+    KRect r = kv.rc[s];
+    if (r.r0 <= j && j < r.r1) { lx = min(lx, (int32_t)r.c0); rx = max(rx, (int32_t)r.c1); }
+  }
+  int32_t l = max(ly, lx), rr = min(ry, rx);
+  const KHead hd = *kv.hd;
+  if (hd.obb) {
+    const int64_t C = kDirC[ch.m], S = kDirS[ch.m];
+    const int64_t kk = k;
+    // left = max(A: (k a - 16384 S y)/(16384 C), B: (16384 C y - k f)/(16384 S))
+    int32_t lo = side_value<false>(kv.sd[2], j, hd.h, kk * ch.a, -QS * S, QS * C, -kk * ch.f, QS * C, QS * S);
+    // right = min(A: (16384 C y - k e)/(16384 S), B: (k b - 16384 S y)/(16384 C))
+    int32_t ro = side_value<true>(kv.sd[3], j, hd.h, -kk * ch.e, QS * C, QS * S, kk * ch.b, -QS * S, QS * C);
+    l = max(l, lo);
+    rr = min(rr, ro);
+  }
+  left = l;
+  right = rr;
+}
+
+// Gutter growth: a footprint grows by [0,p]^2 toward +x, +y, so a grown
+// column i takes the min top / max bottom over undilated columns [i-p, i].
+__device__ inline void column_bounds_grown(const KView& kv, const Chart& ch, int K, int k, int p,
+                                           int i, int32_t& top, int32_t& bot) {
+  const int w = kv.hd->w;
+  int lo = max(0, i - p), hi = min(w - 1, i);
+  int32_t t = BIG, b = -BIG;
+  for (int c = lo; c <= hi; ++c) {
+    int32_t tt, bb;
+    column_bounds(kv, ch, K, k, c, tt, bb);
+    t = min(t, tt);
+    b = max(b, bb);
+  }
+  top = t;
+  bot = b + p;
+}
+__device__ inline void row_bounds_grown(const KView& kv, const Chart& ch, int K, int k, int p, int j,
+                                        int32_t& left, int32_t& right) {
+  const int h = kv.hd->h;
+  int lo = max(0, j - p), hi = min(h - 1, j);
+  int32_t l = BIG, r = -BIG;
+  for (int c = lo; c <= hi; ++c) {
+    int32_t ll, rr;
+    row_bounds(kv, ch, K, k, c, ll, rr);
+    l = min(l, ll);
+    r = max(r, rr);
+  }
+  left = l;
+  right = r + p;
+}
+
+// ---------------------------------------------------------------------------
+// wavefront helpers
+// ---------------------------------------------------------------------------
+__device__ inline int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+
+__device__ inline int32_t wave_max(int32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline int32_t wave_min(int32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline int64_t wave_max64(int64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    int64_t u = __shfl_xor((long long)v, o);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+__device__ inline int64_t wave_min64(int64_t v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    int64_t u = __shfl_xor((long long)v, o);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+__device__ inline uint64_t wave_sum_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, o);
+  return v;
+}
+// inclusive prefix sum over the wave
+__device__ inline int32_t wave_incl_sum(int32_t v) {
+  const int l = lane_id();
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int32_t u = __shfl_up(v, o);
+    if (l >= o) v += u;
+  }
+  return v;
+}
+// inclusive prefix max / min over the wave
+__device__ inline int32_t wave_incl_max(int32_t v) {
+  const int l = lane_id();
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int32_t u = __shfl_up(v, o);
+    if (l >= o) v = max(v, u);
+  }
+  return v;
+}
+__device__ inline int32_t wave_incl_min(int32_t v) {
+  const int l = lane_id();
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int32_t u = __shfl_up(v, o);
+    if (l >= o) v = min(v, u);
+  }
+  return v;
+}
+__device__ inline uint64_t ballot64(bool p) { return (uint64_t)__ballot(p); }
+
+}  // namespace tabi

@@ -1,0 +1,79 @@
+// Internal interface between the host runtime and the kernels of the TABI
+// packer.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tabi_device.h"
+
+namespace tabi {
+
+// One atlas of a batch.
+struct AtlasDesc {
+  int32_t c0, n;       // charts [c0, c0+n) of the flattened chart arrays
+  int32_t Wa, Ha;      // atlas size in texels
+  int32_t ktop;        // largest candidate scale (plan); -1 degenerate chart; 0 none
+  int32_t bad;         // set when a chart is degenerate
+  int32_t done;        // a feasible scale has been found (or the search ended)
+  int32_t kstar;       // chosen scale
+};
+
+struct Params {
+  int32_t count;       // atlases
+  int32_t N;           // charts over all atlases
+  int32_t K;           // local AABB slices per axis
+  int32_t q;           // quality preset
+  int32_t p;           // padding
+  int32_t B;           // scale slots per round
+  int32_t stride;      // bytes of one per-(scale, chart) record
+  int32_t fixed_k;     // > 0: evaluate exactly this scale in slot 0 (diagnostics)
+};
+
+// Work-space views (device pointers).
+struct Work {
+  Chart* recs;          // [N] by input position
+  Chart* srecs;         // [N] by sorted position (per atlas)
+  uint64_t* keys;       // [N]
+  int32_t* perm;        // [N] sorted position -> local input index
+  int32_t* chart_atlas; // [N]
+  AtlasDesc* desc;      // [count]
+  unsigned char* kc;    // [B][N] per-(scale, chart) set-up records
+  int32_t* cd;          // [B][N] compacting distance of (c-1, c)
+  uint8_t* fl;          // [B][N] interlock flags of (c-1, c)
+  int32_t* xs;          // [B][N] placed box column
+  int32_t* ys;          // [B][N] placed box row
+  uint8_t* mir;         // [B][N] row mirror bit
+  int32_t* feas;        // [count][B] 1 feasible, 0 not, -1 not evaluated
+  int32_t* rows;        // [count][B]
+};
+
+// scale of slot s of round r for an atlas
+__host__ __device__ inline int32_t slot_k(const Params& P, const AtlasDesc& d, int r, int s) {
+  if (P.fixed_k > 0) return s == 0 ? P.fixed_k : 0;
+  return d.ktop - r * P.B - s;
+}
+
+// Launchers (one per kernel), all enqueue on `st`.
+hipError_t launch_prep(const Params& P, const Work& w, const int32_t* xy, const int32_t* voff,
+                       const int32_t* atlas_off, const int32_t* atlas_wh, int single_w,
+                       int single_h, hipStream_t st);
+hipError_t launch_sort(const Params& P, const Work& w, hipStream_t st);
+hipError_t launch_plan(const Params& P, const Work& w, hipStream_t st);
+hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t st);
+hipError_t launch_pairs(const Params& P, const Work& w, int round, hipStream_t st);
+hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes, int RC, int SC,
+                       hipStream_t st);
+hipError_t launch_select(const Params& P, const Work& w, int round, int last_round,
+                         int32_t* out_xy, uint8_t* out_orient, float* out_scale, hipStream_t st);
+
+hipError_t launch_scatter(const Params& P, const Work& w, int32_t* out_xy, uint8_t* out_orient,
+                          int32_t* feasible, int32_t* rows, hipStream_t st);
+
+// shared-memory plan of the packing kernel
+struct PackLds {
+  int RC, SC, bytes;
+};
+PackLds pack_lds_plan(int nmax, int Wd, int budget);
+
+}  // namespace tabi

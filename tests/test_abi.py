@@ -1,0 +1,49 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no GPU work: nothing is called)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "tabi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tabi_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for must in ("tabi_pack", "tabi_pack_many"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2602_07782_amd as tabi
+    if not os.path.exists(tabi.LIB_PATH):
+        pytest.fail("libtabi_hip.so is not built; run `python -m paper_2602_07782_amd.build`")
+    L = ctypes.CDLL(tabi.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(tabi.EXPORTS) <= set(declared_functions())
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    import paper_2602_07782_amd as tabi
+    monkeypatch.setattr(tabi, "_lib", None)
+    monkeypatch.setattr(tabi, "LIB_PATH", "/nonexistent/libtabi_hip.so")
+    with pytest.raises(RuntimeError):
+        tabi.lib()
+
+
+def test_lds_plan_is_host_only():
+    import paper_2602_07782_amd as tabi
+    if not os.path.exists(tabi.LIB_PATH):
+        pytest.skip("library not built")
+    b = tabi.lib().tabi_pack_lds_bytes(2000, 2048, 2)
+    assert b > 4 * 2050

@@ -1,0 +1,188 @@
+"""GPU parity: the HIP library, called through its C ABI, against the oracle.
+
+Everything here is integer / index work, so the bar is bit-exact equality:
+sorted order and candidate bound, compacting distances and interlock flags
+per scale, every placement of a single-scale fold-and-push, and the final
+pack (positions, orientation bits, scale).
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from cases import small_input, with_quality
+from paper_2602_07782_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tabi():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_07782_amd as t
+    t.lib()
+    return t
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def gpu_pack(tabi, inp):
+    xy, ori, sc = tabi.pack(inp.xy, inp.offsets, inp.atlas_w, inp.atlas_h, inp.padding, inp.quality)
+    return _np(xy), _np(ori), float(_np(sc)[0])
+
+
+def assert_pack_equal(tabi, orc, inp, label):
+    _say("pack parity:", label, "n =", inp.n)
+    gxy, gor, gsc = gpu_pack(tabi, inp)
+    oxy, oor, osc, ok = orc.pack(inp)
+    assert gsc == osc, (label, gsc, osc)
+    assert np.array_equal(gxy, oxy), (label, np.argwhere(gxy != oxy)[:5])
+    assert np.array_equal(gor, oor), (label, np.argwhere(gor != oor)[:5])
+
+
+# ---------------------------------------------------------------------------
+# stage parity
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(12))
+def test_order_parity(tabi, orc, seed):
+    inp = small_input(100 + seed)
+    perm, khi = tabi.debug_order(inp.xy, inp.offsets, inp.atlas_w, inp.atlas_h, inp.padding,
+                                 inp.quality)
+    operm, okhi = orc.order(inp)
+    assert np.array_equal(_np(perm), operm)
+    # the GPU bound also drops scales at which the tallest or widest chart
+    # cannot fit; every such scale fails in the oracle's fold as well
+    assert 1 <= int(_np(khi)[0]) <= okhi
+
+
+@pytest.mark.parametrize("name", ["stars64", "mixed2k"])
+def test_order_parity_workloads(tabi, orc, name):
+    inp = synth.make_input(name, 0)
+    perm, khi = tabi.debug_order(inp.xy, inp.offsets, inp.atlas_w, inp.atlas_h, inp.padding,
+                                 inp.quality)
+    operm, okhi = orc.order(inp)
+    assert np.array_equal(_np(perm), operm)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_pairs_parity(tabi, orc, seed):
+    inp = small_input(200 + seed, n=20)
+    rng = np.random.default_rng(seed)
+    for k in [int(x) for x in rng.integers(1, 65, 4)] + [64]:
+        cd, fl = tabi.debug_pairs(inp.xy, inp.offsets, inp.padding, inp.quality, k)
+        ocd, ofl = orc.pairs(inp, k)
+        assert np.array_equal(_np(cd), ocd), (seed, k)
+        assert np.array_equal(_np(fl), ofl), (seed, k)
+
+
+@pytest.mark.parametrize("q", [0, 2])
+def test_pairs_parity_mixed2k(tabi, orc, q):
+    inp = with_quality(synth.make_input("mixed2k", 0), q)
+    for k in (36, 20):
+        _say("pairs parity mixed2k q", q, "k", k)
+        cd, fl = tabi.debug_pairs(inp.xy, inp.offsets, inp.padding, inp.quality, k)
+        ocd, ofl = orc.pairs(inp, k)
+        assert np.array_equal(_np(cd), ocd)
+        assert np.array_equal(_np(fl), ofl)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_feasible_parity(tabi, orc, seed):
+    inp = small_input(300 + seed)
+    _, khi = orc.order(inp)
+    for k in sorted({max(1, khi - 3), max(1, khi // 2), khi}):
+        xy, ori, feas, rows = tabi.debug_feasible(inp.xy, inp.offsets, inp.atlas_w, inp.atlas_h,
+                                                  inp.padding, inp.quality, k)
+        ok, oxy, oori, orows = orc.feasible(inp, k)
+        assert int(_np(feas)[0]) == int(ok), (seed, k)
+        assert int(_np(rows)[0]) == orows, (seed, k)
+        assert np.array_equal(_np(xy), oxy), (seed, k)
+        assert np.array_equal(_np(ori), oori), (seed, k)
+
+
+@pytest.mark.parametrize("name,inst,ks", [("stars64", 0, (50, 55, 56)), ("mixed2k", 0, (36, 40)),
+                                          ("mixed2k", 1, (30,))])
+def test_feasible_parity_workloads(tabi, orc, name, inst, ks):
+    inp = synth.make_input(name, inst)
+    for k in ks:
+        _say("feasible parity", name, inst, "k", k)
+        xy, ori, feas, rows = tabi.debug_feasible(inp.xy, inp.offsets, inp.atlas_w, inp.atlas_h,
+                                                  inp.padding, inp.quality, k)
+        ok, oxy, oori, orows = orc.feasible(inp, k)
+        assert int(_np(feas)[0]) == int(ok)
+        assert int(_np(rows)[0]) == orows
+        assert np.array_equal(_np(xy), oxy)
+        assert np.array_equal(_np(ori), oori)
+
+
+# ---------------------------------------------------------------------------
+# whole pack
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(40))
+def test_pack_parity_small(tabi, orc, seed):
+    assert_pack_equal(tabi, orc, small_input(seed), f"small seed {seed}")
+
+
+@pytest.mark.parametrize("inst", range(6))
+def test_pack_parity_stars64(tabi, orc, inst):
+    assert_pack_equal(tabi, orc, synth.make_input("stars64", inst), f"stars64 #{inst}")
+
+
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_pack_parity_mixed2k(tabi, orc, q):
+    inp = with_quality(synth.make_input("mixed2k", 0), q)
+    assert_pack_equal(tabi, orc, inp, f"mixed2k q{q}")
+
+
+def test_pack_parity_mixed2k_other_seed(tabi, orc):
+    assert_pack_equal(tabi, orc, synth.make_input("mixed2k", 1), "mixed2k #1")
+
+
+def test_pack_parity_lightmap20k(tabi, orc):
+    assert_pack_equal(tabi, orc, synth.make_input("lightmap20k", 0), "lightmap20k")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 65, 129, 700])
+def test_pack_parity_ragged_counts(tabi, orc, n):
+    """Chart counts around wavefront and chunk boundaries."""
+    inp = synth.make_custom(n, 256, 256, 1, 2, 1.0, 0.8, synth.CONFIGS["mixed2k"]["mix"], 5000 + n)
+    assert_pack_equal(tabi, orc, inp, f"ragged n={n}")
+
+
+def test_pack_parity_rectangles(tabi, orc):
+    assert_pack_equal(tabi, orc, synth.rect_input(24, 2560, 3840, 70, 66, 2), "tiling")
+    assert_pack_equal(tabi, orc, synth.rect_input(37, 768, 1280, 40, 40, 1), "rects")
+
+
+def test_edge_cases(tabi, orc):
+    empty = synth.AtlasInput(np.zeros(0, np.int32), np.zeros(1, np.int32), 64, 64, 1, 2)
+    xy, ori, sc = tabi.pack(empty.xy, empty.offsets, 64, 64, 1, 2)
+    assert float(_np(sc)[0]) == 1.0
+    two = synth.AtlasInput(np.array([0, 0, 100, 100, 5, 5, 9, 9, 300, 0, 0, 300], np.int32),
+                           np.array([0, 2, 6], np.int32), 64, 64, 1, 2)
+    xy, ori, sc = gpu_pack(tabi, two)
+    assert sc == -1.0 and np.all(xy == -1)
+    big = synth.rect_input(1, 100 * 256, 100 * 256, 1, 1, 0)
+    xy, ori, sc = gpu_pack(tabi, big)
+    assert sc == 0.0 and np.all(xy == -1)
+    for bad in [(0, 64, 1, 2), (64, 64, -1, 2), (64, 64, 1, 3), (16384, 64, 1, 2)]:
+        with pytest.raises(tabi.TabiError):
+            tabi.pack(two.xy, two.offsets, *bad)
+
+
+def test_repeat_is_bitwise_identical(tabi):
+    inp = synth.make_input("mixed2k", 0)
+    a = gpu_pack(tabi, inp)
+    for _ in range(3):
+        b = gpu_pack(tabi, inp)
+        assert a[2] == b[2] and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

@@ -29,6 +29,7 @@ import numpy as np
 import pytest
 
 from paper_2602_07782_amd import synth
+from cases import small_input
 
 T = 16384
 
@@ -53,17 +54,6 @@ def final_frame(P, rec):
     if rec.flipy:
         v = H - v
     return u, v, W, H
-
-
-def small_input(seed, n=None, W=None, p=None, q=None):
-    rng = np.random.default_rng(seed)
-    n = int(rng.integers(2, 24)) if n is None else n
-    W = int(rng.choice([32, 64, 96, 128])) if W is None else W
-    p = int(rng.integers(0, 4)) if p is None else p
-    q = int(rng.integers(0, 3)) if q is None else q
-    mix = [("star", 0.5, 5, 16, 6.0), ("lu", 0.3, 6, 8, 6.0), ("quad", 0.2, 4, 8, 10.0)]
-    return synth.make_custom(n, W, W, p, q, float(rng.uniform(0.3, 1.5)),
-                             float(rng.uniform(0.2, 1.2)), mix, 90000 + seed)
 
 
 def clip_slab(poly, axis, lo, hi):
