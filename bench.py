@@ -48,6 +48,90 @@ def cpu_baseline(inp, seconds):
     return dt * 1000.0 / reps, reps, out
 
 
+def batched_leg(tabi, torch, count=256, reps=3):
+    """The batch workload: `count` atlases (sides 512/1024/2048, 50-5,000
+    charts each, 2,000-chart recipe) in one tabi_pack_many, captured in a HIP
+    graph and replayed, against the same atlases through tabi_pack back to
+    back on one stream."""
+    import numpy as np
+    from paper_2602_07782_amd import synth
+    inputs = synth.make_batch(count)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    plain_in = [(torch.from_numpy(np.ascontiguousarray(i.xy, np.int32)).to(dev),
+                 torch.from_numpy(np.ascontiguousarray(i.offsets, np.int32)).to(dev)) for i in inputs]
+    plain_out = [(torch.empty((i.n, 2), dtype=torch.int32, device=dev),
+                  torch.empty(i.n, dtype=torch.uint8, device=dev),
+                  torch.empty(1, dtype=torch.float32, device=dev)) for i in inputs]
+
+    def plain_pass():
+        for inp, (xy, off), (oxy, oor, osc) in zip(inputs, plain_in, plain_out):
+            tabi.pack_into(xy, off, inp.n, inp.atlas_w, inp.atlas_h, inp.padding, inp.quality,
+                           oxy, oor, osc, stream=stream)
+    plain_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_pass()
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+
+    batch = tabi.Batch(inputs)
+    s = torch.cuda.Stream()
+    s.wait_stream(stream)
+    with torch.cuda.stream(s):
+        batch.run(stream=s, use_workspace=True)
+    stream.wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        batch.run(stream=s, use_workspace=True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        g.replay()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    batched_s = ev0.elapsed_time(ev1) / 1000.0 / reps
+    same, c0 = True, 0
+    bsc = batch.out_scale.cpu().numpy()
+    for ai, (inp, (oxy, oor, osc)) in enumerate(zip(inputs, plain_out)):
+        n = inp.n
+        same &= bool(torch.equal(batch.out_xy[c0:c0 + n], oxy)) and \
+            bool(torch.equal(batch.out_orient[c0:c0 + n], oor)) and \
+            float(bsc[ai]) == float(osc.cpu().numpy()[0])
+        c0 += n
+    return {"atlases": count, "charts": int(sum(i.n for i in inputs)),
+            "atlases_per_s_batched": round(count / batched_s, 2),
+            "atlases_per_s_plain": round(count / plain_s, 2),
+            "speedup_vs_plain": round(plain_s / batched_s, 2),
+            "ms_per_batch": round(batched_s * 1000.0, 3), "hip_graph": True,
+            "bitexact_vs_plain": bool(same)}
+
+
+def served_leg(seconds=1.0, rate=2000.0):
+    """Poisson trace served with continuous batching vs one tabi_pack at a time."""
+    import copy
+    import numpy as np
+    from paper_2602_07782_amd import serve
+    reqs = serve.make_trace(rate=rate, seconds=seconds)
+    plain = [copy.copy(r) for r in reqs]
+    srv = serve.Server()
+    wall = srv.run(reqs)
+    st = serve.latency_stats(reqs)
+    pwall = serve.serve_plain(plain)
+    pst = serve.latency_stats(plain)
+    same = all(a.result[2] == b.result[2] and np.array_equal(a.result[0], b.result[0]) and
+               np.array_equal(a.result[1], b.result[1]) for a, b in zip(reqs, plain))
+    return {"requests": len(reqs), "rate_per_s": rate,
+            "repacks": int(sum(r.replaced is not None for r in reqs)),
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "atlases_per_s": round(len(reqs) / wall, 2),
+            "plain_p50_ms": round(pst["p50_ms"], 3), "plain_p99_ms": round(pst["p99_ms"], 3),
+            "plain_atlases_per_s": round(len(plain) / pwall, 2),
+            "speedup_vs_plain": round(pwall / wall, 2), "bitexact_vs_alone": bool(same)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +140,11 @@ def main():
     ap.add_argument("--quality", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--traffic-pass", action="store_true",
+                    help="for hardware-counter runs: a few packs, then one plain 256 MiB device "
+                         "copy whose byte count calibrates FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -89,6 +178,16 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.traffic_pass:
+        for _ in range(args.steps):
+            step()
+        src = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # reads and writes exactly 256 MiB
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_pass": True, "packs": args.steps, "copy_bytes": 256 << 20}))
+        return
     _, khi_t = tabi.debug_order(xy, off, inp.atlas_w, inp.atlas_h, inp.padding, inp.quality)
     k_top = int(khi_t.cpu()[0])
 
@@ -165,6 +264,16 @@ def main():
                                   "sample": f"{reps} full packs of the same 2,000-chart input"}
         result["bitexact_vs_oracle"] = bool(osc == gsc and np.array_equal(oxy, gxy) and
                                             np.array_equal(oori, gor))
+    if not args.no_batched:
+        try:
+            result["batched"] = batched_leg(tabi, torch)
+        except Exception as e:  # report, do not lose the main line
+            result["batched"] = {"error": repr(e)}
+    if not args.no_served:
+        try:
+            result["served"] = served_leg()
+        except Exception as e:
+            result["served"] = {"error": repr(e)}
     print(json.dumps(result), flush=True)
 
 

@@ -46,7 +46,7 @@ enum {
   TABI_OK = 0,
   TABI_EINVAL = -1, /* bad argument: null pointer, n < 0 or n > TABI_MAX_CHARTS,
                        atlas side < 1, side + padding > 16384, padding < 0,
-                       quality not in {0,1,2}, count < 0 */
+                       quality not in {0,1,2}, count < 0, work space too small */
   TABI_ENOMEM = -2, /* the device memory pool could not supply the work space */
   TABI_EHIP = -3    /* a HIP runtime call failed (launch, memory); see tabi_last_hip_error */
 };
@@ -75,22 +75,76 @@ typedef struct {
  *   out_scale[0]: k/64 for the chosen k >= 1 (exact);
  *        0.0f if no scale fits (out_xy filled with -1);
  *       -1.0f if some chart is degenerate: fewer than 3 vertices, zero width
- *             or height, or a coordinate with |x| >= 2^22 (out_xy filled with -1).
+ *             or height, or a coordinate with |x| >= 2^22 (out_xy filled with -1);
+ *       -2.0f if a row held more than 256 pairs of charts that share columns
+ *             without being neighbours (a limit of the row's shared memory;
+ *             out_xy filled with -1).
  * Errors: TABI_EINVAL, TABI_ENOMEM, TABI_EHIP (nothing is written then). */
 int tabi_pack(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
               int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
               float* out_scale, tabi_stream_t stream);
 
-/* Pack `count` independent atlases in one set of launches.  Charts of all
- * atlases form one CSR (xy, vert_offsets over all charts); atlas a owns charts
- * [atlas_offsets[a], atlas_offsets[a+1]) and has size atlas_wh[2a] x
- * atlas_wh[2a+1] texels (device int32 arrays).  out_xy / out_orient are
- * indexed by global chart index, out_scale by atlas.  Same per-atlas semantics
- * as tabi_pack; padding and quality are shared. */
+/* Pack `count` independent atlases in one set of launches (batched path).
+ * Charts of all atlases form one CSR (xy, vert_offsets over all charts, device
+ * int32); atlas a owns charts [atlas_offsets[a], atlas_offsets[a+1]) and is
+ * atlas_wh[2a] x atlas_wh[2a+1] texels (device int32 arrays).  The host
+ * arguments total_charts (= atlas_offsets[count]), max_charts (most charts in
+ * one atlas) and max_side (largest atlas side) size the work space and shared
+ * memory without reading device memory; an atlas exceeding them gets
+ * out_scale = -2.  out_xy / out_orient are indexed by global chart index,
+ * out_scale by atlas.  Per atlas the result equals tabi_pack on that atlas
+ * alone: every atlas evaluates its candidate scales from the largest down in
+ * rounds of 8 per launch and stops at the first round with a success.
+ * padding and quality are shared.  Errors as tabi_pack. */
 int tabi_pack_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
-                   int32_t count, const int32_t* atlas_wh, int32_t padding, int32_t quality,
+                   int32_t count, const int32_t* atlas_wh, int32_t total_charts,
+                   int32_t max_charts, int32_t max_side, int32_t padding, int32_t quality,
                    int32_t* out_xy, uint8_t* out_orient, float* out_scale,
                    tabi_stream_t stream);
+
+/* Bytes of device work space tabi_pack_many_ws needs for this batch shape
+ * (host only; -1 for a bad shape). */
+int64_t tabi_pack_many_workspace_bytes(int32_t count, int32_t total_charts, int32_t max_charts,
+                                       int32_t max_side, int32_t padding, int32_t quality);
+
+/* tabi_pack_many on a caller-provided device work space of workspace_bytes
+ * (at least tabi_pack_many_workspace_bytes).  Launches kernels only (no
+ * allocation, no memset), so a caller may capture it in a HIP graph and
+ * replay it; calls sharing one work space must not overlap. */
+int tabi_pack_many_ws(const int32_t* xy, const int32_t* vert_offsets,
+                      const int32_t* atlas_offsets, int32_t count, const int32_t* atlas_wh,
+                      int32_t total_charts, int32_t max_charts, int32_t max_side,
+                      int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
+                      float* out_scale, void* workspace, int64_t workspace_bytes,
+                      tabi_stream_t stream);
+
+/* ---- resident proxies (incremental re-packs) ----------------------------
+ * The per-chart proxies of Sec. 4.1.1 (box, turn, reflections, local AABBs,
+ * OBB; everything that does not depend on the scale) as opaque device
+ * records of tabi_record_bytes() bytes each.  A server keeps them resident;
+ * a re-pack that replaces some charts recomputes only those records. */
+int64_t tabi_record_bytes(void);
+
+/* Records of total_charts charts grouped into `count` atlases
+ * (atlas_offsets over the charts, device int32[count+1]); a record keeps its
+ * chart's index within its atlas.  quality fixes the number of slices and
+ * must match the later pack.  records: device buffer of
+ * total_charts * tabi_record_bytes() bytes. */
+int tabi_prep_records(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
+                      int32_t count, int32_t total_charts, int32_t quality, void* records,
+                      tabi_stream_t stream);
+
+/* records[index[i]] = new_records[i] for i < m (device arrays), keeping the
+ * replaced chart's index within its atlas. */
+int tabi_splice_records(void* records, const int32_t* index, int32_t m, const void* new_records,
+                        tabi_stream_t stream);
+
+/* tabi_pack_many starting from resident records instead of polygons; the
+ * result equals tabi_pack_many on the polygons the records came from. */
+int tabi_pack_many_records(const void* records, const int32_t* atlas_offsets, int32_t count,
+                           const int32_t* atlas_wh, int32_t total_charts, int32_t max_charts,
+                           int32_t max_side, int32_t padding, int32_t quality, int32_t* out_xy,
+                           uint8_t* out_orient, float* out_scale, tabi_stream_t stream);
 
 /* ---- diagnostics (same conventions; device pointers) ------------------- */
 

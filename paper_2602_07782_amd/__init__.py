@@ -31,7 +31,9 @@ class Charts(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ["tabi_pack", "tabi_pack_many", "tabi_debug_order", "tabi_debug_pairs",
+EXPORTS = ["tabi_pack", "tabi_pack_many", "tabi_pack_many_ws", "tabi_pack_many_workspace_bytes",
+           "tabi_record_bytes", "tabi_prep_records", "tabi_splice_records",
+           "tabi_pack_many_records", "tabi_debug_order", "tabi_debug_pairs",
            "tabi_debug_feasible", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
            "tabi_timing_enable", "tabi_timing_read", "tabi_timing_reset"]
 STAGES = ["prep", "sort", "setup", "pairs", "pack", "select"]
@@ -47,7 +49,16 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, i32 = ctypes.c_void_p, ctypes.c_int32
         L.tabi_pack.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, i32, vp, vp, vp, vp]
-        L.tabi_pack_many.argtypes = [vp, vp, vp, i32, vp, i32, i32, vp, vp, vp, vp]
+        L.tabi_pack_many.argtypes = [vp, vp, vp, i32, vp, i32, i32, i32, i32, i32, vp, vp, vp, vp]
+        L.tabi_pack_many_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32]
+        L.tabi_pack_many_workspace_bytes.restype = ctypes.c_int64
+        L.tabi_pack_many_ws.argtypes = [vp, vp, vp, i32, vp, i32, i32, i32, i32, i32, vp, vp, vp,
+                                        vp, ctypes.c_int64, vp]
+        L.tabi_record_bytes.restype = ctypes.c_int64
+        L.tabi_prep_records.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp]
+        L.tabi_splice_records.argtypes = [vp, vp, i32, vp, vp]
+        L.tabi_pack_many_records.argtypes = [vp, vp, i32, vp, i32, i32, i32, i32, i32, vp, vp, vp,
+                                             vp]
         L.tabi_debug_order.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, i32, vp, vp, vp]
         L.tabi_debug_pairs.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, vp, vp, vp]
         L.tabi_debug_feasible.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, i32, i32,
@@ -126,24 +137,65 @@ def pack_into(xy, offsets, n, atlas_w, atlas_h, padding, quality, out_xy, out_or
                            _stream(stream)))
 
 
-def pack_many(xy, vert_offsets, atlas_offsets, atlas_wh, padding, quality, stream=None,
-              device="cuda"):
-    """tabi_pack_many over a flattened batch.  Returns (out_xy int32[N,2],
-    out_orient uint8[N], out_scale float32[count])."""
-    torch = _torch()
-    xy = _dev_i32(xy, device)
-    vert_offsets = _dev_i32(vert_offsets, device)
-    atlas_offsets = _dev_i32(atlas_offsets, device)
-    atlas_wh = _dev_i32(atlas_wh, device)
-    count = int(atlas_offsets.numel()) - 1
-    N = int(vert_offsets.numel()) - 1
-    out_xy = torch.empty((N, 2), dtype=torch.int32, device=xy.device)
-    out_or = torch.empty(N, dtype=torch.uint8, device=xy.device)
-    out_sc = torch.empty(count, dtype=torch.float32, device=xy.device)
-    _check(lib().tabi_pack_many(_ptr(xy), _ptr(vert_offsets), _ptr(atlas_offsets), count,
-                                _ptr(atlas_wh), int(padding), int(quality), _ptr(out_xy),
-                                _ptr(out_or), _ptr(out_sc), _stream(stream)))
-    return out_xy, out_or, out_sc
+class Batch:
+    """A flattened batch of atlases resident on the device (inputs of
+    tabi_pack_many), with the host-side shape the library sizes itself by."""
+
+    def __init__(self, inputs, device="cuda"):
+        import numpy as np
+        torch = _torch()
+        xs, offs, aoff, wh = [], [0], [0], []
+        for inp in inputs:
+            xs.append(np.asarray(inp.xy, np.int32))
+            o = np.asarray(inp.offsets, np.int64)
+            offs.extend((o[1:] + offs[-1]).tolist())
+            aoff.append(aoff[-1] + inp.n)
+            wh.extend([inp.atlas_w, inp.atlas_h])
+        self.count = len(inputs)
+        self.total = aoff[-1]
+        self.max_charts = max([inp.n for inp in inputs], default=0)
+        self.max_side = max([max(inp.atlas_w, inp.atlas_h) for inp in inputs], default=1)
+        pads = {inp.padding for inp in inputs}
+        quals = {inp.quality for inp in inputs}
+        if len(pads) > 1 or len(quals) > 1:
+            raise ValueError("one padding and one quality per batch")
+        self.padding = pads.pop() if pads else 0
+        self.quality = quals.pop() if quals else 2
+        self.xy = _dev_i32(np.concatenate(xs) if xs else np.zeros(0, np.int32), device)
+        self.voff = _dev_i32(np.asarray(offs, np.int64), device)
+        self.aoff = _dev_i32(np.asarray(aoff, np.int64), device)
+        self.wh = _dev_i32(np.asarray(wh, np.int64), device)
+        self.out_xy = torch.empty((self.total, 2), dtype=torch.int32, device=self.xy.device)
+        self.out_orient = torch.empty(self.total, dtype=torch.uint8, device=self.xy.device)
+        self.out_scale = torch.empty(self.count, dtype=torch.float32, device=self.xy.device)
+        self.workspace = None
+
+    def workspace_bytes(self):
+        return int(lib().tabi_pack_many_workspace_bytes(self.count, self.total, self.max_charts,
+                                                        self.max_side, self.padding, self.quality))
+
+    def run(self, stream=None, use_workspace=False):
+        """Enqueue tabi_pack_many (or tabi_pack_many_ws on a kept work space)."""
+        args = (_ptr(self.xy), _ptr(self.voff), _ptr(self.aoff), self.count, _ptr(self.wh),
+                self.total, self.max_charts, self.max_side, self.padding, self.quality,
+                _ptr(self.out_xy), _ptr(self.out_orient), _ptr(self.out_scale))
+        if use_workspace:
+            torch = _torch()
+            nb = self.workspace_bytes()
+            if self.workspace is None or self.workspace.numel() < nb:
+                self.workspace = torch.empty(nb, dtype=torch.uint8, device=self.xy.device)
+            _check(lib().tabi_pack_many_ws(*args, _ptr(self.workspace), ctypes.c_int64(nb),
+                                           _stream(stream)))
+        else:
+            _check(lib().tabi_pack_many(*args, _stream(stream)))
+        return self.out_xy, self.out_orient, self.out_scale
+
+
+def pack_many(inputs, stream=None, device="cuda", use_workspace=False):
+    """tabi_pack_many over a list of AtlasInput-like objects.  Returns
+    (out_xy int32[N,2], out_orient uint8[N], out_scale float32[count]) with
+    charts in the order of the inputs."""
+    return Batch(inputs, device).run(stream, use_workspace)
 
 
 def debug_order(xy, offsets, atlas_w, atlas_h, padding, quality, stream=None, device="cuda"):
@@ -200,3 +252,44 @@ def timing_read():
     n = (ctypes.c_int32 * len(STAGES))()
     _check(lib().tabi_timing_read(ms, n, len(STAGES)))
     return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}
+
+
+# ---- resident per-chart proxy records (incremental re-packs) -----------------
+def record_bytes():
+    return int(lib().tabi_record_bytes())
+
+
+def prep_records(xy, vert_offsets, atlas_offsets, quality, stream=None, device="cuda"):
+    """Proxy records (uint8 tensor [N, record_bytes]) of every chart of the
+    atlases delimited by atlas_offsets."""
+    torch = _torch()
+    xy = _dev_i32(xy, device)
+    vert_offsets = _dev_i32(vert_offsets, device)
+    atlas_offsets = _dev_i32(atlas_offsets, device)
+    N = int(vert_offsets.numel()) - 1
+    count = int(atlas_offsets.numel()) - 1
+    rec = torch.empty((max(N, 0), record_bytes()), dtype=torch.uint8, device=xy.device)
+    _check(lib().tabi_prep_records(_ptr(xy), _ptr(vert_offsets), _ptr(atlas_offsets), count, N,
+                                   int(quality), _ptr(rec), _stream(stream)))
+    return rec
+
+
+def splice_records(records, index, new_records, stream=None):
+    """records[index[i]] = new_records[i] on the device (keeps input indices)."""
+    idx = _dev_i32(index, records.device)
+    m = int(idx.numel())
+    if m != int(new_records.shape[0]):
+        raise ValueError("index and new_records differ in length")
+    _check(lib().tabi_splice_records(_ptr(records), _ptr(idx), m, _ptr(new_records),
+                                     _stream(stream)))
+
+
+def pack_many_records(records, atlas_offsets, atlas_wh, max_charts, max_side, padding, quality,
+                      out_xy, out_orient, out_scale, stream=None):
+    """tabi_pack_many_records into caller-provided device tensors."""
+    count = int(atlas_offsets.numel()) - 1
+    N = int(records.shape[0])
+    _check(lib().tabi_pack_many_records(_ptr(records), _ptr(atlas_offsets), count, _ptr(atlas_wh),
+                                        N, int(max_charts), int(max_side), int(padding),
+                                        int(quality), _ptr(out_xy), _ptr(out_orient),
+                                        _ptr(out_scale), _stream(stream)))

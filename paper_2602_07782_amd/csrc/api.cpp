@@ -1,6 +1,5 @@
-// Host runtime of the TABI packer: argument checks, work-space carving from
-// the device's stream-ordered memory pool, launch sequence.  Implements the C
-// ABI declared in include/tabi.h.
+// Host runtime of the TABI packer: argument checks, work-space layout, the
+// launch sequence.  Implements the C ABI declared in include/tabi.h.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -26,9 +25,12 @@ int slices_for_quality(int q) { return q == 0 ? 2 : (q == 1 ? 5 : 10); }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Per-device set-up, once: the LDS a workgroup may use, and a release
-// threshold on the default stream-ordered pool so that work space freed at
-// the end of one call is reused by the next instead of returned to the OS.
+// static shared memory of k_pack (s_cnt, s_red, s_red64, s_lrn, s_lrover, s_lr)
+constexpr int kPackStaticLds = 4 * 4 + 8 * 6 * 4 + 8 * 8 + 8 + 256 * 3 * 4 + 64;
+
+// Per-device set-up, once: the LDS a workgroup may use (the packing kernel is
+// allowed all of it), and a release threshold on the default stream-ordered
+// pool so that work space freed by one call is reused by the next.
 int lds_budget() {
   static std::mutex mu;
   static int cache[64] = {0};
@@ -37,9 +39,11 @@ int lds_budget() {
   std::lock_guard<std::mutex> lk(mu);
   if (!cache[dev]) {
     int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v <= 0)
       v = 64 * 1024;
     cache[dev] = v;
+    (void)pack_set_max_lds(v - kPackStaticLds);
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
       uint64_t thr = UINT64_MAX;
@@ -93,70 +97,105 @@ struct StageScope {  // brackets one stage's launches with a pair of events
   }
 };
 
-// static shared memory of k_pack (s_cnt, s_red, s_red64, s_lrn, s_lrover, s_lr)
-constexpr int kPackStaticLds = 4 * 4 + 8 * 6 * 4 + 8 * 8 + 8 + 256 * 3 * 4 + 64;
-
-struct Job {
-  Params P{};
-  Work W{};
-  void* base = nullptr;
-  PackLds L{};
+// ---- work space -------------------------------------------------------------
+struct Layout {
+  size_t o_recs, o_srecs, o_keys, o_perm, o_ca, o_desc, o_kc, o_cd, o_fl, o_xs, o_ys, o_mir,
+      o_feas, o_rows, total;
 };
 
-// Carve the work space for N charts over `count` atlases with B scale slots.
-int make_job(Job& j, int count, int N, int q, int p, int B, int fixed_k, int nmax, int Wdmax,
-             hipStream_t st) {
-  j.P.count = count;
-  j.P.N = N;
-  j.P.K = slices_for_quality(q);
-  j.P.q = q;
-  j.P.p = p;
-  j.P.B = B;
-  j.P.stride = kchart_stride(j.P.K);
-  j.P.fixed_k = fixed_k;
-  const size_t n1 = (size_t)(N > 0 ? N : 1);
+Layout layout(const Params& P) {
+  Layout L{};
+  const size_t n1 = (size_t)(P.N > 0 ? P.N : 1);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off = align_up(off + bytes, 256);
     return o;
   };
-  const size_t o_recs = take(n1 * sizeof(Chart));
-  const size_t o_srecs = take(n1 * sizeof(Chart));
-  const size_t o_keys = take(n1 * 8);
-  const size_t o_perm = take(n1 * 4);
-  const size_t o_ca = take(n1 * 4);
-  const size_t o_desc = take((size_t)count * sizeof(AtlasDesc));
-  const size_t o_kc = take((size_t)B * n1 * j.P.stride);
-  const size_t o_cd = take((size_t)B * n1 * 4);
-  const size_t o_fl = take((size_t)B * n1);
-  const size_t o_xs = take((size_t)B * n1 * 4);
-  const size_t o_ys = take((size_t)B * n1 * 4);
-  const size_t o_mir = take((size_t)B * n1);
-  const size_t o_feas = take((size_t)count * B * 4);
-  const size_t o_rows = take((size_t)count * B * 4);
+  L.o_recs = take(n1 * sizeof(Chart));
+  L.o_srecs = take(n1 * sizeof(Chart));
+  L.o_keys = take(n1 * 8);
+  L.o_perm = take(n1 * 4);
+  L.o_ca = take(n1 * 4);
+  L.o_desc = take((size_t)P.count * sizeof(AtlasDesc));
+  L.o_kc = take((size_t)P.B * n1 * P.stride);
+  L.o_cd = take((size_t)P.B * n1 * 4);
+  L.o_fl = take((size_t)P.B * n1);
+  L.o_xs = take((size_t)P.B * n1 * 4);
+  L.o_ys = take((size_t)P.B * n1 * 4);
+  L.o_mir = take((size_t)P.B * n1);
+  L.o_feas = take((size_t)P.count * P.B * 4);
+  L.o_rows = take((size_t)P.count * P.B * 4);
+  L.total = off;
+  return L;
+}
+
+Work carve(void* base, const Layout& L) {
+  unsigned char* b = static_cast<unsigned char*>(base);
+  Work W;
+  W.recs = reinterpret_cast<Chart*>(b + L.o_recs);
+  W.srecs = reinterpret_cast<Chart*>(b + L.o_srecs);
+  W.keys = reinterpret_cast<uint64_t*>(b + L.o_keys);
+  W.perm = reinterpret_cast<int32_t*>(b + L.o_perm);
+  W.chart_atlas = reinterpret_cast<int32_t*>(b + L.o_ca);
+  W.desc = reinterpret_cast<AtlasDesc*>(b + L.o_desc);
+  W.kc = b + L.o_kc;
+  W.cd = reinterpret_cast<int32_t*>(b + L.o_cd);
+  W.fl = b + L.o_fl;
+  W.xs = reinterpret_cast<int32_t*>(b + L.o_xs);
+  W.ys = reinterpret_cast<int32_t*>(b + L.o_ys);
+  W.mir = b + L.o_mir;
+  W.feas = reinterpret_cast<int32_t*>(b + L.o_feas);
+  W.rows = reinterpret_cast<int32_t*>(b + L.o_rows);
+  return W;
+}
+
+struct Job {
+  Params P{};
+  Work W{};
+  void* base = nullptr;  // owned (stream-ordered pool) when set
+  PackLds L{};
+};
+
+Params make_params(int count, int N, int q, int p, int B, int fixed_k, int nmax, int Wdmax) {
+  Params P{};
+  P.count = count;
+  P.N = N;
+  P.K = slices_for_quality(q);
+  P.q = q;
+  P.p = p;
+  P.B = B;
+  P.stride = kchart_stride(P.K);
+  P.fixed_k = fixed_k;
+  P.nmax = nmax;
+  P.Wdmax = Wdmax;
+  return P;
+}
+
+// lds_cap: upper bound on the packing kernel's shared memory (0: device limit)
+int make_job(Job& j, const Params& P, hipStream_t st, void* ws = nullptr, size_t ws_bytes = 0,
+             int lds_cap = 0) {
+  j.P = P;
   const int budget = lds_budget();
-  hipError_t e = hipMallocAsync(&j.base, off, st);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return e == hipErrorOutOfMemory ? TABI_ENOMEM : hip_fail(e);
+  int b = budget - kPackStaticLds;
+  if (lds_cap > 0 && lds_cap < b) b = lds_cap;
+  j.L = pack_lds_plan(P.nmax, P.Wdmax, b);
+  if (j.L.bytes > b) return TABI_EINVAL;  // rows of this atlas cannot fit in LDS
+  const Layout L = layout(P);
+  if (ws) {
+    if (ws_bytes < L.total) return TABI_EINVAL;
+    j.base = nullptr;
+    j.W = carve(ws, L);
+  } else {
+    void* base = nullptr;
+    hipError_t e = hipMallocAsync(&base, L.total, st);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return e == hipErrorOutOfMemory ? TABI_ENOMEM : hip_fail(e);
+    }
+    j.base = base;
+    j.W = carve(base, L);
   }
-  unsigned char* b = static_cast<unsigned char*>(j.base);
-  j.W.recs = reinterpret_cast<Chart*>(b + o_recs);
-  j.W.srecs = reinterpret_cast<Chart*>(b + o_srecs);
-  j.W.keys = reinterpret_cast<uint64_t*>(b + o_keys);
-  j.W.perm = reinterpret_cast<int32_t*>(b + o_perm);
-  j.W.chart_atlas = reinterpret_cast<int32_t*>(b + o_ca);
-  j.W.desc = reinterpret_cast<AtlasDesc*>(b + o_desc);
-  j.W.kc = b + o_kc;
-  j.W.cd = reinterpret_cast<int32_t*>(b + o_cd);
-  j.W.fl = b + o_fl;
-  j.W.xs = reinterpret_cast<int32_t*>(b + o_xs);
-  j.W.ys = reinterpret_cast<int32_t*>(b + o_ys);
-  j.W.mir = b + o_mir;
-  j.W.feas = reinterpret_cast<int32_t*>(b + o_feas);
-  j.W.rows = reinterpret_cast<int32_t*>(b + o_rows);
-  j.L = pack_lds_plan(nmax, Wdmax, budget - kPackStaticLds);
   return TABI_OK;
 }
 
@@ -174,17 +213,110 @@ int check_common(int32_t n, int32_t padding, int32_t quality) {
   return TABI_OK;
 }
 
-// front half shared by the single-atlas entry points: descriptors, proxies, order, bound
-int front(Job& j, const tabi_charts* ch, int32_t n, int32_t aw, int32_t ah, hipStream_t st) {
+hipError_t run_front(Job& j, const int32_t* xy, const int32_t* voff, const int32_t* aoff,
+                     const int32_t* awh, int32_t aw, int32_t ah, hipStream_t st) {
   hipError_t e;
   {
     StageScope t(ST_PREP, st);
-    e = launch_prep(j.P, j.W, ch->xy, ch->offsets, nullptr, nullptr, aw, ah, st);
+    e = launch_prep(j.P, j.W, xy, voff, aoff, awh, aw, ah, st);
   }
   if (e == hipSuccess) {
     StageScope t(ST_SORT, st);
     e = launch_sort(j.P, j.W, st);
   }
+  return e;
+}
+
+// rounds of B descending scales per atlas until each atlas has its answer
+hipError_t run_search(Job& j, int rounds, int32_t* out_xy, uint8_t* out_orient, float* out_scale,
+                      hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < rounds && e == hipSuccess; ++r) {
+    {
+      StageScope t(ST_SETUP, st);
+      e = launch_setup(j.P, j.W, r, st);
+    }
+    if (e == hipSuccess) {
+      StageScope t(ST_PAIRS, st);
+      e = launch_pairs(j.P, j.W, r, st);
+    }
+    if (e == hipSuccess) {
+      StageScope t(ST_PACK, st);
+      e = launch_pack(j.P, j.W, r, j.L.bytes, j.L.RC, j.L.SC, st);
+    }
+    if (e == hipSuccess) {
+      StageScope t(ST_SELECT, st);
+      e = launch_select(j.P, j.W, r, r == rounds - 1, out_xy, out_orient, out_scale, st);
+    }
+  }
+  return e;
+}
+
+// batched shape: scale slots per round and the LDS cap (two workgroups per CU)
+constexpr int kManySlots = 8;
+constexpr int kManyLdsCap = 78 * 1024;
+
+int many_check(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
+               int32_t count, const int32_t* atlas_wh, int32_t total_charts, int32_t max_charts,
+               int32_t max_side, int32_t padding, int32_t quality, int32_t* out_xy,
+               uint8_t* out_orient, float* out_scale) {
+  if (count < 0 || total_charts < 0 || max_charts < 0 || max_charts > TABI_MAX_CHARTS ||
+      max_side < 1 || (int64_t)max_side + padding > 16384 || padding < 0 || quality < 0 ||
+      quality > 2)
+    return TABI_EINVAL;
+  if (count > 0 && (!atlas_offsets || !atlas_wh || !out_scale)) return TABI_EINVAL;
+  if (total_charts > 0 && (!xy || !vert_offsets || !out_xy || !out_orient)) return TABI_EINVAL;
+  return TABI_OK;
+}
+
+Params many_params(int32_t count, int32_t total_charts, int32_t max_charts, int32_t max_side,
+                   int32_t padding, int32_t quality) {
+  return make_params(count, total_charts, quality, padding, kManySlots, 0,
+                     max_charts > 0 ? max_charts : 1, max_side + padding);
+}
+
+int pack_many_impl(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
+                   int32_t count, const int32_t* atlas_wh, int32_t total_charts,
+                   int32_t max_charts, int32_t max_side, int32_t padding, int32_t quality,
+                   int32_t* out_xy, uint8_t* out_orient, float* out_scale, void* ws,
+                   size_t ws_bytes, tabi_stream_t stream, const void* records = nullptr) {
+  int rc = many_check(records ? (const int32_t*)records : xy,
+                      records ? atlas_offsets : vert_offsets, atlas_offsets, count, atlas_wh,
+                      total_charts, max_charts, max_side, padding, quality, out_xy, out_orient,
+                      out_scale);
+  if (rc) return rc;
+  if (count == 0) return TABI_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Job j;
+  rc = make_job(j, many_params(count, total_charts, max_charts, max_side, padding, quality), st,
+                ws, ws_bytes, kManyLdsCap);
+  if (rc) {
+    free_job(j, st);
+    return rc;
+  }
+  hipError_t e;
+  if (records) {
+    {
+      StageScope t(ST_PREP, st);
+      e = launch_from_records(j.P, j.W, static_cast<const Chart*>(records), atlas_offsets,
+                              atlas_wh, st);
+    }
+    if (e == hipSuccess) {
+      StageScope t(ST_SORT, st);
+      e = launch_sort(j.P, j.W, st);
+    }
+  } else {
+    e = run_front(j, xy, vert_offsets, atlas_offsets, atlas_wh, 0, 0, st);
+  }
+  if (e == hipSuccess) e = run_search(j, (64 + kManySlots - 1) / kManySlots, out_xy, out_orient,
+                                      out_scale, st);
+  if (e != hipSuccess) rc = hip_fail(e);
+  free_job(j, st);
+  return rc;
+}
+
+int single_front(Job& j, const tabi_charts* ch, int32_t aw, int32_t ah, hipStream_t st) {
+  hipError_t e = run_front(j, ch->xy, ch->offsets, nullptr, nullptr, aw, ah, st);
   return e == hipSuccess ? TABI_OK : hip_fail(e);
 }
 
@@ -201,32 +333,93 @@ int tabi_pack(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atl
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Job j;
   // every candidate scale at once: one workgroup per scale, no host round trip
-  int rc = make_job(j, 1, n, quality, padding, 64, 0, n, atlas_w + padding, st);
-  if (rc) return rc;
-  rc = front(j, charts, n, atlas_w, atlas_h, st);
-  hipError_t e = hipSuccess;
-  if (!rc) { StageScope t(ST_SETUP, st); e = launch_setup(j.P, j.W, 0, st); }
-  if (!rc && e == hipSuccess) { StageScope t(ST_PAIRS, st); e = launch_pairs(j.P, j.W, 0, st); }
-  if (!rc && e == hipSuccess) {
-    StageScope t(ST_PACK, st);
-    e = launch_pack(j.P, j.W, 0, j.L.bytes, j.L.RC, j.L.SC, st);
+  int rc = make_job(j, make_params(1, n, quality, padding, 64, 0, n > 0 ? n : 1, atlas_w + padding),
+                    st);
+  if (!rc) rc = single_front(j, charts, atlas_w, atlas_h, st);
+  if (!rc) {
+    hipError_t e = run_search(j, 1, out_xy, out_orient, out_scale, st);
+    if (e != hipSuccess) rc = hip_fail(e);
   }
-  if (!rc && e == hipSuccess) {
-    StageScope t(ST_SELECT, st);
-    e = launch_select(j.P, j.W, 0, 1, out_xy, out_orient, out_scale, st);
-  }
-  if (!rc && e != hipSuccess) rc = hip_fail(e);
   free_job(j, st);
   return rc;
 }
 
 int tabi_pack_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
-                   int32_t count, const int32_t* atlas_wh, int32_t padding, int32_t quality,
+                   int32_t count, const int32_t* atlas_wh, int32_t total_charts,
+                   int32_t max_charts, int32_t max_side, int32_t padding, int32_t quality,
                    int32_t* out_xy, uint8_t* out_orient, float* out_scale,
                    tabi_stream_t stream) {
-  (void)xy; (void)vert_offsets; (void)atlas_offsets; (void)count; (void)atlas_wh;
-  (void)padding; (void)quality; (void)out_xy; (void)out_orient; (void)out_scale; (void)stream;
-  return TABI_EINVAL;
+  return pack_many_impl(xy, vert_offsets, atlas_offsets, count, atlas_wh, total_charts, max_charts,
+                        max_side, padding, quality, out_xy, out_orient, out_scale, nullptr, 0,
+                        stream);
+}
+
+int64_t tabi_pack_many_workspace_bytes(int32_t count, int32_t total_charts, int32_t max_charts,
+                                       int32_t max_side, int32_t padding, int32_t quality) {
+  if (count < 0 || total_charts < 0 || max_side < 1 || quality < 0 || quality > 2 || padding < 0)
+    return -1;
+  return (int64_t)layout(many_params(count, total_charts, max_charts, max_side, padding, quality))
+      .total;
+}
+
+int tabi_pack_many_ws(const int32_t* xy, const int32_t* vert_offsets,
+                      const int32_t* atlas_offsets, int32_t count, const int32_t* atlas_wh,
+                      int32_t total_charts, int32_t max_charts, int32_t max_side,
+                      int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
+                      float* out_scale, void* workspace, int64_t workspace_bytes,
+                      tabi_stream_t stream) {
+  if (!workspace || workspace_bytes <= 0) return TABI_EINVAL;
+  return pack_many_impl(xy, vert_offsets, atlas_offsets, count, atlas_wh, total_charts, max_charts,
+                        max_side, padding, quality, out_xy, out_orient, out_scale, workspace,
+                        (size_t)workspace_bytes, stream);
+}
+
+int64_t tabi_record_bytes(void) { return (int64_t)sizeof(Chart); }
+
+int tabi_prep_records(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
+                      int32_t count, int32_t total_charts, int32_t quality, void* records,
+                      tabi_stream_t stream) {
+  if (count < 1 || total_charts < 0 || quality < 0 || quality > 2 || !atlas_offsets ||
+      (total_charts > 0 && (!xy || !vert_offsets || !records)))
+    return TABI_EINVAL;
+  if (total_charts == 0) return TABI_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Params P = make_params(count, total_charts, quality, 0, 1, 0, 1, 1);
+  // only the record array and the chart->atlas / key scratch are touched
+  void* scratch = nullptr;
+  hipError_t e = hipMallocAsync(&scratch, (size_t)total_charts * 12 + 256, st);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? TABI_ENOMEM : hip_fail(e);
+  }
+  Work W{};
+  W.recs = static_cast<Chart*>(records);
+  W.keys = static_cast<uint64_t*>(scratch);
+  W.chart_atlas = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(scratch) +
+                                             align_up((size_t)total_charts * 8, 256));
+  W.desc = nullptr;
+  e = launch_prep(P, W, xy, vert_offsets, atlas_offsets, nullptr, 0, 0, st);
+  (void)hipFreeAsync(scratch, st);
+  return e == hipSuccess ? TABI_OK : hip_fail(e);
+}
+
+int tabi_splice_records(void* records, const int32_t* index, int32_t m, const void* new_records,
+                        tabi_stream_t stream) {
+  if (m < 0 || (m > 0 && (!records || !index || !new_records))) return TABI_EINVAL;
+  hipError_t e = launch_splice(static_cast<Chart*>(records), index, m,
+                               static_cast<const Chart*>(new_records),
+                               reinterpret_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TABI_OK : hip_fail(e);
+}
+
+int tabi_pack_many_records(const void* records, const int32_t* atlas_offsets, int32_t count,
+                           const int32_t* atlas_wh, int32_t total_charts, int32_t max_charts,
+                           int32_t max_side, int32_t padding, int32_t quality, int32_t* out_xy,
+                           uint8_t* out_orient, float* out_scale, tabi_stream_t stream) {
+  if (total_charts > 0 && !records) return TABI_EINVAL;
+  return pack_many_impl(nullptr, nullptr, atlas_offsets, count, atlas_wh, total_charts, max_charts,
+                        max_side, padding, quality, out_xy, out_orient, out_scale, nullptr, 0,
+                        stream, records ? records : atlas_offsets);
 }
 
 int tabi_debug_order(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
@@ -237,9 +430,9 @@ int tabi_debug_order(const tabi_charts* charts, int32_t n, int32_t atlas_w, int3
     return TABI_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Job j;
-  int rc = make_job(j, 1, n, quality, padding, 1, 0, n, atlas_w + padding, st);
-  if (rc) return rc;
-  rc = front(j, charts, n, atlas_w, atlas_h, st);
+  int rc = make_job(j, make_params(1, n, quality, padding, 1, 0, n > 0 ? n : 1, atlas_w + padding),
+                    st);
+  if (!rc) rc = single_front(j, charts, atlas_w, atlas_h, st);
   if (!rc) {
     hipError_t e = hipSuccess;
     if (n > 0) e = hipMemcpyAsync(perm, j.W.perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st);
@@ -253,14 +446,13 @@ int tabi_debug_order(const tabi_charts* charts, int32_t n, int32_t atlas_w, int3
 
 int tabi_debug_pairs(const tabi_charts* charts, int32_t n, int32_t padding, int32_t quality,
                      int32_t k, int32_t* cd, uint8_t* flags, tabi_stream_t stream) {
-  if (check_common(n, padding, quality) || k < 1 || k > 64 || !charts ||
+  if (check_common(n, padding, quality) || k < 1 || k > 64 || !charts || padding >= 16384 ||
       (n > 0 && (!charts->xy || !charts->offsets || !cd || !flags)))
     return TABI_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Job j;
-  int rc = make_job(j, 1, n, quality, padding, 1, k, n, 1 + padding, st);
-  if (rc) return rc;
-  rc = front(j, charts, n, 16384 - padding, 16384 - padding, st);
+  int rc = make_job(j, make_params(1, n, quality, padding, 1, k, n > 0 ? n : 1, 1 + padding), st);
+  if (!rc) rc = single_front(j, charts, 16384 - padding, 16384 - padding, st);
   hipError_t e = hipSuccess;
   if (!rc) e = launch_setup(j.P, j.W, 0, st);
   if (!rc && e == hipSuccess) e = launch_pairs(j.P, j.W, 0, st);
@@ -283,9 +475,9 @@ int tabi_debug_feasible(const tabi_charts* charts, int32_t n, int32_t atlas_w, i
     return TABI_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Job j;
-  int rc = make_job(j, 1, n, quality, padding, 1, k, n, atlas_w + padding, st);
-  if (rc) return rc;
-  rc = front(j, charts, n, atlas_w, atlas_h, st);
+  int rc = make_job(j, make_params(1, n, quality, padding, 1, k, n > 0 ? n : 1, atlas_w + padding),
+                    st);
+  if (!rc) rc = single_front(j, charts, atlas_w, atlas_h, st);
   hipError_t e = hipSuccess;
   if (!rc) e = launch_setup(j.P, j.W, 0, st);
   if (!rc && e == hipSuccess) e = launch_pairs(j.P, j.W, 0, st);
@@ -341,10 +533,12 @@ int tabi_timing_read(double* ms, int32_t* launches, int32_t nstages) {
 }
 
 void tabi_timing_reset(void) {
-  int32_t dummy[ST_COUNT];
-  tabi_timing_read(nullptr, dummy, 0);
+  tabi_timing_read(nullptr, nullptr, 0);
   std::lock_guard<std::mutex> lk(g_timing.mu);
-  for (int i = 0; i < ST_COUNT; ++i) { g_timing.ms[i] = 0; g_timing.launches[i] = 0; }
+  for (int i = 0; i < ST_COUNT; ++i) {
+    g_timing.ms[i] = 0;
+    g_timing.launches[i] = 0;
+  }
 }
 
 int64_t tabi_pack_lds_bytes(int32_t n, int32_t atlas_w, int32_t padding) {

@@ -156,6 +156,10 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
     return;
   }
   const int n = d.n, Wd = d.Wa + P.p, Hd = d.Ha + P.p, Ha = d.Ha, p = P.p, K = P.K;
+  if (n > P.nmax || Wd > P.Wdmax) {  // batch larger than the caller's declared shape
+    if (tid == 0) { w.feas[a * P.B + s] = -2; w.rows[a * P.B + s] = 0; }
+    return;
+  }
   const int topt = P.q == 0 ? 5 : (P.q == 1 ? 2 : (n > 10000 ? 1 : 0));
   const size_t slot = (size_t)s * P.N + d.c0;
   int32_t* F = reinterpret_cast<int32_t*>(smem);
@@ -546,11 +550,13 @@ PackLds pack_lds_plan(int nmax, int Wd, int budget) {
   return L;
 }
 
+hipError_t pack_set_max_lds(int bytes) {
+  return hipFuncSetAttribute((const void*)k_pack, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             bytes);
+}
+
 hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes, int RC, int SC,
                        hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_pack,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pack, dim3(P.B, P.count), dim3(PACK_NT), lds_bytes, st, P, w, round, RC, SC);
   return hipGetLastError();
 }

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
       out->valid = 0;
       out->src = local;
       w.keys[c] = ((uint64_t)0x7fffff << 41) | ((uint64_t)0x7fffff << 18) | (uint64_t)local;
-      atomicOr(&w.desc[a].bad, 1);
+      if (w.desc) atomicOr(&w.desc[a].bad, 1);
     }
     return;
   }
@@ -379,11 +379,62 @@ __global__ __launch_bounds__(256) void k_setup(Params P, Work w, int round) {
   sd[3] = sR;
 }
 
+// Start of the packing path from resident proxy records: copy, keys, atlas
+// of each chart, degenerate flags.
+__global__ __launch_bounds__(256) void k_from_records(Params P, Work w, const Chart* __restrict__ in,
+                                                      const int32_t* __restrict__ atlas_off) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.N) return;
+  int lo = 0, hi = P.count - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (atlas_off[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  const int a = lo;
+  const Chart ch = in[c];
+  w.recs[c] = ch;
+  w.chart_atlas[c] = a;
+  const uint64_t local = (uint64_t)ch.src;
+  if (ch.valid) {
+    w.keys[c] = ((uint64_t)(0x7fffff - ch.H) << 41) | ((uint64_t)(0x7fffff - ch.W) << 18) | local;
+  } else {
+    w.keys[c] = ((uint64_t)0x7fffff << 41) | ((uint64_t)0x7fffff << 18) | local;
+    atomicOr(&w.desc[a].bad, 1);
+  }
+}
+
+// dst[idx[i]] = src[i], keeping the replaced chart's input index
+__global__ __launch_bounds__(256) void k_splice(Chart* __restrict__ dst, const int32_t* __restrict__ idx,
+                                                int m, const Chart* __restrict__ src) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int j = idx[i];
+  Chart c = src[i];
+  c.src = dst[j].src;
+  dst[j] = c;
+}
+
+hipError_t launch_from_records(const Params& P, const Work& w, const Chart* in,
+                               const int32_t* atlas_off, const int32_t* atlas_wh, hipStream_t st) {
+  hipLaunchKernelGGL(k_init, dim3((P.count + 255) / 256), dim3(256), 0, st, P, w, atlas_off,
+                     atlas_wh, 0, 0);
+  if (P.N > 0)
+    hipLaunchKernelGGL(k_from_records, dim3((P.N + 255) / 256), dim3(256), 0, st, P, w, in,
+                       atlas_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_splice(Chart* dst, const int32_t* idx, int m, const Chart* src, hipStream_t st) {
+  if (m > 0) hipLaunchKernelGGL(k_splice, dim3((m + 255) / 256), dim3(256), 0, st, dst, idx, m, src);
+  return hipGetLastError();
+}
+
 hipError_t launch_prep(const Params& P, const Work& w, const int32_t* xy, const int32_t* voff,
                        const int32_t* atlas_off, const int32_t* atlas_wh, int single_w,
                        int single_h, hipStream_t st) {
-  hipLaunchKernelGGL(k_init, dim3((P.count + 255) / 256), dim3(256), 0, st, P, w, atlas_off,
-                     atlas_wh, single_w, single_h);
+  if (w.desc)
+    hipLaunchKernelGGL(k_init, dim3((P.count + 255) / 256), dim3(256), 0, st, P, w, atlas_off,
+                       atlas_wh, single_w, single_h);
   if (P.N > 0)
     hipLaunchKernelGGL(k_prep, dim3((P.N + PREP_WAVES - 1) / PREP_WAVES), dim3(256), 0, st, P, w,
                        xy, voff, atlas_off);

@@ -28,6 +28,8 @@ struct Params {
   int32_t B;           // scale slots per round
   int32_t stride;      // bytes of one per-(scale, chart) record
   int32_t fixed_k;     // > 0: evaluate exactly this scale in slot 0 (diagnostics)
+  int32_t nmax;        // largest chart count of one atlas the work space was sized for
+  int32_t Wdmax;       // largest grown atlas width the shared memory was sized for
 };
 
 // Work-space views (device pointers).
@@ -58,6 +60,9 @@ __host__ __device__ inline int32_t slot_k(const Params& P, const AtlasDesc& d, i
 hipError_t launch_prep(const Params& P, const Work& w, const int32_t* xy, const int32_t* voff,
                        const int32_t* atlas_off, const int32_t* atlas_wh, int single_w,
                        int single_h, hipStream_t st);
+hipError_t launch_from_records(const Params& P, const Work& w, const Chart* in,
+                               const int32_t* atlas_off, const int32_t* atlas_wh, hipStream_t st);
+hipError_t launch_splice(Chart* dst, const int32_t* idx, int m, const Chart* src, hipStream_t st);
 hipError_t launch_sort(const Params& P, const Work& w, hipStream_t st);
 hipError_t launch_plan(const Params& P, const Work& w, hipStream_t st);
 hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t st);
@@ -69,6 +74,8 @@ hipError_t launch_select(const Params& P, const Work& w, int round, int last_rou
 
 hipError_t launch_scatter(const Params& P, const Work& w, int32_t* out_xy, uint8_t* out_orient,
                           int32_t* feasible, int32_t* rows, hipStream_t st);
+
+hipError_t pack_set_max_lds(int bytes);
 
 // shared-memory plan of the packing kernel
 struct PackLds {

@@ -262,8 +262,8 @@ def make_input(name: str, instance: int = 0, quality: int | None = None,
                       cfg["q"] if quality is None else int(quality))
 
 
-def make_custom(n, W, H, p, q, sigma, fill, mix, seed) -> AtlasInput:
-    polys = generate_charts(n, W, H, sigma, fill, mix, seed)
+def make_custom(n, W, H, p, q, sigma, fill, mix, seed, fast=False) -> AtlasInput:
+    polys = (generate_charts_fast if fast else generate_charts)(n, W, H, sigma, fill, mix, seed)
     xy, offs = pack_csr(polys)
     return AtlasInput(xy, offs, W, H, p, q)
 
@@ -279,7 +279,7 @@ def make_batch(count: int = 256, seed: int = 4000, nmin: int = 50, nmax: int = 5
     out = []
     for a in range(count):
         out.append(make_custom(int(ns[a]), int(sides[a]), int(sides[a]), 2, 2, 1.2, 1.2, mix,
-                               seed * 1000 + a))
+                               seed * 1000 + a, fast=True))
     return out
 
 
@@ -293,3 +293,190 @@ def rect_input(n, a_q8, b_q8, W, H, p, q=2, seed=0, jitter_xy=True) -> AtlasInpu
                                [ox, oy + b_q8]], np.int64))
     xy, offs = pack_csr(polys)
     return AtlasInput(xy, offs, W, H, p, q)
+
+
+# --------------------------------------------------------------------------
+# vectorised generation for large batches (same recipes, drawn family by
+# family; a different random stream from generate_charts)
+# --------------------------------------------------------------------------
+def _simple_many(P: np.ndarray) -> np.ndarray:
+    """polygon_is_simple over a stack of polygons P (B, m, 2) of equal m.
+    Charts whose test involves a collinear triple are re-checked exactly one
+    by one (rare)."""
+    P = P.astype(np.int64)
+    B, m, _ = P.shape
+    ok = np.ones(B, bool)
+    Q = np.roll(P, -1, axis=1)
+    if np.any(np.all(P == Q, axis=2), axis=1).any():
+        ok &= ~np.any(np.all(P == Q, axis=2), axis=1)
+    ax, ay = P[:, :, None, 0], P[:, :, None, 1]
+    bx, by = Q[:, :, None, 0], Q[:, :, None, 1]
+    cx, cy = P[:, None, :, 0], P[:, None, :, 1]
+    dx, dy = Q[:, None, :, 0], Q[:, None, :, 1]
+    d1 = np.sign((bx - ax) * (cy - ay) - (by - ay) * (cx - ax))
+    d2 = np.sign((bx - ax) * (dy - ay) - (by - ay) * (dx - ax))
+    d3 = np.sign((dx - cx) * (ay - cy) - (dy - cy) * (ax - cx))
+    d4 = np.sign((dx - cx) * (by - cy) - (dy - cy) * (bx - cx))
+    idx = np.arange(m)
+    far = ~((idx[:, None] == idx[None, :]) | ((idx[:, None] + 1) % m == idx[None, :]) |
+            ((idx[None, :] + 1) % m == idx[:, None]))
+    proper = (d1 * d2 < 0) & (d3 * d4 < 0) & far[None]
+    ok &= ~proper.reshape(B, -1).any(axis=1)
+    zero = ((d1 == 0) | (d2 == 0) | (d3 == 0) | (d4 == 0)) & far[None]
+    suspect = zero.reshape(B, -1).any(axis=1)
+    R = np.roll(P, -2, axis=1)
+    e1, e2 = Q - P, R - Q
+    cross = e1[..., 0] * e2[..., 1] - e1[..., 1] * e2[..., 0]
+    dot = e1[..., 0] * e2[..., 0] + e1[..., 1] * e2[..., 1]
+    ok &= ~((cross == 0) & (dot < 0)).any(axis=1)
+    for b in np.nonzero(ok & suspect)[0]:
+        ok[b] = polygon_is_simple(P[b])
+    return ok
+
+
+def _stars_many(rng, cnt, m, amax):
+    ang = 2.0 * np.pi * (np.arange(m)[None, :] + rng.uniform(-0.3, 0.3, (cnt, m))) / m
+    ang.sort(axis=1)
+    r = 1.0 + rng.uniform(-0.4, 0.4, (cnt, m))
+    a = rng.uniform(1.0, amax, cnt)
+    x = r * np.cos(ang) * np.sqrt(a)[:, None]
+    y = r * np.sin(ang) / np.sqrt(a)[:, None]
+    phi = rng.uniform(0.0, np.pi, cnt)
+    c, s = np.cos(phi)[:, None], np.sin(phi)[:, None]
+    return np.stack([x * c - y * s, x * s + y * c], axis=2)
+
+
+def _star_shaped(Q, C):
+    """Exact sufficient test of simplicity: every vertex turns strictly
+    counter-clockwise around the integer point C and the loop winds once."""
+    D = Q - C[:, None, :]
+    E = np.roll(D, -1, axis=1)
+    cr = D[..., 0] * E[..., 1] - D[..., 1] * E[..., 0]
+    # crossings of the ray from C along +x, counted upward
+    up = (D[..., 1] < 0) & (E[..., 1] >= 0)
+    winds = (cr > 0).all(axis=1) & (up.sum(axis=1) == 1)
+    return winds
+
+
+def _place_many(rng, P, areas, W, H, centre=None):
+    x, y = P[..., 0], P[..., 1]
+    A = 0.5 * np.abs((x * np.roll(y, -1, 1) - np.roll(x, -1, 1) * y).sum(1))
+    sc = np.sqrt(areas / A)[:, None, None]
+    P = P * sc
+    lo = P.min(axis=1, keepdims=True)
+    P = P - lo
+    off = np.stack([rng.uniform(0, W, len(areas)), rng.uniform(0, H, len(areas))], 1)
+    Q = np.rint((P + off[:, None, :]) * Q8).astype(np.int64)
+    ext = Q.max(axis=1) - Q.min(axis=1)
+    good = (ext.min(axis=1) >= 4) & (np.abs(Q).max(axis=(1, 2)) < (1 << 21))
+    if centre is not None:
+        C = np.rint((-lo[:, 0, :] + off) * Q8).astype(np.int64)
+        fast = _star_shaped(Q, C)
+        # counter-clockwise in (x, y) coordinates; the fast test proves simplicity
+        rest = good & ~fast
+        if rest.any():
+            good[rest] = _simple_many(Q[rest])
+    else:
+        good &= _simple_many(Q)
+    return Q, good
+
+
+def generate_charts_fast(n, W, H, sigma, fill, mix, seed):
+    """Vectorised counterpart of generate_charts for large batches."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    areas = np.exp(sigma * rng.standard_normal(n))
+    areas *= fill * W * H / areas.sum()
+    fracs = np.array([m[1] for m in mix], float)
+    kinds = rng.choice(len(mix), size=n, p=fracs / fracs.sum())
+    out = [None] * n
+    for ki, (kind, _, vmin, vmax, amax) in enumerate(mix):
+        ids = np.nonzero(kinds == ki)[0]
+        if kind == "star":
+            ms = rng.integers(vmin, vmax + 1, ids.size)
+            for m in np.unique(ms):
+                sel = ids[ms == m]
+                for _attempt in range(64):
+                    if sel.size == 0:
+                        break
+                    Q, good = _place_many(rng, _stars_many(rng, sel.size, int(m), amax),
+                                          areas[sel], W, H, centre=True)
+                    for j in np.nonzero(good)[0]:
+                        out[sel[j]] = Q[j]
+                    sel = sel[~good]
+        else:
+            sel = ids
+            for _attempt in range(64):
+                if sel.size == 0:
+                    break
+                polys = _lu_many(rng, sel.size, amax) if kind == "lu" else \
+                    _quads_many(rng, sel.size, vmax, amax)
+                left = []
+                for m in sorted({p.shape[0] for p in polys}):
+                    js = [j for j, p in enumerate(polys) if p.shape[0] == m]
+                    Q, good = _place_many(rng, np.stack([polys[j] for j in js]), areas[sel[js]],
+                                          W, H)
+                    for jj, j in enumerate(js):
+                        if good[jj]:
+                            out[sel[j]] = Q[jj]
+                        else:
+                            left.append(sel[j])
+                sel = np.array(sorted(left), dtype=np.int64)
+    if any(p is None for p in out):  # pragma: no cover - vanishingly rare
+        raise RuntimeError("could not draw a valid chart")
+    return out
+
+
+def _lu_many(rng, cnt, amax):
+    """cnt L or U shapes (list of float polygons), as _lu draws them."""
+    a = rng.uniform(1.0, amax, cnt)
+    w, h = np.sqrt(a), 1.0 / np.sqrt(a)
+    fx, fy = rng.uniform(0.3, 0.7, cnt), rng.uniform(0.3, 0.7, cnt)
+    isL = rng.uniform(size=cnt) < 0.5
+    turn = rng.integers(0, 4, cnt)
+    mirror = rng.uniform(size=cnt) < 0.5
+    free = rng.uniform(size=cnt) < 0.5
+    phi = rng.uniform(0.0, np.pi, cnt)
+    out = []
+    for i in range(cnt):
+        if isL[i]:
+            P = np.array([[0, 0], [w[i], 0], [w[i], h[i] * fy[i]], [w[i] * fx[i], h[i] * fy[i]],
+                          [w[i] * fx[i], h[i]], [0, h[i]]])
+        else:
+            nw = w[i] * fx[i]
+            x0 = 0.5 * (w[i] - nw)
+            P = np.array([[0, 0], [x0, 0], [x0, h[i] * fy[i]], [x0 + nw, h[i] * fy[i]], [x0 + nw, 0],
+                          [w[i], 0], [w[i], h[i]], [0, h[i]]])
+        P = _rot(P, turn[i] * np.pi / 2)
+        if mirror[i]:
+            P[:, 0] = -P[:, 0]
+            P = P[::-1].copy()
+        if free[i]:
+            P = _rot(P, phi[i])
+        out.append(P)
+    return out
+
+
+def _quads_many(rng, cnt, mv, amax):
+    """cnt near-rectangular quads with 0..mv-4 extra edge vertices."""
+    a = rng.uniform(1.0, amax, cnt)
+    w, h = np.sqrt(a), 1.0 / np.sqrt(a)
+    short = np.minimum(w, h)
+    jit = rng.uniform(-0.05, 0.05, (cnt, 4, 2)) * short[:, None, None]
+    extra = rng.integers(0, mv - 4 + 1, cnt)
+    phi = rng.uniform(-np.pi / 18, np.pi / 18, cnt)
+    out = []
+    for i in range(cnt):
+        corners = np.array([[0, 0], [w[i], 0], [w[i], h[i]], [0, h[i]]]) + jit[i]
+        per_edge = np.bincount(rng.integers(0, 4, extra[i]), minlength=4)
+        pts = []
+        for e in range(4):
+            p0, p1 = corners[e], corners[(e + 1) % 4]
+            pts.append(p0)
+            if per_edge[e]:
+                ts = np.sort(rng.uniform(0.15, 0.85, per_edge[e]))
+                d = p1 - p0
+                nrm = np.array([-d[1], d[0]]) / (np.hypot(*d) + 1e-30)
+                for t in ts:
+                    pts.append(p0 + t * d + nrm * rng.uniform(-0.02, 0.02) * short[i])
+        out.append(_rot(np.array(pts), phi[i]))
+    return out

@@ -1,0 +1,107 @@
+"""Batched path (tabi_pack_many) on the GPU: every atlas of a batch equals the
+oracle's pack of that atlas alone, bit for bit; the work-space variant can be
+captured in a HIP graph and replayed."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2602_07782_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tabi():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_07782_amd as t
+    t.lib()
+    return t
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def small_batch(count, seed, nmin=20, nmax=400, sides=(256, 512, 1024)):
+    rng = np.random.default_rng(seed)
+    mix = synth.CONFIGS["mixed2k"]["mix"]
+    out = []
+    for a in range(count):
+        side = int(rng.choice(sides))
+        n = int(rng.integers(nmin, nmax + 1))
+        out.append(synth.make_custom(n, side, side, 2, 2, 1.2, 1.2, mix, seed * 1000 + a))
+    return out
+
+
+def check_batch(tabi, orc, inputs, use_workspace=False):
+    xy, ori, sc = tabi.pack_many(inputs, use_workspace=use_workspace)
+    xy, ori, sc = xy.cpu().numpy(), ori.cpu().numpy(), sc.cpu().numpy()
+    c0 = 0
+    for a, inp in enumerate(inputs):
+        oxy, oori, osc, ok = orc.pack(inp)
+        n = inp.n
+        assert float(sc[a]) == osc, (a, sc[a], osc)
+        assert np.array_equal(xy[c0:c0 + n], oxy), a
+        assert np.array_equal(ori[c0:c0 + n], oori), a
+        c0 += n
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_batch_equals_oracle_per_atlas(tabi, orc, seed):
+    inputs = small_batch(12, 700 + seed)
+    _say("batch", seed, [i.n for i in inputs])
+    check_batch(tabi, orc, inputs)
+
+
+def test_batch_workspace_variant(tabi, orc):
+    check_batch(tabi, orc, small_batch(8, 777), use_workspace=True)
+
+
+def test_batch_with_degenerate_and_empty_atlas(tabi, orc):
+    inputs = small_batch(4, 900)
+    bad = synth.AtlasInput(np.array([0, 0, 100, 100, 5, 5, 9, 9, 300, 0, 0, 300], np.int32),
+                           np.array([0, 2, 6], np.int32), 64, 64, 2, 2)
+    empty = synth.AtlasInput(np.zeros(0, np.int32), np.zeros(1, np.int32), 64, 64, 2, 2)
+    inputs = inputs[:2] + [bad] + inputs[2:] + [empty]
+    xy, ori, sc = tabi.pack_many(inputs)
+    sc = sc.cpu().numpy()
+    assert sc[2] == -1.0 and sc[-1] == 1.0
+    good = [i for j, i in enumerate(inputs) if j not in (2, len(inputs) - 1)]
+    check_batch(tabi, orc, good)
+
+
+def test_batch_of_mixed2k_atlases(tabi, orc):
+    inputs = [synth.make_input("mixed2k", i) for i in range(2)] + small_batch(3, 901)
+    check_batch(tabi, orc, inputs)
+
+
+def test_graph_capture_replay(tabi):
+    import torch
+    inputs = small_batch(6, 905)
+    batch = tabi.Batch(inputs)
+    ref = [t.clone() for t in batch.run(use_workspace=True)]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.run(stream=s, use_workspace=True)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        batch.run(stream=s, use_workspace=True)
+    for rep in range(3):
+        batch.out_xy.fill_(-7)
+        batch.out_scale.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (batch.out_xy.sum() + 1).item()  # eager work between replays
+        assert torch.equal(batch.out_xy, ref[0]), rep
+        assert torch.equal(batch.out_orient, ref[1]), rep
+        assert torch.equal(batch.out_scale, ref[2]), rep
