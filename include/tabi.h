@@ -174,6 +174,11 @@ int tabi_debug_feasible(const tabi_charts* charts, int32_t n, int32_t atlas_w, i
                         uint8_t* out_orient, int32_t* feasible, int32_t* rows,
                         tabi_stream_t stream);
 
+/* Test knob: cap the per-row LDS staging of texel bounds at `entries`
+ * (texel columns; -1 restores the default).  Rows that do not fit evaluate
+ * the bounds directly; results are identical either way. */
+int tabi_debug_set_stage_cap(int32_t entries);
+
 /* Text for a return code; last HIP error string seen by the library. */
 const char* tabi_strerror(int code);
 const char* tabi_last_hip_error(void);

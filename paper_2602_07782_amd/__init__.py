@@ -35,7 +35,8 @@ EXPORTS = ["tabi_pack", "tabi_pack_many", "tabi_pack_many_ws", "tabi_pack_many_w
            "tabi_record_bytes", "tabi_prep_records", "tabi_splice_records",
            "tabi_pack_many_records", "tabi_debug_order", "tabi_debug_pairs",
            "tabi_debug_feasible", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
-           "tabi_timing_enable", "tabi_timing_read", "tabi_timing_reset"]
+           "tabi_timing_enable", "tabi_timing_read", "tabi_timing_reset",
+           "tabi_debug_set_stage_cap"]
 STAGES = ["prep", "sort", "setup", "pairs", "pack", "select"]
 
 
@@ -71,6 +72,7 @@ def lib():
         L.tabi_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int32), i32]
         L.tabi_timing_reset.restype = None
+        L.tabi_debug_set_stage_cap.argtypes = [i32]
         _lib = L
     return _lib
 
@@ -293,3 +295,8 @@ def pack_many_records(records, atlas_offsets, atlas_wh, max_charts, max_side, pa
                                         N, int(max_charts), int(max_side), int(padding),
                                         int(quality), _ptr(out_xy), _ptr(out_orient),
                                         _ptr(out_scale), _stream(stream)))
+
+
+def debug_set_stage_cap(entries):
+    """Cap the pack kernel's per-row staging (-1 = default); results are unchanged."""
+    _check(lib().tabi_debug_set_stage_cap(int(entries)))

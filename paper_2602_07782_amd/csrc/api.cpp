@@ -25,8 +25,10 @@ int slices_for_quality(int q) { return q == 0 ? 2 : (q == 1 ? 5 : 10); }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// static shared memory of k_pack (s_cnt, s_red, s_red64, s_lrn, s_lrover, s_lr)
-constexpr int kPackStaticLds = 4 * 4 + 8 * 6 * 4 + 8 * 8 + 8 + 256 * 3 * 4 + 64;
+// static shared memory of k_pack, read from the compiled kernel once
+int kPackStaticLds = 32 * 1024;
+// test knob: upper bound on the row staging area (entries); < 0 = none
+int g_stage_cap = -1;
 
 // Per-device set-up, once: the LDS a workgroup may use (the packing kernel is
 // allowed all of it), and a release threshold on the default stream-ordered
@@ -43,6 +45,7 @@ int lds_budget() {
         v <= 0)
       v = 64 * 1024;
     cache[dev] = v;
+    kPackStaticLds = pack_static_lds() + 256;
     (void)pack_set_max_lds(v - kPackStaticLds);
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
@@ -178,9 +181,15 @@ int make_job(Job& j, const Params& P, hipStream_t st, void* ws = nullptr, size_t
   j.P = P;
   const int budget = lds_budget();
   int b = budget - kPackStaticLds;
-  if (lds_cap > 0 && lds_cap < b) b = lds_cap;
+  // a preferred cap (two workgroups per CU) yields to what the widest atlas needs
+  if (lds_cap > 0 && lds_cap < b && pack_lds_plan(P.nmax, P.Wdmax, lds_cap).SC >= 4 * P.Wdmax)
+    b = lds_cap;
   j.L = pack_lds_plan(P.nmax, P.Wdmax, b);
   if (j.L.bytes > b) return TABI_EINVAL;  // rows of this atlas cannot fit in LDS
+  if (g_stage_cap >= 0 && j.L.SC > g_stage_cap) {
+    j.L.bytes -= 4 * (j.L.SC - g_stage_cap);
+    j.L.SC = g_stage_cap;
+  }
   const Layout L = layout(P);
   if (ws) {
     if (ws_bytes < L.total) return TABI_EINVAL;
@@ -500,6 +509,11 @@ const char* tabi_strerror(int code) {
 
 const char* tabi_last_hip_error(void) { return g_last_hip; }
 
+int tabi_debug_set_stage_cap(int32_t entries) {
+  g_stage_cap = entries;
+  return TABI_OK;
+}
+
 int tabi_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_timing.mu);
   g_timing.on = on != 0;
@@ -542,7 +556,8 @@ void tabi_timing_reset(void) {
 }
 
 int64_t tabi_pack_lds_bytes(int32_t n, int32_t atlas_w, int32_t padding) {
-  PackLds L = pack_lds_plan(n, atlas_w + padding, lds_budget() - kPackStaticLds);
+  const int budget = lds_budget();  // also reads the kernel's static size
+  PackLds L = pack_lds_plan(n, atlas_w + padding, budget - kPackStaticLds);
   return (int64_t)L.bytes + kPackStaticLds;
 }
 

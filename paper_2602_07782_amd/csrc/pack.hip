@@ -32,6 +32,7 @@ namespace tabi {
 constexpr int PACK_NT = 512;
 constexpr int PACK_WAVES = PACK_NT / WAVE;
 constexpr int LRCAP = 256;  // pairs per row that share columns without being neighbours
+constexpr int FWIN = 1024;  // charts per row whose fold data is staged in LDS
 enum { DIR_LR = 0, DIR_RL = 1 };
 
 __device__ inline void wsync() {
@@ -145,6 +146,10 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
   __shared__ int64_t s_red64[PACK_WAVES];
   __shared__ int32_t s_lrn, s_lrover;
   __shared__ int32_t s_lr[LRCAP][3];
+  // per-row window of chart data read by the fold and the knee test:
+  // grown width, compacting distance to the next chart, unscaled height
+  __shared__ int32_t s_wd[FWIN], s_cdn[FWIN], s_H[FWIN];
+  __shared__ int32_t s_h0;
 
   const int s = blockIdx.x, a = blockIdx.y;
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
@@ -188,6 +193,15 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
   for (;;) {
     __syncthreads();
     if (rs >= n) break;
+    const int nwin = min(FWIN, n - rs);
+    for (int t = tid; t < nwin; t += PACK_NT) {
+      const int c = rs + t;
+      s_wd[t] = KV(c).hd->w + p;
+      s_cdn[t] = c + 1 < n ? cdv[c + 1] : 0;
+      s_H[t] = ch[c].H;
+    }
+    if (tid == 0) s_h0 = KV(rs).hd->h;
+    __syncthreads();
     // ---- 1. knee location update (Alg. 4)
     if (kn) {
       const int probe = kdir == DIR_LR ? kr : kl - 1;
@@ -209,7 +223,7 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
       }
     }
     // ---- t_opt switch (Sec. 4.4)
-    if (!tail && !kn && 100 * (int64_t)KV(rs).hd->h < (int64_t)topt * Ha) tail = 1;
+    if (!tail && !kn && 100 * (int64_t)s_h0 < (int64_t)topt * Ha) tail = 1;
     // ---- 2. folding (Alg. 2), wavefront 0
     const int kw = kn ? (kdir == DIR_LR ? Wd - kr : kl) : 0;
     if (wv == 0) {
@@ -218,7 +232,10 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
       for (int t0 = 0; cfn < 0; t0 += WAVE) {
         const int t = t0 + lane, c = rs + t;
         int wd = Wd + 1, cdn = 0;
-        if (c < n) {
+        if (t < nwin) {
+          wd = s_wd[t];
+          cdn = s_cdn[t];
+        } else if (c < n) {
           wd = KV(c).hd->w + p;
           if (c + 1 < n) cdn = cdv[c + 1];
         }
@@ -272,15 +289,39 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
 #pragma unroll
     for (int j = 0; j < 4; ++j) { cmax = max(cmax, c_cnt[j]); anyhc |= c_hc[j]; }
     const int E = Xoff[cand], Eall = Xoff[cmax];
-    const bool staged = E <= SC;
+    const int U = E - p * cand;          // undilated texel columns of the candidates
+    // stage layout (int16 units of stT / stB): grown bounds [0,E), undilated
+    // bounds [E, E+U), texel -> chart map in stT[E+U, 2E+U)
+    const bool staged = 2 * E + U <= SC;
+    int16_t* emap = stT + E + U;
     // ---- 3. staging, offset init, neighbour-free pairs that share columns
     if (staged) {
+      // undilated TopEdge / BottomEdge once per texel column, behind the grown ones
+      for (int u = tid; u < U; u += PACK_NT) {
+        int lo = 0, hi = cand - 1;  // chart t with Xoff[t] - p t <= u
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (Xoff[mid] - p * mid <= u) lo = mid; else hi = mid - 1;
+        }
+        int32_t tp, bt;
+        column_bounds(KV(rs + lo), ch[rs + lo], K, k, u - (Xoff[lo] - p * lo), tp, bt);
+        stT[E + u] = (int16_t)tp;
+        stB[E + u] = (int16_t)bt;
+      }
+      __syncthreads();
+      // grown column i: min top / max bottom over undilated columns [i-p, i]
       for (int e = tid; e < E; e += PACK_NT) {
         const int t = find_chart(Xoff, cand, e);
-        int32_t tp, bt;
-        column_bounds_grown(KV(rs + t), ch[rs + t], K, k, p, e - Xoff[t], tp, bt);
+        emap[e] = (int16_t)t;
+        const int i = e - Xoff[t], wt = Xoff[t + 1] - Xoff[t] - p;
+        const int base = E + Xoff[t] - p * t;
+        int32_t tp = BIG, bt = -BIG;
+        for (int c = max(0, i - p); c <= min(wt - 1, i); ++c) {
+          tp = min(tp, (int32_t)stT[base + c]);
+          bt = max(bt, (int32_t)stB[base + c]);
+        }
         stT[e] = (int16_t)tp;
-        stB[e] = (int16_t)bt;
+        stB[e] = (int16_t)(bt + p);
       }
     }
 #pragma unroll
@@ -301,8 +342,9 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
     if (s_lrover) { feasible = -2; break; }
     for (int q = wv; q < lrn; q += PACK_WAVES) {
       const int A = s_lr[q][0], C = s_lr[q][1];
-      const int f = pair_flags(KV(rs + A), ch[rs + A], KV(rs + C), ch[rs + C], K, k, p,
-                               Xon[C] - Xon[A]);
+      const KView va = KV(rs + A);
+      const PairSweep sw = pair_sweep(va, ch[rs + A], KV(rs + C), ch[rs + C], K, k, p);
+      const int f = pair_flags_at(sw, va.hd->w + p, Xon[C] - Xon[A]);
       if (lane == 0) s_lr[q][2] = f;
     }
     __syncthreads();
@@ -310,7 +352,7 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
     for (int e0 = wv * WAVE; e0 < Eall; e0 += PACK_NT) {
       const int e = e0 + lane;
       const bool valid = e < Eall;
-      const int t = valid ? find_chart(Xoff, cand, e) : -1;
+      const int t = valid ? (staged ? (int)emap[e] : find_chart(Xoff, cand, e)) : -1;
       const int i = valid ? e - Xoff[t] : 0;
       int32_t tp = 0;
       if (valid) {
@@ -344,7 +386,7 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
     for (int e0 = wv * WAVE; e0 < Eall; e0 += PACK_NT) {
       const int e = e0 + lane;
       if (e < Eall) {
-        const int t = find_chart(Xoff, cand, e);
+        const int t = staged ? (int)emap[e] : find_chart(Xoff, cand, e);
         int32_t bt;
         if (staged) bt = stB[e];
         else { int32_t tp; column_bounds_grown(KV(rs + t), ch[rs + t], K, k, p, e - Xoff[t], tp, bt); }
@@ -400,7 +442,7 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
     // ---- commit: frontline update, placements
     const int Ew = Xoff[w_cnt];
     for (int e = tid; e < Ew; e += PACK_NT) {
-      const int t = find_chart(Xoff, cand, e);
+      const int t = staged ? (int)emap[e] : find_chart(Xoff, cand, e);
       const int i = e - Xoff[t];
       int32_t bt;
       if (staged) bt = stB[e];
@@ -422,7 +464,8 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
     if (!tail && !knee_used) {
       int64_t best = -1;
       for (int t = tid; t + 1 < w_cnt; t += PACK_NT) {
-        const int64_t h1 = ch[rs + t].H, h2 = ch[rs + t + 1].H, dl = h1 - h2;
+        const int64_t h1 = t < nwin ? s_H[t] : ch[rs + t].H;
+        const int64_t h2 = t + 1 < nwin ? s_H[t + 1] : ch[rs + t + 1].H, dl = h1 - h2;
         if (10 * dl >= 256 * (int64_t)Ha && 5 * dl >= h1) {
           const int64_t key = (dl << 20) | (int64_t)((1 << 20) - 1 - t);
           best = key > best ? key : best;
@@ -548,6 +591,12 @@ PackLds pack_lds_plan(int nmax, int Wd, int budget) {
   L.SC = sc & ~7;
   L.bytes = fixed + 4 * L.SC;
   return L;
+}
+
+int pack_static_lds() {
+  hipFuncAttributes a;
+  if (hipFuncGetAttributes(&a, (const void*)k_pack) != hipSuccess) return 32 * 1024;
+  return (int)a.sharedSizeBytes;
 }
 
 hipError_t pack_set_max_lds(int bytes) {

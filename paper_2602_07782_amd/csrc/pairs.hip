@@ -1,20 +1,28 @@
 // Horizontal compacting distance and interlock flags of sorted neighbours
 // (Sec. 4.1.2 "Compacting Horizontal Gaps", App. A "Detecting Interlocking
-// Charts"), one wavefront per (scale slot, pair).  Lanes walk the rows of the
-// two charts' grown row profiles: the compacting distance is a min-reduction,
-// the interlock tests are prefix max / prefix min scans.
+// Charts"), one wavefront per (scale slot, pair).  The two charts' proxy
+// records are copied to LDS once; one sweep over the rows gives the
+// compacting distance (a min-reduction) and both interlock thresholds
+// (prefix max / prefix min scans).
 #include "tabi_internal.h"
 #include "pairs_dev.h"
 
 namespace tabi {
 
 constexpr int PAIR_WAVES = 4;
+constexpr int KREC_MAX = 16 + 4 * 16 + 2 * KMAX * 8;  // kchart_stride(KMAX)
+
+struct alignas(16) PairCache {
+  Chart ch[2];
+  unsigned char kc[2][KREC_MAX];
+};
 
 __global__ __launch_bounds__(256) void k_pairs(Params P, Work w, int round) {
+  __shared__ PairCache cache[PAIR_WAVES];
   const int wv = threadIdx.x / WAVE, lane = lane_id();
   const int c = blockIdx.x * PAIR_WAVES + wv;
   const int s = blockIdx.y;
-  if (c >= P.N) return;
+  if (c >= P.N) return;  // whole wavefront leaves; no block barrier below
   const AtlasDesc d = w.desc[w.chart_atlas[c]];
   const size_t slot = (size_t)s * P.N;
   const bool run = P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1);
@@ -25,29 +33,34 @@ __global__ __launch_bounds__(256) void k_pairs(Params P, Work w, int round) {
     if (lane == 0) { w.cd[slot + c] = 0; w.fl[slot + c] = 0; }
     return;
   }
-  const int K = P.K, p = P.p;
-  const KView A = kview(w.kc + (slot + c - 1) * P.stride, K);
-  const KView B = kview(w.kc + (slot + c) * P.stride, K);
-  const Chart& cA = w.srecs[c - 1];
-  const Chart& cB = w.srecs[c];
-  const int hdA = A.hd->h + p, hdB = B.hd->h + p, wdA = A.hd->w + p;
-  const int rows = min(hdA, hdB);
-  // compacting distance: min over shared rows of (w'A - RightA(j) + LeftB(j))
-  int32_t cdv = BIG;
-  for (int j0 = 0; j0 < rows; j0 += WAVE) {
-    const int j = j0 + lane;
-    if (j < rows) {
-      int32_t la, ra, lb, rb;
-      row_bounds_grown(A, cA, K, k, p, j, la, ra);
-      row_bounds_grown(B, cB, K, k, p, j, lb, rb);
-      cdv = min(cdv, wdA - ra + lb);
+  const int K = P.K, p = P.p, stride = P.stride;
+  // stage both charts (records of chart c-1 and c) in LDS
+  {
+    const int nch = (int)(sizeof(Chart) / 16), nkc = stride / 16;
+    const int4* srcA = reinterpret_cast<const int4*>(&w.srecs[c - 1]);
+    const int4* srcB = reinterpret_cast<const int4*>(&w.srecs[c]);
+    const int4* kcA = reinterpret_cast<const int4*>(w.kc + (slot + c - 1) * stride);
+    const int4* kcB = reinterpret_cast<const int4*>(w.kc + (slot + c) * stride);
+    int4* dch = reinterpret_cast<int4*>(cache[wv].ch);
+    int4* dk0 = reinterpret_cast<int4*>(cache[wv].kc[0]);
+    int4* dk1 = reinterpret_cast<int4*>(cache[wv].kc[1]);
+    for (int i = lane; i < 2 * nch + 2 * nkc; i += WAVE) {
+      if (i < nch) dch[i] = srcA[i];
+      else if (i < 2 * nch) dch[i] = srcB[i - nch];
+      else if (i < 2 * nch + nkc) dk0[i - 2 * nch] = kcA[i - 2 * nch];
+      else dk1[i - 2 * nch - nkc] = kcB[i - 2 * nch - nkc];
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  cdv = wave_min(cdv);
-  const int32_t fl = pair_flags(A, cA, B, cB, K, k, p, wdA - cdv);
+  const KView A = kview(cache[wv].kc[0], K);
+  const KView B = kview(cache[wv].kc[1], K);
+  const PairSweep r = pair_sweep(A, cache[wv].ch[0], B, cache[wv].ch[1], K, k, p);
+  const int wdA = A.hd->w + p;
   if (lane == 0) {
-    w.cd[slot + c] = cdv;
-    w.fl[slot + c] = (uint8_t)fl;
+    w.cd[slot + c] = r.cd;
+    w.fl[slot + c] = (uint8_t)pair_flags_at(r, wdA, wdA - r.cd);
   }
 }
 

@@ -1,52 +1,81 @@
-// Interlock test of two charts of one compacted row, wavefront-cooperative.
+// Compacting distance and interlock thresholds of two charts of a row, in
+// one wavefront-cooperative sweep over the rows.
 #pragma once
 
 #include "tabi_device.h"
 
 namespace tabi {
 
-// Flags for chart A and a later chart B whose grown box starts d texels right
-// of A's (App. A, "Detecting Interlocking Charts").  bit0: B may not move
-// above A, set when some row j >= 1 of B starts left of where A ends in a row
-// above j; bit1: A may not move above B, set when some row j >= 1 of A ends
-// right of where B starts in a row above j.  Raising one chart by 1..j texels
-// brings exactly those rows side by side, so a clear flag means no upward
-// shift can make the proxies meet.  No shared column, no flag.  All lanes of
-// the wavefront must call this with the same arguments.
-__device__ inline int32_t pair_flags(const KView& A, const Chart& cA, const KView& B,
-                                     const Chart& cB, int K, int k, int p, int d) {
+struct PairSweep {
+  int32_t cd;  // horizontal compacting distance (Sec. 4.1.2)
+  int32_t D1;  // B may not move above A exactly when its box offset d < D1
+  int32_t D2;  // A may not move above B exactly when d < D2
+};
+
+// One pass over the grown rows of A (B, later in sorted order, is at most as
+// tall).  With R'A / L'B the grown right / left row bounds:
+//   cd = min over shared rows j of (w'A - R'A(j) + L'B(j));
+//   B rising by 1..j texels brings row j of B beside rows above j of A, so
+//   B may not rise iff some j >= 1 has d + L'B(j) < max_{j'<j} R'A(j'),
+//   i.e. iff d < D1 = max_j (max_{j'<j} R'A(j') - L'B(j));
+//   symmetrically A may not rise iff d < D2 = max_j (R'A(j) - min_{j'<j} L'B(j'))
+// (App. A, "Detecting Interlocking Charts").  Each lane evaluates one
+// undilated row of each chart; the gutter growth over rows [j-p, j] comes
+// from p shuffles, so a chunk advances 64 - p rows.  All lanes of the
+// wavefront must call this with the same arguments.
+__device__ inline PairSweep pair_sweep(const KView& A, const Chart& cA, const KView& B,
+                                       const Chart& cB, int K, int k, int p) {
   const int lane = lane_id();
-  const int hdA = A.hd->h + p, hdB = B.hd->h + p, wdA = A.hd->w + p;
-  if (d >= wdA) return 0;
-  int32_t carry_max = -BIG;  // max of A's right ends over the rows before this chunk
-  int32_t carry_min = BIG;   // min of B's left ends over the rows before this chunk
-  int flags = 0;
-  for (int j0 = 0; j0 < hdA && flags != 3; j0 += WAVE) {
-    const int j = j0 + lane;
+  const int hA = A.hd->h, hB = B.hd->h, wdA = A.hd->w + p;
+  const int hdA = hA + p, hdB = hB + p;
+  int32_t cd = BIG, D1 = -BIG, D2 = -BIG;
+  int32_t carry_max = -BIG, carry_min = BIG;
+  const int step = WAVE - p;
+  for (int j0 = 0; j0 < hdA; j0 += step) {
+    const int u = j0 - p + lane;  // undilated row held by this lane
     int32_t ra = -BIG, lb = BIG;
-    if (j < hdA) {
+    if (u >= 0 && u < hA) {
       int32_t l, r;
-      row_bounds_grown(A, cA, K, k, p, j, l, r);
+      row_bounds(A, cA, K, k, u, l, r);
       ra = r;
     }
-    if (j < hdB) {
+    if (u >= 0 && u < hB) {
       int32_t l, r;
-      row_bounds_grown(B, cB, K, k, p, j, l, r);
+      row_bounds(B, cB, K, k, u, l, r);
       lb = l;
     }
-    const int32_t imax = wave_incl_max(ra), imin = wave_incl_min(lb);
+    int32_t Ra = ra, Lb = lb;
+    for (int s = 1; s <= p; ++s) {
+      Ra = max(Ra, __shfl_up(ra, s));
+      Lb = min(Lb, __shfl_up(lb, s));
+    }
+    const int j = u;  // grown row j = lanes [j-p, j] of this chunk
+    const bool act = lane >= p && j < hdA;
+    Ra = act ? Ra + p : -BIG;
+    Lb = (act && j < hdB) ? Lb : BIG;
+    if (act && j < hdB) cd = min(cd, wdA - Ra + Lb);
+    const int32_t imax = wave_incl_max(Ra), imin = wave_incl_min(Lb);
     int32_t emax = __shfl_up(imax, 1), emin = __shfl_up(imin, 1);
     if (lane == 0) { emax = -BIG; emin = BIG; }
     emax = max(emax, carry_max);
     emin = min(emin, carry_min);
-    const bool b_up = j >= 1 && j < hdB && d + lb < emax;
-    const bool a_up = j >= 1 && j < hdA && ra > d + emin;
-    if (ballot64(b_up)) flags |= 1;
-    if (ballot64(a_up)) flags |= 2;
+    if (act && j >= 1 && j < hdB) D1 = max(D1, emax - Lb);
+    if (act && j >= 1) D2 = max(D2, Ra - emin);
     carry_max = max(carry_max, __shfl(imax, WAVE - 1));
     carry_min = min(carry_min, __shfl(imin, WAVE - 1));
   }
-  return flags;
+  PairSweep r;
+  r.cd = wave_min(cd);
+  r.D1 = wave_max(D1);
+  r.D2 = wave_max(D2);
+  return r;
+}
+
+// Interlock flags for box offset d (bit0: B may not move above A, bit1: A may
+// not move above B); none without a shared column.
+__device__ inline int32_t pair_flags_at(const PairSweep& s, int wdA, int d) {
+  if (d >= wdA) return 0;
+  return (d < s.D1 ? 1 : 0) | (d < s.D2 ? 2 : 0);
 }
 
 }  // namespace tabi

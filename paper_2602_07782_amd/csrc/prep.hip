@@ -236,18 +236,44 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
   }
 }
 
-// rank of each chart's key inside its atlas; scatter to sorted position
+// rank of each chart's key inside its atlas (keys are unique); scatter to the
+// sorted position.  Keys of the atlases spanned by the block are streamed
+// through LDS in tiles of 256 and every thread counts the smaller ones of its
+// own atlas.
 __global__ __launch_bounds__(256) void k_sort(Params P, Work w) {
+  __shared__ uint64_t tile[256];
+  __shared__ int s_lo, s_hi;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= P.N) return;
-  const AtlasDesc d = w.desc[w.chart_atlas[c]];
-  const uint64_t key = w.keys[c];
+  const bool act = c < P.N;
+  int lo = 0, hi = 0;
+  uint64_t key = 0;
+  if (act) {
+    const AtlasDesc d = w.desc[w.chart_atlas[c]];
+    lo = d.c0;
+    hi = d.c0 + d.n;
+    key = w.keys[c];
+  }
+  if (threadIdx.x == 0) s_lo = lo;
+  const int last = min(P.N, (int)(blockIdx.x + 1) * (int)blockDim.x) - 1;
+  if (c == last) s_hi = hi;
+  __syncthreads();
+  const int blo = s_lo, bhi = s_hi;
   int rank = 0;
-  const uint64_t* ks = w.keys + d.c0;
-  for (int j = 0; j < d.n; ++j) rank += ks[j] < key;
-  const int pos = d.c0 + rank;
-  w.srecs[pos] = w.recs[c];
-  w.perm[pos] = c - d.c0;
+  for (int base = blo; base < bhi; base += 256) {
+    const int i = base + threadIdx.x;
+    tile[threadIdx.x] = i < bhi ? w.keys[i] : ~0ull;
+    __syncthreads();
+    if (act) {
+      const int j0 = max(lo - base, 0), j1 = min(hi - base, 256);
+      for (int j = j0; j < j1; ++j) rank += tile[j] < key;
+    }
+    __syncthreads();
+  }
+  if (act) {
+    const int pos = lo + rank;
+    w.srecs[pos] = w.recs[c];
+    w.perm[pos] = c - lo;
+  }
 }
 
 // candidate scales: the charts' total area and the largest chart must fit

@@ -76,6 +76,7 @@ hipError_t launch_scatter(const Params& P, const Work& w, int32_t* out_xy, uint8
                           int32_t* feasible, int32_t* rows, hipStream_t st);
 
 hipError_t pack_set_max_lds(int bytes);
+int pack_static_lds();
 
 // shared-memory plan of the packing kernel
 struct PackLds {

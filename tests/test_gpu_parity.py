@@ -186,3 +186,17 @@ def test_repeat_is_bitwise_identical(tabi):
     for _ in range(3):
         b = gpu_pack(tabi, inp)
         assert a[2] == b[2] and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("cap", [0, 700])
+def test_pack_parity_without_row_staging(tabi, orc, cap):
+    """Rows whose texel bounds do not fit the staging area are evaluated
+    directly; same results (cap 0: every row, 700: the wide ones)."""
+    tabi.debug_set_stage_cap(cap)
+    try:
+        assert_pack_equal(tabi, orc, synth.make_input("mixed2k", 0), f"mixed2k cap {cap}")
+        assert_pack_equal(tabi, orc, synth.make_input("stars64", 1), f"stars64 cap {cap}")
+        for seed in range(6):
+            assert_pack_equal(tabi, orc, small_input(400 + seed), f"small {seed} cap {cap}")
+    finally:
+        tabi.debug_set_stage_cap(-1)
