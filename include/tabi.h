@@ -24,7 +24,8 @@
  *    on the device are written into out_scale (see tabi_pack).
  *  - Gutters: `padding` is the minimum number of empty texels between two
  *    charts (the paper's 1-pixel gutters around charts correspond to
- *    padding = 2).  Charts may touch the atlas edges.
+ *    padding = 2), 0 <= padding <= TABI_MAX_PADDING.  Charts may touch the
+ *    atlas edges.
  *  - quality selects the paper's quality/speed knob (Sec. 5 ablations):
  *      0: 2 local AABBs per axis, t_opt = 5 %
  *      1: 5 local AABBs per axis, t_opt = 2 %
@@ -45,13 +46,16 @@ typedef struct ihipStream_t* tabi_stream_t; /* a hipStream_t */
 enum {
   TABI_OK = 0,
   TABI_EINVAL = -1, /* bad argument: null pointer, n < 0 or n > TABI_MAX_CHARTS,
-                       atlas side < 1, side + padding > 16384, padding < 0,
+                       atlas side < 1, side + padding > 16384, padding < 0 or
+                       padding > TABI_MAX_PADDING,
                        quality not in {0,1,2}, count < 0, work space too small */
   TABI_ENOMEM = -2, /* the device memory pool could not supply the work space */
   TABI_EHIP = -3    /* a HIP runtime call failed (launch, memory); see tabi_last_hip_error */
 };
 
 #define TABI_MAX_CHARTS 262144 /* charts per atlas */
+#define TABI_MAX_PADDING 32    /* gutter texels; the gutter growth of a texel profile is
+                                  taken within one 64-lane wavefront */
 
 typedef struct {
   const int32_t* xy;      /* device int32[2*total_verts]: x0,y0,x1,y1,... in Q8 */
@@ -175,9 +179,17 @@ int tabi_debug_feasible(const tabi_charts* charts, int32_t n, int32_t atlas_w, i
                         tabi_stream_t stream);
 
 /* Test knob: cap the per-row LDS staging of texel bounds at `entries`
- * (texel columns; -1 restores the default).  Rows that do not fit evaluate
- * the bounds directly; results are identical either way. */
+ * (texel columns; -1 restores the default).  Rows that do not fit read the
+ * stored bounds from device memory; results are identical either way. */
 int tabi_debug_set_stage_cap(int32_t entries);
+
+/* Test knob: size of the per-call arena of stored per-texel profiles, in
+ * 32-bit words (one per grown texel column or row of a chart at a scale;
+ * -1 restores the default, 0 stores none).  Charts whose profiles do not fit
+ * are evaluated from their proxy records inside the pairing and packing
+ * kernels; results are identical either way.  Affects later calls of this
+ * process, including tabi_pack_many_workspace_bytes. */
+int tabi_debug_set_profile_cap(int64_t words);
 
 /* Text for a return code; last HIP error string seen by the library. */
 const char* tabi_strerror(int code);
@@ -186,8 +198,8 @@ const char* tabi_last_hip_error(void);
 /* Stage timing (host side).  When enabled, the calling process brackets each
  * stage of later tabi_pack / tabi_pack_many calls with a pair of HIP events on
  * the call's stream.  Stages, in order: 0 chart proxies (prep), 1 sort and
- * scale bound, 2 per-scale set-up, 3 neighbour pairs, 4 fold-and-push, 5 scale
- * selection.  tabi_timing_read waits for the recorded events and writes the
+ * scale bound, 2 per-scale set-up, 3 per-texel profiles, 4 neighbour pairs,
+ * 5 fold-and-push, 6 scale selection.  tabi_timing_read waits for the recorded events and writes the
  * summed milliseconds and the number of bracketed launches per stage since
  * the last reset (arrays of nstages entries, either may be NULL). */
 int tabi_timing_enable(int on);

@@ -36,8 +36,8 @@ EXPORTS = ["tabi_pack", "tabi_pack_many", "tabi_pack_many_ws", "tabi_pack_many_w
            "tabi_pack_many_records", "tabi_debug_order", "tabi_debug_pairs",
            "tabi_debug_feasible", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
            "tabi_timing_enable", "tabi_timing_read", "tabi_timing_reset",
-           "tabi_debug_set_stage_cap"]
-STAGES = ["prep", "sort", "setup", "pairs", "pack", "select"]
+           "tabi_debug_set_stage_cap", "tabi_debug_set_profile_cap"]
+STAGES = ["prep", "sort", "setup", "profile", "pairs", "pack", "select"]
 
 
 def lib():
@@ -73,6 +73,7 @@ def lib():
                                        ctypes.POINTER(ctypes.c_int32), i32]
         L.tabi_timing_reset.restype = None
         L.tabi_debug_set_stage_cap.argtypes = [i32]
+        L.tabi_debug_set_profile_cap.argtypes = [ctypes.c_int64]
         _lib = L
     return _lib
 
@@ -300,3 +301,9 @@ def pack_many_records(records, atlas_offsets, atlas_wh, max_charts, max_side, pa
 def debug_set_stage_cap(entries):
     """Cap the pack kernel's per-row staging (-1 = default); results are unchanged."""
     _check(lib().tabi_debug_set_stage_cap(int(entries)))
+
+
+def debug_set_profile_cap(words):
+    """Size of the stored-profile arena in words (-1 = default, 0 = none);
+    results are unchanged."""
+    _check(lib().tabi_debug_set_profile_cap(int(words)))

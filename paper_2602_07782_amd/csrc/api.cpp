@@ -27,8 +27,10 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // static shared memory of k_pack, read from the compiled kernel once
 int kPackStaticLds = 32 * 1024;
-// test knob: upper bound on the row staging area (entries); < 0 = none
+// test knobs: upper bound on the row staging area (texel columns) and on the
+// profile arena (32-bit words); < 0 = default
 int g_stage_cap = -1;
+int64_t g_profile_cap = -1;
 
 // Per-device set-up, once: the LDS a workgroup may use (the packing kernel is
 // allowed all of it), and a release threshold on the default stream-ordered
@@ -58,7 +60,7 @@ int lds_budget() {
 }
 
 // ---- opt-in per-stage timing with HIP events on the call's stream ----------
-enum Stage { ST_PREP = 0, ST_SORT, ST_SETUP, ST_PAIRS, ST_PACK, ST_SELECT, ST_COUNT };
+enum Stage { ST_PREP = 0, ST_SORT, ST_SETUP, ST_PROFILE, ST_PAIRS, ST_PACK, ST_SELECT, ST_COUNT };
 struct Timing {
   std::mutex mu;
   bool on = false;
@@ -102,9 +104,23 @@ struct StageScope {  // brackets one stage's launches with a pair of events
 
 // ---- work space -------------------------------------------------------------
 struct Layout {
-  size_t o_recs, o_srecs, o_keys, o_perm, o_ca, o_desc, o_kc, o_cd, o_fl, o_xs, o_ys, o_mir,
-      o_feas, o_rows, total;
+  size_t o_recs, o_srecs, o_keys, o_rank, o_perm, o_ca, o_desc, o_kc, o_cd, o_fl, o_xs, o_ys, o_mir,
+      o_feas, o_rows, o_wdv, o_hdv, o_pcol, o_prow, o_Hs, o_atop, o_arena, total;
 };
+
+// Profile arena words for B scale slots over N charts in `count` atlases of
+// grown width up to Wdmax.  A chart of grown extents w x h takes w + h words
+// at a scale; per slot and chart `per` words are set aside (the single pack
+// spreads its 64 slots over scales 1..k_top, so it needs fewer on average),
+// plus four atlas widths per (atlas, slot).  Segments that do not fit are
+// evaluated directly, so the figure only trades memory for speed.
+int64_t arena_words(const Params& P) {
+  if (g_profile_cap >= 0) return g_profile_cap;
+  const int64_t per = P.B >= 64 ? 48 : 96;
+  int64_t v = (int64_t)P.B * P.N * per + (int64_t)P.B * P.count * 4 * P.Wdmax;
+  const int64_t lim = 0x7fffffffLL;  // word indices are int32
+  return v > lim ? lim : v;
+}
 
 Layout layout(const Params& P) {
   Layout L{};
@@ -118,6 +134,7 @@ Layout layout(const Params& P) {
   L.o_recs = take(n1 * sizeof(Chart));
   L.o_srecs = take(n1 * sizeof(Chart));
   L.o_keys = take(n1 * 8);
+  L.o_rank = take(n1 * 4);
   L.o_perm = take(n1 * 4);
   L.o_ca = take(n1 * 4);
   L.o_desc = take((size_t)P.count * sizeof(AtlasDesc));
@@ -129,6 +146,13 @@ Layout layout(const Params& P) {
   L.o_mir = take((size_t)P.B * n1);
   L.o_feas = take((size_t)P.count * P.B * 4);
   L.o_rows = take((size_t)P.count * P.B * 4);
+  L.o_wdv = take((size_t)P.B * n1 * 4);
+  L.o_hdv = take((size_t)P.B * n1 * 4);
+  L.o_pcol = take((size_t)P.B * n1 * 4);
+  L.o_prow = take((size_t)P.B * n1 * 4);
+  L.o_Hs = take(n1 * 4);
+  L.o_atop = take(8);
+  L.o_arena = take((size_t)P.arena_cap * 4);
   L.total = off;
   return L;
 }
@@ -139,6 +163,7 @@ Work carve(void* base, const Layout& L) {
   W.recs = reinterpret_cast<Chart*>(b + L.o_recs);
   W.srecs = reinterpret_cast<Chart*>(b + L.o_srecs);
   W.keys = reinterpret_cast<uint64_t*>(b + L.o_keys);
+  W.rank = reinterpret_cast<int32_t*>(b + L.o_rank);
   W.perm = reinterpret_cast<int32_t*>(b + L.o_perm);
   W.chart_atlas = reinterpret_cast<int32_t*>(b + L.o_ca);
   W.desc = reinterpret_cast<AtlasDesc*>(b + L.o_desc);
@@ -150,6 +175,13 @@ Work carve(void* base, const Layout& L) {
   W.mir = b + L.o_mir;
   W.feas = reinterpret_cast<int32_t*>(b + L.o_feas);
   W.rows = reinterpret_cast<int32_t*>(b + L.o_rows);
+  W.wdv = reinterpret_cast<int32_t*>(b + L.o_wdv);
+  W.hdv = reinterpret_cast<int32_t*>(b + L.o_hdv);
+  W.pcol = reinterpret_cast<int32_t*>(b + L.o_pcol);
+  W.prow = reinterpret_cast<int32_t*>(b + L.o_prow);
+  W.Hs = reinterpret_cast<int32_t*>(b + L.o_Hs);
+  W.atop = reinterpret_cast<unsigned long long*>(b + L.o_atop);
+  W.arena = reinterpret_cast<uint32_t*>(b + L.o_arena);
   return W;
 }
 
@@ -158,6 +190,7 @@ struct Job {
   Work W{};
   void* base = nullptr;  // owned (stream-ordered pool) when set
   PackLds L{};
+  int stage_cap = 0x7fffffff;
 };
 
 Params make_params(int count, int N, int q, int p, int B, int fixed_k, int nmax, int Wdmax) {
@@ -172,6 +205,8 @@ Params make_params(int count, int N, int q, int p, int B, int fixed_k, int nmax,
   P.fixed_k = fixed_k;
   P.nmax = nmax;
   P.Wdmax = Wdmax;
+  P.arena_cap = 0;
+  P.arena_cap = arena_words(P);
   return P;
 }
 
@@ -181,15 +216,16 @@ int make_job(Job& j, const Params& P, hipStream_t st, void* ws = nullptr, size_t
   j.P = P;
   const int budget = lds_budget();
   int b = budget - kPackStaticLds;
-  // a preferred cap (two workgroups per CU) yields to what the widest atlas needs
-  if (lds_cap > 0 && lds_cap < b && pack_lds_plan(P.nmax, P.Wdmax, lds_cap).SC >= 4 * P.Wdmax)
-    b = lds_cap;
+  // a preferred cap (two workgroups per CU) yields to what the widest atlas
+  // needs: the offsets of every configuration plus a staged row of twice the
+  // atlas width (compaction lets a row's boxes overlap)
+  if (lds_cap > 0 && lds_cap < b) {
+    const PackLds c = pack_lds_plan(P.nmax, P.Wdmax, lds_cap);
+    if (c.bytes <= lds_cap && c.PW >= 4 * c.RC + 3 * P.Wdmax) b = lds_cap;
+  }
   j.L = pack_lds_plan(P.nmax, P.Wdmax, b);
   if (j.L.bytes > b) return TABI_EINVAL;  // rows of this atlas cannot fit in LDS
-  if (g_stage_cap >= 0 && j.L.SC > g_stage_cap) {
-    j.L.bytes -= 4 * (j.L.SC - g_stage_cap);
-    j.L.SC = g_stage_cap;
-  }
+  j.stage_cap = g_stage_cap >= 0 ? g_stage_cap : 0x7fffffff;
   const Layout L = layout(P);
   if (ws) {
     if (ws_bytes < L.total) return TABI_EINVAL;
@@ -218,7 +254,9 @@ bool bad_atlas(int32_t w, int32_t h, int32_t p) {
 }
 
 int check_common(int32_t n, int32_t padding, int32_t quality) {
-  if (n < 0 || n > TABI_MAX_CHARTS || padding < 0 || quality < 0 || quality > 2) return TABI_EINVAL;
+  if (n < 0 || n > TABI_MAX_CHARTS || padding < 0 || padding > TABI_MAX_PADDING || quality < 0 ||
+      quality > 2)
+    return TABI_EINVAL;
   return TABI_OK;
 }
 
@@ -246,12 +284,16 @@ hipError_t run_search(Job& j, int rounds, int32_t* out_xy, uint8_t* out_orient, 
       e = launch_setup(j.P, j.W, r, st);
     }
     if (e == hipSuccess) {
+      StageScope t(ST_PROFILE, st);
+      e = launch_profiles(j.P, j.W, r, st);
+    }
+    if (e == hipSuccess) {
       StageScope t(ST_PAIRS, st);
       e = launch_pairs(j.P, j.W, r, st);
     }
     if (e == hipSuccess) {
       StageScope t(ST_PACK, st);
-      e = launch_pack(j.P, j.W, r, j.L.bytes, j.L.RC, j.L.SC, st);
+      e = launch_pack(j.P, j.W, r, j.L.bytes, j.L.RC, j.L.PW, j.stage_cap, st);
     }
     if (e == hipSuccess) {
       StageScope t(ST_SELECT, st);
@@ -270,7 +312,8 @@ int many_check(const int32_t* xy, const int32_t* vert_offsets, const int32_t* at
                int32_t max_side, int32_t padding, int32_t quality, int32_t* out_xy,
                uint8_t* out_orient, float* out_scale) {
   if (count < 0 || total_charts < 0 || max_charts < 0 || max_charts > TABI_MAX_CHARTS ||
-      max_side < 1 || (int64_t)max_side + padding > 16384 || padding < 0 || quality < 0 ||
+      max_side < 1 || (int64_t)max_side + padding > 16384 || padding < 0 ||
+      padding > TABI_MAX_PADDING || quality < 0 ||
       quality > 2)
     return TABI_EINVAL;
   if (count > 0 && (!atlas_offsets || !atlas_wh || !out_scale)) return TABI_EINVAL;
@@ -365,7 +408,8 @@ int tabi_pack_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t
 
 int64_t tabi_pack_many_workspace_bytes(int32_t count, int32_t total_charts, int32_t max_charts,
                                        int32_t max_side, int32_t padding, int32_t quality) {
-  if (count < 0 || total_charts < 0 || max_side < 1 || quality < 0 || quality > 2 || padding < 0)
+  if (count < 0 || total_charts < 0 || max_side < 1 || quality < 0 || quality > 2 || padding < 0 ||
+      padding > TABI_MAX_PADDING)
     return -1;
   return (int64_t)layout(many_params(count, total_charts, max_charts, max_side, padding, quality))
       .total;
@@ -464,6 +508,7 @@ int tabi_debug_pairs(const tabi_charts* charts, int32_t n, int32_t padding, int3
   if (!rc) rc = single_front(j, charts, 16384 - padding, 16384 - padding, st);
   hipError_t e = hipSuccess;
   if (!rc) e = launch_setup(j.P, j.W, 0, st);
+  if (!rc && e == hipSuccess) e = launch_profiles(j.P, j.W, 0, st);
   if (!rc && e == hipSuccess) e = launch_pairs(j.P, j.W, 0, st);
   if (!rc && e == hipSuccess && n > 0)
     e = hipMemcpyAsync(cd, j.W.cd, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st);
@@ -489,8 +534,10 @@ int tabi_debug_feasible(const tabi_charts* charts, int32_t n, int32_t atlas_w, i
   if (!rc) rc = single_front(j, charts, atlas_w, atlas_h, st);
   hipError_t e = hipSuccess;
   if (!rc) e = launch_setup(j.P, j.W, 0, st);
+  if (!rc && e == hipSuccess) e = launch_profiles(j.P, j.W, 0, st);
   if (!rc && e == hipSuccess) e = launch_pairs(j.P, j.W, 0, st);
-  if (!rc && e == hipSuccess) e = launch_pack(j.P, j.W, 0, j.L.bytes, j.L.RC, j.L.SC, st);
+  if (!rc && e == hipSuccess)
+    e = launch_pack(j.P, j.W, 0, j.L.bytes, j.L.RC, j.L.PW, j.stage_cap, st);
   if (!rc && e == hipSuccess) e = launch_scatter(j.P, j.W, out_xy, out_orient, feasible, rows, st);
   if (!rc && e != hipSuccess) rc = hip_fail(e);
   free_job(j, st);
@@ -511,6 +558,11 @@ const char* tabi_last_hip_error(void) { return g_last_hip; }
 
 int tabi_debug_set_stage_cap(int32_t entries) {
   g_stage_cap = entries;
+  return TABI_OK;
+}
+
+int tabi_debug_set_profile_cap(int64_t words) {
+  g_profile_cap = words < 0 ? -1 : (words > 0x7fffffffLL ? 0x7fffffffLL : words);
   return TABI_OK;
 }
 

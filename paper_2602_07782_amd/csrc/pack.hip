@@ -8,8 +8,13 @@
 //                                      first overflow by ballot; folds with
 //                                      and without compaction and at full and
 //                                      knee width come from the same two scans
-//   3. staging                         grown TopEdge/BottomEdge of the row's
-//                                      candidate charts into LDS (int16)
+//   3. staging                         the candidates' stored grown
+//                                      TopEdge/BottomEdge (one contiguous range
+//                                      of the profile arena) into LDS with a
+//                                      texel -> chart map; rows that do not fit
+//                                      read the arena directly, and charts
+//                                      without stored profiles are evaluated
+//                                      from their proxy records
 //   4. push                            every texel of every configuration:
 //                                      frontline - TopEdge, segmented max per
 //                                      chart across the wavefront, one LDS
@@ -139,17 +144,20 @@ __device__ inline int32_t block_reduce_min(int32_t v, int32_t* red) {
   return r;
 }
 
-__global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, int RC, int SC) {
+// at most 128 VGPRs, so that two 512-thread workgroups can share a CU when
+// their shared memory allows it (batched packs)
+__global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) void k_pack(
+    Params P, Work w, int round, int RC, int PW, int stage_cap) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t s_cnt[4];
   __shared__ int32_t s_red[PACK_WAVES * 6];
   __shared__ int64_t s_red64[PACK_WAVES];
   __shared__ int32_t s_lrn, s_lrover;
   __shared__ int32_t s_lr[LRCAP][3];
-  // per-row window of chart data read by the fold and the knee test:
-  // grown width, compacting distance to the next chart, unscaled height
+  // window of chart data read by the fold and the knee test, charts
+  // [wb, wb + nwin): grown width, compacting distance to the next chart,
+  // unscaled height; it slides when fewer than FWIN / 2 charts remain ahead
   __shared__ int32_t s_wd[FWIN], s_cdn[FWIN], s_H[FWIN];
-  __shared__ int32_t s_h0;
 
   const int s = blockIdx.x, a = blockIdx.y;
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
@@ -167,16 +175,21 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
   }
   const int topt = P.q == 0 ? 5 : (P.q == 1 ? 2 : (n > 10000 ? 1 : 0));
   const size_t slot = (size_t)s * P.N + d.c0;
+  // dynamic LDS: frontline F[Wd], fold offsets without / with compaction
+  // Xoff, Xon[RC+1], then a per-row pool of PW words
   int32_t* F = reinterpret_cast<int32_t*>(smem);
   int32_t* Xoff = F + Wd;
   int32_t* Xon = Xoff + (RC + 1);
-  int32_t* Y = Xon + (RC + 1);
-  int16_t* stT = reinterpret_cast<int16_t*>(Y + 4 * RC);
-  int16_t* stB = stT + SC;
+  int32_t* pool = Xon + (RC + 1);
   const unsigned char* kcb = w.kc + slot * P.stride;
   const Chart* ch = w.srecs + d.c0;
   const int32_t* cdv = w.cd + slot;
   const uint8_t* flv = w.fl + slot;
+  const int32_t* wdv = w.wdv + slot;
+  const int32_t* hdv = w.hdv + slot;
+  const int32_t* pcolv = w.pcol + slot;
+  const int32_t* prowv = w.prow + slot;
+  const int32_t* Hs = w.Hs + d.c0;
   int32_t* xs = w.xs + slot;
   int32_t* ys = w.ys + slot;
   uint8_t* mir = w.mir + slot;
@@ -189,19 +202,27 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
   int rs = 0, rows = 0, feasible = 1, tail = 0, trow = 0;
   int kn = 0, kdir = 0, kl = 0, kr = 0;
   int32_t fmax = 0;
+  int wb = -FWIN, nwin = 0;
+  // arena word of the row's first grown column (-1: no stored profiles); the
+  // charts of a segment are stored back to back, so it advances by the
+  // committed grown width
+  int32_t pc0 = n > 0 ? pcolv[0] : -1;
 
   for (;;) {
     __syncthreads();
     if (rs >= n) break;
-    const int nwin = min(FWIN, n - rs);
-    for (int t = tid; t < nwin; t += PACK_NT) {
-      const int c = rs + t;
-      s_wd[t] = KV(c).hd->w + p;
-      s_cdn[t] = c + 1 < n ? cdv[c + 1] : 0;
-      s_H[t] = ch[c].H;
+    if (rs - wb > FWIN / 2) {
+      wb = rs;
+      nwin = min(FWIN, n - wb);
+      for (int t = tid; t < nwin; t += PACK_NT) {
+        const int c = wb + t;
+        s_wd[t] = wdv[c];
+        s_cdn[t] = c + 1 < n ? cdv[c + 1] : 0;
+        s_H[t] = Hs[c];
+      }
+      __syncthreads();
     }
-    if (tid == 0) s_h0 = KV(rs).hd->h;
-    __syncthreads();
+    const int r0 = rs - wb;  // window index of the row's first chart
     // ---- 1. knee location update (Alg. 4)
     if (kn) {
       const int probe = kdir == DIR_LR ? kr : kl - 1;
@@ -222,8 +243,9 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
         }
       }
     }
-    // ---- t_opt switch (Sec. 4.4)
-    if (!tail && !kn && 100 * (int64_t)s_h0 < (int64_t)topt * Ha) tail = 1;
+    // ---- t_opt switch (Sec. 4.4), on the first chart's texel height
+    const int64_t h0 = cdiv64((int64_t)k * s_H[r0], QS);
+    if (!tail && !kn && 100 * h0 < (int64_t)topt * Ha) tail = 1;
     // ---- 2. folding (Alg. 2), wavefront 0
     const int kw = kn ? (kdir == DIR_LR ? Wd - kr : kl) : 0;
     if (wv == 0) {
@@ -232,11 +254,11 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
       for (int t0 = 0; cfn < 0; t0 += WAVE) {
         const int t = t0 + lane, c = rs + t;
         int wd = Wd + 1, cdn = 0;
-        if (t < nwin) {
-          wd = s_wd[t];
-          cdn = s_cdn[t];
+        if (r0 + t < nwin) {
+          wd = s_wd[r0 + t];
+          cdn = s_cdn[r0 + t];
         } else if (c < n) {
-          wd = KV(c).hd->w + p;
+          wd = wdv[c];
           if (c + 1 < n) cdn = cdv[c + 1];
         }
         const int ao = wd, an = wd - cdn;
@@ -284,49 +306,48 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
       }
     }
     for (int j = ncfg; j < 4; ++j) { c_cnt[j] = 0; c_hc[j] = 0; c_dir[j] = 0; c_R0[j] = 0; c_R1[j] = 0; }
+    // every configuration takes a prefix of the cfn candidates
     const int cand = cfn;
-    int cmax = 0, anyhc = 0;
+    int anyhc = 0, yofs[4], ysum = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) { cmax = max(cmax, c_cnt[j]); anyhc |= c_hc[j]; }
-    const int E = Xoff[cand], Eall = Xoff[cmax];
-    const int U = E - p * cand;          // undilated texel columns of the candidates
-    // stage layout (int16 units of stT / stB): grown bounds [0,E), undilated
-    // bounds [E, E+U), texel -> chart map in stT[E+U, 2E+U)
-    const bool staged = 2 * E + U <= SC;
-    int16_t* emap = stT + E + U;
-    // ---- 3. staging, offset init, neighbour-free pairs that share columns
-    if (staged) {
-      // undilated TopEdge / BottomEdge once per texel column, behind the grown ones
-      for (int u = tid; u < U; u += PACK_NT) {
-        int lo = 0, hi = cand - 1;  // chart t with Xoff[t] - p t <= u
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (Xoff[mid] - p * mid <= u) lo = mid; else hi = mid - 1;
+    for (int j = 0; j < 4; ++j) { anyhc |= c_hc[j]; yofs[j] = ysum; ysum += c_cnt[j]; }
+    const int E = Xoff[cand];  // grown texel columns of the candidates
+    // pool: offsets Y of configuration j at pool[yofs[j]], then (when staged)
+    // packed (top, bottom) of texel e at st[e] and its chart at emap[e]
+    int32_t* Yb = pool;
+    uint32_t* st = reinterpret_cast<uint32_t*>(pool + ysum);
+    int16_t* emap = reinterpret_cast<int16_t*>(pool + ysum + E);
+    const bool prof = pc0 >= 0;  // stored profiles: texel e of the row is word pc0 + e
+    const uint32_t* gprof = w.arena + (prof ? pc0 : 0);
+    const bool staged = prof && E <= stage_cap && ysum + E + (E + 1) / 2 <= PW;
+    // grown top (tp) / bottom (bt) of texel e and its chart t in the row
+    auto texel = [&](int e, int& t, int32_t& tp, int32_t& bt) {
+      if (staged) {
+        t = emap[e];
+        const uint32_t v = st[e];
+        tp = lo16(v);
+        bt = hi16(v);
+      } else {
+        t = find_chart(Xoff, cand, e);
+        if (prof) {
+          const uint32_t v = gprof[e];
+          tp = lo16(v);
+          bt = hi16(v);
+        } else {
+          column_bounds_grown(KV(rs + t), ch[rs + t], K, k, p, e - Xoff[t], tp, bt);
         }
-        int32_t tp, bt;
-        column_bounds(KV(rs + lo), ch[rs + lo], K, k, u - (Xoff[lo] - p * lo), tp, bt);
-        stT[E + u] = (int16_t)tp;
-        stB[E + u] = (int16_t)bt;
       }
-      __syncthreads();
-      // grown column i: min top / max bottom over undilated columns [i-p, i]
+    };
+    // ---- 3. staging, offset init, non-neighbour pairs that share columns
+    if (staged) {
       for (int e = tid; e < E; e += PACK_NT) {
-        const int t = find_chart(Xoff, cand, e);
-        emap[e] = (int16_t)t;
-        const int i = e - Xoff[t], wt = Xoff[t + 1] - Xoff[t] - p;
-        const int base = E + Xoff[t] - p * t;
-        int32_t tp = BIG, bt = -BIG;
-        for (int c = max(0, i - p); c <= min(wt - 1, i); ++c) {
-          tp = min(tp, (int32_t)stT[base + c]);
-          bt = max(bt, (int32_t)stB[base + c]);
-        }
-        stT[e] = (int16_t)tp;
-        stB[e] = (int16_t)(bt + p);
+        st[e] = gprof[e];
+        emap[e] = (int16_t)find_chart(Xoff, cand, e);
       }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      for (int t = tid; t < c_cnt[j]; t += PACK_NT) Y[j * RC + t] = -BIG;
+      for (int t = tid; t < c_cnt[j]; t += PACK_NT) Yb[yofs[j] + t] = -BIG;
     if (anyhc) {
       for (int A = tid; A + 2 < cand; A += PACK_NT) {
         const int wdA = Xoff[A + 1] - Xoff[A];
@@ -340,25 +361,14 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
     __syncthreads();
     const int lrn = min(s_lrn, LRCAP);
     if (s_lrover) { feasible = -2; break; }
-    for (int q = wv; q < lrn; q += PACK_WAVES) {
-      const int A = s_lr[q][0], C = s_lr[q][1];
-      const KView va = KV(rs + A);
-      const PairSweep sw = pair_sweep(va, ch[rs + A], KV(rs + C), ch[rs + C], K, k, p);
-      const int f = pair_flags_at(sw, va.hd->w + p, Xon[C] - Xon[A]);
-      if (lane == 0) s_lr[q][2] = f;
-    }
-    __syncthreads();
     // ---- 4. push every configuration against the committed frontline
-    for (int e0 = wv * WAVE; e0 < Eall; e0 += PACK_NT) {
+    for (int e0 = wv * WAVE; e0 < E; e0 += PACK_NT) {
       const int e = e0 + lane;
-      const bool valid = e < Eall;
-      const int t = valid ? (staged ? (int)emap[e] : find_chart(Xoff, cand, e)) : -1;
+      const bool valid = e < E;
+      int t = -1;
+      int32_t tp = 0, bt = 0;
+      if (valid) texel(e, t, tp, bt);
       const int i = valid ? e - Xoff[t] : 0;
-      int32_t tp = 0;
-      if (valid) {
-        if (staged) tp = stT[e];
-        else { int32_t bt; column_bounds_grown(KV(rs + t), ch[rs + t], K, k, p, i, tp, bt); }
-      }
       const bool head = lane == 0 || __shfl_up(t, 1) != t;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -370,29 +380,43 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
           v = F[col] - tp;
         }
         v = seg_max_to_head(v, t);
-        if (head && v > -BIG) atomicMax(&Y[j * RC + t], v);
+        if (head && v > -BIG) atomicMax(&Yb[yofs[j] + t], v);
       }
+    }
+    // interlock flags of the non-neighbour pairs, read only by the correction
+    for (int q = wv; q < lrn; q += PACK_WAVES) {
+      const int A = s_lr[q][0], C = s_lr[q][1];
+      const int wdA = Xoff[A + 1] - Xoff[A];
+      PairSweep sw;
+      if (prof) {
+        sw = pair_sweep_rows(w.arena + prowv[rs + A], hdv[rs + A], w.arena + prowv[rs + C],
+                             hdv[rs + C], wdA);
+      } else {
+        sw = pair_sweep(KV(rs + A), ch[rs + A], KV(rs + C), ch[rs + C], K, k, p);
+      }
+      const int f = pair_flags_at(sw, wdA, Xon[C] - Xon[A]);
+      if (lane == 0) s_lr[q][2] = f;
     }
     __syncthreads();
     // ---- 5. correction, one wavefront per compacted configuration
     if (wv < ncfg) {
       const int cnt = wv == 0 ? c_cnt[0] : wv == 1 ? c_cnt[1] : wv == 2 ? c_cnt[2] : c_cnt[3];
       const int hc = wv == 0 ? c_hc[0] : wv == 1 ? c_hc[1] : wv == 2 ? c_hc[2] : c_hc[3];
-      if (hc) correct_offsets(Y + wv * RC, cnt, flv + rs, s_lr, lrn);
+      const int yo = wv == 0 ? yofs[0] : wv == 1 ? yofs[1] : wv == 2 ? yofs[2] : yofs[3];
+      if (hc) correct_offsets(Yb + yo, cnt, flv + rs, s_lr, lrn);
     }
     __syncthreads();
     // ---- 6. scores
     int32_t M[4] = {-BIG, -BIG, -BIG, -BIG};
-    for (int e0 = wv * WAVE; e0 < Eall; e0 += PACK_NT) {
+    for (int e0 = wv * WAVE; e0 < E; e0 += PACK_NT) {
       const int e = e0 + lane;
-      if (e < Eall) {
-        const int t = staged ? (int)emap[e] : find_chart(Xoff, cand, e);
-        int32_t bt;
-        if (staged) bt = stB[e];
-        else { int32_t tp; column_bounds_grown(KV(rs + t), ch[rs + t], K, k, p, e - Xoff[t], tp, bt); }
+      if (e < E) {
+        int t;
+        int32_t tp, bt;
+        texel(e, t, tp, bt);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          if (t < c_cnt[j]) M[j] = max(M[j], Y[j * RC + t] + bt);
+          if (t < c_cnt[j]) M[j] = max(M[j], Yb[yofs[j] + t] + bt);
       }
     }
     int32_t fr = -BIG;
@@ -437,16 +461,15 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
     const int w_R0 = win == 0 ? c_R0[0] : win == 1 ? c_R0[1] : win == 2 ? c_R0[2] : c_R0[3];
     const int w_R1 = win == 0 ? c_R1[0] : win == 1 ? c_R1[1] : win == 2 ? c_R1[2] : c_R1[3];
     const int32_t w_score = win == 0 ? whole[0] : win == 1 ? whole[1] : win == 2 ? whole[2] : whole[3];
-    const int32_t* Yw = Y + win * RC;
+    const int32_t* Yw = Yb + (win == 0 ? yofs[0] : win == 1 ? yofs[1] : win == 2 ? yofs[2] : yofs[3]);
     __syncthreads();  // everyone has read the reductions and Y before commit
     // ---- commit: frontline update, placements
     const int Ew = Xoff[w_cnt];
     for (int e = tid; e < Ew; e += PACK_NT) {
-      const int t = staged ? (int)emap[e] : find_chart(Xoff, cand, e);
+      int t;
+      int32_t tp, bt;
+      texel(e, t, tp, bt);
       const int i = e - Xoff[t];
-      int32_t bt;
-      if (staged) bt = stB[e];
-      else { int32_t tp; column_bounds_grown(KV(rs + t), ch[rs + t], K, k, p, i, tp, bt); }
       const int X = w_hc ? Xon[t] : Xoff[t];
       const int col = w_dir == DIR_LR ? w_R0 + X + i : w_R1 - 1 - X - i;
       atomicMax(&F[col], Yw[t] + bt);
@@ -464,8 +487,8 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
     if (!tail && !knee_used) {
       int64_t best = -1;
       for (int t = tid; t + 1 < w_cnt; t += PACK_NT) {
-        const int64_t h1 = t < nwin ? s_H[t] : ch[rs + t].H;
-        const int64_t h2 = t + 1 < nwin ? s_H[t + 1] : ch[rs + t + 1].H, dl = h1 - h2;
+        const int64_t h1 = r0 + t < nwin ? s_H[r0 + t] : Hs[rs + t];
+        const int64_t h2 = r0 + t + 1 < nwin ? s_H[r0 + t + 1] : Hs[rs + t + 1], dl = h1 - h2;
         if (10 * dl >= 256 * (int64_t)Ha && 5 * dl >= h1) {
           const int64_t key = (dl << 20) | (int64_t)((1 << 20) - 1 - t);
           best = key > best ? key : best;
@@ -492,6 +515,7 @@ __global__ __launch_bounds__(PACK_NT) void k_pack(Params P, Work w, int round, i
     ++rows;
     if (w_score > Hd) { feasible = 0; break; }
     rs += w_cnt;
+    if (pc0 >= 0) pc0 += Ew;
   }
   if (tid == 0) {
     w.feas[a * P.B + s] = feasible;
@@ -584,12 +608,12 @@ PackLds pack_lds_plan(int nmax, int Wd, int budget) {
   PackLds L;
   L.RC = nmax < Wd ? nmax : Wd;
   if (L.RC < 1) L.RC = 1;
-  const int fixed = 4 * Wd + 8 * (L.RC + 1) + 16 * L.RC;
-  int sc = (budget - fixed) / 4;
-  if (sc < 0) sc = 0;
-  if (sc > (1 << 20)) sc = 1 << 20;
-  L.SC = sc & ~7;
-  L.bytes = fixed + 4 * L.SC;
+  const int fixed = 4 * Wd + 8 * (L.RC + 1);
+  int pw = (budget - fixed) / 4;
+  if (pw < 4 * L.RC) pw = 4 * L.RC;  // the offsets of four configurations must fit
+  if (pw > (1 << 20)) pw = 1 << 20;
+  L.PW = pw;
+  L.bytes = fixed + 4 * L.PW;
   return L;
 }
 
@@ -604,9 +628,10 @@ hipError_t pack_set_max_lds(int bytes) {
                              bytes);
 }
 
-hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes, int RC, int SC,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_pack, dim3(P.B, P.count), dim3(PACK_NT), lds_bytes, st, P, w, round, RC, SC);
+hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes, int RC, int PW,
+                       int stage_cap, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack, dim3(P.B, P.count), dim3(PACK_NT), lds_bytes, st, P, w, round, RC, PW,
+                     stage_cap);
   return hipGetLastError();
 }
 

@@ -1,9 +1,10 @@
 // Horizontal compacting distance and interlock flags of sorted neighbours
 // (Sec. 4.1.2 "Compacting Horizontal Gaps", App. A "Detecting Interlocking
-// Charts"), one wavefront per (scale slot, pair).  The two charts' proxy
-// records are copied to LDS once; one sweep over the rows gives the
-// compacting distance (a min-reduction) and both interlock thresholds
-// (prefix max / prefix min scans).
+// Charts"), one wavefront per (scale slot, pair).  One sweep over the rows
+// gives the compacting distance (a min-reduction) and both interlock
+// thresholds (prefix max / prefix min scans), reading the stored grown rows
+// of both charts; without stored profiles the two charts' proxy records are
+// copied to LDS and the rows evaluated directly.
 #include "tabi_internal.h"
 #include "pairs_dev.h"
 
@@ -31,6 +32,17 @@ __global__ __launch_bounds__(256) void k_pairs(Params P, Work w, int round) {
   if (k < 1) return;
   if (c == d.c0) {
     if (lane == 0) { w.cd[slot + c] = 0; w.fl[slot + c] = 0; }
+    return;
+  }
+  const int32_t prA = w.prow[slot + c - 1], prB = w.prow[slot + c];
+  if (prA >= 0 && prB >= 0) {  // stored grown rows
+    const int wdA = w.wdv[slot + c - 1];
+    const PairSweep r = pair_sweep_rows(w.arena + prA, w.hdv[slot + c - 1], w.arena + prB,
+                                        w.hdv[slot + c], wdA);
+    if (lane == 0) {
+      w.cd[slot + c] = r.cd;
+      w.fl[slot + c] = (uint8_t)pair_flags_at(r, wdA, wdA - r.cd);
+    }
     return;
   }
   const int K = P.K, p = P.p, stride = P.stride;

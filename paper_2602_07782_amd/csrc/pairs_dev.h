@@ -71,6 +71,38 @@ __device__ inline PairSweep pair_sweep(const KView& A, const Chart& cA, const KV
   return r;
 }
 
+// The same sweep over stored grown rows: ra / rb hold, per grown row j, the
+// grown left bound L' (low half) and grown right bound R' (high half, gutter
+// included) of A and B.  Grown rows need no shuffles, so each chunk advances
+// a full wavefront.
+__device__ inline PairSweep pair_sweep_rows(const uint32_t* ra, int hdA, const uint32_t* rb,
+                                            int hdB, int wdA) {
+  const int lane = lane_id();
+  int32_t cd = BIG, D1 = -BIG, D2 = -BIG;
+  int32_t carry_max = -BIG, carry_min = BIG;
+  for (int j0 = 0; j0 < hdA; j0 += WAVE) {
+    const int j = j0 + lane;
+    const bool act = j < hdA, shr = act && j < hdB;
+    const int32_t Ra = act ? hi16(ra[j]) : -BIG;
+    const int32_t Lb = shr ? lo16(rb[j]) : BIG;
+    if (shr) cd = min(cd, wdA - Ra + Lb);
+    const int32_t imax = wave_incl_max(Ra), imin = wave_incl_min(Lb);
+    int32_t emax = __shfl_up(imax, 1), emin = __shfl_up(imin, 1);
+    if (lane == 0) { emax = -BIG; emin = BIG; }
+    emax = max(emax, carry_max);
+    emin = min(emin, carry_min);
+    if (shr && j >= 1) D1 = max(D1, emax - Lb);
+    if (act && j >= 1) D2 = max(D2, Ra - emin);
+    carry_max = max(carry_max, __shfl(imax, WAVE - 1));
+    carry_min = min(carry_min, __shfl(imin, WAVE - 1));
+  }
+  PairSweep r;
+  r.cd = wave_min(cd);
+  r.D1 = wave_max(D1);
+  r.D2 = wave_max(D2);
+  return r;
+}
+
 // Interlock flags for box offset d (bit0: B may not move above A, bit1: A may
 // not move above B); none without a shared column.
 __device__ inline int32_t pair_flags_at(const PairSweep& s, int wdA, int d) {

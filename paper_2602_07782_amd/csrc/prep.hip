@@ -5,10 +5,12 @@
 //   k_prep   one wavefront per chart: AABB, quarter turn, area, local-AABB
 //            slices (LDS atomics per edge), orientation, 8-direction OBB
 //            (Sec. 4.1.1; App. A "Computing Local AABBs / OBBs / Orientations")
-//   k_sort   height-descending order within each atlas (Sec. 3.1, 4.3)
+//   k_rank,  height-descending order within each atlas (Sec. 3.1, 4.3):
+//   k_place  tiled rank counting, then a scatter
 //   k_plan   largest candidate scale per atlas (area and largest chart fit)
 //   k_setup  per (scale slot, chart): texel rectangles of the slices and the
-//            OBB side split points used by per-texel evaluation
+//            OBB side split points used by per-texel evaluation, grown
+//            extents
 #include "tabi_internal.h"
 
 namespace tabi {
@@ -112,6 +114,7 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
       out->valid = 0;
       out->src = local;
       w.keys[c] = ((uint64_t)0x7fffff << 41) | ((uint64_t)0x7fffff << 18) | (uint64_t)local;
+      if (w.rank) w.rank[c] = 0;
       if (w.desc) atomicOr(&w.desc[a].bad, 1);
     }
     return;
@@ -233,14 +236,17 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
     out->valid = 1;
     // ascending key = height descending, width descending, input index
     w.keys[c] = ((uint64_t)(0x7fffff - H) << 41) | ((uint64_t)(0x7fffff - W) << 18) | (uint64_t)local;
+    if (w.rank) w.rank[c] = 0;
   }
 }
 
-// rank of each chart's key inside its atlas (keys are unique); scatter to the
-// sorted position.  Keys of the atlases spanned by the block are streamed
-// through LDS in tiles of 256 and every thread counts the smaller ones of its
-// own atlas.
-__global__ __launch_bounds__(256) void k_sort(Params P, Work w) {
+// Rank of each chart's key inside its atlas (keys are unique), then scatter
+// to the sorted position.  Workgroup (x, y) holds the 256 charts of tile x
+// and streams key tiles y, y + gridDim.y, ... of the union of the atlases
+// those charts belong to through LDS; every thread counts the smaller keys
+// of its own atlas and adds the count to its rank (integer atomics: the sum
+// does not depend on the order).  Ranks start at zero (written with the keys).
+__global__ __launch_bounds__(256) void k_rank(Params P, Work w) {
   __shared__ uint64_t tile[256];
   __shared__ int s_lo, s_hi;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -259,7 +265,7 @@ __global__ __launch_bounds__(256) void k_sort(Params P, Work w) {
   __syncthreads();
   const int blo = s_lo, bhi = s_hi;
   int rank = 0;
-  for (int base = blo; base < bhi; base += 256) {
+  for (int base = blo + (int)blockIdx.y * 256; base < bhi; base += (int)gridDim.y * 256) {
     const int i = base + threadIdx.x;
     tile[threadIdx.x] = i < bhi ? w.keys[i] : ~0ull;
     __syncthreads();
@@ -269,11 +275,16 @@ __global__ __launch_bounds__(256) void k_sort(Params P, Work w) {
     }
     __syncthreads();
   }
-  if (act) {
-    const int pos = lo + rank;
-    w.srecs[pos] = w.recs[c];
-    w.perm[pos] = c - lo;
-  }
+  if (act && rank) atomicAdd(&w.rank[c], rank);
+}
+
+__global__ __launch_bounds__(256) void k_place(Params P, Work w) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.N) return;
+  const int lo = w.desc[w.chart_atlas[c]].c0;
+  const int pos = lo + w.rank[c];
+  w.srecs[pos] = w.recs[c];
+  w.perm[pos] = c - lo;
 }
 
 // candidate scales: the charts' total area and the largest chart must fit
@@ -318,6 +329,7 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
 __global__ __launch_bounds__(256) void k_setup(Params P, Work w, int round) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
+  if (c == 0 && s == 0) *w.atop = 0;  // the profile arena is laid out afresh each round
   if (c >= P.N) return;
   const AtlasDesc d = w.desc[w.chart_atlas[c]];
   const bool run = P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1);
@@ -332,6 +344,10 @@ __global__ __launch_bounds__(256) void k_setup(Params P, Work w, int round) {
   KRect* rc = reinterpret_cast<KRect*>(base + sizeof(KHead) + 4 * sizeof(KSide));
   const int64_t kk = k, W = ch.W, H = ch.H;
   const int32_t wt = (int32_t)cdiv64(kk * W, QS), ht = (int32_t)cdiv64(kk * H, QS);
+  const size_t sc = (size_t)s * P.N + c;
+  w.wdv[sc] = wt + P.p;
+  w.hdv[sc] = ht + P.p;
+  if (s == 0) w.Hs[c] = ch.H;
   KHead h;
   h.w = wt;
   h.h = ht;
@@ -421,6 +437,7 @@ __global__ __launch_bounds__(256) void k_from_records(Params P, Work w, const Ch
   w.recs[c] = ch;
   w.chart_atlas[c] = a;
   const uint64_t local = (uint64_t)ch.src;
+  w.rank[c] = 0;
   if (ch.valid) {
     w.keys[c] = ((uint64_t)(0x7fffff - ch.H) << 41) | ((uint64_t)(0x7fffff - ch.W) << 18) | local;
   } else {
@@ -468,7 +485,16 @@ hipError_t launch_prep(const Params& P, const Work& w, const int32_t* xy, const 
 }
 
 hipError_t launch_sort(const Params& P, const Work& w, hipStream_t st) {
-  if (P.N > 0) hipLaunchKernelGGL(k_sort, dim3((P.N + 255) / 256), dim3(256), 0, st, P, w);
+  if (P.N > 0) {
+    // key tiles per chart tile: a tile's atlases span at most 2 nmax + 256
+    // charts when every atlas holds at most nmax (longer spans are still
+    // covered, by the loop inside k_rank)
+    const int tiles = (P.N + 255) / 256;
+    int ny = (2 * P.nmax + 255) / 256 + 1;
+    if (ny > tiles) ny = tiles;
+    hipLaunchKernelGGL(k_rank, dim3(tiles, ny), dim3(256), 0, st, P, w);
+    hipLaunchKernelGGL(k_place, dim3(tiles), dim3(256), 0, st, P, w);
+  }
   hipLaunchKernelGGL(k_plan, dim3(P.count), dim3(256), 0, st, P, w);
   return hipGetLastError();
 }

@@ -208,6 +208,20 @@ __device__ inline void row_bounds_grown(const KView& kv, const Chart& ch, int K,
 }
 
 // ---------------------------------------------------------------------------
+// stored per-texel profiles: two int16 bounds in one 32-bit word
+// ---------------------------------------------------------------------------
+// Bounds stay within a chart's own texel extent (plus the gutter); only a
+// chart larger than any atlas would reach the clamp, and such a chart fails
+// its scale on width or height whichever value is stored.
+__device__ inline uint32_t pack16(int32_t lo, int32_t hi) {
+  const int32_t a = lo < -32768 ? -32768 : (lo > 32767 ? 32767 : lo);
+  const int32_t b = hi < -32768 ? -32768 : (hi > 32767 ? 32767 : hi);
+  return (uint32_t)(uint16_t)(int16_t)a | ((uint32_t)(uint16_t)(int16_t)b << 16);
+}
+__device__ inline int32_t lo16(uint32_t v) { return (int32_t)(int16_t)(uint16_t)(v & 0xffffu); }
+__device__ inline int32_t hi16(uint32_t v) { return (int32_t)v >> 16; }
+
+// ---------------------------------------------------------------------------
 // wavefront helpers
 // ---------------------------------------------------------------------------
 __device__ inline int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }

@@ -30,6 +30,7 @@ struct Params {
   int32_t fixed_k;     // > 0: evaluate exactly this scale in slot 0 (diagnostics)
   int32_t nmax;        // largest chart count of one atlas the work space was sized for
   int32_t Wdmax;       // largest grown atlas width the shared memory was sized for
+  int64_t arena_cap;   // 32-bit words of the profile arena (0: no stored profiles)
 };
 
 // Work-space views (device pointers).
@@ -37,6 +38,7 @@ struct Work {
   Chart* recs;          // [N] by input position
   Chart* srecs;         // [N] by sorted position (per atlas)
   uint64_t* keys;       // [N]
+  int32_t* rank;        // [N] position of the chart within its atlas's sorted order
   int32_t* perm;        // [N] sorted position -> local input index
   int32_t* chart_atlas; // [N]
   AtlasDesc* desc;      // [count]
@@ -48,6 +50,14 @@ struct Work {
   uint8_t* mir;         // [B][N] row mirror bit
   int32_t* feas;        // [count][B] 1 feasible, 0 not, -1 not evaluated
   int32_t* rows;        // [count][B]
+  int32_t* wdv;         // [B][N] grown width w + p at the slot's scale
+  int32_t* hdv;         // [B][N] grown height h + p
+  int32_t* pcol;        // [B][N] arena word of the chart's first grown column, -1 none
+  int32_t* prow;        // [B][N] arena word of the chart's first grown row, -1 none
+  int32_t* Hs;          // [N] unscaled height (Q8) by sorted position
+  unsigned long long* atop;  // arena words handed out in this round
+  uint32_t* arena;      // profiles: per grown column (top, bottom), per grown row
+                        // (left, right), int16 pairs (pack16)
 };
 
 // scale of slot s of round r for an atlas
@@ -66,9 +76,10 @@ hipError_t launch_splice(Chart* dst, const int32_t* idx, int m, const Chart* src
 hipError_t launch_sort(const Params& P, const Work& w, hipStream_t st);
 hipError_t launch_plan(const Params& P, const Work& w, hipStream_t st);
 hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t st);
+hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_t st);
 hipError_t launch_pairs(const Params& P, const Work& w, int round, hipStream_t st);
-hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes, int RC, int SC,
-                       hipStream_t st);
+hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes, int RC, int PW,
+                       int stage_cap, hipStream_t st);
 hipError_t launch_select(const Params& P, const Work& w, int round, int last_round,
                          int32_t* out_xy, uint8_t* out_orient, float* out_scale, hipStream_t st);
 
@@ -78,9 +89,11 @@ hipError_t launch_scatter(const Params& P, const Work& w, int32_t* out_xy, uint8
 hipError_t pack_set_max_lds(int bytes);
 int pack_static_lds();
 
-// shared-memory plan of the packing kernel
+// shared-memory plan of the packing kernel: RC charts per row at most, a
+// per-row pool of PW 32-bit words (offsets of every configuration, then the
+// staged texel bounds and the texel -> chart map when they fit)
 struct PackLds {
-  int RC, SC, bytes;
+  int RC, PW, bytes;
 };
 PackLds pack_lds_plan(int nmax, int Wd, int budget);
 

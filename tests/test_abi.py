@@ -47,3 +47,26 @@ def test_lds_plan_is_host_only():
         pytest.skip("library not built")
     b = tabi.lib().tabi_pack_lds_bytes(2000, 2048, 2)
     assert b > 4 * 2050
+
+
+def test_padding_limit_and_arena_sizing_are_host_only():
+    """Padding above TABI_MAX_PADDING is refused before any device work, and
+    the stored-profile arena is part of the batched work space."""
+    import paper_2602_07782_amd as tabi
+    if not os.path.exists(tabi.LIB_PATH):
+        pytest.skip("library not built")
+    L = tabi.lib()
+    hdr = open(os.path.join(ROOT, "include", "tabi.h")).read()
+    maxp = int(re.search(r"#define TABI_MAX_PADDING (\d+)", hdr).group(1))
+    ws = L.tabi_pack_many_workspace_bytes
+    ws.restype = ctypes.c_int64
+    assert ws(4, 8000, 2000, 2048, maxp, 2) > 0
+    assert ws(4, 8000, 2000, 2048, maxp + 1, 2) == -1
+    full = ws(4, 8000, 2000, 2048, 2, 2)
+    tabi.debug_set_profile_cap(0)
+    try:
+        none = ws(4, 8000, 2000, 2048, 2, 2)
+    finally:
+        tabi.debug_set_profile_cap(-1)
+    # 8 scale slots x 8000 charts x 96 words + 8 x 4 x 4 x 2050 words
+    assert full - none >= 4 * (8 * 8000 * 96 + 8 * 4 * 4 * 2050)

@@ -190,8 +190,9 @@ def test_repeat_is_bitwise_identical(tabi):
 
 @pytest.mark.parametrize("cap", [0, 700])
 def test_pack_parity_without_row_staging(tabi, orc, cap):
-    """Rows whose texel bounds do not fit the staging area are evaluated
-    directly; same results (cap 0: every row, 700: the wide ones)."""
+    """Rows whose texel bounds do not fit the staging area read the stored
+    profiles from device memory; same results (cap 0: every row, 700: the
+    wide ones)."""
     tabi.debug_set_stage_cap(cap)
     try:
         assert_pack_equal(tabi, orc, synth.make_input("mixed2k", 0), f"mixed2k cap {cap}")
@@ -200,3 +201,34 @@ def test_pack_parity_without_row_staging(tabi, orc, cap):
             assert_pack_equal(tabi, orc, small_input(400 + seed), f"small {seed} cap {cap}")
     finally:
         tabi.debug_set_stage_cap(-1)
+
+
+@pytest.mark.parametrize("words", [0, 60000])
+def test_pack_parity_without_stored_profiles(tabi, orc, words):
+    """Charts whose profiles do not fit the arena are evaluated from their
+    proxy records in the pair and pack kernels; same results (0: no arena,
+    60000 words: some scales stored, the others not)."""
+    tabi.debug_set_profile_cap(words)
+    try:
+        assert_pack_equal(tabi, orc, synth.make_input("mixed2k", 0), f"mixed2k arena {words}")
+        assert_pack_equal(tabi, orc, synth.make_input("stars64", 2), f"stars64 arena {words}")
+        for seed in range(6):
+            assert_pack_equal(tabi, orc, small_input(500 + seed), f"small {seed} arena {words}")
+        inp = small_input(600, n=20)
+        for k in (64, 33, 7):
+            cd, fl = tabi.debug_pairs(inp.xy, inp.offsets, inp.padding, inp.quality, k)
+            ocd, ofl = orc.pairs(inp, k)
+            assert np.array_equal(_np(cd), ocd) and np.array_equal(_np(fl), ofl), k
+    finally:
+        tabi.debug_set_profile_cap(-1)
+
+
+@pytest.mark.parametrize("p", [0, 5, 32])
+def test_pack_parity_padding_range(tabi, orc, p):
+    """Gutters from none up to the largest accepted padding (the profile
+    kernels take the gutter growth within one wavefront)."""
+    inp = synth.make_custom(90, 512, 384, p, 2, 1.0, 0.7, synth.CONFIGS["mixed2k"]["mix"], 7000 + p)
+    assert_pack_equal(tabi, orc, inp, f"padding {p}")
+    cd, fl = tabi.debug_pairs(inp.xy, inp.offsets, p, inp.quality, 40)
+    ocd, ofl = orc.pairs(inp, 40)
+    assert np.array_equal(_np(cd), ocd) and np.array_equal(_np(fl), ofl)
