@@ -132,6 +132,24 @@ def served_leg(seconds=1.0, rate=2000.0):
             "speedup_vs_plain": round(pwall / wall, 2), "bitexact_vs_alone": bool(same)}
 
 
+def pack_algorithmic_bytes(inp, k_top):
+    """Algorithmic bytes of one fold-and-push launch over the scales 1..k_top:
+    per (chart, scale) the chart's grown column profile, 4 (w_k + p) bytes,
+    where w_k = ceil(k W / 16384) is its texel width at scale k/64 and W the
+    smaller side of its Q8 bounding box (charts are turned so that H >= W),
+    plus 22 bytes of per-chart fields and placement."""
+    import numpy as np
+    xs, ys = inp.xy[0::2].astype(np.int64), inp.xy[1::2].astype(np.int64)
+    starts = inp.offsets[:-1]
+    ex = np.maximum.reduceat(xs, starts) - np.minimum.reduceat(xs, starts)
+    ey = np.maximum.reduceat(ys, starts) - np.minimum.reduceat(ys, starts)
+    wq = np.minimum(ex, ey)
+    ks = np.arange(1, k_top + 1, dtype=np.int64)[:, None]
+    wk = -(-(ks * wq[None, :]) // 16384)
+    units = int(wk.size)
+    return int((4 * (wk + inp.padding) + 22).sum()), units
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,18 +232,18 @@ def main():
     gsc = float(out_sc.cpu().numpy()[0])
     kstar = int(round(gsc * 64))
 
-    # roofline of the dominant kernel (fold-and-push): algorithmic bytes per
-    # (chart, scale) unit = per-scale chart record + neighbour pair data +
-    # chart fields read for OBB evaluation + placement written
-    K = {0: 2, 1: 5, 2: 10}[inp.quality]
-    rec = 16 + 4 * 16 + 2 * K * 8
-    unit_bytes = rec + 4 + 1 + 40 + 9
+    # roofline of the dominant kernel (fold-and-push over every candidate
+    # scale 1..k_top): algorithmic bytes per (chart, scale) unit = the chart's
+    # stored grown column profile (one 4-byte word per grown texel column,
+    # w_k + p of them) + grown width, compacting distance, interlock flags and
+    # height read by the fold (13 B) + placement written (9 B)
+    pack_bytes, units = pack_algorithmic_bytes(inp, k_top)
+    unit_bytes = pack_bytes / max(units, 1)
     dom = max(stages, key=lambda s: stages[s][0])
     dom_ms, dom_launches = stages[dom]
     pack_ms, pack_launches = stages["pack"]
     avg_pack_ms = pack_ms / max(pack_launches, 1)
-    units = n * k_top
-    achieved = unit_bytes * units / (avg_pack_ms * 1e-3) / 1e9 if avg_pack_ms > 0 else 0.0
+    achieved = pack_bytes / (avg_pack_ms * 1e-3) / 1e9 if avg_pack_ms > 0 else 0.0
 
     result = {
         "metric": METRIC,
@@ -254,7 +272,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_pack (fold-and-push, all candidate scales)",
                      "achieved": round(achieved, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 6), "traffic": None,
-                     "bytes_per_unit": unit_bytes, "units_per_launch": units,
+                     "bytes_per_unit": round(unit_bytes, 2), "units_per_launch": units,
+                     "bytes_per_launch": pack_bytes,
                      "avg_launch_ms": round(avg_pack_ms, 4), "dominant_stage": dom},
     }
     if not args.no_cpu:

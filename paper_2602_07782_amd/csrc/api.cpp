@@ -105,18 +105,21 @@ struct StageScope {  // brackets one stage's launches with a pair of events
 // ---- work space -------------------------------------------------------------
 struct Layout {
   size_t o_recs, o_srecs, o_keys, o_rank, o_perm, o_ca, o_desc, o_kc, o_cd, o_fl, o_xs, o_ys, o_mir,
-      o_feas, o_rows, o_wdv, o_hdv, o_pcol, o_prow, o_Hs, o_atop, o_arena, total;
+      o_feas, o_rows, o_wdv, o_hdv, o_pcol, o_prow, o_Hs, o_segneed, o_segbase, o_arena, total;
 };
 
 // Profile arena words for B scale slots over N charts in `count` atlases of
 // grown width up to Wdmax.  A chart of grown extents w x h takes w + h words
 // at a scale; per slot and chart `per` words are set aside (the single pack
-// spreads its 64 slots over scales 1..k_top, so it needs fewer on average),
-// plus four atlas widths per (atlas, slot).  Segments that do not fit are
-// evaluated directly, so the figure only trades memory for speed.
+// spreads its 64 slots over scales 1..k_top, so it needs fewer on average:
+// about 5,400 words per chart over all 64 scales for the 2,000-chart 2048^2
+// workload, 3,200 for 20,000 charts in 4096^2; a batch of mixed atlases about
+// 700 over its top 8 scales), plus four atlas widths per (atlas, slot).
+// Segments are placed in descending-scale order and those that do not fit
+// are evaluated directly, so the figure only trades memory for speed.
 int64_t arena_words(const Params& P) {
   if (g_profile_cap >= 0) return g_profile_cap;
-  const int64_t per = P.B >= 64 ? 48 : 96;
+  const int64_t per = P.B >= 64 ? 90 : 112;
   int64_t v = (int64_t)P.B * P.N * per + (int64_t)P.B * P.count * 4 * P.Wdmax;
   const int64_t lim = 0x7fffffffLL;  // word indices are int32
   return v > lim ? lim : v;
@@ -151,7 +154,8 @@ Layout layout(const Params& P) {
   L.o_pcol = take((size_t)P.B * n1 * 4);
   L.o_prow = take((size_t)P.B * n1 * 4);
   L.o_Hs = take(n1 * 4);
-  L.o_atop = take(8);
+  L.o_segneed = take((size_t)P.count * P.B * 8);
+  L.o_segbase = take((size_t)P.count * P.B * 4);
   L.o_arena = take((size_t)P.arena_cap * 4);
   L.total = off;
   return L;
@@ -180,7 +184,8 @@ Work carve(void* base, const Layout& L) {
   W.pcol = reinterpret_cast<int32_t*>(b + L.o_pcol);
   W.prow = reinterpret_cast<int32_t*>(b + L.o_prow);
   W.Hs = reinterpret_cast<int32_t*>(b + L.o_Hs);
-  W.atop = reinterpret_cast<unsigned long long*>(b + L.o_atop);
+  W.segneed = reinterpret_cast<int64_t*>(b + L.o_segneed);
+  W.segbase = reinterpret_cast<int32_t*>(b + L.o_segbase);
   W.arena = reinterpret_cast<uint32_t*>(b + L.o_arena);
   return W;
 }

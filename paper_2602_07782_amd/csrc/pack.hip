@@ -187,8 +187,8 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   const uint8_t* flv = w.fl + slot;
   const int32_t* wdv = w.wdv + slot;
   const int32_t* hdv = w.hdv + slot;
-  const int32_t* pcolv = w.pcol + slot;
   const int32_t* prowv = w.prow + slot;
+  const int32_t sbase = w.segbase[(size_t)a * P.B + s];  // -1: profiles not stored
   const int32_t* Hs = w.Hs + d.c0;
   int32_t* xs = w.xs + slot;
   int32_t* ys = w.ys + slot;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   // arena word of the row's first grown column (-1: no stored profiles); the
   // charts of a segment are stored back to back, so it advances by the
   // committed grown width
-  int32_t pc0 = n > 0 ? pcolv[0] : -1;
+  int32_t pc0 = n > 0 ? sbase : -1;
 
   for (;;) {
     __syncthreads();
@@ -389,8 +389,8 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       const int wdA = Xoff[A + 1] - Xoff[A];
       PairSweep sw;
       if (prof) {
-        sw = pair_sweep_rows(w.arena + prowv[rs + A], hdv[rs + A], w.arena + prowv[rs + C],
-                             hdv[rs + C], wdA);
+        sw = pair_sweep_rows(w.arena + sbase + prowv[rs + A], hdv[rs + A],
+                             w.arena + sbase + prowv[rs + C], hdv[rs + C], wdA);
       } else {
         sw = pair_sweep(KV(rs + A), ch[rs + A], KV(rs + C), ch[rs + C], K, k, p);
       }

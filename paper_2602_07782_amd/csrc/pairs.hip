@@ -11,7 +11,6 @@
 namespace tabi {
 
 constexpr int PAIR_WAVES = 4;
-constexpr int KREC_MAX = 16 + 4 * 16 + 2 * KMAX * 8;  // kchart_stride(KMAX)
 
 struct alignas(16) PairCache {
   Chart ch[2];
@@ -19,12 +18,13 @@ struct alignas(16) PairCache {
 };
 
 __global__ __launch_bounds__(256) void k_pairs(Params P, Work w, int round) {
-  __shared__ PairCache cache[PAIR_WAVES];
+  __shared__ PairCache cache[PAIR_WAVES];  // used when the rows are not stored
   const int wv = threadIdx.x / WAVE, lane = lane_id();
   const int c = blockIdx.x * PAIR_WAVES + wv;
   const int s = blockIdx.y;
   if (c >= P.N) return;  // whole wavefront leaves; no block barrier below
-  const AtlasDesc d = w.desc[w.chart_atlas[c]];
+  const int a = w.chart_atlas[c];
+  const AtlasDesc d = w.desc[a];
   const size_t slot = (size_t)s * P.N;
   const bool run = P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1);
   if (!run) return;
@@ -34,8 +34,9 @@ __global__ __launch_bounds__(256) void k_pairs(Params P, Work w, int round) {
     if (lane == 0) { w.cd[slot + c] = 0; w.fl[slot + c] = 0; }
     return;
   }
-  const int32_t prA = w.prow[slot + c - 1], prB = w.prow[slot + c];
-  if (prA >= 0 && prB >= 0) {  // stored grown rows
+  const int32_t base = w.segbase[(size_t)a * P.B + s];
+  if (base >= 0) {  // stored grown rows
+    const int32_t prA = base + w.prow[slot + c - 1], prB = base + w.prow[slot + c];
     const int wdA = w.wdv[slot + c - 1];
     const PairSweep r = pair_sweep_rows(w.arena + prA, w.hdv[slot + c - 1], w.arena + prB,
                                         w.hdv[slot + c], wdA);

@@ -329,7 +329,6 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
 __global__ __launch_bounds__(256) void k_setup(Params P, Work w, int round) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
-  if (c == 0 && s == 0) *w.atop = 0;  // the profile arena is laid out afresh each round
   if (c >= P.N) return;
   const AtlasDesc d = w.desc[w.chart_atlas[c]];
   const bool run = P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1);

@@ -9,32 +9,43 @@
 // sequential row loop:
 //
 //   k_layout   one workgroup per (atlas, scale slot): prefix sums of the
-//              grown widths and heights, one allocation in the arena
+//              grown widths and heights (offsets within the segment)
+//   k_alloc    one workgroup: segment bases in descending-scale priority
 //   k_profile  one wavefront per (scale slot, chart): every grown column
 //              (top, bottom) and every grown row (left, right)
 //
 // Within a (atlas, slot) segment the charts' columns are stored back to back
 // in sorted order, so the candidates of a row are one contiguous range and a
-// row's texel e is word pcol[first chart] + e.  A segment that does not fit
-// the arena gets no profiles (pcol = prow = -1) and its consumers evaluate
+// row's texel e is word segbase + pcol[first chart] + e.  A segment that does
+// not fit the arena is not stored (segbase = -1) and its consumers evaluate
 // the proxies directly; results are the same either way.
 #include "tabi_internal.h"
 
 namespace tabi {
 
 constexpr int LAY_NT = 256;
+constexpr int ALLOC_NT = 1024;
 constexpr int PROF_WAVES = 4;
 
+__device__ inline void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Offsets of every chart's grown columns and rows within its (atlas, slot)
+// segment, and the segment's size in words (0 when the slot does not run).
 __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) {
   __shared__ int64_t s_tot[LAY_NT / WAVE][2];
-  __shared__ int64_t s_base;
   const int a = blockIdx.x, s = blockIdx.y;
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
   const AtlasDesc d = w.desc[a];
   const bool run = P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1);
-  if (!run || d.n <= 0) return;
   const int k = slot_k(P, d, round, s);
-  if (k < 1) return;
+  if (!run || d.n <= 0 || k < 1) {
+    if (tid == 0) w.segneed[(size_t)a * P.B + s] = 0;
+    return;
+  }
   const size_t slot = (size_t)s * P.N + d.c0;
   const int n = d.n, per = (n + LAY_NT - 1) / LAY_NT;
   const int t0 = min(n, tid * per), t1 = min(n, t0 + per);
@@ -59,50 +70,93 @@ __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) 
     tw += s_tot[q][0];
     th += s_tot[q][1];
   }
-  if (tid == 0) {
-    // claim [base, base + need) only if it fits: the counter never passes
-    // the capacity, so a large segment that fails leaves room for others
-    const unsigned long long need = (unsigned long long)(tw + th);
-    const unsigned long long cap = (unsigned long long)P.arena_cap;
-    long long base = -1;
-    unsigned long long cur = atomicAdd(w.atop, 0ull);
-    while (need <= cap && cur <= cap - need) {
-      const unsigned long long old = atomicCAS(w.atop, cur, cur + need);
-      if (old == cur) { base = (long long)cur; break; }
-      cur = old;
-    }
-    s_base = base;
-  }
-  __syncthreads();
-  const int64_t base = s_base;
-  int64_t col = base + pw + iw - sw, row = base + tw + ph + ih - sh;
+  if (tid == 0) w.segneed[(size_t)a * P.B + s] = tw + th;
+  // a segment larger than the arena is never stored, so offsets beyond the
+  // int32 range are never used
+  int64_t col = pw + iw - sw, row = tw + ph + ih - sh;
   for (int t = t0; t < t1; ++t) {
-    w.pcol[slot + t] = base < 0 ? -1 : (int32_t)col;
-    w.prow[slot + t] = base < 0 ? -1 : (int32_t)row;
+    w.pcol[slot + t] = (int32_t)min<int64_t>(col, 0x7fffffff);
+    w.prow[slot + t] = (int32_t)min<int64_t>(row, 0x7fffffff);
     col += w.wdv[slot + t];
     row += w.hdv[slot + t];
   }
 }
 
-// Grown bounds of one chart, one wavefront.  Lane l of a chunk evaluates
-// undilated column (row) u = j0 - p + l; the gutter growth over [u-p, u]
-// comes from p shuffles, so a chunk advances 64 - p entries (p <= 32).
+// Segment placement in priority order: slot-major (every atlas's largest
+// candidate scale first), so that when the arena runs out the segments left
+// unstored are those of the smallest scales.  A segment is stored when it ends
+// within the arena counting every segment before it.
+__global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w) {
+  __shared__ int64_t s_tot[ALLOC_NT / WAVE];
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+  const int64_t total = (int64_t)P.count * P.B;
+  int64_t run = 0;
+  for (int64_t q0 = 0; q0 < total; q0 += ALLOC_NT) {
+    const int64_t q = q0 + tid;
+    int64_t a = 0, s = 0, need = 0;
+    if (q < total) {
+      s = q / P.count;
+      a = q - s * P.count;
+      need = w.segneed[a * P.B + s];
+    }
+    int64_t inc = need;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int64_t u = __shfl_up((long long)inc, o);
+      if (lane >= o) inc += u;
+    }
+    if (lane == WAVE - 1) s_tot[wv] = inc;
+    __syncthreads();
+    int64_t pre = 0, chunk = 0;
+    for (int i = 0; i < ALLOC_NT / WAVE; ++i) {
+      if (i < wv) pre += s_tot[i];
+      chunk += s_tot[i];
+    }
+    if (q < total) {
+      const int64_t end = run + pre + inc;
+      w.segbase[a * P.B + s] = (need > 0 && end <= P.arena_cap) ? (int32_t)(end - need) : -1;
+    }
+    run += chunk;
+    __syncthreads();
+  }
+}
+
+// Grown bounds of one chart, one wavefront, from an LDS copy of the chart and
+// its set-up record.  Lane l of a chunk evaluates undilated column (row)
+// u = j0 - p + l; the gutter growth over [u-p, u] comes from p shuffles, so a
+// chunk advances 64 - p entries (p <= 32).
 __global__ __launch_bounds__(PROF_WAVES * WAVE) void k_profile(Params P, Work w, int round) {
+  __shared__ ChartCache cache[PROF_WAVES];
   const int wv = threadIdx.x / WAVE, lane = lane_id();
   const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * PROF_WAVES + wv);
   const int s = blockIdx.y;
-  if (c >= P.N) return;
-  const AtlasDesc d = w.desc[w.chart_atlas[c]];
+  if (c >= P.N) return;  // whole wavefront leaves; no block barrier below
+  const int a = w.chart_atlas[c];
+  const AtlasDesc d = w.desc[a];
   const bool run = P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1);
   if (!run) return;
   const int k = slot_k(P, d, round, s);
   if (k < 1) return;
+  const int32_t base = w.segbase[(size_t)a * P.B + s];
+  if (base < 0) return;
   const size_t sc = (size_t)s * P.N + c;
-  const int32_t pc = w.pcol[sc], pr = w.prow[sc];
-  if (pc < 0) return;
-  const KView kv = kview(w.kc + sc * P.stride, P.K);
-  const Chart& ch = w.srecs[c];
-  const int K = P.K, p = P.p, wt = kv.hd->w, ht = kv.hd->h;
+  const int32_t pc = base + w.pcol[sc], pr = base + w.prow[sc];
+  {
+    const int nch = (int)(sizeof(Chart) / 16), nkc = P.stride / 16;
+    const int4* src = reinterpret_cast<const int4*>(&w.srecs[c]);
+    const int4* kc = reinterpret_cast<const int4*>(w.kc + sc * P.stride);
+    int4* dch = reinterpret_cast<int4*>(&cache[wv].ch);
+    int4* dkc = reinterpret_cast<int4*>(cache[wv].kc);
+    for (int i = lane; i < nch + nkc; i += WAVE) {
+      if (i < nch) dch[i] = src[i];
+      else dkc[i - nch] = kc[i - nch];
+    }
+    wsync();
+  }
+  const KView kv = kview(cache[wv].kc, P.K);
+  const Chart& ch = cache[wv].ch;
+  const KHead hd = khead_load(kv.hd);
+  const int K = P.K, p = P.p, wt = hd.w, ht = hd.h;
   const int step = WAVE - p;
   uint32_t* out = w.arena + pc;
   for (int j0 = 0; j0 < wt + p; j0 += step) {
@@ -132,8 +186,9 @@ __global__ __launch_bounds__(PROF_WAVES * WAVE) void k_profile(Params P, Work w,
 
 hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_t st) {
   if (P.N <= 0) return hipSuccess;
-  // with no arena the layout still runs: it marks every segment unprofiled
+  // with no arena the placement still runs: it marks every segment unstored
   hipLaunchKernelGGL(k_layout, dim3(P.count, P.B), dim3(LAY_NT), 0, st, P, w, round);
+  hipLaunchKernelGGL(k_alloc, dim3(1), dim3(ALLOC_NT), 0, st, P, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || P.arena_cap <= 0) return e;
   hipLaunchKernelGGL(k_profile, dim3((P.N + PROF_WAVES - 1) / PROF_WAVES, P.B),

@@ -58,6 +58,14 @@ __host__ __device__ inline int kchart_stride(int K) {
   return (int)(sizeof(KHead) + 4 * sizeof(KSide) + 2 * K * sizeof(KRect));
 }
 
+constexpr int KREC_MAX = 16 + 4 * 16 + 2 * KMAX * 8;  // kchart_stride(KMAX)
+
+// A chart and its per-scale record, staged in LDS by one wavefront.
+struct alignas(16) ChartCache {
+  Chart ch;
+  unsigned char kc[KREC_MAX];
+};
+
 struct KView {
   const KHead* hd;
   const KSide* sd;   // [0] top, [1] bottom, [2] left, [3] right
@@ -100,6 +108,30 @@ __device__ inline int32_t clamp32(int64_t v) {
 // ---------------------------------------------------------------------------
 // per-texel proxy evaluation
 // ---------------------------------------------------------------------------
+// Whole-record loads: every field of a rectangle / side / head in one memory
+// operation, so that the K rectangles of a proxy are fetched together rather
+// than field by field behind the comparisons.
+__device__ inline void krect_load(const KRect* p, int32_t& c0, int32_t& c1, int32_t& r0,
+                                  int32_t& r1) {
+  const uint2 v = *reinterpret_cast<const uint2*>(p);
+  c0 = (int32_t)(int16_t)(uint16_t)(v.x & 0xffffu);
+  c1 = (int32_t)v.x >> 16;
+  r0 = (int32_t)(int16_t)(uint16_t)(v.y & 0xffffu);
+  r1 = (int32_t)v.y >> 16;
+}
+__device__ inline KSide kside_load(const KSide* p) {
+  const int4 v = *reinterpret_cast<const int4*>(p);
+  KSide s;
+  s.sa = v.x; s.sb = v.y; s.corner = v.z; s.last = v.w;
+  return s;
+}
+__device__ inline KHead khead_load(const KHead* p) {
+  const int4 v = *reinterpret_cast<const int4*>(p);
+  KHead h;
+  h.w = v.x; h.h = v.y; h.obb = v.z; h.pad = v.w;
+  return h;
+}
+
 // OBB side value at texel t (column for top/bottom, row for left/right) of an
 // extent with n texels.  Line A applies left of (above) the corner, line B
 // right of (below) it; each line is (n0 + n1 * x) / d rounded down (lo sides)
@@ -124,23 +156,30 @@ __device__ inline int32_t side_value(const KSide& s, int32_t t, int32_t n, int64
 __device__ inline void column_bounds(const KView& kv, const Chart& ch, int K, int k, int i,
                                      int32_t& top, int32_t& bot) {
   int32_t tx = BIG, bx = -BIG, ty = BIG, by = -BIG;
-  for (int j = 0; j < K; ++j) {
-    KRect r = kv.rc[j];
-    if (r.c0 <= i && i < r.c1) { tx = min(tx, (int32_t)r.r0); bx = max(bx, (int32_t)r.r1); }
-  }
-  for (int j = 0; j < K; ++j) {
-    KRect r = kv.rc[K + j];
-    if (r.c0 <= i && i < r.c1) { ty = min(ty, (int32_t)r.r0); by = max(by, (int32_t)r.r1); }
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) {
+    if (j < K) {
+      int32_t c0, c1, r0, r1;
+      krect_load(kv.rc + j, c0, c1, r0, r1);
+      const bool in = c0 <= i && i < c1;
+      tx = in ? min(tx, r0) : tx;
+      bx = in ? max(bx, r1) : bx;
+      krect_load(kv.rc + K + j, c0, c1, r0, r1);
+      const bool iny = c0 <= i && i < c1;
+      ty = iny ? min(ty, r0) : ty;
+      by = iny ? max(by, r1) : by;
+    }
   }
   int32_t t = max(tx, ty), b = min(bx, by);
-  const KHead hd = *kv.hd;
+  const KHead hd = khead_load(kv.hd);
   if (hd.obb) {
     const int64_t C = kDirC[ch.m], S = kDirS[ch.m];
     const int64_t kk = k;
+    const KSide s0 = kside_load(kv.sd + 0), s1 = kside_load(kv.sd + 1);
     // top = max(A: (k a - 16384 C x)/(16384 S), B: (k e + 16384 S x)/(16384 C))
-    int32_t to = side_value<false>(kv.sd[0], i, hd.w, kk * ch.a, -QS * C, QS * S, kk * ch.e, QS * S, QS * C);
+    int32_t to = side_value<false>(s0, i, hd.w, kk * ch.a, -QS * C, QS * S, kk * ch.e, QS * S, QS * C);
     // bottom = min(A: (k f + 16384 S x)/(16384 C), B: (k b - 16384 C x)/(16384 S))
-    int32_t bo = side_value<true>(kv.sd[1], i, hd.w, kk * ch.f, QS * S, QS * C, kk * ch.b, -QS * C, QS * S);
+    int32_t bo = side_value<true>(s1, i, hd.w, kk * ch.f, QS * S, QS * C, kk * ch.b, -QS * C, QS * S);
     t = max(t, to);
     b = min(b, bo);
   }
@@ -152,23 +191,30 @@ __device__ inline void column_bounds(const KView& kv, const Chart& ch, int K, in
 __device__ inline void row_bounds(const KView& kv, const Chart& ch, int K, int k, int j,
                                   int32_t& left, int32_t& right) {
   int32_t ly = BIG, ry = -BIG, lx = BIG, rx = -BIG;
-  for (int s = 0; s < K; ++s) {
-    KRect r = kv.rc[K + s];
-    if (r.r0 <= j && j < r.r1) { ly = min(ly, (int32_t)r.c0); ry = max(ry, (int32_t)r.c1); }
-  }
-  for (int s = 0; s < K; ++s) {
-    KRect r = kv.rc[s];
-    if (r.r0 <= j && j < r.r1) { lx = min(lx, (int32_t)r.c0); rx = max(rx, (int32_t)r.c1); }
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    if (q < K) {
+      int32_t c0, c1, r0, r1;
+      krect_load(kv.rc + K + q, c0, c1, r0, r1);
+      const bool iny = r0 <= j && j < r1;
+      ly = iny ? min(ly, c0) : ly;
+      ry = iny ? max(ry, c1) : ry;
+      krect_load(kv.rc + q, c0, c1, r0, r1);
+      const bool inx = r0 <= j && j < r1;
+      lx = inx ? min(lx, c0) : lx;
+      rx = inx ? max(rx, c1) : rx;
+    }
   }
   int32_t l = max(ly, lx), rr = min(ry, rx);
-  const KHead hd = *kv.hd;
+  const KHead hd = khead_load(kv.hd);
   if (hd.obb) {
     const int64_t C = kDirC[ch.m], S = kDirS[ch.m];
     const int64_t kk = k;
+    const KSide s2 = kside_load(kv.sd + 2), s3 = kside_load(kv.sd + 3);
     // left = max(A: (k a - 16384 S y)/(16384 C), B: (16384 C y - k f)/(16384 S))
-    int32_t lo = side_value<false>(kv.sd[2], j, hd.h, kk * ch.a, -QS * S, QS * C, -kk * ch.f, QS * C, QS * S);
+    int32_t lo = side_value<false>(s2, j, hd.h, kk * ch.a, -QS * S, QS * C, -kk * ch.f, QS * C, QS * S);
     // right = min(A: (16384 C y - k e)/(16384 S), B: (k b - 16384 S y)/(16384 C))
-    int32_t ro = side_value<true>(kv.sd[3], j, hd.h, -kk * ch.e, QS * C, QS * S, kk * ch.b, -QS * S, QS * C);
+    int32_t ro = side_value<true>(s3, j, hd.h, -kk * ch.e, QS * C, QS * S, kk * ch.b, -QS * S, QS * C);
     l = max(l, lo);
     rr = min(rr, ro);
   }

@@ -52,10 +52,11 @@ struct Work {
   int32_t* rows;        // [count][B]
   int32_t* wdv;         // [B][N] grown width w + p at the slot's scale
   int32_t* hdv;         // [B][N] grown height h + p
-  int32_t* pcol;        // [B][N] arena word of the chart's first grown column, -1 none
-  int32_t* prow;        // [B][N] arena word of the chart's first grown row, -1 none
+  int32_t* pcol;        // [B][N] first grown column of the chart within its segment
+  int32_t* prow;        // [B][N] first grown row of the chart within its segment
   int32_t* Hs;          // [N] unscaled height (Q8) by sorted position
-  unsigned long long* atop;  // arena words handed out in this round
+  int64_t* segneed;     // [count][B] arena words of the (atlas, slot) segment
+  int32_t* segbase;     // [count][B] arena word where the segment starts, -1: not stored
   uint32_t* arena;      // profiles: per grown column (top, bottom), per grown row
                         // (left, right), int16 pairs (pack16)
 };
