@@ -198,8 +198,8 @@ const char* tabi_last_hip_error(void);
 /* Stage timing (host side).  When enabled, the calling process brackets each
  * stage of later tabi_pack / tabi_pack_many calls with a pair of HIP events on
  * the call's stream.  Stages, in order: 0 chart proxies (prep), 1 sort and
- * scale bound, 2 per-scale set-up, 3 per-texel profiles, 4 neighbour pairs,
- * 5 fold-and-push, 6 scale selection.  tabi_timing_read waits for the recorded events and writes the
+ * scale bound, 2 per-scale set-up, 3 per-texel profiles and neighbour pairs,
+ * 4 fold-and-push, 5 scale selection.  tabi_timing_read waits for the recorded events and writes the
  * summed milliseconds and the number of bracketed launches per stage since
  * the last reset (arrays of nstages entries, either may be NULL). */
 int tabi_timing_enable(int on);

@@ -37,7 +37,7 @@ EXPORTS = ["tabi_pack", "tabi_pack_many", "tabi_pack_many_ws", "tabi_pack_many_w
            "tabi_debug_feasible", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
            "tabi_timing_enable", "tabi_timing_read", "tabi_timing_reset",
            "tabi_debug_set_stage_cap", "tabi_debug_set_profile_cap"]
-STAGES = ["prep", "sort", "setup", "profile", "pairs", "pack", "select"]
+STAGES = ["prep", "sort", "setup", "profile", "pack", "select"]
 
 
 def lib():

@@ -60,7 +60,7 @@ int lds_budget() {
 }
 
 // ---- opt-in per-stage timing with HIP events on the call's stream ----------
-enum Stage { ST_PREP = 0, ST_SORT, ST_SETUP, ST_PROFILE, ST_PAIRS, ST_PACK, ST_SELECT, ST_COUNT };
+enum Stage { ST_PREP = 0, ST_SORT, ST_SETUP, ST_PROFILE, ST_PACK, ST_SELECT, ST_COUNT };
 struct Timing {
   std::mutex mu;
   bool on = false;
@@ -293,10 +293,6 @@ hipError_t run_search(Job& j, int rounds, int32_t* out_xy, uint8_t* out_orient, 
       e = launch_profiles(j.P, j.W, r, st);
     }
     if (e == hipSuccess) {
-      StageScope t(ST_PAIRS, st);
-      e = launch_pairs(j.P, j.W, r, st);
-    }
-    if (e == hipSuccess) {
       StageScope t(ST_PACK, st);
       e = launch_pack(j.P, j.W, r, j.L.bytes, j.L.RC, j.L.PW, j.stage_cap, st);
     }
@@ -514,7 +510,6 @@ int tabi_debug_pairs(const tabi_charts* charts, int32_t n, int32_t padding, int3
   hipError_t e = hipSuccess;
   if (!rc) e = launch_setup(j.P, j.W, 0, st);
   if (!rc && e == hipSuccess) e = launch_profiles(j.P, j.W, 0, st);
-  if (!rc && e == hipSuccess) e = launch_pairs(j.P, j.W, 0, st);
   if (!rc && e == hipSuccess && n > 0)
     e = hipMemcpyAsync(cd, j.W.cd, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st);
   if (!rc && e == hipSuccess && n > 0)
@@ -540,7 +535,6 @@ int tabi_debug_feasible(const tabi_charts* charts, int32_t n, int32_t atlas_w, i
   hipError_t e = hipSuccess;
   if (!rc) e = launch_setup(j.P, j.W, 0, st);
   if (!rc && e == hipSuccess) e = launch_profiles(j.P, j.W, 0, st);
-  if (!rc && e == hipSuccess) e = launch_pairs(j.P, j.W, 0, st);
   if (!rc && e == hipSuccess)
     e = launch_pack(j.P, j.W, 0, j.L.bytes, j.L.RC, j.L.PW, j.stage_cap, st);
   if (!rc && e == hipSuccess) e = launch_scatter(j.P, j.W, out_xy, out_orient, feasible, rows, st);

@@ -340,9 +340,15 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     };
     // ---- 3. staging, offset init, non-neighbour pairs that share columns
     if (staged) {
-      for (int e = tid; e < E; e += PACK_NT) {
-        st[e] = gprof[e];
-        emap[e] = (int16_t)find_chart(Xoff, cand, e);
+      for (int e = tid; e < E; e += PACK_NT) st[e] = gprof[e];
+      // texel -> chart map, filled chart by chart: a thread per chart when
+      // charts are narrow, a wavefront per chart when they are wide
+      if (E < 16 * cand) {
+        for (int t = tid; t < cand; t += PACK_NT)
+          for (int e = Xoff[t]; e < Xoff[t + 1]; ++e) emap[e] = (int16_t)t;
+      } else {
+        for (int t = wv; t < cand; t += PACK_WAVES)
+          for (int e = Xoff[t] + lane; e < Xoff[t + 1]; e += WAVE) emap[e] = (int16_t)t;
       }
     }
 #pragma unroll

@@ -11,8 +11,10 @@
 //   k_layout   one workgroup per (atlas, scale slot): prefix sums of the
 //              grown widths and heights (offsets within the segment)
 //   k_alloc    one workgroup: segment bases in descending-scale priority
-//   k_profile  one wavefront per (scale slot, chart): every grown column
-//              (top, bottom) and every grown row (left, right)
+//   k_profile  per (scale slot, 32 charts): every grown column (top,
+//              bottom) and every grown row (left, right), one wavefront per
+//              chart at a time, then the neighbour pairs' compacting
+//              distances and interlock flags
 //
 // Within a (atlas, slot) segment the charts' columns are stored back to back
 // in sorted order, so the candidates of a row are one contiguous range and a
@@ -20,18 +22,14 @@
 // not fit the arena is not stored (segbase = -1) and its consumers evaluate
 // the proxies directly; results are the same either way.
 #include "tabi_internal.h"
+#include "pairs_dev.h"
 
 namespace tabi {
 
 constexpr int LAY_NT = 256;
 constexpr int ALLOC_NT = 1024;
-constexpr int PROF_WAVES = 4;
-
-__device__ inline void wsync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+constexpr int PROF_NT = 256;
+constexpr int PROF_CH = 32;  // charts per profile workgroup
 
 // Offsets of every chart's grown columns and rows within its (atlas, slot)
 // segment, and the segment's size in words (0 when the slot does not run).
@@ -121,66 +119,121 @@ __global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w) {
   }
 }
 
-// Grown bounds of one chart, one wavefront, from an LDS copy of the chart and
-// its set-up record.  Lane l of a chunk evaluates undilated column (row)
-// u = j0 - p + l; the gutter growth over [u-p, u] comes from p shuffles, so a
-// chunk advances 64 - p entries (p <= 32).
-__global__ __launch_bounds__(PROF_WAVES * WAVE) void k_profile(Params P, Work w, int round) {
-  __shared__ ChartCache cache[PROF_WAVES];
-  const int wv = threadIdx.x / WAVE, lane = lane_id();
-  const int c = __builtin_amdgcn_readfirstlane(blockIdx.x * PROF_WAVES + wv);
-  const int s = blockIdx.y;
-  if (c >= P.N) return;  // whole wavefront leaves; no block barrier below
-  const int a = w.chart_atlas[c];
-  const AtlasDesc d = w.desc[a];
-  const bool run = P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1);
-  if (!run) return;
-  const int k = slot_k(P, d, round, s);
-  if (k < 1) return;
-  const int32_t base = w.segbase[(size_t)a * P.B + s];
-  if (base < 0) return;
-  const size_t sc = (size_t)s * P.N + c;
-  const int32_t pc = base + w.pcol[sc], pr = base + w.prow[sc];
+// Grown bounds of PROF_CH charts of one scale slot per workgroup, then the
+// compacting distance and interlock flags of their pairs with the preceding
+// chart (Sec. 4.1.2; App. A "Detecting Interlocking Charts").  The charts'
+// records, and the record of the chart before the first, are copied to LDS
+// in one burst and their segment offsets loaded in parallel; each wavefront
+// evaluates charts from LDS.  Lane l of a chunk evaluates undilated column
+// (row) u = j0 - p + l; the gutter growth over [u-p, u] comes from p
+// shuffles, so a chunk advances 64 - p entries (p <= 32).  After a barrier
+// the pairs read the rows just stored; pairs in segments without stored
+// profiles evaluate the rows from the LDS records.
+__global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round) {
+  constexpr int NJ = PROF_CH + 1;  // entry 0: the chart before the block's first
+  __shared__ ChartCache cache[NJ];
+  __shared__ int32_t s_pc[NJ], s_pr[NJ], s_k[NJ], s_a[NJ], s_run[NJ];
+  const int tid = threadIdx.x, wv = tid / WAVE, lane = lane_id();
+  const int s = blockIdx.y, cb = blockIdx.x * PROF_CH;
+  if (tid < NJ) {
+    const int c = cb - 1 + tid;
+    int32_t pc = -1, pr = -1, kk = 0, a = -1, run = 0;
+    if (c >= 0 && c < P.N) {
+      a = w.chart_atlas[c];
+      const AtlasDesc d = w.desc[a];
+      const int k = slot_k(P, d, round, s);
+      run = (P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1)) && k >= 1;
+      const int32_t base = w.segbase[(size_t)a * P.B + s];
+      if (run) kk = k;
+      if (run && base >= 0) {
+        const size_t sc = (size_t)s * P.N + c;
+        pc = base + w.pcol[sc];
+        pr = base + w.prow[sc];
+      }
+      if (c == d.c0) run |= 2;  // first chart of its atlas: no pair before it
+    }
+    s_pc[tid] = pc;
+    s_pr[tid] = pr;
+    s_k[tid] = kk;
+    s_a[tid] = a;
+    s_run[tid] = run;
+  }
   {
-    const int nch = (int)(sizeof(Chart) / 16), nkc = P.stride / 16;
-    const int4* src = reinterpret_cast<const int4*>(&w.srecs[c]);
-    const int4* kc = reinterpret_cast<const int4*>(w.kc + sc * P.stride);
-    int4* dch = reinterpret_cast<int4*>(&cache[wv].ch);
-    int4* dkc = reinterpret_cast<int4*>(cache[wv].kc);
-    for (int i = lane; i < nch + nkc; i += WAVE) {
-      if (i < nch) dch[i] = src[i];
-      else dkc[i - nch] = kc[i - nch];
+    const int nch = (int)(sizeof(Chart) / 16), nkc = P.stride / 16, per = nch + nkc;
+    const int j0 = cb > 0 ? 0 : 1, j1 = min(NJ, P.N - cb + 1);
+    for (int i = tid; i < (j1 - j0) * per; i += PROF_NT) {
+      const int j = j0 + i / per, r = i % per, c = cb - 1 + j;
+      if (r < nch) {
+        reinterpret_cast<int4*>(&cache[j].ch)[r] = reinterpret_cast<const int4*>(&w.srecs[c])[r];
+      } else {
+        reinterpret_cast<int4*>(cache[j].kc)[r - nch] =
+            reinterpret_cast<const int4*>(w.kc + ((size_t)s * P.N + c) * P.stride)[r - nch];
+      }
     }
-    wsync();
   }
-  const KView kv = kview(cache[wv].kc, P.K);
-  const Chart& ch = cache[wv].ch;
-  const KHead hd = khead_load(kv.hd);
-  const int K = P.K, p = P.p, wt = hd.w, ht = hd.h;
-  const int step = WAVE - p;
-  uint32_t* out = w.arena + pc;
-  for (int j0 = 0; j0 < wt + p; j0 += step) {
-    const int u = j0 - p + lane;
-    int32_t tp = BIG, bt = -BIG;
-    if (u >= 0 && u < wt) column_bounds(kv, ch, K, k, u, tp, bt);
-    int32_t T = tp, Bo = bt;
-    for (int q = 1; q <= p; ++q) {
-      T = min(T, __shfl_up(tp, q));
-      Bo = max(Bo, __shfl_up(bt, q));
+  __syncthreads();
+  const int K = P.K, p = P.p, step = WAVE - p;
+  for (int j = wv; j < NJ; j += PROF_NT / WAVE) {
+    const int32_t pc = s_pc[j];
+    if (pc < 0) continue;
+    // the chart before the block is only needed for its rows, and only when
+    // it belongs to the same atlas as the block's first chart
+    if (j == 0 && (s_a[0] != s_a[1] || (s_run[1] & 2))) continue;
+    const int k = s_k[j];
+    const KView kv = kview(cache[j].kc, K);
+    const Chart& ch = cache[j].ch;
+    const KHead hd = khead_load(kv.hd);
+    const int wt = hd.w, ht = hd.h;
+    if (j > 0) {
+      uint32_t* out = w.arena + pc;
+      for (int j0 = 0; j0 < wt + p; j0 += step) {
+        const int u = j0 - p + lane;
+        int32_t tp = BIG, bt = -BIG;
+        if (u >= 0 && u < wt) column_bounds(kv, ch, K, k, u, tp, bt);
+        int32_t T = tp, Bo = bt;
+        for (int q = 1; q <= p; ++q) {
+          T = min(T, __shfl_up(tp, q));
+          Bo = max(Bo, __shfl_up(bt, q));
+        }
+        if (lane >= p && u < wt + p) out[u] = pack16(T, Bo + p);
+      }
     }
-    if (lane >= p && u < wt + p) out[u] = pack16(T, Bo + p);
+    uint32_t* out = w.arena + s_pr[j];
+    for (int j0 = 0; j0 < ht + p; j0 += step) {
+      const int u = j0 - p + lane;
+      int32_t l = BIG, r = -BIG;
+      if (u >= 0 && u < ht) row_bounds(kv, ch, K, k, u, l, r);
+      int32_t L = l, R = r;
+      for (int q = 1; q <= p; ++q) {
+        L = min(L, __shfl_up(l, q));
+        R = max(R, __shfl_up(r, q));
+      }
+      if (lane >= p && u < ht + p) out[u] = pack16(L, R + p);
+    }
   }
-  out = w.arena + pr;
-  for (int j0 = 0; j0 < ht + p; j0 += step) {
-    const int u = j0 - p + lane;
-    int32_t l = BIG, r = -BIG;
-    if (u >= 0 && u < ht) row_bounds(kv, ch, K, k, u, l, r);
-    int32_t L = l, R = r;
-    for (int q = 1; q <= p; ++q) {
-      L = min(L, __shfl_up(l, q));
-      R = max(R, __shfl_up(r, q));
+  __syncthreads();  // the block's stored rows are visible to all its wavefronts
+  for (int j = 1 + wv; j < NJ; j += PROF_NT / WAVE) {
+    const int run = s_run[j];
+    if (!(run & 1)) continue;
+    const int c = cb - 1 + j;
+    const size_t sc = (size_t)s * P.N + c;
+    if (run & 2) {
+      if (lane == 0) { w.cd[sc] = 0; w.fl[sc] = 0; }
+      continue;
     }
-    if (lane >= p && u < ht + p) out[u] = pack16(L, R + p);
+    const KView A = kview(cache[j - 1].kc, K), B = kview(cache[j].kc, K);
+    const int wdA = khead_load(A.hd).w + p;
+    PairSweep r;
+    if (s_pr[j] >= 0) {
+      r = pair_sweep_rows(w.arena + s_pr[j - 1], khead_load(A.hd).h + p, w.arena + s_pr[j],
+                          khead_load(B.hd).h + p, wdA);
+    } else {
+      r = pair_sweep(A, cache[j - 1].ch, B, cache[j].ch, K, s_k[j], p);
+    }
+    if (lane == 0) {
+      w.cd[sc] = r.cd;
+      w.fl[sc] = (uint8_t)pair_flags_at(r, wdA, wdA - r.cd);
+    }
   }
 }
 
@@ -189,10 +242,8 @@ hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_
   // with no arena the placement still runs: it marks every segment unstored
   hipLaunchKernelGGL(k_layout, dim3(P.count, P.B), dim3(LAY_NT), 0, st, P, w, round);
   hipLaunchKernelGGL(k_alloc, dim3(1), dim3(ALLOC_NT), 0, st, P, w);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || P.arena_cap <= 0) return e;
-  hipLaunchKernelGGL(k_profile, dim3((P.N + PROF_WAVES - 1) / PROF_WAVES, P.B),
-                     dim3(PROF_WAVES * WAVE), 0, st, P, w, round);
+  hipLaunchKernelGGL(k_profile, dim3((P.N + PROF_CH - 1) / PROF_CH, P.B), dim3(PROF_NT), 0, st, P,
+                     w, round);
   return hipGetLastError();
 }
 

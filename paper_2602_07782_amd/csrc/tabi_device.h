@@ -93,6 +93,24 @@ __device__ inline int64_t fdiv53(int64_t n, int64_t d) {
 }
 __device__ inline int64_t cdiv53(int64_t n, int64_t d) { return -fdiv53(-n, d); }
 
+// floor(n / d) for 0 < d < 2^31 and |n| < 2^53, cheaper when the quotient is
+// small: the single-precision estimate (conversions of n and d, an
+// approximate reciprocal within one ulp, the product: relative error below
+// 2^-21) is within 1/2 of n / d whenever |n / d| < 2^20, so its floor is off
+// by at most one and one integer correction makes it exact.  Larger
+// quotients take fdiv53.
+__device__ inline int64_t fdiv_q(int64_t n, int64_t d) {
+  const float qf = floorf((float)n * __builtin_amdgcn_rcpf((float)d));
+  if (fabsf(qf) < 1048576.0f) {
+    int64_t q = (int64_t)(int32_t)qf;
+    const int64_t r = n - q * d;
+    if (r < 0) q -= 1;
+    else if (r >= d) q += 1;
+    return q;
+  }
+  return fdiv53(n, d);
+}
+
 // floor / ceil for any int64 with d > 0
 __host__ __device__ inline int64_t fdiv64(int64_t n, int64_t d) {
   int64_t q = n / d;
@@ -136,19 +154,17 @@ __device__ inline KHead khead_load(const KHead* p) {
 // extent with n texels.  Line A applies left of (above) the corner, line B
 // right of (below) it; each line is (n0 + n1 * x) / d rounded down (lo sides)
 // or up (hi sides).
+// Branch-free: every lane selects its line first, so a wavefront whose
+// lanes straddle the corner still performs one division.
 template <bool CEIL>
 __device__ inline int32_t side_value(const KSide& s, int32_t t, int32_t n, int64_t n0a, int64_t n1a,
                                      int64_t da, int64_t n0b, int64_t n1b, int64_t db) {
-  if (t == n - 1) return s.last;
-  if (t + 1 <= s.sa) {
-    int64_t num = n0a + n1a * (int64_t)(t + 1);
-    return (int32_t)(CEIL ? cdiv53(num, da) : fdiv53(num, da));
-  }
-  if (t >= s.sb) {
-    int64_t num = n0b + n1b * (int64_t)t;
-    return (int32_t)(CEIL ? cdiv53(num, db) : fdiv53(num, db));
-  }
-  return s.corner;
+  const bool useA = t + 1 <= s.sa, useB = t >= s.sb;
+  const int64_t n0 = useA ? n0a : n0b, n1 = useA ? n1a : n1b, d = useA ? da : db;
+  const int64_t x = useA ? (int64_t)t + 1 : (int64_t)t;
+  const int64_t num = n0 + n1 * x;
+  const int32_t q = (int32_t)(CEIL ? -fdiv_q(-num, d) : fdiv_q(num, d));
+  return t == n - 1 ? s.last : ((useA || useB) ? q : s.corner);
 }
 
 // Undilated TopEdge / BottomEdge of column i (App. A, "Parallel Pushing"):

@@ -77,8 +77,8 @@ hipError_t launch_splice(Chart* dst, const int32_t* idx, int m, const Chart* src
 hipError_t launch_sort(const Params& P, const Work& w, hipStream_t st);
 hipError_t launch_plan(const Params& P, const Work& w, hipStream_t st);
 hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t st);
+// per-texel profiles and neighbour pairs (compacting distance, interlock flags)
 hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_t st);
-hipError_t launch_pairs(const Params& P, const Work& w, int round, hipStream_t st);
 hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes, int RC, int PW,
                        int stage_cap, hipStream_t st);
 hipError_t launch_select(const Params& P, const Work& w, int round, int last_round,
