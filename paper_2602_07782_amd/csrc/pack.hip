@@ -17,8 +17,8 @@
 //                                      from their proxy records
 //   4. push                            every texel of every configuration:
 //                                      frontline - TopEdge, segmented max per
-//                                      chart across the wavefront, one LDS
-//                                      atomic per chart segment
+//                                      chart across the wavefront (DPP lane
+//                                      moves), one LDS atomic per chart run
 //   5. correction (Alg. 1)             per configuration one wavefront: forward
 //                                      and backward segmented max scans over the
 //                                      interlock chain, plus the rare pairs that
@@ -56,15 +56,13 @@ __device__ inline int find_chart(const int32_t* Xoff, int cand, int e) {
   return lo;
 }
 
-// segmented max toward the first lane of each run of equal t
-__device__ inline int32_t seg_max_to_head(int32_t v, int t) {
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    int32_t vd = __shfl_down(v, o);
-    int td = __shfl_down(t, o);
-    if (lane_id() + o < WAVE && td == t) v = max(v, vd);
-  }
-  return v;
+// Segmented prefix max over the runs of a wavefront that start at `head`
+// lanes, continuing `carry` into the lanes before the first head: the run
+// start (a max-scan of head lanes) is a non-decreasing key for seg_scan_max.
+__device__ inline int32_t run_scan_max(int32_t v, bool head, int32_t carry) {
+  const int32_t key = wave_incl_max(head ? lane_id() : -1);
+  v = seg_scan_max(v, key, seg_keys(key));
+  return key < 0 ? max(v, carry) : v;
 }
 
 // CorrectYOffsets (Alg. 1) for one configuration, one wavefront.  Chain links
@@ -77,32 +75,20 @@ __device__ void correct_offsets(int32_t* y, int cnt, const uint8_t* fl, const in
     for (int t0 = 0; t0 < cnt; t0 += WAVE) {  // y[t] >= y[t-1] where bit0 of fl[t]
       const int t = t0 + lane;
       int32_t v = t < cnt ? y[t] : -BIG;
-      int head = !(t >= 1 && t < cnt && (fl[t] & 1));
-#pragma unroll
-      for (int o = 1; o < WAVE; o <<= 1) {
-        int32_t vu = __shfl_up(v, o);
-        int hu = __shfl_up(head, o);
-        if (lane >= o && !head) { v = max(v, vu); head |= hu; }
-      }
-      if (!head) v = max(v, carry);
+      const bool head = !(t >= 1 && t < cnt && (fl[t] & 1));
+      v = run_scan_max(v, head, carry);
       if (t < cnt) y[t] = v;
-      carry = __shfl(v, WAVE - 1);
+      carry = lane63(v);
     }
     wsync();
     carry = -BIG;
     for (int r0 = 0; r0 < cnt; r0 += WAVE) {  // y[t] >= y[t+1] where bit1 of fl[t+1]
       const int r = r0 + lane, t = cnt - 1 - r;
       int32_t v = r < cnt ? y[t] : -BIG;
-      int head = !(r >= 1 && r < cnt && (fl[t + 1] & 2));
-#pragma unroll
-      for (int o = 1; o < WAVE; o <<= 1) {
-        int32_t vu = __shfl_up(v, o);
-        int hu = __shfl_up(head, o);
-        if (lane >= o && !head) { v = max(v, vu); head |= hu; }
-      }
-      if (!head) v = max(v, carry);
+      const bool head = !(r >= 1 && r < cnt && (fl[t + 1] & 2));
+      v = run_scan_max(v, head, carry);
       if (r < cnt) y[t] = v;
-      carry = __shfl(v, WAVE - 1);
+      carry = lane63(v);
     }
     wsync();
     int changed = 0;
@@ -271,8 +257,8 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
         if (cfn < 0 && bfn) cfn = t0 + __builtin_ctzll(bfn);
         if (cko < 0 && bko) cko = t0 + __builtin_ctzll(bko);
         if (ckn < 0 && bkn) ckn = t0 + __builtin_ctzll(bkn);
-        xo += __shfl(io, WAVE - 1);
-        xn += __shfl(in, WAVE - 1);
+        xo += lane63(io);
+        xn += lane63(in);
       }
       if (lane == 0) {
         s_cnt[0] = cfo; s_cnt[1] = cfn; s_cnt[2] = cko; s_cnt[3] = ckn;
@@ -375,7 +361,10 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       int32_t tp = 0, bt = 0;
       if (valid) texel(e, t, tp, bt);
       const int i = valid ? e - Xoff[t] : 0;
-      const bool head = lane == 0 || __shfl_up(t, 1) != t;
+      // chart t's texels are a run of lanes (t does not decrease along e):
+      // a segmented prefix max leaves the chart's maximum in its last lane
+      const SegKeys sk = seg_keys(t);
+      const bool tail = valid && wave_shl1(t, -2) != t;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         if (j >= ncfg) break;
@@ -385,8 +374,8 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
           const int col = c_dir[j] == DIR_LR ? c_R0[j] + X + i : c_R1[j] - 1 - X - i;
           v = F[col] - tp;
         }
-        v = seg_max_to_head(v, t);
-        if (head && v > -BIG) atomicMax(&Yb[yofs[j] + t], v);
+        v = seg_scan_max(v, t, sk);
+        if (tail && v > -BIG) atomicMax(&Yb[yofs[j] + t], v);
       }
     }
     // interlock flags of the non-neighbour pairs, read only by the correction

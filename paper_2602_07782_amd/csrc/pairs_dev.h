@@ -44,10 +44,12 @@ __device__ inline PairSweep pair_sweep(const KView& A, const Chart& cA, const KV
       row_bounds(B, cB, K, k, u, l, r);
       lb = l;
     }
-    int32_t Ra = ra, Lb = lb;
-    for (int s = 1; s <= p; ++s) {
-      Ra = max(Ra, __shfl_up(ra, s));
-      Lb = min(Lb, __shfl_up(lb, s));
+    int32_t Ra = ra, Lb = lb, sa = ra, sb = lb;
+    for (int s = 1; s <= p; ++s) {  // lanes >= p see rows [u-p, u] of this chunk
+      sa = wave_shr1(sa, -BIG);
+      sb = wave_shr1(sb, BIG);
+      Ra = max(Ra, sa);
+      Lb = min(Lb, sb);
     }
     const int j = u;  // grown row j = lanes [j-p, j] of this chunk
     const bool act = lane >= p && j < hdA;
@@ -55,14 +57,12 @@ __device__ inline PairSweep pair_sweep(const KView& A, const Chart& cA, const KV
     Lb = (act && j < hdB) ? Lb : BIG;
     if (act && j < hdB) cd = min(cd, wdA - Ra + Lb);
     const int32_t imax = wave_incl_max(Ra), imin = wave_incl_min(Lb);
-    int32_t emax = __shfl_up(imax, 1), emin = __shfl_up(imin, 1);
-    if (lane == 0) { emax = -BIG; emin = BIG; }
-    emax = max(emax, carry_max);
-    emin = min(emin, carry_min);
+    const int32_t emax = max(wave_shr1(imax, -BIG), carry_max);
+    const int32_t emin = min(wave_shr1(imin, BIG), carry_min);
     if (act && j >= 1 && j < hdB) D1 = max(D1, emax - Lb);
     if (act && j >= 1) D2 = max(D2, Ra - emin);
-    carry_max = max(carry_max, __shfl(imax, WAVE - 1));
-    carry_min = min(carry_min, __shfl(imin, WAVE - 1));
+    carry_max = max(carry_max, lane63(imax));
+    carry_min = min(carry_min, lane63(imin));
   }
   PairSweep r;
   r.cd = wave_min(cd);
@@ -87,14 +87,12 @@ __device__ inline PairSweep pair_sweep_rows(const uint32_t* ra, int hdA, const u
     const int32_t Lb = shr ? lo16(rb[j]) : BIG;
     if (shr) cd = min(cd, wdA - Ra + Lb);
     const int32_t imax = wave_incl_max(Ra), imin = wave_incl_min(Lb);
-    int32_t emax = __shfl_up(imax, 1), emin = __shfl_up(imin, 1);
-    if (lane == 0) { emax = -BIG; emin = BIG; }
-    emax = max(emax, carry_max);
-    emin = min(emin, carry_min);
+    const int32_t emax = max(wave_shr1(imax, -BIG), carry_max);
+    const int32_t emin = min(wave_shr1(imin, BIG), carry_min);
     if (shr && j >= 1) D1 = max(D1, emax - Lb);
     if (act && j >= 1) D2 = max(D2, Ra - emin);
-    carry_max = max(carry_max, __shfl(imax, WAVE - 1));
-    carry_min = min(carry_min, __shfl(imin, WAVE - 1));
+    carry_max = max(carry_max, lane63(imax));
+    carry_min = min(carry_min, lane63(imin));
   }
   PairSweep r;
   r.cd = wave_min(cd);

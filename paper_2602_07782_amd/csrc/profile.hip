@@ -126,7 +126,7 @@ __global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w) {
 // in one burst and their segment offsets loaded in parallel; each wavefront
 // evaluates charts from LDS.  Lane l of a chunk evaluates undilated column
 // (row) u = j0 - p + l; the gutter growth over [u-p, u] comes from p
-// shuffles, so a chunk advances 64 - p entries (p <= 32).  After a barrier
+// one-lane moves, so a chunk advances 64 - p entries (p <= 32).  After a barrier
 // the pairs read the rows just stored; pairs in segments without stored
 // profiles evaluate the rows from the LDS records.
 __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round) {
@@ -190,10 +190,12 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
         const int u = j0 - p + lane;
         int32_t tp = BIG, bt = -BIG;
         if (u >= 0 && u < wt) column_bounds(kv, ch, K, k, u, tp, bt);
-        int32_t T = tp, Bo = bt;
+        int32_t T = tp, Bo = bt, st = tp, sb = bt;
         for (int q = 1; q <= p; ++q) {
-          T = min(T, __shfl_up(tp, q));
-          Bo = max(Bo, __shfl_up(bt, q));
+          st = wave_shr1(st, BIG);
+          sb = wave_shr1(sb, -BIG);
+          T = min(T, st);
+          Bo = max(Bo, sb);
         }
         if (lane >= p && u < wt + p) out[u] = pack16(T, Bo + p);
       }
@@ -203,10 +205,12 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
       const int u = j0 - p + lane;
       int32_t l = BIG, r = -BIG;
       if (u >= 0 && u < ht) row_bounds(kv, ch, K, k, u, l, r);
-      int32_t L = l, R = r;
+      int32_t L = l, R = r, sl = l, sr = r;
       for (int q = 1; q <= p; ++q) {
-        L = min(L, __shfl_up(l, q));
-        R = max(R, __shfl_up(r, q));
+        sl = wave_shr1(sl, BIG);
+        sr = wave_shr1(sr, -BIG);
+        L = min(L, sl);
+        R = max(R, sr);
       }
       if (lane >= p && u < ht + p) out[u] = pack16(L, R + p);
     }

@@ -288,14 +288,95 @@ __device__ inline int32_t hi16(uint32_t v) { return (int32_t)v >> 16; }
 // ---------------------------------------------------------------------------
 __device__ inline int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
 
-__device__ inline int32_t wave_max(int32_t v) {
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+// Lane moves by DPP (data-parallel primitives of the VALU; a 64-lane
+// wavefront is four rows of 16): row_shr:n takes lane l-n of the same row,
+// row_bcast:15 / :31 feed lane 15 of a row (31 of the wavefront) to the rows
+// selected by the row mask, wave_shr:1 / wave_shl:1 take lane l-1 / l+1.
+// Lanes without a source keep `fill`.  Every lane of the wavefront must be
+// active: a disabled source lane supplies whatever its register holds.
+template <int CTRL, int ROWS = 0xf>
+__device__ inline int32_t dpp_move(int32_t v, int32_t fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, CTRL, ROWS, 0xf, false);
+}
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114,
+              DPP_ROW_SHR8 = 0x118, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143,
+              DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138;
+
+// value of lane l-1 (lane 0: fill) / lane l+1 (lane 63: fill)
+__device__ inline int32_t wave_shr1(int32_t v, int32_t fill) {
+  return dpp_move<DPP_WAVE_SHR1>(v, fill);
+}
+__device__ inline int32_t wave_shl1(int32_t v, int32_t fill) {
+  return dpp_move<DPP_WAVE_SHL1>(v, fill);
+}
+__device__ inline int32_t lane63(int32_t v) { return __builtin_amdgcn_readlane(v, 63); }
+
+// inclusive prefix over lanes 0..l: Hillis-Steele within each row, then the
+// row totals carried by the two broadcasts
+#define TABI_WAVE_SCAN(OP, ID)                                  \
+  v = OP(v, dpp_move<DPP_ROW_SHR1>(v, ID));                     \
+  v = OP(v, dpp_move<DPP_ROW_SHR2>(v, ID));                     \
+  v = OP(v, dpp_move<DPP_ROW_SHR4>(v, ID));                     \
+  v = OP(v, dpp_move<DPP_ROW_SHR8>(v, ID));                     \
+  v = OP(v, dpp_move<DPP_ROW_BCAST15, 0xa>(v, ID));             \
+  v = OP(v, dpp_move<DPP_ROW_BCAST31, 0xc>(v, ID));
+__device__ inline int32_t add32(int32_t a, int32_t b) { return a + b; }
+__device__ inline int32_t max32(int32_t a, int32_t b) { return max(a, b); }
+__device__ inline int32_t min32(int32_t a, int32_t b) { return min(a, b); }
+__device__ inline int32_t wave_incl_sum(int32_t v) {
+  TABI_WAVE_SCAN(add32, 0)
   return v;
 }
-__device__ inline int32_t wave_min(int32_t v) {
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+__device__ inline int32_t wave_incl_max(int32_t v) {
+  TABI_WAVE_SCAN(max32, -BIG)
   return v;
 }
+__device__ inline int32_t wave_incl_min(int32_t v) {
+  TABI_WAVE_SCAN(min32, BIG)
+  return v;
+}
+#undef TABI_WAVE_SCAN
+__device__ inline int32_t wave_max(int32_t v) { return lane63(wave_incl_max(v)); }
+__device__ inline int32_t wave_min(int32_t v) { return lane63(wave_incl_min(v)); }
+
+// Segmented inclusive max over runs of equal keys, for keys that do not
+// decrease across the valid lanes (lanes after them may hold any smaller
+// key).  The keys of every step's source lane are computed once (SegKeys) and
+// shared by the scans of several value arrays over the same segments.  A
+// guarded step only combines lanes with equal keys; since keys are
+// non-decreasing, a lane whose step source has another key has no earlier
+// lane of its segment either, so the guarded scan is exact.
+struct SegKeys {
+  int32_t k1, k2, k4, k8, k15, k31;
+};
+__device__ inline SegKeys seg_keys(int32_t key) {
+  constexpr int32_t NONE = -0x40000000;  // never a key
+  SegKeys s;
+  s.k1 = dpp_move<DPP_ROW_SHR1>(key, NONE);
+  s.k2 = dpp_move<DPP_ROW_SHR2>(key, NONE);
+  s.k4 = dpp_move<DPP_ROW_SHR4>(key, NONE);
+  s.k8 = dpp_move<DPP_ROW_SHR8>(key, NONE);
+  s.k15 = dpp_move<DPP_ROW_BCAST15, 0xa>(key, NONE);
+  s.k31 = dpp_move<DPP_ROW_BCAST31, 0xc>(key, NONE);
+  return s;
+}
+__device__ inline int32_t seg_scan_max(int32_t v, int32_t key, const SegKeys& s) {
+  int32_t u;
+  u = dpp_move<DPP_ROW_SHR1>(v, -BIG);
+  v = s.k1 == key ? max(v, u) : v;
+  u = dpp_move<DPP_ROW_SHR2>(v, -BIG);
+  v = s.k2 == key ? max(v, u) : v;
+  u = dpp_move<DPP_ROW_SHR4>(v, -BIG);
+  v = s.k4 == key ? max(v, u) : v;
+  u = dpp_move<DPP_ROW_SHR8>(v, -BIG);
+  v = s.k8 == key ? max(v, u) : v;
+  u = dpp_move<DPP_ROW_BCAST15, 0xa>(v, -BIG);
+  v = s.k15 == key ? max(v, u) : v;
+  u = dpp_move<DPP_ROW_BCAST31, 0xc>(v, -BIG);
+  v = s.k31 == key ? max(v, u) : v;
+  return v;
+}
+
 __device__ inline int64_t wave_max64(int64_t v) {
   for (int o = 32; o > 0; o >>= 1) {
     int64_t u = __shfl_xor((long long)v, o);
@@ -312,32 +393,6 @@ __device__ inline int64_t wave_min64(int64_t v) {
 }
 __device__ inline uint64_t wave_sum_u64(uint64_t v) {
   for (int o = 32; o > 0; o >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, o);
-  return v;
-}
-// inclusive prefix sum over the wave
-__device__ inline int32_t wave_incl_sum(int32_t v) {
-  const int l = lane_id();
-  for (int o = 1; o < WAVE; o <<= 1) {
-    int32_t u = __shfl_up(v, o);
-    if (l >= o) v += u;
-  }
-  return v;
-}
-// inclusive prefix max / min over the wave
-__device__ inline int32_t wave_incl_max(int32_t v) {
-  const int l = lane_id();
-  for (int o = 1; o < WAVE; o <<= 1) {
-    int32_t u = __shfl_up(v, o);
-    if (l >= o) v = max(v, u);
-  }
-  return v;
-}
-__device__ inline int32_t wave_incl_min(int32_t v) {
-  const int l = lane_id();
-  for (int o = 1; o < WAVE; o <<= 1) {
-    int32_t u = __shfl_up(v, o);
-    if (l >= o) v = min(v, u);
-  }
   return v;
 }
 __device__ inline uint64_t ballot64(bool p) { return (uint64_t)__ballot(p); }
