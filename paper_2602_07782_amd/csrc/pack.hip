@@ -1,8 +1,8 @@
 // Fold-and-push at one candidate scale per workgroup (Alg. 3), and the scale
 // selection.
 //
-// One workgroup (8 wavefronts) owns one (atlas, scale) pair and walks its rows
-// in order.  The committed frontline lives in LDS.  Per row:
+// One workgroup (16 or 8 wavefronts) owns one (atlas, scale) pair and walks
+// its rows in order.  The committed frontline lives in LDS.  Per row:
 //   1. knee update (Alg. 4)            block max/min over the knee span
 //   2. folding (Alg. 2)                wavefront prefix sums of chart advances,
 //                                      first overflow by ballot; folds with
@@ -34,8 +34,6 @@
 
 namespace tabi {
 
-constexpr int PACK_NT = 512;
-constexpr int PACK_WAVES = PACK_NT / WAVE;
 constexpr int LRCAP = 256;  // pairs per row that share columns without being neighbours
 constexpr int FWIN = 1024;  // charts per row whose fold data is staged in LDS
 enum { DIR_LR = 0, DIR_RL = 1 };
@@ -109,6 +107,7 @@ __device__ void correct_offsets(int32_t* y, int cnt, const uint8_t* fl, const in
   }
 }
 
+template <int PACK_WAVES>
 __device__ inline int32_t block_reduce_max(int32_t v, int32_t* red) {
   v = wave_max(v);
   __syncthreads();
@@ -119,6 +118,7 @@ __device__ inline int32_t block_reduce_max(int32_t v, int32_t* red) {
   for (int i = 1; i < PACK_WAVES; ++i) r = max(r, red[i]);
   return r;
 }
+template <int PACK_WAVES>
 __device__ inline int32_t block_reduce_min(int32_t v, int32_t* red) {
   v = wave_min(v);
   __syncthreads();
@@ -130,10 +130,13 @@ __device__ inline int32_t block_reduce_min(int32_t v, int32_t* red) {
   return r;
 }
 
-// at most 128 VGPRs, so that two 512-thread workgroups can share a CU when
-// their shared memory allows it (batched packs)
+// PACK_NT threads per workgroup: 1024 for a single pack (every per-texel
+// phase of a row spread over 16 wavefronts), 512 for batches (two workgroups
+// per CU when their shared memory allows it).  At most 128 VGPRs either way.
+template <int PACK_NT>
 __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) void k_pack(
     Params P, Work w, int round, int RC, int PW, int stage_cap) {
+  constexpr int PACK_WAVES = PACK_NT / WAVE;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t s_cnt[4];
   __shared__ int32_t s_red[PACK_WAVES * 6];
@@ -219,12 +222,12 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
         if (kdir == DIR_LR) {
           int32_t best = kl - 1;
           for (int x = kl + tid; x < kr; x += PACK_NT) if (F[x] >= h0) best = max(best, x);
-          best = block_reduce_max(best, s_red);
+          best = block_reduce_max<PACK_WAVES>(best, s_red);
           kr = best + 1;
         } else {
           int32_t best = kr;
           for (int x = kl + tid; x < kr; x += PACK_NT) if (F[x] >= h0) best = min(best, x);
-          best = block_reduce_min(best, s_red);
+          best = block_reduce_min<PACK_WAVES>(best, s_red);
           kl = best;
         }
       }
@@ -613,20 +616,32 @@ PackLds pack_lds_plan(int nmax, int Wd, int budget) {
 }
 
 int pack_static_lds() {
-  hipFuncAttributes a;
-  if (hipFuncGetAttributes(&a, (const void*)k_pack) != hipSuccess) return 32 * 1024;
-  return (int)a.sharedSizeBytes;
+  int r = 0;
+  for (const void* f : {(const void*)k_pack<512>, (const void*)k_pack<1024>}) {
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, f) != hipSuccess) return 32 * 1024;
+    r = (int)a.sharedSizeBytes > r ? (int)a.sharedSizeBytes : r;
+  }
+  return r;
 }
 
 hipError_t pack_set_max_lds(int bytes) {
-  return hipFuncSetAttribute((const void*)k_pack, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)k_pack<512>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_pack<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              bytes);
 }
 
 hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes, int RC, int PW,
                        int stage_cap, hipStream_t st) {
-  hipLaunchKernelGGL(k_pack, dim3(P.B, P.count), dim3(PACK_NT), lds_bytes, st, P, w, round, RC, PW,
-                     stage_cap);
+  // one atlas: latency matters, use the wider workgroup
+  if (P.count == 1)
+    hipLaunchKernelGGL(k_pack<1024>, dim3(P.B, P.count), dim3(1024), lds_bytes, st, P, w, round,
+                       RC, PW, stage_cap);
+  else
+    hipLaunchKernelGGL(k_pack<512>, dim3(P.B, P.count), dim3(512), lds_bytes, st, P, w, round, RC,
+                       PW, stage_cap);
   return hipGetLastError();
 }
 

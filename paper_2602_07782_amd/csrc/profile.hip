@@ -119,6 +119,58 @@ __global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w) {
   }
 }
 
+// Stores the grown columns and rows of the workgroup's charts, one chart per
+// wavefront at a time (KT slices per axis).
+template <int KT>
+__device__ void profile_charts(const Work& w, const ChartCache* cache, const int32_t* s_pc,
+                               const int32_t* s_pr, const int32_t* s_k, const int32_t* s_a,
+                               const int32_t* s_run, int p) {
+  constexpr int NJ = PROF_CH + 1;
+  const int wv = threadIdx.x / WAVE, lane = lane_id(), step = WAVE - p;
+  for (int j = wv; j < NJ; j += PROF_NT / WAVE) {
+    const int32_t pc = s_pc[j];
+    if (pc < 0) continue;
+    // the chart before the block is only needed for its rows, and only when
+    // it belongs to the same atlas as the block's first chart
+    if (j == 0 && (s_a[0] != s_a[1] || (s_run[1] & 2))) continue;
+    const int k = s_k[j];
+    const KView kv = kview(cache[j].kc, KT);
+    const Chart& ch = cache[j].ch;
+    const KHead hd = khead_load(kv.hd);
+    const int wt = hd.w, ht = hd.h;
+    if (j > 0) {
+      uint32_t* out = w.arena + pc;
+      for (int j0 = 0; j0 < wt + p; j0 += step) {
+        const int u = j0 - p + lane;
+        int32_t tp = BIG, bt = -BIG;
+        if (u >= 0 && u < wt) column_bounds<KT>(kv, ch, KT, k, u, tp, bt);
+        int32_t T = tp, Bo = bt, st = tp, sb = bt;
+        for (int q = 1; q <= p; ++q) {
+          st = wave_shr1(st, BIG);
+          sb = wave_shr1(sb, -BIG);
+          T = min(T, st);
+          Bo = max(Bo, sb);
+        }
+        if (lane >= p && u < wt + p) out[u] = pack16(T, Bo + p);
+      }
+    }
+    uint32_t* out = w.arena + s_pr[j];
+    for (int j0 = 0; j0 < ht + p; j0 += step) {
+      const int u = j0 - p + lane;
+      int32_t l = BIG, r = -BIG;
+      if (u >= 0 && u < ht) row_bounds<KT>(kv, ch, KT, k, u, l, r);
+      int32_t L = l, R = r, sl = l, sr = r;
+      for (int q = 1; q <= p; ++q) {
+        sl = wave_shr1(sl, BIG);
+        sr = wave_shr1(sr, -BIG);
+        L = min(L, sl);
+        R = max(R, sr);
+      }
+      if (lane >= p && u < ht + p) out[u] = pack16(L, R + p);
+    }
+  }
+}
+
 // Grown bounds of PROF_CH charts of one scale slot per workgroup, then the
 // compacting distance and interlock flags of their pairs with the preceding
 // chart (Sec. 4.1.2; App. A "Detecting Interlocking Charts").  The charts'
@@ -172,49 +224,10 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
     }
   }
   __syncthreads();
-  const int K = P.K, p = P.p, step = WAVE - p;
-  for (int j = wv; j < NJ; j += PROF_NT / WAVE) {
-    const int32_t pc = s_pc[j];
-    if (pc < 0) continue;
-    // the chart before the block is only needed for its rows, and only when
-    // it belongs to the same atlas as the block's first chart
-    if (j == 0 && (s_a[0] != s_a[1] || (s_run[1] & 2))) continue;
-    const int k = s_k[j];
-    const KView kv = kview(cache[j].kc, K);
-    const Chart& ch = cache[j].ch;
-    const KHead hd = khead_load(kv.hd);
-    const int wt = hd.w, ht = hd.h;
-    if (j > 0) {
-      uint32_t* out = w.arena + pc;
-      for (int j0 = 0; j0 < wt + p; j0 += step) {
-        const int u = j0 - p + lane;
-        int32_t tp = BIG, bt = -BIG;
-        if (u >= 0 && u < wt) column_bounds(kv, ch, K, k, u, tp, bt);
-        int32_t T = tp, Bo = bt, st = tp, sb = bt;
-        for (int q = 1; q <= p; ++q) {
-          st = wave_shr1(st, BIG);
-          sb = wave_shr1(sb, -BIG);
-          T = min(T, st);
-          Bo = max(Bo, sb);
-        }
-        if (lane >= p && u < wt + p) out[u] = pack16(T, Bo + p);
-      }
-    }
-    uint32_t* out = w.arena + s_pr[j];
-    for (int j0 = 0; j0 < ht + p; j0 += step) {
-      const int u = j0 - p + lane;
-      int32_t l = BIG, r = -BIG;
-      if (u >= 0 && u < ht) row_bounds(kv, ch, K, k, u, l, r);
-      int32_t L = l, R = r, sl = l, sr = r;
-      for (int q = 1; q <= p; ++q) {
-        sl = wave_shr1(sl, BIG);
-        sr = wave_shr1(sr, -BIG);
-        L = min(L, sl);
-        R = max(R, sr);
-      }
-      if (lane >= p && u < ht + p) out[u] = pack16(L, R + p);
-    }
-  }
+  const int K = P.K, p = P.p;
+  if (K == 10) profile_charts<10>(w, cache, s_pc, s_pr, s_k, s_a, s_run, p);
+  else if (K == 5) profile_charts<5>(w, cache, s_pc, s_pr, s_k, s_a, s_run, p);
+  else profile_charts<2>(w, cache, s_pc, s_pr, s_k, s_a, s_run, p);
   __syncthreads();  // the block's stored rows are visible to all its wavefronts
   for (int j = 1 + wv; j < NJ; j += PROF_NT / WAVE) {
     const int run = s_run[j];

@@ -167,14 +167,16 @@ __device__ inline int32_t side_value(const KSide& s, int32_t t, int32_t n, int64
   return t == n - 1 ? s.last : ((useA || useB) ? q : s.corner);
 }
 
-// Undilated TopEdge / BottomEdge of column i (App. A, "Parallel Pushing"):
-// the tightest of the two proxies, rounded outward.
-__device__ inline void column_bounds(const KView& kv, const Chart& ch, int K, int k, int i,
-                                     int32_t& top, int32_t& bot) {
+// Top / bottom of column i over the local-AABB slices: the x-slices and the
+// y-slices covering the column each give a range; the proxy keeps their
+// intersection.  KT > 0 fixes the slice count at compile time (K == KT).
+template <int KT = 0>
+__device__ inline void column_rects(const KView& kv, int K, int i, int32_t& top, int32_t& bot) {
+  if (KT) K = KT;
   int32_t tx = BIG, bx = -BIG, ty = BIG, by = -BIG;
 #pragma unroll
-  for (int j = 0; j < KMAX; ++j) {
-    if (j < K) {
+  for (int j = 0; j < (KT ? KT : KMAX); ++j) {
+    if (KT || j < K) {
       int32_t c0, c1, r0, r1;
       krect_load(kv.rc + j, c0, c1, r0, r1);
       const bool in = c0 <= i && i < c1;
@@ -186,7 +188,17 @@ __device__ inline void column_bounds(const KView& kv, const Chart& ch, int K, in
       by = iny ? max(by, r1) : by;
     }
   }
-  int32_t t = max(tx, ty), b = min(bx, by);
+  top = max(tx, ty);
+  bot = min(bx, by);
+}
+
+// Undilated TopEdge / BottomEdge of column i (App. A, "Parallel Pushing"):
+// the tightest of the two proxies, rounded outward.
+template <int KT = 0>
+__device__ inline void column_bounds(const KView& kv, const Chart& ch, int K, int k, int i,
+                                     int32_t& top, int32_t& bot) {
+  int32_t t, b;
+  column_rects<KT>(kv, K, i, t, b);
   const KHead hd = khead_load(kv.hd);
   if (hd.obb) {
     const int64_t C = kDirC[ch.m], S = kDirS[ch.m];
@@ -203,13 +215,14 @@ __device__ inline void column_bounds(const KView& kv, const Chart& ch, int K, in
   bot = b;
 }
 
-// Undilated left / right bound of row j.
-__device__ inline void row_bounds(const KView& kv, const Chart& ch, int K, int k, int j,
-                                  int32_t& left, int32_t& right) {
+// Left / right of row j over the local-AABB slices.
+template <int KT = 0>
+__device__ inline void row_rects(const KView& kv, int K, int j, int32_t& left, int32_t& right) {
+  if (KT) K = KT;
   int32_t ly = BIG, ry = -BIG, lx = BIG, rx = -BIG;
 #pragma unroll
-  for (int q = 0; q < KMAX; ++q) {
-    if (q < K) {
+  for (int q = 0; q < (KT ? KT : KMAX); ++q) {
+    if (KT || q < K) {
       int32_t c0, c1, r0, r1;
       krect_load(kv.rc + K + q, c0, c1, r0, r1);
       const bool iny = r0 <= j && j < r1;
@@ -221,7 +234,16 @@ __device__ inline void row_bounds(const KView& kv, const Chart& ch, int K, int k
       rx = inx ? max(rx, c1) : rx;
     }
   }
-  int32_t l = max(ly, lx), rr = min(ry, rx);
+  left = max(ly, lx);
+  right = min(ry, rx);
+}
+
+// Undilated left / right bound of row j.
+template <int KT = 0>
+__device__ inline void row_bounds(const KView& kv, const Chart& ch, int K, int k, int j,
+                                  int32_t& left, int32_t& right) {
+  int32_t l, rr;
+  row_rects<KT>(kv, K, j, l, rr);
   const KHead hd = khead_load(kv.hd);
   if (hd.obb) {
     const int64_t C = kDirC[ch.m], S = kDirS[ch.m];
