@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import re
 import os
 import sys
 import time
@@ -130,6 +131,39 @@ def served_leg(seconds=1.0, rate=2000.0):
             "plain_p50_ms": round(pst["p50_ms"], 3), "plain_p99_ms": round(pst["p99_ms"], 3),
             "plain_atlases_per_s": round(len(plain) / pwall, 2),
             "speedup_vs_plain": round(pwall / wall, 2), "bitexact_vs_alone": bool(same)}
+
+
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "k_pack_mixed2k_traffic.md")
+
+
+def kernel_sources_sha256():
+    """Digest of the HIP sources the counters were taken from."""
+    import hashlib
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2602_07782_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per fold-and-push launch from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when the kernels changed since it was taken."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = dict(re.findall(r"^(sources_sha256|traffic_bytes_per_launch):\s*(\S+)\s*$", text, re.M))
+    if vals.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def pack_algorithmic_bytes(inp, k_top):
@@ -271,7 +305,7 @@ def main():
         "stage_ms_per_pack": {s: round(v[0] / max(v[1], 1), 4) for s, v in stages.items()},
         "roofline": {"bound": "hbm", "kernel": "k_pack (fold-and-push, all candidate scales)",
                      "achieved": round(achieved, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 6), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 6), "traffic": recorded_traffic(),
                      "bytes_per_unit": round(unit_bytes, 2), "units_per_launch": units,
                      "bytes_per_launch": pack_bytes,
                      "avg_launch_ms": round(avg_pack_ms, 4), "dominant_stage": dom},

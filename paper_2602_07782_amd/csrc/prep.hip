@@ -326,10 +326,9 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
 }
 
 // one thread per (slot, chart)
-__global__ __launch_bounds__(256) void k_setup(Params P, Work w, int round) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = blockIdx.y;
-  if (c >= P.N) return;
+// The record of chart c at slot s, written to `base` (LDS).
+__device__ void setup_record(const Params& P, const Work& w, int round, int c, int s,
+                             unsigned char* base) {
   const AtlasDesc d = w.desc[w.chart_atlas[c]];
   const bool run = P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1);
   if (!run) return;
@@ -337,12 +336,11 @@ __global__ __launch_bounds__(256) void k_setup(Params P, Work w, int round) {
   if (k < 1) return;
   const Chart& ch = w.srecs[c];
   const int K = P.K;
-  unsigned char* base = w.kc + ((size_t)s * P.N + c) * P.stride;
   KHead* hd = reinterpret_cast<KHead*>(base);
   KSide* sd = reinterpret_cast<KSide*>(base + sizeof(KHead));
   KRect* rc = reinterpret_cast<KRect*>(base + sizeof(KHead) + 4 * sizeof(KSide));
   const int64_t kk = k, W = ch.W, H = ch.H;
-  const int32_t wt = (int32_t)cdiv64(kk * W, QS), ht = (int32_t)cdiv64(kk * H, QS);
+  const int32_t wt = (int32_t)cdiv_i64(kk * W, QS), ht = (int32_t)cdiv_i64(kk * H, QS);
   const size_t sc = (size_t)s * P.N + c;
   w.wdv[sc] = wt + P.p;
   w.hdv[sc] = ht + P.p;
@@ -375,49 +373,66 @@ __global__ __launch_bounds__(256) void k_setup(Params P, Work w, int round) {
   const int64_t C = kDirC[ch.m], S = kDirS[ch.m], N = C * C + S * S, D = QS * N;
   const int64_t a = ch.a, b = ch.b, e = ch.e, f = ch.f;
   auto split = [&](int64_t num, KSide& sdv) {  // corner position num/D (texels)
-    sdv.sa = clamp32(fdiv64(num, D));
-    sdv.sb = clamp32(cdiv64(num, D));
+    sdv.sa = clamp32(fdiv_i64(num, D));
+    sdv.sb = clamp32(cdiv_i64(num, D));
   };
   KSide st, sb, sL, sR;
   // top: corner (p=a, q=e); A: (k a - 16384 C x)/(16384 S); B: (k e + 16384 S x)/(16384 C)
   split(kk * (C * a - S * e), st);
-  st.corner = clamp32(fdiv64(kk * (S * a + C * e), D));
+  st.corner = clamp32(fdiv_i64(kk * (S * a + C * e), D));
   // bottom: corner (p=b, q=f); A: (k f + 16384 S x)/(16384 C); B: (k b - 16384 C x)/(16384 S)
   split(kk * (C * b - S * f), sb);
-  sb.corner = clamp32(cdiv64(kk * (S * b + C * f), D));
+  sb.corner = clamp32(cdiv_i64(kk * (S * b + C * f), D));
   // left: corner (p=a, q=f) at row k(Sa+Cf)/D; A: (k a - 16384 S y)/(16384 C); B: (16384 C y - k f)/(16384 S)
   split(kk * (S * a + C * f), sL);
-  sL.corner = clamp32(fdiv64(kk * (C * a - S * f), D));
+  sL.corner = clamp32(fdiv_i64(kk * (C * a - S * f), D));
   // right: corner (p=b, q=e) at row k(Sb+Ce)/D; A: (16384 C y - k e)/(16384 S); B: (k b - 16384 S y)/(16384 C)
   split(kk * (S * b + C * e), sR);
-  sR.corner = clamp32(cdiv64(kk * (C * b - S * e), D));
+  sR.corner = clamp32(cdiv_i64(kk * (C * b - S * e), D));
   // last column / row: the extent may end inside the texel
   const int64_t tw = wt - 1, th = ht - 1;
   const bool wfrac = (kk * W) % QS != 0, hfrac = (kk * H) % QS != 0;
   // top
   if (!wfrac ? (tw + 1 <= st.sa) : (W * N <= C * a - S * e))
-    st.last = clamp32(!wfrac ? fdiv64(kk * a - QS * C * (tw + 1), QS * S) : fdiv64(kk * (a - C * W), QS * S));
-  else if (tw >= st.sb) st.last = clamp32(fdiv64(kk * e + QS * S * tw, QS * C));
+    st.last = clamp32(!wfrac ? fdiv_i64(kk * a - QS * C * (tw + 1), QS * S) : fdiv_i64(kk * (a - C * W), QS * S));
+  else if (tw >= st.sb) st.last = clamp32(fdiv_i64(kk * e + QS * S * tw, QS * C));
   else st.last = st.corner;
   // bottom
   if (!wfrac ? (tw + 1 <= sb.sa) : (W * N <= C * b - S * f))
-    sb.last = clamp32(!wfrac ? cdiv64(kk * f + QS * S * (tw + 1), QS * C) : cdiv64(kk * (f + S * W), QS * C));
-  else if (tw >= sb.sb) sb.last = clamp32(cdiv64(kk * b - QS * C * tw, QS * S));
+    sb.last = clamp32(!wfrac ? cdiv_i64(kk * f + QS * S * (tw + 1), QS * C) : cdiv_i64(kk * (f + S * W), QS * C));
+  else if (tw >= sb.sb) sb.last = clamp32(cdiv_i64(kk * b - QS * C * tw, QS * S));
   else sb.last = sb.corner;
   // left
   if (!hfrac ? (th + 1 <= sL.sa) : (H * N <= S * a + C * f))
-    sL.last = clamp32(!hfrac ? fdiv64(kk * a - QS * S * (th + 1), QS * C) : fdiv64(kk * (a - S * H), QS * C));
-  else if (th >= sL.sb) sL.last = clamp32(fdiv64(QS * C * th - kk * f, QS * S));
+    sL.last = clamp32(!hfrac ? fdiv_i64(kk * a - QS * S * (th + 1), QS * C) : fdiv_i64(kk * (a - S * H), QS * C));
+  else if (th >= sL.sb) sL.last = clamp32(fdiv_i64(QS * C * th - kk * f, QS * S));
   else sL.last = sL.corner;
   // right
   if (!hfrac ? (th + 1 <= sR.sa) : (H * N <= S * b + C * e))
-    sR.last = clamp32(!hfrac ? cdiv64(QS * C * (th + 1) - kk * e, QS * S) : cdiv64(kk * (C * H - e), QS * S));
-  else if (th >= sR.sb) sR.last = clamp32(cdiv64(kk * b - QS * S * th, QS * C));
+    sR.last = clamp32(!hfrac ? cdiv_i64(QS * C * (th + 1) - kk * e, QS * S) : cdiv_i64(kk * (C * H - e), QS * S));
+  else if (th >= sR.sb) sR.last = clamp32(cdiv_i64(kk * b - QS * S * th, QS * C));
   else sR.last = sR.corner;
   sd[0] = st;
   sd[1] = sb;
   sd[2] = sL;
   sd[3] = sR;
+}
+
+// Records are built in LDS by their threads and written out together with
+// coalesced 16-byte stores (one thread writing its own 16 + 64 + 16K bytes
+// field by field would cost a memory transaction per field).
+constexpr int SETUP_NT = 128;
+__global__ __launch_bounds__(SETUP_NT) void k_setup(Params P, Work w, int round) {
+  __shared__ __align__(16) unsigned char s_rec[SETUP_NT * KREC_MAX];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (c < P.N) setup_record(P, w, round, c, s, s_rec + threadIdx.x * P.stride);
+  __syncthreads();
+  const int c0 = blockIdx.x * blockDim.x, nc = min(SETUP_NT, P.N - c0);
+  const int n16 = nc * (P.stride / 16);
+  const int4* src = reinterpret_cast<const int4*>(s_rec);
+  int4* dst = reinterpret_cast<int4*>(w.kc + ((size_t)s * P.N + c0) * P.stride);
+  for (int i = threadIdx.x; i < n16; i += SETUP_NT) dst[i] = src[i];
 }
 
 // Start of the packing path from resident proxy records: copy, keys, atlas
@@ -502,7 +517,8 @@ hipError_t launch_plan(const Params&, const Work&, hipStream_t) { return hipSucc
 
 hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t st) {
   if (P.N > 0)
-    hipLaunchKernelGGL(k_setup, dim3((P.N + 255) / 256, P.B), dim3(256), 0, st, P, w, round);
+    hipLaunchKernelGGL(k_setup, dim3((P.N + SETUP_NT - 1) / SETUP_NT, P.B), dim3(SETUP_NT), 0, st,
+                       P, w, round);
   return hipGetLastError();
 }
 

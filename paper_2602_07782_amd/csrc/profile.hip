@@ -11,9 +11,9 @@
 //   k_layout   one workgroup per (atlas, scale slot): prefix sums of the
 //              grown widths and heights (offsets within the segment)
 //   k_alloc    one workgroup: segment bases in descending-scale priority
-//   k_profile  per (scale slot, 32 charts): every grown column (top,
-//              bottom) and every grown row (left, right), one wavefront per
-//              chart at a time, then the neighbour pairs' compacting
+//   k_profile  per (scale slot, 16 charts): every grown column (top,
+//              bottom) and every grown row (left, right), in chunks spread
+//              over the wavefronts, then the neighbour pairs' compacting
 //              distances and interlock flags
 //
 // Within a (atlas, slot) segment the charts' columns are stored back to back
@@ -29,7 +29,7 @@ namespace tabi {
 constexpr int LAY_NT = 256;
 constexpr int ALLOC_NT = 1024;
 constexpr int PROF_NT = 256;
-constexpr int PROF_CH = 32;  // charts per profile workgroup
+constexpr int PROF_CH = 16;  // charts per profile workgroup
 
 // Offsets of every chart's grown columns and rows within its (atlas, slot)
 // segment, and the segment's size in words (0 when the slot does not run).
@@ -119,54 +119,47 @@ __global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w) {
   }
 }
 
-// Stores the grown columns and rows of the workgroup's charts, one chart per
-// wavefront at a time (KT slices per axis).
+// Stores the grown columns and rows of the workgroup's charts (KT slices per
+// axis).  The work is split into items: chunk m of a chart covers grown
+// columns and grown rows [m (64 - p), (m + 1) (64 - p)), both evaluated in
+// the same pass; the wavefronts take items in turn, so a tall chart's chunks
+// run side by side.  s_ni is the exclusive prefix of the charts' item counts.
 template <int KT>
 __device__ void profile_charts(const Work& w, const ChartCache* cache, const int32_t* s_pc,
-                               const int32_t* s_pr, const int32_t* s_k, const int32_t* s_a,
-                               const int32_t* s_run, int p) {
+                               const int32_t* s_pr, const int32_t* s_k, const int32_t* s_ni,
+                               const int32_t* s_cols, int p) {
   constexpr int NJ = PROF_CH + 1;
   const int wv = threadIdx.x / WAVE, lane = lane_id(), step = WAVE - p;
-  for (int j = wv; j < NJ; j += PROF_NT / WAVE) {
-    const int32_t pc = s_pc[j];
-    if (pc < 0) continue;
-    // the chart before the block is only needed for its rows, and only when
-    // it belongs to the same atlas as the block's first chart
-    if (j == 0 && (s_a[0] != s_a[1] || (s_run[1] & 2))) continue;
-    const int k = s_k[j];
+  const int total = s_ni[NJ];
+  for (int it = wv; it < total; it += PROF_NT / WAVE) {
+    int j = 0;
+    while (s_ni[j + 1] <= it) ++j;
+    const int m = it - s_ni[j];
     const KView kv = kview(cache[j].kc, KT);
-    const Chart& ch = cache[j].ch;
     const KHead hd = khead_load(kv.hd);
     const int wt = hd.w, ht = hd.h;
-    if (j > 0) {
-      uint32_t* out = w.arena + pc;
-      for (int j0 = 0; j0 < wt + p; j0 += step) {
-        const int u = j0 - p + lane;
-        int32_t tp = BIG, bt = -BIG;
-        if (u >= 0 && u < wt) column_bounds<KT>(kv, ch, KT, k, u, tp, bt);
-        int32_t T = tp, Bo = bt, st = tp, sb = bt;
-        for (int q = 1; q <= p; ++q) {
-          st = wave_shr1(st, BIG);
-          sb = wave_shr1(sb, -BIG);
-          T = min(T, st);
-          Bo = max(Bo, sb);
-        }
-        if (lane >= p && u < wt + p) out[u] = pack16(T, Bo + p);
-      }
+    const int u = m * step - p + lane;  // undilated column and row of this lane
+    int32_t tp = BIG, bt = -BIG, l = BIG, r = -BIG;
+    {
+      int32_t t1, b1, l1, r1;
+      column_row_bounds<KT>(kv, cache[j].ch, s_k[j], u, u, t1, b1, l1, r1);
+      if (u >= 0 && u < wt) { tp = t1; bt = b1; }
+      if (u >= 0 && u < ht) { l = l1; r = r1; }
     }
-    uint32_t* out = w.arena + s_pr[j];
-    for (int j0 = 0; j0 < ht + p; j0 += step) {
-      const int u = j0 - p + lane;
-      int32_t l = BIG, r = -BIG;
-      if (u >= 0 && u < ht) row_bounds<KT>(kv, ch, KT, k, u, l, r);
-      int32_t L = l, R = r, sl = l, sr = r;
-      for (int q = 1; q <= p; ++q) {
-        sl = wave_shr1(sl, BIG);
-        sr = wave_shr1(sr, -BIG);
-        L = min(L, sl);
-        R = max(R, sr);
-      }
-      if (lane >= p && u < ht + p) out[u] = pack16(L, R + p);
+    int32_t T = tp, Bo = bt, L = l, R = r, st = tp, sb = bt, sl = l, sr = r;
+    for (int q = 1; q <= p; ++q) {
+      st = wave_shr1(st, BIG);
+      sb = wave_shr1(sb, -BIG);
+      sl = wave_shr1(sl, BIG);
+      sr = wave_shr1(sr, -BIG);
+      T = min(T, st);
+      Bo = max(Bo, sb);
+      L = min(L, sl);
+      R = max(R, sr);
+    }
+    if (lane >= p) {
+      if (s_cols[j] && u < wt + p) w.arena[s_pc[j] + u] = pack16(T, Bo + p);
+      if (u < ht + p) w.arena[s_pr[j] + u] = pack16(L, R + p);
     }
   }
 }
@@ -175,8 +168,10 @@ __device__ void profile_charts(const Work& w, const ChartCache* cache, const int
 // compacting distance and interlock flags of their pairs with the preceding
 // chart (Sec. 4.1.2; App. A "Detecting Interlocking Charts").  The charts'
 // records, and the record of the chart before the first, are copied to LDS
-// in one burst and their segment offsets loaded in parallel; each wavefront
-// evaluates charts from LDS.  Lane l of a chunk evaluates undilated column
+// in one burst and their segment offsets loaded in parallel; the wavefronts
+// evaluate chunks of them from LDS (charts are sorted by height, so few
+// charts per workgroup keep the tallest ones from forming one long
+// workgroup).  Lane l of a chunk evaluates undilated column
 // (row) u = j0 - p + l; the gutter growth over [u-p, u] comes from p
 // one-lane moves, so a chunk advances 64 - p entries (p <= 32).  After a barrier
 // the pairs read the rows just stored; pairs in segments without stored
@@ -184,7 +179,7 @@ __device__ void profile_charts(const Work& w, const ChartCache* cache, const int
 __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round) {
   constexpr int NJ = PROF_CH + 1;  // entry 0: the chart before the block's first
   __shared__ ChartCache cache[NJ];
-  __shared__ int32_t s_pc[NJ], s_pr[NJ], s_k[NJ], s_a[NJ], s_run[NJ];
+  __shared__ int32_t s_pc[NJ], s_pr[NJ], s_k[NJ], s_a[NJ], s_run[NJ], s_nc[NJ], s_ni[NJ + 1];
   const int tid = threadIdx.x, wv = tid / WAVE, lane = lane_id();
   const int s = blockIdx.y, cb = blockIdx.x * PROF_CH;
   if (tid < NJ) {
@@ -225,9 +220,25 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
   }
   __syncthreads();
   const int K = P.K, p = P.p;
-  if (K == 10) profile_charts<10>(w, cache, s_pc, s_pr, s_k, s_a, s_run, p);
-  else if (K == 5) profile_charts<5>(w, cache, s_pc, s_pr, s_k, s_a, s_run, p);
-  else profile_charts<2>(w, cache, s_pc, s_pr, s_k, s_a, s_run, p);
+  if (wv == 0) {  // work items per chart and their prefix
+    int ni = 0;
+    // the chart before the block is only needed for its rows, and only when
+    // it belongs to the same atlas as the block's first chart (its columns
+    // are stored by its own workgroup)
+    if (lane < NJ && s_pc[lane] >= 0 && !(lane == 0 && (s_a[0] != s_a[1] || (s_run[1] & 2)))) {
+      const KHead hd = khead_load(kview(cache[lane].kc, K).hd);
+      const int step = WAVE - p;
+      // rows: H >= W at every scale, so the row chunks cover the column ones
+      ni = (max(hd.h, lane > 0 ? hd.w : 0) + p + step - 1) / step;
+    }
+    const int incl = wave_incl_sum(ni);
+    if (lane < NJ) { s_nc[lane] = lane > 0; s_ni[lane + 1] = incl; }
+    if (lane == 0) s_ni[0] = 0;
+  }
+  __syncthreads();
+  if (K == 10) profile_charts<10>(w, cache, s_pc, s_pr, s_k, s_ni, s_nc, p);
+  else if (K == 5) profile_charts<5>(w, cache, s_pc, s_pr, s_k, s_ni, s_nc, p);
+  else profile_charts<2>(w, cache, s_pc, s_pr, s_k, s_ni, s_nc, p);
   __syncthreads();  // the block's stored rows are visible to all its wavefronts
   for (int j = 1 + wv; j < NJ; j += PROF_NT / WAVE) {
     const int run = s_run[j];

@@ -119,6 +119,24 @@ __host__ __device__ inline int64_t fdiv64(int64_t n, int64_t d) {
 }
 __host__ __device__ inline int64_t cdiv64(int64_t n, int64_t d) { return -fdiv64(-n, d); }
 
+// floor / ceil for any int64 n and d > 0, fast when the quotient is small:
+// the single-precision estimate (n and d rounded, an approximate reciprocal,
+// the product: relative error below 2^-21) is within 1/2 of n / d when
+// |n / d| < 2^20, so one correction makes its floor exact (n - q d cannot
+// overflow: |q d| <= |n| + d).  Other quotients take the 64-bit division.
+__device__ inline int64_t fdiv_i64(int64_t n, int64_t d) {
+  const float qf = floorf((float)n * __builtin_amdgcn_rcpf((float)d));
+  if (fabsf(qf) < 1048576.0f) {
+    int64_t q = (int64_t)(int32_t)qf;
+    const int64_t r = n - q * d;
+    if (r < 0) q -= 1;
+    else if (r >= d) q += 1;
+    return q;
+  }
+  return fdiv64(n, d);
+}
+__device__ inline int64_t cdiv_i64(int64_t n, int64_t d) { return -fdiv_i64(-n, d); }
+
 __device__ inline int32_t clamp32(int64_t v) {
   return (int32_t)(v < -(1 << 30) ? -(1 << 30) : (v > (1 << 30) ? (1 << 30) : v));
 }
@@ -154,16 +172,40 @@ __device__ inline KHead khead_load(const KHead* p) {
 // extent with n texels.  Line A applies left of (above) the corner, line B
 // right of (below) it; each line is (n0 + n1 * x) / d rounded down (lo sides)
 // or up (hi sides).
+// floor(P / d) in 32-bit arithmetic for |P| < 2^30 and 3196 <= d <= 2^14
+// (the OBB directions' rounded 2^14 cos / sin): |P / d| < 2^19, and the
+// single-precision estimate (P rounded, d exact, an approximate reciprocal
+// within one ulp, the product rounded: relative error below 2^-21) is
+// within 1/4 of P / d, so its floor is off by at most one and one
+// correction makes it exact.
+__device__ inline int32_t fdiv_i32(int32_t P, int32_t d) {
+  int32_t q = (int32_t)floorf((float)P * __builtin_amdgcn_rcpf((float)d));
+  const int32_t r = P - q * d;
+  q += r < 0 ? -1 : (r >= d ? 1 : 0);
+  return q;
+}
+
 // Branch-free: every lane selects its line first, so a wavefront whose
-// lanes straddle the corner still performs one division.
+// lanes straddle the corner still performs one division.  Every line has
+// n1 and d multiples of 2^14 (= QS), so with n0 = 2^14 M + L, 0 <= L < 2^14,
+//   floor((n0 + n1 x) / d) = floor((M + (n1 / 2^14) x) / (d / 2^14)),
+// because L < 2^14 cannot lift the numerator past the next multiple of d:
+// the whole evaluation fits 32 bits (|M| < 2^30, |n1 / 2^14| <= 2^14 and
+// |x| <= 2^15 + 64 bound the numerator by 2^30 + 2^29; larger values take
+// the 64-bit route).
 template <bool CEIL>
 __device__ inline int32_t side_value(const KSide& s, int32_t t, int32_t n, int64_t n0a, int64_t n1a,
                                      int64_t da, int64_t n0b, int64_t n1b, int64_t db) {
   const bool useA = t + 1 <= s.sa, useB = t >= s.sb;
   const int64_t n0 = useA ? n0a : n0b, n1 = useA ? n1a : n1b, d = useA ? da : db;
   const int64_t x = useA ? (int64_t)t + 1 : (int64_t)t;
-  const int64_t num = n0 + n1 * x;
-  const int32_t q = (int32_t)(CEIL ? -fdiv_q(-num, d) : fdiv_q(num, d));
+  // ceil(v / d) = -floor(-v / d)
+  const int64_t N0 = CEIL ? -n0 : n0, N1 = CEIL ? -n1 : n1;
+  const int64_t P = (N0 >> 14) + (N1 >> 14) * x;
+  int32_t q;
+  if (P > -(1ll << 30) && P < (1ll << 30)) q = fdiv_i32((int32_t)P, (int32_t)(d >> 14));
+  else q = (int32_t)fdiv_q(N0 + N1 * x, d);
+  if (CEIL) q = -q;
   return t == n - 1 ? s.last : ((useA || useB) ? q : s.corner);
 }
 
@@ -236,6 +278,50 @@ __device__ inline void row_rects(const KView& kv, int K, int j, int32_t& left, i
   }
   left = max(ly, lx);
   right = min(ry, rx);
+}
+
+// Column i and row j of the same chart at once (the profile sweep needs
+// both): every slice rectangle is loaded once and tested against both, and
+// the four OBB side values are independent of each other.
+template <int KT>
+__device__ inline void column_row_bounds(const KView& kv, const Chart& ch, int k, int i, int j,
+                                         int32_t& top, int32_t& bot, int32_t& left,
+                                         int32_t& right) {
+  constexpr int K = KT;
+  int32_t tx = BIG, bx = -BIG, ty = BIG, by = -BIG;
+  int32_t ly = BIG, ry = -BIG, lx = BIG, rx = -BIG;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    int32_t c0, c1, r0, r1;
+    krect_load(kv.rc + q, c0, c1, r0, r1);  // x-slice
+    const bool ci = c0 <= i && i < c1, rj = r0 <= j && j < r1;
+    tx = ci ? min(tx, r0) : tx;
+    bx = ci ? max(bx, r1) : bx;
+    lx = rj ? min(lx, c0) : lx;
+    rx = rj ? max(rx, c1) : rx;
+    krect_load(kv.rc + K + q, c0, c1, r0, r1);  // y-slice
+    const bool ci2 = c0 <= i && i < c1, rj2 = r0 <= j && j < r1;
+    ty = ci2 ? min(ty, r0) : ty;
+    by = ci2 ? max(by, r1) : by;
+    ly = rj2 ? min(ly, c0) : ly;
+    ry = rj2 ? max(ry, c1) : ry;
+  }
+  int32_t t = max(tx, ty), b = min(bx, by), l = max(ly, lx), rr = min(ry, rx);
+  const KHead hd = khead_load(kv.hd);
+  if (hd.obb) {
+    const int64_t C = kDirC[ch.m], S = kDirS[ch.m];
+    const int64_t kk = k;
+    const KSide s0 = kside_load(kv.sd + 0), s1 = kside_load(kv.sd + 1);
+    const KSide s2 = kside_load(kv.sd + 2), s3 = kside_load(kv.sd + 3);
+    t = max(t, side_value<false>(s0, i, hd.w, kk * ch.a, -QS * C, QS * S, kk * ch.e, QS * S, QS * C));
+    b = min(b, side_value<true>(s1, i, hd.w, kk * ch.f, QS * S, QS * C, kk * ch.b, -QS * C, QS * S));
+    l = max(l, side_value<false>(s2, j, hd.h, kk * ch.a, -QS * S, QS * C, -kk * ch.f, QS * C, QS * S));
+    rr = min(rr, side_value<true>(s3, j, hd.h, -kk * ch.e, QS * C, QS * S, kk * ch.b, -QS * S, QS * C));
+  }
+  top = t;
+  bot = b;
+  left = l;
+  right = rr;
 }
 
 // Undilated left / right bound of row j.
