@@ -280,6 +280,40 @@ __device__ inline void row_rects(const KView& kv, int K, int j, int32_t& left, i
   right = min(ry, rx);
 }
 
+// The two lines of an OBB side in 32-bit form: line value at x is
+// floor((M + n x) / d) (negated for a rounded-up side), from side_value's
+// (n0, n1, d) by the same exact reduction (M = n0 >> 14, n = n1 / 2^14,
+// d / 2^14).  ok is false when an M is too large for 32-bit evaluation
+// (|M| >= 2^29: a chart far larger than any atlas), then side_value is used.
+struct SideLines {
+  int32_t MA, nA, dA, MB, nB, dB;
+  bool ok;
+};
+template <bool CEIL>
+__device__ inline SideLines side_lines(int64_t n0a, int64_t n1a, int64_t da, int64_t n0b,
+                                       int64_t n1b, int64_t db) {
+  const int64_t MA = (CEIL ? -n0a : n0a) >> 14, MB = (CEIL ? -n0b : n0b) >> 14;
+  SideLines L;
+  L.ok = MA > -(1ll << 29) && MA < (1ll << 29) && MB > -(1ll << 29) && MB < (1ll << 29);
+  L.MA = (int32_t)MA;
+  L.MB = (int32_t)MB;
+  L.nA = (int32_t)((CEIL ? -n1a : n1a) >> 14);
+  L.nB = (int32_t)((CEIL ? -n1b : n1b) >> 14);
+  L.dA = (int32_t)(da >> 14);
+  L.dB = (int32_t)(db >> 14);
+  return L;
+}
+// side value at texel t (|t| <= 2^15 + 64, so |M + n x| < 2^31)
+template <bool CEIL>
+__device__ inline int32_t side_eval(const KSide& s, int32_t t, int32_t n, const SideLines& L) {
+  const bool useA = t + 1 <= s.sa, useB = t >= s.sb;
+  const int32_t M = useA ? L.MA : L.MB, nn = useA ? L.nA : L.nB, d = useA ? L.dA : L.dB;
+  const int32_t x = useA ? t + 1 : t;
+  int32_t q = fdiv_i32(M + nn * x, d);
+  if (CEIL) q = -q;
+  return t == n - 1 ? s.last : ((useA || useB) ? q : s.corner);
+}
+
 // Column i and row j of the same chart at once (the profile sweep needs
 // both): every slice rectangle is loaded once and tested against both, and
 // the four OBB side values are independent of each other.
@@ -313,10 +347,22 @@ __device__ inline void column_row_bounds(const KView& kv, const Chart& ch, int k
     const int64_t kk = k;
     const KSide s0 = kside_load(kv.sd + 0), s1 = kside_load(kv.sd + 1);
     const KSide s2 = kside_load(kv.sd + 2), s3 = kside_load(kv.sd + 3);
-    t = max(t, side_value<false>(s0, i, hd.w, kk * ch.a, -QS * C, QS * S, kk * ch.e, QS * S, QS * C));
-    b = min(b, side_value<true>(s1, i, hd.w, kk * ch.f, QS * S, QS * C, kk * ch.b, -QS * C, QS * S));
-    l = max(l, side_value<false>(s2, j, hd.h, kk * ch.a, -QS * S, QS * C, -kk * ch.f, QS * C, QS * S));
-    rr = min(rr, side_value<true>(s3, j, hd.h, -kk * ch.e, QS * C, QS * S, kk * ch.b, -QS * S, QS * C));
+    // the same lines as column_bounds / row_bounds
+    const SideLines L0 = side_lines<false>(kk * ch.a, -QS * C, QS * S, kk * ch.e, QS * S, QS * C);
+    const SideLines L1 = side_lines<true>(kk * ch.f, QS * S, QS * C, kk * ch.b, -QS * C, QS * S);
+    const SideLines L2 = side_lines<false>(kk * ch.a, -QS * S, QS * C, -kk * ch.f, QS * C, QS * S);
+    const SideLines L3 = side_lines<true>(-kk * ch.e, QS * C, QS * S, kk * ch.b, -QS * S, QS * C);
+    if (L0.ok && L1.ok && L2.ok && L3.ok) {
+      t = max(t, side_eval<false>(s0, i, hd.w, L0));
+      b = min(b, side_eval<true>(s1, i, hd.w, L1));
+      l = max(l, side_eval<false>(s2, j, hd.h, L2));
+      rr = min(rr, side_eval<true>(s3, j, hd.h, L3));
+    } else {
+      t = max(t, side_value<false>(s0, i, hd.w, kk * ch.a, -QS * C, QS * S, kk * ch.e, QS * S, QS * C));
+      b = min(b, side_value<true>(s1, i, hd.w, kk * ch.f, QS * S, QS * C, kk * ch.b, -QS * C, QS * S));
+      l = max(l, side_value<false>(s2, j, hd.h, kk * ch.a, -QS * S, QS * C, -kk * ch.f, QS * C, QS * S));
+      rr = min(rr, side_value<true>(s3, j, hd.h, -kk * ch.e, QS * C, QS * S, kk * ch.b, -QS * S, QS * C));
+    }
   }
   top = t;
   bot = b;
