@@ -326,14 +326,15 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
 }
 
 // one thread per (slot, chart)
-// The record of chart c at slot s, written to `base` (LDS).
-__device__ void setup_record(const Params& P, const Work& w, int round, int c, int s,
+// The record of chart c at slot s, written to `base` (LDS); false when the
+// chart does not run at this slot.
+__device__ bool setup_record(const Params& P, const Work& w, int round, int c, int s,
                              unsigned char* base) {
   const AtlasDesc d = w.desc[w.chart_atlas[c]];
   const bool run = P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1);
-  if (!run) return;
+  if (!run) return false;
   const int k = slot_k(P, d, round, s);
-  if (k < 1) return;
+  if (k < 1) return false;
   const Chart& ch = w.srecs[c];
   const int K = P.K;
   KHead* hd = reinterpret_cast<KHead*>(base);
@@ -369,7 +370,7 @@ __device__ void setup_record(const Params& P, const Work& w, int round, int c, i
     y.r1 = i16((((int64_t)(j + 1) * H * kk + QS * K - 1) >> 14) / K);
     rc[K + j] = y;
   }
-  if (!h.obb) return;
+  if (!h.obb) return true;
   const int64_t C = kDirC[ch.m], S = kDirS[ch.m], N = C * C + S * S, D = QS * N;
   const int64_t a = ch.a, b = ch.b, e = ch.e, f = ch.f;
   auto split = [&](int64_t num, KSide& sdv) {  // corner position num/D (texels)
@@ -416,6 +417,7 @@ __device__ void setup_record(const Params& P, const Work& w, int round, int c, i
   sd[1] = sb;
   sd[2] = sL;
   sd[3] = sR;
+  return true;
 }
 
 // Records are built in LDS by their threads and written out together with
@@ -426,8 +428,8 @@ __global__ __launch_bounds__(SETUP_NT) void k_setup(Params P, Work w, int round)
   __shared__ __align__(16) unsigned char s_rec[SETUP_NT * KREC_MAX];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
-  if (c < P.N) setup_record(P, w, round, c, s, s_rec + threadIdx.x * P.stride);
-  __syncthreads();
+  const bool active = c < P.N && setup_record(P, w, round, c, s, s_rec + threadIdx.x * P.stride);
+  if (!__syncthreads_or(active)) return;  // no chart of the block runs at this slot
   const int c0 = blockIdx.x * blockDim.x, nc = min(SETUP_NT, P.N - c0);
   const int n16 = nc * (P.stride / 16);
   const int4* src = reinterpret_cast<const int4*>(s_rec);

@@ -121,24 +121,35 @@ __global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w) {
 
 // Stores the grown columns and rows of the workgroup's charts (KT slices per
 // axis).  The work is split into items: chunk m of a chart covers grown
-// columns and grown rows [m (64 - p), (m + 1) (64 - p)), both evaluated in
-// the same pass; the wavefronts take items in turn, so a tall chart's chunks
-// run side by side.  s_ni is the exclusive prefix of the charts' item counts.
+// columns and grown rows [m (G - p), (m + 1) (G - p)), both evaluated in the
+// same pass by a group of G lanes (G = 16, 32 or 64, chosen per workgroup so
+// that small charts do not leave most of a wavefront idle); the wavefronts
+// take 64 / G items at a time, so a tall chart's chunks also run side by
+// side.  s_ni is the exclusive prefix of the charts' item counts.  The gutter
+// growth shifts values by one lane across the whole wavefront: a group's first
+// p lanes only feed the others and are never stored, so no value crosses from
+// one group into another's stored lanes.
 template <int KT>
 __device__ void profile_charts(const Work& w, const ChartCache* cache, const int32_t* s_pc,
                                const int32_t* s_pr, const int32_t* s_k, const int32_t* s_ni,
-                               const int32_t* s_cols, int p) {
+                               const int32_t* s_cols, int p, int G) {
   constexpr int NJ = PROF_CH + 1;
-  const int wv = threadIdx.x / WAVE, lane = lane_id(), step = WAVE - p;
+  const int wv = threadIdx.x / WAVE, lane = lane_id();
+  const int per = WAVE / G, gi = lane / G, gl = lane - gi * G, step = G - p;
   const int total = s_ni[NJ];
-  for (int it = wv; it < total; it += PROF_NT / WAVE) {
+  for (int it0 = wv * per; it0 < total; it0 += (PROF_NT / WAVE) * per) {
+    const int it = it0 + gi;
+    const bool live = it < total;
+    // lanes past the last item evaluate the last item again (never stored),
+    // so every lane reads a record that was copied
+    const int itc = live ? it : total - 1;
     int j = 0;
-    while (s_ni[j + 1] <= it) ++j;
-    const int m = it - s_ni[j];
+    while (s_ni[j + 1] <= itc) ++j;
+    const int m = itc - s_ni[j];
     const KView kv = kview(cache[j].kc, KT);
     const KHead hd = khead_load(kv.hd);
     const int wt = hd.w, ht = hd.h;
-    const int u = m * step - p + lane;  // undilated column and row of this lane
+    const int u = m * step - p + gl;  // undilated column and row of this lane
     int32_t tp = BIG, bt = -BIG, l = BIG, r = -BIG;
     {
       int32_t t1, b1, l1, r1;
@@ -157,7 +168,7 @@ __device__ void profile_charts(const Work& w, const ChartCache* cache, const int
       L = min(L, sl);
       R = max(R, sr);
     }
-    if (lane >= p) {
+    if (live && gl >= p) {
       if (s_cols[j] && u < wt + p) w.arena[s_pc[j] + u] = pack16(T, Bo + p);
       if (u < ht + p) w.arena[s_pr[j] + u] = pack16(L, R + p);
     }
@@ -179,7 +190,7 @@ __device__ void profile_charts(const Work& w, const ChartCache* cache, const int
 __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round) {
   constexpr int NJ = PROF_CH + 1;  // entry 0: the chart before the block's first
   __shared__ ChartCache cache[NJ];
-  __shared__ int32_t s_pc[NJ], s_pr[NJ], s_k[NJ], s_a[NJ], s_run[NJ], s_nc[NJ], s_ni[NJ + 1];
+  __shared__ int32_t s_pc[NJ], s_pr[NJ], s_k[NJ], s_a[NJ], s_run[NJ], s_nc[NJ], s_ni[NJ + 1], s_G;
   const int tid = threadIdx.x, wv = tid / WAVE, lane = lane_id();
   const int s = blockIdx.y, cb = blockIdx.x * PROF_CH;
   if (tid < NJ) {
@@ -205,11 +216,16 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
     s_a[tid] = a;
     s_run[tid] = run;
   }
+  // nothing to do when none of the block's charts runs at this slot (their
+  // atlas is finished or its scale is out of range): leave before any copy
+  const int active = tid >= 1 && tid < NJ && (s_run[tid] & 1);
+  if (!__syncthreads_or(active)) return;
   {
     const int nch = (int)(sizeof(Chart) / 16), nkc = P.stride / 16, per = nch + nkc;
     const int j0 = cb > 0 ? 0 : 1, j1 = min(NJ, P.N - cb + 1);
     for (int i = tid; i < (j1 - j0) * per; i += PROF_NT) {
       const int j = j0 + i / per, r = i % per, c = cb - 1 + j;
+      if (!(s_run[j] & 1)) continue;  // record not needed
       if (r < nch) {
         reinterpret_cast<int4*>(&cache[j].ch)[r] = reinterpret_cast<const int4*>(&w.srecs[c])[r];
       } else {
@@ -220,25 +236,33 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
   }
   __syncthreads();
   const int K = P.K, p = P.p;
-  if (wv == 0) {  // work items per chart and their prefix
-    int ni = 0;
+  if (wv == 0) {  // lane group size, work items per chart and their prefix
+    int e = 0;  // grown entries to evaluate (rows cover columns: h >= w)
     // the chart before the block is only needed for its rows, and only when
     // it belongs to the same atlas as the block's first chart (its columns
     // are stored by its own workgroup)
     if (lane < NJ && s_pc[lane] >= 0 && !(lane == 0 && (s_a[0] != s_a[1] || (s_run[1] & 2)))) {
       const KHead hd = khead_load(kview(cache[lane].kc, K).hd);
-      const int step = WAVE - p;
-      // rows: H >= W at every scale, so the row chunks cover the column ones
-      ni = (max(hd.h, lane > 0 ? hd.w : 0) + p + step - 1) / step;
+      e = max(hd.h, lane > 0 ? hd.w : 0) + p;
     }
+    // lanes spent per group size: sum of chunks x G; a group needs p <= G / 2
+    int G = WAVE;
+    int best = lane63(wave_incl_sum((e + WAVE - p - 1) / (WAVE - p))) * WAVE;
+    for (int g = 32; g >= 16; g >>= 1) {
+      if (2 * p > g) break;
+      const int cost = lane63(wave_incl_sum((e + g - p - 1) / (g - p))) * g;
+      if (cost < best) { best = cost; G = g; }
+    }
+    const int ni = (e + G - p - 1) / (G - p);
     const int incl = wave_incl_sum(ni);
     if (lane < NJ) { s_nc[lane] = lane > 0; s_ni[lane + 1] = incl; }
-    if (lane == 0) s_ni[0] = 0;
+    if (lane == 0) { s_ni[0] = 0; s_G = G; }
   }
   __syncthreads();
-  if (K == 10) profile_charts<10>(w, cache, s_pc, s_pr, s_k, s_ni, s_nc, p);
-  else if (K == 5) profile_charts<5>(w, cache, s_pc, s_pr, s_k, s_ni, s_nc, p);
-  else profile_charts<2>(w, cache, s_pc, s_pr, s_k, s_ni, s_nc, p);
+  const int G = s_G;
+  if (K == 10) profile_charts<10>(w, cache, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
+  else if (K == 5) profile_charts<5>(w, cache, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
+  else profile_charts<2>(w, cache, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
   __syncthreads();  // the block's stored rows are visible to all its wavefronts
   for (int j = 1 + wv; j < NJ; j += PROF_NT / WAVE) {
     const int run = s_run[j];
