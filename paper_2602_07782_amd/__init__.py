@@ -36,7 +36,8 @@ EXPORTS = ["tabi_pack", "tabi_pack_many", "tabi_pack_many_ws", "tabi_pack_many_w
            "tabi_pack_many_records", "tabi_debug_order", "tabi_debug_pairs",
            "tabi_debug_feasible", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
            "tabi_timing_enable", "tabi_timing_read", "tabi_timing_reset",
-           "tabi_debug_set_stage_cap", "tabi_debug_set_profile_cap"]
+           "tabi_debug_set_stage_cap", "tabi_debug_set_profile_cap", "tabi_tune_many",
+           "tabi_many_shape", "tabi_many_shape_count", "tabi_debug_set_many_shape"]
 STAGES = ["prep", "sort", "setup", "profile", "pack", "select"]
 
 
@@ -74,6 +75,11 @@ def lib():
         L.tabi_timing_reset.restype = None
         L.tabi_debug_set_stage_cap.argtypes = [i32]
         L.tabi_debug_set_profile_cap.argtypes = [ctypes.c_int64]
+        L.tabi_tune_many.argtypes = [vp, vp, vp, i32, vp, i32, i32, i32, i32, i32, vp, vp, vp, i32,
+                                     vp, vp, vp]
+        L.tabi_many_shape.argtypes = [i32, vp]
+        L.tabi_many_shape_count.restype = i32
+        L.tabi_debug_set_many_shape.argtypes = [i32, i32]
         _lib = L
     return _lib
 
@@ -173,6 +179,20 @@ class Batch:
         self.out_scale = torch.empty(self.count, dtype=torch.float32, device=self.xy.device)
         self.workspace = None
 
+    def tune(self, stream=None, reps=2):
+        """tabi_tune_many on this batch: times every candidate batched shape
+        and keeps the fastest for this quality on the device.  Returns
+        {"shape": (slots per round, threads, LDS cap), "ms": [per shape]}."""
+        n = int(lib().tabi_many_shape_count())
+        shape = (ctypes.c_int32 * 3)()
+        ms = (ctypes.c_float * n)()
+        _check(lib().tabi_tune_many(_ptr(self.xy), _ptr(self.voff), _ptr(self.aoff), self.count,
+                                    _ptr(self.wh), self.total, self.max_charts, self.max_side,
+                                    self.padding, self.quality, _ptr(self.out_xy),
+                                    _ptr(self.out_orient), _ptr(self.out_scale), int(reps), shape,
+                                    ms, _stream(stream)))
+        return {"shape": tuple(int(v) for v in shape), "ms": [round(float(v), 4) for v in ms]}
+
     def workspace_bytes(self):
         return int(lib().tabi_pack_many_workspace_bytes(self.count, self.total, self.max_charts,
                                                         self.max_side, self.padding, self.quality))
@@ -192,6 +212,18 @@ class Batch:
         else:
             _check(lib().tabi_pack_many(*args, _stream(stream)))
         return self.out_xy, self.out_orient, self.out_scale
+
+
+def many_shape(quality):
+    """Current batched shape (slots per round, threads, LDS cap) on this device."""
+    shape = (ctypes.c_int32 * 3)()
+    _check(lib().tabi_many_shape(int(quality), shape))
+    return tuple(int(v) for v in shape)
+
+
+def debug_set_many_shape(quality, index):
+    """Force candidate batched shape `index` (-1: default); results are unchanged."""
+    _check(lib().tabi_debug_set_many_shape(int(quality), int(index)))
 
 
 def pack_many(inputs, stream=None, device="cuda", use_workspace=False):

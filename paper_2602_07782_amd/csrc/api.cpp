@@ -211,6 +211,7 @@ Params make_params(int count, int N, int q, int p, int B, int fixed_k, int nmax,
   P.nmax = nmax;
   P.Wdmax = Wdmax;
   P.arena_cap = 0;
+  P.pack_nt = 0;
   P.arena_cap = arena_words(P);
   return P;
 }
@@ -304,9 +305,33 @@ hipError_t run_search(Job& j, int rounds, int32_t* out_xy, uint8_t* out_orient, 
   return e;
 }
 
-// batched shape: scale slots per round and the LDS cap (two workgroups per CU)
-constexpr int kManySlots = 8;
-constexpr int kManyLdsCap = 78 * 1024;
+// Batched shape: scale slots per round, fold-and-push workgroup size, and
+// the shared-memory cap of that workgroup (78 KB lets two 512-thread
+// workgroups share a CU; 0 = the device limit).  Chosen per device and
+// quality by tabi_tune_many; the first entry is the default.
+struct ManyShape {
+  int B, nt, cap;
+};
+const ManyShape kManyShapes[] = {{8, 512, 78 * 1024}, {4, 512, 78 * 1024}, {16, 512, 78 * 1024},
+                                 {8, 1024, 0},        {16, 1024, 0}};
+constexpr int kNumManyShapes = (int)(sizeof(kManyShapes) / sizeof(kManyShapes[0]));
+std::mutex g_shape_mu;
+int g_shape[64][3] = {};  // [device][quality]: index + 1 into kManyShapes, 0 = default
+
+ManyShape many_shape(int quality) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || quality < 0 || quality > 2)
+    return kManyShapes[0];
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  const int i = g_shape[dev][quality];
+  return i > 0 ? kManyShapes[i - 1] : kManyShapes[0];
+}
+void set_many_shape(int quality, int index) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || quality < 0 || quality > 2) return;
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  g_shape[dev][quality] = index + 1;
+}
 
 int many_check(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
                int32_t count, const int32_t* atlas_wh, int32_t total_charts, int32_t max_charts,
@@ -324,8 +349,11 @@ int many_check(const int32_t* xy, const int32_t* vert_offsets, const int32_t* at
 
 Params many_params(int32_t count, int32_t total_charts, int32_t max_charts, int32_t max_side,
                    int32_t padding, int32_t quality) {
-  return make_params(count, total_charts, quality, padding, kManySlots, 0,
-                     max_charts > 0 ? max_charts : 1, max_side + padding);
+  const ManyShape sh = many_shape(quality);
+  Params P = make_params(count, total_charts, quality, padding, sh.B, 0,
+                         max_charts > 0 ? max_charts : 1, max_side + padding);
+  P.pack_nt = sh.nt;
+  return P;
 }
 
 int pack_many_impl(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
@@ -341,8 +369,9 @@ int pack_many_impl(const int32_t* xy, const int32_t* vert_offsets, const int32_t
   if (count == 0) return TABI_OK;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Job j;
+  const ManyShape sh = many_shape(quality);
   rc = make_job(j, many_params(count, total_charts, max_charts, max_side, padding, quality), st,
-                ws, ws_bytes, kManyLdsCap);
+                ws, ws_bytes, sh.cap);
   if (rc) {
     free_job(j, st);
     return rc;
@@ -361,7 +390,7 @@ int pack_many_impl(const int32_t* xy, const int32_t* vert_offsets, const int32_t
   } else {
     e = run_front(j, xy, vert_offsets, atlas_offsets, atlas_wh, 0, 0, st);
   }
-  if (e == hipSuccess) e = run_search(j, (64 + kManySlots - 1) / kManySlots, out_xy, out_orient,
+  if (e == hipSuccess) e = run_search(j, (64 + j.P.B - 1) / j.P.B, out_xy, out_orient,
                                       out_scale, st);
   if (e != hipSuccess) rc = hip_fail(e);
   free_job(j, st);
@@ -405,6 +434,77 @@ int tabi_pack_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t
   return pack_many_impl(xy, vert_offsets, atlas_offsets, count, atlas_wh, total_charts, max_charts,
                         max_side, padding, quality, out_xy, out_orient, out_scale, nullptr, 0,
                         stream);
+}
+
+int tabi_tune_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
+                   int32_t count, const int32_t* atlas_wh, int32_t total_charts,
+                   int32_t max_charts, int32_t max_side, int32_t padding, int32_t quality,
+                   int32_t* out_xy, uint8_t* out_orient, float* out_scale, int32_t reps,
+                   int32_t* shape, float* ms_per_shape, tabi_stream_t stream) {
+  int rc = many_check(xy, vert_offsets, atlas_offsets, count, atlas_wh, total_charts, max_charts,
+                      max_side, padding, quality, out_xy, out_orient, out_scale);
+  if (rc) return rc;
+  if (count == 0 || reps < 1) return TABI_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(e);
+  int best = -1;
+  float best_ms = 0.f;
+  for (int i = 0; i < kNumManyShapes && rc == TABI_OK; ++i) {
+    set_many_shape(quality, i);
+    // one untimed call (pool growth, first launches), then reps timed ones
+    rc = pack_many_impl(xy, vert_offsets, atlas_offsets, count, atlas_wh, total_charts, max_charts,
+                        max_side, padding, quality, out_xy, out_orient, out_scale, nullptr, 0,
+                        stream);
+    if (rc == TABI_EINVAL) {  // this shape cannot hold the batch's rows; skip it
+      rc = TABI_OK;
+      if (ms_per_shape) ms_per_shape[i] = -1.f;
+      continue;
+    }
+    if (rc) break;
+    e = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && rc == TABI_OK && e == hipSuccess; ++r)
+      rc = pack_many_impl(xy, vert_offsets, atlas_offsets, count, atlas_wh, total_charts,
+                          max_charts, max_side, padding, quality, out_xy, out_orient, out_scale,
+                          nullptr, 0, stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) { rc = hip_fail(e); break; }
+    ms /= (float)reps;
+    if (ms_per_shape) ms_per_shape[i] = ms;
+    if (best < 0 || ms < best_ms) { best = i; best_ms = ms; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  set_many_shape(quality, best >= 0 ? best : 0);
+  if (rc == TABI_OK && best < 0) rc = TABI_EINVAL;
+  if (rc == TABI_OK && shape) {
+    shape[0] = kManyShapes[best].B;
+    shape[1] = kManyShapes[best].nt;
+    shape[2] = kManyShapes[best].cap;
+  }
+  return rc;
+}
+
+int tabi_many_shape(int32_t quality, int32_t* shape) {
+  if (!shape || quality < 0 || quality > 2) return TABI_EINVAL;
+  const ManyShape sh = many_shape(quality);
+  shape[0] = sh.B;
+  shape[1] = sh.nt;
+  shape[2] = sh.cap;
+  return TABI_OK;
+}
+
+int32_t tabi_many_shape_count(void) { return kNumManyShapes; }
+
+int tabi_debug_set_many_shape(int32_t quality, int32_t index) {
+  if (quality < 0 || quality > 2 || index >= kNumManyShapes) return TABI_EINVAL;
+  set_many_shape(quality, index < 0 ? 0 : index);
+  return TABI_OK;
 }
 
 int64_t tabi_pack_many_workspace_bytes(int32_t count, int32_t total_charts, int32_t max_charts,

@@ -635,8 +635,8 @@ hipError_t pack_set_max_lds(int bytes) {
 
 hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes, int RC, int PW,
                        int stage_cap, hipStream_t st) {
-  // one atlas: latency matters, use the wider workgroup
-  if (P.count == 1)
+  // one atlas: latency matters, use the wider workgroup (batches: as tuned)
+  if (P.pack_nt == 1024 || (P.pack_nt == 0 && P.count == 1))
     hipLaunchKernelGGL(k_pack<1024>, dim3(P.B, P.count), dim3(1024), lds_bytes, st, P, w, round,
                        RC, PW, stage_cap);
   else

@@ -31,6 +31,7 @@ struct Params {
   int32_t nmax;        // largest chart count of one atlas the work space was sized for
   int32_t Wdmax;       // largest grown atlas width the shared memory was sized for
   int64_t arena_cap;   // 32-bit words of the profile arena (0: no stored profiles)
+  int32_t pack_nt;     // fold-and-push workgroup size: 512, 1024, or 0 (by atlas count)
 };
 
 // Work-space views (device pointers).

@@ -105,3 +105,44 @@ def test_graph_capture_replay(tabi):
         assert torch.equal(batch.out_xy, ref[0]), rep
         assert torch.equal(batch.out_orient, ref[1]), rep
         assert torch.equal(batch.out_scale, ref[2]), rep
+
+
+def test_every_batched_shape_gives_the_same_results(tabi, orc):
+    """Each candidate shape of the batched path (slots per round, workgroup
+    size, LDS cap) packs the batch identically, and equals the oracle."""
+    inputs = small_batch(8, 930)
+    q = inputs[0].quality
+    first = None
+    try:
+        for idx in range(int(tabi.lib().tabi_many_shape_count())):
+            tabi.debug_set_many_shape(q, idx)
+            _say("shape", idx, tabi.many_shape(q))
+            out = [t.cpu().numpy() for t in tabi.pack_many(inputs)]
+            if first is None:
+                first = out
+                check_batch(tabi, orc, inputs)
+            else:
+                for x, y in zip(out, first):
+                    assert np.array_equal(x, y), idx
+    finally:
+        tabi.debug_set_many_shape(q, -1)
+
+
+def test_tuner_keeps_results(tabi):
+    """tabi_tune_many times the candidate shapes, keeps the fastest, and
+    later batched calls (plain and work-space) still give the same results."""
+    inputs = small_batch(6, 931)
+    q = inputs[0].quality
+    try:
+        ref = [t.cpu().numpy() for t in tabi.pack_many(inputs)]
+        batch = tabi.Batch(inputs)
+        res = batch.tune(reps=1)
+        _say("tuned", res)
+        assert res["shape"] == tabi.many_shape(q)
+        assert min(m for m in res["ms"] if m >= 0) > 0
+        for use_ws in (False, True):
+            out = [t.cpu().numpy() for t in tabi.Batch(inputs).run(use_workspace=use_ws)]
+            for x, y in zip(out, ref):
+                assert np.array_equal(x, y), use_ws
+    finally:
+        tabi.debug_set_many_shape(q, -1)
