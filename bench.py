@@ -130,13 +130,27 @@ def served_leg(seconds=1.0, rate=2000.0):
     pst = serve.latency_stats(plain)
     same = all(a.result[2] == b.result[2] and np.array_equal(a.result[0], b.result[0]) and
                np.array_equal(a.result[1], b.result[1]) for a, b in zip(reqs, plain))
+    # capacity: the same requests all waiting at once (no arrival pacing), so
+    # the rate is what each path can sustain rather than the trace's 2,000/s
+    sat = [copy.copy(r) for r in reqs]
+    splain = [copy.copy(r) for r in reqs]
+    for r in sat + splain:
+        r.done, r.result = -1.0, None
+    swall = serve.Server().run(sat, realtime=False)
+    spwall = serve.serve_plain(splain, realtime=False)
+    same &= all(a.result[2] == b.result[2] and np.array_equal(a.result[0], b.result[0])
+                for a, b in zip(sat, plain))
     return {"requests": len(reqs), "rate_per_s": rate,
             "repacks": int(sum(r.replaced is not None for r in reqs)),
             "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
             "atlases_per_s": round(len(reqs) / wall, 2),
             "plain_p50_ms": round(pst["p50_ms"], 3), "plain_p99_ms": round(pst["p99_ms"], 3),
             "plain_atlases_per_s": round(len(plain) / pwall, 2),
-            "speedup_vs_plain": round(pwall / wall, 2), "bitexact_vs_alone": bool(same)}
+            "speedup_vs_plain": round(pwall / wall, 2),
+            "capacity_atlases_per_s": round(len(sat) / swall, 2),
+            "plain_capacity_atlases_per_s": round(len(splain) / spwall, 2),
+            "capacity_speedup_vs_plain": round(spwall / swall, 2),
+            "bitexact_vs_alone": bool(same)}
 
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",

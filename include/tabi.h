@@ -132,9 +132,10 @@ int tabi_pack_many_ws(const int32_t* xy, const int32_t* vert_offsets,
  * tabi_tune_many packs the given batch (arguments as tabi_pack_many) once
  * untimed and `reps` times timed with HIP events on `stream` for each of the
  * tabi_many_shape_count() candidate shapes, keeps the fastest as the shape of
- * later tabi_pack_many / _ws / _records calls with this quality on the
- * current device, and writes it to shape[3] = {B, threads, LDS cap bytes (0:
- * device limit)}; ms_per_shape (may be NULL) receives the mean milliseconds
+ * later tabi_pack_many / _ws / _records calls with this quality and a batch
+ * of the same size class (up to 8 atlases, up to 64, more) on the current
+ * device, and writes it to shape[3] = {B, threads, LDS cap bytes (0: device
+ * limit)}; ms_per_shape (may be NULL) receives the mean milliseconds
  * per call of each candidate (-1 for a shape the batch's rows do not fit).
  * Synchronizes `stream`.  A workspace sized with
  * tabi_pack_many_workspace_bytes before tuning must be sized again after it
@@ -146,14 +147,15 @@ int tabi_tune_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t
                    int32_t* out_xy, uint8_t* out_orient, float* out_scale, int32_t reps,
                    int32_t* shape, float* ms_per_shape, tabi_stream_t stream);
 
-/* Current batched shape for `quality` on the current device (shape[3] as
- * above); the number of candidate shapes the tuner tries. */
-int tabi_many_shape(int32_t quality, int32_t* shape);
+/* Current batched shape for `quality` and a batch of `count` atlases on the
+ * current device (shape[3] as above); the number of candidate shapes the
+ * tuner tries. */
+int tabi_many_shape(int32_t quality, int32_t count, int32_t* shape);
 int32_t tabi_many_shape_count(void);
 
 /* Test knob: make candidate shape `index` (0 .. tabi_many_shape_count()-1;
- * negative: the default, index 0) the batched shape for `quality` on the
- * current device. */
+ * negative: the default, index 0) the batched shape for `quality` and every
+ * batch size on the current device. */
 int tabi_debug_set_many_shape(int32_t quality, int32_t index);
 
 /* ---- resident proxies (incremental re-packs) ----------------------------

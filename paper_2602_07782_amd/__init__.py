@@ -77,7 +77,7 @@ def lib():
         L.tabi_debug_set_profile_cap.argtypes = [ctypes.c_int64]
         L.tabi_tune_many.argtypes = [vp, vp, vp, i32, vp, i32, i32, i32, i32, i32, vp, vp, vp, i32,
                                      vp, vp, vp]
-        L.tabi_many_shape.argtypes = [i32, vp]
+        L.tabi_many_shape.argtypes = [i32, i32, vp]
         L.tabi_many_shape_count.restype = i32
         L.tabi_debug_set_many_shape.argtypes = [i32, i32]
         _lib = L
@@ -214,10 +214,11 @@ class Batch:
         return self.out_xy, self.out_orient, self.out_scale
 
 
-def many_shape(quality):
-    """Current batched shape (slots per round, threads, LDS cap) on this device."""
+def many_shape(quality, count=256):
+    """Current batched shape (slots per round, threads, LDS cap) on this device
+    for a batch of `count` atlases."""
     shape = (ctypes.c_int32 * 3)()
-    _check(lib().tabi_many_shape(int(quality), shape))
+    _check(lib().tabi_many_shape(int(quality), int(count), shape))
     return tuple(int(v) for v in shape)
 
 

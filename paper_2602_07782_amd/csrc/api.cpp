@@ -315,22 +315,28 @@ struct ManyShape {
 const ManyShape kManyShapes[] = {{8, 512, 78 * 1024}, {4, 512, 78 * 1024}, {16, 512, 78 * 1024},
                                  {8, 1024, 0},        {16, 1024, 0}};
 constexpr int kNumManyShapes = (int)(sizeof(kManyShapes) / sizeof(kManyShapes[0]));
+// batch size classes: up to 8 atlases, up to 64, more
+constexpr int kShapeClasses = 3;
+int shape_class(int count) { return count <= 8 ? 0 : (count <= 64 ? 1 : 2); }
 std::mutex g_shape_mu;
-int g_shape[64][3] = {};  // [device][quality]: index + 1 into kManyShapes, 0 = default
+// [device][quality][class]: index + 1 into kManyShapes, 0 = default
+int g_shape[64][3][kShapeClasses] = {};
 
-ManyShape many_shape(int quality) {
+ManyShape many_shape(int quality, int count) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || quality < 0 || quality > 2)
     return kManyShapes[0];
   std::lock_guard<std::mutex> lk(g_shape_mu);
-  const int i = g_shape[dev][quality];
+  const int i = g_shape[dev][quality][shape_class(count)];
   return i > 0 ? kManyShapes[i - 1] : kManyShapes[0];
 }
-void set_many_shape(int quality, int index) {
+// cls < 0: every size class
+void set_many_shape(int quality, int cls, int index) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || quality < 0 || quality > 2) return;
   std::lock_guard<std::mutex> lk(g_shape_mu);
-  g_shape[dev][quality] = index + 1;
+  for (int c = 0; c < kShapeClasses; ++c)
+    if (cls < 0 || c == cls) g_shape[dev][quality][c] = index + 1;
 }
 
 int many_check(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
@@ -349,7 +355,7 @@ int many_check(const int32_t* xy, const int32_t* vert_offsets, const int32_t* at
 
 Params many_params(int32_t count, int32_t total_charts, int32_t max_charts, int32_t max_side,
                    int32_t padding, int32_t quality) {
-  const ManyShape sh = many_shape(quality);
+  const ManyShape sh = many_shape(quality, count);
   Params P = make_params(count, total_charts, quality, padding, sh.B, 0,
                          max_charts > 0 ? max_charts : 1, max_side + padding);
   P.pack_nt = sh.nt;
@@ -369,7 +375,7 @@ int pack_many_impl(const int32_t* xy, const int32_t* vert_offsets, const int32_t
   if (count == 0) return TABI_OK;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Job j;
-  const ManyShape sh = many_shape(quality);
+  const ManyShape sh = many_shape(quality, count);
   rc = make_job(j, many_params(count, total_charts, max_charts, max_side, padding, quality), st,
                 ws, ws_bytes, sh.cap);
   if (rc) {
@@ -453,7 +459,7 @@ int tabi_tune_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t
   int best = -1;
   float best_ms = 0.f;
   for (int i = 0; i < kNumManyShapes && rc == TABI_OK; ++i) {
-    set_many_shape(quality, i);
+    set_many_shape(quality, shape_class(count), i);
     // one untimed call (pool growth, first launches), then reps timed ones
     rc = pack_many_impl(xy, vert_offsets, atlas_offsets, count, atlas_wh, total_charts, max_charts,
                         max_side, padding, quality, out_xy, out_orient, out_scale, nullptr, 0,
@@ -480,7 +486,7 @@ int tabi_tune_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  set_many_shape(quality, best >= 0 ? best : 0);
+  set_many_shape(quality, shape_class(count), best >= 0 ? best : 0);
   if (rc == TABI_OK && best < 0) rc = TABI_EINVAL;
   if (rc == TABI_OK && shape) {
     shape[0] = kManyShapes[best].B;
@@ -490,9 +496,9 @@ int tabi_tune_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t
   return rc;
 }
 
-int tabi_many_shape(int32_t quality, int32_t* shape) {
-  if (!shape || quality < 0 || quality > 2) return TABI_EINVAL;
-  const ManyShape sh = many_shape(quality);
+int tabi_many_shape(int32_t quality, int32_t count, int32_t* shape) {
+  if (!shape || quality < 0 || quality > 2 || count < 0) return TABI_EINVAL;
+  const ManyShape sh = many_shape(quality, count);
   shape[0] = sh.B;
   shape[1] = sh.nt;
   shape[2] = sh.cap;
@@ -503,7 +509,7 @@ int32_t tabi_many_shape_count(void) { return kNumManyShapes; }
 
 int tabi_debug_set_many_shape(int32_t quality, int32_t index) {
   if (quality < 0 || quality > 2 || index >= kNumManyShapes) return TABI_EINVAL;
-  set_many_shape(quality, index < 0 ? 0 : index);
+  set_many_shape(quality, -1, index < 0 ? 0 : index);
   return TABI_OK;
 }
 

@@ -116,7 +116,7 @@ def test_every_batched_shape_gives_the_same_results(tabi, orc):
     try:
         for idx in range(int(tabi.lib().tabi_many_shape_count())):
             tabi.debug_set_many_shape(q, idx)
-            _say("shape", idx, tabi.many_shape(q))
+            _say("shape", idx, tabi.many_shape(q, len(inputs)))
             out = [t.cpu().numpy() for t in tabi.pack_many(inputs)]
             if first is None:
                 first = out
@@ -138,7 +138,7 @@ def test_tuner_keeps_results(tabi):
         batch = tabi.Batch(inputs)
         res = batch.tune(reps=1)
         _say("tuned", res)
-        assert res["shape"] == tabi.many_shape(q)
+        assert res["shape"] == tabi.many_shape(q, len(inputs))
         assert min(m for m in res["ms"] if m >= 0) > 0
         for use_ws in (False, True):
             out = [t.cpu().numpy() for t in tabi.Batch(inputs).run(use_workspace=use_ws)]
