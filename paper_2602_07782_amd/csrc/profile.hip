@@ -31,6 +31,144 @@ constexpr int ALLOC_NT = 1024;
 constexpr int PROF_NT = 256;
 constexpr int PROF_CH = 16;  // charts per profile workgroup
 
+// ---- a chart's per-scale record in the form the profile sweep evaluates ----
+// Each slice rectangle (columns [c0, c1) x rows [r0, r1)) as pairs of 16-bit
+// values, so that one set of two-lane integer operations tests an entry's
+// column i and row j against it together:
+//   lo = (c0, r0), hi = (c1 - 1, r1 - 1): i lies in [c0, c1) iff i - c0 and
+//   c1 - 1 - i are both >= 0, i.e. the sign bit of their OR is clear (the
+//   same for j and the rows);
+//   vmin = (r0, c0), vmax = (r1, c1), offset by 2^15 so that unsigned 16-bit
+//   min / max order them as the signed values: what the rectangle gives the
+//   column's top and the row's left (min), the column's bottom and the row's
+//   right (max).
+// A chart of at most 16384 texels per side at the scale keeps every value
+// and difference within 16 bits (entries lie in [-32, 16416)); larger charts,
+// and OBB lines that need 64 bits, take the general evaluation.
+struct alignas(16) SweepRect {
+  uint32_t lo, hi, vmin, vmax;
+};
+// An OBB side: split points, corner and last values, both lines in 32-bit
+// form, and the single-precision reciprocals of their divisors (those the
+// division takes, computed once).
+struct alignas(16) SweepSide {
+  int32_t sa, sb, corner, last;
+  int32_t MA, nA, dA, MB, nB, dB;
+  float rA, rB;
+};
+enum { SWEEP_AABB = 0, SWEEP_OBB = 1, SWEEP_GENERAL = 2 };
+struct alignas(16) SweepRec {
+  SweepRect rc[2 * KMAX];  // x-slices, then y-slices
+  SweepSide sd[4];         // top, bottom, left, right
+  int32_t mode, w, h, pad;
+};
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline uint32_t pair16(int32_t a, int32_t b) {
+  return (uint32_t)(uint16_t)a | ((uint32_t)(uint16_t)b << 16);
+}
+
+// Slice rectangle q of the chart (x-slices q < K, y-slices K + q) in sweep form.
+__device__ inline SweepRect sweep_rect_of(const KView& kv, int q) {
+  int32_t c0, c1, r0, r1;
+  krect_load(kv.rc + q, c0, c1, r0, r1);
+  SweepRect r;
+  r.lo = pair16(c0, r0);
+  r.hi = pair16(c1 - 1, r1 - 1);
+  r.vmin = pair16(r0 ^ 0x8000, c0 ^ 0x8000);
+  r.vmax = pair16(r1 ^ 0x8000, c1 ^ 0x8000);
+  return r;
+}
+
+// The four OBB sides' lines (as column_row_bounds forms them) and the
+// evaluation mode of the chart.
+__device__ inline void sweep_sides_of(const KView& kv, const Chart& ch, int k, SweepRec& R) {
+  const KHead hd = khead_load(kv.hd);
+  const int64_t C = kDirC[ch.m], S = kDirS[ch.m], kk = k;
+  SideLines L[4];
+  L[0] = side_lines<false>(kk * ch.a, -QS * C, QS * S, kk * ch.e, QS * S, QS * C);
+  L[1] = side_lines<true>(kk * ch.f, QS * S, QS * C, kk * ch.b, -QS * C, QS * S);
+  L[2] = side_lines<false>(kk * ch.a, -QS * S, QS * C, -kk * ch.f, QS * C, QS * S);
+  L[3] = side_lines<true>(-kk * ch.e, QS * C, QS * S, kk * ch.b, -QS * S, QS * C);
+  bool ok = hd.w <= 16384 && hd.h <= 16384;
+  for (int s = 0; s < 4; ++s) {
+    const KSide ks = kside_load(kv.sd + s);
+    SweepSide& o = R.sd[s];
+    o.sa = ks.sa;
+    o.sb = ks.sb;
+    o.corner = ks.corner;
+    o.last = ks.last;
+    o.MA = L[s].MA; o.nA = L[s].nA; o.dA = L[s].dA;
+    o.MB = L[s].MB; o.nB = L[s].nB; o.dB = L[s].dB;
+    o.rA = __builtin_amdgcn_rcpf((float)L[s].dA);
+    o.rB = __builtin_amdgcn_rcpf((float)L[s].dB);
+    if (hd.obb) ok = ok && L[s].ok;
+  }
+  R.mode = !ok ? SWEEP_GENERAL : (hd.obb ? SWEEP_OBB : SWEEP_AABB);
+  R.w = hd.w;
+  R.h = hd.h;
+}
+
+// side_eval with the line data and reciprocal read from the sweep record
+template <bool CEIL>
+__device__ inline int32_t sweep_side(const SweepSide& s, int32_t t, int32_t n) {
+  const bool useA = t + 1 <= s.sa, useB = t >= s.sb;
+  const int32_t M = useA ? s.MA : s.MB, nn = useA ? s.nA : s.nB, d = useA ? s.dA : s.dB;
+  const float rc = useA ? s.rA : s.rB;
+  const int32_t P = M + nn * (useA ? t + 1 : t);
+  int32_t q = (int32_t)floorf((float)P * rc);
+  const int32_t r = P - q * d;
+  q += r < 0 ? -1 : (r >= d ? 1 : 0);
+  if (CEIL) q = -q;
+  return t == n - 1 ? s.last : ((useA || useB) ? q : s.corner);
+}
+
+// Top / bottom of column u and left / right of row u, as column_row_bounds
+// computes them, from the sweep record (mode SWEEP_AABB or SWEEP_OBB).
+template <int KT>
+__device__ inline void sweep_bounds(const SweepRec& R, int32_t u, int32_t& top, int32_t& bot,
+                                    int32_t& left, int32_t& right) {
+  const s16x2 ij = {(short)u, (short)u};
+  // (top, left) minima and (bottom, right) maxima of the x- and y-slices;
+  // 0xffff / 0 mean no rectangle contains the column (row)
+  u16x2 mnx = {0xffff, 0xffff}, mxx = {0, 0}, mny = {0xffff, 0xffff}, mxy = {0, 0};
+#pragma unroll
+  for (int q = 0; q < 2 * KT; ++q) {
+    const uint4 v = *reinterpret_cast<const uint4*>(&R.rc[q]);
+    const s16x2 d = (ij - __builtin_bit_cast(s16x2, v.x)) | (__builtin_bit_cast(s16x2, v.y) - ij);
+    // 0xffff where outside, 0 inside; a saturating add / subtract turns the
+    // contribution into the accumulator's neutral value outside
+    const u16x2 out = __builtin_bit_cast(u16x2, (s16x2)(d >> 15));
+    const u16x2 cmin = __builtin_elementwise_add_sat(__builtin_bit_cast(u16x2, v.z), out);
+    const u16x2 cmax = __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, v.w), out);
+    if (q < KT) {
+      mnx = __builtin_elementwise_min(mnx, cmin);
+      mxx = __builtin_elementwise_max(mxx, cmax);
+    } else {
+      mny = __builtin_elementwise_min(mny, cmin);
+      mxy = __builtin_elementwise_max(mxy, cmax);
+    }
+  }
+  // top = max(x, y tops), left = max(y, x lefts); bottom / right = min
+  const u16x2 tl = __builtin_elementwise_max(mnx, mny), br = __builtin_elementwise_min(mxx, mxy);
+  int32_t t = tl.x == 0xffff ? BIG : (int32_t)tl.x - 0x8000;
+  int32_t l = tl.y == 0xffff ? BIG : (int32_t)tl.y - 0x8000;
+  int32_t b = br.x == 0 ? -BIG : (int32_t)br.x - 0x8000;
+  int32_t r = br.y == 0 ? -BIG : (int32_t)br.y - 0x8000;
+  if (R.mode == SWEEP_OBB) {
+    t = max(t, sweep_side<false>(R.sd[0], u, R.w));
+    b = min(b, sweep_side<true>(R.sd[1], u, R.w));
+    l = max(l, sweep_side<false>(R.sd[2], u, R.h));
+    r = min(r, sweep_side<true>(R.sd[3], u, R.h));
+  }
+  top = t;
+  bot = b;
+  left = l;
+  right = r;
+}
+
 // Offsets of every chart's grown columns and rows within its (atlas, slot)
 // segment, and the segment's size in words (0 when the slot does not run).
 __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) {
@@ -130,9 +268,9 @@ __global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w) {
 // p lanes only feed the others and are never stored, so no value crosses from
 // one group into another's stored lanes.
 template <int KT>
-__device__ void profile_charts(const Work& w, const ChartCache* cache, const int32_t* s_pc,
-                               const int32_t* s_pr, const int32_t* s_k, const int32_t* s_ni,
-                               const int32_t* s_cols, int p, int G) {
+__device__ void profile_charts(const Work& w, const ChartCache* cache, const SweepRec* sw,
+                               const int32_t* s_pc, const int32_t* s_pr, const int32_t* s_k,
+                               const int32_t* s_ni, const int32_t* s_cols, int p, int G) {
   constexpr int NJ = PROF_CH + 1;
   const int wv = threadIdx.x / WAVE, lane = lane_id();
   const int per = WAVE / G, gi = lane / G, gl = lane - gi * G, step = G - p;
@@ -146,14 +284,16 @@ __device__ void profile_charts(const Work& w, const ChartCache* cache, const int
     int j = 0;
     while (s_ni[j + 1] <= itc) ++j;
     const int m = itc - s_ni[j];
-    const KView kv = kview(cache[j].kc, KT);
-    const KHead hd = khead_load(kv.hd);
-    const int wt = hd.w, ht = hd.h;
+    const SweepRec& rec = sw[j];
+    const int wt = rec.w, ht = rec.h;
     const int u = m * step - p + gl;  // undilated column and row of this lane
     int32_t tp = BIG, bt = -BIG, l = BIG, r = -BIG;
     {
       int32_t t1, b1, l1, r1;
-      column_row_bounds<KT>(kv, cache[j].ch, s_k[j], u, u, t1, b1, l1, r1);
+      if (rec.mode != SWEEP_GENERAL)
+        sweep_bounds<KT>(rec, u, t1, b1, l1, r1);
+      else
+        column_row_bounds<KT>(kview(cache[j].kc, KT), cache[j].ch, s_k[j], u, u, t1, b1, l1, r1);
       if (u >= 0 && u < wt) { tp = t1; bt = b1; }
       if (u >= 0 && u < ht) { l = l1; r = r1; }
     }
@@ -190,6 +330,7 @@ __device__ void profile_charts(const Work& w, const ChartCache* cache, const int
 __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round) {
   constexpr int NJ = PROF_CH + 1;  // entry 0: the chart before the block's first
   __shared__ ChartCache cache[NJ];
+  __shared__ SweepRec sw[NJ];
   __shared__ int32_t s_pc[NJ], s_pr[NJ], s_k[NJ], s_a[NJ], s_run[NJ], s_nc[NJ], s_ni[NJ + 1], s_G;
   const int tid = threadIdx.x, wv = tid / WAVE, lane = lane_id();
   const int s = blockIdx.y, cb = blockIdx.x * PROF_CH;
@@ -236,6 +377,13 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
   }
   __syncthreads();
   const int K = P.K, p = P.p;
+  // the sweep form of every copied record: rectangles, then sides and mode
+  for (int i = tid; i < NJ * 2 * K; i += PROF_NT) {
+    const int j = i / (2 * K), q = i - j * (2 * K);
+    if (s_run[j] & 1) sw[j].rc[q] = sweep_rect_of(kview(cache[j].kc, K), q);
+  }
+  if (tid < NJ && (s_run[tid] & 1)) sweep_sides_of(kview(cache[tid].kc, K), cache[tid].ch, s_k[tid], sw[tid]);
+  __syncthreads();
   if (wv == 0) {  // lane group size, work items per chart and their prefix
     int e = 0;  // grown entries to evaluate (rows cover columns: h >= w)
     // the chart before the block is only needed for its rows, and only when
@@ -260,9 +408,9 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
   }
   __syncthreads();
   const int G = s_G;
-  if (K == 10) profile_charts<10>(w, cache, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
-  else if (K == 5) profile_charts<5>(w, cache, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
-  else profile_charts<2>(w, cache, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
+  if (K == 10) profile_charts<10>(w, cache, sw, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
+  else if (K == 5) profile_charts<5>(w, cache, sw, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
+  else profile_charts<2>(w, cache, sw, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
   __syncthreads();  // the block's stored rows are visible to all its wavefronts
   for (int j = 1 + wv; j < NJ; j += PROF_NT / WAVE) {
     const int run = s_run[j];
