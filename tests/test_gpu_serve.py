@@ -6,7 +6,12 @@ from __future__ import annotations
 import numpy as np
 import pytest
 
-pytestmark = pytest.mark.gpu
+# Skipped: two full-trace runs of this serving path (four streams, thousands
+# of batches) faulted the GPU and no cause has been found in the kernels or
+# in the server; these smaller runs stay off the GPU until one is.
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skip(reason="multi-stream serving faulted the GPU on full traces; "
+                                      "cause not yet found")]
 
 
 @pytest.fixture(scope="module")
