@@ -44,8 +44,49 @@ __global__ void k_init(Params P, Work w, const int32_t* atlas_off, const int32_t
   w.desc[a] = d;
 }
 
-// charts per 256-thread block in k_prep
-constexpr int PREP_WAVES = 4;
+// k_prep: one group of PREP_G lanes (a DPP row) per chart, PREP_CH charts
+// per 256-thread block; charts have a few dozen vertices, so a whole
+// wavefront per chart would leave most lanes idle and pay six-step 64-bit
+// reductions over 64 lanes
+constexpr int PREP_G = 16;
+constexpr int PREP_CH = 256 / PREP_G;
+
+// Reductions over the 16-lane row of the calling lane by row rotations
+// (every lane of the row receives the result).
+template <int R>
+__device__ inline int32_t row_ror(int32_t v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x120 + R, 0xf, 0xf, false);
+}
+template <int R>
+__device__ inline int64_t row_ror64(int64_t v) {
+  const uint32_t lo = (uint32_t)row_ror<R>((int32_t)(uint32_t)(uint64_t)v);
+  const uint32_t hi = (uint32_t)row_ror<R>((int32_t)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline int32_t row_min(int32_t v) {
+  v = min(v, row_ror<8>(v)); v = min(v, row_ror<4>(v));
+  v = min(v, row_ror<2>(v)); return min(v, row_ror<1>(v));
+}
+__device__ inline int32_t row_max(int32_t v) {
+  v = max(v, row_ror<8>(v)); v = max(v, row_ror<4>(v));
+  v = max(v, row_ror<2>(v)); return max(v, row_ror<1>(v));
+}
+__device__ inline int64_t row_min64(int64_t v) {
+  int64_t u = row_ror64<8>(v); v = u < v ? u : v;
+  u = row_ror64<4>(v); v = u < v ? u : v;
+  u = row_ror64<2>(v); v = u < v ? u : v;
+  u = row_ror64<1>(v); return u < v ? u : v;
+}
+__device__ inline int64_t row_max64(int64_t v) {
+  int64_t u = row_ror64<8>(v); v = u > v ? u : v;
+  u = row_ror64<4>(v); v = u > v ? u : v;
+  u = row_ror64<2>(v); v = u > v ? u : v;
+  u = row_ror64<1>(v); return u > v ? u : v;
+}
+__device__ inline uint64_t row_sum_u64(uint64_t v) {
+  v += (uint64_t)row_ror64<8>((int64_t)v); v += (uint64_t)row_ror64<4>((int64_t)v);
+  v += (uint64_t)row_ror64<2>((int64_t)v); return v + (uint64_t)row_ror64<1>((int64_t)v);
+}
 
 __device__ inline void slab_contrib(int32_t* lo, int32_t* hi, int K, int64_t E, int64_t a1,
                                     int64_t b1, int64_t a2, int64_t b2) {
@@ -77,10 +118,11 @@ __device__ inline void slab_contrib(int32_t* lo, int32_t* hi, int K, int64_t E, 
 __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* __restrict__ xy,
                                               const int32_t* __restrict__ voff,
                                               const int32_t* __restrict__ atlas_off) {
-  __shared__ int32_t sl[PREP_WAVES][4][KMAX];
-  const int wv = threadIdx.x / WAVE, lane = lane_id();
-  const int c = blockIdx.x * PREP_WAVES + wv;
-  if (c >= P.N) return;  // whole wavefront leaves; no block barrier below
+  __shared__ int32_t sl[PREP_CH][4][KMAX];
+  const int g = threadIdx.x / PREP_G, lane = threadIdx.x % PREP_G;  // lane within the group
+  const int base = lane_id() - lane;  // wavefront lane of the group's first lane
+  const int c = blockIdx.x * PREP_CH + g;
+  if (c >= P.N) return;  // whole group leaves; no block barrier below
   const int K = P.K;
   int a = 0;
   if (atlas_off) {  // atlas of this chart: last a with atlas_off[a] <= c
@@ -98,15 +140,15 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
 
   int32_t xmn = BIG, xmx = -BIG, ymn = BIG, ymx = -BIG;
   int range_bad = 0;
-  for (int i = lane; i < nv; i += WAVE) {
+  for (int i = lane; i < nv; i += PREP_G) {
     int2 p = V[i];
     if (p.x <= -(1 << 22) || p.x >= (1 << 22) || p.y <= -(1 << 22) || p.y >= (1 << 22)) range_bad = 1;
     xmn = min(xmn, p.x); xmx = max(xmx, p.x);
     ymn = min(ymn, p.y); ymx = max(ymx, p.y);
   }
-  xmn = wave_min(xmn); xmx = wave_max(xmx);
-  ymn = wave_min(ymn); ymx = wave_max(ymx);
-  range_bad = wave_max(range_bad);
+  xmn = row_min(xmn); xmx = row_max(xmx);
+  ymn = row_min(ymn); ymx = row_max(ymx);
+  range_bad = row_max(range_bad);
   const int32_t W0 = xmx - xmn, H0 = ymx - ymn;
   Chart* out = &w.recs[c];
   if (nv < 3 || range_bad || W0 <= 0 || H0 <= 0) {
@@ -128,15 +170,15 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
     if (rot) { u = H0 - vv; v = u0; } else { u = u0; v = vv; }
   };
 
-  int32_t* ylo = sl[wv][0];
-  int32_t* yhi = sl[wv][1];
-  int32_t* xlo = sl[wv][2];
-  int32_t* xhi = sl[wv][3];
+  int32_t* ylo = sl[g][0];
+  int32_t* yhi = sl[g][1];
+  int32_t* xlo = sl[g][2];
+  int32_t* xhi = sl[g][3];
   if (lane < K) { ylo[lane] = BIG; yhi[lane] = -BIG; xlo[lane] = BIG; xhi[lane] = -BIG; }
   wave_sync();
 
   uint64_t area = 0;
-  for (int i = lane; i < nv; i += WAVE) {
+  for (int i = lane; i < nv; i += PREP_G) {
     int i2 = (i + 1 == nv) ? 0 : i + 1;
     int64_t u1, v1, u2, v2;
     local_uv(i, u1, v1);
@@ -145,7 +187,7 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
     slab_contrib(ylo, yhi, K, W, u1, v1, u2, v2);  // x-slices: slab axis u
     slab_contrib(xlo, xhi, K, H, v1, u1, v2, u2);  // y-slices: slab axis v
   }
-  area = wave_sum_u64(area);
+  area = row_sum_u64(area);
   int64_t area2 = (int64_t)area;
   if (area2 < 0) area2 = -area2;
   wave_sync();
@@ -155,29 +197,29 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
   if (lane < K) { sylo = ylo[lane]; syhi = yhi[lane]; sxlo = xlo[lane]; sxhi = xhi[lane]; }
   const bool in = lane < K;
   // empty area above the top boundary vs below the bottom boundary
-  int64_t top_area = (int64_t)wave_sum_u64(in ? (uint64_t)(int64_t)sylo : 0);
-  int64_t bot_area = (int64_t)wave_sum_u64(in ? (uint64_t)(int64_t)(H - syhi) : 0);
+  int64_t top_area = (int64_t)row_sum_u64(in ? (uint64_t)(int64_t)sylo : 0);
+  int64_t bot_area = (int64_t)row_sum_u64(in ? (uint64_t)(int64_t)(H - syhi) : 0);
   const bool flipy = top_area > bot_area;
   if (flipy) {
     int32_t l2 = H - syhi, h2 = H - sylo;
     sylo = l2; syhi = h2;
-    int src = K - 1 - lane;
-    int32_t a1 = __shfl(sxlo, src < 0 ? 0 : src), a2 = __shfl(sxhi, src < 0 ? 0 : src);
+    const int src = base + (in ? K - 1 - lane : 0);
+    int32_t a1 = __shfl(sxlo, src), a2 = __shfl(sxhi, src);
     if (in) { sxlo = a1; sxhi = a2; }
   }
-  int64_t Ls = (int64_t)wave_sum_u64(in ? (uint64_t)(int64_t)sxlo : 0);
-  int64_t Rs = (int64_t)wave_sum_u64(in ? (uint64_t)(int64_t)(W - sxhi) : 0);
+  int64_t Ls = (int64_t)row_sum_u64(in ? (uint64_t)(int64_t)sxlo : 0);
+  int64_t Rs = (int64_t)row_sum_u64(in ? (uint64_t)(int64_t)(W - sxhi) : 0);
   const int half = K / 2;
-  int64_t BL = (int64_t)wave_sum_u64((lane < half) ? (uint64_t)(int64_t)(H - syhi) : 0);
-  int64_t BR = (int64_t)wave_sum_u64((lane >= K - half && in) ? (uint64_t)(int64_t)(H - syhi) : 0);
+  int64_t BL = (int64_t)row_sum_u64((lane < half) ? (uint64_t)(int64_t)(H - syhi) : 0);
+  int64_t BR = (int64_t)row_sum_u64((lane >= K - half && in) ? (uint64_t)(int64_t)(H - syhi) : 0);
   int64_t diff = Ls - Rs;
   bool flipx;
   if (10 * diff > (int64_t)K * W) flipx = true;
   else if (10 * (diff < 0 ? -diff : diff) <= (int64_t)K * W) flipx = BL > BR;
   else flipx = false;
   if (flipx) {
-    int src = K - 1 - lane;
-    int32_t a1 = __shfl(sylo, src < 0 ? 0 : src), a2 = __shfl(syhi, src < 0 ? 0 : src);
+    const int src = base + (in ? K - 1 - lane : 0);
+    int32_t a1 = __shfl(sylo, src), a2 = __shfl(syhi, src);
     if (in) { sylo = a1; syhi = a2; }
     int32_t l2 = W - sxhi, h2 = W - sxlo;
     sxlo = l2; sxhi = h2;
@@ -187,7 +229,7 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
   int64_t pmin[8], pmax[8], qmin[8], qmax[8];
 #pragma unroll
   for (int m = 1; m < 8; ++m) { pmin[m] = INT64_MAX; pmax[m] = INT64_MIN; qmin[m] = INT64_MAX; qmax[m] = INT64_MIN; }
-  for (int i = lane; i < nv; i += WAVE) {
+  for (int i = lane; i < nv; i += PREP_G) {
     int64_t u, v;
     local_uv(i, u, v);
     if (flipx) u = W - u;
@@ -202,8 +244,8 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
   }
 #pragma unroll
   for (int m = 1; m < 8; ++m) {
-    pmin[m] = wave_min64(pmin[m]); pmax[m] = wave_max64(pmax[m]);
-    qmin[m] = wave_min64(qmin[m]); qmax[m] = wave_max64(qmax[m]);
+    pmin[m] = row_min64(pmin[m]); pmax[m] = row_max64(pmax[m]);
+    qmin[m] = row_min64(qmin[m]); qmax[m] = row_max64(qmax[m]);
   }
   // smallest area (b-a)(f-e)/(C^2+S^2), exact; ties keep the smaller m
   int best = 0;
@@ -495,7 +537,7 @@ hipError_t launch_prep(const Params& P, const Work& w, const int32_t* xy, const 
     hipLaunchKernelGGL(k_init, dim3((P.count + 255) / 256), dim3(256), 0, st, P, w, atlas_off,
                        atlas_wh, single_w, single_h);
   if (P.N > 0)
-    hipLaunchKernelGGL(k_prep, dim3((P.N + PREP_WAVES - 1) / PREP_WAVES), dim3(256), 0, st, P, w,
+    hipLaunchKernelGGL(k_prep, dim3((P.N + PREP_CH - 1) / PREP_CH), dim3(256), 0, st, P, w,
                        xy, voff, atlas_off);
   return hipGetLastError();
 }

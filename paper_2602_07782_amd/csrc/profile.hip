@@ -82,33 +82,26 @@ __device__ inline SweepRect sweep_rect_of(const KView& kv, int q) {
   return r;
 }
 
-// The four OBB sides' lines (as column_row_bounds forms them) and the
-// evaluation mode of the chart.
-__device__ inline void sweep_sides_of(const KView& kv, const Chart& ch, int k, SweepRec& R) {
-  const KHead hd = khead_load(kv.hd);
+// OBB side sd of the chart (0 top, 1 bottom, 2 left, 3 right): its lines as
+// column_row_bounds forms them; false when they need 64-bit evaluation.
+__device__ inline bool sweep_side_of(const KView& kv, const Chart& ch, int k, int sd,
+                                     SweepSide& o) {
   const int64_t C = kDirC[ch.m], S = kDirS[ch.m], kk = k;
-  SideLines L[4];
-  L[0] = side_lines<false>(kk * ch.a, -QS * C, QS * S, kk * ch.e, QS * S, QS * C);
-  L[1] = side_lines<true>(kk * ch.f, QS * S, QS * C, kk * ch.b, -QS * C, QS * S);
-  L[2] = side_lines<false>(kk * ch.a, -QS * S, QS * C, -kk * ch.f, QS * C, QS * S);
-  L[3] = side_lines<true>(-kk * ch.e, QS * C, QS * S, kk * ch.b, -QS * S, QS * C);
-  bool ok = hd.w <= 16384 && hd.h <= 16384;
-  for (int s = 0; s < 4; ++s) {
-    const KSide ks = kside_load(kv.sd + s);
-    SweepSide& o = R.sd[s];
-    o.sa = ks.sa;
-    o.sb = ks.sb;
-    o.corner = ks.corner;
-    o.last = ks.last;
-    o.MA = L[s].MA; o.nA = L[s].nA; o.dA = L[s].dA;
-    o.MB = L[s].MB; o.nB = L[s].nB; o.dB = L[s].dB;
-    o.rA = __builtin_amdgcn_rcpf((float)L[s].dA);
-    o.rB = __builtin_amdgcn_rcpf((float)L[s].dB);
-    if (hd.obb) ok = ok && L[s].ok;
-  }
-  R.mode = !ok ? SWEEP_GENERAL : (hd.obb ? SWEEP_OBB : SWEEP_AABB);
-  R.w = hd.w;
-  R.h = hd.h;
+  SideLines L;
+  if (sd == 0) L = side_lines<false>(kk * ch.a, -QS * C, QS * S, kk * ch.e, QS * S, QS * C);
+  else if (sd == 1) L = side_lines<true>(kk * ch.f, QS * S, QS * C, kk * ch.b, -QS * C, QS * S);
+  else if (sd == 2) L = side_lines<false>(kk * ch.a, -QS * S, QS * C, -kk * ch.f, QS * C, QS * S);
+  else L = side_lines<true>(-kk * ch.e, QS * C, QS * S, kk * ch.b, -QS * S, QS * C);
+  const KSide ks = kside_load(kv.sd + sd);
+  o.sa = ks.sa;
+  o.sb = ks.sb;
+  o.corner = ks.corner;
+  o.last = ks.last;
+  o.MA = L.MA; o.nA = L.nA; o.dA = L.dA;
+  o.MB = L.MB; o.nB = L.nB; o.dB = L.dB;
+  o.rA = __builtin_amdgcn_rcpf((float)L.dA);
+  o.rB = __builtin_amdgcn_rcpf((float)L.dB);
+  return L.ok;
 }
 
 // side_eval with the line data and reciprocal read from the sweep record
@@ -275,13 +268,13 @@ __device__ void profile_charts(const Work& w, const ChartCache* cache, const Swe
   const int wv = threadIdx.x / WAVE, lane = lane_id();
   const int per = WAVE / G, gi = lane / G, gl = lane - gi * G, step = G - p;
   const int total = s_ni[NJ];
+  int j = 0;  // chart of the lane's item; items only move forward
   for (int it0 = wv * per; it0 < total; it0 += (PROF_NT / WAVE) * per) {
     const int it = it0 + gi;
     const bool live = it < total;
     // lanes past the last item evaluate the last item again (never stored),
     // so every lane reads a record that was copied
     const int itc = live ? it : total - 1;
-    int j = 0;
     while (s_ni[j + 1] <= itc) ++j;
     const int m = itc - s_ni[j];
     const SweepRec& rec = sw[j];
@@ -327,11 +320,17 @@ __device__ void profile_charts(const Work& w, const ChartCache* cache, const Swe
 // one-lane moves, so a chunk advances 64 - p entries (p <= 32).  After a barrier
 // the pairs read the rows just stored; pairs in segments without stored
 // profiles evaluate the rows from the LDS records.
+template <int KT>
 __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round) {
   constexpr int NJ = PROF_CH + 1;  // entry 0: the chart before the block's first
+  constexpr int K = KT;
+  // 16-byte words of a chart record and of its set-up record (P.stride)
+  constexpr int nch = (int)(sizeof(Chart) / 16);
+  constexpr int nkc = (int)((sizeof(KHead) + 4 * sizeof(KSide) + 2 * KT * sizeof(KRect)) / 16);
   __shared__ ChartCache cache[NJ];
   __shared__ SweepRec sw[NJ];
   __shared__ int32_t s_pc[NJ], s_pr[NJ], s_k[NJ], s_a[NJ], s_run[NJ], s_nc[NJ], s_ni[NJ + 1], s_G;
+  __shared__ int32_t s_ok[NJ * 4];
   const int tid = threadIdx.x, wv = tid / WAVE, lane = lane_id();
   const int s = blockIdx.y, cb = blockIdx.x * PROF_CH;
   if (tid < NJ) {
@@ -362,7 +361,7 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
   const int active = tid >= 1 && tid < NJ && (s_run[tid] & 1);
   if (!__syncthreads_or(active)) return;
   {
-    const int nch = (int)(sizeof(Chart) / 16), nkc = P.stride / 16, per = nch + nkc;
+    constexpr int per = nch + nkc;
     const int j0 = cb > 0 ? 0 : 1, j1 = min(NJ, P.N - cb + 1);
     for (int i = tid; i < (j1 - j0) * per; i += PROF_NT) {
       const int j = j0 + i / per, r = i % per, c = cb - 1 + j;
@@ -376,15 +375,28 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
     }
   }
   __syncthreads();
-  const int K = P.K, p = P.p;
-  // the sweep form of every copied record: rectangles, then sides and mode
+  const int p = P.p;
+  // the sweep form of every copied record: rectangles, and one thread per
+  // (chart, OBB side) for the lines
   for (int i = tid; i < NJ * 2 * K; i += PROF_NT) {
     const int j = i / (2 * K), q = i - j * (2 * K);
     if (s_run[j] & 1) sw[j].rc[q] = sweep_rect_of(kview(cache[j].kc, K), q);
   }
-  if (tid < NJ && (s_run[tid] & 1)) sweep_sides_of(kview(cache[tid].kc, K), cache[tid].ch, s_k[tid], sw[tid]);
+  if (tid < NJ * 4 && (s_run[tid >> 2] & 1)) {
+    const int j = tid >> 2;
+    s_ok[tid] = sweep_side_of(kview(cache[j].kc, K), cache[j].ch, s_k[j], tid & 3, sw[j].sd[tid & 3]);
+  }
   __syncthreads();
-  if (wv == 0) {  // lane group size, work items per chart and their prefix
+  if (wv == 0) {  // evaluation mode; lane group size, work items per chart and their prefix
+    if (lane < NJ && (s_run[lane] & 1)) {
+      const KHead hd = khead_load(kview(cache[lane].kc, K).hd);
+      const bool lines = s_ok[4 * lane] && s_ok[4 * lane + 1] && s_ok[4 * lane + 2] &&
+                         s_ok[4 * lane + 3];
+      const bool fits = hd.w <= 16384 && hd.h <= 16384 && (!hd.obb || lines);
+      sw[lane].mode = !fits ? SWEEP_GENERAL : (hd.obb ? SWEEP_OBB : SWEEP_AABB);
+      sw[lane].w = hd.w;
+      sw[lane].h = hd.h;
+    }
     int e = 0;  // grown entries to evaluate (rows cover columns: h >= w)
     // the chart before the block is only needed for its rows, and only when
     // it belongs to the same atlas as the block's first chart (its columns
@@ -408,9 +420,7 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
   }
   __syncthreads();
   const int G = s_G;
-  if (K == 10) profile_charts<10>(w, cache, sw, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
-  else if (K == 5) profile_charts<5>(w, cache, sw, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
-  else profile_charts<2>(w, cache, sw, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
+  profile_charts<KT>(w, cache, sw, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
   __syncthreads();  // the block's stored rows are visible to all its wavefronts
   for (int j = 1 + wv; j < NJ; j += PROF_NT / WAVE) {
     const int run = s_run[j];
@@ -442,8 +452,10 @@ hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_
   // with no arena the placement still runs: it marks every segment unstored
   hipLaunchKernelGGL(k_layout, dim3(P.count, P.B), dim3(LAY_NT), 0, st, P, w, round);
   hipLaunchKernelGGL(k_alloc, dim3(1), dim3(ALLOC_NT), 0, st, P, w);
-  hipLaunchKernelGGL(k_profile, dim3((P.N + PROF_CH - 1) / PROF_CH, P.B), dim3(PROF_NT), 0, st, P,
-                     w, round);
+  const dim3 grid((P.N + PROF_CH - 1) / PROF_CH, P.B);
+  if (P.K == 10) hipLaunchKernelGGL(k_profile<10>, grid, dim3(PROF_NT), 0, st, P, w, round);
+  else if (P.K == 5) hipLaunchKernelGGL(k_profile<5>, grid, dim3(PROF_NT), 0, st, P, w, round);
+  else hipLaunchKernelGGL(k_profile<2>, grid, dim3(PROF_NT), 0, st, P, w, round);
   return hipGetLastError();
 }
 
