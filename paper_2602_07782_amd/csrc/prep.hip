@@ -370,6 +370,7 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
 // one thread per (slot, chart)
 // The record of chart c at slot s, written to `base` (LDS); false when the
 // chart does not run at this slot.
+template <int KT>
 __device__ bool setup_record(const Params& P, const Work& w, int round, int c, int s,
                              unsigned char* base) {
   const AtlasDesc d = w.desc[w.chart_atlas[c]];
@@ -378,7 +379,7 @@ __device__ bool setup_record(const Params& P, const Work& w, int round, int c, i
   const int k = slot_k(P, d, round, s);
   if (k < 1) return false;
   const Chart& ch = w.srecs[c];
-  const int K = P.K;
+  constexpr int K = KT;
   KHead* hd = reinterpret_cast<KHead*>(base);
   KSide* sd = reinterpret_cast<KSide*>(base + sizeof(KHead));
   KRect* rc = reinterpret_cast<KRect*>(base + sizeof(KHead) + 4 * sizeof(KSide));
@@ -398,18 +399,22 @@ __device__ bool setup_record(const Params& P, const Work& w, int round, int c, i
   // (values are clamped to int16; only a chart larger than any atlas reaches
   // the clamp, and such a scale fails on that chart's width or height anyway)
   auto i16 = [](int64_t v) { return (int16_t)(v > 32767 ? 32767 : v); };
+  // slice boundaries: j W k / 2^14 < 11 * 2^23 * 64 / 2^14 < 2^19, so the
+  // quotient by K is a 32-bit division by a constant
+  auto slab = [](int64_t num) { return (int32_t)(uint32_t)((uint64_t)num >> 14) / K; };
+#pragma unroll
   for (int j = 0; j < K; ++j) {
     KRect r;
-    r.c0 = i16(((int64_t)j * W * kk >> 14) / K);
-    r.c1 = i16((((int64_t)(j + 1) * W * kk + QS * K - 1) >> 14) / K);
+    r.c0 = i16(slab((int64_t)j * W * kk));
+    r.c1 = i16(slab((int64_t)(j + 1) * W * kk + QS * K - 1));
     r.r0 = i16(((int64_t)ch.ylo[j] * kk) >> 14);
     r.r1 = i16(((int64_t)ch.yhi[j] * kk + QS - 1) >> 14);
     rc[j] = r;
     KRect y;
     y.c0 = i16(((int64_t)ch.xlo[j] * kk) >> 14);
     y.c1 = i16(((int64_t)ch.xhi[j] * kk + QS - 1) >> 14);
-    y.r0 = i16(((int64_t)j * H * kk >> 14) / K);
-    y.r1 = i16((((int64_t)(j + 1) * H * kk + QS * K - 1) >> 14) / K);
+    y.r0 = i16(slab((int64_t)j * H * kk));
+    y.r1 = i16(slab((int64_t)(j + 1) * H * kk + QS * K - 1));
     rc[K + j] = y;
   }
   if (!h.obb) return true;
@@ -466,11 +471,12 @@ __device__ bool setup_record(const Params& P, const Work& w, int round, int c, i
 // coalesced 16-byte stores (one thread writing its own 16 + 64 + 16K bytes
 // field by field would cost a memory transaction per field).
 constexpr int SETUP_NT = 128;
+template <int KT>
 __global__ __launch_bounds__(SETUP_NT) void k_setup(Params P, Work w, int round) {
   __shared__ __align__(16) unsigned char s_rec[SETUP_NT * KREC_MAX];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
-  const bool active = c < P.N && setup_record(P, w, round, c, s, s_rec + threadIdx.x * P.stride);
+  const bool active = c < P.N && setup_record<KT>(P, w, round, c, s, s_rec + threadIdx.x * P.stride);
   if (!__syncthreads_or(active)) return;  // no chart of the block runs at this slot
   const int c0 = blockIdx.x * blockDim.x, nc = min(SETUP_NT, P.N - c0);
   const int n16 = nc * (P.stride / 16);
@@ -561,8 +567,12 @@ hipError_t launch_plan(const Params&, const Work&, hipStream_t) { return hipSucc
 
 hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t st) {
   if (P.N > 0)
-    hipLaunchKernelGGL(k_setup, dim3((P.N + SETUP_NT - 1) / SETUP_NT, P.B), dim3(SETUP_NT), 0, st,
-                       P, w, round);
+  {
+    const dim3 grid((P.N + SETUP_NT - 1) / SETUP_NT, P.B);
+    if (P.K == 10) hipLaunchKernelGGL(k_setup<10>, grid, dim3(SETUP_NT), 0, st, P, w, round);
+    else if (P.K == 5) hipLaunchKernelGGL(k_setup<5>, grid, dim3(SETUP_NT), 0, st, P, w, round);
+    else hipLaunchKernelGGL(k_setup<2>, grid, dim3(SETUP_NT), 0, st, P, w, round);
+  }
   return hipGetLastError();
 }
 
