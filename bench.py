@@ -96,6 +96,14 @@ def batched_leg(tabi, torch, count=256, reps=3):
     ev1.record(stream)
     torch.cuda.synchronize()
     batched_s = ev0.elapsed_time(ev1) / 1000.0 / reps
+    # per-stage split of one more (eager) batch, outside the timed region
+    tabi.timing_reset()
+    tabi.timing_enable(True)
+    with torch.cuda.stream(s):
+        batch.run(stream=s, use_workspace=True)
+    torch.cuda.synchronize()
+    tabi.timing_enable(False)
+    stages = {k: round(v[0], 3) for k, v in tabi.timing_read().items()}
     same, c0 = True, 0
     bsc = batch.out_scale.cpu().numpy()
     for ai, (inp, (oxy, oor, osc)) in enumerate(zip(inputs, plain_out)):
@@ -109,6 +117,7 @@ def batched_leg(tabi, torch, count=256, reps=3):
             "atlases_per_s_plain": round(count / plain_s, 2),
             "speedup_vs_plain": round(plain_s / batched_s, 2),
             "ms_per_batch": round(batched_s * 1000.0, 3), "hip_graph": True,
+            "stage_ms_per_batch": stages,
             "autotuned_shape": {"slots_per_round": tuned["shape"][0],
                                 "pack_threads": tuned["shape"][1],
                                 "pack_lds_cap": tuned["shape"][2],
