@@ -140,7 +140,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t s_cnt[4];
   __shared__ int32_t s_red[PACK_WAVES * 6];
-  __shared__ int64_t s_red64[PACK_WAVES];
+  __shared__ int32_t s_knee[4];  // knee found by the last row's detection: on, direction, span
   __shared__ int32_t s_lrn, s_lrover;
   __shared__ int32_t s_lr[LRCAP][3];
   // window of chart data read by the fold and the knee test, charts
@@ -190,6 +190,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   // per-row state, identical in every thread
   int rs = 0, rows = 0, feasible = 1, tail = 0, trow = 0;
   int kn = 0, kdir = 0, kl = 0, kr = 0;
+  if (tid == 0) s_knee[0] = -1;
   int32_t fmax = 0;
   int wb = -FWIN, nwin = 0;
   // arena word of the row's first grown column (-1: no stored profiles); the
@@ -199,6 +200,11 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
 
   for (;;) {
     __syncthreads();
+    {  // the previous row's knee detection (-1: none ran)
+      const int kf = s_knee[0];
+      if (kf >= 0) kn = kf;
+      if (kf > 0) { kdir = s_knee[1]; kl = s_knee[2]; kr = s_knee[3]; }
+    }
     if (rs >= n) break;
     if (rs - wb > FWIN / 2) {
       wb = rs;
@@ -403,7 +409,9 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       const int yo = wv == 0 ? yofs[0] : wv == 1 ? yofs[1] : wv == 2 ? yofs[2] : yofs[3];
       if (hc) correct_offsets(Yb + yo, cnt, flv + rs, s_lr, lrn);
     }
-    __syncthreads();
+    // the scores read the corrected offsets (without compaction nothing was
+    // corrected and the barrier after the push suffices)
+    if (anyhc) __syncthreads();
     // ---- 6. scores
     int32_t M[4] = {-BIG, -BIG, -BIG, -BIG};
     for (int e0 = wv * WAVE; e0 < E; e0 += PACK_NT) {
@@ -460,8 +468,10 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     const int w_R1 = win == 0 ? c_R1[0] : win == 1 ? c_R1[1] : win == 2 ? c_R1[2] : c_R1[3];
     const int32_t w_score = win == 0 ? whole[0] : win == 1 ? whole[1] : win == 2 ? whole[2] : whole[3];
     const int32_t* Yw = Yb + (win == 0 ? yofs[0] : win == 1 ? yofs[1] : win == 2 ? yofs[2] : yofs[3]);
-    __syncthreads();  // everyone has read the reductions and Y before commit
-    // ---- commit: frontline update, placements
+    // ---- commit: frontline update, placements.  No barrier before it: every
+    // read of the frontline in this row (push, knee region maximum) happened
+    // before the barrier of the score reduction, and the reduction slots and
+    // offsets read since are next written after the loop's opening barrier.
     const int Ew = Xoff[w_cnt];
     for (int e = tid; e < Ew; e += PACK_NT) {
       int t;
@@ -482,9 +492,13 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     // knee detection on a row folded at full width (Sec. 4.2; App. A): the
     // largest drop in unscaled height between consecutive charts that is at
     // least 10% of the atlas height and 20% of the taller chart; first wins
-    if (!tail && !knee_used) {
+    // (wavefront 0 alone; the others take the result from LDS after the
+    // next row's opening barrier)
+    if (wv == 0 && (tail || knee_used)) {
+      if (lane == 0) s_knee[0] = -1;  // no detection: the knee state stays
+    } else if (wv == 0) {
       int64_t best = -1;
-      for (int t = tid; t + 1 < w_cnt; t += PACK_NT) {
+      for (int t = lane; t + 1 < w_cnt; t += WAVE) {
         const int64_t h1 = r0 + t < nwin ? s_H[r0 + t] : Hs[rs + t];
         const int64_t h2 = r0 + t + 1 < nwin ? s_H[r0 + t + 1] : Hs[rs + t + 1], dl = h1 - h2;
         if (10 * dl >= 256 * (int64_t)Ha && 5 * dl >= h1) {
@@ -492,21 +506,20 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
           best = key > best ? key : best;
         }
       }
-      best = wave_max64(best);
-      if (lane == 0) s_red64[wv] = best;
-      __syncthreads();
-      int64_t b = s_red64[0];
-      for (int q = 1; q < PACK_WAVES; ++q) b = s_red64[q] > b ? s_red64[q] : b;
-      if (b >= 0) {
-        const int t = (1 << 20) - 1 - (int)(b & ((1 << 20) - 1));
-        const int X = w_hc ? Xon[t] : Xoff[t];
-        const int wd = Xoff[t + 1] - Xoff[t];
-        kn = 1;
-        kdir = w_dir;
-        kl = w_dir == DIR_LR ? w_R0 + X : w_R1 - X - wd;
-        kr = kl + wd;
-      } else {
-        kn = 0;
+      const int64_t b = wave_max64(best);
+      if (lane == 0) {
+        if (b >= 0) {
+          const int t = (1 << 20) - 1 - (int)(b & ((1 << 20) - 1));
+          const int X = w_hc ? Xon[t] : Xoff[t];
+          const int wd = Xoff[t + 1] - Xoff[t];
+          const int l = w_dir == DIR_LR ? w_R0 + X : w_R1 - X - wd;
+          s_knee[0] = 1;
+          s_knee[1] = w_dir;
+          s_knee[2] = l;
+          s_knee[3] = l + wd;
+        } else {
+          s_knee[0] = 0;
+        }
       }
     }
     fmax = max(fmax, w_score);
