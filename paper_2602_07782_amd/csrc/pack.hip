@@ -542,20 +542,19 @@ __global__ __launch_bounds__(256) void k_select(Params P, Work w, int round, int
   const int a = blockIdx.x;
   const AtlasDesc d = w.desc[a];
   if (d.done) return;
-  if (threadIdx.x == 0) {
-    int best = -1, limit = 0;
-    if (!d.bad && d.n > 0 && d.ktop >= 1) {
-      for (int s = 0; s < P.B; ++s) {
-        const int f = w.feas[a * P.B + s];
-        if (f == -2) limit = 1;
-        if (f == 1 && best < 0) best = s;
-      }
+  if (threadIdx.x < WAVE) {  // lane s reads slot s (at most 64 slots)
+    const bool live = !d.bad && d.n > 0 && d.ktop >= 1;
+    const int s = threadIdx.x;
+    const int f = live && s < P.B ? w.feas[a * P.B + s] : 0;
+    const uint64_t ok = ballot64(f == 1);
+    const int best = ok ? __builtin_ctzll(ok) : -1;
+    const int limit = ballot64(f == -2) != 0;
+    if (threadIdx.x == 0) {
+      s_best = best;
+      s_limit = limit;
+      // more candidate scales remain for a later round
+      s_more = live && best < 0 && !limit && !last_round && slot_k(P, d, round, P.B - 1) > 1;
     }
-    s_best = best;
-    s_limit = limit;
-    // more candidate scales remain for a later round
-    s_more = !d.bad && d.n > 0 && d.ktop >= 1 && best < 0 && !limit && !last_round &&
-             slot_k(P, d, round, P.B - 1) > 1;
   }
   __syncthreads();
   const int best = s_best;

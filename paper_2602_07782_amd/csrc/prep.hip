@@ -329,12 +329,15 @@ __global__ __launch_bounds__(256) void k_place(Params P, Work w) {
   w.perm[pos] = c - lo;
 }
 
-// candidate scales: the charts' total area and the largest chart must fit
+// candidate scales: the charts' total area and the largest chart must fit.
+// Per-thread sums stay below 2^57 (area2 < 2^47, at most 1,024 charts per
+// thread) and a wavefront's below 2^63; the block total is taken in 128 bits.
+// Lane k - 1 of wavefront 0 tests scale k; k_top is the largest passing one.
 __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
-  __shared__ uint64_t s_sum[256];
-  __shared__ int32_t s_maxw[256];
-  const int a = blockIdx.x;
-  AtlasDesc d = w.desc[a];
+  __shared__ uint64_t s_sum[4];
+  __shared__ int32_t s_maxw[4];
+  const int a = blockIdx.x, lane = lane_id(), wv = threadIdx.x / WAVE;
+  const AtlasDesc d = w.desc[a];
   uint64_t sum = 0;
   int32_t mw = 0;
   for (int t = threadIdx.x; t < d.n; t += blockDim.x) {
@@ -342,29 +345,29 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
     sum += (uint64_t)ch.area2;
     mw = max(mw, ch.W);
   }
-  s_sum[threadIdx.x] = sum;
-  s_maxw[threadIdx.x] = mw;
+  sum = wave_sum_u64(sum);
+  mw = wave_max(mw);
+  if (lane == 0) { s_sum[wv] = sum; s_maxw[wv] = mw; }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned __int128 S = 0;
-    int32_t MW = 0;
-    for (int t = 0; t < (int)blockDim.x; ++t) { S += s_sum[t]; MW = max(MW, s_maxw[t]); }
-    int ktop = 0;
-    if (d.bad) {
-      ktop = -1;
-    } else if (d.n == 0) {
-      ktop = 64;
-    } else {
-      const int32_t MH = w.srecs[d.c0].H;  // tallest chart comes first
-      const unsigned __int128 cap = ((unsigned __int128)1 << 29) * (unsigned)d.Wa * (unsigned)d.Ha;
-      for (int k = 1; k <= 64; ++k) {
-        bool area_ok = S * (unsigned)(k * k) <= cap;
-        bool fit = cdiv64((int64_t)k * MW, QS) <= d.Wa && cdiv64((int64_t)k * MH, QS) <= d.Ha;
-        if (area_ok && fit) ktop = k;
-      }
-    }
-    w.desc[a].ktop = ktop;
+  if (wv != 0) return;
+  unsigned __int128 S = 0;
+  int32_t MW = 0;
+  for (int q = 0; q < 4; ++q) { S += s_sum[q]; MW = max(MW, s_maxw[q]); }
+  int ktop = 0;
+  if (d.bad) {
+    ktop = -1;
+  } else if (d.n == 0) {
+    ktop = 64;
+  } else {
+    const int32_t MH = w.srecs[d.c0].H;  // tallest chart comes first
+    const unsigned __int128 cap = ((unsigned __int128)1 << 29) * (unsigned)d.Wa * (unsigned)d.Ha;
+    const int k = lane + 1;
+    const bool area_ok = S * (unsigned)(k * k) <= cap;
+    const bool fit = cdiv64((int64_t)k * MW, QS) <= d.Wa && cdiv64((int64_t)k * MH, QS) <= d.Ha;
+    const uint64_t pass = ballot64(area_ok && fit);
+    ktop = pass ? 64 - __builtin_clzll(pass) : 0;
   }
+  if (lane == 0) w.desc[a].ktop = ktop;
 }
 
 // one thread per (slot, chart)
