@@ -101,6 +101,67 @@ __device__ inline PairSweep pair_sweep_rows(const uint32_t* ra, int hdA, const u
   return r;
 }
 
+// The same sweep for four pairs at once, one per 16-lane row of the
+// wavefront: each step covers 16 grown rows and every scan stays inside the
+// row (DPP row shifts), the row's last lane carries its running extremes to
+// the next step, and the results are reduced within the row (rotations).
+// Every lane of the wavefront must call it; a row without a pair passes
+// hdA = 0.  The results hold in every lane of the row.
+__device__ inline int32_t row_last(int32_t v) {  // lane 15 of the caller's row
+  const int g = lane_id() >> 4;
+  const int32_t a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
+  const int32_t c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
+  return g == 0 ? a : (g == 1 ? b : (g == 2 ? c : d));
+}
+constexpr int DPP_ROW_ROR1 = 0x121, DPP_ROW_ROR2 = 0x122, DPP_ROW_ROR4 = 0x124,
+              DPP_ROW_ROR8 = 0x128;
+__device__ inline int32_t row_all_max(int32_t v) {
+  v = max(v, dpp_move<DPP_ROW_ROR8>(v, -BIG));
+  v = max(v, dpp_move<DPP_ROW_ROR4>(v, -BIG));
+  v = max(v, dpp_move<DPP_ROW_ROR2>(v, -BIG));
+  return max(v, dpp_move<DPP_ROW_ROR1>(v, -BIG));
+}
+__device__ inline int32_t row_all_min(int32_t v) {
+  v = min(v, dpp_move<DPP_ROW_ROR8>(v, BIG));
+  v = min(v, dpp_move<DPP_ROW_ROR4>(v, BIG));
+  v = min(v, dpp_move<DPP_ROW_ROR2>(v, BIG));
+  return min(v, dpp_move<DPP_ROW_ROR1>(v, BIG));
+}
+__device__ inline PairSweep pair_sweep_rows16(const uint32_t* ra, int hdA, const uint32_t* rb,
+                                              int hdB, int wdA) {
+  const int gl = lane_id() & 15;
+  int32_t cd = BIG, D1 = -BIG, D2 = -BIG;
+  int32_t carry_max = -BIG, carry_min = BIG;
+  const int steps = wave_max((hdA + 15) >> 4);  // the longest of the four pairs
+  for (int q = 0; q < steps; ++q) {
+    const int j = q * 16 + gl;
+    const bool act = j < hdA, shr = act && j < hdB;
+    const int32_t Ra = act ? hi16(ra[j]) : -BIG;
+    const int32_t Lb = shr ? lo16(rb[j]) : BIG;
+    if (shr) cd = min(cd, wdA - Ra + Lb);
+    int32_t imax = Ra, imin = Lb;
+    imax = max(imax, dpp_move<DPP_ROW_SHR1>(imax, -BIG));
+    imin = min(imin, dpp_move<DPP_ROW_SHR1>(imin, BIG));
+    imax = max(imax, dpp_move<DPP_ROW_SHR2>(imax, -BIG));
+    imin = min(imin, dpp_move<DPP_ROW_SHR2>(imin, BIG));
+    imax = max(imax, dpp_move<DPP_ROW_SHR4>(imax, -BIG));
+    imin = min(imin, dpp_move<DPP_ROW_SHR4>(imin, BIG));
+    imax = max(imax, dpp_move<DPP_ROW_SHR8>(imax, -BIG));
+    imin = min(imin, dpp_move<DPP_ROW_SHR8>(imin, BIG));
+    const int32_t emax = max(dpp_move<DPP_ROW_SHR1>(imax, -BIG), carry_max);
+    const int32_t emin = min(dpp_move<DPP_ROW_SHR1>(imin, BIG), carry_min);
+    if (shr && j >= 1) D1 = max(D1, emax - Lb);
+    if (act && j >= 1) D2 = max(D2, Ra - emin);
+    carry_max = max(carry_max, row_last(imax));
+    carry_min = min(carry_min, row_last(imin));
+  }
+  PairSweep r;
+  r.cd = row_all_min(cd);
+  r.D1 = row_all_max(D1);
+  r.D2 = row_all_max(D2);
+  return r;
+}
+
 // Interlock flags for box offset d (bit0: B may not move above A, bit1: A may
 // not move above B); none without a shared column.
 __device__ inline int32_t pair_flags_at(const PairSweep& s, int wdA, int d) {

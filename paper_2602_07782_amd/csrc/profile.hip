@@ -422,27 +422,52 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
   const int G = s_G;
   profile_charts<KT>(w, cache, sw, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
   __syncthreads();  // the block's stored rows are visible to all its wavefronts
-  for (int j = 1 + wv; j < NJ; j += PROF_NT / WAVE) {
-    const int run = s_run[j];
-    if (!(run & 1)) continue;
-    const int c = cb - 1 + j;
-    const size_t sc = (size_t)s * P.N + c;
-    if (run & 2) {
-      if (lane == 0) { w.cd[sc] = 0; w.fl[sc] = 0; }
-      continue;
+  // wavefront wv takes the pairs ending at charts 1 + 4 wv .. 4 + 4 wv: side
+  // by side in its four 16-lane rows when all of them read stored rows, else
+  // one at a time over the whole wavefront (rows evaluated from the records
+  // where none are stored)
+  const int jg = 1 + 4 * wv + (lane >> 4);
+  const bool pg = (s_run[jg] & 1) && !(s_run[jg] & 2);  // a pair with the chart before
+  if (ballot64(pg && s_pr[jg] < 0) == 0) {
+    int hdA = 0, hdB = 0, wdA = 0;
+    const uint32_t* ra = w.arena;
+    const uint32_t* rb = w.arena;
+    if (pg) {
+      const KHead ha = khead_load(kview(cache[jg - 1].kc, K).hd);
+      hdA = ha.h + p;
+      wdA = ha.w + p;
+      hdB = khead_load(kview(cache[jg].kc, K).hd).h + p;
+      ra = w.arena + s_pr[jg - 1];
+      rb = w.arena + s_pr[jg];
     }
-    const KView A = kview(cache[j - 1].kc, K), B = kview(cache[j].kc, K);
-    const int wdA = khead_load(A.hd).w + p;
-    PairSweep r;
-    if (s_pr[j] >= 0) {
-      r = pair_sweep_rows(w.arena + s_pr[j - 1], khead_load(A.hd).h + p, w.arena + s_pr[j],
-                          khead_load(B.hd).h + p, wdA);
-    } else {
-      r = pair_sweep(A, cache[j - 1].ch, B, cache[j].ch, K, s_k[j], p);
+    const PairSweep r = pair_sweep_rows16(ra, hdA, rb, hdB, wdA);
+    if ((lane & 15) == 0 && (s_run[jg] & 1)) {
+      const size_t sc = (size_t)s * P.N + (cb - 1 + jg);
+      w.cd[sc] = pg ? r.cd : 0;
+      w.fl[sc] = pg ? (uint8_t)pair_flags_at(r, wdA, wdA - r.cd) : 0;
     }
-    if (lane == 0) {
-      w.cd[sc] = r.cd;
-      w.fl[sc] = (uint8_t)pair_flags_at(r, wdA, wdA - r.cd);
+  } else {
+    for (int j = 1 + 4 * wv; j < 5 + 4 * wv; ++j) {
+      const int run = s_run[j];
+      if (!(run & 1)) continue;
+      const size_t sc = (size_t)s * P.N + (cb - 1 + j);
+      if (run & 2) {
+        if (lane == 0) { w.cd[sc] = 0; w.fl[sc] = 0; }
+        continue;
+      }
+      const KView A = kview(cache[j - 1].kc, K), B = kview(cache[j].kc, K);
+      const int wdA = khead_load(A.hd).w + p;
+      PairSweep r;
+      if (s_pr[j] >= 0) {
+        r = pair_sweep_rows(w.arena + s_pr[j - 1], khead_load(A.hd).h + p, w.arena + s_pr[j],
+                            khead_load(B.hd).h + p, wdA);
+      } else {
+        r = pair_sweep(A, cache[j - 1].ch, B, cache[j].ch, K, s_k[j], p);
+      }
+      if (lane == 0) {
+        w.cd[sc] = r.cd;
+        w.fl[sc] = (uint8_t)pair_flags_at(r, wdA, wdA - r.cd);
+      }
     }
   }
 }
