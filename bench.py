@@ -118,9 +118,11 @@ def batched_leg(tabi, torch, count=256, reps=3):
             "speedup_vs_plain": round(plain_s / batched_s, 2),
             "ms_per_batch": round(batched_s * 1000.0, 3), "hip_graph": True,
             "stage_ms_per_batch": stages,
-            "autotuned_shape": {"slots_per_round": tuned["shape"][0],
-                                "pack_threads": tuned["shape"][1],
-                                "pack_lds_cap": tuned["shape"][2],
+            "autotuned_shape": {"first_round_slots": tuned["shape"][0],
+                                "rounds_at_first": tuned["shape"][1],
+                                "max_round_slots": tuned["shape"][2],
+                                "pack_threads": tuned["shape"][3],
+                                "pack_lds_cap": tuned["shape"][4],
                                 "candidate_ms": tuned["ms"]},
             "bitexact_vs_plain": bool(same)}
 

@@ -134,8 +134,11 @@ int tabi_pack_many_ws(const int32_t* xy, const int32_t* vert_offsets,
  * tabi_many_shape_count() candidate shapes, keeps the fastest as the shape of
  * later tabi_pack_many / _ws / _records calls with this quality and a batch
  * of the same size class (up to 8 atlases, up to 64, more) on the current
- * device, and writes it to shape[3] = {B, threads, LDS cap bytes (0: device
- * limit)}; ms_per_shape (may be NULL) receives the mean milliseconds
+ * device, and writes it to shape[5] = {b0, flat, bmax, threads, LDS cap bytes
+ * (0: device limit)}: the search runs rounds of b0 scale slots for the first
+ * `flat` rounds, then doubles the slots per round up to bmax until the 64
+ * candidate scales are covered, with fold-and-push workgroups of `threads`
+ * threads; ms_per_shape (may be NULL) receives the mean milliseconds
  * per call of each candidate (-1 for a shape the batch's rows do not fit).
  * Synchronizes `stream`.  A workspace sized with
  * tabi_pack_many_workspace_bytes before tuning must be sized again after it
@@ -148,7 +151,7 @@ int tabi_tune_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t
                    int32_t* shape, float* ms_per_shape, tabi_stream_t stream);
 
 /* Current batched shape for `quality` and a batch of `count` atlases on the
- * current device (shape[3] as above); the number of candidate shapes the
+ * current device (shape[5] as above); the number of candidate shapes the
  * tuner tries. */
 int tabi_many_shape(int32_t quality, int32_t count, int32_t* shape);
 int32_t tabi_many_shape_count(void);

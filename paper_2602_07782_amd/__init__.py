@@ -182,9 +182,10 @@ class Batch:
     def tune(self, stream=None, reps=2):
         """tabi_tune_many on this batch: times every candidate batched shape
         and keeps the fastest for this quality on the device.  Returns
-        {"shape": (slots per round, threads, LDS cap), "ms": [per shape]}."""
+        {"shape": (first-round slots, rounds at that size, largest slots,
+        threads, LDS cap), "ms": [per shape]}."""
         n = int(lib().tabi_many_shape_count())
-        shape = (ctypes.c_int32 * 3)()
+        shape = (ctypes.c_int32 * 5)()
         ms = (ctypes.c_float * n)()
         _check(lib().tabi_tune_many(_ptr(self.xy), _ptr(self.voff), _ptr(self.aoff), self.count,
                                     _ptr(self.wh), self.total, self.max_charts, self.max_side,
@@ -215,9 +216,10 @@ class Batch:
 
 
 def many_shape(quality, count=256):
-    """Current batched shape (slots per round, threads, LDS cap) on this device
-    for a batch of `count` atlases."""
-    shape = (ctypes.c_int32 * 3)()
+    """Current batched shape (first-round slots, rounds at that size, largest
+    slots per round, threads, LDS cap) on this device for a batch of `count`
+    atlases."""
+    shape = (ctypes.c_int32 * 5)()
     _check(lib().tabi_many_shape(int(quality), int(count), shape))
     return tuple(int(v) for v in shape)
 

@@ -2,6 +2,7 @@
 // launch sequence.  Implements the C ABI declared in include/tabi.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <stdint.h>
 #include <string.h>
@@ -206,6 +207,8 @@ Params make_params(int count, int N, int q, int p, int B, int fixed_k, int nmax,
   P.q = q;
   P.p = p;
   P.B = B;
+  P.Br = B;
+  P.koff = 0;
   P.stride = kchart_stride(P.K);
   P.fixed_k = fixed_k;
   P.nmax = nmax;
@@ -280,11 +283,18 @@ hipError_t run_front(Job& j, const int32_t* xy, const int32_t* voff, const int32
   return e;
 }
 
-// rounds of B descending scales per atlas until each atlas has its answer
-hipError_t run_search(Job& j, int rounds, int32_t* out_xy, uint8_t* out_orient, float* out_scale,
-                      hipStream_t st) {
+// rounds of descending scales per atlas until each atlas has its answer:
+// round r evaluates slots[r] scales below those of the earlier rounds
+hipError_t run_search(Job& j, const int* slots, int rounds, int32_t* out_xy, uint8_t* out_orient,
+                      float* out_scale, hipStream_t st) {
   hipError_t e = hipSuccess;
+  const Params P0 = j.P;
+  int koff = 0;
   for (int r = 0; r < rounds && e == hipSuccess; ++r) {
+    j.P = P0;
+    j.P.Br = slots[r];
+    j.P.koff = koff;
+    koff += slots[r];
     {
       StageScope t(ST_SETUP, st);
       e = launch_setup(j.P, j.W, r, st);
@@ -302,19 +312,43 @@ hipError_t run_search(Job& j, int rounds, int32_t* out_xy, uint8_t* out_orient, 
       e = launch_select(j.P, j.W, r, r == rounds - 1, out_xy, out_orient, out_scale, st);
     }
   }
+  j.P = P0;
   return e;
 }
 
-// Batched shape: scale slots per round, fold-and-push workgroup size, and
-// the shared-memory cap of that workgroup (78 KB lets two 512-thread
-// workgroups share a CU; 0 = the device limit).  Chosen per device and
-// quality by tabi_tune_many; the first entry is the default.
+// Batched shape: the round schedule (b0 scale slots per round for the first
+// `flat` rounds, then doubling up to bmax, until the 64 candidate scales are
+// covered: rounds far from an atlas's area bound cost fewer round trips),
+// the fold-and-push workgroup size, and the shared-memory cap of that
+// workgroup (78 KB lets two 512-thread workgroups share a CU; 0 = the device
+// limit).  Chosen per device, quality and batch size class by
+// tabi_tune_many; the first entry is the default.
 struct ManyShape {
-  int B, nt, cap;
+  int b0, flat, bmax, nt, cap;
 };
-const ManyShape kManyShapes[] = {{8, 512, 78 * 1024}, {4, 512, 78 * 1024}, {16, 512, 78 * 1024},
-                                 {8, 1024, 0},        {16, 1024, 0}};
+const ManyShape kManyShapes[] = {
+    {8, 64, 8, 512, 78 * 1024}, {4, 64, 4, 512, 78 * 1024}, {16, 64, 16, 512, 78 * 1024},
+    {8, 64, 8, 1024, 0},        {16, 64, 16, 1024, 0},      {4, 2, 32, 512, 78 * 1024},
+    {4, 3, 16, 512, 78 * 1024}};
 constexpr int kNumManyShapes = (int)(sizeof(kManyShapes) / sizeof(kManyShapes[0]));
+
+// slots per round of a schedule; returns the number of rounds (<= 64)
+int schedule(const ManyShape& sh, int* slots) {
+  int r = 0, covered = 0;
+  while (covered < 64) {
+    const int b = r < sh.flat ? sh.b0 : std::min(sh.bmax, sh.b0 << std::min(r - sh.flat + 1, 6));
+    slots[r++] = b;
+    covered += b;
+  }
+  return r;
+}
+int schedule_max(const ManyShape& sh) {
+  int slots[64];
+  const int n = schedule(sh, slots);
+  int m = 1;
+  for (int i = 0; i < n; ++i) m = std::max(m, slots[i]);
+  return m;
+}
 // batch size classes: up to 8 atlases, up to 64, more
 constexpr int kShapeClasses = 3;
 int shape_class(int count) { return count <= 8 ? 0 : (count <= 64 ? 1 : 2); }
@@ -356,7 +390,7 @@ int many_check(const int32_t* xy, const int32_t* vert_offsets, const int32_t* at
 Params many_params(int32_t count, int32_t total_charts, int32_t max_charts, int32_t max_side,
                    int32_t padding, int32_t quality) {
   const ManyShape sh = many_shape(quality, count);
-  Params P = make_params(count, total_charts, quality, padding, sh.B, 0,
+  Params P = make_params(count, total_charts, quality, padding, schedule_max(sh), 0,
                          max_charts > 0 ? max_charts : 1, max_side + padding);
   P.pack_nt = sh.nt;
   return P;
@@ -396,8 +430,9 @@ int pack_many_impl(const int32_t* xy, const int32_t* vert_offsets, const int32_t
   } else {
     e = run_front(j, xy, vert_offsets, atlas_offsets, atlas_wh, 0, 0, st);
   }
-  if (e == hipSuccess) e = run_search(j, (64 + j.P.B - 1) / j.P.B, out_xy, out_orient,
-                                      out_scale, st);
+  int slots[64];
+  const int rounds = schedule(sh, slots);
+  if (e == hipSuccess) e = run_search(j, slots, rounds, out_xy, out_orient, out_scale, st);
   if (e != hipSuccess) rc = hip_fail(e);
   free_job(j, st);
   return rc;
@@ -425,7 +460,8 @@ int tabi_pack(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atl
                     st);
   if (!rc) rc = single_front(j, charts, atlas_w, atlas_h, st);
   if (!rc) {
-    hipError_t e = run_search(j, 1, out_xy, out_orient, out_scale, st);
+    const int all[1] = {64};
+    hipError_t e = run_search(j, all, 1, out_xy, out_orient, out_scale, st);
     if (e != hipSuccess) rc = hip_fail(e);
   }
   free_job(j, st);
@@ -489,9 +525,8 @@ int tabi_tune_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t
   set_many_shape(quality, shape_class(count), best >= 0 ? best : 0);
   if (rc == TABI_OK && best < 0) rc = TABI_EINVAL;
   if (rc == TABI_OK && shape) {
-    shape[0] = kManyShapes[best].B;
-    shape[1] = kManyShapes[best].nt;
-    shape[2] = kManyShapes[best].cap;
+    const ManyShape& b = kManyShapes[best];
+    shape[0] = b.b0; shape[1] = b.flat; shape[2] = b.bmax; shape[3] = b.nt; shape[4] = b.cap;
   }
   return rc;
 }
@@ -499,9 +534,7 @@ int tabi_tune_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t
 int tabi_many_shape(int32_t quality, int32_t count, int32_t* shape) {
   if (!shape || quality < 0 || quality > 2 || count < 0) return TABI_EINVAL;
   const ManyShape sh = many_shape(quality, count);
-  shape[0] = sh.B;
-  shape[1] = sh.nt;
-  shape[2] = sh.cap;
+  shape[0] = sh.b0; shape[1] = sh.flat; shape[2] = sh.bmax; shape[3] = sh.nt; shape[4] = sh.cap;
   return TABI_OK;
 }
 

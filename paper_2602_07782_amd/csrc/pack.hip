@@ -545,7 +545,7 @@ __global__ __launch_bounds__(256) void k_select(Params P, Work w, int round, int
   if (threadIdx.x < WAVE) {  // lane s reads slot s (at most 64 slots)
     const bool live = !d.bad && d.n > 0 && d.ktop >= 1;
     const int s = threadIdx.x;
-    const int f = live && s < P.B ? w.feas[a * P.B + s] : 0;
+    const int f = live && s < P.Br ? w.feas[a * P.B + s] : 0;
     const uint64_t ok = ballot64(f == 1);
     const int best = ok ? __builtin_ctzll(ok) : -1;
     const int limit = ballot64(f == -2) != 0;
@@ -553,7 +553,7 @@ __global__ __launch_bounds__(256) void k_select(Params P, Work w, int round, int
       s_best = best;
       s_limit = limit;
       // more candidate scales remain for a later round
-      s_more = live && best < 0 && !limit && !last_round && slot_k(P, d, round, P.B - 1) > 1;
+      s_more = live && best < 0 && !limit && !last_round && slot_k(P, d, round, P.Br - 1) > 1;
     }
   }
   __syncthreads();
@@ -649,10 +649,10 @@ hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes,
                        int stage_cap, hipStream_t st) {
   // one atlas: latency matters, use the wider workgroup (batches: as tuned)
   if (P.pack_nt == 1024 || (P.pack_nt == 0 && P.count == 1))
-    hipLaunchKernelGGL(k_pack<1024>, dim3(P.B, P.count), dim3(1024), lds_bytes, st, P, w, round,
+    hipLaunchKernelGGL(k_pack<1024>, dim3(P.Br, P.count), dim3(1024), lds_bytes, st, P, w, round,
                        RC, PW, stage_cap);
   else
-    hipLaunchKernelGGL(k_pack<512>, dim3(P.B, P.count), dim3(512), lds_bytes, st, P, w, round, RC,
+    hipLaunchKernelGGL(k_pack<512>, dim3(P.Br, P.count), dim3(512), lds_bytes, st, P, w, round, RC,
                        PW, stage_cap);
   return hipGetLastError();
 }

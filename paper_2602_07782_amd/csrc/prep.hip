@@ -571,7 +571,7 @@ hipError_t launch_plan(const Params&, const Work&, hipStream_t) { return hipSucc
 hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t st) {
   if (P.N > 0)
   {
-    const dim3 grid((P.N + SETUP_NT - 1) / SETUP_NT, P.B);
+    const dim3 grid((P.N + SETUP_NT - 1) / SETUP_NT, P.Br);
     if (P.K == 10) hipLaunchKernelGGL(k_setup<10>, grid, dim3(SETUP_NT), 0, st, P, w, round);
     else if (P.K == 5) hipLaunchKernelGGL(k_setup<5>, grid, dim3(SETUP_NT), 0, st, P, w, round);
     else hipLaunchKernelGGL(k_setup<2>, grid, dim3(SETUP_NT), 0, st, P, w, round);

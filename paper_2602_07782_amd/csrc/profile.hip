@@ -218,7 +218,7 @@ __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) 
 __global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w) {
   __shared__ int64_t s_tot[ALLOC_NT / WAVE];
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
-  const int64_t total = (int64_t)P.count * P.B;
+  const int64_t total = (int64_t)P.count * P.Br;  // this round's segments
   int64_t run = 0;
   for (int64_t q0 = 0; q0 < total; q0 += ALLOC_NT) {
     const int64_t q = q0 + tid;
@@ -475,9 +475,9 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
 hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_t st) {
   if (P.N <= 0) return hipSuccess;
   // with no arena the placement still runs: it marks every segment unstored
-  hipLaunchKernelGGL(k_layout, dim3(P.count, P.B), dim3(LAY_NT), 0, st, P, w, round);
+  hipLaunchKernelGGL(k_layout, dim3(P.count, P.Br), dim3(LAY_NT), 0, st, P, w, round);
   hipLaunchKernelGGL(k_alloc, dim3(1), dim3(ALLOC_NT), 0, st, P, w);
-  const dim3 grid((P.N + PROF_CH - 1) / PROF_CH, P.B);
+  const dim3 grid((P.N + PROF_CH - 1) / PROF_CH, P.Br);
   if (P.K == 10) hipLaunchKernelGGL(k_profile<10>, grid, dim3(PROF_NT), 0, st, P, w, round);
   else if (P.K == 5) hipLaunchKernelGGL(k_profile<5>, grid, dim3(PROF_NT), 0, st, P, w, round);
   else hipLaunchKernelGGL(k_profile<2>, grid, dim3(PROF_NT), 0, st, P, w, round);

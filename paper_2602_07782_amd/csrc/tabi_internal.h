@@ -25,7 +25,9 @@ struct Params {
   int32_t K;           // local AABB slices per axis
   int32_t q;           // quality preset
   int32_t p;           // padding
-  int32_t B;           // scale slots per round
+  int32_t B;           // scale slots of the largest round (stride of the per-slot arrays)
+  int32_t Br;          // scale slots of the current round (<= B)
+  int32_t koff;        // candidate scales the earlier rounds covered
   int32_t stride;      // bytes of one per-(scale, chart) record
   int32_t fixed_k;     // > 0: evaluate exactly this scale in slot 0 (diagnostics)
   int32_t nmax;        // largest chart count of one atlas the work space was sized for
@@ -62,10 +64,12 @@ struct Work {
                         // (left, right), int16 pairs (pack16)
 };
 
-// scale of slot s of round r for an atlas
+// scale of slot s of the current round for an atlas (< 1: the slot does not
+// run); round r covers scales k_top - koff - s, s < Br
 __host__ __device__ inline int32_t slot_k(const Params& P, const AtlasDesc& d, int r, int s) {
+  (void)r;
   if (P.fixed_k > 0) return s == 0 ? P.fixed_k : 0;
-  return d.ktop - r * P.B - s;
+  return s < P.Br ? d.ktop - P.koff - s : 0;
 }
 
 // Launchers (one per kernel), all enqueue on `st`.
