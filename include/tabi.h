@@ -230,6 +230,14 @@ int tabi_debug_set_stage_cap(int32_t entries);
  * process, including tabi_pack_many_workspace_bytes. */
 int tabi_debug_set_profile_cap(int64_t words);
 
+/* Returns to the device the memory that earlier calls left in the current
+ * device's stream-ordered pool (work spaces are taken from that pool and kept
+ * there between calls so that later calls reuse them).  Waits for all work on
+ * the device first, so no call may be in flight on another thread.  The
+ * library stays usable; the next call takes fresh memory.  TABI_EHIP if the
+ * device or its pool is unavailable. */
+int tabi_shutdown(void);
+
 /* Text for a return code; last HIP error string seen by the library. */
 const char* tabi_strerror(int code);
 const char* tabi_last_hip_error(void);

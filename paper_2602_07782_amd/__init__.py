@@ -37,7 +37,8 @@ EXPORTS = ["tabi_pack", "tabi_pack_many", "tabi_pack_many_ws", "tabi_pack_many_w
            "tabi_debug_feasible", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
            "tabi_timing_enable", "tabi_timing_read", "tabi_timing_reset",
            "tabi_debug_set_stage_cap", "tabi_debug_set_profile_cap", "tabi_tune_many",
-           "tabi_many_shape", "tabi_many_shape_count", "tabi_debug_set_many_shape"]
+           "tabi_many_shape", "tabi_many_shape_count", "tabi_debug_set_many_shape",
+           "tabi_shutdown"]
 STAGES = ["prep", "sort", "setup", "profile", "pack", "select"]
 
 
@@ -331,6 +332,12 @@ def pack_many_records(records, atlas_offsets, atlas_wh, max_charts, max_side, pa
                                         N, int(max_charts), int(max_side), int(padding),
                                         int(quality), _ptr(out_xy), _ptr(out_orient),
                                         _ptr(out_scale), _stream(stream)))
+
+
+def shutdown():
+    """tabi_shutdown: return the library's pooled work space to the device
+    (waits for the device); later calls still work."""
+    _check(lib().tabi_shutdown())
 
 
 def debug_set_stage_cap(entries):

@@ -682,6 +682,16 @@ int tabi_debug_feasible(const tabi_charts* charts, int32_t n, int32_t atlas_w, i
   return rc;
 }
 
+int tabi_shutdown(void) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  hipMemPool_t pool;
+  if (e == hipSuccess) e = hipDeviceGetDefaultMemPool(&pool, dev);
+  if (e == hipSuccess) e = hipMemPoolTrimTo(pool, 0);
+  return e == hipSuccess ? TABI_OK : hip_fail(e);
+}
+
 const char* tabi_strerror(int code) {
   switch (code) {
     case TABI_OK: return "ok";

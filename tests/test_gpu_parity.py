@@ -232,3 +232,15 @@ def test_pack_parity_padding_range(tabi, orc, p):
     cd, fl = tabi.debug_pairs(inp.xy, inp.offsets, p, inp.quality, 40)
     ocd, ofl = orc.pairs(inp, 40)
     assert np.array_equal(_np(cd), ocd) and np.array_equal(_np(fl), ofl)
+
+
+def test_shutdown_releases_pool_and_library_stays_usable(tabi, orc):
+    """tabi_shutdown returns the pooled work space; the next pack allocates
+    afresh and gives the same result."""
+    inp = small_input(900)
+    before = gpu_pack(tabi, inp)
+    tabi.shutdown()
+    after = gpu_pack(tabi, inp)
+    assert before[2] == after[2]
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    assert_pack_equal(tabi, orc, inp, "after shutdown")
