@@ -146,3 +146,39 @@ def test_tuner_keeps_results(tabi):
                 assert np.array_equal(x, y), use_ws
     finally:
         tabi.debug_set_many_shape(q, -1)
+
+
+@pytest.mark.parametrize("q,p", [(0, 0), (1, 5)])
+def test_batch_other_quality_and_padding(tabi, orc, q, p):
+    """Fewer slices per axis and other gutters through the batched path."""
+    rng = np.random.default_rng(940 + q)
+    mix = synth.CONFIGS["mixed2k"]["mix"]
+    inputs = [synth.make_custom(int(rng.integers(20, 300)), int(s), int(s), p, q, 1.2, 1.2, mix,
+                                9400 + 10 * q + a)
+              for a, s in enumerate(rng.choice([256, 512, 1024], size=6))]
+    _say("batch q", q, "p", p, [i.n for i in inputs])
+    check_batch(tabi, orc, inputs)
+
+
+@pytest.mark.parametrize("shape", [0, 5])
+def test_large_batch_equals_single_packs(tabi, shape):
+    """A batch of more than 64 atlases (its own shape class) under the
+    default shape and under a doubling round schedule equals one tabi_pack
+    per atlas."""
+    inputs = small_batch(72, 950, nmin=20, nmax=200, sides=(256, 512))
+    q = inputs[0].quality
+    try:
+        tabi.debug_set_many_shape(q, shape)
+        _say("large batch shape", tabi.many_shape(q, len(inputs)))
+        xy, ori, sc = [t.cpu().numpy() for t in tabi.pack_many(inputs)]
+    finally:
+        tabi.debug_set_many_shape(q, -1)
+    c0 = 0
+    for a, inp in enumerate(inputs):
+        pxy, por, psc = tabi.pack(inp.xy, inp.offsets, inp.atlas_w, inp.atlas_h, inp.padding,
+                                  inp.quality)
+        n = inp.n
+        assert float(sc[a]) == float(psc.cpu().numpy()[0]), a
+        assert np.array_equal(xy[c0:c0 + n], pxy.cpu().numpy()), a
+        assert np.array_equal(ori[c0:c0 + n], por.cpu().numpy()), a
+        c0 += n
