@@ -472,8 +472,9 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     // read of the frontline in this row (push, knee region maximum) happened
     // before the barrier of the score reduction, and the reduction slots and
     // offsets read since are next written after the loop's opening barrier.
+    // (wavefronts 1.. commit while wavefront 0 runs the knee detection below)
     const int Ew = Xoff[w_cnt];
-    for (int e = tid; e < Ew; e += PACK_NT) {
+    for (int e = tid - WAVE; wv > 0 && e < Ew; e += PACK_NT - WAVE) {
       int t;
       int32_t tp, bt;
       texel(e, t, tp, bt);
@@ -482,7 +483,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       const int col = w_dir == DIR_LR ? w_R0 + X + i : w_R1 - 1 - X - i;
       atomicMax(&F[col], Yw[t] + bt);
     }
-    for (int t = tid; t < w_cnt; t += PACK_NT) {
+    for (int t = tid - WAVE; wv > 0 && t < w_cnt; t += PACK_NT - WAVE) {
       const int X = w_hc ? Xon[t] : Xoff[t];
       const int wd = Xoff[t + 1] - Xoff[t];
       xs[rs + t] = w_dir == DIR_LR ? w_R0 + X : w_R1 - X - wd;
