@@ -362,8 +362,11 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     __syncthreads();
     const int lrn = min(s_lrn, LRCAP);
     if (s_lrover) { feasible = -2; break; }
-    // ---- 4. push every configuration against the committed frontline
-    for (int e0 = wv * WAVE; e0 < E; e0 += PACK_NT) {
+    // ---- 4. push every configuration against the committed frontline; the
+    // last wavefronts (at most a quarter) sweep the non-neighbour pairs at
+    // the same time
+    const int nlr = min(lrn, PACK_WAVES / 4), npush = PACK_WAVES - nlr;
+    for (int e0 = wv * WAVE; wv < npush && e0 < E; e0 += npush * WAVE) {
       const int e = e0 + lane;
       const bool valid = e < E;
       int t = -1;
@@ -388,7 +391,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       }
     }
     // interlock flags of the non-neighbour pairs, read only by the correction
-    for (int q = wv; q < lrn; q += PACK_WAVES) {
+    for (int q = wv - npush; wv >= npush && q < lrn; q += nlr) {
       const int A = s_lr[q][0], C = s_lr[q][1];
       const int wdA = Xoff[A + 1] - Xoff[A];
       PairSweep sw;
