@@ -141,6 +141,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   __shared__ int32_t s_cnt[4];
   __shared__ int32_t s_red[PACK_WAVES * 6];
   __shared__ int32_t s_knee[4];  // knee found by the last row's detection: on, direction, span
+  __shared__ uint32_t s_touch;   // keeps the next row's cache warm-up loads (never read)
   __shared__ int32_t s_lrn, s_lrover;
   __shared__ int32_t s_lr[LRCAP][3];
   // window of chart data read by the fold and the knee test, charts
@@ -197,6 +198,9 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   // charts of a segment are stored back to back, so it advances by the
   // committed grown width
   int32_t pc0 = n > 0 ? sbase : -1;
+  // end of the segment's column area (its rows follow): the cache warm-up
+  // loads for the next row never read past it
+  const int32_t colend = pc0 >= 0 ? sbase + prowv[0] : 0;
 
   for (;;) {
     __syncthreads();
@@ -366,6 +370,18 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     // last wavefronts (at most a quarter) sweep the non-neighbour pairs at
     // the same time
     const int nlr = min(lrn, PACK_WAVES / 4), npush = PACK_WAVES - nlr;
+    // bring the words after this row's range (where the next row's range
+    // ends) into the caches while the push runs, so that the next row's
+    // staging copy hits them; the sum is consumed only after the push
+    uint32_t t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+    if (staged) {
+      const int L = min(Wd + Wd / 2, colend - (pc0 + E));
+      const uint32_t* g = gprof + E;
+      if (tid < L) t0 = g[tid];
+      if (tid + PACK_NT < L) t1 = g[tid + PACK_NT];
+      if (tid + 2 * PACK_NT < L) t2 = g[tid + 2 * PACK_NT];
+      if (tid + 3 * PACK_NT < L) t3 = g[tid + 3 * PACK_NT];
+    }
     for (int e0 = wv * WAVE; wv < npush && e0 < E; e0 += npush * WAVE) {
       const int e = e0 + lane;
       const bool valid = e < E;
@@ -390,6 +406,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
         if (tail && v > -BIG) atomicMax(&Yb[yofs[j] + t], v);
       }
     }
+    if ((t0 ^ t1 ^ t2 ^ t3) == 0x9e3779b9u) s_touch = t0;
     // interlock flags of the non-neighbour pairs, read only by the correction
     for (int q = wv - npush; wv >= npush && q < lrn; q += nlr) {
       const int A = s_lr[q][0], C = s_lr[q][1];
