@@ -106,7 +106,8 @@ struct StageScope {  // brackets one stage's launches with a pair of events
 // ---- work space -------------------------------------------------------------
 struct Layout {
   size_t o_recs, o_srecs, o_keys, o_rank, o_perm, o_ca, o_desc, o_kc, o_cd, o_fl, o_xs, o_ys, o_mir,
-      o_feas, o_rows, o_wdv, o_hdv, o_pcol, o_prow, o_Hs, o_segneed, o_segbase, o_arena, total;
+      o_feas, o_rows, o_wdv, o_hdv, o_pcol, o_prow, o_Hs, o_segneed, o_segbase, o_cnt, o_arena,
+      total;
 };
 
 // Profile arena words for B scale slots over N charts in `count` atlases of
@@ -157,6 +158,7 @@ Layout layout(const Params& P) {
   L.o_Hs = take(n1 * 4);
   L.o_segneed = take((size_t)P.count * P.B * 8);
   L.o_segbase = take((size_t)P.count * P.B * 4);
+  L.o_cnt = take((size_t)P.count * 4);
   L.o_arena = take((size_t)P.arena_cap * 4);
   L.total = off;
   return L;
@@ -187,6 +189,7 @@ Work carve(void* base, const Layout& L) {
   W.Hs = reinterpret_cast<int32_t*>(b + L.o_Hs);
   W.segneed = reinterpret_cast<int64_t*>(b + L.o_segneed);
   W.segbase = reinterpret_cast<int32_t*>(b + L.o_segbase);
+  W.cnt = reinterpret_cast<int32_t*>(b + L.o_cnt);
   W.arena = reinterpret_cast<uint32_t*>(b + L.o_arena);
   return W;
 }
@@ -303,11 +306,12 @@ hipError_t run_search(Job& j, const int* slots, int rounds, int32_t* out_xy, uin
       StageScope t(ST_PROFILE, st);
       e = launch_profiles(j.P, j.W, r, st);
     }
-    if (e == hipSuccess) {
+    if (e == hipSuccess) {  // with the scale selection of a single atlas
       StageScope t(ST_PACK, st);
-      e = launch_pack(j.P, j.W, r, j.L.bytes, j.L.RC, j.L.PW, j.stage_cap, st);
+      e = launch_pack(j.P, j.W, r, j.L.bytes, j.L.RC, j.L.PW, j.stage_cap, r == rounds - 1, out_xy,
+                      out_orient, out_scale, st);
     }
-    if (e == hipSuccess) {
+    if (e == hipSuccess && j.P.count > 1) {
       StageScope t(ST_SELECT, st);
       e = launch_select(j.P, j.W, r, r == rounds - 1, out_xy, out_orient, out_scale, st);
     }
@@ -675,7 +679,8 @@ int tabi_debug_feasible(const tabi_charts* charts, int32_t n, int32_t atlas_w, i
   if (!rc) e = launch_setup(j.P, j.W, 0, st);
   if (!rc && e == hipSuccess) e = launch_profiles(j.P, j.W, 0, st);
   if (!rc && e == hipSuccess)
-    e = launch_pack(j.P, j.W, 0, j.L.bytes, j.L.RC, j.L.PW, j.stage_cap, st);
+    e = launch_pack(j.P, j.W, 0, j.L.bytes, j.L.RC, j.L.PW, j.stage_cap, 1, nullptr, nullptr,
+                    nullptr, st);
   if (!rc && e == hipSuccess) e = launch_scatter(j.P, j.W, out_xy, out_orient, feasible, rows, st);
   if (!rc && e != hipSuccess) rc = hip_fail(e);
   free_job(j, st);

@@ -130,12 +130,65 @@ __device__ inline int32_t block_reduce_min(int32_t v, int32_t* red) {
   return r;
 }
 
+// Largest feasible scale of this round for atlas a (one workgroup, any size
+// of at least one wavefront); outputs in input order.  sh: 3 ints of shared
+// memory.
+__device__ void select_atlas(const Params& P, const Work& w, int round, int last_round, int a,
+                             int32_t* out_xy, uint8_t* out_orient, float* out_scale, int32_t* sh) {
+  const AtlasDesc d = w.desc[a];
+  if (d.done) return;
+  if (threadIdx.x < WAVE) {  // lane s reads slot s (at most 64 slots)
+    const bool live = !d.bad && d.n > 0 && d.ktop >= 1;
+    const int s = threadIdx.x;
+    const int f = live && s < P.Br ? w.feas[a * P.B + s] : 0;
+    const uint64_t ok = ballot64(f == 1);
+    const int best = ok ? __builtin_ctzll(ok) : -1;
+    const int limit = ballot64(f == -2) != 0;
+    if (threadIdx.x == 0) {
+      sh[0] = best;
+      sh[1] = limit;
+      // more candidate scales remain for a later round
+      sh[2] = live && best < 0 && !limit && !last_round && slot_k(P, d, round, P.Br - 1) > 1;
+    }
+  }
+  __syncthreads();
+  const int best = sh[0], limit = sh[1];
+  if (sh[2]) return;
+  float scale;
+  int kstar = 0;
+  if (d.bad) scale = -1.0f;
+  else if (d.n == 0) { scale = 1.0f; kstar = 64; }
+  else if (limit) scale = -2.0f;
+  else if (best >= 0) { kstar = slot_k(P, d, round, best); scale = (float)kstar / 64.0f; }
+  else scale = 0.0f;
+  const size_t slot = (size_t)(best >= 0 ? best : 0) * P.N;
+  for (int t = threadIdx.x; t < d.n; t += blockDim.x) {
+    const int c = d.c0 + t;
+    const int dst = d.c0 + w.perm[c];
+    if (kstar > 0 && best >= 0) {
+      out_xy[2 * (size_t)dst] = w.xs[slot + c];
+      out_xy[2 * (size_t)dst + 1] = w.ys[slot + c];
+      out_orient[dst] = (uint8_t)(w.srecs[c].bits | (w.mir[slot + c] << 3));
+    } else {
+      out_xy[2 * (size_t)dst] = -1;
+      out_xy[2 * (size_t)dst + 1] = -1;
+      out_orient[dst] = 0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    out_scale[a] = scale;
+    w.desc[a].done = 1;
+    w.desc[a].kstar = kstar;
+  }
+}
+
 // PACK_NT threads per workgroup: 1024 for a single pack (every per-texel
 // phase of a row spread over 16 wavefronts), 512 for batches (two workgroups
 // per CU when their shared memory allows it).  At most 128 VGPRs either way.
 template <int PACK_NT>
 __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) void k_pack(
-    Params P, Work w, int round, int RC, int PW, int stage_cap) {
+    Params P, Work w, int round, int RC, int PW, int stage_cap, int last_round, int32_t* out_xy,
+    uint8_t* out_orient, float* out_scale) {
   constexpr int PACK_WAVES = PACK_NT / WAVE;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t s_cnt[4];
@@ -154,14 +207,15 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   const AtlasDesc d = w.desc[a];
   const int k = slot_k(P, d, round, s);
   const bool run = P.fixed_k > 0 ? (k >= 1 && !d.bad) : (!d.done && d.ktop >= 1 && k >= 1);
-  if (!run) {
-    if (tid == 0) { w.feas[a * P.B + s] = -1; w.rows[a * P.B + s] = 0; }
-    return;
-  }
+  // outcome of this (atlas, scale): 1 feasible, 0 not, -1 not run, -2 the
+  // atlas exceeds the shape the call was sized for; rows placed
+  int feasible = -1, rows = 0;
+  do {  // every workgroup reaches the epilogue below
+  if (!run) break;
   const int n = d.n, Wd = d.Wa + P.p, Hd = d.Ha + P.p, Ha = d.Ha, p = P.p, K = P.K;
   if (n > P.nmax || Wd > P.Wdmax) {  // batch larger than the caller's declared shape
-    if (tid == 0) { w.feas[a * P.B + s] = -2; w.rows[a * P.B + s] = 0; }
-    return;
+    feasible = -2;
+    break;
   }
   const int topt = P.q == 0 ? 5 : (P.q == 1 ? 2 : (n > 10000 ? 1 : 0));
   const size_t slot = (size_t)s * P.N + d.c0;
@@ -189,7 +243,8 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   for (int t = tid; t < n; t += PACK_NT) { xs[t] = -1; ys[t] = -1; mir[t] = 0; }
 
   // per-row state, identical in every thread
-  int rs = 0, rows = 0, feasible = 1, tail = 0, trow = 0;
+  int rs = 0, tail = 0, trow = 0;
+  feasible = 1;
   int kn = 0, kdir = 0, kl = 0, kr = 0;
   if (tid == 0) s_knee[0] = -1;
   int32_t fmax = 0;
@@ -549,63 +604,33 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     rs += w_cnt;
     if (pc0 >= 0) pc0 += Ew;
   }
+  } while (false);
   if (tid == 0) {
     w.feas[a * P.B + s] = feasible;
     w.rows[a * P.B + s] = rows;
   }
+  // Single atlas: the last of its workgroups to finish selects the scale and
+  // writes the outputs (no separate launch).  Every workgroup publishes its
+  // results, then counts itself; the counter is zeroed again by the last
+  // one.  Batches launch the selection instead: a device-wide fence in each
+  // of their many workgroups costs more than the launch it saves.
+  if (P.fixed_k > 0 || P.count != 1) return;
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_cnt[0] = atomicAdd(&w.cnt[a], 1) == P.Br - 1;
+  __syncthreads();
+  if (!s_cnt[0]) return;
+  __threadfence();
+  if (tid == 0) w.cnt[a] = 0;
+  select_atlas(P, w, round, last_round, a, out_xy, out_orient, out_scale, s_red);
 }
 
-// Largest feasible scale of this round per atlas; outputs in input order.
+// Scale selection of every atlas of a batch, one workgroup per atlas.
 __global__ __launch_bounds__(256) void k_select(Params P, Work w, int round, int last_round,
                                                 int32_t* out_xy, uint8_t* out_orient,
                                                 float* out_scale) {
-  __shared__ int s_best, s_limit, s_more;
-  const int a = blockIdx.x;
-  const AtlasDesc d = w.desc[a];
-  if (d.done) return;
-  if (threadIdx.x < WAVE) {  // lane s reads slot s (at most 64 slots)
-    const bool live = !d.bad && d.n > 0 && d.ktop >= 1;
-    const int s = threadIdx.x;
-    const int f = live && s < P.Br ? w.feas[a * P.B + s] : 0;
-    const uint64_t ok = ballot64(f == 1);
-    const int best = ok ? __builtin_ctzll(ok) : -1;
-    const int limit = ballot64(f == -2) != 0;
-    if (threadIdx.x == 0) {
-      s_best = best;
-      s_limit = limit;
-      // more candidate scales remain for a later round
-      s_more = live && best < 0 && !limit && !last_round && slot_k(P, d, round, P.Br - 1) > 1;
-    }
-  }
-  __syncthreads();
-  const int best = s_best;
-  if (s_more) return;
-  float scale;
-  int kstar = 0;
-  if (d.bad) scale = -1.0f;
-  else if (d.n == 0) { scale = 1.0f; kstar = 64; }
-  else if (s_limit) scale = -2.0f;
-  else if (best >= 0) { kstar = slot_k(P, d, round, best); scale = (float)kstar / 64.0f; }
-  else scale = 0.0f;
-  const size_t slot = (size_t)(best >= 0 ? best : 0) * P.N;
-  for (int t = threadIdx.x; t < d.n; t += blockDim.x) {
-    const int c = d.c0 + t;
-    const int dst = d.c0 + w.perm[c];
-    if (kstar > 0 && best >= 0) {
-      out_xy[2 * (size_t)dst] = w.xs[slot + c];
-      out_xy[2 * (size_t)dst + 1] = w.ys[slot + c];
-      out_orient[dst] = (uint8_t)(w.srecs[c].bits | (w.mir[slot + c] << 3));
-    } else {
-      out_xy[2 * (size_t)dst] = -1;
-      out_xy[2 * (size_t)dst + 1] = -1;
-      out_orient[dst] = 0;
-    }
-  }
-  if (threadIdx.x == 0) {
-    out_scale[a] = scale;
-    w.desc[a].done = 1;
-    w.desc[a].kstar = kstar;
-  }
+  __shared__ int32_t sh[3];
+  select_atlas(P, w, round, last_round, blockIdx.x, out_xy, out_orient, out_scale, sh);
 }
 
 // Placements of the single diagnostic scale (slot 0, atlas 0) in input order.
@@ -666,23 +691,26 @@ hipError_t pack_set_max_lds(int bytes) {
                              bytes);
 }
 
-hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes, int RC, int PW,
-                       int stage_cap, hipStream_t st) {
-  // one atlas: latency matters, use the wider workgroup (batches: as tuned)
-  if (P.pack_nt == 1024 || (P.pack_nt == 0 && P.count == 1))
-    hipLaunchKernelGGL(k_pack<1024>, dim3(P.Br, P.count), dim3(1024), lds_bytes, st, P, w, round,
-                       RC, PW, stage_cap);
-  else
-    hipLaunchKernelGGL(k_pack<512>, dim3(P.Br, P.count), dim3(512), lds_bytes, st, P, w, round, RC,
-                       PW, stage_cap);
-  return hipGetLastError();
-}
-
 hipError_t launch_select(const Params& P, const Work& w, int round, int last_round,
                          int32_t* out_xy, uint8_t* out_orient, float* out_scale, hipStream_t st) {
+  if (P.count == 1 || P.fixed_k > 0) return hipSuccess;  // done inside k_pack / not wanted
   hipLaunchKernelGGL(k_select, dim3(P.count), dim3(256), 0, st, P, w, round, last_round, out_xy,
                      out_orient, out_scale);
   return hipGetLastError();
 }
+
+hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes, int RC, int PW,
+                       int stage_cap, int last_round, int32_t* out_xy, uint8_t* out_orient,
+                       float* out_scale, hipStream_t st) {
+  // one atlas: latency matters, use the wider workgroup (batches: as tuned)
+  if (P.pack_nt == 1024 || (P.pack_nt == 0 && P.count == 1))
+    hipLaunchKernelGGL(k_pack<1024>, dim3(P.Br, P.count), dim3(1024), lds_bytes, st, P, w, round,
+                       RC, PW, stage_cap, last_round, out_xy, out_orient, out_scale);
+  else
+    hipLaunchKernelGGL(k_pack<512>, dim3(P.Br, P.count), dim3(512), lds_bytes, st, P, w, round, RC,
+                       PW, stage_cap, last_round, out_xy, out_orient, out_scale);
+  return hipGetLastError();
+}
+
 
 }  // namespace tabi

@@ -21,10 +21,11 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ void k_init(Params P, Work w, const int32_t* atlas_off, const int32_t* atlas_wh,
-                       int single_w, int single_h) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= P.count) return;
+// Descriptor of atlas a (the scale bound and the degenerate-chart flag come
+// later, from k_plan).  Called by the first threads of the proxy (or
+// records) kernel, or by k_init when there are no charts.
+__device__ inline void init_desc(const Params& P, const Work& w, const int32_t* atlas_off,
+                                 const int32_t* atlas_wh, int single_w, int single_h, int a) {
   AtlasDesc d;
   if (atlas_off) {
     d.c0 = atlas_off[a];
@@ -42,6 +43,12 @@ __global__ void k_init(Params P, Work w, const int32_t* atlas_off, const int32_t
   d.done = 0;
   d.kstar = 0;
   w.desc[a] = d;
+  if (w.cnt) w.cnt[a] = 0;
+}
+__global__ void k_init(Params P, Work w, const int32_t* atlas_off, const int32_t* atlas_wh,
+                       int single_w, int single_h) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a < P.count) init_desc(P, w, atlas_off, atlas_wh, single_w, single_h, a);
 }
 
 // k_prep: one group of PREP_G lanes (a DPP row) per chart, PREP_CH charts
@@ -117,8 +124,14 @@ __device__ inline void slab_contrib(int32_t* lo, int32_t* hi, int K, int64_t E, 
 
 __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* __restrict__ xy,
                                               const int32_t* __restrict__ voff,
-                                              const int32_t* __restrict__ atlas_off) {
+                                              const int32_t* __restrict__ atlas_off,
+                                              const int32_t* __restrict__ atlas_wh, int single_w,
+                                              int single_h) {
   __shared__ int32_t sl[PREP_CH][4][KMAX];
+  {  // atlas descriptors: thread i of the grid initialises atlas i
+    const int ai = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w.desc && ai < P.count) init_desc(P, w, atlas_off, atlas_wh, single_w, single_h, ai);
+  }
   const int g = threadIdx.x / PREP_G, lane = threadIdx.x % PREP_G;  // lane within the group
   const int base = lane_id() - lane;  // wavefront lane of the group's first lane
   const int c = blockIdx.x * PREP_CH + g;
@@ -157,7 +170,6 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
       out->src = local;
       w.keys[c] = ((uint64_t)0x7fffff << 41) | ((uint64_t)0x7fffff << 18) | (uint64_t)local;
       if (w.rank) w.rank[c] = 0;
-      if (w.desc) atomicOr(&w.desc[a].bad, 1);
     }
     return;
   }
@@ -335,26 +347,29 @@ __global__ __launch_bounds__(256) void k_place(Params P, Work w) {
 // Lane k - 1 of wavefront 0 tests scale k; k_top is the largest passing one.
 __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
   __shared__ uint64_t s_sum[4];
-  __shared__ int32_t s_maxw[4];
+  __shared__ int32_t s_maxw[4], s_bad[4];
   const int a = blockIdx.x, lane = lane_id(), wv = threadIdx.x / WAVE;
   const AtlasDesc d = w.desc[a];
   uint64_t sum = 0;
-  int32_t mw = 0;
+  int32_t mw = 0, bad = 0;  // bad: a degenerate chart (its record is marked invalid)
   for (int t = threadIdx.x; t < d.n; t += blockDim.x) {
     const Chart& ch = w.srecs[d.c0 + t];
     sum += (uint64_t)ch.area2;
     mw = max(mw, ch.W);
+    bad |= !ch.valid;
   }
   sum = wave_sum_u64(sum);
   mw = wave_max(mw);
-  if (lane == 0) { s_sum[wv] = sum; s_maxw[wv] = mw; }
+  bad = wave_max(bad);
+  if (lane == 0) { s_sum[wv] = sum; s_maxw[wv] = mw; s_bad[wv] = bad; }
   __syncthreads();
   if (wv != 0) return;
   unsigned __int128 S = 0;
   int32_t MW = 0;
-  for (int q = 0; q < 4; ++q) { S += s_sum[q]; MW = max(MW, s_maxw[q]); }
+  bad = 0;
+  for (int q = 0; q < 4; ++q) { S += s_sum[q]; MW = max(MW, s_maxw[q]); bad |= s_bad[q]; }
   int ktop = 0;
-  if (d.bad) {
+  if (bad) {
     ktop = -1;
   } else if (d.n == 0) {
     ktop = 64;
@@ -367,7 +382,7 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
     const uint64_t pass = ballot64(area_ok && fit);
     ktop = pass ? 64 - __builtin_clzll(pass) : 0;
   }
-  if (lane == 0) w.desc[a].ktop = ktop;
+  if (lane == 0) { w.desc[a].ktop = ktop; w.desc[a].bad = bad; }
 }
 
 // one thread per (slot, chart)
@@ -491,8 +506,10 @@ __global__ __launch_bounds__(SETUP_NT) void k_setup(Params P, Work w, int round)
 // Start of the packing path from resident proxy records: copy, keys, atlas
 // of each chart, degenerate flags.
 __global__ __launch_bounds__(256) void k_from_records(Params P, Work w, const Chart* __restrict__ in,
-                                                      const int32_t* __restrict__ atlas_off) {
+                                                      const int32_t* __restrict__ atlas_off,
+                                                      const int32_t* __restrict__ atlas_wh) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < P.count) init_desc(P, w, atlas_off, atlas_wh, 0, 0, c);
   if (c >= P.N) return;
   int lo = 0, hi = P.count - 1;
   while (lo < hi) {
@@ -509,7 +526,6 @@ __global__ __launch_bounds__(256) void k_from_records(Params P, Work w, const Ch
     w.keys[c] = ((uint64_t)(0x7fffff - ch.H) << 41) | ((uint64_t)(0x7fffff - ch.W) << 18) | local;
   } else {
     w.keys[c] = ((uint64_t)0x7fffff << 41) | ((uint64_t)0x7fffff << 18) | local;
-    atomicOr(&w.desc[a].bad, 1);
   }
 }
 
@@ -526,11 +542,13 @@ __global__ __launch_bounds__(256) void k_splice(Chart* __restrict__ dst, const i
 
 hipError_t launch_from_records(const Params& P, const Work& w, const Chart* in,
                                const int32_t* atlas_off, const int32_t* atlas_wh, hipStream_t st) {
-  hipLaunchKernelGGL(k_init, dim3((P.count + 255) / 256), dim3(256), 0, st, P, w, atlas_off,
-                     atlas_wh, 0, 0);
+  // the records kernel also writes the atlas descriptors
   if (P.N > 0)
-    hipLaunchKernelGGL(k_from_records, dim3((P.N + 255) / 256), dim3(256), 0, st, P, w, in,
-                       atlas_off);
+    hipLaunchKernelGGL(k_from_records, dim3((max(P.N, P.count) + 255) / 256), dim3(256), 0, st, P,
+                       w, in, atlas_off, atlas_wh);
+  else
+    hipLaunchKernelGGL(k_init, dim3((P.count + 255) / 256), dim3(256), 0, st, P, w, atlas_off,
+                       atlas_wh, 0, 0);
   return hipGetLastError();
 }
 
@@ -542,12 +560,16 @@ hipError_t launch_splice(Chart* dst, const int32_t* idx, int m, const Chart* src
 hipError_t launch_prep(const Params& P, const Work& w, const int32_t* xy, const int32_t* voff,
                        const int32_t* atlas_off, const int32_t* atlas_wh, int single_w,
                        int single_h, hipStream_t st) {
-  if (w.desc)
+  // the proxy kernel also writes the atlas descriptors (enough blocks for
+  // both)
+  if (P.N > 0) {
+    const int blocks = max((P.N + PREP_CH - 1) / PREP_CH, w.desc ? (P.count + 255) / 256 : 0);
+    hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, st, P, w, xy, voff, atlas_off, atlas_wh,
+                       single_w, single_h);
+  } else if (w.desc) {
     hipLaunchKernelGGL(k_init, dim3((P.count + 255) / 256), dim3(256), 0, st, P, w, atlas_off,
                        atlas_wh, single_w, single_h);
-  if (P.N > 0)
-    hipLaunchKernelGGL(k_prep, dim3((P.N + PREP_CH - 1) / PREP_CH), dim3(256), 0, st, P, w,
-                       xy, voff, atlas_off);
+  }
   return hipGetLastError();
 }
 

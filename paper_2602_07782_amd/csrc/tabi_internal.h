@@ -60,6 +60,7 @@ struct Work {
   int32_t* Hs;          // [N] unscaled height (Q8) by sorted position
   int64_t* segneed;     // [count][B] arena words of the (atlas, slot) segment
   int32_t* segbase;     // [count][B] arena word where the segment starts, -1: not stored
+  int32_t* cnt;         // [count] fold-and-push workgroups of the atlas done this round
   uint32_t* arena;      // profiles: per grown column (top, bottom), per grown row
                         // (left, right), int16 pairs (pack16)
 };
@@ -84,8 +85,12 @@ hipError_t launch_plan(const Params& P, const Work& w, hipStream_t st);
 hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t st);
 // per-texel profiles and neighbour pairs (compacting distance, interlock flags)
 hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_t st);
+// fold-and-push of the round's scales; for a single atlas its last workgroup
+// also selects the scale and writes the outputs (not for a fixed diagnostic
+// scale), batches select in launch_select (a no-op for a single atlas)
 hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes, int RC, int PW,
-                       int stage_cap, hipStream_t st);
+                       int stage_cap, int last_round, int32_t* out_xy, uint8_t* out_orient,
+                       float* out_scale, hipStream_t st);
 hipError_t launch_select(const Params& P, const Work& w, int round, int last_round,
                          int32_t* out_xy, uint8_t* out_orient, float* out_scale, hipStream_t st);
 
