@@ -162,10 +162,55 @@ __device__ inline void sweep_bounds(const SweepRec& R, int32_t u, int32_t& top, 
   right = r;
 }
 
+// Segment placement in priority order: slot-major (every atlas's largest
+// candidate scale first), so that when the arena runs out the segments left
+// unstored are those of the smallest scales.  A segment is stored when it ends
+// within the arena counting every segment before it.  One workgroup of NT
+// threads; s_tot: NT / 64 entries of shared memory.
+template <int NT>
+__device__ void alloc_segments(const Params& P, const Work& w, int64_t* s_tot) {
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+  const int64_t total = (int64_t)P.count * P.Br;  // this round's segments
+  int64_t run = 0;
+  for (int64_t q0 = 0; q0 < total; q0 += NT) {
+    const int64_t q = q0 + tid;
+    int64_t a = 0, s = 0, need = 0;
+    if (q < total) {
+      s = q / P.count;
+      a = q - s * P.count;
+      need = w.segneed[a * P.B + s];
+    }
+    int64_t inc = need;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int64_t u = __shfl_up((long long)inc, o);
+      if (lane >= o) inc += u;
+    }
+    if (lane == WAVE - 1) s_tot[wv] = inc;
+    __syncthreads();
+    int64_t pre = 0, chunk = 0;
+    for (int i = 0; i < NT / WAVE; ++i) {
+      if (i < wv) pre += s_tot[i];
+      chunk += s_tot[i];
+    }
+    if (q < total) {
+      const int64_t end = run + pre + inc;
+      w.segbase[a * P.B + s] = (need > 0 && end <= P.arena_cap) ? (int32_t)(end - need) : -1;
+    }
+    run += chunk;
+    __syncthreads();
+  }
+}
+__global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w) {
+  __shared__ int64_t s_tot[ALLOC_NT / WAVE];
+  alloc_segments<ALLOC_NT>(P, w, s_tot);
+}
+
 // Offsets of every chart's grown columns and rows within its (atlas, slot)
 // segment, and the segment's size in words (0 when the slot does not run).
 __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) {
   __shared__ int64_t s_tot[LAY_NT / WAVE][2];
+  __shared__ int32_t s_last;
   const int a = blockIdx.x, s = blockIdx.y;
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
   const AtlasDesc d = w.desc[a];
@@ -173,8 +218,7 @@ __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) 
   const int k = slot_k(P, d, round, s);
   if (!run || d.n <= 0 || k < 1) {
     if (tid == 0) w.segneed[(size_t)a * P.B + s] = 0;
-    return;
-  }
+  } else {
   const size_t slot = (size_t)s * P.N + d.c0;
   const int n = d.n, per = (n + LAY_NT - 1) / LAY_NT;
   const int t0 = min(n, tid * per), t1 = min(n, t0 + per);
@@ -209,45 +253,19 @@ __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) 
     col += w.wdv[slot + t];
     row += w.hdv[slot + t];
   }
-}
-
-// Segment placement in priority order: slot-major (every atlas's largest
-// candidate scale first), so that when the arena runs out the segments left
-// unstored are those of the smallest scales.  A segment is stored when it ends
-// within the arena counting every segment before it.
-__global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w) {
-  __shared__ int64_t s_tot[ALLOC_NT / WAVE];
-  const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
-  const int64_t total = (int64_t)P.count * P.Br;  // this round's segments
-  int64_t run = 0;
-  for (int64_t q0 = 0; q0 < total; q0 += ALLOC_NT) {
-    const int64_t q = q0 + tid;
-    int64_t a = 0, s = 0, need = 0;
-    if (q < total) {
-      s = q / P.count;
-      a = q - s * P.count;
-      need = w.segneed[a * P.B + s];
-    }
-    int64_t inc = need;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-      const int64_t u = __shfl_up((long long)inc, o);
-      if (lane >= o) inc += u;
-    }
-    if (lane == WAVE - 1) s_tot[wv] = inc;
-    __syncthreads();
-    int64_t pre = 0, chunk = 0;
-    for (int i = 0; i < ALLOC_NT / WAVE; ++i) {
-      if (i < wv) pre += s_tot[i];
-      chunk += s_tot[i];
-    }
-    if (q < total) {
-      const int64_t end = run + pre + inc;
-      w.segbase[a * P.B + s] = (need > 0 && end <= P.arena_cap) ? (int32_t)(end - need) : -1;
-    }
-    run += chunk;
-    __syncthreads();
   }
+  // Single atlas: the last of its workgroups to finish places the segments
+  // (no separate launch); the counter is zeroed again for the packing
+  // kernel, which counts with it next.  Batches launch the placement.
+  if (P.count != 1) return;
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = atomicAdd(&w.cnt[0], 1) == P.Br - 1;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (tid == 0) w.cnt[0] = 0;
+  alloc_segments<LAY_NT>(P, w, &s_tot[0][0]);
 }
 
 // Stores the grown columns and rows of the workgroup's charts (KT slices per
@@ -476,7 +494,8 @@ hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_
   if (P.N <= 0) return hipSuccess;
   // with no arena the placement still runs: it marks every segment unstored
   hipLaunchKernelGGL(k_layout, dim3(P.count, P.Br), dim3(LAY_NT), 0, st, P, w, round);
-  hipLaunchKernelGGL(k_alloc, dim3(1), dim3(ALLOC_NT), 0, st, P, w);
+  if (P.count != 1)  // a single atlas is placed by the last k_layout workgroup
+    hipLaunchKernelGGL(k_alloc, dim3(1), dim3(ALLOC_NT), 0, st, P, w);
   const dim3 grid((P.N + PROF_CH - 1) / PROF_CH, P.Br);
   if (P.K == 10) hipLaunchKernelGGL(k_profile<10>, grid, dim3(PROF_NT), 0, st, P, w, round);
   else if (P.K == 5) hipLaunchKernelGGL(k_profile<5>, grid, dim3(PROF_NT), 0, st, P, w, round);
