@@ -106,7 +106,7 @@ struct StageScope {  // brackets one stage's launches with a pair of events
 // ---- work space -------------------------------------------------------------
 struct Layout {
   size_t o_recs, o_srecs, o_keys, o_rank, o_perm, o_ca, o_desc, o_kc, o_cd, o_fl, o_xs, o_ys, o_mir,
-      o_feas, o_rows, o_wdv, o_hdv, o_pcol, o_prow, o_Hs, o_segneed, o_segbase, o_cnt, o_arena,
+      o_feas, o_rows, o_wdv, o_hdv, o_kslot, o_pcol, o_prow, o_Hs, o_segneed, o_segbase, o_cnt, o_arena,
       total;
 };
 
@@ -153,6 +153,7 @@ Layout layout(const Params& P) {
   L.o_rows = take((size_t)P.count * P.B * 4);
   L.o_wdv = take((size_t)P.B * n1 * 4);
   L.o_hdv = take((size_t)P.B * n1 * 4);
+  L.o_kslot = take((size_t)P.B * n1 * 4);
   L.o_pcol = take((size_t)P.B * n1 * 4);
   L.o_prow = take((size_t)P.B * n1 * 4);
   L.o_Hs = take(n1 * 4);
@@ -184,6 +185,7 @@ Work carve(void* base, const Layout& L) {
   W.rows = reinterpret_cast<int32_t*>(b + L.o_rows);
   W.wdv = reinterpret_cast<int32_t*>(b + L.o_wdv);
   W.hdv = reinterpret_cast<int32_t*>(b + L.o_hdv);
+  W.kslot = reinterpret_cast<int32_t*>(b + L.o_kslot);
   W.pcol = reinterpret_cast<int32_t*>(b + L.o_pcol);
   W.prow = reinterpret_cast<int32_t*>(b + L.o_prow);
   W.Hs = reinterpret_cast<int32_t*>(b + L.o_Hs);

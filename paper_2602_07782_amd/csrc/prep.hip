@@ -386,16 +386,16 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
 }
 
 // one thread per (slot, chart)
-// The record of chart c at slot s, written to `base` (LDS); false when the
-// chart does not run at this slot.
+// The record of chart c at slot s, written to `base` (LDS); returns the
+// slot's scale k, 0 when the chart does not run at this slot.
 template <int KT>
-__device__ bool setup_record(const Params& P, const Work& w, int round, int c, int s,
+__device__ int32_t setup_record(const Params& P, const Work& w, int round, int c, int s,
                              unsigned char* base) {
   const AtlasDesc d = w.desc[w.chart_atlas[c]];
   const bool run = P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1);
-  if (!run) return false;
+  if (!run) return 0;
   const int k = slot_k(P, d, round, s);
-  if (k < 1) return false;
+  if (k < 1) return 0;
   const Chart& ch = w.srecs[c];
   constexpr int K = KT;
   KHead* hd = reinterpret_cast<KHead*>(base);
@@ -435,7 +435,7 @@ __device__ bool setup_record(const Params& P, const Work& w, int round, int c, i
     y.r1 = i16(slab((int64_t)(j + 1) * H * kk + QS * K - 1));
     rc[K + j] = y;
   }
-  if (!h.obb) return true;
+  if (!h.obb) return k;
   const int64_t C = kDirC[ch.m], S = kDirS[ch.m], N = C * C + S * S, D = QS * N;
   const int64_t a = ch.a, b = ch.b, e = ch.e, f = ch.f;
   auto split = [&](int64_t num, KSide& sdv) {  // corner position num/D (texels)
@@ -482,7 +482,7 @@ __device__ bool setup_record(const Params& P, const Work& w, int round, int c, i
   sd[1] = sb;
   sd[2] = sL;
   sd[3] = sR;
-  return true;
+  return k;
 }
 
 // Records are built in LDS by their threads and written out together with
@@ -494,7 +494,9 @@ __global__ __launch_bounds__(SETUP_NT) void k_setup(Params P, Work w, int round)
   __shared__ __align__(16) unsigned char s_rec[SETUP_NT * KREC_MAX];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
-  const bool active = c < P.N && setup_record<KT>(P, w, round, c, s, s_rec + threadIdx.x * P.stride);
+  const int32_t k = c < P.N ? setup_record<KT>(P, w, round, c, s, s_rec + threadIdx.x * P.stride) : 0;
+  if (c < P.N) w.kslot[(size_t)s * P.N + c] = k;  // read by the profile kernel
+  const bool active = k > 0;
   if (!__syncthreads_or(active)) return;  // no chart of the block runs at this slot
   const int c0 = blockIdx.x * blockDim.x, nc = min(SETUP_NT, P.N - c0);
   const int n16 = nc * (P.stride / 16);

@@ -308,16 +308,16 @@ __device__ void profile_charts(const Work& w, const ChartCache* cache, const Swe
       if (u >= 0 && u < wt) { tp = t1; bt = b1; }
       if (u >= 0 && u < ht) { l = l1; r = r1; }
     }
-    int32_t T = tp, Bo = bt, L = l, R = r, st = tp, sb = bt, sl = l, sr = r;
-    for (int q = 1; q <= p; ++q) {
-      st = wave_shr1(st, BIG);
-      sb = wave_shr1(sb, -BIG);
-      sl = wave_shr1(sl, BIG);
-      sr = wave_shr1(sr, -BIG);
-      T = min(T, st);
-      Bo = max(Bo, sb);
-      L = min(L, sl);
-      R = max(R, sr);
+    // gutter growth: after step q the lane holds the extremes over entries
+    // [u - q, u] (the window of the lane before it, one entry longer); the
+    // fill is each extreme's identity, so the move and the min / max fold
+    // into one instruction
+    int32_t T = tp, Bo = bt, L = l, R = r;
+    for (int q = 0; q < p; ++q) {
+      T = min(T, wave_shr1(T, INT32_MAX));
+      Bo = max(Bo, wave_shr1(Bo, INT32_MIN));
+      L = min(L, wave_shr1(L, INT32_MAX));
+      R = max(R, wave_shr1(R, INT32_MIN));
     }
     if (live && gl >= p) {
       if (s_cols[j] && u < wt + p) w.arena[s_pc[j] + u] = pack16(T, Bo + p);
@@ -351,39 +351,47 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
   __shared__ int32_t s_ok[NJ * 4];
   const int tid = threadIdx.x, wv = tid / WAVE, lane = lane_id();
   const int s = blockIdx.y, cb = blockIdx.x * PROF_CH;
+  // the charts' atlases, scales at this slot and offsets within their
+  // segments: independent loads, issued together
   if (tid < NJ) {
     const int c = cb - 1 + tid;
-    int32_t pc = -1, pr = -1, kk = 0, a = -1, run = 0;
+    int32_t a = -1, kk = 0, oc = 0, orw = 0;
     if (c >= 0 && c < P.N) {
+      const size_t sc = (size_t)s * P.N + c;
       a = w.chart_atlas[c];
-      const AtlasDesc d = w.desc[a];
-      const int k = slot_k(P, d, round, s);
-      run = (P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1)) && k >= 1;
-      const int32_t base = w.segbase[(size_t)a * P.B + s];
-      if (run) kk = k;
-      if (run && base >= 0) {
-        const size_t sc = (size_t)s * P.N + c;
-        pc = base + w.pcol[sc];
-        pr = base + w.prow[sc];
-      }
-      if (c == d.c0) run |= 2;  // first chart of its atlas: no pair before it
+      kk = w.kslot[sc];
+      oc = w.pcol[sc];
+      orw = w.prow[sc];
     }
-    s_pc[tid] = pc;
-    s_pr[tid] = pr;
-    s_k[tid] = kk;
     s_a[tid] = a;
-    s_run[tid] = run;
+    s_k[tid] = kk;
+    s_pc[tid] = oc;
+    s_pr[tid] = orw;
   }
+  __syncthreads();
+  // run bit 1: the chart runs at this slot; bit 2: it is the first chart of
+  // its atlas (no pair before it); charts of an atlas are contiguous
+  if (tid < NJ) s_run[tid] = (s_k[tid] > 0) | (tid > 0 && s_a[tid - 1] != s_a[tid] ? 2 : 0);
   // nothing to do when none of the block's charts runs at this slot (their
   // atlas is finished or its scale is out of range): leave before any copy
-  const int active = tid >= 1 && tid < NJ && (s_run[tid] & 1);
+  const int active = tid >= 1 && tid < NJ && s_k[tid] > 0;
   if (!__syncthreads_or(active)) return;
+  // segment bases (they depend on the atlas) and the records of the running
+  // charts are loaded together
+  if (tid < NJ && s_k[tid] > 0) {
+    const int32_t base = w.segbase[(size_t)s_a[tid] * P.B + s];
+    s_pc[tid] = base >= 0 ? base + s_pc[tid] : -1;
+    s_pr[tid] = base >= 0 ? base + s_pr[tid] : -1;
+  } else if (tid < NJ) {
+    s_pc[tid] = -1;
+    s_pr[tid] = -1;
+  }
   {
     constexpr int per = nch + nkc;
     const int j0 = cb > 0 ? 0 : 1, j1 = min(NJ, P.N - cb + 1);
     for (int i = tid; i < (j1 - j0) * per; i += PROF_NT) {
       const int j = j0 + i / per, r = i % per, c = cb - 1 + j;
-      if (!(s_run[j] & 1)) continue;  // record not needed
+      if (s_k[j] <= 0) continue;  // record not needed
       if (r < nch) {
         reinterpret_cast<int4*>(&cache[j].ch)[r] = reinterpret_cast<const int4*>(&w.srecs[c])[r];
       } else {

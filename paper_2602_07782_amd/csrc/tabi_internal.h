@@ -55,6 +55,7 @@ struct Work {
   int32_t* rows;        // [count][B]
   int32_t* wdv;         // [B][N] grown width w + p at the slot's scale
   int32_t* hdv;         // [B][N] grown height h + p
+  int32_t* kslot;       // [B][N] the chart's scale k at the slot, 0 when it does not run
   int32_t* pcol;        // [B][N] first grown column of the chart within its segment
   int32_t* prow;        // [B][N] first grown row of the chart within its segment
   int32_t* Hs;          // [N] unscaled height (Q8) by sorted position
