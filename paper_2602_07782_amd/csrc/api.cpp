@@ -106,7 +106,7 @@ struct StageScope {  // brackets one stage's launches with a pair of events
 // ---- work space -------------------------------------------------------------
 struct Layout {
   size_t o_recs, o_srecs, o_keys, o_rank, o_perm, o_ca, o_desc, o_kc, o_cd, o_fl, o_xs, o_ys, o_mir,
-      o_feas, o_rows, o_wdv, o_hdv, o_kslot, o_pcol, o_prow, o_Hs, o_segneed, o_segbase, o_cnt, o_arena,
+      o_feas, o_rows, o_wdv, o_hdv, o_kslot, o_pcol, o_prow, o_Hs, o_segneed, o_segbase, o_cnt, o_gq, o_gq_cnt, o_arena,
       total;
 };
 
@@ -160,6 +160,8 @@ Layout layout(const Params& P) {
   L.o_segneed = take((size_t)P.count * P.B * 8);
   L.o_segbase = take((size_t)P.count * P.B * 4);
   L.o_cnt = take((size_t)P.count * 4);
+  L.o_gq = take((size_t)P.B * ((n1 + PROF_CH - 1) / PROF_CH) * 4);
+  L.o_gq_cnt = take(4);
   L.o_arena = take((size_t)P.arena_cap * 4);
   L.total = off;
   return L;
@@ -192,6 +194,8 @@ Work carve(void* base, const Layout& L) {
   W.segneed = reinterpret_cast<int64_t*>(b + L.o_segneed);
   W.segbase = reinterpret_cast<int32_t*>(b + L.o_segbase);
   W.cnt = reinterpret_cast<int32_t*>(b + L.o_cnt);
+  W.gq = reinterpret_cast<int32_t*>(b + L.o_gq);
+  W.gq_cnt = reinterpret_cast<int32_t*>(b + L.o_gq_cnt);
   W.arena = reinterpret_cast<uint32_t*>(b + L.o_arena);
   return W;
 }

@@ -496,6 +496,7 @@ __global__ __launch_bounds__(SETUP_NT) void k_setup(Params P, Work w, int round)
   const int s = blockIdx.y;
   const int32_t k = c < P.N ? setup_record<KT>(P, w, round, c, s, s_rec + threadIdx.x * P.stride) : 0;
   if (c < P.N) w.kslot[(size_t)s * P.N + c] = k;  // read by the profile kernel
+  if (c == 0 && s == 0) *w.gq_cnt = 0;  // the profile kernel's queue of this round
   const bool active = k > 0;
   if (!__syncthreads_or(active)) return;  // no chart of the block runs at this slot
   const int c0 = blockIdx.x * blockDim.x, nc = min(SETUP_NT, P.N - c0);

@@ -29,7 +29,7 @@ namespace tabi {
 constexpr int LAY_NT = 256;
 constexpr int ALLOC_NT = 1024;
 constexpr int PROF_NT = 256;
-constexpr int PROF_CH = 16;  // charts per profile workgroup
+constexpr int PROF_GEN_BLOCKS = 1024;  // grid of the queued-block launch
 
 // ---- a chart's per-scale record in the form the profile sweep evaluates ----
 // Each slice rectangle (columns [c0, c1) x rows [r0, r1)) as pairs of 16-bit
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) 
 // growth shifts values by one lane across the whole wavefront: a group's first
 // p lanes only feed the others and are never stored, so no value crosses from
 // one group into another's stored lanes.
-template <int KT>
+template <int KT, bool GEN>
 __device__ void profile_charts(const Work& w, const ChartCache* cache, const SweepRec* sw,
                                const int32_t* s_pc, const int32_t* s_pr, const int32_t* s_k,
                                const int32_t* s_ni, const int32_t* s_cols, int p, int G) {
@@ -301,7 +301,7 @@ __device__ void profile_charts(const Work& w, const ChartCache* cache, const Swe
     int32_t tp = BIG, bt = -BIG, l = BIG, r = -BIG;
     {
       int32_t t1, b1, l1, r1;
-      if (rec.mode != SWEEP_GENERAL)
+      if (!GEN || rec.mode != SWEEP_GENERAL)
         sweep_bounds<KT>(rec, u, t1, b1, l1, r1);
       else
         column_row_bounds<KT>(kview(cache[j].kc, KT), cache[j].ch, s_k[j], u, u, t1, b1, l1, r1);
@@ -338,8 +338,13 @@ __device__ void profile_charts(const Work& w, const ChartCache* cache, const Swe
 // one-lane moves, so a chunk advances 64 - p entries (p <= 32).  After a barrier
 // the pairs read the rows just stored; pairs in segments without stored
 // profiles evaluate the rows from the LDS records.
-template <int KT>
-__global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round) {
+// GEN: the block may hold charts without a sweep form or pairs without
+// stored rows, evaluated from the proxy records (64-bit line arithmetic).
+// Without it (the lean form, which needs far fewer registers and so runs at
+// full occupancy) such a block is queued for profile_general instead and
+// leaves; returns false then.
+template <int KT, bool GEN>
+__device__ bool profile_block(const Params& P, const Work& w, int bx, int s) {
   constexpr int NJ = PROF_CH + 1;  // entry 0: the chart before the block's first
   constexpr int K = KT;
   // 16-byte words of a chart record and of its set-up record (P.stride)
@@ -349,8 +354,9 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
   __shared__ SweepRec sw[NJ];
   __shared__ int32_t s_pc[NJ], s_pr[NJ], s_k[NJ], s_a[NJ], s_run[NJ], s_nc[NJ], s_ni[NJ + 1], s_G;
   __shared__ int32_t s_ok[NJ * 4];
+  __shared__ int32_t s_gen;
   const int tid = threadIdx.x, wv = tid / WAVE, lane = lane_id();
-  const int s = blockIdx.y, cb = blockIdx.x * PROF_CH;
+  const int cb = bx * PROF_CH;
   // the charts' atlases, scales at this slot and offsets within their
   // segments: independent loads, issued together
   if (tid < NJ) {
@@ -375,7 +381,7 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
   // nothing to do when none of the block's charts runs at this slot (their
   // atlas is finished or its scale is out of range): leave before any copy
   const int active = tid >= 1 && tid < NJ && s_k[tid] > 0;
-  if (!__syncthreads_or(active)) return;
+  if (!__syncthreads_or(active)) return true;
   // segment bases (they depend on the atlas) and the records of the running
   // charts are loaded together
   if (tid < NJ && s_k[tid] > 0) {
@@ -443,10 +449,17 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
     const int incl = wave_incl_sum(ni);
     if (lane < NJ) { s_nc[lane] = lane > 0; s_ni[lane + 1] = incl; }
     if (lane == 0) { s_ni[0] = 0; s_G = G; }
+    // general evaluation needed: a chart with entries and no sweep form, or
+    // a pair (with the chart before, same atlas) whose rows are not stored
+    const bool gen_item = lane < NJ && e > 0 && sw[lane].mode == SWEEP_GENERAL;
+    const bool gen_pair = lane >= 1 && lane < NJ && s_run[lane] == 1 && s_pr[lane] < 0;
+    if (lane == 0) s_gen = 0;
+    if (ballot64(gen_item || gen_pair) != 0 && lane == 0) s_gen = 1;
   }
   __syncthreads();
+  if (!GEN && s_gen) return false;
   const int G = s_G;
-  profile_charts<KT>(w, cache, sw, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
+  profile_charts<KT, GEN>(w, cache, sw, s_pc, s_pr, s_k, s_ni, s_nc, p, G);
   __syncthreads();  // the block's stored rows are visible to all its wavefronts
   // wavefront wv takes the pairs ending at charts 1 + 4 wv .. 4 + 4 wv: side
   // by side in its four 16-lane rows when all of them read stored rows, else
@@ -454,7 +467,7 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
   // where none are stored)
   const int jg = 1 + 4 * wv + (lane >> 4);
   const bool pg = (s_run[jg] & 1) && !(s_run[jg] & 2);  // a pair with the chart before
-  if (ballot64(pg && s_pr[jg] < 0) == 0) {
+  if (!GEN || ballot64(pg && s_pr[jg] < 0) == 0) {
     int hdA = 0, hdB = 0, wdA = 0;
     const uint32_t* ra = w.arena;
     const uint32_t* rb = w.arena;
@@ -472,7 +485,7 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
       w.cd[sc] = pg ? r.cd : 0;
       w.fl[sc] = pg ? (uint8_t)pair_flags_at(r, wdA, wdA - r.cd) : 0;
     }
-  } else {
+  } else if constexpr (GEN) {
     for (int j = 1 + 4 * wv; j < 5 + 4 * wv; ++j) {
       const int run = s_run[j];
       if (!(run & 1)) continue;
@@ -496,6 +509,29 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
       }
     }
   }
+  return true;
+}
+
+// Grown bounds and pairs of PROF_CH charts of one scale slot per workgroup
+// (Sec. 4.1.2; App. A).  GEN false: the lean form, which queues the blocks
+// that need the general evaluation (w.gq, counted in w.gq_cnt).
+template <int KT, bool GEN>
+__global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round) {
+  (void)round;
+  if (!profile_block<KT, GEN>(P, w, blockIdx.x, blockIdx.y) && threadIdx.x == 0)
+    w.gq[atomicAdd(w.gq_cnt, 1)] = (int32_t)(blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+// The queued blocks, in full form, spread over a fixed grid.  The lean
+// launch has finished, so these blocks' outputs are all written here.
+template <int KT>
+__global__ __launch_bounds__(PROF_NT) void k_profile_general(Params P, Work w, int nbx) {
+  const int nq = *w.gq_cnt;
+  for (int i = blockIdx.x; i < nq; i += gridDim.x) {
+    __syncthreads();  // the previous block's shared data is no longer read
+    const int q = w.gq[i];
+    profile_block<KT, true>(P, w, q % nbx, q / nbx);
+  }
 }
 
 hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_t st) {
@@ -504,10 +540,28 @@ hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_
   hipLaunchKernelGGL(k_layout, dim3(P.count, P.Br), dim3(LAY_NT), 0, st, P, w, round);
   if (P.count != 1)  // a single atlas is placed by the last k_layout workgroup
     hipLaunchKernelGGL(k_alloc, dim3(1), dim3(ALLOC_NT), 0, st, P, w);
-  const dim3 grid((P.N + PROF_CH - 1) / PROF_CH, P.Br);
-  if (P.K == 10) hipLaunchKernelGGL(k_profile<10>, grid, dim3(PROF_NT), 0, st, P, w, round);
-  else if (P.K == 5) hipLaunchKernelGGL(k_profile<5>, grid, dim3(PROF_NT), 0, st, P, w, round);
-  else hipLaunchKernelGGL(k_profile<2>, grid, dim3(PROF_NT), 0, st, P, w, round);
+  const int nbx = (P.N + PROF_CH - 1) / PROF_CH;
+  const dim3 grid(nbx, P.Br);
+  // a single atlas: one launch in full form; a batch: the lean form at full
+  // occupancy, then the queued blocks (the queue counter was cleared by the
+  // set-up kernel of this round)
+  if (P.count == 1) {
+    if (P.K == 10) hipLaunchKernelGGL((k_profile<10, true>), grid, dim3(PROF_NT), 0, st, P, w, round);
+    else if (P.K == 5) hipLaunchKernelGGL((k_profile<5, true>), grid, dim3(PROF_NT), 0, st, P, w, round);
+    else hipLaunchKernelGGL((k_profile<2, true>), grid, dim3(PROF_NT), 0, st, P, w, round);
+    return hipGetLastError();
+  }
+  const dim3 ggrid(PROF_GEN_BLOCKS);
+  if (P.K == 10) {
+    hipLaunchKernelGGL((k_profile<10, false>), grid, dim3(PROF_NT), 0, st, P, w, round);
+    hipLaunchKernelGGL(k_profile_general<10>, ggrid, dim3(PROF_NT), 0, st, P, w, nbx);
+  } else if (P.K == 5) {
+    hipLaunchKernelGGL((k_profile<5, false>), grid, dim3(PROF_NT), 0, st, P, w, round);
+    hipLaunchKernelGGL(k_profile_general<5>, ggrid, dim3(PROF_NT), 0, st, P, w, nbx);
+  } else {
+    hipLaunchKernelGGL((k_profile<2, false>), grid, dim3(PROF_NT), 0, st, P, w, round);
+    hipLaunchKernelGGL(k_profile_general<2>, ggrid, dim3(PROF_NT), 0, st, P, w, nbx);
+  }
   return hipGetLastError();
 }
 

@@ -37,6 +37,8 @@ struct Params {
 };
 
 // Work-space views (device pointers).
+constexpr int PROF_CH = 16;  // charts per profile workgroup
+
 struct Work {
   Chart* recs;          // [N] by input position
   Chart* srecs;         // [N] by sorted position (per atlas)
@@ -62,6 +64,8 @@ struct Work {
   int64_t* segneed;     // [count][B] arena words of the (atlas, slot) segment
   int32_t* segbase;     // [count][B] arena word where the segment starts, -1: not stored
   int32_t* cnt;         // [count] fold-and-push workgroups of the atlas done this round
+  int32_t* gq;          // [B][ceil(N / PROF_CH)] profile blocks queued for the general evaluation
+  int32_t* gq_cnt;      // [1] queued blocks this round (cleared by the set-up kernel)
   uint32_t* arena;      // profiles: per grown column (top, bottom), per grown row
                         // (left, right), int16 pairs (pack16)
 };

@@ -182,3 +182,19 @@ def test_large_batch_equals_single_packs(tabi, shape):
         assert np.array_equal(xy[c0:c0 + n], pxy.cpu().numpy()), a
         assert np.array_equal(ori[c0:c0 + n], por.cpu().numpy()), a
         c0 += n
+
+
+@pytest.mark.parametrize("words", [0, 60000])
+def test_batch_without_stored_profiles(tabi, orc, words):
+    """Profile blocks whose pairs have no stored rows are queued by the lean
+    profile kernel and evaluated in full form by the queued-block launch;
+    the batch still equals the oracle per atlas (0: no arena, every block
+    queued; 60000 words: some segments stored, the others not)."""
+    tabi.debug_set_profile_cap(words)
+    try:
+        inputs = small_batch(6, 960 + words % 7)
+        _say("batch arena", words, [i.n for i in inputs])
+        check_batch(tabi, orc, inputs)
+        check_batch(tabi, orc, small_batch(3, 970), use_workspace=True)
+    finally:
+        tabi.debug_set_profile_cap(-1)
