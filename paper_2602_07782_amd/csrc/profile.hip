@@ -35,18 +35,22 @@ constexpr int PROF_GEN_BLOCKS = 1024;  // grid of the queued-block launch
 // Each slice rectangle (columns [c0, c1) x rows [r0, r1)) as pairs of 16-bit
 // values, so that one set of two-lane integer operations tests an entry's
 // column i and row j against it together:
-//   lo = (c0, r0), hi = (c1 - 1, r1 - 1): i lies in [c0, c1) iff i - c0 and
-//   c1 - 1 - i are both >= 0, i.e. the sign bit of their OR is clear (the
-//   same for j and the rows);
-//   vmin = (r0, c0), vmax = (r1, c1), offset by 2^15 so that unsigned 16-bit
-//   min / max order them as the signed values: what the rectangle gives the
-//   column's top and the row's left (min), the column's bottom and the row's
-//   right (max).
+//   lo = (c0, r0), span = (c1 - 1 - c0, r1 - 1 - r0): i lies in [c0, c1) iff
+//   (i - c0) mod 2^16 <= c1 - 1 - c0, i.e. iff the saturating difference
+//   x = (i - c0) -sat span is 0 (the same for j and the rows; an empty range
+//   is lo = 2^15, span = 0, which no entry reaches);
+//   vmin = (r0, c0), offset by 2^15 so that unsigned 16-bit min orders them
+//   as the signed values, and vmaxc = (r1, c1) offset the same way and
+//   complemented (2^16 - 1 - v), so that the max of the bottoms and rights
+//   is also taken as a min: what the rectangle gives the column's top and
+//   the row's left, the column's bottom and the row's right.
+// x * (2^16 - 1) + v, saturated, is v inside and 2^16 - 1 (the min's
+// identity) outside: one packed multiply-add with clamp per value.
 // A chart of at most 16384 texels per side at the scale keeps every value
 // and difference within 16 bits (entries lie in [-32, 16416)); larger charts,
 // and OBB lines that need 64 bits, take the general evaluation.
 struct alignas(16) SweepRect {
-  uint32_t lo, hi, vmin, vmax;
+  uint32_t lo, span, vmin, vmaxc;
 };
 // An OBB side: split points, corner and last values, both lines in 32-bit
 // form, and the single-precision reciprocals of their divisors (those the
@@ -69,16 +73,23 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ inline uint32_t pair16(int32_t a, int32_t b) {
   return (uint32_t)(uint16_t)a | ((uint32_t)(uint16_t)b << 16);
 }
+// per 16-bit half: min(a * b + c, 2^16 - 1), from the full-width product
+__device__ inline uint32_t pk_mad_sat_u16(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t d;
+  asm("v_pk_mad_u16 %0, %1, %2, %3 clamp" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
 
 // Slice rectangle q of the chart (x-slices q < K, y-slices K + q) in sweep form.
 __device__ inline SweepRect sweep_rect_of(const KView& kv, int q) {
   int32_t c0, c1, r0, r1;
   krect_load(kv.rc + q, c0, c1, r0, r1);
+  const bool ce = c1 - 1 < c0, re = r1 - 1 < r0;  // empty ranges
   SweepRect r;
-  r.lo = pair16(c0, r0);
-  r.hi = pair16(c1 - 1, r1 - 1);
+  r.lo = pair16(ce ? 0x8000 : c0, re ? 0x8000 : r0);
+  r.span = pair16(ce ? 0 : c1 - 1 - c0, re ? 0 : r1 - 1 - r0);
   r.vmin = pair16(r0 ^ 0x8000, c0 ^ 0x8000);
-  r.vmax = pair16(r1 ^ 0x8000, c1 ^ 0x8000);
+  r.vmaxc = ~pair16(r1 ^ 0x8000, c1 ^ 0x8000);
   return r;
 }
 
@@ -123,29 +134,32 @@ __device__ inline int32_t sweep_side(const SweepSide& s, int32_t t, int32_t n) {
 template <int KT>
 __device__ inline void sweep_bounds(const SweepRec& R, int32_t u, int32_t& top, int32_t& bot,
                                     int32_t& left, int32_t& right) {
-  const s16x2 ij = {(short)u, (short)u};
-  // (top, left) minima and (bottom, right) maxima of the x- and y-slices;
-  // 0xffff / 0 mean no rectangle contains the column (row)
-  u16x2 mnx = {0xffff, 0xffff}, mxx = {0, 0}, mny = {0xffff, 0xffff}, mxy = {0, 0};
+  const u16x2 ij = {(unsigned short)u, (unsigned short)u};
+  const uint32_t ones = 0xffffffffu;
+  // (top, left) minima and complemented (bottom, right) maxima of the x- and
+  // y-slices; 0xffff means no rectangle contains the column (row)
+  u16x2 mnx = {0xffff, 0xffff}, mcx = {0xffff, 0xffff}, mny = {0xffff, 0xffff},
+        mcy = {0xffff, 0xffff};
 #pragma unroll
   for (int q = 0; q < 2 * KT; ++q) {
     const uint4 v = *reinterpret_cast<const uint4*>(&R.rc[q]);
-    const s16x2 d = (ij - __builtin_bit_cast(s16x2, v.x)) | (__builtin_bit_cast(s16x2, v.y) - ij);
-    // 0xffff where outside, 0 inside; a saturating add / subtract turns the
-    // contribution into the accumulator's neutral value outside
-    const u16x2 out = __builtin_bit_cast(u16x2, (s16x2)(d >> 15));
-    const u16x2 cmin = __builtin_elementwise_add_sat(__builtin_bit_cast(u16x2, v.z), out);
-    const u16x2 cmax = __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, v.w), out);
+    // 0 inside, > 0 outside
+    const u16x2 x = __builtin_elementwise_sub_sat(ij - __builtin_bit_cast(u16x2, v.x),
+                                                  __builtin_bit_cast(u16x2, v.y));
+    const uint32_t xb = __builtin_bit_cast(uint32_t, x);
+    const u16x2 cmin = __builtin_bit_cast(u16x2, pk_mad_sat_u16(xb, ones, v.z));
+    const u16x2 cmaxc = __builtin_bit_cast(u16x2, pk_mad_sat_u16(xb, ones, v.w));
     if (q < KT) {
       mnx = __builtin_elementwise_min(mnx, cmin);
-      mxx = __builtin_elementwise_max(mxx, cmax);
+      mcx = __builtin_elementwise_min(mcx, cmaxc);
     } else {
       mny = __builtin_elementwise_min(mny, cmin);
-      mxy = __builtin_elementwise_max(mxy, cmax);
+      mcy = __builtin_elementwise_min(mcy, cmaxc);
     }
   }
   // top = max(x, y tops), left = max(y, x lefts); bottom / right = min
-  const u16x2 tl = __builtin_elementwise_max(mnx, mny), br = __builtin_elementwise_min(mxx, mxy);
+  const u16x2 tl = __builtin_elementwise_max(mnx, mny);
+  const u16x2 br = ~__builtin_elementwise_max(mcx, mcy);
   int32_t t = tl.x == 0xffff ? BIG : (int32_t)tl.x - 0x8000;
   int32_t l = tl.y == 0xffff ? BIG : (int32_t)tl.y - 0x8000;
   int32_t b = br.x == 0 ? -BIG : (int32_t)br.x - 0x8000;
