@@ -153,7 +153,10 @@ __device__ void select_atlas(const Params& P, const Work& w, int round, int last
   }
   __syncthreads();
   const int best = sh[0], limit = sh[1];
-  if (sh[2]) return;
+  if (sh[2]) {  // the atlas searches on: the next round runs
+    if (threadIdx.x == 0 && round < MAX_ROUNDS) w.live[round + 1] = 1;
+    return;
+  }
   float scale;
   int kstar = 0;
   if (d.bad) scale = -1.0f;
@@ -202,6 +205,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   // unscaled height; it slides when fewer than FWIN / 2 charts remain ahead
   __shared__ int32_t s_wd[FWIN], s_cdn[FWIN], s_H[FWIN];
 
+  if (round_idle(w, round)) return;
   const int s = blockIdx.x, a = blockIdx.y;
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
   const AtlasDesc d = w.desc[a];
@@ -630,6 +634,7 @@ __global__ __launch_bounds__(256) void k_select(Params P, Work w, int round, int
                                                 int32_t* out_xy, uint8_t* out_orient,
                                                 float* out_scale) {
   __shared__ int32_t sh[3];
+  if (round_idle(w, round)) return;
   select_atlas(P, w, round, last_round, blockIdx.x, out_xy, out_orient, out_scale, sh);
 }
 

@@ -44,6 +44,8 @@ __device__ inline void init_desc(const Params& P, const Work& w, const int32_t* 
   d.kstar = 0;
   w.desc[a] = d;
   if (w.cnt) w.cnt[a] = 0;
+  if (a == 0 && w.live)
+    for (int r = 0; r <= MAX_ROUNDS; ++r) w.live[r] = 0;
 }
 __global__ void k_init(Params P, Work w, const int32_t* atlas_off, const int32_t* atlas_wh,
                        int single_w, int single_h) {
@@ -492,6 +494,7 @@ constexpr int SETUP_NT = 128;
 template <int KT>
 __global__ __launch_bounds__(SETUP_NT) void k_setup(Params P, Work w, int round) {
   __shared__ __align__(16) unsigned char s_rec[SETUP_NT * KREC_MAX];
+  if (round_idle(w, round)) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
   const int32_t k = c < P.N ? setup_record<KT>(P, w, round, c, s, s_rec + threadIdx.x * P.stride) : 0;

@@ -215,8 +215,9 @@ __device__ void alloc_segments(const Params& P, const Work& w, int64_t* s_tot) {
     __syncthreads();
   }
 }
-__global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w) {
+__global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w, int round) {
   __shared__ int64_t s_tot[ALLOC_NT / WAVE];
+  if (round_idle(w, round)) return;
   alloc_segments<ALLOC_NT>(P, w, s_tot);
 }
 
@@ -225,6 +226,7 @@ __global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w) {
 __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) {
   __shared__ int64_t s_tot[LAY_NT / WAVE][2];
   __shared__ int32_t s_last;
+  if (round_idle(w, round)) return;
   const int a = blockIdx.x, s = blockIdx.y;
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
   const AtlasDesc d = w.desc[a];
@@ -531,7 +533,7 @@ __device__ bool profile_block(const Params& P, const Work& w, int bx, int s) {
 // that need the general evaluation (w.gq, counted in w.gq_cnt).
 template <int KT, bool GEN>
 __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round) {
-  (void)round;
+  if (round_idle(w, round)) return;
   if (!profile_block<KT, GEN>(P, w, blockIdx.x, blockIdx.y) && threadIdx.x == 0)
     w.gq[atomicAdd(w.gq_cnt, 1)] = (int32_t)(blockIdx.y * gridDim.x + blockIdx.x);
 }
@@ -539,7 +541,8 @@ __global__ __launch_bounds__(PROF_NT) void k_profile(Params P, Work w, int round
 // The queued blocks, in full form, spread over a fixed grid.  The lean
 // launch has finished, so these blocks' outputs are all written here.
 template <int KT>
-__global__ __launch_bounds__(PROF_NT) void k_profile_general(Params P, Work w, int nbx) {
+__global__ __launch_bounds__(PROF_NT) void k_profile_general(Params P, Work w, int round, int nbx) {
+  if (round_idle(w, round)) return;
   const int nq = *w.gq_cnt;
   for (int i = blockIdx.x; i < nq; i += gridDim.x) {
     __syncthreads();  // the previous block's shared data is no longer read
@@ -553,7 +556,7 @@ hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_
   // with no arena the placement still runs: it marks every segment unstored
   hipLaunchKernelGGL(k_layout, dim3(P.count, P.Br), dim3(LAY_NT), 0, st, P, w, round);
   if (P.count != 1)  // a single atlas is placed by the last k_layout workgroup
-    hipLaunchKernelGGL(k_alloc, dim3(1), dim3(ALLOC_NT), 0, st, P, w);
+    hipLaunchKernelGGL(k_alloc, dim3(1), dim3(ALLOC_NT), 0, st, P, w, round);
   const int nbx = (P.N + PROF_CH - 1) / PROF_CH;
   const dim3 grid(nbx, P.Br);
   // a single atlas: one launch in full form; a batch: the lean form at full
@@ -568,13 +571,13 @@ hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_
   const dim3 ggrid(PROF_GEN_BLOCKS);
   if (P.K == 10) {
     hipLaunchKernelGGL((k_profile<10, false>), grid, dim3(PROF_NT), 0, st, P, w, round);
-    hipLaunchKernelGGL(k_profile_general<10>, ggrid, dim3(PROF_NT), 0, st, P, w, nbx);
+    hipLaunchKernelGGL(k_profile_general<10>, ggrid, dim3(PROF_NT), 0, st, P, w, round, nbx);
   } else if (P.K == 5) {
     hipLaunchKernelGGL((k_profile<5, false>), grid, dim3(PROF_NT), 0, st, P, w, round);
-    hipLaunchKernelGGL(k_profile_general<5>, ggrid, dim3(PROF_NT), 0, st, P, w, nbx);
+    hipLaunchKernelGGL(k_profile_general<5>, ggrid, dim3(PROF_NT), 0, st, P, w, round, nbx);
   } else {
     hipLaunchKernelGGL((k_profile<2, false>), grid, dim3(PROF_NT), 0, st, P, w, round);
-    hipLaunchKernelGGL(k_profile_general<2>, ggrid, dim3(PROF_NT), 0, st, P, w, nbx);
+    hipLaunchKernelGGL(k_profile_general<2>, ggrid, dim3(PROF_NT), 0, st, P, w, round, nbx);
   }
   return hipGetLastError();
 }

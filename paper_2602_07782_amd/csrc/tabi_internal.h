@@ -37,6 +37,7 @@ struct Params {
 };
 
 // Work-space views (device pointers).
+constexpr int MAX_ROUNDS = 64;  // a round covers at least one of the 64 scales
 constexpr int PROF_CH = 16;  // charts per profile workgroup
 
 struct Work {
@@ -66,6 +67,8 @@ struct Work {
   int32_t* cnt;         // [count] fold-and-push workgroups of the atlas done this round
   int32_t* gq;          // [B][ceil(N / PROF_CH)] profile blocks queued for the general evaluation
   int32_t* gq_cnt;      // [1] queued blocks this round (cleared by the set-up kernel)
+  int32_t* live;        // [MAX_ROUNDS + 1] live[r] != 0: some atlas still searches in round
+                        // r >= 1 (set by round r - 1's selection, cleared at the start)
   uint32_t* arena;      // profiles: per grown column (top, bottom), per grown row
                         // (left, right), int16 pairs (pack16)
 };
@@ -76,6 +79,12 @@ __host__ __device__ inline int32_t slot_k(const Params& P, const AtlasDesc& d, i
   (void)r;
   if (P.fixed_k > 0) return s == 0 ? P.fixed_k : 0;
   return s < P.Br ? d.ktop - P.koff - s : 0;
+}
+
+// Round r >= 1 of a search in which every atlas finished in an earlier
+// round: its kernels leave at once.
+__device__ inline bool round_idle(const Work& w, int round) {
+  return round > 0 && w.live[round] == 0;
 }
 
 // Launchers (one per kernel), all enqueue on `st`.
