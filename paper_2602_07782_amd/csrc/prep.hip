@@ -495,14 +495,20 @@ template <int KT>
 __global__ __launch_bounds__(SETUP_NT) void k_setup(Params P, Work w, int round) {
   __shared__ __align__(16) unsigned char s_rec[SETUP_NT * KREC_MAX];
   if (round_idle(w, round)) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = blockIdx.y;
+  // the round's slots of one chart range run on one XCD (blocks are dealt
+  // to the XCDs in turn), one after another, so the chart records they all
+  // read come from that XCD's L2 after the first; the grid is padded to a
+  // multiple of XCDS chart ranges
+  const int xcd = blockIdx.x % XCDS, j = blockIdx.x / XCDS;
+  const int s = j % P.Br, cblk = (j / P.Br) * XCDS + xcd;
+  if (cblk * SETUP_NT >= P.N) return;
+  const int c = cblk * blockDim.x + threadIdx.x;
   const int32_t k = c < P.N ? setup_record<KT>(P, w, round, c, s, s_rec + threadIdx.x * P.stride) : 0;
   if (c < P.N) w.kslot[(size_t)s * P.N + c] = k;  // read by the profile kernel
   if (c == 0 && s == 0) *w.gq_cnt = 0;  // the profile kernel's queue of this round
   const bool active = k > 0;
   if (!__syncthreads_or(active)) return;  // no chart of the block runs at this slot
-  const int c0 = blockIdx.x * blockDim.x, nc = min(SETUP_NT, P.N - c0);
+  const int c0 = cblk * blockDim.x, nc = min(SETUP_NT, P.N - c0);
   const int n16 = nc * (P.stride / 16);
   const int4* src = reinterpret_cast<const int4*>(s_rec);
   int4* dst = reinterpret_cast<int4*>(w.kc + ((size_t)s * P.N + c0) * P.stride);
@@ -599,7 +605,8 @@ hipError_t launch_plan(const Params&, const Work&, hipStream_t) { return hipSucc
 hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t st) {
   if (P.N > 0)
   {
-    const dim3 grid((P.N + SETUP_NT - 1) / SETUP_NT, P.Br);
+    const int nblk = (P.N + SETUP_NT - 1) / SETUP_NT;
+    const dim3 grid(((nblk + XCDS - 1) / XCDS) * XCDS * P.Br);
     if (P.K == 10) hipLaunchKernelGGL(k_setup<10>, grid, dim3(SETUP_NT), 0, st, P, w, round);
     else if (P.K == 5) hipLaunchKernelGGL(k_setup<5>, grid, dim3(SETUP_NT), 0, st, P, w, round);
     else hipLaunchKernelGGL(k_setup<2>, grid, dim3(SETUP_NT), 0, st, P, w, round);

@@ -37,6 +37,7 @@ struct Params {
 };
 
 // Work-space views (device pointers).
+constexpr int XCDS = 8;  // workgroups are dealt to the 8 XCDs in turn; each has its own L2
 constexpr int MAX_ROUNDS = 64;  // a round covers at least one of the 64 scales
 constexpr int PROF_CH = 16;  // charts per profile workgroup
 
