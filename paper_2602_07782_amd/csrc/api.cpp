@@ -106,7 +106,7 @@ struct StageScope {  // brackets one stage's launches with a pair of events
 // ---- work space -------------------------------------------------------------
 struct Layout {
   size_t o_recs, o_srecs, o_keys, o_rank, o_perm, o_ca, o_desc, o_kc, o_cd, o_fl, o_xs, o_ys, o_mir,
-      o_feas, o_rows, o_wdv, o_hdv, o_kslot, o_pcol, o_prow, o_Hs, o_segneed, o_segbase, o_cnt, o_gq, o_gq_cnt, o_live, o_arena,
+      o_feas, o_rows, o_wdv, o_hdv, o_kslot, o_pcol, o_prow, o_Hs, o_segneed, o_segbase, o_cnt, o_gq, o_gq_cnt, o_live, o_aord, o_arena,
       total;
 };
 
@@ -163,6 +163,7 @@ Layout layout(const Params& P) {
   L.o_gq = take((size_t)P.B * ((n1 + PROF_CH - 1) / PROF_CH) * 4);
   L.o_gq_cnt = take(4);
   L.o_live = take((MAX_ROUNDS + 1) * 4);
+  L.o_aord = take((size_t)P.count * 4);
   L.o_arena = take((size_t)P.arena_cap * 4);
   L.total = off;
   return L;
@@ -198,6 +199,7 @@ Work carve(void* base, const Layout& L) {
   W.gq = reinterpret_cast<int32_t*>(b + L.o_gq);
   W.gq_cnt = reinterpret_cast<int32_t*>(b + L.o_gq_cnt);
   W.live = reinterpret_cast<int32_t*>(b + L.o_live);
+  W.aord = reinterpret_cast<int32_t*>(b + L.o_aord);
   W.arena = reinterpret_cast<uint32_t*>(b + L.o_arena);
   return W;
 }

@@ -206,7 +206,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   __shared__ int32_t s_wd[FWIN], s_cdn[FWIN], s_H[FWIN];
 
   if (round_idle(w, round)) return;
-  const int s = blockIdx.x, a = blockIdx.y;
+  const int s = blockIdx.x, a = w.aord[blockIdx.y];
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
   const AtlasDesc d = w.desc[a];
   const int k = slot_k(P, d, round, s);

@@ -347,8 +347,9 @@ __global__ __launch_bounds__(256) void k_place(Params P, Work w) {
 // Per-thread sums stay below 2^57 (area2 < 2^47, at most 1,024 charts per
 // thread) and a wavefront's below 2^63; the block total is taken in 128 bits.
 // Lane k - 1 of wavefront 0 tests scale k; k_top is the largest passing one.
+constexpr int ORDER_MAX = 4096;  // largest batch whose atlases are reordered for packing
 __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
-  __shared__ uint64_t s_sum[4];
+  __shared__ uint64_t s_sum[4], s_before[4];
   __shared__ int32_t s_maxw[4], s_bad[4];
   const int a = blockIdx.x, lane = lane_id(), wv = threadIdx.x / WAVE;
   const AtlasDesc d = w.desc[a];
@@ -360,12 +361,24 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
     mw = max(mw, ch.W);
     bad |= !ch.valid;
   }
+  // the packing kernel takes the atlases with more charts first (their
+  // searches take longest, so they should not start last), ties by index;
+  // a batch of more than ORDER_MAX atlases keeps its own order
+  uint64_t before = 0;
+  if (P.count <= ORDER_MAX)
+    for (int b = threadIdx.x; b < P.count; b += blockDim.x) {
+      const int nb = w.desc[b].n;
+      before += (nb > d.n || (nb == d.n && b < a)) ? 1 : 0;
+    }
   sum = wave_sum_u64(sum);
+  before = wave_sum_u64(before);
   mw = wave_max(mw);
   bad = wave_max(bad);
-  if (lane == 0) { s_sum[wv] = sum; s_maxw[wv] = mw; s_bad[wv] = bad; }
+  if (lane == 0) { s_sum[wv] = sum; s_maxw[wv] = mw; s_bad[wv] = bad; s_before[wv] = before; }
   __syncthreads();
   if (wv != 0) return;
+  if (lane == 0)
+    w.aord[P.count <= ORDER_MAX ? (int)(s_before[0] + s_before[1] + s_before[2] + s_before[3]) : a] = a;
   unsigned __int128 S = 0;
   int32_t MW = 0;
   bad = 0;

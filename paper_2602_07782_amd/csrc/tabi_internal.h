@@ -68,6 +68,7 @@ struct Work {
   int32_t* cnt;         // [count] fold-and-push workgroups of the atlas done this round
   int32_t* gq;          // [B][ceil(N / PROF_CH)] profile blocks queued for the general evaluation
   int32_t* gq_cnt;      // [1] queued blocks this round (cleared by the set-up kernel)
+  int32_t* aord;        // [count] dispatch order of the packing kernel's atlases
   int32_t* live;        // [MAX_ROUNDS + 1] live[r] != 0: some atlas still searches in round
                         // r >= 1 (set by round r - 1's selection, cleared at the start)
   uint32_t* arena;      // profiles: per grown column (top, bottom), per grown row
