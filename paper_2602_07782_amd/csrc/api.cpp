@@ -343,7 +343,7 @@ struct ManyShape {
 const ManyShape kManyShapes[] = {
     {8, 64, 8, 512, 78 * 1024}, {4, 64, 4, 512, 78 * 1024}, {16, 64, 16, 512, 78 * 1024},
     {8, 64, 8, 1024, 0},        {16, 64, 16, 1024, 0},      {4, 2, 32, 512, 78 * 1024},
-    {4, 3, 16, 512, 78 * 1024}};
+    {4, 3, 16, 512, 78 * 1024}, {4, 64, 4, 1024, 0}};
 constexpr int kNumManyShapes = (int)(sizeof(kManyShapes) / sizeof(kManyShapes[0]));
 
 // slots per round of a schedule; returns the number of rounds (<= 64)
