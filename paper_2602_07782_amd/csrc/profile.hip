@@ -26,7 +26,7 @@
 
 namespace tabi {
 
-constexpr int LAY_NT = 256;
+
 constexpr int ALLOC_NT = 1024;
 constexpr int PROF_NT = 256;
 constexpr int PROF_GEN_BLOCKS = 1024;  // grid of the queued-block launch
@@ -223,11 +223,12 @@ __global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w, int round)
 
 // Offsets of every chart's grown columns and rows within its (atlas, slot)
 // segment, and the segment's size in words (0 when the slot does not run).
+template <int LAY_NT>
 __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) {
   __shared__ int64_t s_tot[LAY_NT / WAVE][2];
   __shared__ int32_t s_last;
   if (round_idle(w, round)) return;
-  const int a = blockIdx.x, s = blockIdx.y;
+  const int a = w.aord[blockIdx.x], s = blockIdx.y;  // atlases with more charts first
   const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
   const AtlasDesc d = w.desc[a];
   const bool run = P.fixed_k > 0 ? !d.bad : (!d.done && d.ktop >= 1);
@@ -554,7 +555,12 @@ __global__ __launch_bounds__(PROF_NT) void k_profile_general(Params P, Work w, i
 hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_t st) {
   if (P.N <= 0) return hipSuccess;
   // with no arena the placement still runs: it marks every segment unstored
-  hipLaunchKernelGGL(k_layout, dim3(P.count, P.Br), dim3(LAY_NT), 0, st, P, w, round);
+  // 256 threads per (atlas, slot) for a single atlas; 1024 for batches, whose
+  // largest atlases hold thousands of charts
+  if (P.count == 1)
+    hipLaunchKernelGGL(k_layout<256>, dim3(P.count, P.Br), dim3(256), 0, st, P, w, round);
+  else
+    hipLaunchKernelGGL(k_layout<1024>, dim3(P.count, P.Br), dim3(1024), 0, st, P, w, round);
   if (P.count != 1)  // a single atlas is placed by the last k_layout workgroup
     hipLaunchKernelGGL(k_alloc, dim3(1), dim3(ALLOC_NT), 0, st, P, w, round);
   const int nbx = (P.N + PROF_CH - 1) / PROF_CH;
