@@ -115,18 +115,26 @@ __device__ inline bool sweep_side_of(const KView& kv, const Chart& ch, int k, in
   return L.ok;
 }
 
-// side_eval with the line data and reciprocal read from the sweep record
+// side_eval with the line data and reciprocal read from the sweep record.
+// The whole record is loaded at once and every case is computed and then
+// selected, so a side costs one shared-memory round trip and no branch.  The
+// products run on the 24-bit multiplier: |n|, d <= 2^14 (a direction's
+// cosine or sine in 2^14 units), |t| < 2^15 and |q| < 2^23 (|P| < 2^31,
+// d >= 3196 for an OBB direction), and q * d is only needed modulo 2^32.
 template <bool CEIL>
 __device__ inline int32_t sweep_side(const SweepSide& s, int32_t t, int32_t n) {
-  const bool useA = t + 1 <= s.sa, useB = t >= s.sb;
-  const int32_t M = useA ? s.MA : s.MB, nn = useA ? s.nA : s.nB, d = useA ? s.dA : s.dB;
-  const float rc = useA ? s.rA : s.rB;
-  const int32_t P = M + nn * (useA ? t + 1 : t);
+  const int4 h0 = *reinterpret_cast<const int4*>(&s.sa);  // sa, sb, corner, last
+  const int4 h1 = *reinterpret_cast<const int4*>(&s.MA);  // MA, nA, dA, MB
+  const int4 h2 = *reinterpret_cast<const int4*>(&s.nB);  // nB, dB, rA, rB
+  const bool useA = t + 1 <= h0.x, useB = t >= h0.y;
+  const int32_t M = useA ? h1.x : h1.w, nn = useA ? h1.y : h2.x, d = useA ? h1.z : h2.y;
+  const float rc = __int_as_float(useA ? h2.z : h2.w);
+  const int32_t P = M + __mul24(nn, useA ? t + 1 : t);
   int32_t q = (int32_t)floorf((float)P * rc);
-  const int32_t r = P - q * d;
+  const int32_t r = P - __mul24(q, d);
   q += r < 0 ? -1 : (r >= d ? 1 : 0);
   if (CEIL) q = -q;
-  return t == n - 1 ? s.last : ((useA || useB) ? q : s.corner);
+  return t == n - 1 ? h0.w : ((useA || useB) ? q : h0.z);
 }
 
 // Top / bottom of column u and left / right of row u, as column_row_bounds
