@@ -100,18 +100,21 @@ __device__ inline uint64_t row_sum_u64(uint64_t v) {
 __device__ inline void slab_contrib(int32_t* lo, int32_t* hi, int K, int64_t E, int64_t a1,
                                     int64_t b1, int64_t a2, int64_t b2) {
   // a = slab axis coordinate, b = value; slabs are K*a in [jE, (j+1)E].
+  // The local coordinates lie in [0, E] with 0 < E < 2^23, so K*a < 2^27 and
+  // the slab indices come from 32-bit divisions (same quotients as 64-bit).
   const int64_t A1 = (int64_t)K * a1, A2 = (int64_t)K * a2;
+  const int32_t e32 = (int32_t)E, a1s = (int32_t)A1, a2s = (int32_t)A2;
   // endpoint (a1, b1): the slab containing it, or both slabs at a slab line
-  int64_t q = A1 / E, r = A1 % E;
-  int jh = (int)min<int64_t>(q, K - 1);
-  int jl = (r == 0) ? (int)max<int64_t>(q - 1, 0) : jh;
+  const int32_t q = a1s / e32, r = a1s - q * e32;
+  int jh = min(q, K - 1);
+  int jl = (r == 0) ? max(q - 1, 0) : jh;
   for (int j = jl; j <= jh; ++j) {
     atomicMin(&lo[j], (int32_t)b1);
     atomicMax(&hi[j], (int32_t)b1);
   }
   // crossings with interior slab lines strictly between the endpoints
-  const int64_t mn = min(A1, A2), mx = max(A1, A2);
-  int64_t m0 = mn / E + 1, m1 = (mx - 1) / E;
+  const int32_t mn = min(a1s, a2s), mx = max(a1s, a2s);
+  int32_t m0 = mn / e32 + 1, m1 = (mx - 1) / e32;  // mx - 1 >= -1 truncates to 0
   if (m0 < 1) m0 = 1;
   if (m1 > K - 1) m1 = K - 1;
   for (int64_t m = m0; m <= m1; ++m) {
