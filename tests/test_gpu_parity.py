@@ -50,6 +50,37 @@ def assert_pack_equal(tabi, orc, inp, label):
     assert np.array_equal(gor, oor), (label, np.argwhere(gor != oor)[:5])
 
 
+def test_gpu_equals_stored_oracle_packs(tabi):
+    """The stored oracle packs (tests/golden, written by the oracle alone)
+    through tabi_pack one by one and through one tabi_pack_many batch."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "oracle_packs.json")) as f:
+        cases = json.load(f)["cases"]
+    inputs = []
+    for c in cases:
+        inp = synth.AtlasInput(np.array(c["xy"], np.int32), np.array(c["offsets"], np.int32),
+                               c["atlas_w"], c["atlas_h"], c["padding"], c["quality"])
+        _say("golden:", c["name"], "n =", inp.n)
+        gxy, gor, gsc = gpu_pack(tabi, inp)
+        assert gsc == c["scale"], c["name"]
+        assert np.array_equal(gxy.reshape(-1), np.array(c["out_xy"], np.int32)), c["name"]
+        assert np.array_equal(gor, np.array(c["out_orient"], np.uint8)), c["name"]
+        inputs.append(inp)
+    # one batch per (padding, quality): a batch shares both
+    for pq in sorted({(i.padding, i.quality) for i in inputs}):
+        sel = [(c, i) for c, i in zip(cases, inputs) if (i.padding, i.quality) == pq]
+        xy, ori, sc = [_np(t) for t in tabi.pack_many([i for _, i in sel])]
+        c0 = 0
+        for a, (c, i) in enumerate(sel):
+            assert float(sc[a]) == c["scale"], c["name"]
+            assert np.array_equal(xy[c0:c0 + i.n].reshape(-1),
+                                  np.array(c["out_xy"], np.int32)), c["name"]
+            assert np.array_equal(ori[c0:c0 + i.n], np.array(c["out_orient"], np.uint8)), c["name"]
+            c0 += i.n
+
+
 # ---------------------------------------------------------------------------
 # stage parity
 # ---------------------------------------------------------------------------
