@@ -232,8 +232,8 @@ def main():
                          "copy whose byte count calibrates FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(atlases and scales shard across GPUs without communication; see DESIGN.md)",
+        print("bench.py measures one GPU only: there is no multi-GPU path here "
+              "(atlases and scales would shard across GPUs without communication)",
               file=sys.stderr)
         sys.exit(2)
 
