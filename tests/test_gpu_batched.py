@@ -198,3 +198,24 @@ def test_batch_without_stored_profiles(tabi, orc, words):
         check_batch(tabi, orc, small_batch(3, 970), use_workspace=True)
     finally:
         tabi.debug_set_profile_cap(-1)
+
+
+def test_batch_above_reorder_limit(tabi, orc):
+    """More atlases than the packing kernel reorders (4,096): the batch keeps
+    its own dispatch order and every sampled atlas still equals the oracle."""
+    rng = np.random.default_rng(990)
+    mix = synth.CONFIGS["mixed2k"]["mix"]
+    count = 4100
+    inputs = [synth.make_custom(int(rng.integers(1, 5)), 64, 64, 2, 2, 1.2, 1.2, mix, 99000 + a,
+                                fast=True)
+              for a in range(count)]
+    _say("batch of", count, "atlases,", sum(i.n for i in inputs), "charts")
+    xy, ori, sc = [t.cpu().numpy() for t in tabi.pack_many(inputs)]
+    starts = np.cumsum([0] + [i.n for i in inputs])
+    for a in list(range(0, count, 97)) + [count - 1]:
+        inp = inputs[a]
+        oxy, oori, osc, ok = orc.pack(inp)
+        c0 = starts[a]
+        assert float(sc[a]) == osc, (a, sc[a], osc)
+        assert np.array_equal(xy[c0:c0 + inp.n], oxy), a
+        assert np.array_equal(ori[c0:c0 + inp.n], oori), a
