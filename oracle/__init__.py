@@ -62,6 +62,9 @@ def lib():
         L.orc_prep_chart.argtypes = [I32P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(OrcChart)]
         L.orc_profiles.argtypes = [ctypes.POINTER(OrcChart), ctypes.c_int32, I32P, I32P,
                                    I32P, I32P, I32P, I32P]
+        L.orc_row_proxies.argtypes = [ctypes.POINTER(OrcChart), ctypes.c_int32, I32P, I32P, I32P,
+                                      I32P, I32P]
+        L.orc_knee_update.argtypes = [I32P, ctypes.c_int32, ctypes.c_int32, I32P, I32P]
         L.orc_quality.argtypes = [ctypes.c_int32, ctypes.c_int32, I32P, I32P]
         L.orc_interlock.argtypes = [I32P, ctypes.c_int32, ctypes.c_int32, I32P, ctypes.c_int32,
                                     ctypes.c_int32]
@@ -159,6 +162,25 @@ def profiles(ch, k):
                        _p32(bot), _p32(left), _p32(right))
     assert ww.value == w and hh.value == h
     return top[:w], bot[:w], left[:h], right[:h]
+
+
+def row_proxies(ch, k):
+    """Undilated per-proxy row bounds at k: (la, ra) local AABBs, (lo, ro) OBB."""
+    h = -(-k * int(ch.H) // 16384)
+    out = [np.zeros(max(h, 1), np.int32) for _ in range(4)]
+    hh = ctypes.c_int32(0)
+    lib().orc_row_proxies(ctypes.byref(ch), int(k), ctypes.byref(hh), *[_p32(a) for a in out])
+    assert hh.value == h
+    return tuple(a[:h] for a in out)
+
+
+def knee_update(F, direction, left, right):
+    """Alg. 4 on frontline F: returns (active, left, right)."""
+    f = _c(F, np.int32)
+    lft, rgt = ctypes.c_int32(left), ctypes.c_int32(right)
+    act = lib().orc_knee_update(_p32(f), f.shape[0], int(direction), ctypes.byref(lft),
+                                ctypes.byref(rgt))
+    return bool(act), int(lft.value), int(rgt.value)
 
 
 def interlock(rightA, wdA, leftB, d):

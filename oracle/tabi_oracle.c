@@ -329,6 +329,43 @@ static void obb_row(const orc_chart* ch, int64_t k, int64_t j, int64_t* Lo, int6
   *Ro = (int64_t)right;
 }
 
+/* Left / right of texel row j under each proxy separately (Sec. 4.1.1):
+ * la, ra from the local AABBs (the y-slices overlapping the open row, merged
+ * with the x-slices whose v-range reaches into it: the two sets of local
+ * AABBs refine each other); lo, ro from the OBB alone, over the row band,
+ * kept inside the chart's own texel box [0, w] (when the best of the 8
+ * boxes is the axis-aligned one, the OBB is that box).  Outward rounding
+ * throughout.                                                              */
+static void row_proxies(const orc_chart* ch, int64_t kk, int64_t j, int64_t* la, int64_t* ra,
+                        int64_t* lo, int64_t* ro) {
+  const int64_t W = ch->W, H = ch->H, K = ch->K;
+  const int64_t w = cdiv64(kk * W, QS);
+  int64_t ly = INT64_MAX, ry = INT64_MIN;
+  for (int64_t s = 0; s < K; ++s) {
+    if (s * H * kk < QS * K * (j + 1) && (s + 1) * H * kk > QS * K * j) {
+      ly = mini64(ly, fdiv64(ch->xlo[s] * kk, QS));
+      ry = maxi64(ry, cdiv64(ch->xhi[s] * kk, QS));
+    }
+  }
+  int64_t lx = INT64_MAX, rx = INT64_MIN;
+  for (int64_t s = 0; s < K; ++s) {
+    if (ch->ylo[s] * kk < QS * (j + 1) && ch->yhi[s] * kk > QS * j) {
+      lx = mini64(lx, fdiv64(s * W * kk, QS * K));
+      rx = maxi64(rx, cdiv64((s + 1) * W * kk, QS * K));
+    }
+  }
+  *la = maxi64(ly, lx);
+  *ra = mini64(ry, rx);
+  int64_t ol = 0, orr = w;
+  if (ch->obb) {
+    obb_row(ch, kk, j, &ol, &orr);
+    ol = maxi64(ol, 0);
+    orr = mini64(orr, w);
+  }
+  *lo = ol;
+  *ro = orr;
+}
+
 void orc_profiles(const orc_chart* ch, int32_t k, int32_t* w_out, int32_t* h_out,
                   int32_t* top, int32_t* bot, int32_t* left, int32_t* right) {
   const int64_t W = ch->W, H = ch->H, K = ch->K, kk = k;
@@ -365,29 +402,21 @@ void orc_profiles(const orc_chart* ch, int32_t k, int32_t* w_out, int32_t* h_out
     bot[i] = (int32_t)B;
   }
   for (int64_t j = 0; j < h; ++j) {
-    int64_t ly = INT64_MAX, ry = INT64_MIN;
-    for (int64_t s = 0; s < K; ++s) {
-      if (s * H * kk < QS * K * (j + 1) && (s + 1) * H * kk > QS * K * j) {
-        ly = mini64(ly, fdiv64(ch->xlo[s] * kk, QS));
-        ry = maxi64(ry, cdiv64(ch->xhi[s] * kk, QS));
-      }
-    }
-    int64_t lx = INT64_MAX, rx = INT64_MIN;
-    for (int64_t s = 0; s < K; ++s) {
-      if (ch->ylo[s] * kk < QS * (j + 1) && ch->yhi[s] * kk > QS * j) {
-        lx = mini64(lx, fdiv64(s * W * kk, QS * K));
-        rx = maxi64(rx, cdiv64((s + 1) * W * kk, QS * K));
-      }
-    }
-    int64_t Lf = maxi64(ly, lx), Rf = mini64(ry, rx);
-    if (ch->obb) {
-      int64_t lo, ro;
-      obb_row(ch, kk, j, &lo, &ro);
-      Lf = maxi64(Lf, lo);
-      Rf = mini64(Rf, ro);
-    }
-    left[j] = (int32_t)Lf;
-    right[j] = (int32_t)Rf;
+    int64_t la, ra, lo, ro;
+    row_proxies(ch, kk, j, &la, &ra, &lo, &ro);
+    left[j] = (int32_t)maxi64(la, lo);
+    right[j] = (int32_t)mini64(ra, ro);
+  }
+}
+
+void orc_row_proxies(const orc_chart* ch, int32_t k, int32_t* h_out, int32_t* la, int32_t* ra,
+                     int32_t* lo, int32_t* ro) {
+  int64_t h = cdiv64((int64_t)k * ch->H, QS);
+  *h_out = (int32_t)h;
+  for (int64_t j = 0; j < h; ++j) {
+    int64_t a, b, c, d;
+    row_proxies(ch, k, j, &a, &b, &c, &d);
+    la[j] = (int32_t)a; ra[j] = (int32_t)b; lo[j] = (int32_t)c; ro[j] = (int32_t)d;
   }
 }
 
@@ -421,16 +450,20 @@ typedef struct {
   int n, Wd, Hd, Wa, Ha, p, topt;
   int32_t *wd, *hd, *h;
   int64_t* Hq;                       /* unscaled Q8 heights, for knees */
-  int32_t **topd, **botd, **leftd, **rightd;
+  int32_t **topd, **botd;
+  /* grown row bounds of each proxy: local AABBs (la, ra) and OBB (lo, ro) */
+  int32_t **lad, **rad, **lod, **rod;
   int32_t* cd;
+  uint8_t* nfl;                      /* interlock flags of (c-1, c) */
 } kdata;
 
 static void free_kdata(kdata* D) {
   for (int c = 0; c < D->n; ++c) {
-    free(D->topd[c]); free(D->botd[c]); free(D->leftd[c]); free(D->rightd[c]);
+    free(D->topd[c]); free(D->botd[c]);
+    free(D->lad[c]); free(D->rad[c]); free(D->lod[c]); free(D->rod[c]);
   }
-  free(D->topd); free(D->botd); free(D->leftd); free(D->rightd);
-  free(D->wd); free(D->hd); free(D->h); free(D->Hq); free(D->cd);
+  free(D->topd); free(D->botd); free(D->lad); free(D->rad); free(D->lod); free(D->rod);
+  free(D->wd); free(D->hd); free(D->h); free(D->Hq); free(D->cd); free(D->nfl);
 }
 
 /* Gutters: a chart's footprint is grown by [0,p] x [0,p] toward +x,+y and
@@ -445,8 +478,10 @@ static void build_kdata(kdata* D, const orc_chart* ch, const int* perm, int n, i
   D->wd = calloc(n + 1, sizeof(int32_t)); D->hd = calloc(n + 1, sizeof(int32_t));
   D->h = calloc(n + 1, sizeof(int32_t)); D->Hq = calloc(n + 1, sizeof(int64_t));
   D->cd = calloc(n + 1, sizeof(int32_t));
+  D->nfl = calloc(n + 1, 1);
   D->topd = calloc(n + 1, sizeof(int32_t*)); D->botd = calloc(n + 1, sizeof(int32_t*));
-  D->leftd = calloc(n + 1, sizeof(int32_t*)); D->rightd = calloc(n + 1, sizeof(int32_t*));
+  D->lad = calloc(n + 1, sizeof(int32_t*)); D->rad = calloc(n + 1, sizeof(int32_t*));
+  D->lod = calloc(n + 1, sizeof(int32_t*)); D->rod = calloc(n + 1, sizeof(int32_t*));
   for (int c = 0; c < n; ++c) {
     const orc_chart* q = &ch[perm[c]];
     int64_t w = cdiv64((int64_t)k * q->W, QS), h = cdiv64((int64_t)k * q->H, QS);
@@ -454,12 +489,14 @@ static void build_kdata(kdata* D, const orc_chart* ch, const int* perm, int n, i
     int32_t* bot = malloc(sizeof(int32_t) * w);
     int32_t* lft = malloc(sizeof(int32_t) * h);
     int32_t* rgt = malloc(sizeof(int32_t) * h);
+    int32_t* pr[4];
+    for (int e = 0; e < 4; ++e) pr[e] = malloc(sizeof(int32_t) * h);
     int32_t ww, hh;
     orc_profiles(q, k, &ww, &hh, top, bot, lft, rgt);
+    orc_row_proxies(q, k, &hh, pr[0], pr[1], pr[2], pr[3]);
     int wd = ww + p, hd = hh + p;
     D->wd[c] = wd; D->hd[c] = hd; D->h[c] = hh; D->Hq[c] = q->H;
     D->topd[c] = malloc(sizeof(int32_t) * wd); D->botd[c] = malloc(sizeof(int32_t) * wd);
-    D->leftd[c] = malloc(sizeof(int32_t) * hd); D->rightd[c] = malloc(sizeof(int32_t) * hd);
     for (int i = 0; i < wd; ++i) {
       int lo = i - p < 0 ? 0 : i - p, hi = i < ww - 1 ? i : ww - 1;
       int32_t t = INT32_MAX, b = INT32_MIN;
@@ -467,28 +504,48 @@ static void build_kdata(kdata* D, const orc_chart* ch, const int* perm, int n, i
       D->topd[c][i] = t;
       D->botd[c][i] = b + p;
     }
-    for (int j = 0; j < hd; ++j) {
-      int lo = j - p < 0 ? 0 : j - p, hi = j < hh - 1 ? j : hh - 1;
-      int32_t l = INT32_MAX, r = INT32_MIN;
-      for (int s = lo; s <= hi; ++s) { if (lft[s] < l) l = lft[s]; if (rgt[s] > r) r = rgt[s]; }
-      D->leftd[c][j] = l;
-      D->rightd[c][j] = r + p;
+    int32_t** dst[4] = {&D->lad[c], &D->rad[c], &D->lod[c], &D->rod[c]};
+    for (int e = 0; e < 4; e += 2) {  /* each proxy's rows, grown */
+      int32_t* L = malloc(sizeof(int32_t) * hd);
+      int32_t* R = malloc(sizeof(int32_t) * hd);
+      for (int j = 0; j < hd; ++j) {
+        int lo = j - p < 0 ? 0 : j - p, hi = j < hh - 1 ? j : hh - 1;
+        int32_t l = INT32_MAX, r = INT32_MIN;
+        for (int s = lo; s <= hi; ++s) {
+          if (pr[e][s] < l) l = pr[e][s];
+          if (pr[e + 1][s] > r) r = pr[e + 1][s];
+        }
+        L[j] = l;
+        R[j] = r + p;
+      }
+      *dst[e] = L;
+      *dst[e + 1] = R;
     }
     free(top); free(bot); free(lft); free(rgt);
+    for (int e = 0; e < 4; ++e) free(pr[e]);
   }
   /* Horizontal compacting distance between sorted neighbours (Sec. 4.1.2):
-   * with both charts top-aligned, the largest leftward slide of the second
-   * that keeps every shared row apart, measured on the per-row tightest
-   * proxy bounds. */
+   * with both charts top-aligned, each proxy gives the largest leftward
+   * slide of the second chart that keeps the proxies apart in every shared
+   * texel row; the pair is compacted by the larger of the two.  The
+   * interlock flags come from the proxy that gave that distance (App. A,
+   * "Detecting Interlocking Charts"; the local AABBs on a tie), and a zero
+   * distance restricts neither chart. */
   D->cd[0] = 0;
   for (int c = 1; c < n; ++c) {
     int rows = D->hd[c - 1] < D->hd[c] ? D->hd[c - 1] : D->hd[c];
-    int32_t best = INT32_MAX;
+    int32_t ga = INT32_MAX, go = INT32_MAX;
     for (int j = 0; j < rows; ++j) {
-      int32_t g = D->wd[c - 1] - D->rightd[c - 1][j] + D->leftd[c][j];
-      if (g < best) best = g;
+      int32_t g = D->wd[c - 1] - D->rad[c - 1][j] + D->lad[c][j];
+      if (g < ga) ga = g;
+      g = D->wd[c - 1] - D->rod[c - 1][j] + D->lod[c][j];
+      if (g < go) go = g;
     }
-    D->cd[c] = best;
+    int obb_wins = go > ga;
+    D->cd[c] = obb_wins ? go : ga;
+    D->nfl[c] = (uint8_t)orc_interlock(obb_wins ? D->rod[c - 1] : D->rad[c - 1], D->hd[c - 1],
+                                       D->wd[c - 1], obb_wins ? D->lod[c] : D->lad[c], D->hd[c],
+                                       D->wd[c - 1] - D->cd[c]);
   }
 }
 
@@ -577,9 +634,12 @@ static void evaluate(const kdata* D, const int32_t* F, int rs, config* g) {
     g->y[t] = y;
   }
   /* correct (Alg. 1): charts that may not move above a compacted neighbour
-   * are moved down to it until no such pair is out of order.  Every pair
-   * whose grown boxes share columns is checked, not only direct neighbours:
-   * a narrow chart between two others can let the outer two share columns. */
+   * are moved down to it until no such pair is out of order.  Neighbours
+   * carry the flags of their compacting distance.  Every other pair whose
+   * grown boxes share columns is checked too: a narrow chart between two
+   * others can let the outer two share columns.  Such a pair has no
+   * distance of its own; its flags are tested on the rows both proxies
+   * allow (per grown row, the intersection of the two proxies' spans). */
   if (g->hc) {
     int cap = 16, m = 0;
     int32_t* pa = malloc(sizeof(int32_t) * cap * 3);
@@ -587,8 +647,19 @@ static void evaluate(const kdata* D, const int32_t* F, int rs, config* g) {
       for (int Bt = A + 1; Bt < cnt; ++Bt) {
         int d = g->X[Bt] - g->X[A];
         if (d >= D->wd[rs + A]) break;
-        int fl = orc_interlock(D->rightd[rs + A], D->hd[rs + A], D->wd[rs + A],
-                               D->leftd[rs + Bt], D->hd[rs + Bt], d);
+        int fl;
+        if (Bt == A + 1) {
+          fl = D->nfl[rs + Bt];
+        } else {
+          int ca = rs + A, cb = rs + Bt;
+          int32_t* rA = malloc(sizeof(int32_t) * D->hd[ca]);
+          int32_t* lB = malloc(sizeof(int32_t) * D->hd[cb]);
+          for (int j = 0; j < D->hd[ca]; ++j) rA[j] = mini64(D->rad[ca][j], D->rod[ca][j]);
+          for (int j = 0; j < D->hd[cb]; ++j) lB[j] = maxi64(D->lad[cb][j], D->lod[cb][j]);
+          fl = orc_interlock(rA, D->hd[ca], D->wd[ca], lB, D->hd[cb], d);
+          free(rA);
+          free(lB);
+        }
         if (!fl) continue;
         if (m == cap) { cap *= 2; pa = realloc(pa, sizeof(int32_t) * cap * 3); }
         pa[3 * m] = A; pa[3 * m + 1] = Bt; pa[3 * m + 2] = fl; ++m;
@@ -640,6 +711,14 @@ static void update_knee(knee_t* kn, const int32_t* F, int Wd) {
       if (F[x] >= h0 && x < nl) nl = x;
     kn->left = nl;
   }
+}
+
+int orc_knee_update(const int32_t* F, int32_t Wd, int32_t dir, int32_t* left, int32_t* right) {
+  knee_t kn = {1, dir, *left, *right};
+  update_knee(&kn, F, Wd);
+  *left = kn.left;
+  *right = kn.right;
+  return kn.active;
 }
 
 /* Knee detection (Sec. 4.2, App. A): the largest drop in unscaled height
@@ -886,8 +965,7 @@ int tabi_oracle_pairs(const int32_t* xy, const int32_t* offsets, int32_t n, int3
   flags[0] = 0;
   for (int c = 1; c < n; ++c) {
     cd[c] = D.cd[c];
-    flags[c] = (uint8_t)orc_interlock(D.rightd[c - 1], D.hd[c - 1], D.wd[c - 1], D.leftd[c],
-                                      D.hd[c], D.wd[c - 1] - D.cd[c]);
+    flags[c] = D.nfl[c];
   }
   free_kdata(&D);
   free(perm); free(ch);

@@ -46,6 +46,12 @@ int orc_prep_chart(const int32_t* xy, int32_t nverts, int32_t K, orc_chart* out)
 void orc_profiles(const orc_chart* ch, int32_t k, int32_t* w, int32_t* h,
                   int32_t* top, int32_t* bot, int32_t* left, int32_t* right);
 
+/* Per-proxy left / right of each texel row at scale k/64 (Sec. 4.1.1):
+ * la, ra from the local AABBs, lo, ro from the OBB kept inside the chart's
+ * texel box.  h entries each; returns h. */
+void orc_row_proxies(const orc_chart* ch, int32_t k, int32_t* h, int32_t* la, int32_t* ra,
+                     int32_t* lo, int32_t* ro);
+
 /* Quality preset -> slices K and t_opt percent for a set of n charts. */
 void orc_quality(int32_t quality, int32_t n, int32_t* K, int32_t* topt);
 
@@ -74,7 +80,9 @@ int tabi_oracle_order(const int32_t* xy, const int32_t* offsets, int32_t n,
 
 /* Horizontal compacting distance and interlock flags of every adjacent sorted
  * pair at scale k: cd[c], flags[c] (bit0: c may not move above c-1,
- * bit1: c-1 may not move above c) for c >= 1; cd[0] = flags[0] = 0. */
+ * bit1: c-1 may not move above c) for c >= 1; cd[0] = flags[0] = 0.
+ * cd is the larger of the local-AABB and the OBB distance (Sec. 4.1.2);
+ * the flags come from the proxy that gave it (App. A). */
 int tabi_oracle_pairs(const int32_t* xy, const int32_t* offsets, int32_t n,
                       int32_t padding, int32_t quality, int32_t k,
                       int32_t* cd, uint8_t* flags);
@@ -84,6 +92,12 @@ int tabi_oracle_pairs(const int32_t* xy, const int32_t* offsets, int32_t n,
  * bit1 = A may not move above B.  Zero when d >= wdA (no shared columns). */
 int orc_interlock(const int32_t* rightA, int32_t hdA, int32_t wdA,
                   const int32_t* leftB, int32_t hdB, int32_t d);
+
+/* UpdateKneeLocation (Alg. 4) on a committed frontline F[Wd] for a knee of
+ * direction dir (0 left-to-right, 1 right-to-left) spanning [left, right);
+ * updates the span and returns 0 when the knee ends (its probe texel lies
+ * outside the frontline), 1 otherwise. */
+int orc_knee_update(const int32_t* F, int32_t Wd, int32_t dir, int32_t* left, int32_t* right);
 
 /* CorrectYOffsets over m constrained pairs pa[3q..3q+2] = (A, B, flags):
  * flags bit0 -> y[B] >= y[A], bit1 -> y[A] >= y[B]; y updated in place. */

@@ -10,9 +10,10 @@ is checked here, each by code independent of the oracle:
   and exact rectangles give exact profiles (App. A, "Parallel Pushing");
 * local-AABB slices equal exact rational clipping, rounded outward (Sec. 4.1.1);
 * the OBB contains the chart and is the smallest of the 8 boxes (App. A);
-* compacting distance = first collision of sliding proxy footprints minus one
-  (Sec. 4.1.2) and real rasters never collide at that distance;
-* interlock flags are set whenever an upward shift makes proxies meet (App. A);
+* compacting distance = the larger of the two proxies' first-collision
+  slides (Sec. 4.1.2), and real rasters never collide at that distance;
+* interlock flags are those of the proxy that gave the distance, set exactly
+  when an upward shift makes that proxy's footprints meet (App. A);
 * the correction loop reaches the least fixpoint (Alg. 1);
 * closed forms for a single chart and for identical rectangles (Sec. 3.1 search);
 * knee thresholds at +-1 Q8 unit (App. A "Knee Detection Parameters");
@@ -270,8 +271,39 @@ def _pair_data(orc, inp, K, k):
     return perm, cd, fl, recs
 
 
+def _proxy_footprints(orc, rec, k, p):
+    """Grown row footprints of the local-AABB proxy and of the OBB proxy."""
+    w = -(-k * int(rec.W) // T)
+    la, ra, lo, ro = orc.row_proxies(rec, k)
+    return (dilate(row_footprint(la, ra, w), p), dilate(row_footprint(lo, ro, w), p))
+
+
+def _first_collision(fa, fb):
+    """Largest leftward slide of fb (starting just right of fa, top-aligned)
+    before the two footprints share a texel, by brute force."""
+    wdA = fa.shape[1]
+    rows = min(fa.shape[0], fb.shape[0])
+
+    def collide(shift):  # B's box starts at wdA - shift
+        x = wdA - shift
+        for j in range(rows):
+            a = np.nonzero(fa[j])[0]
+            b = np.nonzero(fb[j])[0] + x
+            if np.intersect1d(a, b).size:
+                return True
+        return False
+    s = 0
+    while s < wdA and not collide(s + 1):
+        s += 1
+    assert not collide(s)
+    return s
+
+
 @pytest.mark.parametrize("seed", range(15))
-def test_compaction_distance_is_first_collision_minus_one(orc, chk, seed):
+def test_compaction_distance_is_the_larger_proxy_distance(orc, chk, seed):
+    """Sec. 4.1.2: each proxy gives the slide at which it first collides;
+    the pair is compacted by the larger of the two, and the real grown
+    rasters are still apart there."""
     inp = small_input(4000 + seed, n=10)
     K, _ = orc.quality(inp.quality, inp.n)
     p = inp.padding
@@ -280,25 +312,15 @@ def test_compaction_distance_is_first_collision_minus_one(orc, chk, seed):
         perm, cd, fl, recs = _pair_data(orc, inp, K, k)
         for t in range(1, inp.n):
             A, B = recs[perm[t - 1]], recs[perm[t]]
-            tA, bA, lA, rA = orc.profiles(A, k)
-            tB, bB, lB, rB = orc.profiles(B, k)
-            fa = dilate(row_footprint(lA, rA, len(tA)), p)
-            fb = dilate(row_footprint(lB, rB, len(tB)), p)
-            wdA = fa.shape[1]
-            rows = min(fa.shape[0], fb.shape[0])
-
-            def collide(shift):  # B's box starts at wdA - shift
-                x = wdA - shift
-                for j in range(rows):
-                    a = np.nonzero(fa[j])[0]
-                    b = np.nonzero(fb[j])[0] + x
-                    if np.intersect1d(a, b).size:
-                        return True
-                return False
+            aA, oA = _proxy_footprints(orc, A, k, p)
+            aB, oB = _proxy_footprints(orc, B, k, p)
+            wdA = aA.shape[1]
             c = int(cd[t])
             assert 0 <= c < wdA
-            assert not collide(c) and collide(c + 1)
+            assert c == max(_first_collision(aA, aB), _first_collision(oA, oB))
             # the real rasters, grown, are apart at that distance too
+            tA, _, lA, _ = orc.profiles(A, k)
+            tB, _, lB, _ = orc.profiles(B, k)
             uA, vA, _, _ = final_frame(inp.chart(perm[t - 1]), A)
             uB, vB, _, _ = final_frame(inp.chart(perm[t]), B)
             ra = dilate(chart_raster(chk, uA, vA, k, len(tA), len(lA)), p)
@@ -312,8 +334,38 @@ def test_compaction_distance_is_first_collision_minus_one(orc, chk, seed):
             assert g.max() <= 1
 
 
+def test_obb_distance_is_used_when_larger(orc):
+    """Two identical thin bars tilted by 3*pi/16 (their OBB direction is one
+    of the eight): the OBBs slide much further than the local AABBs allow,
+    so the OBB distance decides the pair."""
+    ang = 3 * math.pi / 16
+    L, Wb = 60.0, 6.0
+    pts = [(0, 0), (L, 0), (L, Wb), (0, Wb)]
+    def bar(dx):
+        P = []
+        for x, y in pts:
+            X = x * math.cos(ang) - y * math.sin(ang)
+            Y = x * math.sin(ang) + y * math.cos(ang)
+            P.append((round(256 * X) + dx, round(256 * Y)))
+        return np.array(P)
+    xy, off = synth.pack_csr([bar(0), bar(40000)])
+    inp = synth.AtlasInput(xy, off, 200, 200, 1, 0)
+    K, _ = orc.quality(0, 2)
+    recs = [orc.prep_chart(inp.chart(c), K) for c in range(2)]
+    assert all(r.obb for r in recs)
+    cd, fl = orc.pairs(inp, 64)
+    aA, oA = _proxy_footprints(orc, recs[0], 64, 1)
+    aB, oB = _proxy_footprints(orc, recs[1], 64, 1)
+    ca, co = _first_collision(aA, aB), _first_collision(oA, oB)
+    assert co > ca and int(cd[1]) == co
+
+
 @pytest.mark.parametrize("seed", range(15))
-def test_interlock_flags_are_sound(orc, seed):
+def test_interlock_flags_follow_the_deciding_proxy(orc, seed):
+    """App. A: the flags are those of the proxy that gave the compacting
+    distance (local AABBs on a tie); a flag is set exactly when some upward
+    shift of that chart makes the two grown proxies meet; a zero distance
+    restricts neither chart."""
     inp = small_input(5000 + seed, n=10)
     K, _ = orc.quality(inp.quality, inp.n)
     p = inp.padding
@@ -321,11 +373,13 @@ def test_interlock_flags_are_sound(orc, seed):
     perm, cd, fl, recs = _pair_data(orc, inp, K, k)
     for t in range(1, inp.n):
         A, B = recs[perm[t - 1]], recs[perm[t]]
-        tA, _, lA, rA = orc.profiles(A, k)
-        tB, _, lB, rB = orc.profiles(B, k)
-        LA, RA = hulls(dilate(row_footprint(lA, rA, len(tA)), p))
-        LB, RB = hulls(dilate(row_footprint(lB, rB, len(tB)), p))
-        d = len(tA) + p - int(cd[t])
+        aA, oA = _proxy_footprints(orc, A, k, p)
+        aB, oB = _proxy_footprints(orc, B, k, p)
+        use_obb = _first_collision(oA, oB) > _first_collision(aA, aB)
+        fa, fb = (oA, oB) if use_obb else (aA, aB)
+        LA, RA = hulls(fa)
+        LB, RB = hulls(fb)
+        d = fa.shape[1] - int(cd[t])
         hA, hB = len(LA), len(LB)
 
         def meet(ja, jb):
@@ -336,10 +390,9 @@ def test_interlock_flags_are_sound(orc, seed):
                    if 0 <= ja - dl < hB)
         if int(cd[t]) == 0:
             assert fl[t] == 0
-        if b_up:
-            assert fl[t] & 1, (t, k)
-        if a_up:
-            assert fl[t] & 2, (t, k)
+            continue
+        assert bool(fl[t] & 1) == b_up, (t, k)
+        assert bool(fl[t] & 2) == a_up, (t, k)
 
 
 def test_interlock_hand_cases(orc):

@@ -1,0 +1,368 @@
+"""Pins of the oracle's per-chart and per-row rules on hand-built cases.
+
+Each expected value here follows by hand from the rule as the paper states
+it, or from independent exact geometry (rational clipping with Fraction),
+never from the oracle's own code:
+
+* chart orientation (App. A, "Computing Chart Orientations"): vertical
+  reflection when the empty area above the chart exceeds the one below;
+  horizontal reflection when the left empty area exceeds the right one by
+  more than 10 % of the box area, else, when they are within 10 %, when the
+  bottom empty area left of the midline exceeds the one right of it;
+* the per-texel merge of the proxies (App. A, "Parallel Pushing
+  Algorithm"): TopEdge / BottomEdge are the tightest of the x-slices, the
+  y-slices and the OBB, each rounded outward on its own;
+* the per-proxy row bounds the compacting distance is measured on
+  (Sec. 4.1.2);
+* UpdateKneeLocation (Alg. 4) on hand-written frontlines;
+* the compaction choice of a row (Sec. 4.2 "Placing Rows": compaction only
+  when it fits more charts);
+* the sort order's width tie-break (height descending, then width).
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2602_07782_amd import synth
+from cases import small_input
+
+T = 16384
+Q = 256  # Q8 units per texel
+
+
+def poly(*pts):
+    return np.array(pts, np.int64)
+
+
+# ---------------------------------------------------------------------------
+# orientation
+# ---------------------------------------------------------------------------
+def test_flip_y_when_more_empty_area_above(orc):
+    # triangle with its apex on top: empty area above, none below
+    apex_up = poly((0, 4000), (3000, 4000), (1500, 0))
+    rec = orc.prep_chart(apex_up, 10)
+    assert (rec.rot, rec.flipy) == (0, 1)
+    # apex at the bottom: the empty area is already below
+    apex_down = poly((0, 0), (3000, 0), (1500, 4000))
+    rec = orc.prep_chart(apex_down, 10)
+    assert (rec.rot, rec.flipy) == (0, 0)
+    # a rectangle: equal (zero) areas, no reflection
+    rec = orc.prep_chart(poly((0, 0), (3000, 0), (3000, 4000), (0, 4000)), 10)
+    assert (rec.flipx, rec.flipy) == (0, 0)
+
+
+def _left_notch(c):
+    """W = 1000, H = 2000 (Q8).  The top-left block [0, c] x [0, 1001] is cut
+    away: with K = 2 the upper y-slice (v in [0, 1000]) spans u in [c, 1000],
+    the lower one (v in [1000, 2000]) u in [0, 1000].  Left empty area
+    c * (H / 2), right 0, box area W * H: 10 % of it is c = 200."""
+    return poly((c, 0), (1000, 0), (1000, 2000), (0, 2000), (0, 1001), (c, 1001))
+
+
+@pytest.mark.parametrize("c,flip", [(199, False), (200, False), (201, True), (450, True)])
+def test_flip_x_threshold_is_ten_percent_of_box_area(orc, c, flip):
+    rec = orc.prep_chart(_left_notch(c), 2)
+    assert rec.rot == 0 and rec.flipy == 0
+    # both x-slices reach the bottom, so the midline rule never reflects here
+    assert rec.flipx == int(flip)
+
+
+def _bottom_notch(u0, u1, depth=300):
+    """W = 1000, H = 2000: a notch [u0, u1] x [2000 - depth, 2000] cut from
+    the bottom edge.  Left and right empty areas are both zero."""
+    return poly((0, 0), (1000, 0), (1000, 2000), (u1, 2000), (u1, 2000 - depth),
+                (u0, 2000 - depth), (u0, 2000), (0, 2000))
+
+
+def test_midline_rule_reflects_toward_bottom_right(orc):
+    # K = 2: the left x-slice is u in [0, 500]; a notch over [0, 501] (from
+    # the corner) empties the bottom of the left slice only -> reflect
+    P = poly((0, 0), (1000, 0), (1000, 2000), (501, 2000), (501, 1700), (0, 1700))
+    rec = orc.prep_chart(P, 2)
+    assert (rec.rot, rec.flipy, rec.flipx) == (0, 0, 1)
+    # the mirror image already has its bottom hole on the right -> keep
+    P = poly((0, 0), (1000, 0), (1000, 1700), (499, 1700), (499, 2000), (0, 2000))
+    rec = orc.prep_chart(P, 2)
+    assert (rec.rot, rec.flipy, rec.flipx) == (0, 0, 0)
+
+
+def test_midline_rule_odd_k_middle_slice_cancels(orc):
+    # K = 5: x-slices of width 200 (closed ranges); a notch over the whole
+    # middle slice (u in [400, 600]) leaves every other slice reaching the
+    # bottom.  The
+    # middle slice is split evenly between the two halves, so bottom-left
+    # equals bottom-right and nothing is reflected.
+    rec = orc.prep_chart(_bottom_notch(399, 601), 5)
+    assert (rec.rot, rec.flipy, rec.flipx) == (0, 0, 0)
+    # the same notch over the second slice (u in [200, 400]) empties the
+    # bottom left of the midline only -> reflect
+    rec = orc.prep_chart(_bottom_notch(199, 401), 5)
+    assert (rec.rot, rec.flipy, rec.flipx) == (0, 0, 1)
+    # a notch over the second and the middle slice: bottom-left 300 + 150,
+    # bottom-right 150 -> reflect (a middle slice counted wholly on the
+    # right would make the two equal)
+    rec = orc.prep_chart(_bottom_notch(199, 601), 5)
+    assert (rec.rot, rec.flipy, rec.flipx) == (0, 0, 1)
+    # a two-step notch: depth 300 over the middle slice, 200 over the fourth
+    # (u in [600, 800]): bottom-left 150, bottom-right 150 + 200 -> keep (a
+    # middle slice counted wholly on the left would give 300 > 200)
+    P = poly((0, 0), (1000, 0), (1000, 2000), (801, 2000), (801, 1800), (601, 1800),
+             (601, 1700), (399, 1700), (399, 2000), (0, 2000))
+    rec = orc.prep_chart(P, 5)
+    assert (rec.rot, rec.flipy, rec.flipx) == (0, 0, 0)
+
+
+def test_l_u_and_diagonal_charts(orc):
+    W, H = 3000, 5000
+    # L with its top-right corner missing: reflect vertically only, which
+    # moves the hole to the bottom right
+    L_tr = poly((0, 0), (1200, 0), (1200, 2100), (W, 2100), (W, H), (0, H))
+    rec = orc.prep_chart(L_tr, 10)
+    assert (rec.rot, rec.flipy, rec.flipx) == (0, 1, 0)
+    # L with its top-left corner missing (a large block: left area far above
+    # 10 % of the box): reflect both ways -> hole at the bottom right
+    L_tl = poly((1800, 0), (W, 0), (W, H), (0, H), (0, 2100), (1800, 2100))
+    rec = orc.prep_chart(L_tl, 10)
+    assert (rec.rot, rec.flipy, rec.flipx) == (0, 1, 1)
+    # a cup (U opening upward, centred): reflect vertically; left and right
+    # are symmetric, so no horizontal reflection
+    U = poly((0, 0), (900, 0), (900, 3000), (2100, 3000), (2100, 0), (W, 0), (W, H), (0, H))
+    rec = orc.prep_chart(U, 10)
+    assert (rec.rot, rec.flipy, rec.flipx) == (0, 1, 0)
+    # a thin diagonal band from the top left to the bottom right: the empty
+    # areas above / below and left / right are equal, the bottom-left one is
+    # the larger -> reflect horizontally (the band then runs "/")
+    D = poly((0, 0), (400, 0), (W, H - 400), (W, H), (2600, H), (0, 400))
+    rec = orc.prep_chart(D, 10)
+    assert rec.rot == 0 and rec.flipy == 0 and rec.flipx == 1
+
+
+# ---------------------------------------------------------------------------
+# the per-texel merge and the per-proxy rows, against exact geometry
+# ---------------------------------------------------------------------------
+def final_frame(P, rec):
+    P = np.asarray(P, np.int64)
+    u = P[:, 0] - P[:, 0].min()
+    v = P[:, 1] - P[:, 1].min()
+    w0, h0 = int(u.max()), int(v.max())
+    if rec.rot:
+        u, v = h0 - v, u
+        W, H = h0, w0
+    else:
+        W, H = w0, h0
+    if rec.flipx:
+        u = W - u
+    if rec.flipy:
+        v = H - v
+    return u, v, W, H
+
+
+def clip_band(pts, axis, lo, hi):
+    """Sutherland-Hodgman clip of a closed polygon to lo <= coord <= hi."""
+    def clip(ps, keep, inter):
+        out = []
+        for i in range(len(ps)):
+            a, b = ps[i], ps[(i + 1) % len(ps)]
+            if keep(a):
+                out.append(a)
+            if keep(a) != keep(b):
+                out.append(inter(a, b))
+        return out
+
+    def at(c):
+        def f(a, b):
+            t = (c - a[axis]) / (b[axis] - a[axis])
+            return (a[0] + t * (b[0] - a[0]), a[1] + t * (b[1] - a[1]))
+        return f
+    ps = clip(pts, lambda P: P[axis] >= lo, at(lo))
+    return clip(ps, lambda P: P[axis] <= hi, at(hi)) if ps else ps
+
+
+def obb_corners(rec, k):
+    """Corners of the OBB {a <= Cu+Sv <= b, e <= -Su+Cv <= f}, scaled to
+    texels at k (exact rationals)."""
+    C, S = int(rec.C), int(rec.S)
+    N = C * C + S * S
+    out = []
+    for p, q in ((rec.a, rec.e), (rec.b, rec.e), (rec.b, rec.f), (rec.a, rec.f)):
+        u = Fraction(C * int(p) - S * int(q), N)
+        v = Fraction(S * int(p) + C * int(q), N)
+        out.append((u * k / T, v * k / T))
+    return out
+
+
+def independent_bounds(rec, k):
+    """Per column: (x-slice top, y-slice top, OBB top, and bottoms); per row:
+    (y-slice left, x-slice left, OBB left, rights) -- each rounded outward
+    on its own; None where a proxy gives nothing."""
+    K, W, H = rec.K, int(rec.W), int(rec.H)
+    w, h = -(-k * W // T), -(-k * H // T)
+    ylo = [Fraction(int(rec.ylo[j]) * k, T) for j in range(K)]
+    yhi = [Fraction(int(rec.yhi[j]) * k, T) for j in range(K)]
+    xlo = [Fraction(int(rec.xlo[j]) * k, T) for j in range(K)]
+    xhi = [Fraction(int(rec.xhi[j]) * k, T) for j in range(K)]
+    xs = [Fraction(j * W * k, T * K) for j in range(K + 1)]  # x-slice borders, texels
+    ys = [Fraction(j * H * k, T * K) for j in range(K + 1)]
+    corners = obb_corners(rec, k) if rec.obb else None
+    wr, hr = Fraction(k * W, T), Fraction(k * H, T)
+    cols, rows = [], []
+    for i in range(w):
+        # x-slices whose closed range meets the open column (i, i+1)
+        sx = [j for j in range(K) if xs[j] < i + 1 and xs[j + 1] > i]
+        # y-slices whose u-range reaches into the open column
+        sy = [j for j in range(K) if xlo[j] < i + 1 and xhi[j] > i]
+        tx = math.floor(min(ylo[j] for j in sx))
+        bx = math.ceil(max(yhi[j] for j in sx))
+        ty = math.floor(min(ys[j] for j in sy))
+        by = math.ceil(max(ys[j + 1] for j in sy))
+        to = bo = None
+        if corners:
+            cl = clip_band(corners, 0, Fraction(i), min(Fraction(i + 1), wr))
+            to = math.floor(min(p[1] for p in cl))
+            bo = math.ceil(max(p[1] for p in cl))
+        cols.append((tx, ty, to, bx, by, bo))
+    for j in range(h):
+        sy = [s for s in range(K) if ys[s] < j + 1 and ys[s + 1] > j]
+        sx = [s for s in range(K) if ylo[s] < j + 1 and yhi[s] > j]
+        ly = math.floor(min(xlo[s] for s in sy))
+        ry = math.ceil(max(xhi[s] for s in sy))
+        lx = math.floor(min(xs[s] for s in sx))
+        rx = math.ceil(max(xs[s + 1] for s in sx))
+        lo, ro = 0, w
+        if corners:
+            cl = clip_band(corners, 1, Fraction(j), min(Fraction(j + 1), hr))
+            lo = max(0, math.floor(min(p[0] for p in cl)))
+            ro = min(w, math.ceil(max(p[0] for p in cl)))
+        rows.append((ly, lx, lo, ry, rx, ro))
+    return cols, rows
+
+
+def test_merge_is_the_tightest_of_each_proxy(orc):
+    """TopEdge = max of the three proxies' own rounded tops (BottomEdge: min);
+    row bounds per proxy as the compaction uses them.  Over the sample every
+    proxy is strictly the tightest somewhere, the y-slices included."""
+    wins = {"x": 0, "y": 0, "obb": 0}
+    rng = np.random.default_rng(11)
+    for seed in range(12):
+        inp = small_input(12000 + seed, n=5)
+        for c in range(inp.n):
+            for K in (2, 5, 10):
+                rec = orc.prep_chart(inp.chart(c), K)
+                k = int(rng.integers(6, 65))
+                top, bot, left, right = orc.profiles(rec, k)
+                la, ra, lo, ro = orc.row_proxies(rec, k)
+                cols, rows = independent_bounds(rec, k)
+                for i, (tx, ty, to, bx, by, bo) in enumerate(cols):
+                    cand = [tx, ty] + ([to] if to is not None else [])
+                    assert top[i] == max(cand)
+                    assert bot[i] == min([bx, by] + ([bo] if bo is not None else []))
+                    m = max(cand)
+                    if [tx, ty, to].count(m) == 1:
+                        wins["x" if tx == m else ("y" if ty == m else "obb")] += 1
+                for j, (ly, lx, lo_, ry, rx, ro_) in enumerate(rows):
+                    assert la[j] == max(ly, lx) and ra[j] == min(ry, rx)
+                    assert lo[j] == lo_ and ro[j] == ro_
+                    assert left[j] == max(la[j], lo[j]) and right[j] == min(ra[j], ro[j])
+    assert min(wins.values()) > 0, wins
+
+
+def test_y_slices_alone_tighten_a_column(orc):
+    """A hand-built case: with K = 2, a bar u in [0, 1000] over the full
+    height with a base u in [1000, 1600] below v = 1001.  Both x-slices
+    (u in [0, 800] and [800, 1600]) reach v = 0, so they give top 0 in every
+    column; the upper y-slice (v in [0, 1000]) spans only u in [0, 1000],
+    so at k = 64 the columns right of u = 1000 / 256 texels (4, 5 and the
+    partial column 6) meet only the lower y-slice, whose top is v = 1000:
+    the y-slices alone give top = floor(1000 / 256) = 3 there."""
+    # rotated L: a tall bar on the left, a wide base at the bottom
+    P = poly((0, 0), (1000, 0), (1000, 1001), (1600, 1001), (1600, 2000), (0, 2000))
+    rec = orc.prep_chart(P, 2)
+    assert (rec.rot, rec.flipx, rec.flipy, rec.obb) == (0, 0, 0, 0)
+    top, bot, left, right = orc.profiles(rec, 64)
+    # the x-slices give 0 everywhere; the y-slices lift columns 4 to 6
+    assert list(top) == [0, 0, 0, 0, 3, 3, 3]
+
+
+# ---------------------------------------------------------------------------
+# UpdateKneeLocation (Alg. 4)
+# ---------------------------------------------------------------------------
+def test_knee_update_left_to_right(orc):
+    # knee span [2, 6): probe F[6] = 10; texels of the span with F >= 10:
+    # x = 3 (F = 10 exactly) -> new right edge 4
+    F = [0, 0, 5, 10, 7, 3, 10, 0]
+    assert orc.knee_update(F, 0, 2, 6) == (True, 2, 4)
+    # one less everywhere in the span: nothing reaches the probe height; the
+    # edge moves to the span's left end
+    F = [0, 0, 5, 9, 7, 3, 10, 0]
+    assert orc.knee_update(F, 0, 2, 6) == (True, 2, 2)
+    # probe outside the frontline ends the knee
+    assert orc.knee_update([1, 2, 3, 4], 0, 1, 4)[0] is False
+
+
+def test_knee_update_right_to_left(orc):
+    # span [3, 7): probe F[2] = 8; texels with F >= 8: x = 4 (equal) and 5
+    # -> the nearest, 4, becomes the left edge
+    F = [0, 0, 8, 1, 8, 9, 2, 0, 0]
+    assert orc.knee_update(F, 1, 3, 7) == (True, 4, 7)
+    F = [0, 0, 8, 1, 7, 9, 2, 0, 0]
+    assert orc.knee_update(F, 1, 3, 7) == (True, 5, 7)
+    F = [0, 0, 8, 1, 7, 7, 2, 0, 0]
+    assert orc.knee_update(F, 1, 3, 7) == (True, 7, 7)
+    # a knee at the atlas's left edge has no probe texel
+    assert orc.knee_update([5, 5, 5], 1, 0, 2)[0] is False
+
+
+# ---------------------------------------------------------------------------
+# compaction choice of a row (Sec. 4.2, "Placing Rows")
+# ---------------------------------------------------------------------------
+def _slanted_row(n, Wa, p):
+    """n identical parallelograms leaning left: 17 x 40 texels, slant 3
+    texels, so two of them side by side can slide together."""
+    a, W, H = 3 * Q, 17 * Q, 40 * Q
+    P = [np.array([[a + 20000 * i, 0], [W + 20000 * i, 0], [W - a + 20000 * i, H],
+                   [20000 * i, H]]) for i in range(n)]
+    xy, off = synth.pack_csr(P)
+    return synth.AtlasInput(xy, off, Wa, 4000, p, 2)
+
+
+@pytest.mark.parametrize("extra", [0, 1])
+def test_compaction_only_when_it_fits_more(orc, extra):
+    p, n = 3, 12
+    probe = _slanted_row(n, 100, p)
+    cd, _ = orc.pairs(probe, 64)
+    wd = 17 + p
+    c = int(cd[1])
+    assert c > 0 and np.all(cd[1:] == c)  # identical charts: one distance
+    m = 3
+    assert m * c < wd  # so that m compacted charts do not leave room for one more
+    if extra == 0:
+        Wd = m * wd                     # m fit either way
+    else:
+        Wd = m * (wd - c) + wd          # compaction fits m + 1, plain m
+        assert Wd // wd == m
+    inp = _slanted_row(n, Wd - p, p)
+    ok, xy, ori, rows = orc.feasible(inp, 64)
+    perm, _ = orc.order(inp)
+    assert np.array_equal(perm, np.arange(n))
+    first = [int(xy[t][0]) for t in range(m + extra)]
+    step = wd - c if extra else wd
+    # left to right on the flat frontline (the two directions tie)
+    assert first == [t * step for t in range(m + extra)]
+    assert int(xy[m + extra][1]) > 0  # the next chart starts the second row
+
+
+# ---------------------------------------------------------------------------
+# sort ties (height descending, then width descending, then input index)
+# ---------------------------------------------------------------------------
+def test_sort_breaks_height_ties_by_width(orc):
+    widths = [3, 7, 5, 7, 2]
+    heights = [10, 10, 10, 10, 12]
+    P = [np.array([[1000 * i, 0], [1000 * i + w * Q, 0], [1000 * i + w * Q, h * Q],
+                   [1000 * i, h * Q]]) for i, (w, h) in enumerate(zip(widths, heights))]
+    xy, off = synth.pack_csr(P)
+    perm, _ = orc.order(synth.AtlasInput(xy, off, 64, 64, 0, 2))
+    assert list(perm) == [4, 1, 3, 2, 0]
