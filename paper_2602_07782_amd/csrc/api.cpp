@@ -111,17 +111,18 @@ struct Layout {
 };
 
 // Profile arena words for B scale slots over N charts in `count` atlases of
-// grown width up to Wdmax.  A chart of grown extents w x h takes w + h words
-// at a scale; per slot and chart `per` words are set aside (the single pack
-// spreads its 64 slots over scales 1..k_top, so it needs fewer on average:
-// about 5,400 words per chart over all 64 scales for the 2,000-chart 2048^2
-// workload, 3,200 for 20,000 charts in 4096^2; a batch of mixed atlases about
-// 700 over its top 8 scales), plus four atlas widths per (atlas, slot).
-// Segments are placed in descending-scale order and those that do not fit
-// are evaluated directly, so the figure only trades memory for speed.
+// grown width up to Wdmax.  A chart of grown extents w x h takes w + 2h words
+// at a scale (its columns, then its rows once per proxy); per slot and chart
+// `per` words are set aside (the single pack spreads its 64 slots over scales
+// 1..k_top, so it needs fewer on average: about 8,400 words per chart over
+// all 64 scales for the 2,000-chart 2048^2 workload; a batch of mixed
+// atlases about 1,100 over its top 8 scales), plus four atlas widths per
+// (atlas, slot).  Segments are placed in descending-scale order and those
+// that do not fit are evaluated directly, so the figure only trades memory
+// for speed.
 int64_t arena_words(const Params& P) {
   if (g_profile_cap >= 0) return g_profile_cap;
-  const int64_t per = P.B >= 64 ? 90 : 112;
+  const int64_t per = P.B >= 64 ? 150 : 180;
   int64_t v = (int64_t)P.B * P.N * per + (int64_t)P.B * P.count * 4 * P.Wdmax;
   const int64_t lim = 0x7fffffffLL;  // word indices are int32
   return v > lim ? lim : v;

@@ -470,14 +470,16 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     for (int q = wv - npush; wv >= npush && q < lrn; q += nlr) {
       const int A = s_lr[q][0], C = s_lr[q][1];
       const int wdA = Xoff[A + 1] - Xoff[A];
-      PairSweep sw;
+      const int dd = Xon[C] - Xon[A];
+      int f;
       if (prof) {
-        sw = pair_sweep_rows(w.arena + sbase + prowv[rs + A], hdv[rs + A],
-                             w.arena + sbase + prowv[rs + C], hdv[rs + C], wdA);
+        f = pair_flags_at(pair_rows_meet(w.arena + sbase + prowv[rs + A], hdv[rs + A],
+                                         w.arena + sbase + prowv[rs + C], hdv[rs + C], wdA),
+                          wdA, dd);
       } else {
-        sw = pair_sweep(KV(rs + A), ch[rs + A], KV(rs + C), ch[rs + C], K, k, p);
+        f = pair_flags_at(pair_records_sweep<2>(KV(rs + A), ch[rs + A], KV(rs + C), ch[rs + C], K, k, p),
+                          wdA, dd);
       }
-      const int f = pair_flags_at(sw, wdA, Xon[C] - Xon[A]);
       if (lane == 0) s_lr[q][2] = f;
     }
     __syncthreads();

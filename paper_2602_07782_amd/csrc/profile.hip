@@ -12,9 +12,9 @@
 //              grown widths and heights (offsets within the segment)
 //   k_alloc    one workgroup: segment bases in descending-scale priority
 //   k_profile  per (scale slot, 16 charts): every grown column (top,
-//              bottom) and every grown row (left, right), in chunks spread
-//              over the wavefronts, then the neighbour pairs' compacting
-//              distances and interlock flags
+//              bottom) and every grown row (left, right) of each proxy, in
+//              chunks spread over the wavefronts, then the neighbour pairs'
+//              compacting distances and interlock flags
 //
 // Within a (atlas, slot) segment the charts' columns are stored back to back
 // in sorted order, so the candidates of a row are one contiguous range and a
@@ -137,11 +137,12 @@ __device__ inline int32_t sweep_side(const SweepSide& s, int32_t t, int32_t n) {
   return t == n - 1 ? h0.w : ((useA || useB) ? q : h0.z);
 }
 
-// Top / bottom of column u and left / right of row u, as column_row_bounds
-// computes them, from the sweep record (mode SWEEP_AABB or SWEEP_OBB).
+// Top / bottom of column u and the per-proxy left / right of row u, as
+// column_row_bounds computes them, from the sweep record (mode SWEEP_AABB or
+// SWEEP_OBB).
 template <int KT>
 __device__ inline void sweep_bounds(const SweepRec& R, int32_t u, int32_t& top, int32_t& bot,
-                                    int32_t& left, int32_t& right) {
+                                    int32_t& la, int32_t& ra, int32_t& lo, int32_t& ro) {
   const u16x2 ij = {(unsigned short)u, (unsigned short)u};
   const uint32_t ones = 0xffffffffu;
   // (top, left) minima and complemented (bottom, right) maxima of the x- and
@@ -172,16 +173,20 @@ __device__ inline void sweep_bounds(const SweepRec& R, int32_t u, int32_t& top, 
   int32_t l = tl.y == 0xffff ? BIG : (int32_t)tl.y - 0x8000;
   int32_t b = br.x == 0 ? -BIG : (int32_t)br.x - 0x8000;
   int32_t r = br.y == 0 ? -BIG : (int32_t)br.y - 0x8000;
+  // the OBB's rows kept inside the chart's texel box [0, w]
+  int32_t ol = 0, orr = R.w;
   if (R.mode == SWEEP_OBB) {
     t = max(t, sweep_side<false>(R.sd[0], u, R.w));
     b = min(b, sweep_side<true>(R.sd[1], u, R.w));
-    l = max(l, sweep_side<false>(R.sd[2], u, R.h));
-    r = min(r, sweep_side<true>(R.sd[3], u, R.h));
+    ol = max(ol, sweep_side<false>(R.sd[2], u, R.h));
+    orr = min(orr, sweep_side<true>(R.sd[3], u, R.h));
   }
   top = t;
   bot = b;
-  left = l;
-  right = r;
+  la = l;
+  ra = r;
+  lo = ol;
+  ro = orr;
 }
 
 // Segment placement in priority order: slot-major (every atlas's largest
@@ -231,6 +236,7 @@ __global__ __launch_bounds__(ALLOC_NT) void k_alloc(Params P, Work w, int round)
 
 // Offsets of every chart's grown columns and rows within its (atlas, slot)
 // segment, and the segment's size in words (0 when the slot does not run).
+// A chart's rows take two words each: its local-AABB rows, then its OBB rows.
 template <int LAY_NT>
 __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) {
   __shared__ int64_t s_tot[LAY_NT / WAVE][2];
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) 
   int64_t sw = 0, sh = 0;
   for (int t = t0; t < t1; ++t) {
     sw += w.wdv[slot + t];
-    sh += w.hdv[slot + t];
+    sh += 2 * w.hdv[slot + t];
   }
   // block-wide exclusive scans of both sums
   int64_t iw = sw, ih = sh;
@@ -276,7 +282,7 @@ __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) 
     w.pcol[slot + t] = (int32_t)min<int64_t>(col, 0x7fffffff);
     w.prow[slot + t] = (int32_t)min<int64_t>(row, 0x7fffffff);
     col += w.wdv[slot + t];
-    row += w.hdv[slot + t];
+    row += 2 * w.hdv[slot + t];
   }
   }
   // Single atlas: the last of its workgroups to finish places the segments
@@ -323,30 +329,36 @@ __device__ void profile_charts(const Work& w, const ChartCache* cache, const Swe
     const SweepRec& rec = sw[j];
     const int wt = rec.w, ht = rec.h;
     const int u = m * step - p + gl;  // undilated column and row of this lane
-    int32_t tp = BIG, bt = -BIG, l = BIG, r = -BIG;
+    int32_t tp = BIG, bt = -BIG, la = BIG, ra = -BIG, lo = BIG, ro = -BIG;
     {
-      int32_t t1, b1, l1, r1;
+      int32_t t1, b1, la1, ra1, lo1, ro1;
       if (!GEN || rec.mode != SWEEP_GENERAL)
-        sweep_bounds<KT>(rec, u, t1, b1, l1, r1);
+        sweep_bounds<KT>(rec, u, t1, b1, la1, ra1, lo1, ro1);
       else
-        column_row_bounds<KT>(kview(cache[j].kc, KT), cache[j].ch, s_k[j], u, u, t1, b1, l1, r1);
+        column_row_bounds<KT>(kview(cache[j].kc, KT), cache[j].ch, s_k[j], u, u, t1, b1, la1,
+                              ra1, lo1, ro1);
       if (u >= 0 && u < wt) { tp = t1; bt = b1; }
-      if (u >= 0 && u < ht) { l = l1; r = r1; }
+      if (u >= 0 && u < ht) { la = la1; ra = ra1; lo = lo1; ro = ro1; }
     }
     // gutter growth: after step q the lane holds the extremes over entries
     // [u - q, u] (the window of the lane before it, one entry longer); the
     // fill is each extreme's identity, so the move and the min / max fold
-    // into one instruction
-    int32_t T = tp, Bo = bt, L = l, R = r;
+    // into one instruction.  Each proxy's rows grow on their own.
+    int32_t T = tp, Bo = bt, LA = la, RA = ra, LO = lo, RO = ro;
     for (int q = 0; q < p; ++q) {
       T = min(T, wave_shr1(T, INT32_MAX));
       Bo = max(Bo, wave_shr1(Bo, INT32_MIN));
-      L = min(L, wave_shr1(L, INT32_MAX));
-      R = max(R, wave_shr1(R, INT32_MIN));
+      LA = min(LA, wave_shr1(LA, INT32_MAX));
+      RA = max(RA, wave_shr1(RA, INT32_MIN));
+      LO = min(LO, wave_shr1(LO, INT32_MAX));
+      RO = max(RO, wave_shr1(RO, INT32_MIN));
     }
     if (live && gl >= p) {
       if (s_cols[j] && u < wt + p) w.arena[s_pc[j] + u] = pack16(T, Bo + p);
-      if (u < ht + p) w.arena[s_pr[j] + u] = pack16(L, R + p);
+      if (u < ht + p) {
+        w.arena[s_pr[j] + u] = pack16(LA, RA + p);
+        w.arena[s_pr[j] + ht + p + u] = pack16(LO, RO + p);
+      }
     }
   }
 }
@@ -504,11 +516,11 @@ __device__ bool profile_block(const Params& P, const Work& w, int bx, int s) {
       ra = w.arena + s_pr[jg - 1];
       rb = w.arena + s_pr[jg];
     }
-    const PairSweep r = pair_sweep_rows16(ra, hdA, rb, hdB, wdA);
+    const PairResult r = pair_rows_both<true>(ra, hdA, rb, hdB, wdA);
     if ((lane & 15) == 0 && (s_run[jg] & 1)) {
       const size_t sc = (size_t)s * P.N + (cb - 1 + jg);
       w.cd[sc] = pg ? r.cd : 0;
-      w.fl[sc] = pg ? (uint8_t)pair_flags_at(r, wdA, wdA - r.cd) : 0;
+      w.fl[sc] = pg ? (uint8_t)r.flags : 0;
     }
   } else if constexpr (GEN) {
     for (int j = 1 + 4 * wv; j < 5 + 4 * wv; ++j) {
@@ -520,17 +532,17 @@ __device__ bool profile_block(const Params& P, const Work& w, int bx, int s) {
         continue;
       }
       const KView A = kview(cache[j - 1].kc, K), B = kview(cache[j].kc, K);
-      const int wdA = khead_load(A.hd).w + p;
-      PairSweep r;
+      PairResult r;
       if (s_pr[j] >= 0) {
-        r = pair_sweep_rows(w.arena + s_pr[j - 1], khead_load(A.hd).h + p, w.arena + s_pr[j],
-                            khead_load(B.hd).h + p, wdA);
+        r = pair_rows_both<false>(w.arena + s_pr[j - 1], khead_load(A.hd).h + p,
+                                  w.arena + s_pr[j], khead_load(B.hd).h + p,
+                                  khead_load(A.hd).w + p);
       } else {
-        r = pair_sweep(A, cache[j - 1].ch, B, cache[j].ch, K, s_k[j], p);
+        r = pair_records_both(A, cache[j - 1].ch, B, cache[j].ch, K, s_k[j], p);
       }
       if (lane == 0) {
         w.cd[sc] = r.cd;
-        w.fl[sc] = (uint8_t)pair_flags_at(r, wdA, wdA - r.cd);
+        w.fl[sc] = (uint8_t)r.flags;
       }
     }
   }

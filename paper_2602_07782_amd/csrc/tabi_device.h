@@ -316,11 +316,15 @@ __device__ inline int32_t side_eval(const KSide& s, int32_t t, int32_t n, const 
 
 // Column i and row j of the same chart at once (the profile sweep needs
 // both): every slice rectangle is loaded once and tested against both, and
-// the four OBB side values are independent of each other.
+// the four OBB side values are independent of each other.  The column's
+// top / bottom are the tightest of both proxies; the row's bounds are given
+// per proxy: la, ra from the local AABBs, lo, ro from the OBB kept inside
+// the chart's texel box [0, w] (that box when the chart has no OBB), so that
+// the compacting distance can be measured on each proxy (Sec. 4.1.2).
 template <int KT>
 __device__ inline void column_row_bounds(const KView& kv, const Chart& ch, int k, int i, int j,
-                                         int32_t& top, int32_t& bot, int32_t& left,
-                                         int32_t& right) {
+                                         int32_t& top, int32_t& bot, int32_t& la, int32_t& ra,
+                                         int32_t& lo, int32_t& ro) {
   constexpr int K = KT;
   int32_t tx = BIG, bx = -BIG, ty = BIG, by = -BIG;
   int32_t ly = BIG, ry = -BIG, lx = BIG, rx = -BIG;
@@ -340,14 +344,17 @@ __device__ inline void column_row_bounds(const KView& kv, const Chart& ch, int k
     ly = rj2 ? min(ly, c0) : ly;
     ry = rj2 ? max(ry, c1) : ry;
   }
-  int32_t t = max(tx, ty), b = min(bx, by), l = max(ly, lx), rr = min(ry, rx);
+  int32_t t = max(tx, ty), b = min(bx, by);
+  la = max(ly, lx);
+  ra = min(ry, rx);
   const KHead hd = khead_load(kv.hd);
+  int32_t l = 0, rr = hd.w;
   if (hd.obb) {
     const int64_t C = kDirC[ch.m], S = kDirS[ch.m];
     const int64_t kk = k;
     const KSide s0 = kside_load(kv.sd + 0), s1 = kside_load(kv.sd + 1);
     const KSide s2 = kside_load(kv.sd + 2), s3 = kside_load(kv.sd + 3);
-    // the same lines as column_bounds / row_bounds
+    // the same lines as column_bounds / row_proxies
     const SideLines L0 = side_lines<false>(kk * ch.a, -QS * C, QS * S, kk * ch.e, QS * S, QS * C);
     const SideLines L1 = side_lines<true>(kk * ch.f, QS * S, QS * C, kk * ch.b, -QS * C, QS * S);
     const SideLines L2 = side_lines<false>(kk * ch.a, -QS * S, QS * C, -kk * ch.f, QS * C, QS * S);
@@ -366,30 +373,29 @@ __device__ inline void column_row_bounds(const KView& kv, const Chart& ch, int k
   }
   top = t;
   bot = b;
-  left = l;
-  right = rr;
+  lo = l;
+  ro = rr;
 }
 
-// Undilated left / right bound of row j.
+// Undilated left / right bounds of row j under each proxy separately, as
+// column_row_bounds gives them.
 template <int KT = 0>
-__device__ inline void row_bounds(const KView& kv, const Chart& ch, int K, int k, int j,
-                                  int32_t& left, int32_t& right) {
-  int32_t l, rr;
-  row_rects<KT>(kv, K, j, l, rr);
+__device__ inline void row_proxies(const KView& kv, const Chart& ch, int K, int k, int j,
+                                   int32_t& la, int32_t& ra, int32_t& lo, int32_t& ro) {
+  row_rects<KT>(kv, K, j, la, ra);
   const KHead hd = khead_load(kv.hd);
+  int32_t l = 0, rr = hd.w;
   if (hd.obb) {
     const int64_t C = kDirC[ch.m], S = kDirS[ch.m];
     const int64_t kk = k;
     const KSide s2 = kside_load(kv.sd + 2), s3 = kside_load(kv.sd + 3);
     // left = max(A: (k a - 16384 S y)/(16384 C), B: (16384 C y - k f)/(16384 S))
-    int32_t lo = side_value<false>(s2, j, hd.h, kk * ch.a, -QS * S, QS * C, -kk * ch.f, QS * C, QS * S);
+    l = max(l, side_value<false>(s2, j, hd.h, kk * ch.a, -QS * S, QS * C, -kk * ch.f, QS * C, QS * S));
     // right = min(A: (16384 C y - k e)/(16384 S), B: (k b - 16384 S y)/(16384 C))
-    int32_t ro = side_value<true>(s3, j, hd.h, -kk * ch.e, QS * C, QS * S, kk * ch.b, -QS * S, QS * C);
-    l = max(l, lo);
-    rr = min(rr, ro);
+    rr = min(rr, side_value<true>(s3, j, hd.h, -kk * ch.e, QS * C, QS * S, kk * ch.b, -QS * S, QS * C));
   }
-  left = l;
-  right = rr;
+  lo = l;
+  ro = rr;
 }
 
 // Gutter growth: a footprint grows by [0,p]^2 toward +x, +y, so a grown
@@ -408,21 +414,6 @@ __device__ inline void column_bounds_grown(const KView& kv, const Chart& ch, int
   top = t;
   bot = b + p;
 }
-__device__ inline void row_bounds_grown(const KView& kv, const Chart& ch, int K, int k, int p, int j,
-                                        int32_t& left, int32_t& right) {
-  const int h = kv.hd->h;
-  int lo = max(0, j - p), hi = min(h - 1, j);
-  int32_t l = BIG, r = -BIG;
-  for (int c = lo; c <= hi; ++c) {
-    int32_t ll, rr;
-    row_bounds(kv, ch, K, k, c, ll, rr);
-    l = min(l, ll);
-    r = max(r, rr);
-  }
-  left = l;
-  right = r + p;
-}
-
 // ---------------------------------------------------------------------------
 // stored per-texel profiles: two int16 bounds in one 32-bit word
 // ---------------------------------------------------------------------------

@@ -72,7 +72,8 @@ struct Work {
   int32_t* live;        // [MAX_ROUNDS + 1] live[r] != 0: some atlas still searches in round
                         // r >= 1 (set by round r - 1's selection, cleared at the start)
   uint32_t* arena;      // profiles: per grown column (top, bottom), per grown row
-                        // (left, right), int16 pairs (pack16)
+                        // (left, right) of the local AABBs, then of the OBB, int16
+                        // pairs (pack16)
 };
 
 // scale of slot s of the current round for an atlas (< 1: the slot does not
