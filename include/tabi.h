@@ -50,7 +50,9 @@ enum {
                        padding > TABI_MAX_PADDING,
                        quality not in {0,1,2}, count < 0, work space too small */
   TABI_ENOMEM = -2, /* the device memory pool could not supply the work space */
-  TABI_EHIP = -3    /* a HIP runtime call failed (launch, memory); see tabi_last_hip_error */
+  TABI_EHIP = -3,   /* a HIP runtime call failed (launch, memory); see tabi_last_hip_error */
+  TABI_ETOOBIG = -4 /* tabi_pack_noalloc: the input needs more work space than its
+                       static array of TABI_NOALLOC_BYTES holds */
 };
 
 #define TABI_MAX_CHARTS 262144 /* charts per atlas */
@@ -87,6 +89,27 @@ typedef struct {
 int tabi_pack(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
               int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
               float* out_scale, tabi_stream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): tabi_pack
+ * with the same arguments, outputs and device-detected conditions, whose work
+ * space is a static device array of TABI_NOALLOC_BYTES held by every GPU the
+ * library runs on until the process ends.  It calls no allocation routine
+ * and no memset (its kernels initialise what they read).  The per-scale
+ * profile arena takes what the fixed arrays leave of the array; segments
+ * beyond it are evaluated from the proxy records, so results equal
+ * tabi_pack's bit for bit (larger inputs run slower, not differently).
+ * About 2,000 charts of a 2048^2 atlas at quality 2 fit with their profiles
+ * stored, about 7,000 charts at all.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on the
+ * same GPU (different streams, or host threads) race and give wrong results;
+ * order them on one stream.
+ * Errors: as tabi_pack, and TABI_ETOOBIG when the input's fixed work space
+ * (per-chart records and per-(scale, chart) set-up) exceeds the array. */
+#define TABI_NOALLOC_BYTES (128ll << 20)
+int tabi_pack_noalloc(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+                      int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
+                      float* out_scale, tabi_stream_t stream);
 
 /* Pack `count` independent atlases in one set of launches (batched path).
  * Charts of all atlases form one CSR (xy, vert_offsets over all charts, device

@@ -14,9 +14,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtabi_hip.so")
 
-TABI_OK, TABI_EINVAL, TABI_ENOMEM, TABI_EHIP = 0, -1, -2, -3
+TABI_OK, TABI_EINVAL, TABI_ENOMEM, TABI_EHIP, TABI_ETOOBIG = 0, -1, -2, -3, -4
 ERRORS = {TABI_EINVAL: "invalid argument", TABI_ENOMEM: "out of device memory",
-          TABI_EHIP: "HIP runtime error"}
+          TABI_EHIP: "HIP runtime error",
+          TABI_ETOOBIG: "input exceeds the static work space of tabi_pack_noalloc"}
 
 
 class TabiError(RuntimeError):
@@ -31,7 +32,7 @@ class Charts(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ["tabi_pack", "tabi_pack_many", "tabi_pack_many_ws", "tabi_pack_many_workspace_bytes",
+EXPORTS = ["tabi_pack", "tabi_pack_noalloc", "tabi_pack_many", "tabi_pack_many_ws", "tabi_pack_many_workspace_bytes",
            "tabi_record_bytes", "tabi_prep_records", "tabi_splice_records",
            "tabi_pack_many_records", "tabi_debug_order", "tabi_debug_pairs",
            "tabi_debug_feasible", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
@@ -52,6 +53,8 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, i32 = ctypes.c_void_p, ctypes.c_int32
         L.tabi_pack.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, i32, vp, vp, vp, vp]
+        L.tabi_pack_noalloc.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, i32, vp, vp,
+                                        vp, vp]
         L.tabi_pack_many.argtypes = [vp, vp, vp, i32, vp, i32, i32, i32, i32, i32, vp, vp, vp, vp]
         L.tabi_pack_many_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32]
         L.tabi_pack_many_workspace_bytes.restype = ctypes.c_int64
@@ -136,6 +139,16 @@ def pack(xy, offsets, atlas_w, atlas_h, padding, quality, stream=None, device="c
     _check(lib().tabi_pack(ctypes.byref(ch), n, int(atlas_w), int(atlas_h), int(padding),
                            int(quality), _ptr(out_xy), _ptr(out_or), _ptr(out_sc), _stream(stream)))
     return out_xy, out_or, out_sc
+
+
+def pack_noalloc_into(xy, offsets, n, atlas_w, atlas_h, padding, quality, out_xy, out_orient,
+                      out_scale, stream=None):
+    """tabi_pack_noalloc on caller tensors (device int32 xy / offsets, outputs
+    int32[n,2], uint8[n], float32[1]): the library allocates nothing."""
+    ch = Charts(_ptr(xy).value, _ptr(offsets).value, int(xy.numel() // 2))
+    _check(lib().tabi_pack_noalloc(ctypes.byref(ch), int(n), int(atlas_w), int(atlas_h),
+                                   int(padding), int(quality), _ptr(out_xy), _ptr(out_orient),
+                                   _ptr(out_scale), _stream(stream)))
 
 
 def pack_into(xy, offsets, n, atlas_w, atlas_h, padding, quality, out_xy, out_orient, out_scale,

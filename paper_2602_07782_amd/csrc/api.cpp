@@ -458,6 +458,39 @@ int single_front(Job& j, const tabi_charts* ch, int32_t aw, int32_t ah, hipStrea
   return e == hipSuccess ? TABI_OK : hip_fail(e);
 }
 
+// Work space of tabi_pack_noalloc: a static device array, one copy per GPU
+// the library runs on, held until the process ends.  Host code never uses
+// the array's name as an address: its device address is looked up once per
+// device (scratch_ptr) and that pointer is what the kernels receive.
+constexpr size_t kScratchBytes = (size_t)TABI_NOALLOC_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+// Device address of `scratch` on the current device; nullptr (and the HIP
+// error recorded) if the lookup fails.
+void* scratch_ptr() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= 64) {
+    if (e != hipSuccess) hip_fail(e);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -481,6 +514,36 @@ int tabi_pack(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atl
   }
   free_job(j, st);
   return rc;
+}
+
+int tabi_pack_noalloc(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+                      int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
+                      float* out_scale, tabi_stream_t stream) {
+  if (check_common(n, padding, quality) || bad_atlas(atlas_w, atlas_h, padding) || !charts ||
+      !out_scale || (n > 0 && (!charts->xy || !charts->offsets || !out_xy || !out_orient)))
+    return TABI_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // the same plan as tabi_pack; the profile arena takes what the fixed
+  // arrays leave of the static work space (segments beyond it are evaluated
+  // from the proxy records, with the same results)
+  Params P = make_params(1, n, quality, padding, 64, 0, n > 0 ? n : 1, atlas_w + padding);
+  const int64_t want = P.arena_cap;
+  P.arena_cap = 0;
+  const size_t fixed = layout(P).total;
+  if (fixed > kScratchBytes) return TABI_ETOOBIG;
+  P.arena_cap = std::min<int64_t>(want, (int64_t)((kScratchBytes - fixed) / 4));
+  if (layout(P).total > kScratchBytes) P.arena_cap = 0;  // alignment slack
+  void* ws = scratch_ptr();
+  if (!ws) return TABI_EHIP;
+  Job j;
+  int rc = make_job(j, P, st, ws, kScratchBytes);
+  if (!rc) rc = single_front(j, charts, atlas_w, atlas_h, st);
+  if (!rc) {
+    const int all[1] = {64};
+    hipError_t e = run_search(j, all, 1, out_xy, out_orient, out_scale, st);
+    if (e != hipSuccess) rc = hip_fail(e);
+  }
+  return rc;  // nothing to release: the work space is the static array
 }
 
 int tabi_pack_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
@@ -714,6 +777,8 @@ const char* tabi_strerror(int code) {
     case TABI_EINVAL: return "invalid argument";
     case TABI_ENOMEM: return "out of device memory";
     case TABI_EHIP: return "HIP runtime error";
+    case TABI_ETOOBIG:
+      return "input needs more work space than tabi_pack_noalloc's static array holds";
     default: return "unknown error";
   }
 }
