@@ -49,7 +49,7 @@ def cpu_baseline(inp, seconds):
     return dt * 1000.0 / reps, reps, out
 
 
-def batched_leg(tabi, torch, count=256, reps=3):
+def batched_leg(tabi, torch, count=256, reps=3, cpu_seconds=15.0):
     """The batch workload: `count` atlases (sides 512/1024/2048, 50-5,000
     charts each, 2,000-chart recipe) in one tabi_pack_many, captured in a HIP
     graph and replayed, against the same atlases through tabi_pack back to
@@ -112,7 +112,10 @@ def batched_leg(tabi, torch, count=256, reps=3):
             bool(torch.equal(batch.out_orient[c0:c0 + n], oor)) and \
             float(bsc[ai]) == float(osc.cpu().numpy()[0])
         c0 += n
-    return {"atlases": count, "charts": int(sum(i.n for i in inputs)),
+    alg = sum(atlas_algorithmic_bytes(inp, int(round(float(bsc[a]) * 64)))
+              for a, inp in enumerate(inputs))
+    gbs = alg / batched_s / 1e9
+    out = {"atlases": count, "charts": int(sum(i.n for i in inputs)),
             "atlases_per_s_batched": round(count / batched_s, 2),
             "atlases_per_s_plain": round(count / plain_s, 2),
             "speedup_vs_plain": round(plain_s / batched_s, 2),
@@ -124,11 +127,148 @@ def batched_leg(tabi, torch, count=256, reps=3):
                                 "pack_threads": tuned["shape"][3],
                                 "pack_lds_cap": tuned["shape"][4],
                                 "candidate_ms": tuned["ms"]},
+            "hbm": {"algorithmic_bytes_per_batch": alg, "achieved_GBps": round(gbs, 2),
+                    "peak_GBps": PEAK_HBM_GBS, "frac": round(gbs / PEAK_HBM_GBS, 6)},
             "bitexact_vs_plain": bool(same)}
+    if cpu_seconds > 0:
+        out["cpu_baseline"] = batched_cpu_baseline(inputs, cpu_seconds)
+    return out
+
+
+def host_cores():
+    """Host cores this process may run on, capped at the 16 a one-GPU share
+    of the box holds."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def batched_cpu_baseline(inputs, seconds):
+    """The oracle over the batch's atlases on all host cores (one atlas per
+    task, a thread per core; the oracle's C code runs outside the Python
+    lock), for about `seconds` of wall time: atlases per second."""
+    import concurrent.futures as cf
+    import oracle
+    oracle.build()
+    cores = host_cores()
+    t0 = time.perf_counter()
+    done = 0
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        it = iter(inputs)
+        running = set()
+        for _ in range(cores):
+            inp = next(it, None)
+            if inp is not None:
+                running.add(ex.submit(oracle.pack, inp))
+        while running:
+            fin, running = cf.wait(running, return_when=cf.FIRST_COMPLETED)
+            done += len(fin)
+            if time.perf_counter() - t0 < seconds:
+                for _ in fin:
+                    inp = next(it, None)
+                    if inp is not None:
+                        running.add(ex.submit(oracle.pack, inp))
+    wall = time.perf_counter() - t0
+    return {"value": round(done / wall, 3), "unit": "atlases/s", "cores": cores,
+            "kind": "oracle", "sample": f"the first {done} atlases of the same batch, "
+                                        f"one per thread, {wall:.1f} s wall"}
+
+
+def config_legs(tabi, torch, cpu):
+    """The other single-pack configurations: the 64-chart 512^2 workload,
+    the 2,000-chart 2048^2 workload at low quality, and the 20,000-chart
+    4096^2 workload; p50 / p99 of tabi_pack (HIP events per call) and the
+    oracle on one host core (one pack each)."""
+    import numpy as np
+    from paper_2602_07782_amd import synth
+    import oracle
+    legs = {}
+    for name, q, steps in (("stars64", 2, 100), ("mixed2k", 0, 100), ("lightmap20k", 2, 30)):
+        base = synth.make_input(name, 0)
+        inp = synth.AtlasInput(base.xy, base.offsets, base.atlas_w, base.atlas_h, base.padding, q)
+        dev = torch.device("cuda:0")
+        xy = torch.from_numpy(np.ascontiguousarray(inp.xy, np.int32)).to(dev)
+        off = torch.from_numpy(np.ascontiguousarray(inp.offsets, np.int32)).to(dev)
+        oxy = torch.empty((inp.n, 2), dtype=torch.int32, device=dev)
+        oor = torch.empty(inp.n, dtype=torch.uint8, device=dev)
+        osc = torch.empty(1, dtype=torch.float32, device=dev)
+        st = torch.cuda.current_stream()
+        for _ in range(5):
+            tabi.pack_into(xy, off, inp.n, inp.atlas_w, inp.atlas_h, inp.padding, q, oxy, oor,
+                           osc, stream=st)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(st)
+            tabi.pack_into(xy, off, inp.n, inp.atlas_w, inp.atlas_h, inp.padding, q, oxy, oor,
+                           osc, stream=st)
+            b.record(st)
+        torch.cuda.synchronize()
+        per = [a.elapsed_time(b) for a, b in ev]
+        gsc = float(osc.cpu().numpy()[0])
+        leg = {"charts": inp.n, "atlas": [inp.atlas_w, inp.atlas_h], "padding": inp.padding,
+               "quality": q, "p50_ms": round(percentile(per, 50), 4),
+               "p99_ms": round(percentile(per, 99), 4), "scale": gsc}
+        if cpu:
+            t0 = time.perf_counter()
+            e_xy, e_or, e_sc, _ = oracle.pack(inp)
+            leg["cpu_baseline"] = {"value": round((time.perf_counter() - t0) * 1000.0, 2),
+                                   "unit": "ms per atlas pack", "cores": 1, "kind": "oracle",
+                                   "sample": "one pack of the same input"}
+            leg["bitexact_vs_oracle"] = bool(e_sc == gsc and
+                                             np.array_equal(e_xy, oxy.cpu().numpy()) and
+                                             np.array_equal(e_or, oor.cpu().numpy()))
+        legs[f"{name}_q{q}"] = leg
+    return legs
+
+
+def atlas_algorithmic_bytes(inp, kstar):
+    """Bytes the method must move for one atlas pack: vertices and offsets
+    read (8 V + 4 (n + 1)), per-chart proxies written and read
+    (n (16 K + 80)), for every evaluated scale the grown profiles written
+    once and read once (8 per grown column and row: two int16 bounds each
+    way), and the outputs (9 n + 4).  The evaluated scales are those from
+    the largest candidate down to the chosen one (all candidates when none
+    fits).  Chart extents come from the input polygons (host numpy)."""
+    import numpy as np
+    n = inp.n
+    if n == 0:
+        return 4
+    K = {0: 2, 1: 5, 2: 10}[inp.quality]
+    xy = np.asarray(inp.xy, np.int64).reshape(-1)
+    xs, ys = xy[0::2], xy[1::2]
+    off = np.asarray(inp.offsets, np.int64)
+    starts = off[:-1]
+    ex = np.maximum.reduceat(xs, starts) - np.minimum.reduceat(xs, starts)
+    ey = np.maximum.reduceat(ys, starts) - np.minimum.reduceat(ys, starts)
+    W, H = np.minimum(ex, ey), np.maximum(ex, ey)
+    x1 = np.roll(xs, -1)
+    y1 = np.roll(ys, -1)
+    last = off[1:] - 1
+    x1[last], y1[last] = xs[starts], ys[starts]
+    cross = xs * y1 - x1 * ys
+    area2 = np.abs(np.add.reduceat(cross, starts)).astype(object).sum()
+    ktop = 0
+    for k in range(1, 65):  # area bound and the tallest / widest chart
+        if (area2 * k * k <= (1 << 29) * inp.atlas_w * inp.atlas_h and
+                -(-k * int(W.max()) // 16384) <= inp.atlas_w and
+                -(-k * int(H.max()) // 16384) <= inp.atlas_h):
+            ktop = k
+    klo = kstar if kstar > 0 else 1
+    prof = 0
+    for k in range(klo, ktop + 1):
+        wk, hk = -(-k * W // 16384) + inp.padding, -(-k * H // 16384) + inp.padding
+        prof += 8 * int((wk + hk).sum())
+    V = int(off[-1])
+    return 8 * V + 4 * (n + 1) + n * (16 * K + 80) + prof + 9 * n + 4
 
 
 def served_leg(seconds=1.0, rate=2000.0):
-    """Poisson trace served with continuous batching vs one tabi_pack at a time."""
+    """Poisson trace served by the library's serving context (continuous
+    batching, resident proxies) vs one tabi_pack at a time."""
     import copy
     import numpy as np
     from paper_2602_07782_amd import serve
@@ -136,21 +276,27 @@ def served_leg(seconds=1.0, rate=2000.0):
     plain = [copy.copy(r) for r in reqs]
     srv = serve.Server()
     wall = srv.run(reqs)
+    stats = srv.stats()
+    srv.close()
     st = serve.latency_stats(reqs)
     pwall = serve.serve_plain(plain)
     pst = serve.latency_stats(plain)
     same = all(a.result[2] == b.result[2] and np.array_equal(a.result[0], b.result[0]) and
                np.array_equal(a.result[1], b.result[1]) for a, b in zip(reqs, plain))
+    alg = sum(atlas_algorithmic_bytes(r.inp, int(round(r.result[2] * 64))) for r in reqs)
     # capacity: the same requests all waiting at once (no arrival pacing), so
     # the rate is what each path can sustain rather than the trace's 2,000/s
     sat = [copy.copy(r) for r in reqs]
     splain = [copy.copy(r) for r in reqs]
     for r in sat + splain:
         r.done, r.result = -1.0, None
-    swall = serve.Server().run(sat, realtime=False)
+    srv = serve.Server()
+    swall = srv.run(sat, realtime=False)
+    srv.close()
     spwall = serve.serve_plain(splain, realtime=False)
     same &= all(a.result[2] == b.result[2] and np.array_equal(a.result[0], b.result[0])
                 for a, b in zip(sat, plain))
+    gbs = alg / swall / 1e9
     return {"requests": len(reqs), "rate_per_s": rate,
             "repacks": int(sum(r.replaced is not None for r in reqs)),
             "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
@@ -161,6 +307,11 @@ def served_leg(seconds=1.0, rate=2000.0):
             "capacity_atlases_per_s": round(len(sat) / swall, 2),
             "plain_capacity_atlases_per_s": round(len(splain) / spwall, 2),
             "capacity_speedup_vs_plain": round(spwall / swall, 2),
+            "capacity_hbm": {"algorithmic_bytes": alg, "achieved_GBps": round(gbs, 2),
+                             "peak_GBps": PEAK_HBM_GBS, "frac": round(gbs / PEAK_HBM_GBS, 6)},
+            "context": {k: stats[k] for k in ("launches", "evicted", "resubmitted",
+                                               "device_bytes_peak", "peak_in_flight",
+                                               "cross_slot_waits")},
             "bitexact_vs_alone": bool(same)}
 
 
@@ -224,9 +375,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    # the serving leg (several streams, continuous batching) is opt-in: its
-    # full-trace runs have faulted the GPU and the cause is not yet found
-    ap.add_argument("--served", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other single-pack configurations")
     ap.add_argument("--traffic-pass", action="store_true",
                     help="for hardware-counter runs: a few packs, then one plain 256 MiB device "
                          "copy whose byte count calibrates FETCH_SIZE / WRITE_SIZE")
@@ -350,20 +501,23 @@ def main():
                                   "sample": f"{reps} full packs of the same 2,000-chart input"}
         result["bitexact_vs_oracle"] = bool(osc == gsc and np.array_equal(oxy, gxy) and
                                             np.array_equal(oori, gor))
+    result["host_cores"] = host_cores()
+    if not args.no_configs:
+        try:
+            result["configs"] = config_legs(tabi, torch, not args.no_cpu)
+        except Exception as e:  # report, do not lose the main line
+            result["configs"] = {"error": repr(e)}
     if not args.no_batched:
         try:
-            result["batched"] = batched_leg(tabi, torch)
-        except Exception as e:  # report, do not lose the main line
+            result["batched"] = batched_leg(tabi, torch,
+                                            cpu_seconds=0.0 if args.no_cpu else args.cpu_seconds)
+        except Exception as e:
             result["batched"] = {"error": repr(e)}
-    if args.served:
+    if not args.no_served:
         try:
             result["served"] = served_leg()
         except Exception as e:
             result["served"] = {"error": repr(e)}
-    else:
-        result["served"] = {"run": False,
-                            "reason": "opt-in (--served): the multi-stream serving run faulted "
-                                      "the GPU; cause not yet found"}
     print(json.dumps(result), flush=True)
 
 

@@ -51,8 +51,11 @@ enum {
                        quality not in {0,1,2}, count < 0, work space too small */
   TABI_ENOMEM = -2, /* the device memory pool could not supply the work space */
   TABI_EHIP = -3,   /* a HIP runtime call failed (launch, memory); see tabi_last_hip_error */
-  TABI_ETOOBIG = -4 /* tabi_pack_noalloc: the input needs more work space than its
-                       static array of TABI_NOALLOC_BYTES holds */
+  TABI_ETOOBIG = -4, /* tabi_pack_noalloc: the input needs more work space than its
+                       static array of TABI_NOALLOC_BYTES holds; a served request
+                       larger than the serving context's memory or staging */
+  TABI_ENOTRESIDENT = -5 /* a served re-pack of an atlas whose records are no longer
+                            resident (evicted under the memory budget) */
 };
 
 #define TABI_MAX_CHARTS 262144 /* charts per atlas */
@@ -211,6 +214,73 @@ int tabi_pack_many_records(const void* records, const int32_t* atlas_offsets, in
                            const int32_t* atlas_wh, int32_t total_charts, int32_t max_charts,
                            int32_t max_side, int32_t padding, int32_t quality, int32_t* out_xy,
                            uint8_t* out_orient, float* out_scale, tabi_stream_t stream);
+
+/* ---- serving (continuous batching with resident proxies) ----------------
+ * A serving context admits pack requests as they arrive and runs them in
+ * batches, one batch per launch slot (a HIP stream of its own), so batches on
+ * different slots overlap on the GPU and requests that arrive while others
+ * run join the next batch as slots and memory free up.  Each atlas's chart
+ * proxy records (Sec. 4.1.1) stay resident on the device, so a re-pack with
+ * some charts replaced recomputes only those charts' records.  A request's
+ * result equals tabi_pack of its chart set alone, bit for bit.
+ *
+ * Memory: the context allocates, once at creation, device_bytes of device
+ * memory (batches in flight and resident records, admitted by footprint;
+ * least recently used atlases are evicted when a batch needs room) and two
+ * pinned host staging buffers of staging_bytes per slot.  Nothing else is
+ * allocated afterwards.  Unlike tabi_pack, chart data and outputs are HOST
+ * arrays: inputs are copied before tabi_submit / tabi_repack return; the
+ * output arrays must stay valid until tabi_poll reports the ticket done.
+ * A context is used from one host thread at a time. */
+typedef struct tabi_ctx tabi_ctx;
+typedef struct {
+  int32_t quality, padding; /* as tabi_pack, shared by every request */
+  int32_t streams;          /* launch slots, 1..16 */
+  int32_t max_batch;        /* requests per batch, 1..1024 */
+  int64_t device_bytes;     /* device memory budget (>= 1 MiB) */
+  int64_t staging_bytes;    /* pinned staging per slot and direction (>= 64 KiB) */
+} tabi_ctx_config;
+typedef struct {
+  int64_t ticket;
+  int32_t atlas_id;
+  int32_t status;      /* TABI_OK, TABI_ETOOBIG, TABI_ENOTRESIDENT or a launch error */
+  int32_t batch;       /* batch it ran in (0: it did not run) */
+  int32_t pad;
+  double latency_ms;   /* submission to completion of its batch on the GPU */
+  double submit_ms;    /* submission time since the context was created */
+  double done_ms;      /* completion time since the context was created */
+} tabi_done;
+
+/* Errors: TABI_EINVAL for a bad configuration; TABI_ENOMEM / TABI_EHIP if
+ * the memory, streams or events cannot be created (*ctx stays NULL). */
+int tabi_ctx_create(const tabi_ctx_config* cfg, tabi_ctx** ctx);
+/* Waits for the batches in flight, then releases everything. */
+int tabi_ctx_destroy(tabi_ctx* ctx);
+/* A pack of a new atlas: n >= 1 charts (host CSR: xy int32[2*offsets[n]]
+ * in Q8, offsets int32[n+1]) into atlas_w x atlas_h.  Returns the atlas id
+ * its records stay resident under and a ticket.  Outputs as tabi_pack
+ * (host arrays): out_xy int32[2n], out_orient uint8[n], out_scale float[1]. */
+int tabi_submit(tabi_ctx* ctx, const int32_t* xy, const int32_t* offsets, int32_t n,
+                int32_t atlas_w, int32_t atlas_h, int32_t* out_xy, uint8_t* out_orient,
+                float* out_scale, int32_t* atlas_id, int64_t* ticket);
+/* A re-pack of a resident atlas whose charts replaced_idx[0..m) (strictly
+ * increasing indices of its current chart set) are replaced by the m charts
+ * of the host CSR (xy, offsets); every other chart keeps its records and its
+ * index.  The atlas's chart set becomes the new one (later re-packs build on
+ * it, in submission order).  Outputs as tabi_submit, for the whole atlas. */
+int tabi_repack(tabi_ctx* ctx, int32_t atlas_id, const int32_t* replaced_idx, int32_t m,
+                const int32_t* xy, const int32_t* offsets, int32_t* out_xy,
+                uint8_t* out_orient, float* out_scale, int64_t* ticket);
+/* Retire completed batches (their outputs are written to the callers'
+ * arrays), admit queued requests into free slots, and report up to max_done
+ * finished tickets in done[0..*n_done).  wait != 0: block until at least one
+ * batch completes when none is reported yet and some are in flight. */
+int tabi_poll(tabi_ctx* ctx, int32_t wait, tabi_done* done, int32_t max_done, int32_t* n_done);
+/* stats[0..nstats): batches launched, requests finished, requests failed,
+ * atlases evicted, atlases resident, device bytes in use, peak device bytes,
+ * requests queued, batches in flight, cross-slot waits, most batches in
+ * flight at once. */
+int tabi_ctx_stats(tabi_ctx* ctx, int64_t* stats, int32_t nstats);
 
 /* ---- diagnostics (same conventions; device pointers) ------------------- */
 

@@ -423,7 +423,7 @@ void orc_row_proxies(const orc_chart* ch, int32_t k, int32_t* h_out, int32_t* la
 /* ------------------------------------------------------------------------ */
 /* Sorting (Sec. 3.1): height descending; ties by width descending, then by
  * input index.                                                              */
-static const orc_chart* g_sort_charts;
+static _Thread_local const orc_chart* g_sort_charts;  /* per thread: packs may run side by side */
 static int cmp_order(const void* pa, const void* pb) {
   int ia = *(const int*)pa, ib = *(const int*)pb;
   const orc_chart *a = &g_sort_charts[ia], *b = &g_sort_charts[ib];

@@ -14,10 +14,11 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtabi_hip.so")
 
-TABI_OK, TABI_EINVAL, TABI_ENOMEM, TABI_EHIP, TABI_ETOOBIG = 0, -1, -2, -3, -4
+TABI_OK, TABI_EINVAL, TABI_ENOMEM, TABI_EHIP, TABI_ETOOBIG, TABI_ENOTRESIDENT = 0, -1, -2, -3, -4, -5
 ERRORS = {TABI_EINVAL: "invalid argument", TABI_ENOMEM: "out of device memory",
           TABI_EHIP: "HIP runtime error",
-          TABI_ETOOBIG: "input exceeds the static work space of tabi_pack_noalloc"}
+          TABI_ETOOBIG: "input exceeds the work space available to it",
+          TABI_ENOTRESIDENT: "atlas records no longer resident"}
 
 
 class TabiError(RuntimeError):
@@ -31,6 +32,19 @@ class Charts(ctypes.Structure):
                 ("total_verts", ctypes.c_int32)]
 
 
+class CtxConfig(ctypes.Structure):
+    _fields_ = [("quality", ctypes.c_int32), ("padding", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64), ("staging_bytes", ctypes.c_int64)]
+
+
+class Done(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("atlas_id", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("batch", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("latency_ms", ctypes.c_double), ("submit_ms", ctypes.c_double),
+                ("done_ms", ctypes.c_double)]
+
+
 _lib = None
 EXPORTS = ["tabi_pack", "tabi_pack_noalloc", "tabi_pack_many", "tabi_pack_many_ws", "tabi_pack_many_workspace_bytes",
            "tabi_record_bytes", "tabi_prep_records", "tabi_splice_records",
@@ -39,7 +53,8 @@ EXPORTS = ["tabi_pack", "tabi_pack_noalloc", "tabi_pack_many", "tabi_pack_many_w
            "tabi_timing_enable", "tabi_timing_read", "tabi_timing_reset",
            "tabi_debug_set_stage_cap", "tabi_debug_set_profile_cap", "tabi_tune_many",
            "tabi_many_shape", "tabi_many_shape_count", "tabi_debug_set_many_shape",
-           "tabi_shutdown"]
+           "tabi_shutdown", "tabi_ctx_create", "tabi_ctx_destroy", "tabi_submit", "tabi_repack",
+           "tabi_poll", "tabi_ctx_stats"]
 STAGES = ["prep", "sort", "setup", "profile", "pack", "select"]
 
 
@@ -84,6 +99,14 @@ def lib():
         L.tabi_many_shape.argtypes = [i32, i32, vp]
         L.tabi_many_shape_count.restype = i32
         L.tabi_debug_set_many_shape.argtypes = [i32, i32]
+        L.tabi_ctx_create.argtypes = [ctypes.POINTER(CtxConfig), ctypes.POINTER(vp)]
+        L.tabi_ctx_destroy.argtypes = [vp]
+        L.tabi_submit.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp,
+                                  ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]
+        L.tabi_repack.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, vp,
+                                  ctypes.POINTER(ctypes.c_int64)]
+        L.tabi_poll.argtypes = [vp, i32, ctypes.POINTER(Done), i32, ctypes.POINTER(i32)]
+        L.tabi_ctx_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), i32]
         _lib = L
     return _lib
 
@@ -362,3 +385,89 @@ def debug_set_profile_cap(words):
     """Size of the stored-profile arena in words (-1 = default, 0 = none);
     results are unchanged."""
     _check(lib().tabi_debug_set_profile_cap(int(words)))
+
+
+CTX_STATS = ["launches", "finished", "failed", "evicted", "resident", "device_bytes_used",
+             "device_bytes_peak", "queued", "in_flight", "cross_slot_waits", "peak_in_flight"]
+
+
+def _hptr(a):
+    """Host address of a C-contiguous numpy array."""
+    return ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(0)
+
+
+class ServeContext:
+    """tabi_ctx: continuous batching of pack requests with resident proxies.
+    Chart data are host numpy arrays (copied at submission); each request's
+    outputs are host numpy arrays filled when tabi_poll reports it done."""
+
+    def __init__(self, quality=2, padding=2, streams=4, max_batch=256, device_bytes=16 << 30,
+                 staging_bytes=64 << 20):
+        cfg = CtxConfig(int(quality), int(padding), int(streams), int(max_batch),
+                        int(device_bytes), int(staging_bytes))
+        h = ctypes.c_void_p()
+        _check(lib().tabi_ctx_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+        self.outputs = {}  # ticket -> (xy, orient, scale): kept alive until reported
+
+    def _outs(self, n):
+        import numpy as np
+        return (np.empty((n, 2), np.int32), np.empty(n, np.uint8), np.empty(1, np.float32))
+
+    def submit(self, xy, offsets, atlas_w, atlas_h):
+        """New atlas; returns (atlas_id, ticket)."""
+        import numpy as np
+        xy = np.ascontiguousarray(xy, np.int32)
+        off = np.ascontiguousarray(offsets, np.int32)
+        n = off.size - 1
+        o = self._outs(n)
+        aid, t = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().tabi_submit(self.h, _hptr(xy), _hptr(off), n, int(atlas_w), int(atlas_h),
+                                 _hptr(o[0]), _hptr(o[1]), _hptr(o[2]), ctypes.byref(aid),
+                                 ctypes.byref(t)))
+        self.outputs[t.value] = o
+        return aid.value, t.value
+
+    def repack(self, atlas_id, replaced, xy, offsets, n):
+        """Re-pack of resident atlas `atlas_id` (n charts) with charts
+        `replaced` (increasing indices) replaced by the CSR (xy, offsets)."""
+        import numpy as np
+        idx = np.ascontiguousarray(replaced, np.int32)
+        xy = np.ascontiguousarray(xy, np.int32)
+        off = np.ascontiguousarray(offsets, np.int32)
+        o = self._outs(n)
+        t = ctypes.c_int64()
+        _check(lib().tabi_repack(self.h, int(atlas_id), _hptr(idx), int(idx.size), _hptr(xy),
+                                 _hptr(off), _hptr(o[0]), _hptr(o[1]), _hptr(o[2]),
+                                 ctypes.byref(t)))
+        self.outputs[t.value] = o
+        return t.value
+
+    def poll(self, wait=False, max_done=4096):
+        """Finished requests: list of (ticket, atlas_id, status, batch,
+        latency_ms, (xy, orient, scale) or None)."""
+        buf = (Done * max_done)()
+        k = ctypes.c_int32()
+        _check(lib().tabi_poll(self.h, 1 if wait else 0, buf, max_done, ctypes.byref(k)))
+        out = []
+        for d in buf[:k.value]:
+            o = self.outputs.pop(d.ticket)
+            out.append((d.ticket, d.atlas_id, d.status, d.batch, d.latency_ms,
+                        o if d.status == TABI_OK else None))
+        return out
+
+    def stats(self):
+        v = (ctypes.c_int64 * len(CTX_STATS))()
+        _check(lib().tabi_ctx_stats(self.h, v, len(CTX_STATS)))
+        return dict(zip(CTX_STATS, list(v)))
+
+    def close(self):
+        if self.h:
+            h, self.h = self.h, None
+            _check(lib().tabi_ctx_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -493,6 +493,44 @@ void* scratch_ptr() {
 
 }  // namespace
 
+namespace tabi {
+
+int64_t host_many_workspace_bytes(int count, int N, int nmax, int max_side, int p, int q) {
+  return (int64_t)layout(many_params(count, N, nmax, max_side, p, q)).total;
+}
+
+int host_pack_many_records_ws(const Chart* recs, const int32_t* aoff, int count,
+                              const int32_t* awh, int N, int nmax, int max_side, int p, int q,
+                              int32_t* out_xy, uint8_t* out_orient, float* out_scale, void* ws,
+                              size_t ws_bytes, hipStream_t st) {
+  if (!ws) return TABI_EINVAL;
+  return pack_many_impl(nullptr, nullptr, aoff, count, awh, N, nmax, max_side, p, q, out_xy,
+                        out_orient, out_scale, ws, ws_bytes, reinterpret_cast<tabi_stream_t>(st),
+                        recs ? static_cast<const void*>(recs) : static_cast<const void*>(aoff));
+}
+
+size_t host_prep_scratch_bytes(int M) {
+  return align_up((size_t)(M > 0 ? M : 1) * 8, 256) + align_up((size_t)(M > 0 ? M : 1) * 4, 256);
+}
+
+int host_prep_records(const int32_t* xy, const int32_t* voff, const int32_t* goff, int groups,
+                      int M, int q, Chart* recs, void* scratch, hipStream_t st) {
+  if (M <= 0) return TABI_OK;
+  Params P = make_params(groups, M, q, 0, 1, 0, 1, 1);
+  Work W{};
+  W.recs = recs;
+  W.keys = static_cast<uint64_t*>(scratch);
+  W.chart_atlas = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(scratch) +
+                                             align_up((size_t)M * 8, 256));
+  W.desc = nullptr;  // no atlas descriptors, no ranks
+  const hipError_t e = launch_prep(P, W, xy, voff, goff, nullptr, 0, 0, st);
+  return e == hipSuccess ? TABI_OK : hip_fail(e);
+}
+
+int host_hip_fail(hipError_t e) { return hip_fail(e); }
+
+}  // namespace tabi
+
 extern "C" {
 
 int tabi_pack(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
@@ -655,23 +693,16 @@ int tabi_prep_records(const int32_t* xy, const int32_t* vert_offsets, const int3
     return TABI_EINVAL;
   if (total_charts == 0) return TABI_OK;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  Params P = make_params(count, total_charts, quality, 0, 1, 0, 1, 1);
-  // only the record array and the chart->atlas / key scratch are touched
   void* scratch = nullptr;
-  hipError_t e = hipMallocAsync(&scratch, (size_t)total_charts * 12 + 256, st);
+  hipError_t e = hipMallocAsync(&scratch, host_prep_scratch_bytes(total_charts), st);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return e == hipErrorOutOfMemory ? TABI_ENOMEM : hip_fail(e);
   }
-  Work W{};
-  W.recs = static_cast<Chart*>(records);
-  W.keys = static_cast<uint64_t*>(scratch);
-  W.chart_atlas = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(scratch) +
-                                             align_up((size_t)total_charts * 8, 256));
-  W.desc = nullptr;
-  e = launch_prep(P, W, xy, vert_offsets, atlas_offsets, nullptr, 0, 0, st);
+  const int rc = host_prep_records(xy, vert_offsets, atlas_offsets, count, total_charts, quality,
+                                   static_cast<Chart*>(records), scratch, st);
   (void)hipFreeAsync(scratch, st);
-  return e == hipSuccess ? TABI_OK : hip_fail(e);
+  return rc;
 }
 
 int tabi_splice_records(void* records, const int32_t* index, int32_t m, const void* new_records,

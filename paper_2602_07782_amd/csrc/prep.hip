@@ -568,6 +568,67 @@ __global__ __launch_bounds__(256) void k_splice(Chart* __restrict__ dst, const i
   dst[j] = c;
 }
 
+// Records of a serving batch: request r owns charts [aoff[r], aoff[r+1]) of
+// the batch.  A re-pack (src_res[r] != 0) starts from its atlas's resident
+// records, a new atlas from its freshly prepared records at poff[r]; every
+// record is also written to the request's new resident block dst_res[r].
+__global__ __launch_bounds__(256) void k_assemble(int N, int count, const int32_t* __restrict__ aoff,
+                                                  const int32_t* __restrict__ poff,
+                                                  const uint64_t* __restrict__ src_res,
+                                                  const uint64_t* __restrict__ dst_res,
+                                                  const Chart* __restrict__ prep, Chart* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  int lo = 0, hi = count - 1;  // last r with aoff[r] <= c
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (aoff[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  const int t = c - aoff[lo];
+  const Chart* src = reinterpret_cast<const Chart*>(src_res[lo]);
+  const Chart ch = src ? src[t] : prep[poff[lo] + t];
+  out[c] = ch;
+  reinterpret_cast<Chart*>(dst_res[lo])[t] = ch;
+}
+
+// The replaced charts of the re-packs: prepared record i of request r
+// (i in [poff[r], poff[r+1])) replaces chart idx[i] of the request, which
+// keeps its input index.
+__global__ __launch_bounds__(256) void k_assemble_splice(int M, int count,
+                                                         const int32_t* __restrict__ aoff,
+                                                         const int32_t* __restrict__ poff,
+                                                         const uint64_t* __restrict__ src_res,
+                                                         const uint64_t* __restrict__ dst_res,
+                                                         const int32_t* __restrict__ idx,
+                                                         const Chart* __restrict__ prep,
+                                                         Chart* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  int lo = 0, hi = count - 1;  // last r with poff[r] <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (poff[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  if (!src_res[lo]) return;  // a new atlas: already in place
+  const int j = idx[i];
+  Chart ch = prep[i];
+  ch.src = j;
+  out[aoff[lo] + j] = ch;
+  reinterpret_cast<Chart*>(dst_res[lo])[j] = ch;
+}
+
+hipError_t launch_assemble(int N, int M, int count, const int32_t* aoff, const int32_t* poff,
+                           const uint64_t* src_res, const uint64_t* dst_res, const int32_t* idx,
+                           const Chart* prep, Chart* out, hipStream_t st) {
+  if (N > 0)
+    hipLaunchKernelGGL(k_assemble, dim3((N + 255) / 256), dim3(256), 0, st, N, count, aoff, poff,
+                       src_res, dst_res, prep, out);
+  if (M > 0)
+    hipLaunchKernelGGL(k_assemble_splice, dim3((M + 255) / 256), dim3(256), 0, st, M, count, aoff,
+                       poff, src_res, dst_res, idx, prep, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_from_records(const Params& P, const Work& w, const Chart* in,
                                const int32_t* atlas_off, const int32_t* atlas_wh, hipStream_t st) {
   // the records kernel also writes the atlas descriptors
@@ -615,8 +676,6 @@ hipError_t launch_sort(const Params& P, const Work& w, hipStream_t st) {
   hipLaunchKernelGGL(k_plan, dim3(P.count), dim3(256), 0, st, P, w);
   return hipGetLastError();
 }
-
-hipError_t launch_plan(const Params&, const Work&, hipStream_t) { return hipSuccess; }
 
 hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t st) {
   if (P.N > 0)

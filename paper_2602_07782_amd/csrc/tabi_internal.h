@@ -98,8 +98,13 @@ hipError_t launch_from_records(const Params& P, const Work& w, const Chart* in,
                                const int32_t* atlas_off, const int32_t* atlas_wh, hipStream_t st);
 hipError_t launch_splice(Chart* dst, const int32_t* idx, int m, const Chart* src, hipStream_t st);
 hipError_t launch_sort(const Params& P, const Work& w, hipStream_t st);
-hipError_t launch_plan(const Params& P, const Work& w, hipStream_t st);
 hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t st);
+// records of a serving batch (N charts of `count` requests, M of them freshly
+// prepared): resident or prepared records into `out` and each request's new
+// resident block, then the re-packs' replaced charts
+hipError_t launch_assemble(int N, int M, int count, const int32_t* aoff, const int32_t* poff,
+                           const uint64_t* src_res, const uint64_t* dst_res, const int32_t* idx,
+                           const Chart* prep, Chart* out, hipStream_t st);
 // per-texel profiles and neighbour pairs (compacting distance, interlock flags)
 hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_t st);
 // fold-and-push of the round's scales; for a single atlas its last workgroup
@@ -124,5 +129,23 @@ struct PackLds {
   int RC, PW, bytes;
 };
 PackLds pack_lds_plan(int nmax, int Wd, int budget);
+
+// Host runtime shared by the C ABI entry points (api.cpp) and the serving
+// context (serve.cpp).  Return TABI_* codes.
+// bytes of work space a batched call of this shape takes
+int64_t host_many_workspace_bytes(int count, int N, int nmax, int max_side, int p, int q);
+// the batched pack from proxy records, on a caller work space
+int host_pack_many_records_ws(const Chart* recs, const int32_t* aoff, int count,
+                              const int32_t* awh, int N, int nmax, int max_side, int p, int q,
+                              int32_t* out_xy, uint8_t* out_orient, float* out_scale, void* ws,
+                              size_t ws_bytes, hipStream_t st);
+// proxy records of M charts in `groups` groups (group g: charts
+// [goff[g], goff[g+1]); a record's input index is its position in its group)
+// with caller scratch of host_prep_scratch_bytes(M)
+size_t host_prep_scratch_bytes(int M);
+int host_prep_records(const int32_t* xy, const int32_t* voff, const int32_t* goff, int groups,
+                      int M, int q, Chart* recs, void* scratch, hipStream_t st);
+// record the HIP error text of a failed call; returns TABI_EHIP
+int host_hip_fail(hipError_t e);
 
 }  // namespace tabi

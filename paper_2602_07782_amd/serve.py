@@ -1,23 +1,21 @@
-"""Continuous-batching pack server over the C ABI.
+"""Serving workload and driver over the library's serving context.
 
 Requests (new atlases, or re-packs of a resident atlas with some charts
-replaced) arrive over time.  The server admits them while their device
-footprint fits an HBM budget and a launch slot (stream) is free, merges every
-admitted request into one batched launch (tabi_pack_many_records) on that
-stream, and keeps going: batches on different streams overlap on the GPU,
-and requests that arrive meanwhile join the next batch.  Per-chart proxy
-records stay resident on the device per atlas, so a re-pack recomputes only
-the replaced charts' records (tabi_prep_records + tabi_splice_records).
+replaced) arrive over time as a Poisson trace.  The library's serving
+context (tabi_ctx, C ABI) admits them while their device footprint fits its
+memory budget and a launch slot (stream) is free, merges every admitted
+request into one batched launch on that slot, and keeps going: batches on
+different slots overlap on the GPU, and requests that arrive meanwhile join
+the next batch.  Per-chart proxy records stay resident on the device per
+atlas, so a re-pack recomputes only the replaced charts' records.
 
-Completion times come from HIP events, latency = completion - arrival.
-All packing work runs in the library's kernels; PyTorch supplies device
-memory, streams and events.
+Latency = completion of the request's batch on the GPU (HIP event) - arrival.
 """
 from __future__ import annotations
 
 import dataclasses
 import time
-from collections import OrderedDict, deque
+from collections import deque
 
 import numpy as np
 
@@ -33,6 +31,7 @@ class Request:
     replaced: np.ndarray | None = None   # for re-packs: replaced chart indices
     done: float = -1.0
     result: tuple | None = None  # (xy[n,2], orient[n], scale) on the host
+    t_sub: float = -1.0          # when it was (last) submitted, since trace start
 
 
 def make_trace(rate=2000.0, seconds=1.0, seed=5000, pool_size=24, repack_frac=0.2,
@@ -84,158 +83,75 @@ def _latest(reqs, aid):
 
 
 class Server:
+    """Serving loop over the library's serving context (tabi_ctx): each
+    request is submitted at its arrival time (tabi_submit for a new atlas,
+    tabi_repack with the replaced charts for a re-pack of a resident one) and
+    completions are polled.  The context batches what is queued into free
+    launch slots, admits by device-memory footprint and keeps every atlas's
+    proxy records resident; a re-pack whose atlas was evicted under the budget
+    is submitted again as a new atlas with its whole chart set."""
+
     def __init__(self, quality=2, padding=2, hbm_budget=16 << 30, streams=4, max_batch=256,
-                 device="cuda"):
-        import torch
+                 staging_bytes=64 << 20, device="cuda"):
         import paper_2602_07782_amd as tabi
-        self.torch, self.tabi = torch, tabi
-        self.dev = torch.device(device)
-        self.q, self.p = quality, padding
-        self.budget = int(hbm_budget)
-        self.max_batch = max_batch
-        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(streams)]
-        self.free_streams = deque(range(streams))
-        self.inflight = []          # (stream idx, event, requests, outputs, bytes)
-        self.used = 0
-        self.resident = OrderedDict()  # atlas_id -> device records (LRU order)
-        self.resident_event = {}       # atlas_id -> event of the batch that wrote them
-        self.resident_bytes = 0
-        self.rb = tabi.record_bytes()
-        self.t0_event = torch.cuda.Event(enable_timing=True)
-        self.t0_wall = 0.0
+        self.tabi = tabi
+        self.ctx = tabi.ServeContext(quality, padding, streams, max_batch, hbm_budget,
+                                     staging_bytes)
+        self.ids = {}        # trace atlas id -> context atlas id
+        self.by_ticket = {}  # ticket -> request
+        self.resubmitted = 0
 
-    # -- footprint ---------------------------------------------------------
-    def footprint(self, r):
-        n = r.inp.n
-        side = max(r.inp.atlas_w, r.inp.atlas_h)
-        ws = self.tabi.lib().tabi_pack_many_workspace_bytes(1, n, n, side, self.p, self.q)
-        return int(ws) + 2 * n * self.rb + 16 * n
+    def _submit(self, r, now):
+        r.t_sub = now
+        if r.replaced is not None and r.atlas_id in self.ids:
+            sub = [r.inp.chart(int(c)) for c in r.replaced]
+            sxy, soff = synth.pack_csr(sub)
+            aid = self.ids[r.atlas_id]
+            t = self.ctx.repack(aid, r.replaced, sxy, soff, r.inp.n)
+        else:
+            aid, t = self.ctx.submit(r.inp.xy, r.inp.offsets, r.inp.atlas_w, r.inp.atlas_h)
+        self.ids[r.atlas_id] = aid
+        self.by_ticket[t] = r
 
-    def _evict_for(self, need):
-        while self.resident and self.used + self.resident_bytes + need > self.budget:
-            aid, rec = self.resident.popitem(last=False)
-            self.resident_event.pop(aid, None)
-            self.resident_bytes -= rec.numel()
-
-    # -- one batched launch --------------------------------------------------
-    def _launch(self, batch):
-        torch, tabi = self.torch, self.tabi
-        si = self.free_streams.popleft()
-        s = self.streams[si]
-        nbytes = sum(self.footprint(r) for r in batch)
-        with torch.cuda.stream(s):
-            recs, wh, aoff = [], [], [0]
-            for r in batch:
-                inp = r.inp
-                base = self.resident.get(r.atlas_id) if r.replaced is not None else None
-                if base is not None:
-                    ev0 = self.resident_event.get(r.atlas_id)
-                    if ev0 is not None:
-                        s.wait_event(ev0)  # records written by a batch on another stream
-                    base.record_stream(s)
-                    rec = base.clone()
-                    sub = [inp.chart(int(c)) for c in r.replaced]
-                    sxy, soff = synth.pack_csr(sub)
-                    new = tabi.prep_records(sxy, soff, np.array([0, len(sub)], np.int32), self.q,
-                                            stream=s, device=self.dev)
-                    tabi.splice_records(rec, r.replaced, new, stream=s)
-                else:
-                    rec = tabi.prep_records(inp.xy, inp.offsets, np.array([0, inp.n], np.int32),
-                                            self.q, stream=s, device=self.dev)
-                self._keep(r.atlas_id, rec)
-                recs.append(rec)
-                wh += [inp.atlas_w, inp.atlas_h]
-                aoff.append(aoff[-1] + inp.n)
-            allrec = torch.cat(recs) if len(recs) > 1 else recs[0]
-            N = aoff[-1]
-            aoff_t = torch.tensor(aoff, dtype=torch.int32).to(self.dev, non_blocking=True)
-            wh_t = torch.tensor(wh, dtype=torch.int32).to(self.dev, non_blocking=True)
-            out_xy = torch.empty((N, 2), dtype=torch.int32, device=self.dev)
-            out_or = torch.empty(N, dtype=torch.uint8, device=self.dev)
-            out_sc = torch.empty(len(batch), dtype=torch.float32, device=self.dev)
-            tabi.pack_many_records(allrec, aoff_t, wh_t, max(r.inp.n for r in batch),
-                                   max(max(r.inp.atlas_w, r.inp.atlas_h) for r in batch), self.p,
-                                   self.q, out_xy, out_or, out_sc, stream=s)
-            ev = torch.cuda.Event(enable_timing=True)
-            ev.record(s)
-        for r in batch:
-            self.resident_event[r.atlas_id] = ev
-        self.used += nbytes
-        self.inflight.append((si, ev, batch, (out_xy, out_or, out_sc, aoff, allrec), nbytes))
-
-    def _keep(self, aid, rec):
-        old = self.resident.pop(aid, None)
-        if old is not None:
-            self.resident_bytes -= old.numel()
-        self.resident[aid] = rec
-        self.resident_bytes += rec.numel()
-
-    def _poll(self, block=False):
-        done_any = False
-        keep = []
-        for item in self.inflight:
-            si, ev, batch, outs, nbytes = item
-            if block or ev.query():
-                ev.synchronize()
-                t_done = self.t0_wall + self.t0_event.elapsed_time(ev) / 1000.0
-                out_xy, out_or, out_sc, aoff, _ = outs
-                xy, ori, sc = out_xy.cpu().numpy(), out_or.cpu().numpy(), out_sc.cpu().numpy()
-                for j, r in enumerate(batch):
-                    a, b = aoff[j], aoff[j + 1]
-                    r.result = (xy[a:b], ori[a:b], float(sc[j]))
-                    r.done = t_done
-                self.used -= nbytes
-                self.free_streams.append(si)
-                done_any = True
-                block = False
-            else:
-                keep.append(item)
-        self.inflight = keep
-        return done_any
+    def _collect(self, wait, now):
+        got = self.ctx.poll(wait)
+        for ticket, _aid, status, _batch, lat_ms, out in got:
+            r = self.by_ticket.pop(ticket)
+            if status == self.tabi.TABI_ENOTRESIDENT:
+                self.ids.pop(r.atlas_id, None)
+                self.resubmitted += 1
+                self._submit(r, now)
+                continue
+            if status != self.tabi.TABI_OK:
+                raise self.tabi.TabiError(status, f"request {r.rid}")
+            r.result = (out[0], out[1], float(out[2][0]))
+            r.done = r.t_sub + lat_ms / 1000.0
+        return bool(got)
 
     def run(self, requests, realtime=True):
-        """Serve a trace; returns wall seconds from the first arrival to the
-        last completion."""
-        torch = self.torch
+        """Serve a trace; returns seconds from the trace start to the last
+        completion (arrival times are relative to the start)."""
         pending = deque(sorted(requests, key=lambda r: r.arrival))
-        queue = deque()
-        torch.cuda.synchronize()
-        self.t0_event.record(torch.cuda.current_stream())
-        self.t0_wall = time.perf_counter()
-        start = self.t0_wall
-        while pending or queue or self.inflight:
+        start = time.perf_counter()
+        while pending or self.by_ticket:
             now = time.perf_counter() - start
             while pending and (pending[0].arrival <= now or not realtime):
-                queue.append(pending.popleft())
-            progressed = self._poll()
-            launched = False
-            while queue and self.free_streams:
-                # admit in arrival order while the footprint fits the budget;
-                # a request larger than the budget runs alone on an idle GPU
-                batch, need = [], 0
-                while queue and len(batch) < self.max_batch:
-                    f = self.footprint(queue[0])
-                    alone = not batch and not self.inflight
-                    if self.used + need + f > self.budget and not alone:
-                        break
-                    self._evict_for(need + f)
-                    need += f
-                    batch.append(queue.popleft())
-                if not batch:
-                    break
-                self._launch(batch)
-                launched = True
-            if not launched and not progressed:
-                if self.inflight and not pending and not queue:
-                    self._poll(block=True)       # nothing else to do: wait for the GPU
-                elif self.inflight:
-                    time.sleep(0.0002)
-                elif pending and realtime:
-                    time.sleep(max(0.0, min(0.001, pending[0].arrival - now)))
-        # arrivals are relative to start; completions are wall times
-        for r in requests:
-            r.done -= start
+                self._submit(pending.popleft(), time.perf_counter() - start)
+            if self._collect(False, time.perf_counter() - start):
+                continue
+            if pending and realtime:
+                time.sleep(max(0.0, min(0.0005, pending[0].arrival - now)))
+            elif self.by_ticket:
+                self._collect(True, time.perf_counter() - start)
         return max(r.done for r in requests)
+
+    def stats(self):
+        d = self.ctx.stats()
+        d["resubmitted"] = self.resubmitted
+        return d
+
+    def close(self):
+        self.ctx.close()
 
 
 def serve_plain(requests, quality=2, padding=2, device="cuda", realtime=True):

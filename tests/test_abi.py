@@ -70,3 +70,29 @@ def test_padding_limit_and_arena_sizing_are_host_only():
         tabi.debug_set_profile_cap(-1)
     # 8 scale slots x 8000 charts x 96 words + 8 x 4 x 4 x 2050 words
     assert full - none >= 4 * (8 * 8000 * 96 + 8 * 4 * 4 * 2050)
+
+
+def test_serving_context_refuses_bad_arguments_on_the_host():
+    """Configuration and request checks of the serving context come before
+    any HIP call, so they run without a GPU."""
+    import paper_2602_07782_amd as tabi
+    if not os.path.exists(tabi.LIB_PATH):
+        pytest.skip("library not built")
+    L = tabi.lib()
+    h = ctypes.c_void_p()
+    for bad in [tabi.CtxConfig(3, 2, 4, 16, 1 << 30, 1 << 20),     # quality
+                tabi.CtxConfig(2, 33, 4, 16, 1 << 30, 1 << 20),    # padding
+                tabi.CtxConfig(2, 2, 0, 16, 1 << 30, 1 << 20),     # streams
+                tabi.CtxConfig(2, 2, 4, 0, 1 << 30, 1 << 20),      # batch
+                tabi.CtxConfig(2, 2, 4, 16, 1000, 1 << 20),        # device budget
+                tabi.CtxConfig(2, 2, 4, 16, 1 << 30, 100)]:        # staging
+        assert L.tabi_ctx_create(ctypes.byref(bad), ctypes.byref(h)) == tabi.TABI_EINVAL
+        assert not h.value
+    assert L.tabi_ctx_create(None, ctypes.byref(h)) == tabi.TABI_EINVAL
+    i32, i64 = ctypes.c_int32(), ctypes.c_int64()
+    assert L.tabi_submit(None, None, None, 1, 64, 64, None, None, None, ctypes.byref(i32),
+                         ctypes.byref(i64)) == tabi.TABI_EINVAL
+    assert L.tabi_repack(None, 0, None, 1, None, None, None, None, None,
+                         ctypes.byref(i64)) == tabi.TABI_EINVAL
+    assert L.tabi_poll(None, 0, None, 0, ctypes.byref(i32)) == tabi.TABI_EINVAL
+    assert L.tabi_ctx_destroy(None) == tabi.TABI_EINVAL

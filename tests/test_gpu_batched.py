@@ -219,3 +219,59 @@ def test_batch_above_reorder_limit(tabi, orc):
         assert float(sc[a]) == osc, (a, sc[a], osc)
         assert np.array_equal(xy[c0:c0 + inp.n], oxy), a
         assert np.array_equal(ori[c0:c0 + inp.n], oori), a
+
+
+def test_records_entry_points_on_one_stream(tabi, orc):
+    """tabi_prep_records, tabi_splice_records and tabi_pack_many_records on
+    the current stream: a batch packed from records equals the oracle per
+    atlas, and a spliced re-pack equals the oracle on the new chart set."""
+    import torch
+    inputs = small_batch(3, 41, nmax=250)
+    dev = torch.device("cuda:0")
+    xy, voff, aoff, wh = [], [0], [0], []
+    for inp in inputs:
+        xy.append(np.asarray(inp.xy, np.int32).reshape(-1))
+        o = np.asarray(inp.offsets, np.int64)
+        voff += list((o[1:] + voff[-1]).astype(np.int64))
+        aoff.append(aoff[-1] + inp.n)
+        wh += [inp.atlas_w, inp.atlas_h]
+    rec = tabi.prep_records(np.concatenate(xy), np.array(voff, np.int32),
+                            np.array(aoff, np.int32), 2, device=dev)
+    N = aoff[-1]
+    aoff_t = torch.tensor(aoff, dtype=torch.int32).to(dev)
+    wh_t = torch.tensor(wh, dtype=torch.int32).to(dev)
+    oxy = torch.empty((N, 2), dtype=torch.int32, device=dev)
+    oor = torch.empty(N, dtype=torch.uint8, device=dev)
+    osc = torch.empty(len(inputs), dtype=torch.float32, device=dev)
+    side = max(max(i.atlas_w, i.atlas_h) for i in inputs)
+    tabi.pack_many_records(rec, aoff_t, wh_t, max(i.n for i in inputs), side, 2, 2, oxy, oor, osc)
+    gxy, gor, gsc = oxy.cpu().numpy(), oor.cpu().numpy(), osc.cpu().numpy()
+    for a, inp in enumerate(inputs):
+        _say("records batch atlas", a, "n =", inp.n)
+        e_xy, e_or, e_sc, _ = orc.pack(inp)
+        assert float(gsc[a]) == e_sc
+        assert np.array_equal(gxy[aoff[a]:aoff[a + 1]], e_xy)
+        assert np.array_equal(gor[aoff[a]:aoff[a + 1]], e_or)
+    # re-pack of the first atlas with three charts replaced by charts of the second
+    base, donor = inputs[0], inputs[1]
+    idx = np.array([1, 4, 7], np.int32)
+    polys = [base.chart(c) for c in range(base.n)]
+    for j, c in enumerate(idx):
+        polys[c] = donor.chart(j)
+    nxy, noff = synth.pack_csr(polys)
+    new_inp = synth.AtlasInput(nxy, noff, base.atlas_w, base.atlas_h, base.padding, base.quality)
+    sub_xy, sub_off = synth.pack_csr([donor.chart(j) for j in range(len(idx))])
+    new = tabi.prep_records(sub_xy, sub_off, np.array([0, len(idx)], np.int32), 2, device=dev)
+    rec0 = rec[:base.n].clone()
+    tabi.splice_records(rec0, idx, new)
+    one = torch.tensor([0, base.n], dtype=torch.int32).to(dev)
+    wh1 = torch.tensor([base.atlas_w, base.atlas_h], dtype=torch.int32).to(dev)
+    oxy1 = torch.empty((base.n, 2), dtype=torch.int32, device=dev)
+    oor1 = torch.empty(base.n, dtype=torch.uint8, device=dev)
+    osc1 = torch.empty(1, dtype=torch.float32, device=dev)
+    tabi.pack_many_records(rec0, one, wh1, base.n, max(base.atlas_w, base.atlas_h), 2, 2, oxy1,
+                           oor1, osc1)
+    e_xy, e_or, e_sc, _ = orc.pack(new_inp)
+    assert float(osc1.cpu().numpy()[0]) == e_sc
+    assert np.array_equal(oxy1.cpu().numpy(), e_xy)
+    assert np.array_equal(oor1.cpu().numpy(), e_or)
