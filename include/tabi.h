@@ -84,10 +84,7 @@ typedef struct {
  *   out_scale[0]: k/64 for the chosen k >= 1 (exact);
  *        0.0f if no scale fits (out_xy filled with -1);
  *       -1.0f if some chart is degenerate: fewer than 3 vertices, zero width
- *             or height, or a coordinate with |x| >= 2^22 (out_xy filled with -1);
- *       -2.0f if a row held more than 256 pairs of charts that share columns
- *             without being neighbours (a limit of the row's shared memory;
- *             out_xy filled with -1).
+ *             or height, or a coordinate with |x| >= 2^22 (out_xy filled with -1).
  * Errors: TABI_EINVAL, TABI_ENOMEM, TABI_EHIP (nothing is written then). */
 int tabi_pack(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
               int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
@@ -124,7 +121,8 @@ int tabi_pack_noalloc(const tabi_charts* charts, int32_t n, int32_t atlas_w, int
  * out_scale = -2.  out_xy / out_orient are indexed by global chart index,
  * out_scale by atlas.  Per atlas the result equals tabi_pack on that atlas
  * alone: every atlas evaluates its candidate scales from the largest down in
- * rounds of 8 per launch and stops at the first round with a success.
+ * rounds (a few scales per atlas per round, the number set by the batched
+ * shape, see tabi_tune_many) and stops at the first round with a success.
  * padding and quality are shared.  Errors as tabi_pack. */
 int tabi_pack_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
                    int32_t count, const int32_t* atlas_wh, int32_t total_charts,

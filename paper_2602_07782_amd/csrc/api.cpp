@@ -106,7 +106,7 @@ struct StageScope {  // brackets one stage's launches with a pair of events
 // ---- work space -------------------------------------------------------------
 struct Layout {
   size_t o_recs, o_srecs, o_keys, o_rank, o_perm, o_ca, o_desc, o_kc, o_cd, o_fl, o_xs, o_ys, o_mir,
-      o_feas, o_rows, o_wdv, o_hdv, o_kslot, o_pcol, o_prow, o_Hs, o_segneed, o_segbase, o_cnt, o_gq, o_gq_cnt, o_live, o_aord, o_arena,
+      o_feas, o_rows, o_wdv, o_hdv, o_kslot, o_pcol, o_prow, o_lrpre, o_Hs, o_segneed, o_segbase, o_cnt, o_gq, o_gq_cnt, o_live, o_aord, o_arena,
       total;
 };
 
@@ -157,6 +157,7 @@ Layout layout(const Params& P) {
   L.o_kslot = take((size_t)P.B * n1 * 4);
   L.o_pcol = take((size_t)P.B * n1 * 4);
   L.o_prow = take((size_t)P.B * n1 * 4);
+  L.o_lrpre = take((size_t)P.B * n1 * 4);
   L.o_Hs = take(n1 * 4);
   L.o_segneed = take((size_t)P.count * P.B * 8);
   L.o_segbase = take((size_t)P.count * P.B * 4);
@@ -193,6 +194,7 @@ Work carve(void* base, const Layout& L) {
   W.kslot = reinterpret_cast<int32_t*>(b + L.o_kslot);
   W.pcol = reinterpret_cast<int32_t*>(b + L.o_pcol);
   W.prow = reinterpret_cast<int32_t*>(b + L.o_prow);
+  W.lrpre = reinterpret_cast<int32_t*>(b + L.o_lrpre);
   W.Hs = reinterpret_cast<int32_t*>(b + L.o_Hs);
   W.segneed = reinterpret_cast<int64_t*>(b + L.o_segneed);
   W.segbase = reinterpret_cast<int32_t*>(b + L.o_segbase);

@@ -34,7 +34,9 @@
 
 namespace tabi {
 
-constexpr int LRCAP = 256;  // pairs per row that share columns without being neighbours
+// pairs per row that share columns without being neighbours, held in shared
+// memory at once; a row with more walks them in chunks of this size
+constexpr int LRCAP = 256;
 constexpr int FWIN = 1024;  // charts per row whose fold data is staged in LDS
 enum { DIR_LR = 0, DIR_RL = 1 };
 
@@ -65,46 +67,95 @@ __device__ inline int32_t run_scan_max(int32_t v, bool head, int32_t carry) {
 
 // CorrectYOffsets (Alg. 1) for one configuration, one wavefront.  Chain links
 // come from the neighbour flags; fl[t] holds the flags of (t-1, t).
-__device__ void correct_offsets(int32_t* y, int cnt, const uint8_t* fl, const int32_t (*lr)[3],
-                                int lrn) {
+// chain_scans closes the chain constraints (a forward and a backward
+// segmented max scan); apply_pairs applies those of non-neighbour pairs
+// lr[0..lrn) once and reports whether any offset moved.
+__device__ void chain_scans(int32_t* y, int cnt, const uint8_t* fl) {
   const int lane = lane_id();
-  for (;;) {
-    int32_t carry = -BIG;
-    for (int t0 = 0; t0 < cnt; t0 += WAVE) {  // y[t] >= y[t-1] where bit0 of fl[t]
-      const int t = t0 + lane;
-      int32_t v = t < cnt ? y[t] : -BIG;
-      const bool head = !(t >= 1 && t < cnt && (fl[t] & 1));
-      v = run_scan_max(v, head, carry);
-      if (t < cnt) y[t] = v;
-      carry = lane63(v);
-    }
-    wsync();
-    carry = -BIG;
-    for (int r0 = 0; r0 < cnt; r0 += WAVE) {  // y[t] >= y[t+1] where bit1 of fl[t+1]
-      const int r = r0 + lane, t = cnt - 1 - r;
-      int32_t v = r < cnt ? y[t] : -BIG;
-      const bool head = !(r >= 1 && r < cnt && (fl[t + 1] & 2));
-      v = run_scan_max(v, head, carry);
-      if (r < cnt) y[t] = v;
-      carry = lane63(v);
-    }
-    wsync();
-    int changed = 0;
-    for (int q0 = 0; q0 < lrn; q0 += WAVE) {
-      const int q = q0 + lane;
-      if (q < lrn) {
-        const int A = lr[q][0], C = lr[q][1], f = lr[q][2];
-        if (C < cnt) {
-          const int32_t ya = y[A], yc = y[C];
-          if ((f & 1) && yc < ya) { atomicMax(&y[C], ya); changed = 1; }
-          if ((f & 2) && ya < yc) { atomicMax(&y[A], yc); changed = 1; }
-        }
+  int32_t carry = -BIG;
+  for (int t0 = 0; t0 < cnt; t0 += WAVE) {  // y[t] >= y[t-1] where bit0 of fl[t]
+    const int t = t0 + lane;
+    int32_t v = t < cnt ? y[t] : -BIG;
+    const bool head = !(t >= 1 && t < cnt && (fl[t] & 1));
+    v = run_scan_max(v, head, carry);
+    if (t < cnt) y[t] = v;
+    carry = lane63(v);
+  }
+  wsync();
+  carry = -BIG;
+  for (int r0 = 0; r0 < cnt; r0 += WAVE) {  // y[t] >= y[t+1] where bit1 of fl[t+1]
+    const int r = r0 + lane, t = cnt - 1 - r;
+    int32_t v = r < cnt ? y[t] : -BIG;
+    const bool head = !(r >= 1 && r < cnt && (fl[t + 1] & 2));
+    v = run_scan_max(v, head, carry);
+    if (r < cnt) y[t] = v;
+    carry = lane63(v);
+  }
+  wsync();
+}
+__device__ bool apply_pairs(int32_t* y, int cnt, const int32_t (*lr)[3], int lrn) {
+  const int lane = lane_id();
+  int changed = 0;
+  for (int q0 = 0; q0 < lrn; q0 += WAVE) {
+    const int q = q0 + lane;
+    if (q < lrn) {
+      const int A = lr[q][0], C = lr[q][1], f = lr[q][2];
+      if (C < cnt) {
+        const int32_t ya = y[A], yc = y[C];
+        if ((f & 1) && yc < ya) { atomicMax(&y[C], ya); changed = 1; }
+        if ((f & 2) && ya < yc) { atomicMax(&y[A], yc); changed = 1; }
       }
     }
-    const bool any = ballot64(changed) != 0;
-    wsync();
-    if (!any) break;
   }
+  const bool any = ballot64(changed) != 0;
+  wsync();
+  return any;
+}
+__device__ void correct_offsets(int32_t* y, int cnt, const uint8_t* fl, const int32_t (*lr)[3],
+                                int lrn) {
+  do {
+    chain_scans(y, cnt, fl);
+  } while (apply_pairs(y, cnt, lr, lrn));
+}
+
+// Non-neighbour partners of each candidate A of a compacted row: the charts
+// C >= A + 2 whose offset lies within A's grown width (offsets increase, so
+// they are consecutive).  Writes the exclusive prefix of their counts to
+// pre[0..cand) and returns the total (whole workgroup; red: PACK_WAVES ints).
+template <int PACK_NT>
+__device__ int pair_prefix(const int32_t* Xon, const int32_t* Xoff, int cand, int32_t* pre,
+                           int32_t* red) {
+  constexpr int PACK_WAVES = PACK_NT / WAVE;
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+  auto count = [&](int A) {
+    const int lim = Xon[A] + (Xoff[A + 1] - Xoff[A]);
+    int lo = A + 2, hi = cand;  // first C >= A + 2 with Xon[C] >= lim
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (Xon[mid] < lim) lo = mid + 1; else hi = mid;
+    }
+    return max(0, lo - (A + 2));
+  };
+  const int per = (cand + PACK_NT - 1) / PACK_NT;
+  const int a0 = min(cand, tid * per), a1 = min(cand, a0 + per);
+  int sum = 0;
+  for (int A = a0; A < a1; ++A) sum += count(A);
+  const int incl = wave_incl_sum(sum);
+  __syncthreads();
+  if (lane == WAVE - 1) red[wv] = incl;
+  __syncthreads();
+  int base = 0, total = 0;
+  for (int i = 0; i < PACK_WAVES; ++i) {
+    if (i < wv) base += red[i];
+    total += red[i];
+  }
+  int run = base + incl - sum;
+  for (int A = a0; A < a1; ++A) {
+    pre[A] = run;
+    run += count(A);
+  }
+  __syncthreads();  // pre[] written by every thread before it is searched
+  return total;
 }
 
 template <int PACK_WAVES>
@@ -236,6 +287,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   const int32_t* wdv = w.wdv + slot;
   const int32_t* hdv = w.hdv + slot;
   const int32_t* prowv = w.prow + slot;
+  int32_t* lrpre = w.lrpre + slot;
   const int32_t sbase = w.segbase[(size_t)a * P.B + s];  // -1: profiles not stored
   const int32_t* Hs = w.Hs + d.c0;
   int32_t* xs = w.xs + slot;
@@ -423,8 +475,10 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       }
     }
     __syncthreads();
-    const int lrn = min(s_lrn, LRCAP);
-    if (s_lrover) { feasible = -2; break; }
+    // more pairs than the shared list holds: none is swept with the push,
+    // the correction walks them in chunks
+    const bool lrover = s_lrover != 0;
+    const int lrn = lrover ? 0 : s_lrn;
     // ---- 4. push every configuration against the committed frontline; the
     // last wavefronts (at most a quarter) sweep the non-neighbour pairs at
     // the same time
@@ -484,11 +538,53 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     }
     __syncthreads();
     // ---- 5. correction, one wavefront per compacted configuration
-    if (wv < ncfg) {
-      const int cnt = wv == 0 ? c_cnt[0] : wv == 1 ? c_cnt[1] : wv == 2 ? c_cnt[2] : c_cnt[3];
-      const int hc = wv == 0 ? c_hc[0] : wv == 1 ? c_hc[1] : wv == 2 ? c_hc[2] : c_hc[3];
-      const int yo = wv == 0 ? yofs[0] : wv == 1 ? yofs[1] : wv == 2 ? yofs[2] : yofs[3];
-      if (hc) correct_offsets(Yb + yo, cnt, flv + rs, s_lr, lrn);
+    const int my_cnt = wv == 0 ? c_cnt[0] : wv == 1 ? c_cnt[1] : wv == 2 ? c_cnt[2] : c_cnt[3];
+    const int my_hc = wv < ncfg && (wv == 0 ? c_hc[0] : wv == 1 ? c_hc[1] : wv == 2 ? c_hc[2] : c_hc[3]);
+    int32_t* my_y = Yb + (wv == 0 ? yofs[0] : wv == 1 ? yofs[1] : wv == 2 ? yofs[2] : yofs[3]);
+    if (!lrover) {
+      if (my_hc) correct_offsets(my_y, my_cnt, flv + rs, s_lr, lrn);
+    } else {
+      // the pairs' flags depend only on the compacted offsets, the same in
+      // every configuration; each pass recomputes them chunk by chunk and
+      // applies them, until a whole pass moves no offset
+      const int total = pair_prefix<PACK_NT>(Xon, Xoff, cand, lrpre + rs, s_red);
+      for (;;) {
+        if (my_hc) chain_scans(my_y, my_cnt, flv + rs);
+        int moved = 0;
+        for (int q0 = 0; q0 < total; q0 += LRCAP) {
+          const int m = min(LRCAP, total - q0);
+          __syncthreads();  // the previous chunk is no longer read
+          for (int t = tid; t < m; t += PACK_NT) {
+            const int q = q0 + t;
+            int lo = 0, hi = cand - 1;  // last A with pre[A] <= q
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (lrpre[rs + mid] <= q) lo = mid; else hi = mid - 1;
+            }
+            s_lr[t][0] = lo;
+            s_lr[t][1] = lo + 2 + (q - lrpre[rs + lo]);
+          }
+          __syncthreads();
+          for (int q = wv; q < m; q += PACK_WAVES) {
+            const int A = s_lr[q][0], C = s_lr[q][1];
+            const int wdA = Xoff[A + 1] - Xoff[A];
+            const int dd = Xon[C] - Xon[A];
+            int f;
+            if (prof) {
+              f = pair_flags_at(pair_rows_meet(w.arena + sbase + prowv[rs + A], hdv[rs + A],
+                                               w.arena + sbase + prowv[rs + C], hdv[rs + C], wdA),
+                                wdA, dd);
+            } else {
+              f = pair_flags_at(pair_records_sweep<2>(KV(rs + A), ch[rs + A], KV(rs + C),
+                                                      ch[rs + C], K, k, p), wdA, dd);
+            }
+            if (lane == 0) s_lr[q][2] = f;
+          }
+          __syncthreads();
+          if (my_hc && apply_pairs(my_y, my_cnt, s_lr, m)) moved = 1;
+        }
+        if (!__syncthreads_or(moved)) break;
+      }
     }
     // the scores read the corrected offsets (without compaction nothing was
     // corrected and the barrier after the push suffices)

@@ -63,6 +63,7 @@ struct Work {
   int32_t* pcol;        // [B][N] first grown column of the chart within its segment
   int32_t* prow;        // [B][N] first grown row of the chart within its segment
   int32_t* Hs;          // [N] unscaled height (Q8) by sorted position
+  int32_t* lrpre;       // [B][N] rows with many non-neighbour pairs: prefix of their counts
   int64_t* segneed;     // [count][B] arena words of the (atlas, slot) segment
   int32_t* segbase;     // [count][B] arena word where the segment starts, -1: not stored
   int32_t* cnt;         // [count] fold-and-push workgroups of the atlas done this round

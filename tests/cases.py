@@ -21,3 +21,24 @@ def small_input(seed, n=None, W=None, p=None, q=None):
 
 def with_quality(inp, q):
     return synth.AtlasInput(inp.xy, inp.offsets, inp.atlas_w, inp.atlas_h, inp.padding, q)
+
+
+def many_pairs_input(quality=2, slivers=400):
+    """A row with more than 256 pairs of charts that share columns without
+    being neighbours: a chart shaped like a T on its side (a full-height bar
+    on the left, a bar to the right across the middle, empty above and below
+    it on the right) followed by `slivers` one-texel-wide rectangles short
+    enough to slide into its empty top-right part.  In a 1024^2 atlas with
+    padding 1, at scale 64/64 the first sliver compacts under the T and every
+    sliver starting within the T's width shares columns with it."""
+    Q = 256
+    Wl, Hl, wv, ym, hb = 700, 800, 100, 300, 60  # texels; the empty part above the bar is 300 tall
+    hs = 200 if quality == 2 else 150            # below the slice that meets the bar
+    tee = np.array([(0, 0), (wv, 0), (wv, ym), (Wl, ym), (Wl, ym + hb), (wv, ym + hb), (wv, Hl),
+                    (0, Hl)], np.int64) * Q
+    polys = [tee]
+    for i in range(slivers):
+        x0 = 2000 + 3 * i  # anywhere: positions come from the packer
+        polys.append(np.array([(x0, 0), (x0 + 1, 0), (x0 + 1, hs), (x0, hs)], np.int64) * Q)
+    xy, off = synth.pack_csr(polys)
+    return synth.AtlasInput(xy, off, 1024, 1024, 1, quality)

@@ -12,7 +12,7 @@ import sys
 import numpy as np
 import pytest
 
-from cases import small_input, with_quality
+from cases import many_pairs_input, small_input, with_quality
 from paper_2602_07782_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -209,6 +209,24 @@ def test_edge_cases(tabi, orc):
     for bad in [(0, 64, 1, 2), (64, 64, -1, 2), (64, 64, 1, 3), (16384, 64, 1, 2)]:
         with pytest.raises(tabi.TabiError):
             tabi.pack(two.xy, two.offsets, *bad)
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_row_with_more_than_256_non_neighbour_pairs(tabi, orc, q):
+    """A row whose non-neighbour pairs exceed the shared-memory list (the
+    correction walks them in chunks): the scale-64 fold-and-push and the
+    whole pack equal the oracle."""
+    inp = many_pairs_input(q)
+    _say("many non-neighbour pairs, quality", q, "n =", inp.n)
+    for k in (64, 60):
+        xy, ori, feas, rows = tabi.debug_feasible(inp.xy, inp.offsets, inp.atlas_w, inp.atlas_h,
+                                                  inp.padding, inp.quality, k)
+        ok, oxy, oori, orows = orc.feasible(inp, k)
+        assert int(_np(feas)[0]) == int(ok), k
+        assert int(_np(rows)[0]) == orows, k
+        assert np.array_equal(_np(xy), oxy), k
+        assert np.array_equal(_np(ori), oori), k
+    assert_pack_equal(tabi, orc, inp, f"many pairs q{q}")
 
 
 def test_repeat_is_bitwise_identical(tabi):

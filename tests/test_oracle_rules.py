@@ -366,3 +366,28 @@ def test_sort_breaks_height_ties_by_width(orc):
     xy, off = synth.pack_csr(P)
     perm, _ = orc.order(synth.AtlasInput(xy, off, 64, 64, 0, 2))
     assert list(perm) == [4, 1, 3, 2, 0]
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_many_pairs_case_has_more_than_256_in_one_row(orc, q):
+    """The input built to exceed the fold-and-push kernel's shared pair list
+    really does: at scale 64/64 the oracle's compacting distances place more
+    than 256 charts of the first row within the T's grown width, none of them
+    its neighbour; and the oracle packs it at that scale."""
+    from cases import many_pairs_input
+    inp = many_pairs_input(q)
+    perm, _ = orc.order(inp)
+    assert perm[0] == 0  # the T is the tallest
+    cd, _ = orc.pairs(inp, 64)
+    wd = []
+    for c in perm:
+        pts = inp.chart(int(c))
+        ext = pts.max(0) - pts.min(0)
+        wd.append(int(-(-64 * int(min(ext)) // 16384)) + inp.padding)
+    X = [0]
+    for c in range(1, inp.n):
+        X.append(X[-1] + wd[c - 1] - int(cd[c]))
+    in_row = [c for c in range(inp.n) if X[c] + wd[c] <= inp.atlas_w + inp.padding]
+    pairs = sum(1 for C in in_row if C >= 2 and X[C] - X[0] < wd[0])
+    assert pairs > 256, pairs
+    assert orc.pack(inp)[3] == 64
