@@ -60,6 +60,12 @@ def lib():
         L.tabi_oracle_pairs.argtypes = [I32P, I32P, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, I32P, U8P]
         L.orc_prep_chart.argtypes = [I32P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(OrcChart)]
+        L.orc_prep_chart_ex.argtypes = [I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(OrcChart)]
+        L.tabi_oracle_pack_method.argtypes = [I32P, I32P, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.c_int32, I32P, U8P,
+                                              ctypes.POINTER(ctypes.c_float), I32P]
         L.orc_profiles.argtypes = [ctypes.POINTER(OrcChart), ctypes.c_int32, I32P, I32P,
                                    I32P, I32P, I32P, I32P]
         L.orc_row_proxies.argtypes = [ctypes.POINTER(OrcChart), ctypes.c_int32, I32P, I32P, I32P,
@@ -94,6 +100,34 @@ def pack(inp):
     if rc != 0:
         raise ValueError(f"oracle rejected the arguments (rc={rc})")
     return oxy[:2 * n].reshape(n, 2), ori[:n], float(sc.value), int(kk.value)
+
+
+FULL, TIGHT_ONLY, BALANCED_ONLY = 0, 1, 2
+
+
+def pack_method(inp, K, topt, variant):
+    """Whole pack with the method's knobs (K slices, t_opt percent or -1 for
+    the paper's setting, variant) -> as pack()."""
+    n = inp.n
+    xy, off = _c(inp.xy, np.int32), _c(inp.offsets, np.int32)
+    oxy = np.zeros(max(2 * n, 1), np.int32)
+    ori = np.zeros(max(n, 1), np.uint8)
+    sc = ctypes.c_float(0)
+    kk = ctypes.c_int32(0)
+    rc = lib().tabi_oracle_pack_method(_p32(xy), _p32(off), n, inp.atlas_w, inp.atlas_h,
+                                       inp.padding, int(K), int(topt), int(variant), _p32(oxy),
+                                       ori.ctypes.data_as(U8P), ctypes.byref(sc),
+                                       ctypes.byref(kk))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the arguments (rc={rc})")
+    return oxy[:2 * n].reshape(n, 2), ori[:n], float(sc.value), int(kk.value)
+
+
+def prep_chart_ex(verts_q8, K, use_obb):
+    v = _c(verts_q8, np.int32).reshape(-1)
+    ch = OrcChart()
+    lib().orc_prep_chart_ex(_p32(v), int(v.shape[0] // 2), int(K), int(use_obb), ctypes.byref(ch))
+    return ch
 
 
 def feasible(inp, k):

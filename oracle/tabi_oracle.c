@@ -63,6 +63,30 @@ void orc_quality(int32_t quality, int32_t n, int32_t* K, int32_t* topt) {
   else { *K = 10; *topt = (n > 10000) ? 1 : 0; }
 }
 
+/* The method's knobs (Sec. 5 ablations; App. D, local-AABB count and t_opt
+ * tables): K local AABBs per axis, t_opt in percent of the atlas height
+ * (negative: the paper's setting, 0 up to 10,000 charts and 1 above), and
+ * the variant:
+ *   ORC_FULL           tightness and balance (the method);
+ *   ORC_TIGHT_ONLY     tightness without balanced folding: every row is
+ *                      folded at the full atlas width with compaction, in the
+ *                      fixed alternation of one left-to-right row to two
+ *                      right-to-left rows, with no knees and no per-row
+ *                      choice of direction or compaction;
+ *   ORC_BALANCED_ONLY  balanced folding without tightening: the charts'
+ *                      boxes stand in for the proxies (one slice per axis, no
+ *                      OBB), so nothing compacts and no chart is reflected. */
+static int method_resolve(int K, int topt, int variant, int n, int* Kout, int* topt_out,
+                          int* use_obb) {
+  if (variant < ORC_FULL || variant > ORC_BALANCED_ONLY) return -1;
+  if (variant == ORC_BALANCED_ONLY) K = 1;
+  if (K < 1 || K > ORC_KMAX || topt > 100) return -1;
+  *Kout = K;
+  *topt_out = topt < 0 ? ((n > 10000) ? 1 : 0) : topt;
+  *use_obb = variant != ORC_BALANCED_ONLY;
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* The 8 box directions m*pi/16, m = 0..7 (App. A: eight evenly spaced
  * rotations in [0, 7pi/16]), as integer vectors 2^14 (cos, sin) rounded.   */
@@ -100,7 +124,7 @@ static void slice_range(const int64_t* A, const int64_t* B, int nv, int64_t E, i
   *hi = h;
 }
 
-int orc_prep_chart(const int32_t* xy, int32_t nv, int32_t K, orc_chart* ch) {
+int orc_prep_chart_ex(const int32_t* xy, int32_t nv, int32_t K, int32_t use_obb, orc_chart* ch) {
   memset(ch, 0, sizeof(*ch));
   ch->K = K;
   if (nv < 3) return 0;
@@ -216,6 +240,11 @@ int orc_prep_chart(const int32_t* xy, int32_t nv, int32_t K, orc_chart* ch) {
       bC = C; bS = S; ba = a; bb = b; be = e; bf = f;
     }
   }
+  if (!use_obb) {  /* the chart's box alone: the axis-aligned direction */
+    best = 0;
+    direction(0, &bC, &bS);
+    ba = 0; bb = bC * W; be = 0; bf = bC * H;
+  }
   ch->obb_m = best;
   ch->obb = best != 0;
   ch->C = bC; ch->S = bS; ch->a = ba; ch->b = bb; ch->e = be; ch->f = bf;
@@ -223,6 +252,10 @@ int orc_prep_chart(const int32_t* xy, int32_t nv, int32_t K, orc_chart* ch) {
   free(v);
   ch->valid = 1;
   return 1;
+}
+
+int orc_prep_chart(const int32_t* xy, int32_t nv, int32_t K, orc_chart* ch) {
+  return orc_prep_chart_ex(xy, nv, K, 1, ch);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -448,6 +481,7 @@ static int area_bound(const orc_chart* ch, int n, int Wa, int Ha) {
 /* Per-scale data: dilated profiles, compacting distances.                   */
 typedef struct {
   int n, Wd, Hd, Wa, Ha, p, topt;
+  int static_rows;                   /* tight-only: every row folded like a tail row */
   int32_t *wd, *hd, *h;
   int64_t* Hq;                       /* unscaled Q8 heights, for knees */
   int32_t **topd, **botd;
@@ -473,7 +507,7 @@ static void free_kdata(kdata* D) {
  * charts, none along the 4 atlas edges).                                     */
 static void build_kdata(kdata* D, const orc_chart* ch, const int* perm, int n, int k,
                         int Wa, int Ha, int p, int topt) {
-  D->n = n; D->Wa = Wa; D->Ha = Ha; D->p = p; D->topt = topt;
+  D->n = n; D->Wa = Wa; D->Ha = Ha; D->p = p; D->topt = topt; D->static_rows = 0;
   D->Wd = Wa + p; D->Hd = Ha + p;
   D->wd = calloc(n + 1, sizeof(int32_t)); D->hd = calloc(n + 1, sizeof(int32_t));
   D->h = calloc(n + 1, sizeof(int32_t)); D->Hq = calloc(n + 1, sizeof(int64_t));
@@ -761,7 +795,7 @@ static int pack_scale(const kdata* D, int32_t* xs, int32_t* ys, uint8_t* mir, in
   config full[2], kc[2];
   for (int d = 0; d < 2; ++d) { config_alloc(&full[d], n, Wd); config_alloc(&kc[d], n, Wd); }
   knee_t kn = {0, 0, 0, 0};
-  int tail = 0, trow = 0, rs = 0, rows = 0, ok = 1;
+  int tail = D->static_rows, trow = 0, rs = 0, rows = 0, ok = 1;
   while (rs < n) {
     if (kn.active) update_knee(&kn, F, Wd);
     /* t_opt (Sec. 4.4): once no knee is pending and the row's tallest chart
@@ -845,11 +879,12 @@ static int check_args(const int32_t* xy, const int32_t* offsets, int32_t n, int3
   return 0;
 }
 
-static int prep_all(const int32_t* xy, const int32_t* offsets, int n, int K, orc_chart* ch) {
+static int prep_all(const int32_t* xy, const int32_t* offsets, int n, int K, int use_obb,
+                    orc_chart* ch) {
   int ok = 1;
   for (int c = 0; c < n; ++c) {
     int nv = offsets[c + 1] - offsets[c];
-    if (!orc_prep_chart(xy + 2 * (int64_t)offsets[c], nv, K, &ch[c])) ok = 0;
+    if (!orc_prep_chart_ex(xy + 2 * (int64_t)offsets[c], nv, K, use_obb, &ch[c])) ok = 0;
   }
   return ok;
 }
@@ -860,16 +895,15 @@ static void sort_charts(const orc_chart* ch, int n, int* perm) {
   qsort(perm, n, sizeof(int), cmp_order);
 }
 
-int tabi_oracle_pack(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
-                     int32_t Ha, int32_t p, int32_t q, int32_t* out_xy, uint8_t* out_orient,
-                     float* out_scale, int32_t* out_k) {
-  if (check_args(xy, offsets, n, Wa, Ha, p, q)) return -1;
-  int K, topt;
-  orc_quality(q, n, &K, &topt);
+/* Whole pack with the given knobs (K slices, t_opt percent, OBB used,
+ * static rows). */
+static int pack_with(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa, int32_t Ha,
+                     int32_t p, int K, int topt, int use_obb, int static_rows, int32_t* out_xy,
+                     uint8_t* out_orient, float* out_scale, int32_t* out_k) {
   if (n == 0) { *out_scale = 1.0f; if (out_k) *out_k = 64; return 0; }
   orc_chart* ch = calloc(n, sizeof(orc_chart));
   for (int c = 0; c < n; ++c) { out_xy[2 * c] = -1; out_xy[2 * c + 1] = -1; out_orient[c] = 0; }
-  if (!prep_all(xy, offsets, n, K, ch)) {
+  if (!prep_all(xy, offsets, n, K, use_obb, ch)) {
     free(ch);
     *out_scale = -1.0f;
     if (out_k) *out_k = -1;
@@ -886,6 +920,7 @@ int tabi_oracle_pack(const int32_t* xy, const int32_t* offsets, int32_t n, int32
   for (int k = khi; k >= 1; --k) {
     kdata D;
     build_kdata(&D, ch, perm, n, k, Wa, Ha, p, topt);
+    D.static_rows = static_rows;
     int ok = pack_scale(&D, xs, ys, mir, NULL);
     free_kdata(&D);
     if (ok) { kstar = k; break; }
@@ -904,6 +939,27 @@ int tabi_oracle_pack(const int32_t* xy, const int32_t* offsets, int32_t n, int32
   return 0;
 }
 
+int tabi_oracle_pack(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                     int32_t Ha, int32_t p, int32_t q, int32_t* out_xy, uint8_t* out_orient,
+                     float* out_scale, int32_t* out_k) {
+  if (check_args(xy, offsets, n, Wa, Ha, p, q)) return -1;
+  int K, topt;
+  orc_quality(q, n, &K, &topt);
+  return pack_with(xy, offsets, n, Wa, Ha, p, K, topt, 1, 0, out_xy, out_orient, out_scale, out_k);
+}
+
+int tabi_oracle_pack_method(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                            int32_t Ha, int32_t p, int32_t K, int32_t topt, int32_t variant,
+                            int32_t* out_xy, uint8_t* out_orient, float* out_scale,
+                            int32_t* out_k) {
+  int Kr, tr, use_obb;
+  if (check_args(xy, offsets, n, Wa, Ha, p, 0) || method_resolve(K, topt, variant, n, &Kr, &tr,
+                                                                 &use_obb))
+    return -1;
+  return pack_with(xy, offsets, n, Wa, Ha, p, Kr, tr, use_obb, variant == ORC_TIGHT_ONLY, out_xy,
+                   out_orient, out_scale, out_k);
+}
+
 int tabi_oracle_feasible(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
                          int32_t Ha, int32_t p, int32_t q, int32_t k, int32_t* out_xy,
                          uint8_t* out_orient, int32_t* rows_out) {
@@ -912,7 +968,7 @@ int tabi_oracle_feasible(const int32_t* xy, const int32_t* offsets, int32_t n, i
   orc_quality(q, n, &K, &topt);
   if (n == 0) return 1;
   orc_chart* ch = calloc(n, sizeof(orc_chart));
-  if (!prep_all(xy, offsets, n, K, ch)) { free(ch); return -1; }
+  if (!prep_all(xy, offsets, n, K, 1, ch)) { free(ch); return -1; }
   int* perm = malloc(sizeof(int) * n);
   sort_charts(ch, n, perm);
   int32_t* xs = malloc(sizeof(int32_t) * n);
@@ -940,7 +996,7 @@ int tabi_oracle_order(const int32_t* xy, const int32_t* offsets, int32_t n, int3
   int K, topt;
   orc_quality(q, n, &K, &topt);
   orc_chart* ch = calloc(n > 0 ? n : 1, sizeof(orc_chart));
-  if (!prep_all(xy, offsets, n, K, ch)) { free(ch); return -1; }
+  if (!prep_all(xy, offsets, n, K, 1, ch)) { free(ch); return -1; }
   int* perm = malloc(sizeof(int) * (n > 0 ? n : 1));
   sort_charts(ch, n, perm);
   for (int t = 0; t < n; ++t) perm_out[t] = perm[t];
@@ -956,7 +1012,7 @@ int tabi_oracle_pairs(const int32_t* xy, const int32_t* offsets, int32_t n, int3
   orc_quality(q, n, &K, &topt);
   if (n == 0) return 0;
   orc_chart* ch = calloc(n, sizeof(orc_chart));
-  if (!prep_all(xy, offsets, n, K, ch)) { free(ch); return -1; }
+  if (!prep_all(xy, offsets, n, K, 1, ch)) { free(ch); return -1; }
   int* perm = malloc(sizeof(int) * n);
   sort_charts(ch, n, perm);
   kdata D;

@@ -52,8 +52,25 @@ void orc_profiles(const orc_chart* ch, int32_t k, int32_t* w, int32_t* h,
 void orc_row_proxies(const orc_chart* ch, int32_t k, int32_t* h, int32_t* la, int32_t* ra,
                      int32_t* lo, int32_t* ro);
 
+/* Proxy construction with K slices (1..10); use_obb 0 keeps the chart's
+ * axis-aligned box as its second proxy. */
+int orc_prep_chart_ex(const int32_t* xy, int32_t nverts, int32_t K, int32_t use_obb,
+                      orc_chart* out);
+
 /* Quality preset -> slices K and t_opt percent for a set of n charts. */
 void orc_quality(int32_t quality, int32_t n, int32_t* K, int32_t* topt);
+
+/* Variants of the method (Sec. 5 ablations). */
+enum { ORC_FULL = 0, ORC_TIGHT_ONLY = 1, ORC_BALANCED_ONLY = 2 };
+
+/* Whole pack with the method's knobs: K local AABBs per axis (1..10; the
+ * balanced-only variant uses 1), t_opt percent (< 0: the paper's setting,
+ * 0 up to 10,000 charts, 1 above), variant ORC_*.  Outputs as
+ * tabi_oracle_pack; -1 on invalid arguments. */
+int tabi_oracle_pack_method(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                            int32_t Ha, int32_t p, int32_t K, int32_t topt, int32_t variant,
+                            int32_t* out_xy, uint8_t* out_orient, float* out_scale,
+                            int32_t* out_k);
 
 /* Whole pack.  Returns 0 on success, -1 on invalid arguments.
  * out_xy[2n]: texel (X,Y) of each chart's box top-left, out_orient[n]: bit0 turn,
