@@ -90,6 +90,31 @@ int tabi_pack(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atl
               int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
               float* out_scale, tabi_stream_t stream);
 
+/* The method's knobs (Sec. 5 "Ablations"; App. D, local-AABB count and t_opt
+ * tables), for the ablation variants and sweeps.  The quality presets are
+ * {2, 5, FULL}, {5, 2, FULL} and {10, -1, FULL}.
+ *   slices:        local AABBs per axis: 1, 2, 5 or 10 (Sec. 4.1.1)
+ *   topt_percent:  t_opt of Sec. 4.4 in percent of the atlas height, 0..100;
+ *                  -1: the paper's setting, 0 up to 10,000 charts and 1 above
+ *   variant:       TABI_FULL: the method;
+ *                  TABI_TIGHT_ONLY: tightness without balanced folding (every
+ *                  row folded at the atlas width with compaction, one
+ *                  left-to-right row to two right-to-left rows, no knees, no
+ *                  per-row choices);
+ *                  TABI_BALANCED_ONLY: balanced folding without tightening
+ *                  (the charts' boxes as proxies: one slice per axis whatever
+ *                  `slices` says, no OBB, so no compaction and no reflection). */
+enum { TABI_FULL = 0, TABI_TIGHT_ONLY = 1, TABI_BALANCED_ONLY = 2 };
+typedef struct {
+  int32_t slices, topt_percent, variant;
+} tabi_method;
+
+/* tabi_pack with the method's knobs instead of a quality preset.
+ * TABI_EINVAL for knobs outside the ranges above. */
+int tabi_pack_method(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+                     int32_t padding, const tabi_method* method, int32_t* out_xy,
+                     uint8_t* out_orient, float* out_scale, tabi_stream_t stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): tabi_pack
  * with the same arguments, outputs and device-detected conditions, whose work
@@ -129,6 +154,15 @@ int tabi_pack_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t
                    int32_t max_charts, int32_t max_side, int32_t padding, int32_t quality,
                    int32_t* out_xy, uint8_t* out_orient, float* out_scale,
                    tabi_stream_t stream);
+
+/* tabi_pack_many with the method's knobs (shared by the batch) instead of a
+ * quality preset; batched shapes are those tuned for the preset with the
+ * nearest slice count. */
+int tabi_pack_many_method(const int32_t* xy, const int32_t* vert_offsets,
+                          const int32_t* atlas_offsets, int32_t count, const int32_t* atlas_wh,
+                          int32_t total_charts, int32_t max_charts, int32_t max_side,
+                          int32_t padding, const tabi_method* method, int32_t* out_xy,
+                          uint8_t* out_orient, float* out_scale, tabi_stream_t stream);
 
 /* Bytes of device work space tabi_pack_many_ws needs for this batch shape
  * (host only; -1 for a bad shape). */

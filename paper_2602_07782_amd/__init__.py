@@ -32,6 +32,14 @@ class Charts(ctypes.Structure):
                 ("total_verts", ctypes.c_int32)]
 
 
+class Method(ctypes.Structure):
+    _fields_ = [("slices", ctypes.c_int32), ("topt_percent", ctypes.c_int32),
+                ("variant", ctypes.c_int32)]
+
+
+FULL, TIGHT_ONLY, BALANCED_ONLY = 0, 1, 2
+
+
 class CtxConfig(ctypes.Structure):
     _fields_ = [("quality", ctypes.c_int32), ("padding", ctypes.c_int32),
                 ("streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
@@ -46,7 +54,8 @@ class Done(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ["tabi_pack", "tabi_pack_noalloc", "tabi_pack_many", "tabi_pack_many_ws", "tabi_pack_many_workspace_bytes",
+EXPORTS = ["tabi_pack", "tabi_pack_method", "tabi_pack_many_method", "tabi_pack_noalloc",
+           "tabi_pack_many", "tabi_pack_many_ws", "tabi_pack_many_workspace_bytes",
            "tabi_record_bytes", "tabi_prep_records", "tabi_splice_records",
            "tabi_pack_many_records", "tabi_debug_order", "tabi_debug_pairs",
            "tabi_debug_feasible", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
@@ -70,6 +79,10 @@ def lib():
         L.tabi_pack.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, i32, vp, vp, vp, vp]
         L.tabi_pack_noalloc.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, i32, vp, vp,
                                         vp, vp]
+        L.tabi_pack_method.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32,
+                                       ctypes.POINTER(Method), vp, vp, vp, vp]
+        L.tabi_pack_many_method.argtypes = [vp, vp, vp, i32, vp, i32, i32, i32, i32,
+                                            ctypes.POINTER(Method), vp, vp, vp, vp]
         L.tabi_pack_many.argtypes = [vp, vp, vp, i32, vp, i32, i32, i32, i32, i32, vp, vp, vp, vp]
         L.tabi_pack_many_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32]
         L.tabi_pack_many_workspace_bytes.restype = ctypes.c_int64
@@ -164,6 +177,25 @@ def pack(xy, offsets, atlas_w, atlas_h, padding, quality, stream=None, device="c
     return out_xy, out_or, out_sc
 
 
+def pack_method(xy, offsets, atlas_w, atlas_h, padding, slices, topt_percent, variant,
+                stream=None, device="cuda"):
+    """tabi_pack_method: the method's knobs (local AABBs per axis, t_opt in
+    percent or -1 for the paper's setting, variant FULL / TIGHT_ONLY /
+    BALANCED_ONLY) instead of a quality preset.  Returns as pack()."""
+    torch = _torch()
+    xy = _dev_i32(xy, device)
+    offsets = _dev_i32(offsets, device)
+    ch, n = _charts(xy, offsets)
+    out_xy = torch.empty((max(n, 0), 2), dtype=torch.int32, device=xy.device)
+    out_or = torch.empty(max(n, 0), dtype=torch.uint8, device=xy.device)
+    out_sc = torch.empty(1, dtype=torch.float32, device=xy.device)
+    m = Method(int(slices), int(topt_percent), int(variant))
+    _check(lib().tabi_pack_method(ctypes.byref(ch), n, int(atlas_w), int(atlas_h), int(padding),
+                                  ctypes.byref(m), _ptr(out_xy), _ptr(out_or), _ptr(out_sc),
+                                  _stream(stream)))
+    return out_xy, out_or, out_sc
+
+
 def pack_noalloc_into(xy, offsets, n, atlas_w, atlas_h, padding, quality, out_xy, out_orient,
                       out_scale, stream=None):
     """tabi_pack_noalloc on caller tensors (device int32 xy / offsets, outputs
@@ -249,6 +281,17 @@ class Batch:
                                            _stream(stream)))
         else:
             _check(lib().tabi_pack_many(*args, _stream(stream)))
+        return self.out_xy, self.out_orient, self.out_scale
+
+    def run_method(self, slices, topt_percent, variant, stream=None):
+        """Enqueue tabi_pack_many_method: the batch with the method's knobs."""
+        m = Method(int(slices), int(topt_percent), int(variant))
+        _check(lib().tabi_pack_many_method(_ptr(self.xy), _ptr(self.voff), _ptr(self.aoff),
+                                           self.count, _ptr(self.wh), self.total,
+                                           self.max_charts, self.max_side, self.padding,
+                                           ctypes.byref(m), _ptr(self.out_xy),
+                                           _ptr(self.out_orient), _ptr(self.out_scale),
+                                           _stream(stream)))
         return self.out_xy, self.out_orient, self.out_scale
 
 

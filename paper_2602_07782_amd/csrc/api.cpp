@@ -22,7 +22,37 @@ int hip_fail(hipError_t e) {
   return TABI_EHIP;
 }
 
-int slices_for_quality(int q) { return q == 0 ? 2 : (q == 1 ? 5 : 10); }
+// A method code names the method's knobs (Sec. 5 ablations): the quality
+// presets 0, 1, 2, or a packed custom setting (bit 24 set) of the local-AABB
+// count (bits 4-7), t_opt + 1 (bits 8-15) and variant (bits 16-19).
+constexpr int32_t kCustom = 1 << 24;
+struct Method {
+  int K, topt, variant;  // topt < 0: the paper's setting, per atlas
+  int cls;               // 0..2: the preset whose tuned batched shapes it uses
+};
+bool code_ok(int32_t code) {
+  if (code >= 0 && code <= 2) return true;
+  if ((code >> 24) != 1) return false;
+  const int K = (code >> 4) & 0xf, topt = ((code >> 8) & 0xff) - 1, v = (code >> 16) & 0xf;
+  return (K == 1 || K == 2 || K == 5 || K == 10) && topt >= -1 && topt <= 100 && v <= 2;
+}
+Method decode_method(int32_t code) {
+  if (code >= 0 && code <= 2)
+    return {code == 0 ? 2 : (code == 1 ? 5 : 10), code == 0 ? 5 : (code == 1 ? 2 : -1),
+            TABI_FULL, code};
+  const int K = (code >> 4) & 0xf, topt = ((code >> 8) & 0xff) - 1, v = (code >> 16) & 0xf;
+  const int Kr = v == TABI_BALANCED_ONLY ? 1 : K;  // balanced-only packs the boxes
+  return {Kr, topt, v, Kr >= 10 ? 2 : (Kr >= 5 ? 1 : 0)};
+}
+int32_t encode_method(const tabi_method& m) {
+  return kCustom | ((m.slices & 0xf) << 4) | (((m.topt_percent + 1) & 0xff) << 8) |
+         ((m.variant & 0xf) << 16);
+}
+bool method_ok(const tabi_method* m) {
+  return m && (m->slices == 1 || m->slices == 2 || m->slices == 5 || m->slices == 10) &&
+         m->topt_percent >= -1 && m->topt_percent <= 100 && m->variant >= TABI_FULL &&
+         m->variant <= TABI_BALANCED_ONLY;
+}
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -216,11 +246,14 @@ struct Job {
 };
 
 Params make_params(int count, int N, int q, int p, int B, int fixed_k, int nmax, int Wdmax) {
+  const Method m = decode_method(q);
   Params P{};
   P.count = count;
   P.N = N;
-  P.K = slices_for_quality(q);
-  P.q = q;
+  P.K = m.K;
+  P.q = m.cls;
+  P.topt = m.topt;
+  P.variant = m.variant;
   P.p = p;
   P.B = B;
   P.Br = B;
@@ -278,11 +311,17 @@ bool bad_atlas(int32_t w, int32_t h, int32_t p) {
   return w < 1 || h < 1 || (int64_t)w + p > 16384 || (int64_t)h + p > 16384;
 }
 
-int check_common(int32_t n, int32_t padding, int32_t quality) {
-  if (n < 0 || n > TABI_MAX_CHARTS || padding < 0 || padding > TABI_MAX_PADDING || quality < 0 ||
-      quality > 2)
+// code: a method code (pack_single); the public entry points that take a
+// quality preset use check_common, which admits only the presets
+int check_common_code(int32_t n, int32_t padding, int32_t code) {
+  if (n < 0 || n > TABI_MAX_CHARTS || padding < 0 || padding > TABI_MAX_PADDING ||
+      !code_ok(code))
     return TABI_EINVAL;
   return TABI_OK;
+}
+int check_common(int32_t n, int32_t padding, int32_t quality) {
+  if (quality < 0 || quality > 2) return TABI_EINVAL;
+  return check_common_code(n, padding, quality);
 }
 
 hipError_t run_front(Job& j, const int32_t* xy, const int32_t* voff, const int32_t* aoff,
@@ -373,18 +412,20 @@ std::mutex g_shape_mu;
 // [device][quality][class]: index + 1 into kManyShapes, 0 = default
 int g_shape[64][3][kShapeClasses] = {};
 
-ManyShape many_shape(int quality, int count) {
+ManyShape many_shape(int code, int count) {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || quality < 0 || quality > 2)
+  if (!code_ok(code) || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
     return kManyShapes[0];
+  const int quality = decode_method(code).cls;
   std::lock_guard<std::mutex> lk(g_shape_mu);
   const int i = g_shape[dev][quality][shape_class(count)];
   return i > 0 ? kManyShapes[i - 1] : kManyShapes[0];
 }
 // cls < 0: every size class
-void set_many_shape(int quality, int cls, int index) {
+void set_many_shape(int code, int cls, int index) {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || quality < 0 || quality > 2) return;
+  if (!code_ok(code) || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+  const int quality = decode_method(code).cls;
   std::lock_guard<std::mutex> lk(g_shape_mu);
   for (int c = 0; c < kShapeClasses; ++c)
     if (cls < 0 || c == cls) g_shape[dev][quality][c] = index + 1;
@@ -396,8 +437,7 @@ int many_check(const int32_t* xy, const int32_t* vert_offsets, const int32_t* at
                uint8_t* out_orient, float* out_scale) {
   if (count < 0 || total_charts < 0 || max_charts < 0 || max_charts > TABI_MAX_CHARTS ||
       max_side < 1 || (int64_t)max_side + padding > 16384 || padding < 0 ||
-      padding > TABI_MAX_PADDING || quality < 0 ||
-      quality > 2)
+      padding > TABI_MAX_PADDING || !code_ok(quality))
     return TABI_EINVAL;
   if (count > 0 && (!atlas_offsets || !atlas_wh || !out_scale)) return TABI_EINVAL;
   if (total_charts > 0 && (!xy || !vert_offsets || !out_xy || !out_orient)) return TABI_EINVAL;
@@ -458,6 +498,28 @@ int pack_many_impl(const int32_t* xy, const int32_t* vert_offsets, const int32_t
 int single_front(Job& j, const tabi_charts* ch, int32_t aw, int32_t ah, hipStream_t st) {
   hipError_t e = run_front(j, ch->xy, ch->offsets, nullptr, nullptr, aw, ah, st);
   return e == hipSuccess ? TABI_OK : hip_fail(e);
+}
+
+// A single pack with method code `code`: every candidate scale at once, one
+// workgroup per scale, no host round trip.
+int pack_single(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+                int32_t padding, int32_t code, int32_t* out_xy, uint8_t* out_orient,
+                float* out_scale, tabi_stream_t stream) {
+  if (check_common_code(n, padding, code) || bad_atlas(atlas_w, atlas_h, padding) || !charts ||
+      !out_scale || (n > 0 && (!charts->xy || !charts->offsets || !out_xy || !out_orient)))
+    return TABI_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Job j;
+  int rc = make_job(j, make_params(1, n, code, padding, 64, 0, n > 0 ? n : 1, atlas_w + padding),
+                    st);
+  if (!rc) rc = single_front(j, charts, atlas_w, atlas_h, st);
+  if (!rc) {
+    const int all[1] = {64};
+    hipError_t e = run_search(j, all, 1, out_xy, out_orient, out_scale, st);
+    if (e != hipSuccess) rc = hip_fail(e);
+  }
+  free_job(j, st);
+  return rc;
 }
 
 // Work space of tabi_pack_noalloc: a static device array, one copy per GPU
@@ -538,22 +600,17 @@ extern "C" {
 int tabi_pack(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
               int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
               float* out_scale, tabi_stream_t stream) {
-  if (check_common(n, padding, quality) || bad_atlas(atlas_w, atlas_h, padding) || !charts ||
-      !out_scale || (n > 0 && (!charts->xy || !charts->offsets || !out_xy || !out_orient)))
-    return TABI_EINVAL;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  Job j;
-  // every candidate scale at once: one workgroup per scale, no host round trip
-  int rc = make_job(j, make_params(1, n, quality, padding, 64, 0, n > 0 ? n : 1, atlas_w + padding),
-                    st);
-  if (!rc) rc = single_front(j, charts, atlas_w, atlas_h, st);
-  if (!rc) {
-    const int all[1] = {64};
-    hipError_t e = run_search(j, all, 1, out_xy, out_orient, out_scale, st);
-    if (e != hipSuccess) rc = hip_fail(e);
-  }
-  free_job(j, st);
-  return rc;
+  if (quality < 0 || quality > 2) return TABI_EINVAL;
+  return pack_single(charts, n, atlas_w, atlas_h, padding, quality, out_xy, out_orient, out_scale,
+                     stream);
+}
+
+int tabi_pack_method(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+                     int32_t padding, const tabi_method* method, int32_t* out_xy,
+                     uint8_t* out_orient, float* out_scale, tabi_stream_t stream) {
+  if (!method_ok(method)) return TABI_EINVAL;
+  return pack_single(charts, n, atlas_w, atlas_h, padding, encode_method(*method), out_xy,
+                     out_orient, out_scale, stream);
 }
 
 int tabi_pack_noalloc(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
@@ -591,9 +648,21 @@ int tabi_pack_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t
                    int32_t max_charts, int32_t max_side, int32_t padding, int32_t quality,
                    int32_t* out_xy, uint8_t* out_orient, float* out_scale,
                    tabi_stream_t stream) {
+  if (quality < 0 || quality > 2) return TABI_EINVAL;
   return pack_many_impl(xy, vert_offsets, atlas_offsets, count, atlas_wh, total_charts, max_charts,
                         max_side, padding, quality, out_xy, out_orient, out_scale, nullptr, 0,
                         stream);
+}
+
+int tabi_pack_many_method(const int32_t* xy, const int32_t* vert_offsets,
+                          const int32_t* atlas_offsets, int32_t count, const int32_t* atlas_wh,
+                          int32_t total_charts, int32_t max_charts, int32_t max_side,
+                          int32_t padding, const tabi_method* method, int32_t* out_xy,
+                          uint8_t* out_orient, float* out_scale, tabi_stream_t stream) {
+  if (!method_ok(method)) return TABI_EINVAL;
+  return pack_many_impl(xy, vert_offsets, atlas_offsets, count, atlas_wh, total_charts, max_charts,
+                        max_side, padding, encode_method(*method), out_xy, out_orient, out_scale,
+                        nullptr, 0, stream);
 }
 
 int tabi_tune_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t* atlas_offsets,
@@ -601,6 +670,7 @@ int tabi_tune_many(const int32_t* xy, const int32_t* vert_offsets, const int32_t
                    int32_t max_charts, int32_t max_side, int32_t padding, int32_t quality,
                    int32_t* out_xy, uint8_t* out_orient, float* out_scale, int32_t reps,
                    int32_t* shape, float* ms_per_shape, tabi_stream_t stream) {
+  if (quality < 0 || quality > 2) return TABI_EINVAL;
   int rc = many_check(xy, vert_offsets, atlas_offsets, count, atlas_wh, total_charts, max_charts,
                       max_side, padding, quality, out_xy, out_orient, out_scale);
   if (rc) return rc;
@@ -679,6 +749,7 @@ int tabi_pack_many_ws(const int32_t* xy, const int32_t* vert_offsets,
                       int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
                       float* out_scale, void* workspace, int64_t workspace_bytes,
                       tabi_stream_t stream) {
+  if (quality < 0 || quality > 2) return TABI_EINVAL;
   if (!workspace || workspace_bytes <= 0) return TABI_EINVAL;
   return pack_many_impl(xy, vert_offsets, atlas_offsets, count, atlas_wh, total_charts, max_charts,
                         max_side, padding, quality, out_xy, out_orient, out_scale, workspace,
@@ -720,6 +791,7 @@ int tabi_pack_many_records(const void* records, const int32_t* atlas_offsets, in
                            const int32_t* atlas_wh, int32_t total_charts, int32_t max_charts,
                            int32_t max_side, int32_t padding, int32_t quality, int32_t* out_xy,
                            uint8_t* out_orient, float* out_scale, tabi_stream_t stream) {
+  if (quality < 0 || quality > 2) return TABI_EINVAL;
   if (total_charts > 0 && !records) return TABI_EINVAL;
   return pack_many_impl(nullptr, nullptr, atlas_offsets, count, atlas_wh, total_charts, max_charts,
                         max_side, padding, quality, out_xy, out_orient, out_scale, nullptr, 0,

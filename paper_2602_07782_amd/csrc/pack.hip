@@ -272,7 +272,8 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     feasible = -2;
     break;
   }
-  const int topt = P.q == 0 ? 5 : (P.q == 1 ? 2 : (n > 10000 ? 1 : 0));
+  // t_opt (Sec. 4.4): the call's setting, or the paper's per atlas
+  const int topt = P.topt >= 0 ? P.topt : (n > 10000 ? 1 : 0);
   const size_t slot = (size_t)s * P.N + d.c0;
   // dynamic LDS: frontline F[Wd], fold offsets without / with compaction
   // Xoff, Xon[RC+1], then a per-row pool of PW words
@@ -298,8 +299,9 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   for (int x = tid; x < Wd; x += PACK_NT) F[x] = 0;
   for (int t = tid; t < n; t += PACK_NT) { xs[t] = -1; ys[t] = -1; mir[t] = 0; }
 
-  // per-row state, identical in every thread
-  int rs = 0, tail = 0, trow = 0;
+  // per-row state, identical in every thread; the tight-only variant folds
+  // every row like a tail row (Sec. 5 ablations)
+  int rs = 0, tail = P.variant == 1, trow = 0;
   feasible = 1;
   int kn = 0, kdir = 0, kl = 0, kr = 0;
   if (tid == 0) s_knee[0] = -1;

@@ -275,6 +275,7 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
     unsigned __int128 N = (unsigned __int128)(C * C + S * S);
     if (ext * bN < bext * N) { best = m; bext = ext; bN = N; }
   }
+  if (P.variant == 2) best = 0;  // balanced-only: the chart's box alone
   int64_t ba = 0, bb = 0, be = 0, bf = 0;
 #pragma unroll
   for (int m = 1; m < 8; ++m)
@@ -684,7 +685,8 @@ hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t s
     const dim3 grid(((nblk + XCDS - 1) / XCDS) * XCDS * P.Br);
     if (P.K == 10) hipLaunchKernelGGL(k_setup<10>, grid, dim3(SETUP_NT), 0, st, P, w, round);
     else if (P.K == 5) hipLaunchKernelGGL(k_setup<5>, grid, dim3(SETUP_NT), 0, st, P, w, round);
-    else hipLaunchKernelGGL(k_setup<2>, grid, dim3(SETUP_NT), 0, st, P, w, round);
+    else if (P.K == 2) hipLaunchKernelGGL(k_setup<2>, grid, dim3(SETUP_NT), 0, st, P, w, round);
+    else hipLaunchKernelGGL(k_setup<1>, grid, dim3(SETUP_NT), 0, st, P, w, round);
   }
   return hipGetLastError();
 }

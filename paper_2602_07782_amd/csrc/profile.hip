@@ -591,7 +591,8 @@ hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_
   if (P.count == 1) {
     if (P.K == 10) hipLaunchKernelGGL((k_profile<10, true>), grid, dim3(PROF_NT), 0, st, P, w, round);
     else if (P.K == 5) hipLaunchKernelGGL((k_profile<5, true>), grid, dim3(PROF_NT), 0, st, P, w, round);
-    else hipLaunchKernelGGL((k_profile<2, true>), grid, dim3(PROF_NT), 0, st, P, w, round);
+    else if (P.K == 2) hipLaunchKernelGGL((k_profile<2, true>), grid, dim3(PROF_NT), 0, st, P, w, round);
+    else hipLaunchKernelGGL((k_profile<1, true>), grid, dim3(PROF_NT), 0, st, P, w, round);
     return hipGetLastError();
   }
   const dim3 ggrid(PROF_GEN_BLOCKS);
@@ -601,9 +602,12 @@ hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_
   } else if (P.K == 5) {
     hipLaunchKernelGGL((k_profile<5, false>), grid, dim3(PROF_NT), 0, st, P, w, round);
     hipLaunchKernelGGL(k_profile_general<5>, ggrid, dim3(PROF_NT), 0, st, P, w, round, nbx);
-  } else {
+  } else if (P.K == 2) {
     hipLaunchKernelGGL((k_profile<2, false>), grid, dim3(PROF_NT), 0, st, P, w, round);
     hipLaunchKernelGGL(k_profile_general<2>, ggrid, dim3(PROF_NT), 0, st, P, w, round, nbx);
+  } else {
+    hipLaunchKernelGGL((k_profile<1, false>), grid, dim3(PROF_NT), 0, st, P, w, round);
+    hipLaunchKernelGGL(k_profile_general<1>, ggrid, dim3(PROF_NT), 0, st, P, w, round, nbx);
   }
   return hipGetLastError();
 }

@@ -34,6 +34,8 @@ struct Params {
   int32_t Wdmax;       // largest grown atlas width the shared memory was sized for
   int64_t arena_cap;   // 32-bit words of the profile arena (0: no stored profiles)
   int32_t pack_nt;     // fold-and-push workgroup size: 512, 1024, or 0 (by atlas count)
+  int32_t topt;        // t_opt in percent; < 0: 0 up to 10,000 charts in the atlas, 1 above
+  int32_t variant;     // 0 full, 1 tight-only (static rows), 2 balanced-only (boxes)
 };
 
 // Work-space views (device pointers).
