@@ -176,6 +176,45 @@ def batched_cpu_baseline(inputs, seconds):
                                         f"one per thread, {wall:.1f} s wall"}
 
 
+def ablation_leg(tabi, torch, reps=10):
+    """The paper's ablations on synthetic sets (Sec. 5 ablation table; App. D
+    local-AABB count and t_opt tables): per setting, the mean over inputs of
+    the p50 time of tabi_pack_method and of the L2 stretch 64/k."""
+    import numpy as np
+    from paper_2602_07782_amd import synth
+    inputs = [synth.make_input("mixed2k", i) for i in range(4)]
+    inputs += [synth.make_input("lightmap20k", i) for i in range(2)]
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream()
+    dev_in = [(torch.from_numpy(np.ascontiguousarray(i.xy, np.int32)).to(dev),
+               torch.from_numpy(np.ascontiguousarray(i.offsets, np.int32)).to(dev))
+              for i in inputs]
+    settings = {"full": (10, -1, 0), "tight_only": (10, -1, 1), "balanced_only": (10, -1, 2),
+                "K2": (2, -1, 0), "K5": (5, -1, 0), "topt5": (10, 5, 0), "topt2": (10, 2, 0),
+                "topt1": (10, 1, 0), "topt0": (10, 0, 0)}
+    out = {"inputs": "mixed2k instances 0-3 (2,000 charts, 2048^2) and lightmap20k "
+                     "instances 0-1 (20,000 charts, 4096^2)"}
+    for name, (K, t, v) in settings.items():
+        ms, stretch = [], []
+        for inp, (xy, off) in zip(inputs, dev_in):
+            res = None
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(reps)]
+            tabi.pack_method(xy, off, inp.atlas_w, inp.atlas_h, inp.padding, K, t, v, stream=st)
+            for a, b in ev:
+                a.record(st)
+                res = tabi.pack_method(xy, off, inp.atlas_w, inp.atlas_h, inp.padding, K, t, v,
+                                       stream=st)
+                b.record(st)
+            torch.cuda.synchronize()
+            ms.append(percentile([a.elapsed_time(b) for a, b in ev], 50))
+            k = int(round(float(res[2].cpu().numpy()[0]) * 64))
+            stretch.append(64.0 / k if k > 0 else float("inf"))
+        out[name] = {"mean_ms": round(float(np.mean(ms)), 4),
+                     "mean_stretch": round(float(np.mean(stretch)), 4)}
+    return out
+
+
 def config_legs(tabi, torch, cpu):
     """The other single-pack configurations: the 64-chart 512^2 workload,
     the 2,000-chart 2048^2 workload at low quality, and the 20,000-chart
@@ -507,6 +546,11 @@ def main():
             result["configs"] = config_legs(tabi, torch, not args.no_cpu)
         except Exception as e:  # report, do not lose the main line
             result["configs"] = {"error": repr(e)}
+    if not args.no_configs:
+        try:
+            result["ablations"] = ablation_leg(tabi, torch)
+        except Exception as e:
+            result["ablations"] = {"error": repr(e)}
     if not args.no_batched:
         try:
             result["batched"] = batched_leg(tabi, torch,

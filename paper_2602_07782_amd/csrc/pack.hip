@@ -40,6 +40,10 @@ constexpr int LRCAP = 256;
 constexpr int FWIN = 1024;  // charts per row whose fold data is staged in LDS
 enum { DIR_LR = 0, DIR_RL = 1 };
 
+// A value every thread of the workgroup holds alike (read from shared
+// memory after a barrier): kept in a scalar register.
+__device__ inline int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ inline void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -158,6 +162,64 @@ __device__ int pair_prefix(const int32_t* Xon, const int32_t* Xoff, int cand, in
   return total;
 }
 
+// The correction of a row whose pairs that share columns without being
+// neighbours outnumber the shared-memory list (rare; every thread of the
+// workgroup calls it).  Their flags depend only on the compacted offsets,
+// the same in every configuration; each pass recomputes them chunk by chunk
+// and applies them, until a whole pass moves no offset.  Kept out of line so
+// that its registers do not add to those of the row loop.  lrpre, flv,
+// prowv, hdv: the slot's per-chart arrays of the atlas; seg: the profile
+// segment (stored rows) when prof.
+template <int PACK_NT>
+__device__ __attribute__((noinline)) void correct_many_pairs(
+    const int32_t* Xon, const int32_t* Xoff, int cand, int rs, int32_t* lrpre, int32_t* red,
+    int32_t (*lr)[3], int32_t* my_y, int my_cnt, int my_hc, const uint8_t* flv, bool prof,
+    const uint32_t* seg, const int32_t* prowv, const int32_t* hdv, const unsigned char* kcb,
+    int stride, const Chart* ch, int K, int k, int p) {
+  constexpr int PACK_WAVES = PACK_NT / WAVE;
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+  auto KV = [&](int c) { return kview(kcb + (size_t)c * stride, K); };
+  const int total = pair_prefix<PACK_NT>(Xon, Xoff, cand, lrpre + rs, red);
+  for (;;) {
+    if (my_hc) chain_scans(my_y, my_cnt, flv + rs);
+    int moved = 0;
+    for (int q0 = 0; q0 < total; q0 += LRCAP) {
+      const int m = min(LRCAP, total - q0);
+      __syncthreads();  // the previous chunk is no longer read
+      for (int t = tid; t < m; t += PACK_NT) {
+        const int q = q0 + t;
+        int lo = 0, hi = cand - 1;  // last A with pre[A] <= q
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (lrpre[rs + mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        lr[t][0] = lo;
+        lr[t][1] = lo + 2 + (q - lrpre[rs + lo]);
+      }
+      __syncthreads();
+      for (int q = wv; q < m; q += PACK_WAVES) {
+        const int A = lr[q][0], C = lr[q][1];
+        const int wdA = Xoff[A + 1] - Xoff[A];
+        const int dd = Xon[C] - Xon[A];
+        int f;
+        if (prof) {
+          f = pair_flags_at(pair_rows_meet(seg + prowv[rs + A], hdv[rs + A], seg + prowv[rs + C],
+                                           hdv[rs + C], wdA),
+                            wdA, dd);
+        } else {
+          f = pair_flags_at(pair_records_sweep<2>(KV(rs + A), ch[rs + A], KV(rs + C), ch[rs + C],
+                                                  K, k, p),
+                            wdA, dd);
+        }
+        if (lane == 0) lr[q][2] = f;
+      }
+      __syncthreads();
+      if (my_hc && apply_pairs(my_y, my_cnt, lr, m)) moved = 1;
+    }
+    if (!__syncthreads_or(moved)) break;
+  }
+}
+
 template <int PACK_WAVES>
 __device__ inline int32_t block_reduce_max(int32_t v, int32_t* red) {
   v = wave_max(v);
@@ -167,7 +229,7 @@ __device__ inline int32_t block_reduce_max(int32_t v, int32_t* red) {
   int32_t r = red[0];
 #pragma unroll
   for (int i = 1; i < PACK_WAVES; ++i) r = max(r, red[i]);
-  return r;
+  return uni(r);
 }
 template <int PACK_WAVES>
 __device__ inline int32_t block_reduce_min(int32_t v, int32_t* red) {
@@ -178,7 +240,7 @@ __device__ inline int32_t block_reduce_min(int32_t v, int32_t* red) {
   int32_t r = red[0];
 #pragma unroll
   for (int i = 1; i < PACK_WAVES; ++i) r = min(r, red[i]);
-  return r;
+  return uni(r);
 }
 
 // Largest feasible scale of this round for atlas a (one workgroup, any size
@@ -318,9 +380,9 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   for (;;) {
     __syncthreads();
     {  // the previous row's knee detection (-1: none ran)
-      const int kf = s_knee[0];
+      const int kf = uni(s_knee[0]);
       if (kf >= 0) kn = kf;
-      if (kf > 0) { kdir = s_knee[1]; kl = s_knee[2]; kr = s_knee[3]; }
+      if (kf > 0) { kdir = uni(s_knee[1]); kl = uni(s_knee[2]); kr = uni(s_knee[3]); }
     }
     if (rs >= n) break;
     if (rs - wb > FWIN / 2) {
@@ -356,7 +418,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       }
     }
     // ---- t_opt switch (Sec. 4.4), on the first chart's texel height
-    const int64_t h0 = cdiv64((int64_t)k * s_H[r0], QS);
+    const int64_t h0 = cdiv64((int64_t)k * uni(s_H[r0]), QS);
     if (!tail && !kn && 100 * h0 < (int64_t)topt * Ha) tail = 1;
     // ---- 2. folding (Alg. 2), wavefront 0
     const int kw = kn ? (kdir == DIR_LR ? Wd - kr : kl) : 0;
@@ -392,7 +454,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       }
     }
     __syncthreads();
-    const int cfo = s_cnt[0], cfn = s_cnt[1], cko = s_cnt[2], ckn = s_cnt[3];
+    const int cfo = uni(s_cnt[0]), cfn = uni(s_cnt[1]), cko = uni(s_cnt[2]), ckn = uni(s_cnt[3]);
     if (cfn == 0) { feasible = 0; break; }  // a chart wider than the atlas
     if (cfn > RC) { feasible = -2; break; }   // cannot happen: advances are >= 1
     // ---- configurations: direction x compaction x (full | knee) (Sec. 4.2)
@@ -423,7 +485,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     int anyhc = 0, yofs[4], ysum = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) { anyhc |= c_hc[j]; yofs[j] = ysum; ysum += c_cnt[j]; }
-    const int E = Xoff[cand];  // grown texel columns of the candidates
+    const int E = uni(Xoff[cand]);  // grown texel columns of the candidates
     // pool: offsets Y of configuration j at pool[yofs[j]], then (when staged)
     // packed (top, bottom) of texel e at st[e] and its chart at emap[e]
     int32_t* Yb = pool;
@@ -477,10 +539,11 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       }
     }
     __syncthreads();
-    // more pairs than the shared list holds: none is swept with the push,
-    // the correction walks them in chunks
-    const bool lrover = s_lrover != 0;
-    const int lrn = lrover ? 0 : s_lrn;
+    // more pairs than the shared list holds, or pairs whose rows are not
+    // stored: none is swept with the push, the correction walks them out of
+    // line (both rare)
+    const bool lrover = uni(s_lrover) != 0 || (!prof && uni(s_lrn) > 0);
+    const int lrn = lrover ? 0 : uni(s_lrn);
     // ---- 4. push every configuration against the committed frontline; the
     // last wavefronts (at most a quarter) sweep the non-neighbour pairs at
     // the same time
@@ -526,16 +589,11 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     for (int q = wv - npush; wv >= npush && q < lrn; q += nlr) {
       const int A = s_lr[q][0], C = s_lr[q][1];
       const int wdA = Xoff[A + 1] - Xoff[A];
-      const int dd = Xon[C] - Xon[A];
-      int f;
-      if (prof) {
-        f = pair_flags_at(pair_rows_meet(w.arena + sbase + prowv[rs + A], hdv[rs + A],
-                                         w.arena + sbase + prowv[rs + C], hdv[rs + C], wdA),
-                          wdA, dd);
-      } else {
-        f = pair_flags_at(pair_records_sweep<2>(KV(rs + A), ch[rs + A], KV(rs + C), ch[rs + C], K, k, p),
-                          wdA, dd);
-      }
+      const int dd = Xon[C] - Xon[A];  // rows stored (prof): the others go out of line
+      const int f = pair_flags_at(pair_rows_meet(w.arena + sbase + prowv[rs + A], hdv[rs + A],
+                                                 w.arena + sbase + prowv[rs + C], hdv[rs + C],
+                                                 wdA),
+                                  wdA, dd);
       if (lane == 0) s_lr[q][2] = f;
     }
     __syncthreads();
@@ -546,62 +604,28 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     if (!lrover) {
       if (my_hc) correct_offsets(my_y, my_cnt, flv + rs, s_lr, lrn);
     } else {
-      // the pairs' flags depend only on the compacted offsets, the same in
-      // every configuration; each pass recomputes them chunk by chunk and
-      // applies them, until a whole pass moves no offset
-      const int total = pair_prefix<PACK_NT>(Xon, Xoff, cand, lrpre + rs, s_red);
-      for (;;) {
-        if (my_hc) chain_scans(my_y, my_cnt, flv + rs);
-        int moved = 0;
-        for (int q0 = 0; q0 < total; q0 += LRCAP) {
-          const int m = min(LRCAP, total - q0);
-          __syncthreads();  // the previous chunk is no longer read
-          for (int t = tid; t < m; t += PACK_NT) {
-            const int q = q0 + t;
-            int lo = 0, hi = cand - 1;  // last A with pre[A] <= q
-            while (lo < hi) {
-              const int mid = (lo + hi + 1) >> 1;
-              if (lrpre[rs + mid] <= q) lo = mid; else hi = mid - 1;
-            }
-            s_lr[t][0] = lo;
-            s_lr[t][1] = lo + 2 + (q - lrpre[rs + lo]);
-          }
-          __syncthreads();
-          for (int q = wv; q < m; q += PACK_WAVES) {
-            const int A = s_lr[q][0], C = s_lr[q][1];
-            const int wdA = Xoff[A + 1] - Xoff[A];
-            const int dd = Xon[C] - Xon[A];
-            int f;
-            if (prof) {
-              f = pair_flags_at(pair_rows_meet(w.arena + sbase + prowv[rs + A], hdv[rs + A],
-                                               w.arena + sbase + prowv[rs + C], hdv[rs + C], wdA),
-                                wdA, dd);
-            } else {
-              f = pair_flags_at(pair_records_sweep<2>(KV(rs + A), ch[rs + A], KV(rs + C),
-                                                      ch[rs + C], K, k, p), wdA, dd);
-            }
-            if (lane == 0) s_lr[q][2] = f;
-          }
-          __syncthreads();
-          if (my_hc && apply_pairs(my_y, my_cnt, s_lr, m)) moved = 1;
-        }
-        if (!__syncthreads_or(moved)) break;
-      }
+      correct_many_pairs<PACK_NT>(Xon, Xoff, cand, rs, lrpre, s_red, s_lr, my_y, my_cnt, my_hc,
+                                  flv, prof, w.arena + (prof ? sbase : 0), prowv, hdv, kcb,
+                                  P.stride, ch, K, k, p);
     }
     // the scores read the corrected offsets (without compaction nothing was
     // corrected and the barrier after the push suffices)
     if (anyhc) __syncthreads();
-    // ---- 6. scores
+    // ---- 6. scores: the largest offset + grown bottom over a
+    // configuration's texels.  A chart's largest bottom is its height h:
+    // every proxy bounds the chart from outside, so at a column holding the
+    // chart's lowest point all of them reach h, and the local AABBs never
+    // pass it; grown, the largest is h + p.  So a configuration scores
+    // max over its charts of offset + h + p, one term per chart.
     int32_t M[4] = {-BIG, -BIG, -BIG, -BIG};
-    for (int e0 = wv * WAVE; e0 < E; e0 += PACK_NT) {
-      const int e = e0 + lane;
-      if (e < E) {
-        int t;
-        int32_t tp, bt;
-        texel(e, t, tp, bt);
+    {
+      const int cmax = max(max(c_cnt[0], c_cnt[1]), max(c_cnt[2], c_cnt[3]));
+      for (int t = tid; t < cmax; t += PACK_NT) {
+        const int64_t Hq = r0 + t < nwin ? s_H[r0 + t] : Hs[rs + t];
+        const int32_t hdt = (int32_t)((k * Hq + QS - 1) >> 14) + p;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          if (t < c_cnt[j]) M[j] = max(M[j], Yb[yofs[j] + t] + bt);
+          if (t < c_cnt[j]) M[j] = max(M[j], Yb[yofs[j] + t] + hdt);
       }
     }
     int32_t fr = -BIG;
@@ -621,11 +645,11 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       for (int j = 0; j < 4; ++j) {
         int32_t m = -BIG;
         for (int q = 0; q < PACK_WAVES; ++q) m = max(m, s_red[q * 6 + j]);
-        M[j] = m;
+        M[j] = uni(m);
       }
       int32_t f2 = -BIG;
       for (int q = 0; q < PACK_WAVES; ++q) f2 = max(f2, s_red[q * 6 + 4]);
-      fr = f2;
+      fr = uni(f2);
     }
     // ---- 7. selection: lower maximal height wins, ties left to right; the
     // knee fold only if strictly lower over the whole frontline

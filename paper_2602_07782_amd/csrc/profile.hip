@@ -585,10 +585,10 @@ hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_
     hipLaunchKernelGGL(k_alloc, dim3(1), dim3(ALLOC_NT), 0, st, P, w, round);
   const int nbx = (P.N + PROF_CH - 1) / PROF_CH;
   const dim3 grid(nbx, P.Br);
-  // a single atlas: one launch in full form; a batch: the lean form at full
-  // occupancy, then the queued blocks (the queue counter was cleared by the
-  // set-up kernel of this round)
-  if (P.count == 1) {
+  // the lean form at full occupancy, then the queued blocks in full form
+  // (the queue counter was cleared by the set-up kernel of this round); a
+  // single atlas without stored profiles takes the full form at once
+  if (P.count == 1 && P.arena_cap == 0) {
     if (P.K == 10) hipLaunchKernelGGL((k_profile<10, true>), grid, dim3(PROF_NT), 0, st, P, w, round);
     else if (P.K == 5) hipLaunchKernelGGL((k_profile<5, true>), grid, dim3(PROF_NT), 0, st, P, w, round);
     else if (P.K == 2) hipLaunchKernelGGL((k_profile<2, true>), grid, dim3(PROF_NT), 0, st, P, w, round);

@@ -196,6 +196,25 @@ def test_profiles_contain_raster(orc, chk, seed):
             assert m.any(axis=0).all() and m.any(axis=1).all()
 
 
+@pytest.mark.parametrize("seed", range(60))
+def test_profiles_reach_the_box_bottom(orc, seed):
+    """Some column of every chart reaches the bottom of its texel box
+    (max BottomEdge = h) and none passes it: every proxy bounds the chart from
+    outside, so all of them reach the chart's lowest point, and the x-slices
+    never pass the box.  The fold-and-push kernel scores a row from this (a
+    chart's largest grown bottom is h + p), where the oracle sweeps the
+    frontline texel by texel; charts of every shape family, all scales."""
+    rng = np.random.default_rng(20000 + seed)
+    inp = small_input(2000 + seed, n=8)
+    K = [2, 5, 10][seed % 3]
+    for c in range(inp.n):
+        rec = orc.prep_chart(inp.chart(c), K)
+        for k in list(rng.integers(1, 65, 4)) + [64]:
+            top, bot, left, right = orc.profiles(rec, int(k))
+            assert int(bot.max()) == len(left), (c, int(k))
+            assert int(top.min()) == 0 and int(left.min()) == 0 and int(right.max()) == len(top)
+
+
 @pytest.mark.parametrize("a,b,k", [(256 * 5, 256 * 9, 64), (1000, 2000, 64), (777, 1531, 17),
                                    (256 * 7, 256 * 7, 32), (300, 4000, 5)])
 def test_rectangle_profiles_are_exact(orc, chk, a, b, k):
