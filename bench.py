@@ -217,15 +217,17 @@ def ablation_leg(tabi, torch, reps=10):
 
 def config_legs(tabi, torch, cpu):
     """The other single-pack configurations: the 64-chart 512^2 workload,
-    the 2,000-chart 2048^2 workload at low quality, and the 20,000-chart
-    4096^2 workload; p50 / p99 of tabi_pack (HIP events per call) and the
-    oracle on one host core (one pack each)."""
+    the 2,000-chart 2048^2 workload at low quality, the 20,000-chart 4096^2
+    workload and a TSS-like frame (4,000 clipped screen-space patches into
+    1024^2); p50 / p99 of tabi_pack (HIP events per call) and the oracle on
+    one host core (one pack each)."""
     import numpy as np
     from paper_2602_07782_amd import synth
     import oracle
     legs = {}
-    for name, q, steps in (("stars64", 2, 100), ("mixed2k", 0, 100), ("lightmap20k", 2, 30)):
-        base = synth.make_input(name, 0)
+    for name, q, steps in (("stars64", 2, 100), ("mixed2k", 0, 100), ("lightmap20k", 2, 30),
+                           ("tss4k", 2, 100)):
+        base = synth.make_tss(0) if name == "tss4k" else synth.make_input(name, 0)
         inp = synth.AtlasInput(base.xy, base.offsets, base.atlas_w, base.atlas_h, base.padding, q)
         dev = torch.device("cuda:0")
         xy = torch.from_numpy(np.ascontiguousarray(inp.xy, np.int32)).to(dev)

@@ -295,6 +295,14 @@ int tabi_ctx_destroy(tabi_ctx* ctx);
 int tabi_submit(tabi_ctx* ctx, const int32_t* xy, const int32_t* offsets, int32_t n,
                 int32_t atlas_w, int32_t atlas_h, int32_t* out_xy, uint8_t* out_orient,
                 float* out_scale, int32_t* atlas_id, int64_t* ticket);
+/* tabi_submit with the request's own padding and quality preset instead of
+ * the context's: requests are batched only with consecutive requests of the
+ * same settings (tabi_pack_many shares them across a batch).  Re-packs keep
+ * the settings of their atlas. */
+int tabi_submit_with(tabi_ctx* ctx, const int32_t* xy, const int32_t* offsets, int32_t n,
+                     int32_t atlas_w, int32_t atlas_h, int32_t padding, int32_t quality,
+                     int32_t* out_xy, uint8_t* out_orient, float* out_scale, int32_t* atlas_id,
+                     int64_t* ticket);
 /* A re-pack of a resident atlas whose charts replaced_idx[0..m) (strictly
  * increasing indices of its current chart set) are replaced by the m charts
  * of the host CSR (xy, offsets); every other chart keeps its records and its

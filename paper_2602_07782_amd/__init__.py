@@ -55,7 +55,7 @@ class Done(ctypes.Structure):
 
 _lib = None
 EXPORTS = ["tabi_pack", "tabi_pack_method", "tabi_pack_many_method", "tabi_pack_noalloc",
-           "tabi_pack_many", "tabi_pack_many_ws", "tabi_pack_many_workspace_bytes",
+           "tabi_pack_many", "tabi_pack_many_ws", "tabi_submit_with", "tabi_pack_many_workspace_bytes",
            "tabi_record_bytes", "tabi_prep_records", "tabi_splice_records",
            "tabi_pack_many_records", "tabi_debug_order", "tabi_debug_pairs",
            "tabi_debug_feasible", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
@@ -118,6 +118,8 @@ def lib():
                                   ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]
         L.tabi_repack.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, vp,
                                   ctypes.POINTER(ctypes.c_int64)]
+        L.tabi_submit_with.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, vp, vp, vp,
+                                       ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_int64)]
         L.tabi_poll.argtypes = [vp, i32, ctypes.POINTER(Done), i32, ctypes.POINTER(i32)]
         L.tabi_ctx_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), i32]
         _lib = L
@@ -457,17 +459,24 @@ class ServeContext:
         import numpy as np
         return (np.empty((n, 2), np.int32), np.empty(n, np.uint8), np.empty(1, np.float32))
 
-    def submit(self, xy, offsets, atlas_w, atlas_h):
-        """New atlas; returns (atlas_id, ticket)."""
+    def submit(self, xy, offsets, atlas_w, atlas_h, padding=None, quality=None):
+        """New atlas; returns (atlas_id, ticket).  padding / quality: the
+        request's own (tabi_submit_with), else the context's."""
         import numpy as np
         xy = np.ascontiguousarray(xy, np.int32)
         off = np.ascontiguousarray(offsets, np.int32)
         n = off.size - 1
         o = self._outs(n)
         aid, t = ctypes.c_int32(), ctypes.c_int64()
-        _check(lib().tabi_submit(self.h, _hptr(xy), _hptr(off), n, int(atlas_w), int(atlas_h),
-                                 _hptr(o[0]), _hptr(o[1]), _hptr(o[2]), ctypes.byref(aid),
-                                 ctypes.byref(t)))
+        if padding is None and quality is None:
+            _check(lib().tabi_submit(self.h, _hptr(xy), _hptr(off), n, int(atlas_w),
+                                     int(atlas_h), _hptr(o[0]), _hptr(o[1]), _hptr(o[2]),
+                                     ctypes.byref(aid), ctypes.byref(t)))
+        else:
+            _check(lib().tabi_submit_with(self.h, _hptr(xy), _hptr(off), n, int(atlas_w),
+                                          int(atlas_h), int(padding), int(quality),
+                                          _hptr(o[0]), _hptr(o[1]), _hptr(o[2]),
+                                          ctypes.byref(aid), ctypes.byref(t)))
         self.outputs[t.value] = o
         return aid.value, t.value
 

@@ -94,14 +94,14 @@ struct Block {       // one version of an atlas's records
 };
 
 struct Atlas {
-  int32_t n = 0, W = 0, H = 0;
+  int32_t n = 0, W = 0, H = 0, padding = 0, quality = 0;
   int64_t block = -1;   // current version (-1: not resident)
   int64_t last_use = 0;
 };
 
 struct Req {
   int64_t ticket = 0;
-  int32_t atlas = 0, n = 0, W = 0, H = 0;
+  int32_t atlas = 0, n = 0, W = 0, H = 0, padding = 0, quality = 0;
   bool repack = false;
   std::vector<int32_t> xy, off, idx;  // prepared charts (all of a new atlas, or the replaced)
   int32_t* oxy = nullptr;
@@ -111,7 +111,7 @@ struct Req {
 };
 
 struct Plan {  // byte offsets of one batch's device region
-  int count = 0, N = 0, M = 0, nmax = 0, side = 0;
+  int count = 0, N = 0, M = 0, nmax = 0, side = 0, padding = 0, quality = 0;
   int64_t V = 0;
   size_t aoff, poff, awh, src, dst, voff, idx, xy, up_end;  // uploaded part
   size_t scratch, prep, recs;
@@ -168,6 +168,10 @@ double now_s(const tabi_ctx* c) {
 Plan plan_batch(const tabi_ctx* c, const std::vector<const Req*>& rs) {
   Plan p;
   p.count = (int)rs.size();
+  if (!rs.empty()) {  // the requests of a batch share padding and quality
+    p.padding = rs[0]->padding;
+    p.quality = rs[0]->quality;
+  }
   for (const Req* r : rs) {
     p.N += r->n;
     p.M += (int)(r->off.size() - 1);
@@ -197,8 +201,8 @@ Plan plan_batch(const tabi_ctx* c, const std::vector<const Req*>& rs) {
   p.oor = take((size_t)std::max(p.N, 1));
   p.osc = take(4 * (size_t)p.count);
   p.down_end = o;
-  p.ws_bytes = (size_t)host_many_workspace_bytes(p.count, p.N, p.nmax, p.side,
-                                                 c->cfg.padding, c->cfg.quality);
+  p.ws_bytes = (size_t)host_many_workspace_bytes(p.count, p.N, p.nmax, p.side, p.padding,
+                                                 p.quality);
   p.ws = take(p.ws_bytes);
   p.total = o;
   return p;
@@ -344,7 +348,7 @@ int launch(tabi_ctx* c, int si, std::vector<Req>& reqs, const Plan& pl, size_t r
   if (!rc)
     rc = host_prep_records(reinterpret_cast<const int32_t*>(d + pl.xy),
                            reinterpret_cast<const int32_t*>(d + pl.voff), dpoff, pl.count, pl.M,
-                           c->cfg.quality, prep, d + pl.scratch, s.st);
+                           pl.quality, prep, d + pl.scratch, s.st);
   if (!rc) {
     e = launch_assemble(pl.N, pl.M, pl.count, daoff, dpoff,
                         reinterpret_cast<const uint64_t*>(d + pl.src),
@@ -355,7 +359,7 @@ int launch(tabi_ctx* c, int si, std::vector<Req>& reqs, const Plan& pl, size_t r
   if (!rc)
     rc = host_pack_many_records_ws(recs, daoff, pl.count,
                                    reinterpret_cast<const int32_t*>(d + pl.awh), pl.N, pl.nmax,
-                                   pl.side, c->cfg.padding, c->cfg.quality,
+                                   pl.side, pl.padding, pl.quality,
                                    reinterpret_cast<int32_t*>(d + pl.oxy), d + pl.oor,
                                    reinterpret_cast<float*>(d + pl.osc), d + pl.ws, pl.ws_bytes,
                                    s.st);
@@ -403,6 +407,8 @@ int pump(tabi_ctx* c) {
     for (size_t q = 0; q < c->queue.size() && (int)rs.size() < c->cfg.max_batch; ++q) {
       const Req& r = c->queue[q];
       if (std::find(ids.begin(), ids.end(), r.atlas) != ids.end()) break;  // one per atlas
+      if (!rs.empty() && (r.padding != rs[0]->padding || r.quality != rs[0]->quality))
+        break;  // a batch shares padding and quality
       if (r.repack && c->atlases[r.atlas].block < 0) break;
       rs.push_back(&r);
       const Plan t = plan_batch(c, rs);
@@ -573,11 +579,13 @@ int tabi_ctx_destroy(tabi_ctx* c) {
   return first == hipSuccess ? TABI_OK : host_hip_fail(first);
 }
 
-int tabi_submit(tabi_ctx* c, const int32_t* xy, const int32_t* offsets, int32_t n,
-                int32_t atlas_w, int32_t atlas_h, int32_t* out_xy, uint8_t* out_orient,
-                float* out_scale, int32_t* atlas_id, int64_t* ticket) {
-  if (!c || n < 1 || n > TABI_MAX_CHARTS || atlas_w < 1 || atlas_h < 1 ||
-      (int64_t)atlas_w + c->cfg.padding > 16384 || (int64_t)atlas_h + c->cfg.padding > 16384 ||
+int tabi_submit_with(tabi_ctx* c, const int32_t* xy, const int32_t* offsets, int32_t n,
+                     int32_t atlas_w, int32_t atlas_h, int32_t padding, int32_t quality,
+                     int32_t* out_xy, uint8_t* out_orient, float* out_scale, int32_t* atlas_id,
+                     int64_t* ticket) {
+  if (!c || n < 1 || n > TABI_MAX_CHARTS || atlas_w < 1 || atlas_h < 1 || padding < 0 ||
+      padding > TABI_MAX_PADDING || quality < 0 || quality > 2 ||
+      (int64_t)atlas_w + padding > 16384 || (int64_t)atlas_h + padding > 16384 ||
       !out_xy || !out_orient || !out_scale || !check_csr(xy, offsets, n))
     return TABI_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
@@ -588,6 +596,8 @@ int tabi_submit(tabi_ctx* c, const int32_t* xy, const int32_t* offsets, int32_t 
   r.n = n;
   r.W = atlas_w;
   r.H = atlas_h;
+  r.padding = padding;
+  r.quality = quality;
   r.xy.assign(xy, xy + 2 * (size_t)offsets[n]);
   r.off.assign(offsets, offsets + n + 1);
   r.oxy = out_xy;
@@ -598,10 +608,20 @@ int tabi_submit(tabi_ctx* c, const int32_t* xy, const int32_t* offsets, int32_t 
   a.n = n;
   a.W = atlas_w;
   a.H = atlas_h;
+  a.padding = padding;
+  a.quality = quality;
   if (atlas_id) *atlas_id = r.atlas;
   if (ticket) *ticket = r.ticket;
   c->queue.push_back(std::move(r));
   return pump(c);
+}
+
+int tabi_submit(tabi_ctx* c, const int32_t* xy, const int32_t* offsets, int32_t n,
+                int32_t atlas_w, int32_t atlas_h, int32_t* out_xy, uint8_t* out_orient,
+                float* out_scale, int32_t* atlas_id, int64_t* ticket) {
+  if (!c) return TABI_EINVAL;
+  return tabi_submit_with(c, xy, offsets, n, atlas_w, atlas_h, c->cfg.padding, c->cfg.quality,
+                          out_xy, out_orient, out_scale, atlas_id, ticket);
 }
 
 int tabi_repack(tabi_ctx* c, int32_t atlas_id, const int32_t* replaced_idx, int32_t m,
@@ -625,6 +645,8 @@ int tabi_repack(tabi_ctx* c, int32_t atlas_id, const int32_t* replaced_idx, int3
   r.W = it->second.W;
   r.H = it->second.H;
   r.repack = true;
+  r.padding = it->second.padding;  // a re-pack keeps its atlas's settings
+  r.quality = it->second.quality;
   r.idx = std::move(idx);
   r.xy.assign(xy, xy + 2 * (size_t)offsets[m]);
   r.off.assign(offsets, offsets + m + 1);

@@ -56,7 +56,13 @@ CONFIGS = {
     "lightmap20k": dict(W=4096, H=4096, p=1, n=20000, sigma=1.5, fill=1.5, q=2,
                   mix=[("quad", 0.9, 4, 8, 16.0), ("star", 0.1, 16, 48, 4.0)]),
 }
-CONFIG_INDEX = {"stars64": 1, "mixed2k": 2, "lightmap20k": 3, "batch": 4, "serve": 5}
+CONFIG_INDEX = {"stars64": 1, "mixed2k": 2, "lightmap20k": 3, "batch": 4, "serve": 5, "tss4k": 6}
+
+# Texture-space-shading-like frames (a second workload; the paper's TSS chart
+# sets come from camera paths and are not available): screen-space patches of
+# a 1920 x 1080 frame clipped to the view frustum, at their on-screen
+# orientation (not pre-rotated), packed into a 1024^2 atlas.
+TSS = dict(screen=(1920, 1080), W=1024, H=1024, p=2, n=4000, sigma=1.3, cover=0.6, q=2)
 
 
 def config_seed(name: str, instance: int) -> int:
@@ -237,6 +243,97 @@ def generate_charts(n, W, H, sigma, fill, mix, seed):
             raise RuntimeError("could not draw a valid chart")
         polys.append(Q)
     return polys
+
+
+def clip_to_rect(P, x0, y0, x1, y1):
+    """Sutherland-Hodgman clip of a float polygon to the box [x0,x1] x [y0,y1]."""
+    def clip(poly, inside, cross):
+        out = []
+        m = len(poly)
+        for i in range(m):
+            a, b = poly[i], poly[(i + 1) % m]
+            ia, ib = inside(a), inside(b)
+            if ia:
+                out.append(a)
+            if ia != ib:
+                out.append(cross(a, b))
+        return out
+
+    def xcut(xv):
+        return lambda a, b: (xv, a[1] + (b[1] - a[1]) * (xv - a[0]) / (b[0] - a[0]))
+
+    def ycut(yv):
+        return lambda a, b: (a[0] + (b[0] - a[0]) * (yv - a[1]) / (b[1] - a[1]), yv)
+    poly = [tuple(p) for p in np.asarray(P, float)]
+    for inside, cross in ((lambda q: q[0] >= x0, xcut(x0)), (lambda q: q[0] <= x1, xcut(x1)),
+                          (lambda q: q[1] >= y0, ycut(y0)), (lambda q: q[1] <= y1, ycut(y1))):
+        if len(poly) < 3:
+            return np.zeros((0, 2))
+        poly = clip(poly, inside, cross)
+    return np.array(poly, float) if len(poly) >= 3 else np.zeros((0, 2))
+
+
+def _tss_patch(rng):
+    """A projected surface patch: a perspective-distorted quad (a planar
+    rectangle seen at an angle), a convex fan of 5-9 vertices, or a concave
+    L-shaped patch, at a random on-screen angle."""
+    r = rng.uniform()
+    if r < 0.5:
+        a = rng.uniform(1.0, 6.0)
+        w, h = math.sqrt(a), 1.0 / math.sqrt(a)
+        t = rng.uniform(0.4, 1.0)  # far edge shrunk by perspective
+        P = np.array([[-w / 2, 0], [w / 2, 0], [t * w / 2, h], [-t * w / 2, h]], float)
+    elif r < 0.8:
+        m = int(rng.integers(5, 10))
+        ang = np.sort(2 * np.pi * (np.arange(m) + rng.uniform(-0.25, 0.25, m)) / m)
+        rr = 1.0 + rng.uniform(-0.15, 0.15, m)
+        P = np.stack([rr * np.cos(ang), rr * np.sin(ang) * rng.uniform(0.3, 1.0)], axis=1)
+    else:
+        P = _lu(rng, 4.0)
+    return _rot(P, rng.uniform(0.0, 2 * np.pi))
+
+
+def generate_tss_charts(n, screen, sigma, cover, seed):
+    """n clipped screen-space patches whose areas (log-normal, sigma) sum to
+    about `cover` of the screen; patch centres fall on the screen grown by a
+    fifth of its size on every side, so the border patches are clipped to
+    the frustum (straight edges along the screen edges)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    SW, SH = screen
+    areas = np.exp(sigma * rng.standard_normal(n))
+    areas *= cover * SW * SH / areas.sum()
+    polys = []
+    i = 0
+    while len(polys) < n:
+        P = _tss_patch(rng)
+        A = _shoelace(P)
+        P = P * math.sqrt(areas[i % n] / A)
+        c = np.array([rng.uniform(-0.2 * SW, 1.2 * SW), rng.uniform(-0.2 * SH, 1.2 * SH)])
+        C = clip_to_rect(P + c, 0.0, 0.0, float(SW), float(SH))
+        i += 1
+        if C.shape[0] < 3 or _shoelace(C) < 1.0:
+            continue  # outside the frustum, or a sliver
+        Q = np.rint(C * Q8).astype(np.int64)
+        keep = np.any(Q != np.roll(Q, 1, axis=0), axis=1)  # merge repeated points
+        Q = Q[keep]
+        ext = Q.max(axis=0) - Q.min(axis=0) if Q.shape[0] else np.zeros(2)
+        if Q.shape[0] < 3 or ext.min() < 4 or not polygon_is_simple(Q):
+            continue
+        polys.append(Q)
+    return polys
+
+
+@functools.lru_cache(maxsize=16)
+def make_tss(instance: int = 0, n: int | None = None, atlas: int | None = None,
+             quality: int | None = None) -> AtlasInput:
+    """A TSS-like frame (see TSS): instance 0 is the timed input."""
+    nn = TSS["n"] if n is None else int(n)
+    seed = config_seed("tss4k", instance) + (0 if n is None else 7919 * nn)
+    polys = generate_tss_charts(nn, TSS["screen"], TSS["sigma"],
+                                TSS["cover"] * nn / TSS["n"], seed)
+    xy, offs = pack_csr(polys)
+    side = TSS["W"] if atlas is None else int(atlas)
+    return AtlasInput(xy, offs, side, side, TSS["p"], TSS["q"] if quality is None else quality)
 
 
 def pack_csr(polys):

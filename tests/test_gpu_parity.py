@@ -229,6 +229,18 @@ def test_row_with_more_than_256_non_neighbour_pairs(tabi, orc, q):
     assert_pack_equal(tabi, orc, inp, f"many pairs q{q}")
 
 
+@pytest.mark.parametrize("atlas,q", [(1024, 2), (2048, 2), (1024, 0)])
+def test_pack_parity_tss_frame(tabi, orc, atlas, q):
+    """TSS-like frames: 4,000 screen-space patches clipped to a 1920 x 1080
+    frustum, not pre-rotated, into 1K^2 and 2K^2 atlases."""
+    assert_pack_equal(tabi, orc, synth.make_tss(0, atlas=atlas, quality=q), f"tss {atlas} q{q}")
+
+
+def test_pack_parity_tss_other_frames(tabi, orc):
+    for inst in (1, 2):
+        assert_pack_equal(tabi, orc, synth.make_tss(inst, n=1500), f"tss frame {inst}")
+
+
 def test_repeat_is_bitwise_identical(tabi):
     inp = synth.make_input("mixed2k", 0)
     a = gpu_pack(tabi, inp)

@@ -103,3 +103,53 @@ def test_single_slot_gives_same_results():
     _serve(reqs, streams=1, max_batch=4, hbm_budget=256 << 20, staging_bytes=4 << 20)
     for r in reqs:
         _same(r, _alone(r))
+
+
+def test_requests_with_their_own_padding_and_quality():
+    """tabi_submit_with: requests of mixed padding and quality in one
+    context (batched only with same-setting neighbours); each result equals
+    tabi_pack of that request alone with its settings, and re-packs keep
+    their atlas's settings."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_07782_amd as tabi
+    from paper_2602_07782_amd import synth
+    rng = np.random.default_rng(515)
+    mix = synth.CONFIGS["mixed2k"]["mix"]
+    ctx = tabi.ServeContext(quality=2, padding=2, streams=3, max_batch=8, device_bytes=512 << 20,
+                            staging_bytes=8 << 20)
+    reqs = []
+    for i in range(24):
+        p, q = int(rng.choice([0, 1, 2, 5])), int(rng.integers(0, 3))
+        inp = synth.make_custom(int(rng.integers(20, 300)), 512, 512, p, q, 1.2, 1.2, mix, 5150 + i)
+        aid, t = ctx.submit(inp.xy, inp.offsets, inp.atlas_w, inp.atlas_h, padding=p, quality=q)
+        reqs.append((t, aid, inp))
+    got = {}
+    while len(got) < len(reqs):
+        for ticket, aid, status, batch, lat, out in ctx.poll(wait=True):
+            assert status == tabi.TABI_OK
+            got[ticket] = out
+    # a re-pack of the first atlas keeps its padding and quality
+    t0, aid0, inp0 = reqs[0]
+    idx = np.array([0, 2], np.int32)
+    polys = [inp0.chart(c) for c in range(inp0.n)]
+    donor = reqs[1][2]
+    for j, c in enumerate(idx):
+        polys[c] = donor.chart(j)
+    nxy, noff = synth.pack_csr(polys)
+    new_inp = synth.AtlasInput(nxy, noff, inp0.atlas_w, inp0.atlas_h, inp0.padding, inp0.quality)
+    sxy, soff = synth.pack_csr([donor.chart(j) for j in range(len(idx))])
+    tr = ctx.repack(aid0, idx, sxy, soff, inp0.n)
+    while tr not in got:
+        for ticket, aid, status, batch, lat, out in ctx.poll(wait=True):
+            assert status == tabi.TABI_OK
+            got[ticket] = out
+    st = ctx.stats()
+    ctx.close()
+    _say("mixed-setting serving stats", st)
+    from types import SimpleNamespace
+    for t, aid, inp in reqs + [(tr, aid0, new_inp)]:
+        xy, ori, sc = got[t]
+        r = SimpleNamespace(rid=t, inp=inp, result=(xy, ori, float(sc[0])))
+        _same(r, _alone(r))
