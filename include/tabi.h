@@ -90,6 +90,28 @@ int tabi_pack(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atl
               int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
               float* out_scale, tabi_stream_t stream);
 
+/* Charts of one or more boundary loops each (a mesh chart's outer boundary
+ * and holes, or several islands packed as one chart; all device arrays):
+ * loop l is vertices [loop_offsets[l], loop_offsets[l+1]) of xy (Q8,
+ * loop_offsets[0] = 0), chart c is loops [chart_loops[c], chart_loops[c+1])
+ * (chart_loops[0] = 0, at least one loop per chart, total_loops of them). */
+typedef struct {
+  const int32_t* xy;
+  const int32_t* loop_offsets;
+  const int32_t* chart_loops;
+  int32_t total_loops;
+} tabi_charts_loops;
+
+/* tabi_pack for charts of several loops: the proxies (Sec. 4.1.1) bound the
+ * edges and vertices of every loop, and the area that bounds the scale from
+ * above is the largest loop's less all others' (exact for an outer loop with
+ * holes, a lower bound for islands, so no feasible scale is skipped).  A
+ * chart with a loop of fewer than 3 vertices is degenerate (out_scale -1).
+ * Outputs and errors as tabi_pack. */
+int tabi_pack_loops(const tabi_charts_loops* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+                    int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
+                    float* out_scale, tabi_stream_t stream);
+
 /* The method's knobs (Sec. 5 "Ablations"; App. D, local-AABB count and t_opt
  * tables), for the ablation variants and sweeps.  The quality presets are
  * {2, 5, FULL}, {5, 2, FULL} and {10, -1, FULL}.

@@ -60,8 +60,13 @@ def lib():
         L.tabi_oracle_pairs.argtypes = [I32P, I32P, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, I32P, U8P]
         L.orc_prep_chart.argtypes = [I32P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(OrcChart)]
+        L.orc_prep_chart_loops.argtypes = [I32P, I32P, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(OrcChart)]
         L.orc_prep_chart_ex.argtypes = [I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.POINTER(OrcChart)]
+        L.tabi_oracle_pack_loops.argtypes = [I32P, I32P, I32P, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, I32P,
+                                             U8P, ctypes.POINTER(ctypes.c_float), I32P]
         L.tabi_oracle_pack_method.argtypes = [I32P, I32P, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_int32, ctypes.c_int32, I32P, U8P,
@@ -121,6 +126,34 @@ def pack_method(inp, K, topt, variant):
     if rc != 0:
         raise ValueError(f"oracle rejected the arguments (rc={rc})")
     return oxy[:2 * n].reshape(n, 2), ori[:n], float(sc.value), int(kk.value)
+
+
+def pack_loops(inp):
+    """Whole pack of a LoopsInput (charts of several loops) -> as pack()."""
+    n = inp.n
+    xy = _c(inp.xy, np.int32)
+    lo, cl = _c(inp.loop_offsets, np.int32), _c(inp.chart_loops, np.int32)
+    oxy = np.zeros(max(2 * n, 1), np.int32)
+    ori = np.zeros(max(n, 1), np.uint8)
+    sc = ctypes.c_float(0)
+    kk = ctypes.c_int32(0)
+    rc = lib().tabi_oracle_pack_loops(_p32(xy), _p32(lo), _p32(cl), n, inp.atlas_w, inp.atlas_h,
+                                      inp.padding, inp.quality, _p32(oxy),
+                                      ori.ctypes.data_as(U8P), ctypes.byref(sc), ctypes.byref(kk))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the arguments (rc={rc})")
+    return oxy[:2 * n].reshape(n, 2), ori[:n], float(sc.value), int(kk.value)
+
+
+def prep_chart_loops(loops_q8, K):
+    """Proxy record of a chart of several loops (list of (m,2) Q8 arrays)."""
+    v = np.ascontiguousarray(np.concatenate([np.asarray(L).reshape(-1) for L in loops_q8]),
+                             np.int32)
+    lofs = np.zeros(len(loops_q8) + 1, np.int32)
+    lofs[1:] = np.cumsum([len(L) for L in loops_q8])
+    ch = OrcChart()
+    lib().orc_prep_chart_loops(_p32(v), _p32(lofs), len(loops_q8), int(K), ctypes.byref(ch))
+    return ch
 
 
 def prep_chart_ex(verts_q8, K, use_obb):

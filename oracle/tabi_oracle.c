@@ -100,12 +100,12 @@ static void direction(int m, int64_t* C, int64_t* S) {
  * values over polygon-inside-slab lie on the boundary clipped to the slab:
  * edge endpoints inside it, and crossings of edges with the two slab lines.
  * Rounded outward to whole Q8 units.                                        */
-static void slice_range(const int64_t* A, const int64_t* B, int nv, int64_t E, int K, int j,
-                        int64_t* lo, int64_t* hi) {
+static void slice_range(const int64_t* A, const int64_t* B, const int* nxt, int nv, int64_t E,
+                        int K, int j, int64_t* lo, int64_t* hi) {
   int64_t L = (int64_t)j * E, R = (int64_t)(j + 1) * E;
   int64_t l = INT64_MAX, h = INT64_MIN;
   for (int i = 0; i < nv; ++i) {
-    int i2 = (i + 1) % nv;
+    int i2 = nxt[i];  /* the edge to the next vertex of the same loop */
     int64_t a1 = (int64_t)K * A[i], a2 = (int64_t)K * A[i2];
     int64_t b1 = B[i], b2 = B[i2];
     if (L <= a1 && a1 <= R) { l = mini64(l, b1); h = maxi64(h, b1); }
@@ -124,10 +124,18 @@ static void slice_range(const int64_t* A, const int64_t* B, int nv, int64_t E, i
   *hi = h;
 }
 
-int orc_prep_chart_ex(const int32_t* xy, int32_t nv, int32_t K, int32_t use_obb, orc_chart* ch) {
+/* A chart of nl boundary loops: loop l holds vertices [lofs[l], lofs[l+1])
+ * of xy (lofs[0] = 0).  One loop is the common case; a mesh chart with holes
+ * has an outer loop and hole loops, and a chart may also hold several
+ * islands.  The proxies bound every loop's edges and vertices. */
+static int prep_loops(const int32_t* xy, const int32_t* lofs, int nl, int32_t K, int32_t use_obb,
+                      orc_chart* ch) {
   memset(ch, 0, sizeof(*ch));
   ch->K = K;
-  if (nv < 3) return 0;
+  if (nl < 1) return 0;
+  for (int l = 0; l < nl; ++l)
+    if (lofs[l + 1] - lofs[l] < 3) return 0;
+  const int nv = lofs[nl];
   int64_t xmin = INT64_MAX, ymin = INT64_MAX, xmax = INT64_MIN, ymax = INT64_MIN;
   for (int i = 0; i < nv; ++i) {
     int64_t x = xy[2 * i], y = xy[2 * i + 1];
@@ -154,19 +162,37 @@ int orc_prep_chart_ex(const int32_t* xy, int32_t nv, int32_t K, int32_t use_obb,
   int64_t W = ch->rot ? h0 : w0, H = ch->rot ? w0 : h0;
   ch->W = W;
   ch->H = H;
+  int* nxt = (int*)malloc(sizeof(int) * nv);
+  for (int l = 0; l < nl; ++l)
+    for (int i = lofs[l]; i < lofs[l + 1]; ++i) nxt[i] = i + 1 < lofs[l + 1] ? i + 1 : lofs[l];
 
-  /* twice the area (shoelace) */
-  i128 s = 0;
-  for (int i = 0; i < nv; ++i) {
-    int i2 = (i + 1) % nv;
-    s += (i128)u[i] * v[i2] - (i128)u[i2] * v[i];
+  /* twice the area (shoelace), per loop; the chart's area is taken as the
+   * largest loop's less every other loop's: exact for an outer loop with
+   * holes, and a lower bound otherwise, which keeps the area bound on the
+   * scale rigorous (it may only start the search higher) */
+  i128 amax = 0, arest = 0;
+  for (int l = 0; l < nl; ++l) {
+    i128 s = 0;
+    for (int i = lofs[l]; i < lofs[l + 1]; ++i)
+      s += (i128)u[i] * v[nxt[i]] - (i128)u[nxt[i]] * v[i];
+    if (s < 0) s = -s;
+    if (s > amax) { arest += amax; amax = s; }
+    else arest += s;
   }
-  ch->area2 = (int64_t)(s < 0 ? -s : s);
+  ch->area2 = (int64_t)(amax > arest ? amax - arest : 0);
 
   /* local AABBs: K equal slices along x (giving top/bottom bounds) and along
    * y (giving left/right bounds) (Sec. 4.1.1, App. A) */
-  for (int j = 0; j < K; ++j) slice_range(u, v, nv, W, K, j, &ch->ylo[j], &ch->yhi[j]);
-  for (int j = 0; j < K; ++j) slice_range(v, u, nv, H, K, j, &ch->xlo[j], &ch->xhi[j]);
+  for (int j = 0; j < K; ++j) slice_range(u, v, nxt, nv, W, K, j, &ch->ylo[j], &ch->yhi[j]);
+  for (int j = 0; j < K; ++j) slice_range(v, u, nxt, nv, H, K, j, &ch->xlo[j], &ch->xhi[j]);
+  free(nxt);
+  /* A slice that meets no loop (only possible between islands of one
+   * chart: a connected loop meets every slice) takes the slice's whole box,
+   * a conservative local AABB. */
+  for (int j = 0; j < K; ++j) {
+    if (ch->ylo[j] > ch->yhi[j]) { ch->ylo[j] = 0; ch->yhi[j] = H; }
+    if (ch->xlo[j] > ch->xhi[j]) { ch->xlo[j] = 0; ch->xhi[j] = W; }
+  }
 
   /* orientation (App. A, "Computing Chart Orientations").  Empty area above
    * the top boundary vs below the bottom boundary: reflect vertically when
@@ -252,6 +278,16 @@ int orc_prep_chart_ex(const int32_t* xy, int32_t nv, int32_t K, int32_t use_obb,
   free(v);
   ch->valid = 1;
   return 1;
+}
+
+int orc_prep_chart_loops(const int32_t* xy, const int32_t* lofs, int32_t nl, int32_t K,
+                         orc_chart* ch) {
+  return prep_loops(xy, lofs, nl, K, 1, ch);
+}
+
+int orc_prep_chart_ex(const int32_t* xy, int32_t nv, int32_t K, int32_t use_obb, orc_chart* ch) {
+  const int32_t lofs[2] = {0, nv};
+  return prep_loops(xy, lofs, 1, K, use_obb, ch);
 }
 
 int orc_prep_chart(const int32_t* xy, int32_t nv, int32_t K, orc_chart* ch) {
@@ -897,13 +933,26 @@ static void sort_charts(const orc_chart* ch, int n, int* perm) {
 
 /* Whole pack with the given knobs (K slices, t_opt percent, OBB used,
  * static rows). */
+/* Whole pack of prepared charts (ok: every chart valid). */
+static int pack_charts(orc_chart* ch, int ok, int32_t n, int32_t Wa, int32_t Ha, int32_t p, int topt,
+                       int static_rows, int32_t* out_xy, uint8_t* out_orient, float* out_scale,
+                       int32_t* out_k);
+
 static int pack_with(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa, int32_t Ha,
                      int32_t p, int K, int topt, int use_obb, int static_rows, int32_t* out_xy,
                      uint8_t* out_orient, float* out_scale, int32_t* out_k) {
   if (n == 0) { *out_scale = 1.0f; if (out_k) *out_k = 64; return 0; }
   orc_chart* ch = calloc(n, sizeof(orc_chart));
+  const int ok = prep_all(xy, offsets, n, K, use_obb, ch);
+  return pack_charts(ch, ok, n, Wa, Ha, p, topt, static_rows, out_xy, out_orient, out_scale,
+                     out_k);
+}
+
+static int pack_charts(orc_chart* ch, int ok, int32_t n, int32_t Wa, int32_t Ha, int32_t p, int topt,
+                       int static_rows, int32_t* out_xy, uint8_t* out_orient, float* out_scale,
+                       int32_t* out_k) {
   for (int c = 0; c < n; ++c) { out_xy[2 * c] = -1; out_xy[2 * c + 1] = -1; out_orient[c] = 0; }
-  if (!prep_all(xy, offsets, n, K, use_obb, ch)) {
+  if (!ok) {
     free(ch);
     *out_scale = -1.0f;
     if (out_k) *out_k = -1;
@@ -946,6 +995,33 @@ int tabi_oracle_pack(const int32_t* xy, const int32_t* offsets, int32_t n, int32
   int K, topt;
   orc_quality(q, n, &K, &topt);
   return pack_with(xy, offsets, n, Wa, Ha, p, K, topt, 1, 0, out_xy, out_orient, out_scale, out_k);
+}
+
+int tabi_oracle_pack_loops(const int32_t* xy, const int32_t* loop_offsets,
+                           const int32_t* chart_loops, int32_t n, int32_t Wa, int32_t Ha,
+                           int32_t p, int32_t q, int32_t* out_xy, uint8_t* out_orient,
+                           float* out_scale, int32_t* out_k) {
+  if (n < 0 || (n > 0 && (!xy || !loop_offsets || !chart_loops)) || Wa <= 0 || Ha <= 0 || p < 0 ||
+      Wa + p > 16384 || Ha + p > 16384 || q < 0 || q > 2)
+    return -1;
+  if (n > 0 && (chart_loops[0] != 0 || loop_offsets[0] != 0)) return -1;
+  for (int c = 0; c < n; ++c)
+    if (chart_loops[c + 1] <= chart_loops[c]) return -1;  /* at least one loop per chart */
+  for (int l = 0; n > 0 && l < chart_loops[n]; ++l)
+    if (loop_offsets[l + 1] < loop_offsets[l]) return -1;
+  int K, topt;
+  orc_quality(q, n, &K, &topt);
+  if (n == 0) { *out_scale = 1.0f; if (out_k) *out_k = 64; return 0; }
+  orc_chart* ch = calloc(n, sizeof(orc_chart));
+  int ok = 1;
+  for (int c = 0; c < n; ++c) {
+    const int l0 = chart_loops[c], nl = chart_loops[c + 1] - l0, v0 = loop_offsets[l0];
+    int32_t* lofs = malloc(sizeof(int32_t) * (nl + 1));
+    for (int l = 0; l <= nl; ++l) lofs[l] = loop_offsets[l0 + l] - v0;
+    if (!prep_loops(xy + 2 * (int64_t)v0, lofs, nl, K, 1, &ch[c])) ok = 0;
+    free(lofs);
+  }
+  return pack_charts(ch, ok, n, Wa, Ha, p, topt, 0, out_xy, out_orient, out_scale, out_k);
 }
 
 int tabi_oracle_pack_method(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,

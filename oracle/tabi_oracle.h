@@ -57,8 +57,22 @@ void orc_row_proxies(const orc_chart* ch, int32_t k, int32_t* h, int32_t* la, in
 int orc_prep_chart_ex(const int32_t* xy, int32_t nverts, int32_t K, int32_t use_obb,
                       orc_chart* out);
 
+/* Proxy construction for a chart of nl loops: loop l is vertices
+ * [lofs[l], lofs[l+1]) of xy (lofs[0] = 0). */
+int orc_prep_chart_loops(const int32_t* xy, const int32_t* lofs, int32_t nl, int32_t K,
+                         orc_chart* out);
+
 /* Quality preset -> slices K and t_opt percent for a set of n charts. */
 void orc_quality(int32_t quality, int32_t n, int32_t* K, int32_t* topt);
+
+/* Whole pack of charts given as one or more boundary loops each: loop l is
+ * vertices [loop_offsets[l], loop_offsets[l+1]) of xy, chart c is loops
+ * [chart_loops[c], chart_loops[c+1]) (at least one).  Outputs as
+ * tabi_oracle_pack. */
+int tabi_oracle_pack_loops(const int32_t* xy, const int32_t* loop_offsets,
+                           const int32_t* chart_loops, int32_t n, int32_t Wa, int32_t Ha,
+                           int32_t p, int32_t q, int32_t* out_xy, uint8_t* out_orient,
+                           float* out_scale, int32_t* out_k);
 
 /* Variants of the method (Sec. 5 ablations). */
 enum { ORC_FULL = 0, ORC_TIGHT_ONLY = 1, ORC_BALANCED_ONLY = 2 };

@@ -32,6 +32,11 @@ class Charts(ctypes.Structure):
                 ("total_verts", ctypes.c_int32)]
 
 
+class ChartsLoops(ctypes.Structure):
+    _fields_ = [("xy", ctypes.c_void_p), ("loop_offsets", ctypes.c_void_p),
+                ("chart_loops", ctypes.c_void_p), ("total_loops", ctypes.c_int32)]
+
+
 class Method(ctypes.Structure):
     _fields_ = [("slices", ctypes.c_int32), ("topt_percent", ctypes.c_int32),
                 ("variant", ctypes.c_int32)]
@@ -54,7 +59,7 @@ class Done(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ["tabi_pack", "tabi_pack_method", "tabi_pack_many_method", "tabi_pack_noalloc",
+EXPORTS = ["tabi_pack", "tabi_pack_loops", "tabi_pack_method", "tabi_pack_many_method", "tabi_pack_noalloc",
            "tabi_pack_many", "tabi_pack_many_ws", "tabi_submit_with", "tabi_pack_many_workspace_bytes",
            "tabi_record_bytes", "tabi_prep_records", "tabi_splice_records",
            "tabi_pack_many_records", "tabi_debug_order", "tabi_debug_pairs",
@@ -79,6 +84,8 @@ def lib():
         L.tabi_pack.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, i32, vp, vp, vp, vp]
         L.tabi_pack_noalloc.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, i32, vp, vp,
                                         vp, vp]
+        L.tabi_pack_loops.argtypes = [ctypes.POINTER(ChartsLoops), i32, i32, i32, i32, i32, vp,
+                                      vp, vp, vp]
         L.tabi_pack_method.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32,
                                        ctypes.POINTER(Method), vp, vp, vp, vp]
         L.tabi_pack_many_method.argtypes = [vp, vp, vp, i32, vp, i32, i32, i32, i32,
@@ -176,6 +183,26 @@ def pack(xy, offsets, atlas_w, atlas_h, padding, quality, stream=None, device="c
     out_sc = torch.empty(1, dtype=torch.float32, device=xy.device)
     _check(lib().tabi_pack(ctypes.byref(ch), n, int(atlas_w), int(atlas_h), int(padding),
                            int(quality), _ptr(out_xy), _ptr(out_or), _ptr(out_sc), _stream(stream)))
+    return out_xy, out_or, out_sc
+
+
+def pack_loops(xy, loop_offsets, chart_loops, atlas_w, atlas_h, padding, quality, stream=None,
+               device="cuda"):
+    """tabi_pack_loops: charts of one or more boundary loops (loop l:
+    vertices [loop_offsets[l], loop_offsets[l+1]), chart c: loops
+    [chart_loops[c], chart_loops[c+1])).  Returns as pack()."""
+    torch = _torch()
+    xy = _dev_i32(xy, device)
+    lo = _dev_i32(loop_offsets, device)
+    cl = _dev_i32(chart_loops, device)
+    n = int(cl.numel()) - 1
+    ch = ChartsLoops(_ptr(xy).value, _ptr(lo).value, _ptr(cl).value, int(lo.numel()) - 1)
+    out_xy = torch.empty((max(n, 0), 2), dtype=torch.int32, device=xy.device)
+    out_or = torch.empty(max(n, 0), dtype=torch.uint8, device=xy.device)
+    out_sc = torch.empty(1, dtype=torch.float32, device=xy.device)
+    _check(lib().tabi_pack_loops(ctypes.byref(ch), n, int(atlas_w), int(atlas_h), int(padding),
+                                 int(quality), _ptr(out_xy), _ptr(out_or), _ptr(out_sc),
+                                 _stream(stream)))
     return out_xy, out_or, out_sc
 
 

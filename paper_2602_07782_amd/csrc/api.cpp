@@ -325,11 +325,12 @@ int check_common(int32_t n, int32_t padding, int32_t quality) {
 }
 
 hipError_t run_front(Job& j, const int32_t* xy, const int32_t* voff, const int32_t* aoff,
-                     const int32_t* awh, int32_t aw, int32_t ah, hipStream_t st) {
+                     const int32_t* awh, int32_t aw, int32_t ah, hipStream_t st,
+                     const int32_t* cloop = nullptr) {
   hipError_t e;
   {
     StageScope t(ST_PREP, st);
-    e = launch_prep(j.P, j.W, xy, voff, aoff, awh, aw, ah, st);
+    e = launch_prep(j.P, j.W, xy, voff, aoff, awh, aw, ah, st, cloop);
   }
   if (e == hipSuccess) {
     StageScope t(ST_SORT, st);
@@ -495,8 +496,9 @@ int pack_many_impl(const int32_t* xy, const int32_t* vert_offsets, const int32_t
   return rc;
 }
 
-int single_front(Job& j, const tabi_charts* ch, int32_t aw, int32_t ah, hipStream_t st) {
-  hipError_t e = run_front(j, ch->xy, ch->offsets, nullptr, nullptr, aw, ah, st);
+int single_front(Job& j, const tabi_charts* ch, int32_t aw, int32_t ah, hipStream_t st,
+                 const int32_t* cloop = nullptr) {
+  hipError_t e = run_front(j, ch->xy, ch->offsets, nullptr, nullptr, aw, ah, st, cloop);
   return e == hipSuccess ? TABI_OK : hip_fail(e);
 }
 
@@ -504,7 +506,7 @@ int single_front(Job& j, const tabi_charts* ch, int32_t aw, int32_t ah, hipStrea
 // workgroup per scale, no host round trip.
 int pack_single(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
                 int32_t padding, int32_t code, int32_t* out_xy, uint8_t* out_orient,
-                float* out_scale, tabi_stream_t stream) {
+                float* out_scale, tabi_stream_t stream, const int32_t* cloop = nullptr) {
   if (check_common_code(n, padding, code) || bad_atlas(atlas_w, atlas_h, padding) || !charts ||
       !out_scale || (n > 0 && (!charts->xy || !charts->offsets || !out_xy || !out_orient)))
     return TABI_EINVAL;
@@ -512,7 +514,7 @@ int pack_single(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t a
   Job j;
   int rc = make_job(j, make_params(1, n, code, padding, 64, 0, n > 0 ? n : 1, atlas_w + padding),
                     st);
-  if (!rc) rc = single_front(j, charts, atlas_w, atlas_h, st);
+  if (!rc) rc = single_front(j, charts, atlas_w, atlas_h, st, cloop);
   if (!rc) {
     const int all[1] = {64};
     hipError_t e = run_search(j, all, 1, out_xy, out_orient, out_scale, st);
@@ -603,6 +605,19 @@ int tabi_pack(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atl
   if (quality < 0 || quality > 2) return TABI_EINVAL;
   return pack_single(charts, n, atlas_w, atlas_h, padding, quality, out_xy, out_orient, out_scale,
                      stream);
+}
+
+int tabi_pack_loops(const tabi_charts_loops* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+                    int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
+                    float* out_scale, tabi_stream_t stream) {
+  if (quality < 0 || quality > 2 || !charts || charts->total_loops < 0 ||
+      (n > 0 && (!charts->xy || !charts->loop_offsets || !charts->chart_loops)))
+    return TABI_EINVAL;
+  // the loops' vertex offsets stand where the charts' would, and the chart
+  // -> loops table tells the proxy kernel which loops make a chart
+  const tabi_charts as_charts{charts->xy, charts->loop_offsets, 0};
+  return pack_single(&as_charts, n, atlas_w, atlas_h, padding, quality, out_xy, out_orient,
+                     out_scale, stream, charts->chart_loops);
 }
 
 int tabi_pack_method(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,

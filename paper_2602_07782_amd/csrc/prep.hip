@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
                                               const int32_t* __restrict__ voff,
                                               const int32_t* __restrict__ atlas_off,
                                               const int32_t* __restrict__ atlas_wh, int single_w,
-                                              int single_h) {
+                                              int single_h, const int32_t* __restrict__ cloop) {
   __shared__ int32_t sl[PREP_CH][4][KMAX];
   {  // atlas descriptors: thread i of the grid initialises atlas i
     const int ai = blockIdx.x * blockDim.x + threadIdx.x;
@@ -153,7 +153,20 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
   }
   const int local = c - (atlas_off ? atlas_off[a] : 0);
   if (lane == 0) w.chart_atlas[c] = a;
-  const int v0 = voff[c], nv = voff[c + 1] - v0;
+  // vertices of the chart: one loop (voff: chart vertex offsets), or its
+  // loops [cloop[c], cloop[c+1]) when cloop is given (voff: loop vertex
+  // offsets); each vertex's edge runs to the next vertex of its own loop
+  const int l0 = cloop ? cloop[c] : 0, l1 = cloop ? cloop[c + 1] : 0;
+  const int v0 = cloop ? voff[l0] : voff[c], nv = (cloop ? voff[l1] : voff[c + 1]) - v0;
+  auto next_of = [&](int i) {
+    if (!cloop) return (i + 1 == nv) ? 0 : i + 1;
+    int l = l0;
+    while (l + 1 < l1 && voff[l + 1] <= v0 + i) ++l;
+    return (v0 + i + 1 == voff[l + 1]) ? voff[l] - v0 : i + 1;
+  };
+  int short_loop = 0;  // a loop of fewer than 3 vertices
+  if (cloop)
+    for (int l = l0 + lane; l < l1; l += PREP_G) short_loop |= voff[l + 1] - voff[l] < 3;
   const int2* V = reinterpret_cast<const int2*>(xy) + v0;
 
   int32_t xmn = BIG, xmx = -BIG, ymn = BIG, ymx = -BIG;
@@ -166,7 +179,7 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
   }
   xmn = row_min(xmn); xmx = row_max(xmx);
   ymn = row_min(ymn); ymx = row_max(ymx);
-  range_bad = row_max(range_bad);
+  range_bad = row_max(range_bad | short_loop);
   const int32_t W0 = xmx - xmn, H0 = ymx - ymn;
   Chart* out = &w.recs[c];
   if (nv < 3 || range_bad || W0 <= 0 || H0 <= 0) {
@@ -196,7 +209,7 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
 
   uint64_t area = 0;
   for (int i = lane; i < nv; i += PREP_G) {
-    int i2 = (i + 1 == nv) ? 0 : i + 1;
+    const int i2 = next_of(i);
     int64_t u1, v1, u2, v2;
     local_uv(i, u1, v1);
     local_uv(i2, u2, v2);
@@ -207,11 +220,36 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
   area = row_sum_u64(area);
   int64_t area2 = (int64_t)area;
   if (area2 < 0) area2 = -area2;
+  if (cloop && l1 - l0 > 1) {
+    // several loops: the largest loop's area less every other loop's (exact
+    // for an outer loop with holes, a lower bound otherwise, which keeps the
+    // area bound on the scale rigorous)
+    int64_t amax = 0, arest = 0;
+    for (int l = l0; l < l1; ++l) {
+      uint64_t al = 0;
+      for (int i = voff[l] - v0 + lane; i < voff[l + 1] - v0; i += PREP_G) {
+        const int i2 = (v0 + i + 1 == voff[l + 1]) ? voff[l] - v0 : i + 1;
+        int64_t u1, v1, u2, v2;
+        local_uv(i, u1, v1);
+        local_uv(i2, u2, v2);
+        al += (uint64_t)(u1 * v2) - (uint64_t)(u2 * v1);
+      }
+      int64_t a = (int64_t)row_sum_u64(al);
+      if (a < 0) a = -a;
+      if (a > amax) { arest += amax; amax = a; }
+      else arest += a;
+    }
+    area2 = amax > arest ? amax - arest : 0;
+  }
   wave_sync();
 
-  // orientation: lanes j < K hold slice j
+  // orientation: lanes j < K hold slice j.  A slice that meets no loop
+  // (only between islands of one chart: a connected loop meets every slice)
+  // takes the slice's whole box, a conservative local AABB.
   int32_t sylo = 0, syhi = 0, sxlo = 0, sxhi = 0;
   if (lane < K) { sylo = ylo[lane]; syhi = yhi[lane]; sxlo = xlo[lane]; sxhi = xhi[lane]; }
+  if (sylo > syhi) { sylo = 0; syhi = H; }
+  if (sxlo > sxhi) { sxlo = 0; sxhi = W; }
   const bool in = lane < K;
   // empty area above the top boundary vs below the bottom boundary
   int64_t top_area = (int64_t)row_sum_u64(in ? (uint64_t)(int64_t)sylo : 0);
@@ -649,13 +687,13 @@ hipError_t launch_splice(Chart* dst, const int32_t* idx, int m, const Chart* src
 
 hipError_t launch_prep(const Params& P, const Work& w, const int32_t* xy, const int32_t* voff,
                        const int32_t* atlas_off, const int32_t* atlas_wh, int single_w,
-                       int single_h, hipStream_t st) {
+                       int single_h, hipStream_t st, const int32_t* cloop) {
   // the proxy kernel also writes the atlas descriptors (enough blocks for
   // both)
   if (P.N > 0) {
     const int blocks = max((P.N + PREP_CH - 1) / PREP_CH, w.desc ? (P.count + 255) / 256 : 0);
     hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, st, P, w, xy, voff, atlas_off, atlas_wh,
-                       single_w, single_h);
+                       single_w, single_h, cloop);
   } else if (w.desc) {
     hipLaunchKernelGGL(k_init, dim3((P.count + 255) / 256), dim3(256), 0, st, P, w, atlas_off,
                        atlas_wh, single_w, single_h);

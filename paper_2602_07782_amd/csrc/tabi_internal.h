@@ -94,9 +94,12 @@ __device__ inline bool round_idle(const Work& w, int round) {
 }
 
 // Launchers (one per kernel), all enqueue on `st`.
+// cloop: charts of several boundary loops (chart c: loops [cloop[c],
+// cloop[c+1]), voff then holds the loops' vertex offsets); nullptr: one loop
+// per chart (voff: the charts' vertex offsets)
 hipError_t launch_prep(const Params& P, const Work& w, const int32_t* xy, const int32_t* voff,
                        const int32_t* atlas_off, const int32_t* atlas_wh, int single_w,
-                       int single_h, hipStream_t st);
+                       int single_h, hipStream_t st, const int32_t* cloop = nullptr);
 hipError_t launch_from_records(const Params& P, const Work& w, const Chart* in,
                                const int32_t* atlas_off, const int32_t* atlas_wh, hipStream_t st);
 hipError_t launch_splice(Chart* dst, const int32_t* idx, int m, const Chart* src, hipStream_t st);

@@ -336,6 +336,126 @@ def make_tss(instance: int = 0, n: int | None = None, atlas: int | None = None,
     return AtlasInput(xy, offs, side, side, TSS["p"], TSS["q"] if quality is None else quality)
 
 
+@dataclasses.dataclass
+class LoopsInput:
+    """Charts of one or more boundary loops each: loop l is vertices
+    [loop_offsets[l], loop_offsets[l+1]) of xy (Q8), chart c is loops
+    [chart_loops[c], chart_loops[c+1])."""
+
+    xy: np.ndarray
+    loop_offsets: np.ndarray
+    chart_loops: np.ndarray
+    atlas_w: int
+    atlas_h: int
+    padding: int
+    quality: int
+
+    @property
+    def n(self) -> int:
+        return int(self.chart_loops.shape[0] - 1)
+
+    def loops(self, c: int):
+        out = []
+        for l in range(int(self.chart_loops[c]), int(self.chart_loops[c + 1])):
+            a, b = int(self.loop_offsets[l]), int(self.loop_offsets[l + 1])
+            out.append(self.xy[2 * a:2 * b].reshape(-1, 2))
+        return out
+
+
+def loops_csr(charts, W, H, p, q):
+    """LoopsInput from a list of charts, each a list of Q8 loops."""
+    loops = [L for ch in charts for L in ch]
+    xy, lofs = pack_csr(loops)
+    cl = np.zeros(len(charts) + 1, np.int32)
+    cl[1:] = np.cumsum([len(ch) for ch in charts])
+    return LoopsInput(xy, lofs, cl, W, H, p, q)
+
+
+def make_loops(n, W, H, p, q, seed, hole_frac=0.4, island_frac=0.2, fill=0.9):
+    """Mesh-like charts: stars and L/U shapes, some with one or two holes
+    (smaller loops inside, opposite orientation), some made of two islands
+    side by side; log-normal areas (sigma 1.2) summing to `fill` of the
+    atlas.  Returns (LoopsInput, the charts' outer loops only as an
+    AtlasInput; islands have no single outer loop, that entry is None)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mix = CONFIGS["mixed2k"]["mix"]
+    base = generate_charts(n, W, H, 1.2, fill, mix, seed + 1)
+    charts, outers = [], []
+    for P in base:
+        P = P.astype(np.int64)
+        r = rng.uniform()
+        c = P.mean(axis=0)
+        if r < hole_frac:
+            holes = []
+            for _ in range(int(rng.integers(1, 3))):
+                # a small square well inside: shrink towards an inner point until it fits
+                ext = (P.max(0) - P.min(0)).min()
+                hs = max(2, int(ext * rng.uniform(0.05, 0.12)))
+                for t in np.linspace(0.0, 0.8, 9):
+                    o = (c + t * (P[int(rng.integers(0, len(P)))] - c)).astype(np.int64)
+                    Hq = np.array([o, o + [0, hs], o + [hs, hs], o + [hs, 0]], np.int64)
+                    if _inside_all(Hq, P) and all(not _overlap_box(Hq, h2) for h2 in holes):
+                        holes.append(Hq)
+                        break
+            charts.append([P] + holes)
+            outers.append(P)
+        elif r < hole_frac + island_frac:
+            # two islands: the shape and a shifted, smaller copy beside it
+            ext = P.max(0) - P.min(0)
+            Q = ((P - P.min(0)) // 2 + P.min(0) + [ext[0] + 4 * 256, 0]).astype(np.int64)
+            if polygon_is_simple(Q) and np.abs(Q).max() < (1 << 21):
+                charts.append([P, Q])
+                outers.append(None)
+            else:
+                charts.append([P])
+                outers.append(P)
+        else:
+            charts.append([P])
+            outers.append(P)
+    return loops_csr(charts, W, H, p, q), outers
+
+
+def _inside_all(Q, P):
+    """Every vertex of Q strictly inside polygon P, and no edge of Q crossing P
+    (even-odd test on the vertices; edges checked against P's edges)."""
+    def inside(pt):
+        x, y = pt
+        c = False
+        m = len(P)
+        for i in range(m):
+            (x1, y1), (x2, y2) = P[i], P[(i + 1) % m]
+            if (y1 > y) != (y2 > y):
+                xc = x1 + (x2 - x1) * (y - y1) / (y2 - y1)
+                if xc == x:
+                    return False
+                if xc > x:
+                    c = not c
+        return c
+    if not all(inside(q) for q in Q):
+        return False
+    both = np.concatenate([P, Q])
+    return polygon_is_simple(P) and not _edges_cross(P, Q)
+
+
+def _edges_cross(P, Q):
+    for i in range(len(P)):
+        a, b = P[i], P[(i + 1) % len(P)]
+        for j in range(len(Q)):
+            c, d = Q[j], Q[(j + 1) % len(Q)]
+            d1 = _orient(*a, *b, *c)
+            d2 = _orient(*a, *b, *d)
+            d3 = _orient(*c, *d, *a)
+            d4 = _orient(*c, *d, *b)
+            if d1 * d2 <= 0 and d3 * d4 <= 0:
+                return True
+    return False
+
+
+def _overlap_box(A, B):
+    return not (A[:, 0].max() < B[:, 0].min() or B[:, 0].max() < A[:, 0].min() or
+                A[:, 1].max() < B[:, 1].min() or B[:, 1].max() < A[:, 1].min())
+
+
 def pack_csr(polys):
     offs = np.zeros(len(polys) + 1, np.int32)
     offs[1:] = np.cumsum([p.shape[0] for p in polys])
