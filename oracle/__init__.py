@@ -64,6 +64,11 @@ def lib():
                                            ctypes.POINTER(OrcChart)]
         L.orc_prep_chart_ex.argtypes = [I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.POINTER(OrcChart)]
+        L.orc_prerotate.argtypes = [I32P, ctypes.c_int32, I32P, I32P]
+        L.tabi_oracle_pack_prerotate.argtypes = [I32P, I32P, ctypes.c_int32, ctypes.c_int32,
+                                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                 I32P, U8P, U8P, ctypes.POINTER(ctypes.c_float),
+                                                 I32P]
         L.tabi_oracle_pack_loops.argtypes = [I32P, I32P, I32P, ctypes.c_int32, ctypes.c_int32,
                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, I32P,
                                              U8P, ctypes.POINTER(ctypes.c_float), I32P]
@@ -126,6 +131,33 @@ def pack_method(inp, K, topt, variant):
     if rc != 0:
         raise ValueError(f"oracle rejected the arguments (rc={rc})")
     return oxy[:2 * n].reshape(n, 2), ori[:n], float(sc.value), int(kk.value)
+
+
+def prerotate(verts_q8):
+    """Pre-rotation of one chart: (rotated Q8 vertices (m,2), direction m)."""
+    v = _c(verts_q8, np.int32).reshape(-1)
+    out = np.zeros_like(v)
+    m = ctypes.c_int32(0)
+    lib().orc_prerotate(_p32(v), int(v.shape[0] // 2), _p32(out), ctypes.byref(m))
+    return out.reshape(-1, 2), int(m.value)
+
+
+def pack_prerotate(inp):
+    """Whole pack after pre-rotation -> (xy, orient, scale, k, directions)."""
+    n = inp.n
+    xy, off = _c(inp.xy, np.int32), _c(inp.offsets, np.int32)
+    oxy = np.zeros(max(2 * n, 1), np.int32)
+    ori = np.zeros(max(n, 1), np.uint8)
+    dirs = np.zeros(max(n, 1), np.uint8)
+    sc = ctypes.c_float(0)
+    kk = ctypes.c_int32(0)
+    rc = lib().tabi_oracle_pack_prerotate(_p32(xy), _p32(off), n, inp.atlas_w, inp.atlas_h,
+                                          inp.padding, inp.quality, _p32(oxy),
+                                          ori.ctypes.data_as(U8P), dirs.ctypes.data_as(U8P),
+                                          ctypes.byref(sc), ctypes.byref(kk))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the arguments (rc={rc})")
+    return oxy[:2 * n].reshape(n, 2), ori[:n], float(sc.value), int(kk.value), dirs[:n]
 
 
 def pack_loops(inp):

@@ -997,6 +997,87 @@ int tabi_oracle_pack(const int32_t* xy, const int32_t* offsets, int32_t n, int32
   return pack_with(xy, offsets, n, Wa, Ha, p, K, topt, 1, 0, out_xy, out_orient, out_scale, out_k);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Pre-rotation of a chart to its tight box (Sec. 5, "Experimental Setup":
+ * UV charts are rotated so that their tight bounding boxes align with the
+ * axes before packing).  The box is sought, as for the OBB proxy, over a
+ * fixed set of directions, here 64 (m pi / 128, m = 0..63, which include
+ * the OBB's 8), as integer vectors 2^14 (cos, sin) rounded; the box of least
+ * area wins (exact comparison; ties keep the smaller m).  The chart is then
+ * turned about its box corner, (dx, dy) -> (C dx + S dy, -S dx + C dy) / 2^14
+ * rounded to the nearest Q8 unit (halves up), and moved so that its new box
+ * starts at (0, 0).  A chart the pack rejects anyway (fewer than 3 vertices,
+ * a coordinate outside (-2^22, 2^22)) is copied unchanged with m = 0.       */
+static void predir(int m, int64_t* C, int64_t* S) {
+  *C = llround(16384.0 * cos((double)m * M_PI / 128.0));
+  *S = llround(16384.0 * sin((double)m * M_PI / 128.0));
+}
+
+int orc_prerotate(const int32_t* xy, int32_t nv, int32_t* out, int32_t* m_out) {
+  int bad = nv < 3;
+  for (int i = 0; i < 2 * nv; ++i)
+    if (xy[i] <= -(1 << 22) || xy[i] >= (1 << 22)) bad = 1;
+  if (bad) {
+    for (int i = 0; i < 2 * nv; ++i) out[i] = xy[i];
+    *m_out = 0;
+    return 0;
+  }
+  int64_t xmin = INT64_MAX, ymin = INT64_MAX;
+  for (int i = 0; i < nv; ++i) {
+    xmin = mini64(xmin, xy[2 * i]);
+    ymin = mini64(ymin, xy[2 * i + 1]);
+  }
+  int best = 0;
+  i128 bext = 0, bN = 1;
+  for (int m = 0; m < 64; ++m) {
+    int64_t C, S;
+    predir(m, &C, &S);
+    int64_t a = INT64_MAX, b = INT64_MIN, e = INT64_MAX, f = INT64_MIN;
+    for (int i = 0; i < nv; ++i) {
+      int64_t dx = xy[2 * i] - xmin, dy = xy[2 * i + 1] - ymin;
+      int64_t p = C * dx + S * dy, q = -S * dx + C * dy;
+      a = mini64(a, p); b = maxi64(b, p);
+      e = mini64(e, q); f = maxi64(f, q);
+    }
+    i128 ext = (i128)(b - a) * (i128)(f - e), N = (i128)C * C + (i128)S * S;
+    if (m == 0 || ext * bN < bext * N) { best = m; bext = ext; bN = N; }
+  }
+  int64_t C, S, tx = INT64_MAX, ty = INT64_MAX;
+  predir(best, &C, &S);
+  for (int i = 0; i < nv; ++i) {
+    int64_t dx = xy[2 * i] - xmin, dy = xy[2 * i + 1] - ymin;
+    out[2 * i] = (int32_t)fdiv64(C * dx + S * dy + 8192, 16384);
+    out[2 * i + 1] = (int32_t)fdiv64(-S * dx + C * dy + 8192, 16384);
+    tx = mini64(tx, out[2 * i]);
+    ty = mini64(ty, out[2 * i + 1]);
+  }
+  for (int i = 0; i < nv; ++i) {
+    out[2 * i] -= (int32_t)tx;
+    out[2 * i + 1] -= (int32_t)ty;
+  }
+  *m_out = best;
+  return best;
+}
+
+int tabi_oracle_pack_prerotate(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                               int32_t Ha, int32_t p, int32_t q, int32_t* out_xy,
+                               uint8_t* out_orient, uint8_t* out_dir, float* out_scale,
+                               int32_t* out_k) {
+  if (check_args(xy, offsets, n, Wa, Ha, p, q)) return -1;
+  const int64_t V = n > 0 ? offsets[n] : 0;
+  int32_t* rxy = malloc(sizeof(int32_t) * (2 * V + 2));
+  for (int c = 0; c < n; ++c) {
+    int32_t m = 0;
+    orc_prerotate(xy + 2 * (int64_t)offsets[c], offsets[c + 1] - offsets[c],
+                  rxy + 2 * (int64_t)offsets[c], &m);
+    out_dir[c] = (uint8_t)m;
+  }
+  const int rc = tabi_oracle_pack(rxy, offsets, n, Wa, Ha, p, q, out_xy, out_orient, out_scale,
+                                  out_k);
+  free(rxy);
+  return rc;
+}
+
 int tabi_oracle_pack_loops(const int32_t* xy, const int32_t* loop_offsets,
                            const int32_t* chart_loops, int32_t n, int32_t Wa, int32_t Ha,
                            int32_t p, int32_t q, int32_t* out_xy, uint8_t* out_orient,

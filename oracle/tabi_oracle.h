@@ -74,6 +74,18 @@ int tabi_oracle_pack_loops(const int32_t* xy, const int32_t* loop_offsets,
                            int32_t p, int32_t q, int32_t* out_xy, uint8_t* out_orient,
                            float* out_scale, int32_t* out_k);
 
+/* Pre-rotation of one chart to its tight box over 64 directions m pi/128
+ * (Sec. 5 "Experimental Setup"): turned vertices (Q8, new box corner at the
+ * origin) into out[2 nv]; returns and stores the direction m (0, vertices
+ * copied, for a chart the pack rejects). */
+int orc_prerotate(const int32_t* xy, int32_t nv, int32_t* out, int32_t* m_out);
+
+/* Whole pack after pre-rotating every chart; out_dir[n] = its direction. */
+int tabi_oracle_pack_prerotate(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                               int32_t Ha, int32_t p, int32_t q, int32_t* out_xy,
+                               uint8_t* out_orient, uint8_t* out_dir, float* out_scale,
+                               int32_t* out_k);
+
 /* Variants of the method (Sec. 5 ablations). */
 enum { ORC_FULL = 0, ORC_TIGHT_ONLY = 1, ORC_BALANCED_ONLY = 2 };
 
