@@ -112,6 +112,31 @@ int tabi_pack_loops(const tabi_charts_loops* charts, int32_t n, int32_t atlas_w,
                     int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
                     float* out_scale, tabi_stream_t stream);
 
+/* tabi_pack after turning every chart to its tight box (Sec. 5,
+ * experimental setup: UV charts are pre-rotated so that their tight bounding
+ * boxes are axis-aligned; texture-space-shading charts are not).  The box is
+ * the least-area one over 64 directions m*pi/128, m = 0..63 (the OBB proxy's
+ * 8 directions are m = 0, 8, ..., 56), with C = round(2^14 cos(m*pi/128)),
+ * S = round(2^14 sin(m*pi/128)); areas are compared exactly and ties go to
+ * the smaller m.  Vertex (x, y) of chart c, with (x0, y0) the corner of the
+ * chart's input box, becomes
+ *     x' = floor((C (x - x0) + S (y - y0) + 2^13) / 2^14) - tx
+ *     y' = floor((C (y - y0) - S (x - x0) + 2^13) / 2^14) - ty
+ * (a turn by -m*pi/128, rounded to the nearest Q8 unit) with (tx, ty) the
+ * smallest such values, so that the turned box starts at (0, 0).
+ *   out_rxy: device int32[2*total_verts], the turned vertices (CSR offsets as
+ *            charts->offsets); it may be charts->xy itself (turned in place).
+ *   out_dir: device uint8[n], the direction m of each chart.
+ * A chart the pack rejects as degenerate (fewer than 3 vertices, a
+ * coordinate with |x| >= 2^22) is copied unchanged with m = 0.
+ * out_xy, out_orient, out_scale: as tabi_pack, for the turned charts.
+ * Errors: TABI_EINVAL (nothing written); TABI_ENOMEM or TABI_EHIP after the
+ * pre-rotation has been enqueued (out_rxy and out_dir may be written). */
+int tabi_pack_prerotate(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+                        int32_t padding, int32_t quality, int32_t* out_rxy, uint8_t* out_dir,
+                        int32_t* out_xy, uint8_t* out_orient, float* out_scale,
+                        tabi_stream_t stream);
+
 /* The method's knobs (Sec. 5 "Ablations"; App. D, local-AABB count and t_opt
  * tables), for the ablation variants and sweeps.  The quality presets are
  * {2, 5, FULL}, {5, 2, FULL} and {10, -1, FULL}.

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtabi_hip.so")
-SOURCES = ["prep.hip", "profile.hip", "pack.hip", "api.cpp", "serve.cpp"]
+SOURCES = ["prep.hip", "prerot.hip", "profile.hip", "pack.hip", "api.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # no packed fp32 instructions in device code

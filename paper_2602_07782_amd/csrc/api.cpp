@@ -628,6 +628,24 @@ int tabi_pack_method(const tabi_charts* charts, int32_t n, int32_t atlas_w, int3
                      out_orient, out_scale, stream);
 }
 
+int tabi_pack_prerotate(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+                        int32_t padding, int32_t quality, int32_t* out_rxy, uint8_t* out_dir,
+                        int32_t* out_xy, uint8_t* out_orient, float* out_scale,
+                        tabi_stream_t stream) {
+  if (check_common(n, padding, quality) || bad_atlas(atlas_w, atlas_h, padding) || !charts ||
+      !out_scale ||
+      (n > 0 && (!charts->xy || !charts->offsets || !out_rxy || !out_dir || !out_xy ||
+                 !out_orient)))
+    return TABI_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = launch_prerotate(charts->xy, charts->offsets, n, out_rxy, out_dir, st);
+  if (e != hipSuccess) return hip_fail(e);
+  // the turned charts are packed like any other input
+  const tabi_charts turned{out_rxy, charts->offsets, charts->total_verts};
+  return pack_single(&turned, n, atlas_w, atlas_h, padding, quality, out_xy, out_orient,
+                     out_scale, stream);
+}
+
 int tabi_pack_noalloc(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
                       int32_t padding, int32_t quality, int32_t* out_xy, uint8_t* out_orient,
                       float* out_scale, tabi_stream_t stream) {

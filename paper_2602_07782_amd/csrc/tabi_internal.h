@@ -111,6 +111,10 @@ hipError_t launch_setup(const Params& P, const Work& w, int round, hipStream_t s
 hipError_t launch_assemble(int N, int M, int count, const int32_t* aoff, const int32_t* poff,
                            const uint64_t* src_res, const uint64_t* dst_res, const int32_t* idx,
                            const Chart* prep, Chart* out, hipStream_t st);
+// pre-rotation of n single-loop charts to their tight boxes (64 directions):
+// turned vertices into out (may be xy itself), each chart's direction into dir
+hipError_t launch_prerotate(const int32_t* xy, const int32_t* voff, int n, int32_t* out,
+                            uint8_t* dir, hipStream_t st);
 // per-texel profiles and neighbour pairs (compacting distance, interlock flags)
 hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_t st);
 // fold-and-push of the round's scales; for a single atlas its last workgroup
