@@ -275,3 +275,24 @@ def test_records_entry_points_on_one_stream(tabi, orc):
     assert float(osc1.cpu().numpy()[0]) == e_sc
     assert np.array_equal(oxy1.cpu().numpy(), e_xy)
     assert np.array_equal(oor1.cpu().numpy(), e_or)
+
+
+def test_timed_256_atlas_batch_sample_equals_oracle(tabi, orc):
+    """The timed batch itself (256 atlases, sides 512-2048, 50-5,000 charts),
+    packed in one tabi_pack_many call; the three largest 2048^2 atlases and
+    five others drawn at random are compared with the oracle."""
+    batch = synth.make_batch(256, 4000)
+    _say("timed batch: generated, charts", sum(i.n for i in batch))
+    xy, ori, sc = tabi.pack_many(batch)
+    xy, ori, sc = xy.cpu().numpy(), ori.cpu().numpy(), sc.cpu().numpy()
+    ns = np.array([i.n for i in batch])
+    c0 = np.concatenate([[0], np.cumsum(ns)])
+    big = [int(i) for i in np.argsort(-ns, kind="stable") if batch[i].atlas_w == 2048][:3]
+    rng = np.random.default_rng(4001)
+    rest = [int(i) for i in rng.choice(np.setdiff1d(np.arange(256), big), 5, replace=False)]
+    for a in big + rest:
+        _say("timed batch atlas", a, "n =", batch[a].n, "side", batch[a].atlas_w)
+        oxy, oori, osc, ok = orc.pack(batch[a])
+        assert float(sc[a]) == osc, (a, sc[a], osc)
+        assert np.array_equal(xy[c0[a]:c0[a + 1]], oxy), a
+        assert np.array_equal(ori[c0[a]:c0[a + 1]], oori), a
