@@ -64,6 +64,11 @@ def lib():
                                            ctypes.POINTER(OrcChart)]
         L.orc_prep_chart_ex.argtypes = [I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.POINTER(OrcChart)]
+        i32 = ctypes.c_int32
+        L.tabi_oracle_pack_hybrid.argtypes = [I32P, I32P, i32, i32, i32, i32, i32, i32, I32P, U8P,
+                                              I32P, I32P]
+        L.tabi_oracle_feasible_hybrid.argtypes = [I32P, I32P, i32, i32, i32, i32, i32, i32, i32,
+                                                  I32P, I32P, U8P, I32P, I32P]
         L.orc_prerotate.argtypes = [I32P, ctypes.c_int32, I32P, I32P]
         L.tabi_oracle_pack_prerotate.argtypes = [I32P, I32P, ctypes.c_int32, ctypes.c_int32,
                                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -131,6 +136,40 @@ def pack_method(inp, K, topt, variant):
     if rc != 0:
         raise ValueError(f"oracle rejected the arguments (rc={rc})")
     return oxy[:2 * n].reshape(n, 2), ori[:n], float(sc.value), int(kk.value)
+
+
+def pack_hybrid(inp, K=10, topt=-1):
+    """Whole pack with the hybrid tail -> (xy, orient, per-chart k, head k)."""
+    n = inp.n
+    xy, off = _c(inp.xy, np.int32), _c(inp.offsets, np.int32)
+    oxy = np.zeros(max(2 * n, 1), np.int32)
+    ori = np.zeros(max(n, 1), np.uint8)
+    ks = np.zeros(max(n, 1), np.int32)
+    kk = ctypes.c_int32(0)
+    rc = lib().tabi_oracle_pack_hybrid(_p32(xy), _p32(off), n, inp.atlas_w, inp.atlas_h,
+                                       inp.padding, int(K), int(topt), _p32(oxy),
+                                       ori.ctypes.data_as(U8P), _p32(ks), ctypes.byref(kk))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the arguments (rc={rc})")
+    return oxy[:2 * n].reshape(n, 2), ori[:n], ks[:n], int(kk.value)
+
+
+def feasible_hybrid(inp, k, K=10, topt=0):
+    """One candidate k of the hybrid pack -> (ok, xs, ys, mir (sorted order),
+    t0, kt)."""
+    n = inp.n
+    xy, off = _c(inp.xy, np.int32), _c(inp.offsets, np.int32)
+    xs = np.zeros(max(n, 1), np.int32)
+    ys = np.zeros(max(n, 1), np.int32)
+    mir = np.zeros(max(n, 1), np.uint8)
+    t0, kt = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = lib().tabi_oracle_feasible_hybrid(_p32(xy), _p32(off), n, inp.atlas_w, inp.atlas_h,
+                                           inp.padding, int(K), int(topt), int(k), _p32(xs),
+                                           _p32(ys), mir.ctypes.data_as(U8P), ctypes.byref(t0),
+                                           ctypes.byref(kt))
+    if rc < 0:
+        raise ValueError(f"oracle rejected the arguments (rc={rc})")
+    return bool(rc), xs[:n], ys[:n], mir[:n], int(t0.value), int(kt.value)
 
 
 def prerotate(verts_q8):

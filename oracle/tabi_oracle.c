@@ -518,6 +518,10 @@ static int area_bound(const orc_chart* ch, int n, int Wa, int Ha) {
 typedef struct {
   int n, Wd, Hd, Wa, Ha, p, topt;
   int static_rows;                   /* tight-only: every row folded like a tail row */
+  int k;                             /* the scale, k/64 */
+  int hybrid;                        /* tail rows folded by prefix sums (Sec. 4.4) */
+  const orc_chart* ch;               /* charts and their order, for tails at */
+  const int* perm;                   /* other scales */
   int32_t *wd, *hd, *h;
   int64_t* Hq;                       /* unscaled Q8 heights, for knees */
   int32_t **topd, **botd;
@@ -544,6 +548,7 @@ static void free_kdata(kdata* D) {
 static void build_kdata(kdata* D, const orc_chart* ch, const int* perm, int n, int k,
                         int Wa, int Ha, int p, int topt) {
   D->n = n; D->Wa = Wa; D->Ha = Ha; D->p = p; D->topt = topt; D->static_rows = 0;
+  D->k = k; D->hybrid = 0; D->ch = ch; D->perm = perm;
   D->Wd = Wa + p; D->Hd = Ha + p;
   D->wd = calloc(n + 1, sizeof(int32_t)); D->hd = calloc(n + 1, sizeof(int32_t));
   D->h = calloc(n + 1, sizeof(int32_t)); D->Hq = calloc(n + 1, sizeof(int64_t));
@@ -820,10 +825,88 @@ static void config_alloc(config* g, int n, int Wd) {
 }
 static void config_free(config* g) { free(g->X); free(g->xa); free(g->y); free(g->Fp); }
 
+/* Hybrid tail (Sec. 4.4, "Performance Optimization"): the charts from t0 on
+ * are folded all at once.  Each gets an offset, its grown width at the head
+ * scale less its compacting distance to the next chart; the prefix sums of
+ * the offsets, divided by the grown atlas width, give every chart its row
+ * (prefix-sum folding, as in FastAtlas, with the compaction added).  Rows so
+ * formed may run past the atlas's right edge, so the tail is downscaled: its
+ * scale kt is the largest k' <= k at which every row, laid out left to right
+ * with compaction at k', fits the width.  The rows are then placed in the
+ * fixed one left-to-right : two right-to-left alternation and pushed up
+ * against the frontline like any other row, at kt.  Returns 1 on success
+ * (positions of the tail charts written, *kt_out set), 0 when some row does
+ * not fit at any scale or the frontline passes the atlas height.            */
+static int hybrid_tail(const kdata* D, int32_t* F, int t0, int32_t* xs, int32_t* ys,
+                       uint8_t* mir, int* kt_out) {
+  const int n = D->n, m = n - t0, Wd = D->Wd;
+  int64_t* row = malloc(sizeof(int64_t) * (m + 1));
+  int32_t* X = malloc(sizeof(int32_t) * (m + 1));
+  int64_t P = 0;
+  for (int j = 0; j < m; ++j) {
+    const int c = t0 + j;
+    row[j] = P / Wd;
+    P += D->wd[c] - (c + 1 < n ? D->cd[c + 1] : 0);
+  }
+  kdata T;
+  int kt, fits = 0;
+  for (kt = D->k; kt >= 1 && !fits; --kt) {
+    build_kdata(&T, D->ch, D->perm + t0, m, kt, D->Wa, D->Ha, D->p, D->topt);
+    fits = 1;
+    int64_t x = 0;
+    for (int j = 0; j < m && fits; ++j) {
+      if (j > 0) x = row[j] != row[j - 1] ? 0 : x + T.wd[j - 1] - T.cd[j];
+      X[j] = (int32_t)x;
+      if (x + T.wd[j] > Wd) fits = 0;
+    }
+    if (!fits) free_kdata(&T);
+  }
+  int ok = fits;
+  if (fits) {
+    ++kt;  /* the loop stepped past the scale that fit */
+    config g;
+    config_alloc(&g, m, Wd);
+    int trow = 0;
+    for (int j0 = 0; j0 < m && ok;) {
+      int j1 = j0 + 1;
+      while (j1 < m && row[j1] == row[j0]) ++j1;
+      g.R0 = 0; g.R1 = Wd; g.hc = 1; g.knee = 0;
+      g.dir = (trow % 3 == 0) ? LR : RL;
+      ++trow;
+      g.cnt = j1 - j0;
+      memcpy(g.X, X + j0, sizeof(int32_t) * g.cnt);
+      evaluate(&T, F, j0, &g);
+      memcpy(F, g.Fp, sizeof(int32_t) * Wd);
+      for (int t = 0; t < g.cnt; ++t) {
+        xs[t0 + j0 + t] = g.xa[t];
+        ys[t0 + j0 + t] = g.y[t];
+        mir[t0 + j0 + t] = (uint8_t)(g.dir == RL);
+      }
+      if (g.whole > D->Hd) ok = 0;
+      j0 = j1;
+    }
+    config_free(&g);
+    free_kdata(&T);
+    *kt_out = kt;
+  }
+  free(row);
+  free(X);
+  return ok;
+}
+
 /* Full packing at one scale (Alg. 3).  Positions (sorted order) into xs, ys,
  * mirror flags into mir.  Returns 1 when every chart is placed without the
  * frontline passing the (grown) atlas height.                               */
+static int pack_scale_ex(const kdata* D, int32_t* xs, int32_t* ys, uint8_t* mir, int* rows_out,
+                         int* t0_out, int* kt_out);
 static int pack_scale(const kdata* D, int32_t* xs, int32_t* ys, uint8_t* mir, int* rows_out) {
+  return pack_scale_ex(D, xs, ys, mir, rows_out, NULL, NULL);
+}
+
+/* t0_out: the first chart of the hybrid tail (n without one); kt_out: the
+ * tail's scale (k without a tail). */
+static int pack_scale_ex(const kdata* D, int32_t* xs, int32_t* ys, uint8_t* mir, int* rows_out,
+                         int* t0_out, int* kt_out) {
   int n = D->n, Wd = D->Wd, Hd = D->Hd;
   int32_t* F = calloc(Wd, sizeof(int32_t));
   int32_t* Xoff = malloc(sizeof(int32_t) * (n + 1));
@@ -832,13 +915,24 @@ static int pack_scale(const kdata* D, int32_t* xs, int32_t* ys, uint8_t* mir, in
   for (int d = 0; d < 2; ++d) { config_alloc(&full[d], n, Wd); config_alloc(&kc[d], n, Wd); }
   knee_t kn = {0, 0, 0, 0};
   int tail = D->static_rows, trow = 0, rs = 0, rows = 0, ok = 1;
+  if (t0_out) *t0_out = n;
+  if (kt_out) *kt_out = D->k;
   while (rs < n) {
     if (kn.active) update_knee(&kn, F, Wd);
     /* t_opt (Sec. 4.4): once no knee is pending and the row's tallest chart
      * is shorter than t_opt of the atlas height, the remaining rows are full
      * width, compacted, in the fixed 1 left-to-right : 2 right-to-left
      * alternation, without per-row configuration search. */
-    if (!tail && !kn.active && 100 * (int64_t)D->h[rs] < (int64_t)D->topt * D->Ha) tail = 1;
+    if (!tail && !kn.active && 100 * (int64_t)D->h[rs] < (int64_t)D->topt * D->Ha) {
+      tail = 1;
+      if (D->hybrid) {
+        int kt = 0;
+        ok = hybrid_tail(D, F, rs, xs, ys, mir, &kt);
+        if (t0_out) *t0_out = rs;
+        if (kt_out) *kt_out = kt;
+        break;
+      }
+    }
     config* ch;
     int knee_used = 0;
     if (tail) {
@@ -986,6 +1080,100 @@ static int pack_charts(orc_chart* ch, int ok, int32_t n, int32_t Wa, int32_t Ha,
   if (out_k) *out_k = kstar;
   free(xs); free(ys); free(mir); free(perm); free(ch);
   return 0;
+}
+
+/* Whole pack with the hybrid tail (Sec. 4.4): with the tail at its own
+ * scale the final scale differs between the charts placed row by row (k/64)
+ * and the tail (kt/64), so the chosen candidate k maximises the charts'
+ * final scales weighted by their areas, sum over charts of area * scale,
+ * among the k whose packing succeeds; ties keep the larger k.  The scale
+ * bound from the total area no longer holds (the tail is smaller), so every
+ * k from 64 down is a candidate; the search stops once k times the total
+ * area, which no packing at k or below can exceed, is no more than the best
+ * found.  out_k: k of the head; out_ks[c]: each chart's own k.             */
+int tabi_oracle_pack_hybrid(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                            int32_t Ha, int32_t p, int32_t K, int32_t topt, int32_t* out_xy,
+                            uint8_t* out_orient, int32_t* out_ks, int32_t* out_k) {
+  if (check_args(xy, offsets, n, Wa, Ha, p, 0)) return -1;
+  if (!(K == 1 || K == 2 || K == 5 || K == 10) || topt < -1 || topt > 100) return -1;
+  if (topt < 0) topt = n > 10000 ? 1 : 0;
+  for (int c = 0; c < n; ++c) {
+    out_xy[2 * c] = -1; out_xy[2 * c + 1] = -1; out_orient[c] = 0; out_ks[c] = 0;
+  }
+  if (n <= 0) { *out_k = 64; return 0; }
+  orc_chart* ch = calloc(n, sizeof(orc_chart));
+  if (!prep_all(xy, offsets, n, K, 1, ch)) {
+    free(ch);
+    *out_k = -1;
+    return 0;
+  }
+  int* perm = malloc(sizeof(int) * n);
+  sort_charts(ch, n, perm);
+  i128 total = 0;
+  for (int c = 0; c < n; ++c) total += ch[c].area2;
+  int32_t* xs = malloc(sizeof(int32_t) * n);
+  int32_t* ys = malloc(sizeof(int32_t) * n);
+  uint8_t* mir = malloc(n);
+  int32_t* bx = malloc(sizeof(int32_t) * n);
+  int32_t* by = malloc(sizeof(int32_t) * n);
+  uint8_t* bm = malloc(n);
+  int best = 0, bt0 = n, bkt = 0;
+  i128 bobj = 0;
+  for (int k = 64; k >= 1; --k) {
+    if (best > 0 && (i128)k * total <= bobj) break;
+    kdata D;
+    build_kdata(&D, ch, perm, n, k, Wa, Ha, p, topt);
+    D.hybrid = 1;
+    int t0 = n, kt = k;
+    const int ok = pack_scale_ex(&D, xs, ys, mir, NULL, &t0, &kt);
+    free_kdata(&D);
+    if (!ok) continue;
+    i128 head = 0, tail = 0;
+    for (int t = 0; t < n; ++t) {
+      if (t < t0) head += ch[perm[t]].area2;
+      else tail += ch[perm[t]].area2;
+    }
+    const i128 obj = (i128)k * head + (i128)kt * tail;
+    if (best == 0 || obj > bobj) {
+      best = k; bobj = obj; bt0 = t0; bkt = kt;
+      memcpy(bx, xs, sizeof(int32_t) * n);
+      memcpy(by, ys, sizeof(int32_t) * n);
+      memcpy(bm, mir, n);
+    }
+  }
+  if (best > 0) {
+    for (int t = 0; t < n; ++t) {
+      const int c = perm[t];
+      out_xy[2 * c] = bx[t];
+      out_xy[2 * c + 1] = by[t];
+      out_orient[c] = (uint8_t)(ch[c].rot | (ch[c].flipx << 1) | (ch[c].flipy << 2) | (bm[t] << 3));
+      out_ks[c] = t < bt0 ? best : bkt;
+    }
+  }
+  *out_k = best;
+  free(xs); free(ys); free(mir); free(bx); free(by); free(bm); free(perm); free(ch);
+  return 0;
+}
+
+/* One candidate scale of the hybrid pack: feasibility, positions in sorted
+ * order, the tail's first chart t0 and scale kt. */
+int tabi_oracle_feasible_hybrid(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                                int32_t Ha, int32_t p, int32_t K, int32_t topt, int32_t k,
+                                int32_t* out_xs, int32_t* out_ys, uint8_t* out_mir,
+                                int32_t* out_t0, int32_t* out_kt) {
+  if (check_args(xy, offsets, n, Wa, Ha, p, 0) || n < 0 || k < 1 || k > 64) return -1;
+  if (!(K == 1 || K == 2 || K == 5 || K == 10) || topt < 0 || topt > 100) return -1;
+  orc_chart* ch = calloc(n > 0 ? n : 1, sizeof(orc_chart));
+  if (!prep_all(xy, offsets, n, K, 1, ch)) { free(ch); return -2; }
+  int* perm = malloc(sizeof(int) * (n > 0 ? n : 1));
+  sort_charts(ch, n, perm);
+  kdata D;
+  build_kdata(&D, ch, perm, n, k, Wa, Ha, p, topt);
+  D.hybrid = 1;
+  const int ok = pack_scale_ex(&D, out_xs, out_ys, out_mir, NULL, out_t0, out_kt);
+  free_kdata(&D);
+  free(perm); free(ch);
+  return ok;
 }
 
 int tabi_oracle_pack(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,

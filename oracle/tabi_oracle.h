@@ -74,6 +74,22 @@ int tabi_oracle_pack_loops(const int32_t* xy, const int32_t* loop_offsets,
                            int32_t p, int32_t q, int32_t* out_xy, uint8_t* out_orient,
                            float* out_scale, int32_t* out_k);
 
+/* Whole pack with the hybrid tail of Sec. 4.4 (prefix-sum folding of the
+ * charts after the t_opt switch, downscaled to fit, and the candidate scale
+ * chosen by the area-weighted final scale).  K slices, t_opt percent (-1:
+ * the paper's setting).  out_ks[c]: chart c's own k (0 when nothing fits);
+ * out_k: the head's k (0 no fit, -1 degenerate chart). */
+int tabi_oracle_pack_hybrid(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                            int32_t Ha, int32_t p, int32_t K, int32_t topt, int32_t* out_xy,
+                            uint8_t* out_orient, int32_t* out_ks, int32_t* out_k);
+/* One candidate k of it: returns 1 feasible, 0 not, -1 bad arguments, -2 a
+ * degenerate chart; positions in sorted order, the tail's first chart t0 (n:
+ * no tail) and its k. */
+int tabi_oracle_feasible_hybrid(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                                int32_t Ha, int32_t p, int32_t K, int32_t topt, int32_t k,
+                                int32_t* out_xs, int32_t* out_ys, uint8_t* out_mir,
+                                int32_t* out_t0, int32_t* out_kt);
+
 /* Pre-rotation of one chart to its tight box over 64 directions m pi/128
  * (Sec. 5 "Experimental Setup"): turned vertices (Q8, new box corner at the
  * origin) into out[2 nv]; returns and stores the direction m (0, vertices

@@ -41,6 +41,9 @@ def lib():
         L.tabi_check_layout.argtypes = [I32P, I32P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, I32P, U8P, ctypes.c_int32, I64P]
         L.tabi_check_layout.restype = ctypes.c_long
+        L.tabi_check_layout_ks.argtypes = [I32P, I32P, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_int32, I32P, U8P, I32P, I64P]
+        L.tabi_check_layout_ks.restype = ctypes.c_long
         _lib = L
     return _lib
 
@@ -66,6 +69,21 @@ def check_layout(inp, out_xy, out_orient, k):
     lib().tabi_check_layout(xy.ctypes.data_as(I32P), off.ctypes.data_as(I32P), inp.n, inp.atlas_w,
                             inp.atlas_h, inp.padding, oxy.ctypes.data_as(I32P),
                             ori.ctypes.data_as(U8P), int(k), st.ctypes.data_as(I64P))
+    return dict(overlap=int(st[0]), outside=int(st[1]), covered=int(st[2]), empty=int(st[3]))
+
+
+def check_layout_ks(inp, out_xy, out_orient, ks):
+    """check_layout with a scale ks[c]/64 of its own for every chart."""
+    xy = np.ascontiguousarray(inp.xy, np.int32)
+    off = np.ascontiguousarray(inp.offsets, np.int32)
+    oxy = np.ascontiguousarray(np.asarray(out_xy).reshape(-1), np.int32)
+    ori = np.ascontiguousarray(out_orient, np.uint8)
+    kk = np.ascontiguousarray(ks, np.int32)
+    st = np.zeros(4, np.int64)
+    lib().tabi_check_layout_ks(xy.ctypes.data_as(I32P), off.ctypes.data_as(I32P), inp.n,
+                               inp.atlas_w, inp.atlas_h, inp.padding, oxy.ctypes.data_as(I32P),
+                               ori.ctypes.data_as(U8P), kk.ctypes.data_as(I32P),
+                               st.ctypes.data_as(I64P))
     return dict(overlap=int(st[0]), outside=int(st[1]), covered=int(st[2]), empty=int(st[3]))
 
 

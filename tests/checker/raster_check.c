@@ -168,9 +168,24 @@ static void place_chart(const int32_t* xy, int m, int32_t ox, int32_t oy, int or
  * footprints, stats[1] = covered texels outside the atlas, stats[2] = covered
  * texels in total, stats[3] = charts with fewer than one covered texel.
  * Returns stats[0] + stats[1]. */
+long tabi_check_layout_ks(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                          int32_t Ha, int32_t p, const int32_t* out_xy, const uint8_t* out_orient,
+                          const int32_t* ks, int64_t* stats);
+
 long tabi_check_layout(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
                        int32_t Ha, int32_t p, const int32_t* out_xy, const uint8_t* out_orient,
                        int32_t k, int64_t* stats) {
+  int32_t* ks = malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+  for (int c = 0; c < n; ++c) ks[c] = k;
+  long r = tabi_check_layout_ks(xy, offsets, n, Wa, Ha, p, out_xy, out_orient, ks, stats);
+  free(ks);
+  return r;
+}
+
+/* The same with a scale ks[c]/64 of its own for every chart. */
+long tabi_check_layout_ks(const int32_t* xy, const int32_t* offsets, int32_t n, int32_t Wa,
+                          int32_t Ha, int32_t p, const int32_t* out_xy, const uint8_t* out_orient,
+                          const int32_t* ks, int64_t* stats) {
   int64_t Wd = (int64_t)Wa + p, Hd = (int64_t)Ha + p;
   uint8_t* grid = calloc((size_t)(Wd * Hd), 1);
   int64_t overlap = 0, outside = 0, total = 0, empty = 0;
@@ -179,7 +194,7 @@ long tabi_check_layout(const int32_t* xy, const int32_t* offsets, int32_t n, int
     const int32_t* v = xy + 2 * (int64_t)offsets[c];
     int64_t* X = malloc(sizeof(int64_t) * m);
     int64_t* Y = malloc(sizeof(int64_t) * m);
-    place_chart(v, m, out_xy[2 * c], out_xy[2 * c + 1], out_orient[c], k, X, Y);
+    place_chart(v, m, out_xy[2 * c], out_xy[2 * c + 1], out_orient[c], ks[c], X, Y);
     int64_t xmin = X[0], xmax = X[0], ymin = Y[0], ymax = Y[0];
     for (int i = 1; i < m; ++i) {
       if (X[i] < xmin) xmin = X[i];
