@@ -162,6 +162,33 @@ int tabi_pack_method(const tabi_charts* charts, int32_t n, int32_t atlas_w, int3
                      int32_t padding, const tabi_method* method, int32_t* out_xy,
                      uint8_t* out_orient, float* out_scale, tabi_stream_t stream);
 
+/* tabi_pack_method with the hybrid tail of Sec. 4.4 ("Performance
+ * Optimization"), for the full method (method->variant = TABI_FULL).  Rows
+ * are folded and pushed one by one until the t_opt switch (no knee pending
+ * and the row's first chart shorter than t_opt of the atlas height); the
+ * remaining charts, in sorted order, are then folded all at once: each
+ * chart's offset is its grown width less its compacting distance to the next
+ * chart, and the prefix sum of the offsets divided by the grown atlas width
+ * W + padding gives its row.  The tail is downscaled to the largest k' <= k
+ * at which every such row, laid out with compaction at k', fits the width;
+ * its rows are placed in the fixed one left-to-right : two right-to-left
+ * alternation and pushed up at k'.  Head and tail scales differ, so the
+ * candidate k is the one whose packing succeeds with the largest sum over
+ * charts of area * final scale (ties to the larger k), searched over all 64.
+ * Outputs as tabi_pack, except:
+ *   out_scale[0]:       k/64 of the rows before the switch (or 0 / -1 as
+ *                       tabi_pack);
+ *   out_chart_scale[c]: device float[n], chart c's own scale (k/64 before
+ *                       the switch, k'/64 in the tail; 0 when nothing fits),
+ *                       which takes the place of s in tabi_pack's transform.
+ * With t_opt 0 there is no tail and the result is tabi_pack_method's.
+ * Errors: TABI_EINVAL (also for a variant other than TABI_FULL), TABI_ENOMEM,
+ * TABI_EHIP. */
+int tabi_pack_hybrid(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+                     int32_t padding, const tabi_method* method, int32_t* out_xy,
+                     uint8_t* out_orient, float* out_chart_scale, float* out_scale,
+                     tabi_stream_t stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): tabi_pack
  * with the same arguments, outputs and device-detected conditions, whose work

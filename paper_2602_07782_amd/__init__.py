@@ -59,7 +59,7 @@ class Done(ctypes.Structure):
 
 
 _lib = None
-EXPORTS = ["tabi_pack", "tabi_pack_loops", "tabi_pack_prerotate", "tabi_pack_method", "tabi_pack_many_method", "tabi_pack_noalloc",
+EXPORTS = ["tabi_pack", "tabi_pack_loops", "tabi_pack_prerotate", "tabi_pack_hybrid", "tabi_pack_method", "tabi_pack_many_method", "tabi_pack_noalloc",
            "tabi_pack_many", "tabi_pack_many_ws", "tabi_submit_with", "tabi_pack_many_workspace_bytes",
            "tabi_record_bytes", "tabi_prep_records", "tabi_splice_records",
            "tabi_pack_many_records", "tabi_debug_order", "tabi_debug_pairs",
@@ -86,6 +86,8 @@ def lib():
                                         vp, vp]
         L.tabi_pack_loops.argtypes = [ctypes.POINTER(ChartsLoops), i32, i32, i32, i32, i32, vp,
                                       vp, vp, vp]
+        L.tabi_pack_hybrid.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32,
+                                       ctypes.POINTER(Method), vp, vp, vp, vp, vp]
         L.tabi_pack_prerotate.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32, i32, vp,
                                           vp, vp, vp, vp, vp]
         L.tabi_pack_method.argtypes = [ctypes.POINTER(Charts), i32, i32, i32, i32,
@@ -206,6 +208,26 @@ def pack_loops(xy, loop_offsets, chart_loops, atlas_w, atlas_h, padding, quality
                                  int(quality), _ptr(out_xy), _ptr(out_or), _ptr(out_sc),
                                  _stream(stream)))
     return out_xy, out_or, out_sc
+
+
+def pack_hybrid(xy, offsets, atlas_w, atlas_h, padding, slices=10, topt_percent=-1,
+                stream=None, device="cuda"):
+    """tabi_pack_hybrid: the full method with the hybrid tail.  Returns
+    (out_xy int32[n,2], out_orient uint8[n], out_chart_scale float32[n],
+    out_scale float32[1]) on the device."""
+    torch = _torch()
+    xy = _dev_i32(xy, device)
+    offsets = _dev_i32(offsets, device)
+    ch, n = _charts(xy, offsets)
+    out_xy = torch.empty((max(n, 0), 2), dtype=torch.int32, device=xy.device)
+    out_or = torch.empty(max(n, 0), dtype=torch.uint8, device=xy.device)
+    out_ks = torch.empty(max(n, 0), dtype=torch.float32, device=xy.device)
+    out_sc = torch.empty(1, dtype=torch.float32, device=xy.device)
+    m = Method(int(slices), int(topt_percent), 0)
+    _check(lib().tabi_pack_hybrid(ctypes.byref(ch), n, int(atlas_w), int(atlas_h), int(padding),
+                                  ctypes.byref(m), _ptr(out_xy), _ptr(out_or), _ptr(out_ks),
+                                  _ptr(out_sc), _stream(stream)))
+    return out_xy, out_or, out_ks, out_sc
 
 
 def pack_prerotate(xy, offsets, atlas_w, atlas_h, padding, quality, stream=None, device="cuda",

@@ -136,7 +136,8 @@ struct StageScope {  // brackets one stage's launches with a pair of events
 // ---- work space -------------------------------------------------------------
 struct Layout {
   size_t o_recs, o_srecs, o_keys, o_rank, o_perm, o_ca, o_desc, o_kc, o_cd, o_fl, o_xs, o_ys, o_mir,
-      o_feas, o_rows, o_wdv, o_hdv, o_kslot, o_pcol, o_prow, o_lrpre, o_Hs, o_segneed, o_segbase, o_cnt, o_gq, o_gq_cnt, o_live, o_aord, o_arena,
+      o_feas, o_rows, o_wdv, o_hdv, o_kslot, o_pcol, o_prow, o_lrpre, o_Hs, o_segneed, o_segbase, o_cnt, o_gq, o_gq_cnt, o_live, o_aord,
+      o_tailF, o_tail_t0, o_tail_kt, o_tail_obj, o_arena,
       total;
 };
 
@@ -196,6 +197,11 @@ Layout layout(const Params& P) {
   L.o_gq_cnt = take(4);
   L.o_live = take((MAX_ROUNDS + 1) * 4);
   L.o_aord = take((size_t)P.count * 4);
+  const size_t hb = P.hybrid ? (size_t)P.B : 0;
+  L.o_tailF = take(hb * (size_t)P.Wdmax * 4);
+  L.o_tail_t0 = take(hb * 4);
+  L.o_tail_kt = take(hb * 4);
+  L.o_tail_obj = take(hb * 16);
   L.o_arena = take((size_t)P.arena_cap * 4);
   L.total = off;
   return L;
@@ -233,6 +239,10 @@ Work carve(void* base, const Layout& L) {
   W.gq_cnt = reinterpret_cast<int32_t*>(b + L.o_gq_cnt);
   W.live = reinterpret_cast<int32_t*>(b + L.o_live);
   W.aord = reinterpret_cast<int32_t*>(b + L.o_aord);
+  W.tailF = reinterpret_cast<int32_t*>(b + L.o_tailF);
+  W.tail_t0 = reinterpret_cast<int32_t*>(b + L.o_tail_t0);
+  W.tail_kt = reinterpret_cast<int32_t*>(b + L.o_tail_kt);
+  W.tail_obj = reinterpret_cast<uint64_t*>(b + L.o_tail_obj);
   W.arena = reinterpret_cast<uint32_t*>(b + L.o_arena);
   return W;
 }
@@ -626,6 +636,50 @@ int tabi_pack_method(const tabi_charts* charts, int32_t n, int32_t atlas_w, int3
   if (!method_ok(method)) return TABI_EINVAL;
   return pack_single(charts, n, atlas_w, atlas_h, padding, encode_method(*method), out_xy,
                      out_orient, out_scale, stream);
+}
+
+int tabi_pack_hybrid(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,
+                     int32_t padding, const tabi_method* method, int32_t* out_xy,
+                     uint8_t* out_orient, float* out_chart_scale, float* out_scale,
+                     tabi_stream_t stream) {
+  if (!method_ok(method) || method->variant != TABI_FULL) return TABI_EINVAL;
+  const int32_t code = encode_method(*method);
+  if (check_common_code(n, padding, code) || bad_atlas(atlas_w, atlas_h, padding) || !charts ||
+      !out_scale ||
+      (n > 0 && (!charts->xy || !charts->offsets || !out_xy || !out_orient || !out_chart_scale)))
+    return TABI_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Params P = make_params(1, n, code, padding, 64, 0, n > 0 ? n : 1, atlas_w + padding);
+  P.hybrid = 1;
+  Job j;
+  int rc = make_job(j, P, st);
+  if (!rc) rc = single_front(j, charts, atlas_w, atlas_h, st);
+  if (!rc) {
+    // every scale in one round: per-scale set-up, profiles and pairs, the
+    // rows before the t_opt switch, the tails, then the choice
+    hipError_t e;
+    {
+      StageScope t(ST_SETUP, st);
+      e = launch_setup(j.P, j.W, 0, st);
+    }
+    if (e == hipSuccess) {
+      StageScope t(ST_PROFILE, st);
+      e = launch_profiles(j.P, j.W, 0, st);
+    }
+    if (e == hipSuccess) {
+      StageScope t(ST_PACK, st);
+      e = launch_pack(j.P, j.W, 0, j.L.bytes, j.L.RC, j.L.PW, j.stage_cap, 1, out_xy, out_orient,
+                      out_scale, st);
+      if (e == hipSuccess) e = launch_tail(j.P, j.W, j.L.bytes, j.L.RC, st);
+    }
+    if (e == hipSuccess) {
+      StageScope t(ST_SELECT, st);
+      e = launch_select_hybrid(j.P, j.W, out_xy, out_orient, out_chart_scale, out_scale, st);
+    }
+    if (e != hipSuccess) rc = hip_fail(e);
+  }
+  free_job(j, st);
+  return rc;
 }
 
 int tabi_pack_prerotate(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t atlas_h,

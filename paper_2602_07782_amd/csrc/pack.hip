@@ -220,6 +220,15 @@ __device__ __attribute__((noinline)) void correct_many_pairs(
   }
 }
 
+// The hybrid tail's hand-over: the frontline and the tail's first chart
+// (kept out of line, off the row loop's registers).
+template <int PACK_NT>
+__device__ __attribute__((noinline)) void save_tail(const int32_t* F, int Wd, int32_t* dst,
+                                                    int32_t* t0, int rs) {
+  for (int x = threadIdx.x; x < Wd; x += PACK_NT) dst[x] = F[x];
+  if (threadIdx.x == 0) *t0 = rs;
+}
+
 template <int PACK_WAVES>
 __device__ inline int32_t block_reduce_max(int32_t v, int32_t* red) {
   v = wave_max(v);
@@ -301,7 +310,9 @@ __device__ void select_atlas(const Params& P, const Work& w, int round, int last
 // PACK_NT threads per workgroup: 1024 for a single pack (every per-texel
 // phase of a row spread over 16 wavefronts), 512 for batches (two workgroups
 // per CU when their shared memory allows it).  At most 128 VGPRs either way.
-template <int PACK_NT>
+// HYB: the hybrid tail's variant (a single atlas), which hands the rows
+// after the t_opt switch over to k_tail.
+template <int PACK_NT, bool HYB = false>
 __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) void k_pack(
     Params P, Work w, int round, int RC, int PW, int stage_cap, int last_round, int32_t* out_xy,
     uint8_t* out_orient, float* out_scale) {
@@ -419,7 +430,14 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     }
     // ---- t_opt switch (Sec. 4.4), on the first chart's texel height
     const int64_t h0 = cdiv64((int64_t)k * uni(s_H[r0]), QS);
-    if (!tail && !kn && 100 * h0 < (int64_t)topt * Ha) tail = 1;
+    if (!tail && !kn && 100 * h0 < (int64_t)topt * Ha) {
+      tail = 1;
+      if (HYB) {  // the rest is folded by prefix sums (k_tail)
+        save_tail<PACK_NT>(F, Wd, w.tailF + (size_t)s * P.Wdmax, w.tail_t0 + s, rs);
+        feasible = 2;
+        break;
+      }
+    }
     // ---- 2. folding (Alg. 2), wavefront 0
     const int kw = kn ? (kdir == DIR_LR ? Wd - kr : kl) : 0;
     if (wv == 0) {
@@ -736,13 +754,14 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   if (tid == 0) {
     w.feas[a * P.B + s] = feasible;
     w.rows[a * P.B + s] = rows;
+    if (HYB && feasible != 2) w.tail_t0[s] = d.n;
   }
   // Single atlas: the last of its workgroups to finish selects the scale and
   // writes the outputs (no separate launch).  Every workgroup publishes its
   // results, then counts itself; the counter is zeroed again by the last
   // one.  Batches launch the selection instead: a device-wide fence in each
   // of their many workgroups costs more than the launch it saves.
-  if (P.fixed_k > 0 || P.count != 1) return;
+  if (P.fixed_k > 0 || P.count != 1 || HYB) return;
   __threadfence();
   __syncthreads();
   if (tid == 0) s_cnt[0] = atomicAdd(&w.cnt[a], 1) == P.Br - 1;
@@ -832,12 +851,374 @@ hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes,
                        int stage_cap, int last_round, int32_t* out_xy, uint8_t* out_orient,
                        float* out_scale, hipStream_t st) {
   // one atlas: latency matters, use the wider workgroup (batches: as tuned)
-  if (P.pack_nt == 1024 || (P.pack_nt == 0 && P.count == 1))
+  if (P.hybrid) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_pack<1024, true>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_pack<1024, true>), dim3(P.Br, P.count), dim3(1024), lds_bytes, st, P, w,
+                       round, RC, PW, stage_cap, last_round, out_xy, out_orient, out_scale);
+  } else if (P.pack_nt == 1024 || (P.pack_nt == 0 && P.count == 1))
     hipLaunchKernelGGL(k_pack<1024>, dim3(P.Br, P.count), dim3(1024), lds_bytes, st, P, w, round,
                        RC, PW, stage_cap, last_round, out_xy, out_orient, out_scale);
   else
     hipLaunchKernelGGL(k_pack<512>, dim3(P.Br, P.count), dim3(512), lds_bytes, st, P, w, round, RC,
                        PW, stage_cap, last_round, out_xy, out_orient, out_scale);
+  return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Hybrid tail (Sec. 4.4, "Performance Optimization"), single atlas.
+//
+// The fold-and-push workgroup of a scale slot that reaches the t_opt switch
+// leaves its frontline and the tail's first chart t0 in the work space
+// (feasible = 2).  k_tail then takes that slot, one workgroup:
+//   1. rows by prefix-sum folding at the head scale k: chart j's offset is
+//      its grown width less the compacting distance to chart j + 1, and the
+//      prefix sum of the offsets divided by the grown atlas width is its row;
+//   2. the tail's scale kt, from k down: the set-up records, grown extents
+//      and neighbour pairs of the tail charts at kt (records overwritten in
+//      the slot's arrays), accepted when every row laid out with compaction
+//      at kt fits the width;
+//   3. the rows in order, in the one left-to-right : two right-to-left
+//      alternation: push, correction (Alg. 1), frontline update and the
+//      overflow test, every texel bound evaluated from the records at kt;
+//   4. the slot's sum over charts of area * scale.
+// k_select_hybrid then keeps the slot with the largest sum (ties to the
+// larger k) and writes the outputs with each chart's own scale.
+// ---------------------------------------------------------------------------
+constexpr int TAIL_NT = 1024;
+
+// inclusive block scan of int32 values whose block total fits 31 bits;
+// `total` gets the block total (every thread); red: TAIL_NT / WAVE ints
+template <int WAVES>
+__device__ inline int32_t block_incl_sum(int32_t v, int32_t* red, int32_t& total) {
+  const int lane = lane_id(), wv = threadIdx.x / WAVE;
+  const int32_t incl = wave_incl_sum(v);
+  __syncthreads();
+  if (lane == WAVE - 1) red[wv] = incl;
+  __syncthreads();
+  int32_t base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < WAVES; ++i) {
+    const int32_t r = red[i];
+    base += i < wv ? r : 0;
+    tot += r;
+  }
+  total = uni(tot);
+  return base + incl;
+}
+
+// inclusive block max scan (same contract)
+template <int WAVES>
+__device__ inline int32_t block_incl_max(int32_t v, int32_t* red, int32_t& total) {
+  const int lane = lane_id(), wv = threadIdx.x / WAVE;
+  const int32_t incl = wave_incl_max(v);
+  __syncthreads();
+  if (lane == WAVE - 1) red[wv] = incl;
+  __syncthreads();
+  int32_t base = -BIG, tot = -BIG;
+#pragma unroll
+  for (int i = 0; i < WAVES; ++i) {
+    const int32_t r = red[i];
+    base = i < wv ? max(base, r) : base;
+    tot = max(tot, r);
+  }
+  total = uni(tot);
+  return max(base, incl);
+}
+
+__device__ inline void build_krec_rt(int K, const Chart& ch, int k, unsigned char* base,
+                                     int32_t& wt, int32_t& ht) {
+  if (K == 10) build_krec<10>(ch, k, base, wt, ht);
+  else if (K == 5) build_krec<5>(ch, k, base, wt, ht);
+  else if (K == 2) build_krec<2>(ch, k, base, wt, ht);
+  else build_krec<1>(ch, k, base, wt, ht);
+}
+
+__global__ __launch_bounds__(TAIL_NT) void k_tail(Params P, Work w, int RC) {
+  constexpr int WAVES = TAIL_NT / WAVE;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t s_red[WAVES * 6];
+  __shared__ int32_t s_lr[LRCAP][3];
+  __shared__ uint64_t s_area[2 * WAVES];
+  const int s = blockIdx.x;
+  if (w.feas[s] != 2) return;  // no tail at this slot (uniform)
+  const AtlasDesc d = w.desc[0];
+  const int k = slot_k(P, d, 0, s);
+  const int n = d.n, Wd = d.Wa + P.p, Hd = d.Ha + P.p, p = P.p, K = P.K;
+  const int tid = threadIdx.x, wv = tid / WAVE, lane = lane_id();
+  const size_t slot = (size_t)s * P.N;
+  // dynamic LDS (the fold-and-push plan): frontline, row offsets without /
+  // with compaction, the row's offsets Y
+  int32_t* F = reinterpret_cast<int32_t*>(smem);
+  int32_t* Xoff = F + Wd;
+  int32_t* Xon = Xoff + (RC + 1);
+  int32_t* Y = Xon + (RC + 1);
+  unsigned char* kcb = w.kc + slot * P.stride;
+  const Chart* ch = w.srecs;
+  int32_t* cdv = w.cd + slot;
+  uint8_t* flv = w.fl + slot;
+  int32_t* wdv = w.wdv + slot;
+  int32_t* hdv = w.hdv + slot;
+  int32_t* xs = w.xs + slot;   // first: each tail chart's row start
+  int32_t* ys = w.ys + slot;   // first: each tail chart's row (low 32 bits)
+  uint8_t* mir = w.mir + slot;
+  int32_t* lrpre = w.lrpre + slot;  // first: prefix sums of the offsets at kt
+  auto KV = [&](int c) { return kview(kcb + (size_t)c * P.stride, K); };
+  const int t0 = w.tail_t0[s];
+
+  int32_t fm = 0;
+  for (int x = tid; x < Wd; x += TAIL_NT) {
+    const int32_t v = w.tailF[(size_t)s * P.Wdmax + x];
+    F[x] = v;
+    fm = max(fm, v);
+  }
+  int32_t fmax = block_reduce_max<WAVES>(fm, s_red);
+
+  // ---- 1. rows by prefix sums of the offsets at the head scale
+  {
+    int64_t carry = 0;
+    for (int b0 = t0; b0 < n; b0 += TAIL_NT) {
+      const int j = b0 + tid;
+      const int32_t a = j < n ? wdv[j] - (j + 1 < n ? cdv[j + 1] : 0) : 0;
+      int32_t tot;
+      const int32_t incl = block_incl_sum<WAVES>(a, s_red, tot);
+      if (j < n) ys[j] = (int32_t)(uint32_t)((uint64_t)(carry + incl - a) / (uint64_t)Wd);
+      carry += tot;
+    }
+    __syncthreads();
+    // row start of every tail chart: a running max of the row heads
+    int32_t run = t0;
+    for (int b0 = t0; b0 < n; b0 += TAIL_NT) {
+      const int j = b0 + tid;
+      const bool head = j < n && (j == t0 || ys[j] != ys[j - 1]);
+      int32_t tot;
+      const int32_t st = max(run, block_incl_max<WAVES>(head ? j : -BIG, s_red, tot));
+      if (j < n) xs[j] = st;
+      run = max(run, tot);
+    }
+  }
+
+  // ---- 2. the tail's scale: the largest kt <= k at which every row fits
+  int kt = k, feasible = 0;
+  for (; kt >= 1; --kt) {
+    __syncthreads();
+    for (int j = t0 + tid; j < n; j += TAIL_NT) {
+      int32_t wt, ht;
+      build_krec_rt(K, ch[j], kt, kcb + (size_t)j * P.stride, wt, ht);
+      wdv[j] = wt + p;
+      hdv[j] = ht + p;
+    }
+    __syncthreads();
+    // neighbours in one row: compacting distance and flags at kt (one
+    // wavefront per pair); other neighbours are never compacted
+    for (int j = t0 + wv; j < n; j += WAVES) {
+      PairResult r{0, 0};
+      if (j > t0 && xs[j] == xs[j - 1]) r = pair_records_both(KV(j - 1), ch[j - 1], KV(j), ch[j], K, kt, p);
+      if (lane == 0) {
+        cdv[j] = r.cd;
+        flv[j] = (uint8_t)r.flags;
+      }
+    }
+    __syncthreads();
+    // offsets within the rows: prefix sums (mod 2^32) of the offsets, less
+    // the sum at the row start; a row's offsets stay below 2^29
+    {
+      uint32_t carry = 0;
+      for (int b0 = t0; b0 < n; b0 += TAIL_NT) {
+        const int j = b0 + tid;
+        const int32_t a = j < n ? wdv[j] - (j + 1 < n ? cdv[j + 1] : 0) : 0;
+        int32_t tot;
+        const int32_t incl = block_incl_sum<WAVES>(a, s_red, tot);
+        if (j < n) lrpre[j] = (int32_t)(carry + (uint32_t)(incl - a));
+        carry += (uint32_t)tot;
+      }
+    }
+    __syncthreads();
+    int over = 0;
+    for (int j = t0 + tid; j < n; j += TAIL_NT) {
+      const int64_t X = (int32_t)((uint32_t)lrpre[j] - (uint32_t)lrpre[xs[j]]);
+      over |= X + wdv[j] > Wd;
+    }
+    if (!__syncthreads_or(over)) {
+      feasible = 1;
+      break;
+    }
+  }
+
+  // ---- 3. the rows, pushed up in the fixed direction alternation
+  if (feasible) {
+    int rs = t0, trow = 0;
+    while (rs < n) {
+      int re = n;  // the row ends at the first chart of another row
+      for (int b0 = rs + 1; b0 < n; b0 += TAIL_NT) {
+        const int j = b0 + tid;
+        const int e = block_reduce_min<WAVES>(j < n && xs[j] != rs ? j : n, s_red);
+        if (e < n) { re = e; break; }
+      }
+      const int cnt = re - rs;
+      if (cnt > RC) { feasible = -2; break; }  // cannot happen: advances are >= 1
+      int32_t co = 0, cn = 0;
+      for (int b0 = 0; b0 < cnt; b0 += TAIL_NT) {
+        const int t = b0 + tid, c = rs + t;
+        const int32_t wd = t < cnt ? wdv[c] : 0;
+        const int32_t adv = t < cnt ? wd - (t + 1 < cnt ? cdv[c + 1] : 0) : 0;
+        int32_t to, tn;
+        const int32_t io = block_incl_sum<WAVES>(wd, s_red, to);
+        const int32_t in = block_incl_sum<WAVES>(adv, s_red, tn);
+        if (t < cnt) {
+          Xoff[t] = co + io - wd;
+          Xon[t] = cn + in - adv;
+          Y[t] = -BIG;
+        }
+        co += to;
+        cn += tn;
+      }
+      if (tid == 0) { Xoff[cnt] = co; Xon[cnt] = cn; }
+      __syncthreads();
+      const int dir = (trow % 3 == 0) ? DIR_LR : DIR_RL;
+      ++trow;
+      const int E = co;  // grown columns of the row's charts
+      for (int e = tid; e < E; e += TAIL_NT) {
+        const int t = find_chart(Xoff, cnt, e), i = e - Xoff[t];
+        int32_t tp, bt;
+        column_bounds_grown(KV(rs + t), ch[rs + t], K, kt, p, i, tp, bt);
+        const int col = dir == DIR_LR ? Xon[t] + i : Wd - 1 - Xon[t] - i;
+        atomicMax(&Y[t], F[col] - tp);
+      }
+      __syncthreads();
+      correct_many_pairs<TAIL_NT>(Xon, Xoff, cnt, rs, lrpre, s_red, s_lr, Y, cnt, wv == 0, flv,
+                                  false, nullptr, w.prow + slot, hdv, kcb, P.stride, ch, K, kt, p);
+      __syncthreads();
+      for (int e = tid; e < E; e += TAIL_NT) {
+        const int t = find_chart(Xoff, cnt, e), i = e - Xoff[t];
+        int32_t tp, bt;
+        column_bounds_grown(KV(rs + t), ch[rs + t], K, kt, p, i, tp, bt);
+        const int col = dir == DIR_LR ? Xon[t] + i : Wd - 1 - Xon[t] - i;
+        atomicMax(&F[col], Y[t] + bt);
+      }
+      // the row's score: a chart's largest grown bottom is h + p
+      int32_t M = -BIG;
+      for (int t = tid; t < cnt; t += TAIL_NT) {
+        const int c = rs + t;
+        const int32_t hdt = (int32_t)(((int64_t)kt * ch[c].H + QS - 1) >> 14) + p;
+        M = max(M, Y[t] + hdt);
+        const int wd = Xoff[t + 1] - Xoff[t];
+        xs[c] = dir == DIR_LR ? Xon[t] : Wd - Xon[t] - wd;
+        ys[c] = Y[t];
+        mir[c] = (uint8_t)(dir == DIR_RL);
+      }
+      fmax = max(fmax, block_reduce_max<WAVES>(M, s_red));
+      if (fmax > Hd) { feasible = 0; break; }
+      rs = re;
+    }
+  }
+
+  // ---- 4. sum over charts of area2 * scale: head at k, tail at kt
+  uint64_t ah = 0, at = 0;  // per thread below 2^56 (area2 < 2^47, n <= 2^18)
+  for (int c = tid; c < n; c += TAIL_NT) {
+    if (c < t0) ah += (uint64_t)ch[c].area2;
+    else at += (uint64_t)ch[c].area2;
+  }
+  ah = wave_sum_u64(ah);  // per wavefront below 2^62
+  at = wave_sum_u64(at);
+  __syncthreads();
+  if (lane == 0) { s_area[wv] = ah; s_area[WAVES + wv] = at; }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned __int128 H = 0, T = 0;
+    for (int i = 0; i < WAVES; ++i) { H += s_area[i]; T += s_area[WAVES + i]; }
+    const unsigned __int128 obj = H * (unsigned)k + T * (unsigned)(feasible == 1 ? kt : 0);
+    w.tail_obj[2 * s] = (uint64_t)obj;
+    w.tail_obj[2 * s + 1] = (uint64_t)(obj >> 64);
+    w.tail_kt[s] = feasible == 1 ? kt : 0;
+    w.feas[s] = feasible;
+  }
+}
+
+// The scale of a hybrid pack: among the feasible slots, the largest sum
+// over charts of area2 * scale (slots without a tail: k times the total
+// area), ties to the larger k; then the outputs with each chart's scale.
+__global__ __launch_bounds__(1024) void k_select_hybrid(Params P, Work w, int32_t* out_xy,
+                                                        uint8_t* out_orient, float* out_ks,
+                                                        float* out_scale) {
+  __shared__ uint64_t s_area[16];
+  __shared__ int32_t s_best;
+  const AtlasDesc d = w.desc[0];
+  const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
+  uint64_t a = 0;
+  for (int c = tid; c < d.n; c += blockDim.x) a += (uint64_t)w.srecs[c].area2;
+  a = wave_sum_u64(a);
+  if (lane == 0) s_area[wv] = a;
+  __syncthreads();
+  if (wv == 0) {
+    unsigned __int128 total = 0;
+    for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) total += s_area[i];
+    const int sl = lane;
+    const bool live = !d.bad && d.n > 0 && sl < P.Br;
+    const int f = live ? w.feas[sl] : 0;
+    const int k = live ? slot_k(P, d, 0, sl) : 0;
+    bool ok = f == 1 && k >= 1;
+    unsigned __int128 obj = 0;
+    if (ok) {
+      if (w.tail_t0[sl] < d.n)
+        obj = ((unsigned __int128)w.tail_obj[2 * sl + 1] << 64) | w.tail_obj[2 * sl];
+      else
+        obj = total * (unsigned)k;
+    }
+    int kk = ok ? k : 0, best = ok ? sl : -1;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const uint64_t ohi = __shfl_xor((unsigned long long)(uint64_t)(obj >> 64), o);
+      const uint64_t olo = __shfl_xor((unsigned long long)(uint64_t)obj, o);
+      const int okk = __shfl_xor(kk, o), ob = __shfl_xor(best, o);
+      const unsigned __int128 oo = ((unsigned __int128)ohi << 64) | olo;
+      if (ob >= 0 && (best < 0 || oo > obj || (oo == obj && okk > kk))) {
+        obj = oo;
+        kk = okk;
+        best = ob;
+      }
+    }
+    if (lane == 0) s_best = best;
+  }
+  __syncthreads();
+  const int best = s_best;
+  const int k = best >= 0 ? slot_k(P, d, 0, best) : 0;
+  const int t0 = best >= 0 ? w.tail_t0[best] : 0;
+  const int kt = best >= 0 && t0 < d.n ? w.tail_kt[best] : k;
+  const size_t slot = (size_t)(best >= 0 ? best : 0) * P.N;
+  for (int t = tid; t < d.n; t += blockDim.x) {
+    const int dst = w.perm[t];
+    if (!d.bad && best >= 0) {
+      out_xy[2 * (size_t)dst] = w.xs[slot + t];
+      out_xy[2 * (size_t)dst + 1] = w.ys[slot + t];
+      out_orient[dst] = (uint8_t)(w.srecs[t].bits | (w.mir[slot + t] << 3));
+      out_ks[dst] = (float)(t < t0 ? k : kt) / 64.0f;
+    } else {
+      out_xy[2 * (size_t)dst] = -1;
+      out_xy[2 * (size_t)dst + 1] = -1;
+      out_orient[dst] = 0;
+      out_ks[dst] = 0.0f;
+    }
+  }
+  if (tid == 0)
+    out_scale[0] = d.bad ? -1.0f : (d.n == 0 ? 1.0f : (best >= 0 ? (float)k / 64.0f : 0.0f));
+}
+
+hipError_t launch_tail(const Params& P, const Work& w, int lds_bytes, int RC, hipStream_t st) {
+  const hipError_t e = hipFuncSetAttribute((const void*)k_tail,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tail, dim3(P.Br), dim3(TAIL_NT), lds_bytes, st, P, w, RC);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_hybrid(const Params& P, const Work& w, int32_t* out_xy,
+                                uint8_t* out_orient, float* out_ks, float* out_scale,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_select_hybrid, dim3(1), dim3(1024), 0, st, P, w, out_xy, out_orient,
+                     out_ks, out_scale);
   return hipGetLastError();
 }
 

@@ -398,6 +398,97 @@ __device__ inline void row_proxies(const KView& kv, const Chart& ch, int K, int 
   ro = rr;
 }
 
+// The per-(scale, chart) set-up record of chart ch at scale k/64, written to
+// `base` (KHead, four KSide, 2K KRect): the chart's texel extents, its
+// local-AABB slices as texel rectangles, and the OBB sides' split points and
+// corners at this scale.  wt, ht: the texel extents.
+template <int KT>
+__device__ inline void build_krec(const Chart& ch, int k, unsigned char* base, int32_t& wt,
+                                  int32_t& ht) {
+  constexpr int K = KT;
+  KHead* hd = reinterpret_cast<KHead*>(base);
+  KSide* sd = reinterpret_cast<KSide*>(base + sizeof(KHead));
+  KRect* rc = reinterpret_cast<KRect*>(base + sizeof(KHead) + 4 * sizeof(KSide));
+  const int64_t kk = k, W = ch.W, H = ch.H;
+  wt = (int32_t)cdiv_i64(kk * W, QS);
+  ht = (int32_t)cdiv_i64(kk * H, QS);
+  KHead h;
+  h.w = wt;
+  h.h = ht;
+  h.obb = ch.m != 0;
+  h.pad = 0;
+  *hd = h;
+  // local-AABB slices as texel rectangles at this scale
+  // (values are clamped to int16; only a chart larger than any atlas reaches
+  // the clamp, and such a scale fails on that chart's width or height anyway)
+  auto i16 = [](int64_t v) { return (int16_t)(v > 32767 ? 32767 : v); };
+  // slice boundaries: j W k / 2^14 < 11 * 2^23 * 64 / 2^14 < 2^19, so the
+  // quotient by K is a 32-bit division by a constant
+  auto slab = [](int64_t num) { return (int32_t)(uint32_t)((uint64_t)num >> 14) / K; };
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    KRect r;
+    r.c0 = i16(slab((int64_t)j * W * kk));
+    r.c1 = i16(slab((int64_t)(j + 1) * W * kk + QS * K - 1));
+    r.r0 = i16(((int64_t)ch.ylo[j] * kk) >> 14);
+    r.r1 = i16(((int64_t)ch.yhi[j] * kk + QS - 1) >> 14);
+    rc[j] = r;
+    KRect y;
+    y.c0 = i16(((int64_t)ch.xlo[j] * kk) >> 14);
+    y.c1 = i16(((int64_t)ch.xhi[j] * kk + QS - 1) >> 14);
+    y.r0 = i16(slab((int64_t)j * H * kk));
+    y.r1 = i16(slab((int64_t)(j + 1) * H * kk + QS * K - 1));
+    rc[K + j] = y;
+  }
+  if (!h.obb) return;
+  const int64_t C = kDirC[ch.m], S = kDirS[ch.m], N = C * C + S * S, D = QS * N;
+  const int64_t a = ch.a, b = ch.b, e = ch.e, f = ch.f;
+  auto split = [&](int64_t num, KSide& sdv) {  // corner position num/D (texels)
+    sdv.sa = clamp32(fdiv_i64(num, D));
+    sdv.sb = clamp32(cdiv_i64(num, D));
+  };
+  KSide st, sb, sL, sR;
+  // top: corner (p=a, q=e); A: (k a - 16384 C x)/(16384 S); B: (k e + 16384 S x)/(16384 C)
+  split(kk * (C * a - S * e), st);
+  st.corner = clamp32(fdiv_i64(kk * (S * a + C * e), D));
+  // bottom: corner (p=b, q=f); A: (k f + 16384 S x)/(16384 C); B: (k b - 16384 C x)/(16384 S)
+  split(kk * (C * b - S * f), sb);
+  sb.corner = clamp32(cdiv_i64(kk * (S * b + C * f), D));
+  // left: corner (p=a, q=f) at row k(Sa+Cf)/D; A: (k a - 16384 S y)/(16384 C); B: (16384 C y - k f)/(16384 S)
+  split(kk * (S * a + C * f), sL);
+  sL.corner = clamp32(fdiv_i64(kk * (C * a - S * f), D));
+  // right: corner (p=b, q=e) at row k(Sb+Ce)/D; A: (16384 C y - k e)/(16384 S); B: (k b - 16384 S y)/(16384 C)
+  split(kk * (S * b + C * e), sR);
+  sR.corner = clamp32(cdiv_i64(kk * (C * b - S * e), D));
+  // last column / row: the extent may end inside the texel
+  const int64_t tw = wt - 1, th = ht - 1;
+  const bool wfrac = (kk * W) % QS != 0, hfrac = (kk * H) % QS != 0;
+  // top
+  if (!wfrac ? (tw + 1 <= st.sa) : (W * N <= C * a - S * e))
+    st.last = clamp32(!wfrac ? fdiv_i64(kk * a - QS * C * (tw + 1), QS * S) : fdiv_i64(kk * (a - C * W), QS * S));
+  else if (tw >= st.sb) st.last = clamp32(fdiv_i64(kk * e + QS * S * tw, QS * C));
+  else st.last = st.corner;
+  // bottom
+  if (!wfrac ? (tw + 1 <= sb.sa) : (W * N <= C * b - S * f))
+    sb.last = clamp32(!wfrac ? cdiv_i64(kk * f + QS * S * (tw + 1), QS * C) : cdiv_i64(kk * (f + S * W), QS * C));
+  else if (tw >= sb.sb) sb.last = clamp32(cdiv_i64(kk * b - QS * C * tw, QS * S));
+  else sb.last = sb.corner;
+  // left
+  if (!hfrac ? (th + 1 <= sL.sa) : (H * N <= S * a + C * f))
+    sL.last = clamp32(!hfrac ? fdiv_i64(kk * a - QS * S * (th + 1), QS * C) : fdiv_i64(kk * (a - S * H), QS * C));
+  else if (th >= sL.sb) sL.last = clamp32(fdiv_i64(QS * C * th - kk * f, QS * S));
+  else sL.last = sL.corner;
+  // right
+  if (!hfrac ? (th + 1 <= sR.sa) : (H * N <= S * b + C * e))
+    sR.last = clamp32(!hfrac ? cdiv_i64(QS * C * (th + 1) - kk * e, QS * S) : cdiv_i64(kk * (C * H - e), QS * S));
+  else if (th >= sR.sb) sR.last = clamp32(cdiv_i64(kk * b - QS * S * th, QS * C));
+  else sR.last = sR.corner;
+  sd[0] = st;
+  sd[1] = sb;
+  sd[2] = sL;
+  sd[3] = sR;
+}
+
 // Gutter growth: a footprint grows by [0,p]^2 toward +x, +y, so a grown
 // column i takes the min top / max bottom over undilated columns [i-p, i].
 __device__ inline void column_bounds_grown(const KView& kv, const Chart& ch, int K, int k, int p,

@@ -36,6 +36,8 @@ struct Params {
   int32_t pack_nt;     // fold-and-push workgroup size: 512, 1024, or 0 (by atlas count)
   int32_t topt;        // t_opt in percent; < 0: 0 up to 10,000 charts in the atlas, 1 above
   int32_t variant;     // 0 full, 1 tight-only (static rows), 2 balanced-only (boxes)
+  int32_t hybrid;      // 1: after the t_opt switch the charts are folded by prefix sums at a
+                       // scale of their own (Sec. 4.4); single atlas, every scale a slot
 };
 
 // Work-space views (device pointers).
@@ -74,6 +76,10 @@ struct Work {
   int32_t* aord;        // [count] dispatch order of the packing kernel's atlases
   int32_t* live;        // [MAX_ROUNDS + 1] live[r] != 0: some atlas still searches in round
                         // r >= 1 (set by round r - 1's selection, cleared at the start)
+  int32_t* tailF;       // [B][Wdmax] hybrid: the frontline at the t_opt switch
+  int32_t* tail_t0;     // [B] hybrid: first chart of the tail (sorted), n when there is none
+  int32_t* tail_kt;     // [B] hybrid: the tail's scale
+  uint64_t* tail_obj;   // [B][2] hybrid: sum over charts of area2 * scale (low, high word)
   uint32_t* arena;      // profiles: per grown column (top, bottom), per grown row
                         // (left, right) of the local AABBs, then of the OBB, int16
                         // pairs (pack16)
@@ -125,6 +131,13 @@ hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes,
                        float* out_scale, hipStream_t st);
 hipError_t launch_select(const Params& P, const Work& w, int round, int last_round,
                          int32_t* out_xy, uint8_t* out_orient, float* out_scale, hipStream_t st);
+// hybrid tail of every slot that reached the t_opt switch (single atlas,
+// after launch_pack), then the choice of the scale by the area-weighted
+// final scale and the outputs, with each chart's own scale in out_ks
+hipError_t launch_tail(const Params& P, const Work& w, int lds_bytes, int RC, hipStream_t st);
+hipError_t launch_select_hybrid(const Params& P, const Work& w, int32_t* out_xy,
+                                uint8_t* out_orient, float* out_ks, float* out_scale,
+                                hipStream_t st);
 
 hipError_t launch_scatter(const Params& P, const Work& w, int32_t* out_xy, uint8_t* out_orient,
                           int32_t* feasible, int32_t* rows, hipStream_t st);
