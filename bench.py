@@ -266,6 +266,79 @@ def config_legs(tabi, torch, cpu):
     return legs
 
 
+def variants_leg(tabi, torch, reps=20):
+    """Input-side and tail variants, p50 of HIP-event times per call: the
+    2,000-chart workload pre-rotated to tight boxes (tabi_pack_prerotate,
+    against tabi_pack on the same charts as given); the hybrid tail
+    (tabi_pack_hybrid) on the 20,000-chart workload at the paper's t_opt and
+    on the 2,000-chart workload at t_opt 5 %, against tabi_pack_method with the
+    same knobs (exact greedy tail), with the area-weighted mean L2 stretch
+    (64 / k per chart); and 2,000 mesh charts of several boundary loops
+    (tabi_pack_loops)."""
+    import numpy as np
+    from paper_2602_07782_amd import synth
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        out = fn()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(st)
+            out = fn()
+            b.record(st)
+        torch.cuda.synchronize()
+        return round(percentile([a.elapsed_time(b) for a, b in ev], 50), 4), out
+
+    def area2(inp):
+        out = []
+        for c in range(inp.n):
+            P = inp.chart(c).astype(np.int64)
+            x, y = P[:, 0], P[:, 1]
+            out.append(abs(int(np.dot(x, np.roll(y, -1)) - np.dot(np.roll(x, -1), y))))
+        return np.array(out, np.float64)
+
+    res = {}
+    inp = synth.make_input("mixed2k", 0)
+    xy = torch.from_numpy(np.ascontiguousarray(inp.xy, np.int32)).to(dev)
+    off = torch.from_numpy(np.ascontiguousarray(inp.offsets, np.int32)).to(dev)
+    ms, out = timed(lambda: tabi.pack_prerotate(xy, off, inp.atlas_w, inp.atlas_h, inp.padding, 2,
+                                                stream=st))
+    ms0, out0 = timed(lambda: tabi.pack(xy, off, inp.atlas_w, inp.atlas_h, inp.padding, 2,
+                                        stream=st))
+    res["prerotate_mixed2k_q2"] = {"p50_ms": ms, "scale": float(out[4].cpu()[0]),
+                                   "plain_p50_ms": ms0, "plain_scale": float(out0[2].cpu()[0])}
+    for name, topt in (("lightmap20k", -1), ("mixed2k", 5)):
+        inp = synth.make_input(name, 0)
+        xy = torch.from_numpy(np.ascontiguousarray(inp.xy, np.int32)).to(dev)
+        off = torch.from_numpy(np.ascontiguousarray(inp.offsets, np.int32)).to(dev)
+        ms, out = timed(lambda: tabi.pack_hybrid(xy, off, inp.atlas_w, inp.atlas_h, inp.padding,
+                                                 10, topt, stream=st))
+        ms0, out0 = timed(lambda: tabi.pack_method(xy, off, inp.atlas_w, inp.atlas_h,
+                                                   inp.padding, 10, topt, 0, stream=st))
+        w = area2(inp)
+        ks = out[2].cpu().numpy().astype(np.float64)
+        k0 = float(out0[2].cpu()[0])
+        res[f"hybrid_{name}_topt{topt}"] = {
+            "p50_ms": ms, "head_scale": float(out[3].cpu()[0]),
+            "tail_charts": int((ks < float(out[3].cpu()[0])).sum()),
+            "area_weighted_stretch": round(float((w / ks).sum() / w.sum()), 4) if ks.min() > 0
+            else None,
+            "greedy_tail_p50_ms": ms0,
+            "greedy_tail_stretch": round(1.0 / k0, 4) if k0 > 0 else None}
+    L, _ = synth.make_loops(2000, 2048, 2048, 2, 2, 7100)
+    lxy = torch.from_numpy(np.ascontiguousarray(L.xy, np.int32)).to(dev)
+    llo = torch.from_numpy(np.ascontiguousarray(L.loop_offsets, np.int32)).to(dev)
+    lcl = torch.from_numpy(np.ascontiguousarray(L.chart_loops, np.int32)).to(dev)
+    ms, out = timed(lambda: tabi.pack_loops(lxy, llo, lcl, L.atlas_w, L.atlas_h, L.padding,
+                                            L.quality, stream=st))
+    res["loops_2000"] = {"p50_ms": ms, "scale": float(out[2].cpu()[0]),
+                         "loops": int(len(L.loop_offsets) - 1)}
+    return res
+
+
 def atlas_algorithmic_bytes(inp, kstar):
     """Bytes the method must move for one atlas pack: vertices and offsets
     read (8 V + 4 (n + 1)), per-chart proxies written and read
@@ -553,6 +626,11 @@ def main():
             result["ablations"] = ablation_leg(tabi, torch)
         except Exception as e:
             result["ablations"] = {"error": repr(e)}
+    if not args.no_configs:
+        try:
+            result["variants"] = variants_leg(tabi, torch)
+        except Exception as e:
+            result["variants"] = {"error": repr(e)}
     if not args.no_batched:
         try:
             result["batched"] = batched_leg(tabi, torch,

@@ -201,7 +201,7 @@ Layout layout(const Params& P) {
   L.o_tailF = take(hb * (size_t)P.Wdmax * 4);
   L.o_tail_t0 = take(hb * 4);
   L.o_tail_kt = take(hb * 4);
-  L.o_tail_obj = take(hb * 16);
+  L.o_tail_obj = take(P.hybrid ? (hb + 1) * 16 : 0);
   L.o_arena = take((size_t)P.arena_cap * 4);
   L.total = off;
   return L;
@@ -670,7 +670,7 @@ int tabi_pack_hybrid(const tabi_charts* charts, int32_t n, int32_t atlas_w, int3
       StageScope t(ST_PACK, st);
       e = launch_pack(j.P, j.W, 0, j.L.bytes, j.L.RC, j.L.PW, j.stage_cap, 1, out_xy, out_orient,
                       out_scale, st);
-      if (e == hipSuccess) e = launch_tail(j.P, j.W, j.L.bytes, j.L.RC, st);
+      if (e == hipSuccess) e = launch_tail(j.P, j.W, j.L.bytes, j.L.RC, j.L.PW, st);
     }
     if (e == hipSuccess) {
       StageScope t(ST_SELECT, st);

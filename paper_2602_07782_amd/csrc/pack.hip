@@ -876,14 +876,16 @@ hipError_t launch_pack(const Params& P, const Work& w, int round, int lds_bytes,
 //   1. rows by prefix-sum folding at the head scale k: chart j's offset is
 //      its grown width less the compacting distance to chart j + 1, and the
 //      prefix sum of the offsets divided by the grown atlas width is its row;
-//   2. the tail's scale kt, from k down: the set-up records, grown extents
-//      and neighbour pairs of the tail charts at kt (records overwritten in
-//      the slot's arrays), accepted when every row laid out with compaction
-//      at kt fits the width;
+//   2. the tail's scale kt, from k down, accepted when every row laid out
+//      with compaction at kt fits the width;
 //   3. the rows in order, in the one left-to-right : two right-to-left
 //      alternation: push, correction (Alg. 1), frontline update and the
-//      overflow test, every texel bound evaluated from the records at kt;
+//      overflow test.
 //   4. the slot's sum over charts of area * scale.
+// A hybrid pack evaluates every scale 1..64 in a slot of its own, so all
+// the tail needs at kt (grown extents, set-up records, compacting distances
+// and flags of sorted neighbours, stored profiles) is read, unchanged, from
+// the slot of scale kt.
 // k_select_hybrid then keeps the slot with the largest sum (ties to the
 // larger k) and writes the outputs with each chart's own scale.
 // ---------------------------------------------------------------------------
@@ -928,19 +930,13 @@ __device__ inline int32_t block_incl_max(int32_t v, int32_t* red, int32_t& total
   return max(base, incl);
 }
 
-__device__ inline void build_krec_rt(int K, const Chart& ch, int k, unsigned char* base,
-                                     int32_t& wt, int32_t& ht) {
-  if (K == 10) build_krec<10>(ch, k, base, wt, ht);
-  else if (K == 5) build_krec<5>(ch, k, base, wt, ht);
-  else if (K == 2) build_krec<2>(ch, k, base, wt, ht);
-  else build_krec<1>(ch, k, base, wt, ht);
-}
-
-__global__ __launch_bounds__(TAIL_NT) void k_tail(Params P, Work w, int RC) {
+__global__ __launch_bounds__(TAIL_NT) void k_tail(Params P, Work w, int RC, int PW) {
   constexpr int WAVES = TAIL_NT / WAVE;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t s_red[WAVES * 6];
   __shared__ int32_t s_lr[LRCAP][3];
+  __shared__ int32_t s_lrn, s_lrover;
+  __shared__ int32_t s_seg[TAIL_NT];
   __shared__ uint64_t s_area[2 * WAVES];
   const int s = blockIdx.x;
   if (w.feas[s] != 2) return;  // no tail at this slot (uniform)
@@ -948,24 +944,19 @@ __global__ __launch_bounds__(TAIL_NT) void k_tail(Params P, Work w, int RC) {
   const int k = slot_k(P, d, 0, s);
   const int n = d.n, Wd = d.Wa + P.p, Hd = d.Ha + P.p, p = P.p, K = P.K;
   const int tid = threadIdx.x, wv = tid / WAVE, lane = lane_id();
-  const size_t slot = (size_t)s * P.N;
   // dynamic LDS (the fold-and-push plan): frontline, row offsets without /
-  // with compaction, the row's offsets Y
+  // with compaction, then a pool of PW words: the row's offsets Y (RC) and
+  // its texel bounds
   int32_t* F = reinterpret_cast<int32_t*>(smem);
   int32_t* Xoff = F + Wd;
   int32_t* Xon = Xoff + (RC + 1);
   int32_t* Y = Xon + (RC + 1);
-  unsigned char* kcb = w.kc + slot * P.stride;
   const Chart* ch = w.srecs;
-  int32_t* cdv = w.cd + slot;
-  uint8_t* flv = w.fl + slot;
-  int32_t* wdv = w.wdv + slot;
-  int32_t* hdv = w.hdv + slot;
+  const size_t slot = (size_t)s * P.N;
   int32_t* xs = w.xs + slot;   // first: each tail chart's row start
   int32_t* ys = w.ys + slot;   // first: each tail chart's row (low 32 bits)
   uint8_t* mir = w.mir + slot;
-  int32_t* lrpre = w.lrpre + slot;  // first: prefix sums of the offsets at kt
-  auto KV = [&](int c) { return kview(kcb + (size_t)c * P.stride, K); };
+  int32_t* lrpre = w.lrpre + slot;
   const int t0 = w.tail_t0[s];
 
   int32_t fm = 0;
@@ -978,10 +969,12 @@ __global__ __launch_bounds__(TAIL_NT) void k_tail(Params P, Work w, int RC) {
 
   // ---- 1. rows by prefix sums of the offsets at the head scale
   {
+    const int32_t* wdk = w.wdv + slot;
+    const int32_t* cdk = w.cd + slot;
     int64_t carry = 0;
     for (int b0 = t0; b0 < n; b0 += TAIL_NT) {
       const int j = b0 + tid;
-      const int32_t a = j < n ? wdv[j] - (j + 1 < n ? cdv[j + 1] : 0) : 0;
+      const int32_t a = j < n ? wdk[j] - (j + 1 < n ? cdk[j + 1] : 0) : 0;
       int32_t tot;
       const int32_t incl = block_incl_sum<WAVES>(a, s_red, tot);
       if (j < n) ys[j] = (int32_t)(uint32_t)((uint64_t)(carry + incl - a) / (uint64_t)Wd);
@@ -1000,55 +993,56 @@ __global__ __launch_bounds__(TAIL_NT) void k_tail(Params P, Work w, int RC) {
     }
   }
 
-  // ---- 2. the tail's scale: the largest kt <= k at which every row fits
+  // ---- 2. the tail's scale: the largest kt <= k at which every row fits.
+  // A chunk of charts at a time (offsets within the rows, a segmented sum);
+  // a candidate is dropped at the first chunk with a chart past the right
+  // edge (rows folded by prefix sums mostly end in such a chart).
   int kt = k, feasible = 0;
-  for (; kt >= 1; --kt) {
-    __syncthreads();
-    for (int j = t0 + tid; j < n; j += TAIL_NT) {
-      int32_t wt, ht;
-      build_krec_rt(K, ch[j], kt, kcb + (size_t)j * P.stride, wt, ht);
-      wdv[j] = wt + p;
-      hdv[j] = ht + p;
-    }
-    __syncthreads();
-    // neighbours in one row: compacting distance and flags at kt (one
-    // wavefront per pair); other neighbours are never compacted
-    for (int j = t0 + wv; j < n; j += WAVES) {
-      PairResult r{0, 0};
-      if (j > t0 && xs[j] == xs[j - 1]) r = pair_records_both(KV(j - 1), ch[j - 1], KV(j), ch[j], K, kt, p);
-      if (lane == 0) {
-        cdv[j] = r.cd;
-        flv[j] = (uint8_t)r.flags;
-      }
-    }
-    __syncthreads();
-    // offsets within the rows: prefix sums (mod 2^32) of the offsets, less
-    // the sum at the row start; a row's offsets stay below 2^29
-    {
-      uint32_t carry = 0;
-      for (int b0 = t0; b0 < n; b0 += TAIL_NT) {
-        const int j = b0 + tid;
-        const int32_t a = j < n ? wdv[j] - (j + 1 < n ? cdv[j + 1] : 0) : 0;
-        int32_t tot;
-        const int32_t incl = block_incl_sum<WAVES>(a, s_red, tot);
-        if (j < n) lrpre[j] = (int32_t)(carry + (uint32_t)(incl - a));
-        carry += (uint32_t)tot;
-      }
-    }
-    __syncthreads();
+  for (; kt >= 1 && !feasible; --kt) {
+    const size_t sl = (size_t)(d.ktop - P.koff - kt) * P.N;  // the slot of scale kt
+    const int32_t* wdt = w.wdv + sl;
+    const int32_t* cdt = w.cd + sl;
     int over = 0;
-    for (int j = t0 + tid; j < n; j += TAIL_NT) {
-      const int64_t X = (int32_t)((uint32_t)lrpre[j] - (uint32_t)lrpre[xs[j]]);
-      over |= X + wdv[j] > Wd;
+    int32_t xc = 0;  // offset of the chart after the previous chunk, within its row
+    for (int b0 = t0; b0 < n && !over; b0 += TAIL_NT) {
+      const int j = b0 + tid, b1 = min(n, b0 + TAIL_NT);
+      const bool in = j < b1;
+      // X_j = X_{j-1} + w'_{j-1} - cd_j, 0 at a row's first chart
+      const bool head = in && xs[j] == j;
+      const int32_t inc = (in && !head) ? wdt[j - 1] - cdt[j] : 0;
+      int32_t tot;
+      const int32_t S = block_incl_sum<WAVES>(inc, s_red, tot);
+      s_seg[tid] = S;
+      __syncthreads();
+      int32_t X = 0;
+      if (in) {
+        const int st = xs[j];
+        X = st < b0 ? xc + S : S - s_seg[st - b0];
+        over = X + wdt[j] > Wd;
+      }
+      if (j == b1 - 1) s_red[WAVES * 6 - 1] = X;
+      over = __syncthreads_or(over);
+      xc = uni(s_red[WAVES * 6 - 1]);
     }
-    if (!__syncthreads_or(over)) {
-      feasible = 1;
-      break;
-    }
+    if (!over) feasible = 1;
   }
+  ++kt;  // the loop stepped past the scale that fit
 
-  // ---- 3. the rows, pushed up in the fixed direction alternation
+  // ---- 3. the rows, pushed up in the fixed direction alternation, with
+  // the data of the slot of scale kt
   if (feasible) {
+    const size_t sl = (size_t)(d.ktop - P.koff - kt) * P.N;
+    const int32_t* wdt = w.wdv + sl;
+    const int32_t* hdt = w.hdv + sl;
+    const int32_t* cdt = w.cd + sl;
+    const uint8_t* flt = w.fl + sl;
+    const int32_t* pcol = w.pcol + sl;
+    const int32_t* prow = w.prow + sl;
+    const unsigned char* kct = w.kc + sl * P.stride;
+    const int32_t sbase = w.segbase[d.ktop - P.koff - kt];  // -1: profiles not stored
+    const bool prof = sbase >= 0;
+    const uint32_t* seg = w.arena + (prof ? sbase : 0);
+    auto KV = [&](int c) { return kview(kct + (size_t)c * P.stride, K); };
     int rs = t0, trow = 0;
     while (rs < n) {
       int re = n;  // the row ends at the first chart of another row
@@ -1062,8 +1056,8 @@ __global__ __launch_bounds__(TAIL_NT) void k_tail(Params P, Work w, int RC) {
       int32_t co = 0, cn = 0;
       for (int b0 = 0; b0 < cnt; b0 += TAIL_NT) {
         const int t = b0 + tid, c = rs + t;
-        const int32_t wd = t < cnt ? wdv[c] : 0;
-        const int32_t adv = t < cnt ? wd - (t + 1 < cnt ? cdv[c + 1] : 0) : 0;
+        const int32_t wd = t < cnt ? wdt[c] : 0;
+        const int32_t adv = t < cnt ? wd - (t + 1 < cnt ? cdt[c + 1] : 0) : 0;
         int32_t to, tn;
         const int32_t io = block_incl_sum<WAVES>(wd, s_red, to);
         const int32_t in = block_incl_sum<WAVES>(adv, s_red, tn);
@@ -1075,26 +1069,70 @@ __global__ __launch_bounds__(TAIL_NT) void k_tail(Params P, Work w, int RC) {
         co += to;
         cn += tn;
       }
-      if (tid == 0) { Xoff[cnt] = co; Xon[cnt] = cn; }
+      if (tid == 0) {
+        Xoff[cnt] = co;
+        Xon[cnt] = cn;
+        s_lrn = 0;
+        s_lrover = 0;
+      }
       __syncthreads();
       const int dir = (trow % 3 == 0) ? DIR_LR : DIR_RL;
       ++trow;
       const int E = co;  // grown columns of the row's charts
+      // texel bounds: stored (the row's charts are consecutive in the
+      // segment, so texel e is word pcol[rs] + e), else from the records and
+      // kept in shared memory for the update when they fit
+      uint32_t* stg = reinterpret_cast<uint32_t*>(Y + RC);
+      const bool staged = !prof && RC + E <= PW;
+      const uint32_t* gprof = seg + (prof ? pcol[rs] : 0);
       for (int e = tid; e < E; e += TAIL_NT) {
         const int t = find_chart(Xoff, cnt, e), i = e - Xoff[t];
         int32_t tp, bt;
-        column_bounds_grown(KV(rs + t), ch[rs + t], K, kt, p, i, tp, bt);
+        if (prof) {
+          tp = lo16(gprof[e]);
+        } else {
+          column_bounds_grown(KV(rs + t), ch[rs + t], K, kt, p, i, tp, bt);
+          if (staged) stg[e] = pack16(tp, bt);
+        }
         const int col = dir == DIR_LR ? Xon[t] + i : Wd - 1 - Xon[t] - i;
         atomicMax(&Y[t], F[col] - tp);
       }
+      // pairs that share columns without being neighbours
+      for (int A = tid; A + 2 < cnt; A += TAIL_NT) {
+        const int wdA = Xoff[A + 1] - Xoff[A];
+        for (int C = A + 2; C < cnt && Xon[C] - Xon[A] < wdA; ++C) {
+          const int q = atomicAdd(&s_lrn, 1);
+          if (q < LRCAP) { s_lr[q][0] = A; s_lr[q][1] = C; s_lr[q][2] = 0; }
+          else s_lrover = 1;
+        }
+      }
       __syncthreads();
-      correct_many_pairs<TAIL_NT>(Xon, Xoff, cnt, rs, lrpre, s_red, s_lr, Y, cnt, wv == 0, flv,
-                                  false, nullptr, w.prow + slot, hdv, kcb, P.stride, ch, K, kt, p);
+      if (uni(s_lrover)) {  // more than the shared list holds: out of line
+        correct_many_pairs<TAIL_NT>(Xon, Xoff, cnt, rs, lrpre, s_red, s_lr, Y, cnt, wv == 0, flt,
+                                    prof, seg, prow, hdt, kct, P.stride, ch, K, kt, p);
+      } else {
+        const int lrn = uni(s_lrn);
+        for (int q = wv; q < lrn; q += WAVES) {
+          const int A = s_lr[q][0], C = s_lr[q][1];
+          const int wdA = Xoff[A + 1] - Xoff[A];
+          const PairSweep sw =
+              prof ? pair_rows_meet(seg + prow[rs + A], hdt[rs + A], seg + prow[rs + C],
+                                    hdt[rs + C], wdA)
+                   : pair_records_sweep<2>(KV(rs + A), ch[rs + A], KV(rs + C), ch[rs + C], K,
+                                           kt, p);
+          const int f = pair_flags_at(sw, wdA, Xon[C] - Xon[A]);
+          if (lane == 0) s_lr[q][2] = f;
+        }
+        __syncthreads();
+        if (wv == 0) correct_offsets(Y, cnt, flt + rs, s_lr, lrn);
+      }
       __syncthreads();
       for (int e = tid; e < E; e += TAIL_NT) {
         const int t = find_chart(Xoff, cnt, e), i = e - Xoff[t];
         int32_t tp, bt;
-        column_bounds_grown(KV(rs + t), ch[rs + t], K, kt, p, i, tp, bt);
+        if (prof) bt = hi16(gprof[e]);
+        else if (staged) bt = hi16(stg[e]);
+        else column_bounds_grown(KV(rs + t), ch[rs + t], K, kt, p, i, tp, bt);
         const int col = dir == DIR_LR ? Xon[t] + i : Wd - 1 - Xon[t] - i;
         atomicMax(&F[col], Y[t] + bt);
       }
@@ -1102,8 +1140,7 @@ __global__ __launch_bounds__(TAIL_NT) void k_tail(Params P, Work w, int RC) {
       int32_t M = -BIG;
       for (int t = tid; t < cnt; t += TAIL_NT) {
         const int c = rs + t;
-        const int32_t hdt = (int32_t)(((int64_t)kt * ch[c].H + QS - 1) >> 14) + p;
-        M = max(M, Y[t] + hdt);
+        M = max(M, Y[t] + hdt[c]);
         const int wd = Xoff[t + 1] - Xoff[t];
         xs[c] = dir == DIR_LR ? Xon[t] : Wd - Xon[t] - wd;
         ys[c] = Y[t];
@@ -1140,26 +1177,21 @@ __global__ __launch_bounds__(TAIL_NT) void k_tail(Params P, Work w, int RC) {
 // The scale of a hybrid pack: among the feasible slots, the largest sum
 // over charts of area2 * scale (slots without a tail: k times the total
 // area), ties to the larger k; then the outputs with each chart's scale.
-__global__ __launch_bounds__(1024) void k_select_hybrid(Params P, Work w, int32_t* out_xy,
-                                                        uint8_t* out_orient, float* out_ks,
-                                                        float* out_scale) {
-  __shared__ uint64_t s_area[16];
+// Every workgroup finds the same slot and writes its share of the charts.
+__global__ __launch_bounds__(256) void k_select_hybrid(Params P, Work w, int32_t* out_xy,
+                                                       uint8_t* out_orient, float* out_ks,
+                                                       float* out_scale) {
   __shared__ int32_t s_best;
   const AtlasDesc d = w.desc[0];
-  const int tid = threadIdx.x, lane = lane_id(), wv = tid / WAVE;
-  uint64_t a = 0;
-  for (int c = tid; c < d.n; c += blockDim.x) a += (uint64_t)w.srecs[c].area2;
-  a = wave_sum_u64(a);
-  if (lane == 0) s_area[wv] = a;
-  __syncthreads();
-  if (wv == 0) {
-    unsigned __int128 total = 0;
-    for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) total += s_area[i];
+  const int tid = threadIdx.x, lane = lane_id();
+  if (tid < WAVE) {
+    const unsigned __int128 total =
+        ((unsigned __int128)w.tail_obj[2 * P.B + 1] << 64) | w.tail_obj[2 * P.B];
     const int sl = lane;
     const bool live = !d.bad && d.n > 0 && sl < P.Br;
     const int f = live ? w.feas[sl] : 0;
     const int k = live ? slot_k(P, d, 0, sl) : 0;
-    bool ok = f == 1 && k >= 1;
+    const bool ok = f == 1 && k >= 1;
     unsigned __int128 obj = 0;
     if (ok) {
       if (w.tail_t0[sl] < d.n)
@@ -1188,7 +1220,7 @@ __global__ __launch_bounds__(1024) void k_select_hybrid(Params P, Work w, int32_
   const int t0 = best >= 0 ? w.tail_t0[best] : 0;
   const int kt = best >= 0 && t0 < d.n ? w.tail_kt[best] : k;
   const size_t slot = (size_t)(best >= 0 ? best : 0) * P.N;
-  for (int t = tid; t < d.n; t += blockDim.x) {
+  for (int t = blockIdx.x * blockDim.x + tid; t < d.n; t += gridDim.x * blockDim.x) {
     const int dst = w.perm[t];
     if (!d.bad && best >= 0) {
       out_xy[2 * (size_t)dst] = w.xs[slot + t];
@@ -1202,22 +1234,25 @@ __global__ __launch_bounds__(1024) void k_select_hybrid(Params P, Work w, int32_
       out_ks[dst] = 0.0f;
     }
   }
-  if (tid == 0)
+  if (blockIdx.x == 0 && tid == 0)
     out_scale[0] = d.bad ? -1.0f : (d.n == 0 ? 1.0f : (best >= 0 ? (float)k / 64.0f : 0.0f));
 }
 
-hipError_t launch_tail(const Params& P, const Work& w, int lds_bytes, int RC, hipStream_t st) {
+hipError_t launch_tail(const Params& P, const Work& w, int lds_bytes, int RC, int PW,
+                       hipStream_t st) {
   const hipError_t e = hipFuncSetAttribute((const void*)k_tail,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_tail, dim3(P.Br), dim3(TAIL_NT), lds_bytes, st, P, w, RC);
+  hipLaunchKernelGGL(k_tail, dim3(P.Br), dim3(TAIL_NT), lds_bytes, st, P, w, RC, PW);
   return hipGetLastError();
 }
 
 hipError_t launch_select_hybrid(const Params& P, const Work& w, int32_t* out_xy,
                                 uint8_t* out_orient, float* out_ks, float* out_scale,
                                 hipStream_t st) {
-  hipLaunchKernelGGL(k_select_hybrid, dim3(1), dim3(1024), 0, st, P, w, out_xy, out_orient,
+  int blocks = (P.N + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+  hipLaunchKernelGGL(k_select_hybrid, dim3(blocks), dim3(256), 0, st, P, w, out_xy, out_orient,
                      out_ks, out_scale);
   return hipGetLastError();
 }

@@ -218,12 +218,43 @@ __device__ inline PairSweep pair_records_sweep(const KView& A, const Chart& cA, 
   return sweep_end<false>(st);
 }
 
-// A neighbour pair from the proxy records: both proxies, the larger distance.
+// A neighbour pair from the proxy records: both proxies' sweeps in one pass
+// over the rows (each row of each chart evaluated once), the larger distance.
 __device__ inline PairResult pair_records_both(const KView& A, const Chart& cA, const KView& B,
                                                const Chart& cB, int K, int k, int p) {
-  const PairSweep sa = pair_records_sweep<0>(A, cA, B, cB, K, k, p);
-  const PairSweep so = pair_records_sweep<1>(A, cA, B, cB, K, k, p);
-  return pair_pick(sa, so, A.hd->w + p);
+  const int lane = lane_id();
+  const int hA = A.hd->h, hB = B.hd->h, wdA = A.hd->w + p;
+  const int hdA = hA + p, hdB = hB + p;
+  SweepState sa = sweep_start(), so = sweep_start();
+  const int step = WAVE - p;
+  for (int j0 = 0; j0 < hdA; j0 += step) {
+    const int u = j0 - p + lane;  // undilated row held by this lane
+    int32_t raa = -BIG, rao = -BIG, lba = BIG, lbo = BIG;
+    if (u >= 0 && u < hA) {
+      int32_t l1, l2;
+      row_proxies(A, cA, K, k, u, l1, raa, l2, rao);
+    }
+    if (u >= 0 && u < hB) {
+      int32_t r1, r2;
+      row_proxies(B, cB, K, k, u, lba, r1, lbo, r2);
+    }
+    int32_t Ra = raa, La = lba, Ro = rao, Lo = lbo;
+    for (int s = 1; s <= p; ++s) {
+      raa = wave_shr1(raa, -BIG);
+      lba = wave_shr1(lba, BIG);
+      rao = wave_shr1(rao, -BIG);
+      lbo = wave_shr1(lbo, BIG);
+      Ra = max(Ra, raa);
+      La = min(La, lba);
+      Ro = max(Ro, rao);
+      Lo = min(Lo, lbo);
+    }
+    const int j = u;  // grown row j = lanes [j-p, j] of this chunk
+    const bool act = lane >= p && j < hdA, shr = act && j < hdB;
+    sweep_chunk<false>(sa, Ra + p, La, act, shr, j, wdA);
+    sweep_chunk<false>(so, Ro + p, Lo, act, shr, j, wdA);
+  }
+  return pair_pick(sweep_end<false>(sa), sweep_end<false>(so), wdA);
 }
 
 }  // namespace tabi

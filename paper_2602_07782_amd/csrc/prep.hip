@@ -442,7 +442,14 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
     // holds for the scale of the rows before it: every scale is a candidate
     if (P.hybrid) ktop = 64;
   }
-  if (lane == 0) { w.desc[a].ktop = ktop; w.desc[a].bad = bad; }
+  if (lane == 0) {
+    w.desc[a].ktop = ktop;
+    w.desc[a].bad = bad;
+    if (P.hybrid) {  // the total area, for the choice among the hybrid packs
+      w.tail_obj[2 * P.B] = (uint64_t)S;
+      w.tail_obj[2 * P.B + 1] = (uint64_t)(S >> 64);
+    }
+  }
 }
 
 // one thread per (slot, chart)

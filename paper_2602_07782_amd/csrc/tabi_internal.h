@@ -79,7 +79,8 @@ struct Work {
   int32_t* tailF;       // [B][Wdmax] hybrid: the frontline at the t_opt switch
   int32_t* tail_t0;     // [B] hybrid: first chart of the tail (sorted), n when there is none
   int32_t* tail_kt;     // [B] hybrid: the tail's scale
-  uint64_t* tail_obj;   // [B][2] hybrid: sum over charts of area2 * scale (low, high word)
+  uint64_t* tail_obj;   // [B + 1][2] hybrid: sum over charts of area2 * scale (low, high
+                        // word) per slot, then the charts' total area2 (from the plan)
   uint32_t* arena;      // profiles: per grown column (top, bottom), per grown row
                         // (left, right) of the local AABBs, then of the OBB, int16
                         // pairs (pack16)
@@ -134,7 +135,8 @@ hipError_t launch_select(const Params& P, const Work& w, int round, int last_rou
 // hybrid tail of every slot that reached the t_opt switch (single atlas,
 // after launch_pack), then the choice of the scale by the area-weighted
 // final scale and the outputs, with each chart's own scale in out_ks
-hipError_t launch_tail(const Params& P, const Work& w, int lds_bytes, int RC, hipStream_t st);
+hipError_t launch_tail(const Params& P, const Work& w, int lds_bytes, int RC, int PW,
+                       hipStream_t st);
 hipError_t launch_select_hybrid(const Params& P, const Work& w, int32_t* out_xy,
                                 uint8_t* out_orient, float* out_ks, float* out_scale,
                                 hipStream_t st);
