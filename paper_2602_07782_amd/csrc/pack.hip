@@ -439,6 +439,9 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       }
     }
     // ---- 2. folding (Alg. 2), wavefront 0
+    const bool prof = pc0 >= 0;  // stored profiles: texel e of the row is word pc0 + e
+    const uint32_t* gprof = w.arena + (prof ? pc0 : 0);
+    uint32_t* st = reinterpret_cast<uint32_t*>(pool);
     const int kw = kn ? (kdir == DIR_LR ? Wd - kr : kl) : 0;
     if (wv == 0) {
       int cfo = -1, cfn = -1, cko = -1, ckn = -1;
@@ -504,13 +507,10 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
 #pragma unroll
     for (int j = 0; j < 4; ++j) { anyhc |= c_hc[j]; yofs[j] = ysum; ysum += c_cnt[j]; }
     const int E = uni(Xoff[cand]);  // grown texel columns of the candidates
-    // pool: offsets Y of configuration j at pool[yofs[j]], then (when staged)
-    // packed (top, bottom) of texel e at st[e] and its chart at emap[e]
-    int32_t* Yb = pool;
-    uint32_t* st = reinterpret_cast<uint32_t*>(pool + ysum);
-    int16_t* emap = reinterpret_cast<int16_t*>(pool + ysum + E);
-    const bool prof = pc0 >= 0;  // stored profiles: texel e of the row is word pc0 + e
-    const uint32_t* gprof = w.arena + (prof ? pc0 : 0);
+    // pool: (when staged) packed (top, bottom) of texel e at st[e] and its
+    // chart at emap[e]; offsets Y of configuration j at the top of the pool
+    int32_t* Yb = pool + PW - ysum;
+    int16_t* emap = reinterpret_cast<int16_t*>(pool + E);
     const bool staged = prof && E <= stage_cap && ysum + E + (E + 1) / 2 <= PW;
     // grown top (tp) / bottom (bt) of texel e and its chart t in the row
     auto texel = [&](int e, int& t, int32_t& tp, int32_t& bt) {
@@ -615,60 +615,44 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       if (lane == 0) s_lr[q][2] = f;
     }
     __syncthreads();
-    // ---- 5. correction, one wavefront per compacted configuration
+    // ---- 5. correction and score, one wavefront per configuration.  The
+    // score is the largest offset + grown bottom over the configuration's
+    // texels.  A chart's largest bottom is its height h: every proxy bounds
+    // the chart from outside, so at a column holding the chart's lowest
+    // point all of them reach h, and the local AABBs never pass it; grown,
+    // the largest is h + p.  So a configuration scores max over its charts
+    // of offset + h + p, one term per chart, taken by the wavefront that
+    // corrected it; the other wavefronts take the frontline's maximum over
+    // the knee region meanwhile.
     const int my_cnt = wv == 0 ? c_cnt[0] : wv == 1 ? c_cnt[1] : wv == 2 ? c_cnt[2] : c_cnt[3];
     const int my_hc = wv < ncfg && (wv == 0 ? c_hc[0] : wv == 1 ? c_hc[1] : wv == 2 ? c_hc[2] : c_hc[3]);
     int32_t* my_y = Yb + (wv == 0 ? yofs[0] : wv == 1 ? yofs[1] : wv == 2 ? yofs[2] : yofs[3]);
-    if (!lrover) {
-      if (my_hc) correct_offsets(my_y, my_cnt, flv + rs, s_lr, lrn);
-    } else {
+    if (lrover)
       correct_many_pairs<PACK_NT>(Xon, Xoff, cand, rs, lrpre, s_red, s_lr, my_y, my_cnt, my_hc,
                                   flv, prof, w.arena + (prof ? sbase : 0), prowv, hdv, kcb,
                                   P.stride, ch, K, k, p);
+    if (wv < 4) {
+      if (!lrover && my_hc) correct_offsets(my_y, my_cnt, flv + rs, s_lr, lrn);
+      int32_t m = -BIG;
+      if (wv < ncfg)
+        for (int t = lane; t < my_cnt; t += WAVE) {
+          const int64_t Hq = r0 + t < nwin ? s_H[r0 + t] : Hs[rs + t];
+          m = max(m, my_y[t] + (int32_t)((k * Hq + QS - 1) >> 14) + p);
+        }
+      m = wave_max(m);
+      if (lane == 0) s_red[wv] = m;
+    } else if (ncfg == 4) {
+      int32_t f = -BIG;
+      for (int x = c_R0[2] + tid - 4 * WAVE; x < c_R1[2]; x += PACK_NT - 4 * WAVE) f = max(f, F[x]);
+      f = wave_max(f);
+      if (lane == 0) s_red[wv] = f;
     }
-    // the scores read the corrected offsets (without compaction nothing was
-    // corrected and the barrier after the push suffices)
-    if (anyhc) __syncthreads();
-    // ---- 6. scores: the largest offset + grown bottom over a
-    // configuration's texels.  A chart's largest bottom is its height h:
-    // every proxy bounds the chart from outside, so at a column holding the
-    // chart's lowest point all of them reach h, and the local AABBs never
-    // pass it; grown, the largest is h + p.  So a configuration scores
-    // max over its charts of offset + h + p, one term per chart.
-    int32_t M[4] = {-BIG, -BIG, -BIG, -BIG};
-    {
-      const int cmax = max(max(c_cnt[0], c_cnt[1]), max(c_cnt[2], c_cnt[3]));
-      for (int t = tid; t < cmax; t += PACK_NT) {
-        const int64_t Hq = r0 + t < nwin ? s_H[r0 + t] : Hs[rs + t];
-        const int32_t hdt = (int32_t)((k * Hq + QS - 1) >> 14) + p;
+    __syncthreads();
+    int32_t M[4], fr = -BIG;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (t < c_cnt[j]) M[j] = max(M[j], Yb[yofs[j] + t] + hdt);
-      }
-    }
-    int32_t fr = -BIG;
+    for (int j = 0; j < 4; ++j) M[j] = uni(s_red[j]);
     if (ncfg == 4)
-      for (int x = c_R0[2] + tid; x < c_R1[2]; x += PACK_NT) fr = max(fr, F[x]);
-    {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) M[j] = wave_max(M[j]);
-      fr = wave_max(fr);
-      if (lane == 0) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) s_red[wv * 6 + j] = M[j];
-        s_red[wv * 6 + 4] = fr;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int32_t m = -BIG;
-        for (int q = 0; q < PACK_WAVES; ++q) m = max(m, s_red[q * 6 + j]);
-        M[j] = uni(m);
-      }
-      int32_t f2 = -BIG;
-      for (int q = 0; q < PACK_WAVES; ++q) f2 = max(f2, s_red[q * 6 + 4]);
-      fr = uni(f2);
-    }
+      for (int q = 4; q < PACK_WAVES; ++q) fr = max(fr, uni(s_red[q]));
     // ---- 7. selection: lower maximal height wins, ties left to right; the
     // knee fold only if strictly lower over the whole frontline
     int win = 0, knee_used = 0;
