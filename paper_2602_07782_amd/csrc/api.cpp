@@ -522,8 +522,9 @@ int pack_single(const tabi_charts* charts, int32_t n, int32_t atlas_w, int32_t a
     return TABI_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Job j;
-  int rc = make_job(j, make_params(1, n, code, padding, 64, 0, n > 0 ? n : 1, atlas_w + padding),
-                    st);
+  Params P = make_params(1, n, code, padding, 64, 0, n > 0 ? n : 1, atlas_w + padding);
+  P.loops = cloop != nullptr;
+  int rc = make_job(j, P, st);
   if (!rc) rc = single_front(j, charts, atlas_w, atlas_h, st, cloop);
   if (!rc) {
     const int all[1] = {64};

@@ -385,21 +385,34 @@ __global__ __launch_bounds__(256) void k_place(Params P, Work w) {
   w.perm[pos] = c - lo;
 }
 
-// candidate scales: the charts' total area and the largest chart must fit.
+// candidate scales: the charts' total area and the largest chart must fit,
+// and so must the charts' grown footprints.  At scale s = k/64 the texels a
+// chart is packed as (its proxies' per-texel bounds) cover the chart, so at
+// least a s^2 of them (a its area), and reach every column and row of its
+// w x h texel box; the gutter growth adds at least p texels to every row of
+// them (past the rightmost) and then p to every column of the result (w + p
+// columns), so the grown footprint covers at least a s^2 + p (w + h) + p^2
+// texels.  A packing's grown footprints are disjoint inside the
+// (W+p) x (H+p) grown atlas, hence, with w, h >= s W, s H (W, H the box in
+// Q8) and everything times 2^29:
+//   sum(area2) k^2 + 2^15 p k sum(W + H) + 2^29 n p^2 <= 2^29 (W+p)(H+p).
+// (For charts of several loops only the area and p^2 terms are used.)  Both
+// bounds are exact prunes: they never remove a scale whose packing succeeds.
 // Per-thread sums stay below 2^57 (area2 < 2^47, at most 1,024 charts per
 // thread) and a wavefront's below 2^63; the block total is taken in 128 bits.
 // Lane k - 1 of wavefront 0 tests scale k; k_top is the largest passing one.
 constexpr int ORDER_MAX = 4096;  // largest batch whose atlases are reordered for packing
 __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
-  __shared__ uint64_t s_sum[4], s_before[4];
+  __shared__ uint64_t s_sum[4], s_before[4], s_wh[4];
   __shared__ int32_t s_maxw[4], s_bad[4];
   const int a = blockIdx.x, lane = lane_id(), wv = threadIdx.x / WAVE;
   const AtlasDesc d = w.desc[a];
-  uint64_t sum = 0;
+  uint64_t sum = 0, wh = 0;  // wh: sum of W + H (Q8), below 2^42
   int32_t mw = 0, bad = 0;  // bad: a degenerate chart (its record is marked invalid)
   for (int t = threadIdx.x; t < d.n; t += blockDim.x) {
     const Chart& ch = w.srecs[d.c0 + t];
     sum += (uint64_t)ch.area2;
+    wh += (uint64_t)ch.W + (uint64_t)ch.H;
     mw = max(mw, ch.W);
     bad |= !ch.valid;
   }
@@ -413,18 +426,31 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
       before += (nb > d.n || (nb == d.n && b < a)) ? 1 : 0;
     }
   sum = wave_sum_u64(sum);
+  wh = wave_sum_u64(wh);
   before = wave_sum_u64(before);
   mw = wave_max(mw);
   bad = wave_max(bad);
-  if (lane == 0) { s_sum[wv] = sum; s_maxw[wv] = mw; s_bad[wv] = bad; s_before[wv] = before; }
+  if (lane == 0) {
+    s_sum[wv] = sum;
+    s_wh[wv] = wh;
+    s_maxw[wv] = mw;
+    s_bad[wv] = bad;
+    s_before[wv] = before;
+  }
   __syncthreads();
   if (wv != 0) return;
   if (lane == 0)
     w.aord[P.count <= ORDER_MAX ? (int)(s_before[0] + s_before[1] + s_before[2] + s_before[3]) : a] = a;
   unsigned __int128 S = 0;
+  uint64_t SWH = 0;
   int32_t MW = 0;
   bad = 0;
-  for (int q = 0; q < 4; ++q) { S += s_sum[q]; MW = max(MW, s_maxw[q]); bad |= s_bad[q]; }
+  for (int q = 0; q < 4; ++q) {
+    S += s_sum[q];
+    SWH += s_wh[q];
+    MW = max(MW, s_maxw[q]);
+    bad |= s_bad[q];
+  }
   int ktop = 0;
   if (bad) {
     ktop = -1;
@@ -436,7 +462,14 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
     const int k = lane + 1;
     const bool area_ok = S * (unsigned)(k * k) <= cap;
     const bool fit = cdiv64((int64_t)k * MW, QS) <= d.Wa && cdiv64((int64_t)k * MH, QS) <= d.Ha;
-    const uint64_t pass = ballot64(area_ok && fit);
+    const uint64_t pp = (uint64_t)P.p;
+    const unsigned __int128 grown =
+        S * (unsigned)(k * k) +
+        (P.loops ? 0 : ((unsigned __int128)(pp * (uint64_t)k) * SWH << 15)) +
+        ((unsigned __int128)((uint64_t)d.n * pp * pp) << 29);
+    const unsigned __int128 gcap =
+        ((unsigned __int128)((uint64_t)(d.Wa + P.p) * (uint64_t)(d.Ha + P.p))) << 29;
+    const uint64_t pass = ballot64(area_ok && fit && grown <= gcap);
     ktop = pass ? 64 - __builtin_clzll(pass) : 0;
     // the hybrid tail packs its charts at a smaller scale, so neither bound
     // holds for the scale of the rows before it: every scale is a candidate

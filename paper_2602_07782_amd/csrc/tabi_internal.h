@@ -38,6 +38,7 @@ struct Params {
   int32_t variant;     // 0 full, 1 tight-only (static rows), 2 balanced-only (boxes)
   int32_t hybrid;      // 1: after the t_opt switch the charts are folded by prefix sums at a
                        // scale of their own (Sec. 4.4); single atlas, every scale a slot
+  int32_t loops;       // 1: charts of several boundary loops (not necessarily connected)
 };
 
 // Work-space views (device pointers).
