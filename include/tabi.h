@@ -48,7 +48,9 @@ enum {
   TABI_EINVAL = -1, /* bad argument: null pointer, n < 0 or n > TABI_MAX_CHARTS,
                        atlas side < 1, side + padding > 16384, padding < 0 or
                        padding > TABI_MAX_PADDING,
-                       quality not in {0,1,2}, count < 0, work space too small */
+                       quality not in {0,1,2}, count < 0, work space too small,
+                       or a wide atlas with more charts than the packing
+                       kernel's shared memory holds (see tabi_pack_lds_bytes) */
   TABI_ENOMEM = -2, /* the device memory pool could not supply the work space */
   TABI_EHIP = -3,   /* a HIP runtime call failed (launch, memory); see tabi_last_hip_error */
   TABI_ETOOBIG = -4, /* tabi_pack_noalloc: the input needs more work space than its
@@ -461,7 +463,14 @@ int tabi_timing_read(double* ms, int32_t* launches, int32_t nstages);
 void tabi_timing_reset(void);
 
 /* Device shared memory (bytes) the packing kernel will use for an atlas of
- * width atlas_w + padding and n charts (host only; no device work). */
+ * width atlas_w + padding and n charts (host only; no device work).  The
+ * row state of one scale lives in the packing kernel's shared memory: the
+ * frontline (4 (W + p) bytes) and the offsets of a row's charts
+ * (24 min(n, W + p) + 8 bytes at least).  A call whose atlas needs more than
+ * the device's shared memory per workgroup less the kernel's own use (about
+ * 148 KB on MI355X) returns TABI_EINVAL: this limits atlases of width 8192
+ * to about 4,800 charts and of width 16384 to about 3,400; atlases up to
+ * 4096 wide take any chart count up to TABI_MAX_CHARTS. */
 int64_t tabi_pack_lds_bytes(int32_t n, int32_t atlas_w, int32_t padding);
 
 #ifdef __cplusplus

@@ -305,3 +305,21 @@ def test_shutdown_releases_pool_and_library_stays_usable(tabi, orc):
     assert before[2] == after[2]
     assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
     assert_pack_equal(tabi, orc, inp, "after shutdown")
+
+
+def test_shared_memory_limit_of_wide_atlases(tabi):
+    """An 8192-wide atlas holds the row state of about 4,800 charts in the
+    packing kernel's shared memory: 4,000 charts pack, 6,000 are refused with
+    TABI_EINVAL (the documented limit), and the reported shared-memory size
+    crosses the device limit in between."""
+    import ctypes
+    L = tabi.lib()
+    L.tabi_pack_lds_bytes.restype = ctypes.c_int64
+    L.tabi_pack_lds_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    assert L.tabi_pack_lds_bytes(4000, 8192, 2) <= 160 * 1024 < L.tabi_pack_lds_bytes(6000, 8192, 2)
+    ok = synth.rect_input(4000, 256 * 20, 256 * 30, 8192, 8192, 2)
+    xy, ori, sc = tabi.pack(ok.xy, ok.offsets, 8192, 8192, 2, 2, device="cuda:0")
+    assert float(sc.cpu().numpy()[0]) > 0
+    big = synth.rect_input(6000, 256 * 20, 256 * 30, 8192, 8192, 2)
+    with pytest.raises(tabi.TabiError):
+        tabi.pack(big.xy, big.offsets, 8192, 8192, 2, 2, device="cuda:0")
