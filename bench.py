@@ -486,12 +486,20 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quality", type=int, default=2)
+    ap.add_argument("--workload", default="mixed2k",
+                    choices=["mixed2k", "stars64", "lightmap20k", "tss4k"],
+                    help="the single-pack workload of the main leg (the default is the "
+                         "headline configuration; the others are for per-workload profiles)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other single-pack configurations")
+    ap.add_argument("--phase-clock", action="store_true",
+                    help="with the diagnostic library (python -m paper_2602_07782_amd.build "
+                         "--phase-clock): the fold-and-push kernel's per-row phase split of the "
+                         "main leg's workload, per scale slot, then exit")
     ap.add_argument("--traffic-pass", action="store_true",
                     help="for hardware-counter runs: a few packs, then one plain 256 MiB device "
                          "copy whose byte count calibrates FETCH_SIZE / WRITE_SIZE")
@@ -508,9 +516,16 @@ def main():
     import paper_2602_07782_amd as tabi
     from paper_2602_07782_amd import synth
 
+    if args.phase_clock:
+        from paper_2602_07782_amd import build as tabi_build
+        if not os.path.exists(tabi_build.OUT_PHASE):
+            print(f"{tabi_build.OUT_PHASE} is missing: build it with "
+                  "`python -m paper_2602_07782_amd.build --phase-clock`", file=sys.stderr)
+            sys.exit(2)
+        tabi.LIB_PATH = tabi_build.OUT_PHASE
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    base = synth.make_input("mixed2k", 0)
+    base = synth.make_tss(0) if args.workload == "tss4k" else synth.make_input(args.workload, 0)
     inp = synth.AtlasInput(base.xy, base.offsets, base.atlas_w, base.atlas_h, base.padding,
                            args.quality)
     n = inp.n
@@ -528,6 +543,24 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.phase_clock:
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ph = tabi.debug_phase_clock(64)
+        names = ["commit_and_loop_head", "knee_update", "fold", "configs_and_staging", "push",
+                 "correction_and_score", "selection_and_knee_detection"]
+        slots = {}
+        for r in ph:
+            if r[8] <= 0:
+                continue
+            slots[int(r[9])] = {"rows": int(r[8]), "feasible": int(r[10]),
+                                "us": {nm: round(int(r[q]) / 100.0, 1) for q, nm in enumerate(names)},
+                                "us_total": round(int(r[:7].sum()) / 100.0, 1)}
+        print(json.dumps({"phase_clock": True, "workload": args.workload, "packs": args.steps,
+                          "clock": "constant 100 MHz device clock, sums over the last pack's rows",
+                          "slots": slots}))
+        return
     if args.traffic_pass:
         for _ in range(args.steps):
             step()
@@ -577,6 +610,7 @@ def main():
     avg_pack_ms = pack_ms / max(pack_launches, 1)
     achieved = pack_bytes / (avg_pack_ms * 1e-3) / 1e9 if avg_pack_ms > 0 else 0.0
 
+    mix = " (70% stars 8-64 verts, 30% L/U)" if args.workload == "mixed2k" else ""
     result = {
         "metric": METRIC,
         "value": round(p50, 4),
@@ -590,7 +624,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"mixed2k: {n} charts (70% stars 8-64 verts, 30% L/U) into "
+        "config": {"workload": f"{args.workload}: {n} charts{mix} into "
                                f"{inp.atlas_w}x{inp.atlas_h}, padding {inp.padding}, quality "
                                f"{inp.quality}, plain single pack",
                    "charts": n, "atlas": [inp.atlas_w, inp.atlas_h], "padding": inp.padding,
@@ -603,7 +637,7 @@ def main():
         "stage_ms_per_pack": {s: round(v[0] / max(v[1], 1), 4) for s, v in stages.items()},
         "roofline": {"bound": "hbm", "kernel": "k_pack (fold-and-push, all candidate scales)",
                      "achieved": round(achieved, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 6), "traffic": recorded_traffic(),
+                     "frac": round(achieved / PEAK_HBM_GBS, 6), "traffic": recorded_traffic() if args.workload == "mixed2k" else None,
                      "bytes_per_unit": round(unit_bytes, 2), "units_per_launch": units,
                      "bytes_per_launch": pack_bytes,
                      "avg_launch_ms": round(avg_pack_ms, 4), "dominant_stage": dom},
@@ -612,7 +646,7 @@ def main():
         ms, reps, (oxy, oori, osc, ok) = cpu_baseline(inp, args.cpu_seconds)
         result["cpu_baseline"] = {"value": round(ms, 2), "unit": "ms per atlas pack",
                                   "cores": 1, "kind": "oracle",
-                                  "sample": f"{reps} full packs of the same 2,000-chart input"}
+                                  "sample": f"{reps} full packs of the same {n}-chart input"}
         result["bitexact_vs_oracle"] = bool(osc == gsc and np.array_equal(oxy, gxy) and
                                             np.array_equal(oori, gor))
     result["host_cores"] = host_cores()

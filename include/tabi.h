@@ -426,6 +426,19 @@ int tabi_debug_feasible(const tabi_charts* charts, int32_t n, int32_t atlas_w, i
                         uint8_t* out_orient, int32_t* feasible, int32_t* rows,
                         tabi_stream_t stream);
 
+/* Diagnostic: with the library built with TABI_PHASE_CLOCK defined
+ * (`python -m paper_2602_07782_amd.build --phase-clock`, a separate
+ * libtabi_hip_phase.so), the fold-and-push kernel of a single pack sums per
+ * scale slot the device's constant 100 MHz clock between the phases of its
+ * rows as wavefront 0 sees them.  Writes 11 values per slot for `slots`
+ * slots (at most 64) to host memory `out`: [0] the previous row's commit and
+ * the loop head, [1] knee update, [2] fold, [3] configurations and staging,
+ * [4] push, [5] correction and score, [6] selection and knee detection,
+ * [7] 0, [8] rows, [9] the slot's scale k, [10] its outcome (1 feasible, 0
+ * not), from the last pack.  Returns the number of slots written;
+ * TABI_EINVAL when the library was built without the clock. */
+int tabi_debug_phase_clock(int64_t* out, int32_t slots);
+
 /* Test knob: cap the per-row LDS staging of texel bounds at `entries`
  * (texel columns; -1 restores the default).  Rows that do not fit read the
  * stored bounds from device memory; results are identical either way. */

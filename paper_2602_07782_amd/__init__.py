@@ -63,7 +63,7 @@ EXPORTS = ["tabi_pack", "tabi_pack_loops", "tabi_pack_prerotate", "tabi_pack_hyb
            "tabi_pack_many", "tabi_pack_many_ws", "tabi_submit_with", "tabi_pack_many_workspace_bytes",
            "tabi_record_bytes", "tabi_prep_records", "tabi_splice_records",
            "tabi_pack_many_records", "tabi_debug_order", "tabi_debug_pairs",
-           "tabi_debug_feasible", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
+           "tabi_debug_feasible", "tabi_debug_phase_clock", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
            "tabi_timing_enable", "tabi_timing_read", "tabi_timing_reset",
            "tabi_debug_set_stage_cap", "tabi_debug_set_profile_cap", "tabi_tune_many",
            "tabi_many_shape", "tabi_many_shape_count", "tabi_debug_set_many_shape",
@@ -428,6 +428,19 @@ def debug_feasible(xy, offsets, atlas_w, atlas_h, padding, quality, k, stream=No
                                      int(padding), int(quality), int(k), _ptr(out_xy),
                                      _ptr(out_or), _ptr(feas), _ptr(rows), _stream(stream)))
     return out_xy, out_or, feas, rows
+
+
+def debug_phase_clock(slots=64):
+    """tabi_debug_phase_clock: per-slot phase clock sums of the last single
+    pack (the diagnostic library only).  Returns an int64 array [slots, 11]."""
+    import numpy as np
+    out = np.zeros((slots, 11), np.int64)
+    L = lib()
+    L.tabi_debug_phase_clock.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    n = L.tabi_debug_phase_clock(out.ctypes.data_as(ctypes.c_void_p), int(slots))
+    if n < 0:
+        _check(n)
+    return out[:n]
 
 
 def timing_enable(on=True):

@@ -978,6 +978,13 @@ const char* tabi_strerror(int code) {
 
 const char* tabi_last_hip_error(void) { return g_last_hip; }
 
+int tabi_debug_phase_clock(int64_t* out, int32_t slots) {
+  if (!out || slots < 1) return TABI_EINVAL;
+  const int r = read_phase_clock(out, slots);
+  if (r == -2) return TABI_EINVAL;
+  return r < 0 ? hip_fail(hipGetLastError()) : r;
+}
+
 int tabi_debug_set_stage_cap(int32_t entries) {
   g_stage_cap = entries;
   return TABI_OK;

@@ -38,6 +38,28 @@ namespace tabi {
 // memory at once; a row with more walks them in chunks of this size
 constexpr int LRCAP = 256;
 constexpr int FWIN = 1024;  // charts per row whose fold data is staged in LDS
+
+// Diagnostic build (TABI_PHASE_CLOCK): the fold-and-push kernel of a single
+// pack sums, per scale slot, the constant 100 MHz clock between the phases
+// of its rows as wavefront 0 sees them (loop head, knee update, fold,
+// configurations and staging, push, correction and score, selection,
+// commit), with the slot's rows, scale and outcome; read back by
+// tabi_debug_phase_clock.  The product build has none of it.
+#ifdef TABI_PHASE_CLOCK
+__device__ long long g_phase_clock[64][11];
+#define PHASE_CLOCK_DECL long long ph_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, ph_t = wall_clock64();
+#define PHASE_CLOCK(q)                       \
+  do {                                       \
+    const long long ph_n = wall_clock64();   \
+    ph_acc[q] += ph_n - ph_t;                \
+    ph_t = ph_n;                             \
+  } while (0)
+#else
+#define PHASE_CLOCK_DECL
+#define PHASE_CLOCK(q) \
+  do {                 \
+  } while (0)
+#endif
 enum { DIR_LR = 0, DIR_RL = 1 };
 
 // A value every thread of the workgroup holds alike (read from shared
@@ -388,6 +410,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   // loads for the next row never read past it
   const int32_t colend = pc0 >= 0 ? sbase + prowv[0] : 0;
 
+  PHASE_CLOCK_DECL
   for (;;) {
     __syncthreads();
     {  // the previous row's knee detection (-1: none ran)
@@ -408,6 +431,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       __syncthreads();
     }
     const int r0 = rs - wb;  // window index of the row's first chart
+    PHASE_CLOCK(0);
     // ---- 1. knee location update (Alg. 4)
     if (kn) {
       const int probe = kdir == DIR_LR ? kr : kl - 1;
@@ -428,6 +452,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
         }
       }
     }
+    PHASE_CLOCK(1);
     // ---- t_opt switch (Sec. 4.4), on the first chart's texel height
     const int64_t h0 = cdiv64((int64_t)k * uni(s_H[r0]), QS);
     if (!tail && !kn && 100 * h0 < (int64_t)topt * Ha) {
@@ -475,6 +500,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       }
     }
     __syncthreads();
+    PHASE_CLOCK(2);
     const int cfo = uni(s_cnt[0]), cfn = uni(s_cnt[1]), cko = uni(s_cnt[2]), ckn = uni(s_cnt[3]);
     if (cfn == 0) { feasible = 0; break; }  // a chart wider than the atlas
     if (cfn > RC) { feasible = -2; break; }   // cannot happen: advances are >= 1
@@ -560,6 +586,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     // more pairs than the shared list holds, or pairs whose rows are not
     // stored: none is swept with the push, the correction walks them out of
     // line (both rare)
+    PHASE_CLOCK(3);
     const bool lrover = uni(s_lrover) != 0 || (!prof && uni(s_lrn) > 0);
     const int lrn = lrover ? 0 : uni(s_lrn);
     // ---- 4. push every configuration against the committed frontline; the
@@ -615,6 +642,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       if (lane == 0) s_lr[q][2] = f;
     }
     __syncthreads();
+    PHASE_CLOCK(4);
     // ---- 5. correction and score, one wavefront per configuration.  The
     // score is the largest offset + grown bottom over the configuration's
     // texels.  A chart's largest bottom is its height h: every proxy bounds
@@ -648,6 +676,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       if (lane == 0) s_red[wv] = f;
     }
     __syncthreads();
+    PHASE_CLOCK(5);
     int32_t M[4], fr = -BIG;
 #pragma unroll
     for (int j = 0; j < 4; ++j) M[j] = uni(s_red[j]);
@@ -728,12 +757,21 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
         }
       }
     }
+    PHASE_CLOCK(6);
     fmax = max(fmax, w_score);
     ++rows;
     if (w_score > Hd) { feasible = 0; break; }
     rs += w_cnt;
     if (pc0 >= 0) pc0 += Ew;
   }
+#ifdef TABI_PHASE_CLOCK
+    if (!HYB && tid == 0 && P.count == 1 && s < 64) {
+      for (int q = 0; q < 8; ++q) g_phase_clock[s][q] = ph_acc[q];
+      g_phase_clock[s][8] = rows;
+      g_phase_clock[s][9] = k;
+      g_phase_clock[s][10] = feasible;
+    }
+#endif
   } while (false);
   if (tid == 0) {
     w.feas[a * P.B + s] = feasible;
@@ -1220,6 +1258,21 @@ __global__ __launch_bounds__(256) void k_select_hybrid(Params P, Work w, int32_t
   }
   if (blockIdx.x == 0 && tid == 0)
     out_scale[0] = d.bad ? -1.0f : (d.n == 0 ? 1.0f : (best >= 0 ? (float)k / 64.0f : 0.0f));
+}
+
+int read_phase_clock(int64_t* out, int slots) {
+#ifdef TABI_PHASE_CLOCK
+  static long long buf[64][11];
+  if (hipMemcpyFromSymbol(buf, HIP_SYMBOL(g_phase_clock), sizeof(buf)) != hipSuccess) return -1;
+  const int m = slots < 64 ? slots : 64;
+  for (int i = 0; i < m; ++i)
+    for (int q = 0; q < 11; ++q) out[i * 11 + q] = buf[i][q];
+  return m;
+#else
+  (void)out;
+  (void)slots;
+  return -2;
+#endif
 }
 
 hipError_t launch_tail(const Params& P, const Work& w, int lds_bytes, int RC, int PW,

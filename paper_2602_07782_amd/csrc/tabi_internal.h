@@ -145,6 +145,10 @@ hipError_t launch_select_hybrid(const Params& P, const Work& w, int32_t* out_xy,
 hipError_t launch_scatter(const Params& P, const Work& w, int32_t* out_xy, uint8_t* out_orient,
                           int32_t* feasible, int32_t* rows, hipStream_t st);
 
+// the diagnostic build's per-slot phase clock of the last single pack
+// (slots x 11 values); -2 when the library was built without it
+int read_phase_clock(int64_t* out, int slots);
+
 hipError_t pack_set_max_lds(int bytes);
 int pack_static_lds();
 
