@@ -555,6 +555,8 @@ def main():
             if r[8] <= 0:
                 continue
             slots[int(r[9])] = {"rows": int(r[8]), "feasible": int(r[10]),
+                                "rows_pairs_overflow": int(r[7]) >> 32,
+                                "pairs_listed": int(r[7]) & 0xffffffff,
                                 "us": {nm: round(int(r[q]) / 100.0, 1) for q, nm in enumerate(names)},
                                 "us_total": round(int(r[:7].sum()) / 100.0, 1)}
         print(json.dumps({"phase_clock": True, "workload": args.workload, "packs": args.steps,

@@ -434,8 +434,10 @@ int tabi_debug_feasible(const tabi_charts* charts, int32_t n, int32_t atlas_w, i
  * slots (at most 64) to host memory `out`: [0] the previous row's commit and
  * the loop head, [1] knee update, [2] fold, [3] configurations and staging,
  * [4] push, [5] correction and score, [6] selection and knee detection,
- * [7] 0, [8] rows, [9] the slot's scale k, [10] its outcome (1 feasible, 0
- * not), from the last pack.  Returns the number of slots written;
+ * [7] rows whose pairs that share columns without being neighbours overflow
+ * the shared list, times 2^32, plus the number of such pairs (the list's
+ * count, capped at its overflow), [8] rows, [9] the slot's scale k, [10] its
+ * outcome (1 feasible, 0 not), from the last pack.  Returns the number of slots written;
  * TABI_EINVAL when the library was built without the clock. */
 int tabi_debug_phase_clock(int64_t* out, int32_t slots);
 

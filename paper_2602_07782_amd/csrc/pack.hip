@@ -54,7 +54,10 @@ __device__ long long g_phase_clock[64][11];
     ph_acc[q] += ph_n - ph_t;                \
     ph_t = ph_n;                             \
   } while (0)
+// rows whose non-neighbour pairs overflow the shared list (x 2^32) + pairs
+#define PHASE_PAIRS(over, pairs) (ph_acc[7] += ((long long)(over) << 32) + (long long)(pairs))
 #else
+#define PHASE_PAIRS(over, pairs) ((void)0)
 #define PHASE_CLOCK_DECL
 #define PHASE_CLOCK(q) \
   do {                 \
@@ -346,10 +349,12 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   __shared__ uint32_t s_touch;   // keeps the next row's cache warm-up loads (never read)
   __shared__ int32_t s_lrn, s_lrover;
   __shared__ int32_t s_lr[LRCAP][3];
-  // window of chart data read by the fold and the knee test, charts
-  // [wb, wb + nwin): grown width, compacting distance to the next chart,
-  // unscaled height; it slides when fewer than FWIN / 2 charts remain ahead
+  // window of chart data read by the fold, the knee test and the chain
+  // scans, charts [wb, wb + nwin): grown width, compacting distance to the
+  // next chart, unscaled height, interlock flags with the previous chart; it
+  // slides when fewer than FWIN / 2 charts remain ahead
   __shared__ int32_t s_wd[FWIN], s_cdn[FWIN], s_H[FWIN];
+  __shared__ uint8_t s_fl[FWIN];  // interlock flags of (c-1, c), read by the chain scans
 
   if (round_idle(w, round)) return;
   const int s = blockIdx.x, a = w.aord[blockIdx.y];
@@ -427,6 +432,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
         s_wd[t] = wdv[c];
         s_cdn[t] = c + 1 < n ? cdv[c + 1] : 0;
         s_H[t] = Hs[c];
+        s_fl[t] = flv[c];
       }
       __syncthreads();
     }
@@ -589,6 +595,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     PHASE_CLOCK(3);
     const bool lrover = uni(s_lrover) != 0 || (!prof && uni(s_lrn) > 0);
     const int lrn = lrover ? 0 : uni(s_lrn);
+    PHASE_PAIRS(lrover, uni(s_lrn));
     // ---- 4. push every configuration against the committed frontline; the
     // last wavefronts (at most a quarter) sweep the non-neighbour pairs at
     // the same time
@@ -660,7 +667,10 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
                                   flv, prof, w.arena + (prof ? sbase : 0), prowv, hdv, kcb,
                                   P.stride, ch, K, k, p);
     if (wv < 4) {
-      if (!lrover && my_hc) correct_offsets(my_y, my_cnt, flv + rs, s_lr, lrn);
+      // the chain's flags from the window when the row lies inside it (a
+      // long row's scans then wait on no global load)
+      if (!lrover && my_hc)
+        correct_offsets(my_y, my_cnt, r0 + my_cnt <= nwin ? s_fl + r0 : flv + rs, s_lr, lrn);
       int32_t m = -BIG;
       if (wv < ncfg)
         for (int t = lane; t < my_cnt; t += WAVE) {
