@@ -38,6 +38,9 @@ namespace tabi {
 // memory at once; a row with more walks them in chunks of this size
 constexpr int LRCAP = 256;
 constexpr int FWIN = 1024;  // charts per row whose fold data is staged in LDS
+// single-configuration rows of at least this many charts are corrected by the
+// whole workgroup
+constexpr int LONG_ROW = 192;
 
 // Diagnostic build (TABI_PHASE_CLOCK): the fold-and-push kernel of a single
 // pack sums, per scale slot, the constant 100 MHz clock between the phases
@@ -145,6 +148,58 @@ __device__ void correct_offsets(int32_t* y, int cnt, const uint8_t* fl, const in
   do {
     chain_scans(y, cnt, fl);
   } while (apply_pairs(y, cnt, lr, lrn));
+}
+
+// chain_scans by the whole workgroup, for a long row of a single
+// configuration: 64 charts per wavefront, each wavefront's segmented scan
+// continued by the carry of the wavefronts before it (a wavefront that holds
+// a chain head passes on its last value, one without passes on the larger of
+// the carry and its last value), the same results as one wavefront walking
+// the chunks in order.  red: 2 * PACK_NT / WAVE ints.
+template <int PACK_NT>
+__device__ void chain_scans_block(int32_t* y, int cnt, const uint8_t* fl, int32_t* red) {
+  constexpr int WAVES = PACK_NT / WAVE;
+  const int lane = lane_id(), wv = threadIdx.x / WAVE;
+#pragma unroll
+  for (int dir = 0; dir < 2; ++dir) {  // forward: y[t] >= y[t-1] where bit0 of fl[t];
+    int32_t carry = -BIG;             // backward: y[t] >= y[t+1] where bit1 of fl[t+1]
+    for (int b0 = 0; b0 < cnt; b0 += PACK_NT) {
+      const int r = b0 + (int)threadIdx.x, t = dir == 0 ? r : cnt - 1 - r;
+      int32_t v = r < cnt ? y[t] : -BIG;
+      const bool head = !(r >= 1 && r < cnt && (dir == 0 ? (fl[t] & 1) : (fl[t + 1] & 2)));
+      const int32_t key = wave_incl_max(head ? lane : -1);
+      v = seg_scan_max(v, key, seg_keys(key));
+      const bool hh = ballot64(head) != 0;
+      const int32_t last = lane63(v);
+      if (lane == 0) {
+        red[2 * wv] = hh;
+        red[2 * wv + 1] = last;
+      }
+      __syncthreads();
+      int32_t c = carry, cn = carry;
+      for (int q = 0; q < WAVES; ++q) {
+        const int32_t h = red[2 * q], l = red[2 * q + 1];
+        if (q == wv) c = cn;
+        cn = h ? l : max(cn, l);
+      }
+      if (key < 0) v = max(v, c);
+      if (r < cnt) y[t] = v;
+      carry = cn;
+      __syncthreads();  // red is written again by the next chunk or pass
+    }
+  }
+}
+// correct_offsets by the whole workgroup (same results): the block's chain
+// scans, wavefront 0 applying the non-neighbour pairs, until no offset moves
+template <int PACK_NT>
+__device__ __attribute__((noinline)) void correct_offsets_block(int32_t* y, int cnt, const uint8_t* fl,
+                                      const int32_t (*lr)[3], int lrn, int32_t* red) {
+  for (;;) {
+    chain_scans_block<PACK_NT>(y, cnt, fl, red);
+    int moved = 0;
+    if (threadIdx.x < WAVE) moved = apply_pairs(y, cnt, lr, lrn);
+    if (!__syncthreads_or(moved)) break;
+  }
 }
 
 // Non-neighbour partners of each candidate A of a compacted row: the charts
@@ -666,32 +721,49 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       correct_many_pairs<PACK_NT>(Xon, Xoff, cand, rs, lrpre, s_red, s_lr, my_y, my_cnt, my_hc,
                                   flv, prof, w.arena + (prof ? sbase : 0), prowv, hdv, kcb,
                                   P.stride, ch, K, k, p);
-    if (wv < 4) {
-      // the chain's flags from the window when the row lies inside it (a
-      // long row's scans then wait on no global load)
-      if (!lrover && my_hc)
-        correct_offsets(my_y, my_cnt, r0 + my_cnt <= nwin ? s_fl + r0 : flv + rs, s_lr, lrn);
+    // the chain's flags from the window when the row lies inside it (a long
+    // row's scans then wait on no global load)
+    const uint8_t* chain_fl = r0 + c_cnt[0] <= nwin ? s_fl + r0 : flv + rs;
+    int32_t M[4] = {-BIG, -BIG, -BIG, -BIG}, fr = -BIG;
+    if (ncfg == 1 && c_cnt[0] >= LONG_ROW) {
+      // a long single-configuration row: the whole workgroup corrects and
+      // scores it
+      if (!lrover && c_hc[0]) correct_offsets_block<PACK_NT>(Yb, c_cnt[0], chain_fl, s_lr, lrn, s_red);
       int32_t m = -BIG;
-      if (wv < ncfg)
-        for (int t = lane; t < my_cnt; t += WAVE) {
-          const int64_t Hq = r0 + t < nwin ? s_H[r0 + t] : Hs[rs + t];
-          m = max(m, my_y[t] + (int32_t)((k * Hq + QS - 1) >> 14) + p);
-        }
+      for (int t = tid; t < c_cnt[0]; t += PACK_NT) {
+        const int64_t Hq = r0 + t < nwin ? s_H[r0 + t] : Hs[rs + t];
+        m = max(m, Yb[t] + (int32_t)((k * Hq + QS - 1) >> 14) + p);
+      }
       m = wave_max(m);
-      if (lane == 0) s_red[wv] = m;
-    } else if (ncfg == 4) {
-      int32_t f = -BIG;
-      for (int x = c_R0[2] + tid - 4 * WAVE; x < c_R1[2]; x += PACK_NT - 4 * WAVE) f = max(f, F[x]);
-      f = wave_max(f);
-      if (lane == 0) s_red[wv] = f;
-    }
-    __syncthreads();
-    PHASE_CLOCK(5);
-    int32_t M[4], fr = -BIG;
+      if (lane == 0) s_red[2 * PACK_WAVES + wv] = m;
+      __syncthreads();
+      for (int q = 0; q < PACK_WAVES; ++q) M[0] = max(M[0], uni(s_red[2 * PACK_WAVES + q]));
+      PHASE_CLOCK(5);
+    } else {
+      if (wv < 4) {
+        if (!lrover && my_hc)
+          correct_offsets(my_y, my_cnt, r0 + my_cnt <= nwin ? s_fl + r0 : flv + rs, s_lr, lrn);
+        int32_t m = -BIG;
+        if (wv < ncfg)
+          for (int t = lane; t < my_cnt; t += WAVE) {
+            const int64_t Hq = r0 + t < nwin ? s_H[r0 + t] : Hs[rs + t];
+            m = max(m, my_y[t] + (int32_t)((k * Hq + QS - 1) >> 14) + p);
+          }
+        m = wave_max(m);
+        if (lane == 0) s_red[wv] = m;
+      } else if (ncfg == 4) {
+        int32_t f = -BIG;
+        for (int x = c_R0[2] + tid - 4 * WAVE; x < c_R1[2]; x += PACK_NT - 4 * WAVE) f = max(f, F[x]);
+        f = wave_max(f);
+        if (lane == 0) s_red[wv] = f;
+      }
+      __syncthreads();
+      PHASE_CLOCK(5);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) M[j] = uni(s_red[j]);
-    if (ncfg == 4)
-      for (int q = 4; q < PACK_WAVES; ++q) fr = max(fr, uni(s_red[q]));
+      for (int j = 0; j < 4; ++j) M[j] = uni(s_red[j]);
+      if (ncfg == 4)
+        for (int q = 4; q < PACK_WAVES; ++q) fr = max(fr, uni(s_red[q]));
+    }
     // ---- 7. selection: lower maximal height wins, ties left to right; the
     // knee fold only if strictly lower over the whole frontline
     int win = 0, knee_used = 0;
