@@ -866,12 +866,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   // one.  Batches launch the selection instead: a device-wide fence in each
   // of their many workgroups costs more than the launch it saves.
   if (P.fixed_k > 0 || P.count != 1 || HYB) return;
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_cnt[0] = atomicAdd(&w.cnt[a], 1) == P.Br - 1;
-  __syncthreads();
-  if (!s_cnt[0]) return;
-  __threadfence();
+  if (!last_to_finish(&w.cnt[a], P.Br, s_cnt)) return;
   if (tid == 0) w.cnt[a] = 0;
   select_atlas(P, w, round, last_round, a, out_xy, out_orient, out_scale, s_red);
 }

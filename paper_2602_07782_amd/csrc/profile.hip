@@ -289,12 +289,7 @@ __global__ __launch_bounds__(LAY_NT) void k_layout(Params P, Work w, int round) 
   // (no separate launch); the counter is zeroed again for the packing
   // kernel, which counts with it next.  Batches launch the placement.
   if (P.count != 1) return;
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = atomicAdd(&w.cnt[0], 1) == P.Br - 1;
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+  if (!last_to_finish(&w.cnt[0], P.Br, &s_last)) return;
   if (tid == 0) w.cnt[0] = 0;
   alloc_segments<LAY_NT>(P, w, &s_tot[0][0]);
 }

@@ -71,6 +71,27 @@ struct KView {
   const KSide* sd;   // [0] top, [1] bottom, [2] left, [3] right
   const KRect* rc;   // 2K rectangles
 };
+// Last-workgroup pattern: the calling workgroup (all its threads) makes its
+// global writes visible device-wide and counts itself in *counter; returns
+// true, uniformly, in the workgroup that counts last of `total`, after it has
+// acquired the others' writes.  Every wavefront waits for its own stores to
+// reach the L2, then one thread releases them all with its increment (a
+// single write-back of the XCD's L2, where a fence in every thread would
+// write back and invalidate once per wavefront); only the last workgroup
+// acquires.  flag: one int of shared memory.
+__device__ inline bool last_to_finish(int32_t* counter, int total, int32_t* flag) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const bool last =
+        __hip_atomic_fetch_add(counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == total - 1;
+    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *flag = last;
+  }
+  __syncthreads();
+  return *flag != 0;
+}
+
 __device__ inline KView kview(const unsigned char* base, int K) {
   KView v;
   v.hd = reinterpret_cast<const KHead*>(base);
