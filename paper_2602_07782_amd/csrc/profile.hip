@@ -379,8 +379,10 @@ template <int KT, bool GEN>
 __device__ bool profile_block(const Params& P, const Work& w, int bx, int s) {
   constexpr int NJ = PROF_CH + 1;  // entry 0: the chart before the block's first
   constexpr int K = KT;
-  // 16-byte words of a chart record and of its set-up record (P.stride)
-  constexpr int nch = (int)(sizeof(Chart) / 16);
+  // 16-byte words of a chart record copied (the lean form reads only the
+  // leading ones: extents, bits, OBB direction and bounds) and of its set-up
+  // record (P.stride)
+  constexpr int nch = GEN ? (int)(sizeof(Chart) / 16) : (int)((offsetof(Chart, ylo) + 15) / 16);
   constexpr int nkc = (int)((sizeof(KHead) + 4 * sizeof(KSide) + 2 * KT * sizeof(KRect)) / 16);
   __shared__ ChartCache cache[NJ];
   __shared__ SweepRec sw[NJ];
