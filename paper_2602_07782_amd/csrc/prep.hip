@@ -369,7 +369,19 @@ __global__ __launch_bounds__(256) void k_rank(Params P, Work w) {
     __syncthreads();
     if (act) {
       const int j0 = max(lo - base, 0), j1 = min(hi - base, 256);
-      for (int j = j0; j < j1; ++j) rank += tile[j] < key;
+      if (j0 == 0 && j1 == 256) {  // a whole tile of this atlas: reads kept in flight
+        int r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+#pragma unroll 8
+        for (int j = 0; j < 256; j += 4) {
+          r0 += tile[j] < key;
+          r1 += tile[j + 1] < key;
+          r2 += tile[j + 2] < key;
+          r3 += tile[j + 3] < key;
+        }
+        rank += r0 + r1 + r2 + r3;
+      } else {
+        for (int j = j0; j < j1; ++j) rank += tile[j] < key;
+      }
     }
     __syncthreads();
   }
