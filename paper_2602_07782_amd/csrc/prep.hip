@@ -344,15 +344,63 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
 // those charts belong to through LDS; every thread counts the smaller keys
 // of its own atlas and adds the count to its rank (integer atomics: the sum
 // does not depend on the order).  Ranks start at zero (written with the keys).
+// Atlases of up to RANK_DIRECT charts compare every key of a tile; larger
+// ones first sort each aligned key tile by (atlas, key) (k_tile_sort) and
+// then count with two binary searches per tile.
+constexpr int RANK_DIRECT = 2048;
+
+// Bitonic sort of key tile blockIdx.x, ascending by (atlas, key), into
+// skey / satl; entries past N are the largest.
+__global__ __launch_bounds__(256) void k_tile_sort(Params P, Work w) {
+  __shared__ uint64_t sk[256];
+  __shared__ int32_t sa[256];
+  const int t = threadIdx.x, i = blockIdx.x * 256 + t;
+  sk[t] = i < P.N ? w.keys[i] : ~0ull;
+  sa[t] = i < P.N ? w.chart_atlas[i] : INT32_MAX;
+  __syncthreads();
+  for (int k = 2; k <= 256; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int u = t ^ j;
+      if (u > t) {
+        const int32_t a0 = sa[t], a1 = sa[u];
+        const uint64_t k0 = sk[t], k1 = sk[u];
+        const bool gt = a0 > a1 || (a0 == a1 && k0 > k1);
+        if (gt == ((t & k) == 0)) {  // ascending where bit k of t is clear
+          sa[t] = a1; sa[u] = a0;
+          sk[t] = k1; sk[u] = k0;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  w.skey[i] = sk[t];
+  w.satl[i] = sa[t];
+}
+
+// entries of a sorted tile before (a, k)
+__device__ inline int tile_lower_bound(const int32_t* ta, const uint64_t* tk, int32_t a,
+                                       uint64_t k) {
+  int pos = 0;
+#pragma unroll
+  for (int step = 256; step > 0; step >>= 1) {
+    const int x = pos + step - 1;
+    if (x < 256 && (ta[x] < a || (ta[x] == a && tk[x] < k))) pos += step;
+  }
+  return pos;
+}
+
+template <bool SORTED>
 __global__ __launch_bounds__(256) void k_rank(Params P, Work w) {
   __shared__ uint64_t tile[256];
+  __shared__ int32_t tatl[256];
   __shared__ int s_lo, s_hi;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = c < P.N;
-  int lo = 0, hi = 0;
+  int lo = 0, hi = 0, a = 0;
   uint64_t key = 0;
   if (act) {
-    const AtlasDesc d = w.desc[w.chart_atlas[c]];
+    a = w.chart_atlas[c];
+    const AtlasDesc d = w.desc[a];
     lo = d.c0;
     hi = d.c0 + d.n;
     key = w.keys[c];
@@ -363,27 +411,38 @@ __global__ __launch_bounds__(256) void k_rank(Params P, Work w) {
   __syncthreads();
   const int blo = s_lo, bhi = s_hi;
   int rank = 0;
-  for (int base = blo + (int)blockIdx.y * 256; base < bhi; base += (int)gridDim.y * 256) {
-    const int i = base + threadIdx.x;
-    tile[threadIdx.x] = i < bhi ? w.keys[i] : ~0ull;
-    __syncthreads();
-    if (act) {
-      const int j0 = max(lo - base, 0), j1 = min(hi - base, 256);
-      if (j0 == 0 && j1 == 256) {  // a whole tile of this atlas: reads kept in flight
-        int r0 = 0, r1 = 0, r2 = 0, r3 = 0;
-#pragma unroll 8
-        for (int j = 0; j < 256; j += 4) {
-          r0 += tile[j] < key;
-          r1 += tile[j + 1] < key;
-          r2 += tile[j + 2] < key;
-          r3 += tile[j + 3] < key;
-        }
-        rank += r0 + r1 + r2 + r3;
-      } else {
-        for (int j = j0; j < j1; ++j) rank += tile[j] < key;
-      }
+  if (SORTED) {
+    // the aligned sorted tiles that overlap the block's atlases
+    for (int t = blo / 256 + (int)blockIdx.y; t * 256 < bhi; t += (int)gridDim.y) {
+      tile[threadIdx.x] = w.skey[t * 256 + threadIdx.x];
+      tatl[threadIdx.x] = w.satl[t * 256 + threadIdx.x];
+      __syncthreads();
+      if (act) rank += tile_lower_bound(tatl, tile, a, key) - tile_lower_bound(tatl, tile, a, 0);
+      __syncthreads();
     }
-    __syncthreads();
+  } else {
+    for (int base = blo + (int)blockIdx.y * 256; base < bhi; base += (int)gridDim.y * 256) {
+      const int i = base + threadIdx.x;
+      tile[threadIdx.x] = i < bhi ? w.keys[i] : ~0ull;
+      __syncthreads();
+      if (act) {
+        const int j0 = max(lo - base, 0), j1 = min(hi - base, 256);
+        if (j0 == 0 && j1 == 256) {  // a whole tile of this atlas: reads kept in flight
+          int r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+#pragma unroll 8
+          for (int j = 0; j < 256; j += 4) {
+            r0 += tile[j] < key;
+            r1 += tile[j + 1] < key;
+            r2 += tile[j + 2] < key;
+            r3 += tile[j + 3] < key;
+          }
+          rank += r0 + r1 + r2 + r3;
+        } else {
+          for (int j = j0; j < j1; ++j) rank += tile[j] < key;
+        }
+      }
+      __syncthreads();
+    }
   }
   if (act && rank) atomicAdd(&w.rank[c], rank);
 }
@@ -683,9 +742,14 @@ hipError_t launch_sort(const Params& P, const Work& w, hipStream_t st) {
     // charts when every atlas holds at most nmax (longer spans are still
     // covered, by the loop inside k_rank)
     const int tiles = (P.N + 255) / 256;
-    int ny = (2 * P.nmax + 255) / 256 + 1;
+    int ny = (2 * P.nmax + 255) / 256 + 2;
     if (ny > tiles) ny = tiles;
-    hipLaunchKernelGGL(k_rank, dim3(tiles, ny), dim3(256), 0, st, P, w);
+    if (P.nmax > RANK_DIRECT) {
+      hipLaunchKernelGGL(k_tile_sort, dim3(tiles), dim3(256), 0, st, P, w);
+      hipLaunchKernelGGL(k_rank<true>, dim3(tiles, ny), dim3(256), 0, st, P, w);
+    } else {
+      hipLaunchKernelGGL(k_rank<false>, dim3(tiles, ny), dim3(256), 0, st, P, w);
+    }
     hipLaunchKernelGGL(k_place, dim3(tiles), dim3(256), 0, st, P, w);
   }
   hipLaunchKernelGGL(k_plan, dim3(P.count), dim3(256), 0, st, P, w);

@@ -50,6 +50,8 @@ struct Work {
   Chart* recs;          // [N] by input position
   Chart* srecs;         // [N] by sorted position (per atlas)
   uint64_t* keys;       // [N]
+  uint64_t* skey;       // [ceil(N / 256) * 256] key tiles of 256, each sorted by (atlas, key)
+  int32_t* satl;        //   and the atlas of each entry (padding: largest atlas and key)
   int32_t* rank;        // [N] position of the chart within its atlas's sorted order
   int32_t* perm;        // [N] sorted position -> local input index
   int32_t* chart_atlas; // [N]
