@@ -135,7 +135,7 @@ struct StageScope {  // brackets one stage's launches with a pair of events
 
 // ---- work space -------------------------------------------------------------
 struct Layout {
-  size_t o_recs, o_srecs, o_keys, o_skey, o_satl, o_rank, o_perm, o_ca, o_desc, o_kc, o_cd, o_fl, o_xs, o_ys, o_mir,
+  size_t o_recs, o_srecs, o_keys, o_pl, o_skey, o_satl, o_rank, o_perm, o_ca, o_desc, o_kc, o_cd, o_fl, o_xs, o_ys, o_mir,
       o_feas, o_rows, o_wdv, o_hdv, o_kslot, o_pcol, o_prow, o_lrpre, o_Hs, o_segneed, o_segbase, o_cnt, o_gq, o_gq_cnt, o_live, o_aord,
       o_tailF, o_tail_t0, o_tail_kt, o_tail_obj, o_arena,
       total;
@@ -171,6 +171,7 @@ Layout layout(const Params& P) {
   L.o_recs = take(n1 * sizeof(Chart));
   L.o_srecs = take(n1 * sizeof(Chart));
   L.o_keys = take(n1 * 8);
+  L.o_pl = take(n1 * 16);
   const size_t nt = (n1 + 255) / 256 * 256;  // whole key tiles
   L.o_skey = take(nt * 8);
   L.o_satl = take(nt * 4);
@@ -216,6 +217,7 @@ Work carve(void* base, const Layout& L) {
   W.recs = reinterpret_cast<Chart*>(b + L.o_recs);
   W.srecs = reinterpret_cast<Chart*>(b + L.o_srecs);
   W.keys = reinterpret_cast<uint64_t*>(b + L.o_keys);
+  W.pl = reinterpret_cast<int4*>(b + L.o_pl);
   W.skey = reinterpret_cast<uint64_t*>(b + L.o_skey);
   W.satl = reinterpret_cast<int32_t*>(b + L.o_satl);
   W.rank = reinterpret_cast<int32_t*>(b + L.o_rank);

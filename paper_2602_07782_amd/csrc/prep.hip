@@ -188,6 +188,7 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
       out->src = local;
       w.keys[c] = ((uint64_t)0x7fffff << 41) | ((uint64_t)0x7fffff << 18) | (uint64_t)local;
       if (w.rank) w.rank[c] = 0;
+      if (w.pl) w.pl[c] = make_int4(0, 0, 0, -1);
     }
     return;
   }
@@ -335,6 +336,7 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
     // ascending key = height descending, width descending, input index
     w.keys[c] = ((uint64_t)(0x7fffff - H) << 41) | ((uint64_t)(0x7fffff - W) << 18) | (uint64_t)local;
     if (w.rank) w.rank[c] = 0;
+    if (w.pl) w.pl[c] = make_int4((int32_t)(uint32_t)area2, (int32_t)((uint64_t)area2 >> 32), W, H);
   }
 }
 
@@ -475,17 +477,21 @@ __global__ __launch_bounds__(256) void k_place(Params P, Work w) {
 constexpr int ORDER_MAX = 4096;  // largest batch whose atlases are reordered for packing
 __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
   __shared__ uint64_t s_sum[4], s_before[4], s_wh[4];
-  __shared__ int32_t s_maxw[4], s_bad[4];
+  __shared__ int32_t s_maxw[4], s_maxh[4], s_bad[4];
   const int a = blockIdx.x, lane = lane_id(), wv = threadIdx.x / WAVE;
   const AtlasDesc d = w.desc[a];
   uint64_t sum = 0, wh = 0;  // wh: sum of W + H (Q8), below 2^42
-  int32_t mw = 0, bad = 0;  // bad: a degenerate chart (its record is marked invalid)
+  int32_t mw = 0, mh = 0, bad = 0;  // bad: a degenerate chart
   for (int t = threadIdx.x; t < d.n; t += blockDim.x) {
-    const Chart& ch = w.srecs[d.c0 + t];
-    sum += (uint64_t)ch.area2;
-    wh += (uint64_t)ch.W + (uint64_t)ch.H;
-    mw = max(mw, ch.W);
-    bad |= !ch.valid;
+    const int4 q = w.pl[d.c0 + t];  // the atlas's charts in input order (the sums do not care)
+    if (q.w < 0) {
+      bad = 1;
+    } else {
+      sum += ((uint64_t)(uint32_t)q.y << 32) | (uint32_t)q.x;
+      wh += (uint64_t)q.z + (uint64_t)q.w;
+      mw = max(mw, q.z);
+      mh = max(mh, q.w);
+    }
   }
   // the packing kernel takes the atlases with more charts first (their
   // searches take longest, so they should not start last), ties by index;
@@ -500,11 +506,13 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
   wh = wave_sum_u64(wh);
   before = wave_sum_u64(before);
   mw = wave_max(mw);
+  mh = wave_max(mh);
   bad = wave_max(bad);
   if (lane == 0) {
     s_sum[wv] = sum;
     s_wh[wv] = wh;
     s_maxw[wv] = mw;
+    s_maxh[wv] = mh;
     s_bad[wv] = bad;
     s_before[wv] = before;
   }
@@ -514,12 +522,13 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
     w.aord[P.count <= ORDER_MAX ? (int)(s_before[0] + s_before[1] + s_before[2] + s_before[3]) : a] = a;
   unsigned __int128 S = 0;
   uint64_t SWH = 0;
-  int32_t MW = 0;
+  int32_t MW = 0, MH = 0;
   bad = 0;
   for (int q = 0; q < 4; ++q) {
     S += s_sum[q];
     SWH += s_wh[q];
     MW = max(MW, s_maxw[q]);
+    MH = max(MH, s_maxh[q]);
     bad |= s_bad[q];
   }
   int ktop = 0;
@@ -528,7 +537,6 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
   } else if (d.n == 0) {
     ktop = 64;
   } else {
-    const int32_t MH = w.srecs[d.c0].H;  // tallest chart comes first
     const unsigned __int128 cap = ((unsigned __int128)1 << 29) * (unsigned)d.Wa * (unsigned)d.Ha;
     const int k = lane + 1;
     const bool area_ok = S * (unsigned)(k * k) <= cap;
@@ -626,8 +634,10 @@ __global__ __launch_bounds__(256) void k_from_records(Params P, Work w, const Ch
   w.rank[c] = 0;
   if (ch.valid) {
     w.keys[c] = ((uint64_t)(0x7fffff - ch.H) << 41) | ((uint64_t)(0x7fffff - ch.W) << 18) | local;
+    w.pl[c] = make_int4((int32_t)(uint32_t)ch.area2, (int32_t)((uint64_t)ch.area2 >> 32), ch.W, ch.H);
   } else {
     w.keys[c] = ((uint64_t)0x7fffff << 41) | ((uint64_t)0x7fffff << 18) | local;
+    w.pl[c] = make_int4(0, 0, 0, -1);
   }
 }
 

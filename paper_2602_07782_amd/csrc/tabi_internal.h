@@ -50,6 +50,8 @@ struct Work {
   Chart* recs;          // [N] by input position
   Chart* srecs;         // [N] by sorted position (per atlas)
   uint64_t* keys;       // [N]
+  int4* pl;             // [N] by input position, read by the scale plan: twice the area
+                        // (low, high word), W, H; H = -1 marks a degenerate chart
   uint64_t* skey;       // [ceil(N / 256) * 256] key tiles of 256, each sorted by (atlas, key)
   int32_t* satl;        //   and the atlas of each entry (padding: largest atlas and key)
   int32_t* rank;        // [N] position of the chart within its atlas's sorted order
