@@ -349,7 +349,7 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
 // Atlases of up to RANK_DIRECT charts compare every key of a tile; larger
 // ones first sort each aligned key tile by (atlas, key) (k_tile_sort) and
 // then count with two binary searches per tile.
-constexpr int RANK_DIRECT = 2048;
+constexpr int RANK_DIRECT = 256;
 
 // Bitonic sort of key tile blockIdx.x, ascending by (atlas, key), into
 // skey / satl; entries past N are the largest.
@@ -475,13 +475,17 @@ __global__ __launch_bounds__(256) void k_place(Params P, Work w) {
 // thread) and a wavefront's below 2^63; the block total is taken in 128 bits.
 // Lane k - 1 of wavefront 0 tests scale k; k_top is the largest passing one.
 constexpr int ORDER_MAX = 4096;  // largest batch whose atlases are reordered for packing
-__global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
-  __shared__ uint64_t s_sum[4], s_before[4], s_wh[4];
-  __shared__ int32_t s_maxw[4], s_maxh[4], s_bad[4];
+// PLAN_NT threads per atlas: 256 up to 1,024 charts, 1024 above
+template <int PLAN_NT>
+__global__ __launch_bounds__(PLAN_NT) void k_plan(Params P, Work w) {
+  constexpr int PW = PLAN_NT / WAVE;
+  __shared__ uint64_t s_sum[PW], s_before[PW], s_wh[PW];
+  __shared__ int32_t s_maxw[PW], s_maxh[PW], s_bad[PW];
   const int a = blockIdx.x, lane = lane_id(), wv = threadIdx.x / WAVE;
   const AtlasDesc d = w.desc[a];
   uint64_t sum = 0, wh = 0;  // wh: sum of W + H (Q8), below 2^42
   int32_t mw = 0, mh = 0, bad = 0;  // bad: a degenerate chart
+#pragma unroll 4
   for (int t = threadIdx.x; t < d.n; t += blockDim.x) {
     const int4 q = w.pl[d.c0 + t];  // the atlas's charts in input order (the sums do not care)
     if (q.w < 0) {
@@ -518,13 +522,16 @@ __global__ __launch_bounds__(256) void k_plan(Params P, Work w) {
   }
   __syncthreads();
   if (wv != 0) return;
-  if (lane == 0)
-    w.aord[P.count <= ORDER_MAX ? (int)(s_before[0] + s_before[1] + s_before[2] + s_before[3]) : a] = a;
+  if (lane == 0) {
+    uint64_t pos = 0;
+    for (int q = 0; q < PW; ++q) pos += s_before[q];
+    w.aord[P.count <= ORDER_MAX ? (int)pos : a] = a;
+  }
   unsigned __int128 S = 0;
   uint64_t SWH = 0;
   int32_t MW = 0, MH = 0;
   bad = 0;
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < PW; ++q) {
     S += s_sum[q];
     SWH += s_wh[q];
     MW = max(MW, s_maxw[q]);
@@ -762,7 +769,10 @@ hipError_t launch_sort(const Params& P, const Work& w, hipStream_t st) {
     }
     hipLaunchKernelGGL(k_place, dim3(tiles), dim3(256), 0, st, P, w);
   }
-  hipLaunchKernelGGL(k_plan, dim3(P.count), dim3(256), 0, st, P, w);
+  if (P.nmax <= 1024)
+    hipLaunchKernelGGL(k_plan<256>, dim3(P.count), dim3(256), 0, st, P, w);
+  else
+    hipLaunchKernelGGL(k_plan<1024>, dim3(P.count), dim3(1024), 0, st, P, w);
   return hipGetLastError();
 }
 

@@ -572,9 +572,9 @@ __global__ __launch_bounds__(PROF_NT) void k_profile_general(Params P, Work w, i
 hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_t st) {
   if (P.N <= 0) return hipSuccess;
   // with no arena the placement still runs: it marks every segment unstored
-  // 256 threads per (atlas, slot) for a single atlas; 1024 for batches, whose
-  // largest atlases hold thousands of charts
-  if (P.count == 1)
+  // 256 threads per (atlas, slot) for a single atlas of up to 4,096 charts;
+  // 1024 for larger ones and for batches, whose largest atlases hold thousands
+  if (P.count == 1 && P.nmax <= 4096)
     hipLaunchKernelGGL(k_layout<256>, dim3(P.count, P.Br), dim3(256), 0, st, P, w, round);
   else
     hipLaunchKernelGGL(k_layout<1024>, dim3(P.count, P.Br), dim3(1024), 0, st, P, w, round);
@@ -592,7 +592,8 @@ hipError_t launch_profiles(const Params& P, const Work& w, int round, hipStream_
     else hipLaunchKernelGGL((k_profile<1, true>), grid, dim3(PROF_NT), 0, st, P, w, round);
     return hipGetLastError();
   }
-  const dim3 ggrid(PROF_GEN_BLOCKS);
+  // (a single atlas's queue is usually empty: a smaller grid leaves sooner)
+  const dim3 ggrid(P.count == 1 ? PROF_GEN_BLOCKS / 4 : PROF_GEN_BLOCKS);
   if (P.K == 10) {
     hipLaunchKernelGGL((k_profile<10, false>), grid, dim3(PROF_NT), 0, st, P, w, round);
     hipLaunchKernelGGL(k_profile_general<10>, ggrid, dim3(PROF_NT), 0, st, P, w, round, nbx);
