@@ -353,9 +353,18 @@ constexpr int RANK_DIRECT = 256;
 
 // Bitonic sort of key tile blockIdx.x, ascending by (atlas, key), into
 // skey / satl; entries past N are the largest.
-__global__ __launch_bounds__(256) void k_tile_sort(Params P, Work w) {
+// A single atlas's scale plan does not depend on the sort: it runs as the
+// extra workgroup plan_block (-1: none) of the sort's first launch.
+template <int PLAN_NT>
+__device__ void plan_atlas(const Params& P, const Work& w, int a);
+
+__global__ __launch_bounds__(256) void k_tile_sort(Params P, Work w, int plan_block) {
   __shared__ uint64_t sk[256];
   __shared__ int32_t sa[256];
+  if ((int)blockIdx.x == plan_block) {
+    plan_atlas<256>(P, w, 0);
+    return;
+  }
   const int t = threadIdx.x, i = blockIdx.x * 256 + t;
   sk[t] = i < P.N ? w.keys[i] : ~0ull;
   sa[t] = i < P.N ? w.chart_atlas[i] : INT32_MAX;
@@ -392,10 +401,14 @@ __device__ inline int tile_lower_bound(const int32_t* ta, const uint64_t* tk, in
 }
 
 template <bool SORTED>
-__global__ __launch_bounds__(256) void k_rank(Params P, Work w) {
+__global__ __launch_bounds__(256) void k_rank(Params P, Work w, int plan_block) {
   __shared__ uint64_t tile[256];
   __shared__ int32_t tatl[256];
   __shared__ int s_lo, s_hi;
+  if ((int)blockIdx.x == plan_block) {  // the extra column: one workgroup plans
+    if (blockIdx.y == 0) plan_atlas<256>(P, w, 0);
+    return;
+  }
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = c < P.N;
   int lo = 0, hi = 0, a = 0;
@@ -477,11 +490,11 @@ __global__ __launch_bounds__(256) void k_place(Params P, Work w) {
 constexpr int ORDER_MAX = 4096;  // largest batch whose atlases are reordered for packing
 // PLAN_NT threads per atlas: 256 up to 1,024 charts, 1024 above
 template <int PLAN_NT>
-__global__ __launch_bounds__(PLAN_NT) void k_plan(Params P, Work w) {
+__device__ void plan_atlas(const Params& P, const Work& w, int a) {
   constexpr int PW = PLAN_NT / WAVE;
   __shared__ uint64_t s_sum[PW], s_before[PW], s_wh[PW];
   __shared__ int32_t s_maxw[PW], s_maxh[PW], s_bad[PW];
-  const int a = blockIdx.x, lane = lane_id(), wv = threadIdx.x / WAVE;
+  const int lane = lane_id(), wv = threadIdx.x / WAVE;
   const AtlasDesc d = w.desc[a];
   uint64_t sum = 0, wh = 0;  // wh: sum of W + H (Q8), below 2^42
   int32_t mw = 0, mh = 0, bad = 0;  // bad: a degenerate chart
@@ -569,6 +582,10 @@ __global__ __launch_bounds__(PLAN_NT) void k_plan(Params P, Work w) {
       w.tail_obj[2 * P.B + 1] = (uint64_t)(S >> 64);
     }
   }
+}
+template <int PLAN_NT>
+__global__ __launch_bounds__(PLAN_NT) void k_plan(Params P, Work w) {
+  plan_atlas<PLAN_NT>(P, w, blockIdx.x);
 }
 
 // one thread per (slot, chart)
@@ -761,13 +778,17 @@ hipError_t launch_sort(const Params& P, const Work& w, hipStream_t st) {
     const int tiles = (P.N + 255) / 256;
     int ny = (2 * P.nmax + 255) / 256 + 2;
     if (ny > tiles) ny = tiles;
+    // a single atlas of up to 4,096 charts plans in an extra workgroup of the
+    // first sort launch (larger ones plan with 1024 threads afterwards)
+    const int pb = P.count == 1 && P.nmax <= 4096 ? tiles : -1;
     if (P.nmax > RANK_DIRECT) {
-      hipLaunchKernelGGL(k_tile_sort, dim3(tiles), dim3(256), 0, st, P, w);
-      hipLaunchKernelGGL(k_rank<true>, dim3(tiles, ny), dim3(256), 0, st, P, w);
+      hipLaunchKernelGGL(k_tile_sort, dim3(tiles + (pb >= 0)), dim3(256), 0, st, P, w, pb);
+      hipLaunchKernelGGL(k_rank<true>, dim3(tiles, ny), dim3(256), 0, st, P, w, -1);
     } else {
-      hipLaunchKernelGGL(k_rank<false>, dim3(tiles, ny), dim3(256), 0, st, P, w);
+      hipLaunchKernelGGL(k_rank<false>, dim3(tiles + (pb >= 0), ny), dim3(256), 0, st, P, w, pb);
     }
     hipLaunchKernelGGL(k_place, dim3(tiles), dim3(256), 0, st, P, w);
+    if (pb >= 0) return hipGetLastError();
   }
   if (P.nmax <= 1024)
     hipLaunchKernelGGL(k_plan<256>, dim3(P.count), dim3(256), 0, st, P, w);
