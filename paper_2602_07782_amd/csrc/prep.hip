@@ -350,6 +350,7 @@ __global__ __launch_bounds__(256) void k_prep(Params P, Work w, const int32_t* _
 // ones first sort each aligned key tile by (atlas, key) (k_tile_sort) and
 // then count with two binary searches per tile.
 constexpr int RANK_DIRECT = 256;
+constexpr int RANK_SCATTER = 256;
 
 // Bitonic sort of key tile blockIdx.x, ascending by (atlas, key), into
 // skey / satl; entries past N are the largest.
@@ -400,7 +401,11 @@ __device__ inline int tile_lower_bound(const int32_t* ta, const uint64_t* tk, in
   return pos;
 }
 
-template <bool SORTED>
+// SCATTER: one workgroup per chart tile walks every key tile of its atlases,
+// so each rank is complete in its thread, which writes the chart to its
+// sorted position (no k_place launch); otherwise ranks accumulate by atomics
+// over the grid's y dimension and k_place scatters.
+template <bool SORTED, bool SCATTER>
 __global__ __launch_bounds__(256) void k_rank(Params P, Work w, int plan_block) {
   __shared__ uint64_t tile[256];
   __shared__ int32_t tatl[256];
@@ -459,7 +464,15 @@ __global__ __launch_bounds__(256) void k_rank(Params P, Work w, int plan_block) 
       __syncthreads();
     }
   }
-  if (act && rank) atomicAdd(&w.rank[c], rank);
+  if (SCATTER) {
+    if (act) {
+      const int pos = lo + rank;
+      w.srecs[pos] = w.recs[c];
+      w.perm[pos] = c - lo;
+    }
+  } else if (act && rank) {
+    atomicAdd(&w.rank[c], rank);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_place(Params P, Work w) {
@@ -781,13 +794,20 @@ hipError_t launch_sort(const Params& P, const Work& w, hipStream_t st) {
     // a single atlas of up to 4,096 charts plans in an extra workgroup of the
     // first sort launch (larger ones plan with 1024 threads afterwards)
     const int pb = P.count == 1 && P.nmax <= 4096 ? tiles : -1;
+    // atlases of up to RANK_SCATTER charts (one key tile) rank with one
+    // workgroup per chart tile, which also scatters; for larger ones a
+    // workgroup walking every key tile of its atlases costs more than the
+    // separate scatter launch
+    const bool sc = P.nmax <= RANK_SCATTER;
     if (P.nmax > RANK_DIRECT) {
       hipLaunchKernelGGL(k_tile_sort, dim3(tiles + (pb >= 0)), dim3(256), 0, st, P, w, pb);
-      hipLaunchKernelGGL(k_rank<true>, dim3(tiles, ny), dim3(256), 0, st, P, w, -1);
+      if (sc) hipLaunchKernelGGL((k_rank<true, true>), dim3(tiles), dim3(256), 0, st, P, w, -1);
+      else hipLaunchKernelGGL((k_rank<true, false>), dim3(tiles, ny), dim3(256), 0, st, P, w, -1);
     } else {
-      hipLaunchKernelGGL(k_rank<false>, dim3(tiles + (pb >= 0), ny), dim3(256), 0, st, P, w, pb);
+      if (sc) hipLaunchKernelGGL((k_rank<false, true>), dim3(tiles + (pb >= 0)), dim3(256), 0, st, P, w, pb);
+      else hipLaunchKernelGGL((k_rank<false, false>), dim3(tiles + (pb >= 0), ny), dim3(256), 0, st, P, w, pb);
     }
-    hipLaunchKernelGGL(k_place, dim3(tiles), dim3(256), 0, st, P, w);
+    if (!sc) hipLaunchKernelGGL(k_place, dim3(tiles), dim3(256), 0, st, P, w);
     if (pb >= 0) return hipGetLastError();
   }
   if (P.nmax <= 1024)
