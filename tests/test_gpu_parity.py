@@ -96,7 +96,19 @@ def test_order_parity(tabi, orc, seed):
     assert 1 <= int(_np(khi)[0]) <= okhi
 
 
-@pytest.mark.parametrize("name", ["stars64", "mixed2k"])
+@pytest.mark.parametrize("n", [255, 256, 257, 511, 513])
+def test_order_parity_at_key_tile_boundaries(tabi, orc, n):
+    """Up to 256 charts the rank compares keys directly; above, key tiles of
+    256 are sorted first; partial last tiles on either side."""
+    inp = small_input(300 + n, n=n, W=512)
+    perm, khi = tabi.debug_order(inp.xy, inp.offsets, inp.atlas_w, inp.atlas_h, inp.padding,
+                                 inp.quality)
+    operm, okhi = orc.order(inp)
+    assert np.array_equal(_np(perm), operm), n
+    assert 1 <= int(_np(khi)[0]) <= okhi
+
+
+@pytest.mark.parametrize("name", ["stars64", "mixed2k", "lightmap20k"])
 def test_order_parity_workloads(tabi, orc, name):
     inp = synth.make_input(name, 0)
     perm, khi = tabi.debug_order(inp.xy, inp.offsets, inp.atlas_w, inp.atlas_h, inp.padding,
