@@ -431,11 +431,20 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   const int topt = P.topt >= 0 ? P.topt : (n > 10000 ? 1 : 0);
   const size_t slot = (size_t)s * P.N + d.c0;
   // dynamic LDS: frontline F[Wd], fold offsets without / with compaction
-  // Xoff, Xon[RC+1], then a per-row pool of PW words
-  int32_t* F = reinterpret_cast<int32_t*>(smem);
-  int32_t* Xoff = F + Wd;
-  int32_t* Xon = Xoff + (RC + 1);
-  int32_t* pool = Xon + (RC + 1);
+  // Xoff, Xon[RC+1], then a per-row pool of PW words.  A second pair of
+  // offset arrays for rows of up to RA charts sits at the top of the pool,
+  // RA the most for which the rest of the pool still holds four
+  // configurations' offsets: the next row is folded into the other pair
+  // while this row commits (rows of more charts are folded again, into the
+  // first pair, after the opening barrier)
+  int32_t* const F = reinterpret_cast<int32_t*>(smem);
+  int32_t* const X0 = F + Wd;
+  int32_t* const pool = X0 + 2 * (RC + 1);
+  const int RA = min(RC, (PW - 2) / 6);
+  const int PWr = PW - 2 * (RA + 1);  // the pool below the second pair
+  int32_t* const X1 = pool + PWr;
+  int32_t* Xoff = X0;  // this row's offsets: (X0, X0 + RC + 1) or (X1, X1 + RA + 1)
+  int32_t* Xon = X0 + (RC + 1);
   const unsigned char* kcb = w.kc + slot * P.stride;
   const Chart* ch = w.srecs + d.c0;
   const int32_t* cdv = w.cd + slot;
@@ -470,6 +479,67 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
   // loads for the next row never read past it
   const int32_t colend = pc0 >= 0 ? sbase + prowv[0] : 0;
 
+  // ---- folding (Alg. 2), by one wavefront: the row from chart rs_f (window
+  // index r0_f), offsets without / with compaction into xo_b / xn_b; the
+  // counts that fit the full width and, for a knee fold, width kw_f go to
+  // s_cnt, and the row's pair list is cleared
+  auto fold = [&](int rs_f, int r0_f, int32_t* xo_b, int32_t* xn_b, int cap, int kw_f) {
+    int cfo = -1, cfn = -1, cko = -1, ckn = -1;
+    int xo = 0, xn = 0;
+    for (int t0 = 0; cfn < 0; t0 += WAVE) {
+      const int t = t0 + lane, c = rs_f + t;
+      int wd = Wd + 1, cdn = 0;
+      if (r0_f + t < nwin) {
+        wd = s_wd[r0_f + t];
+        cdn = s_cdn[r0_f + t];
+      } else if (c < n) {
+        wd = wdv[c];
+        if (c + 1 < n) cdn = cdv[c + 1];
+      }
+      const int ao = wd, an = wd - cdn;
+      const int io = wave_incl_sum(ao), in = wave_incl_sum(an);
+      const int Xo = xo + io - ao, Xn = xn + in - an;
+      if (t <= cap) { xo_b[t] = Xo; xn_b[t] = Xn; }
+      const uint64_t bfo = ballot64(Xo + wd > Wd), bfn = ballot64(Xn + wd > Wd);
+      const uint64_t bko = ballot64(Xo + wd > kw_f), bkn = ballot64(Xn + wd > kw_f);
+      if (cfo < 0 && bfo) cfo = t0 + __builtin_ctzll(bfo);
+      if (cfn < 0 && bfn) cfn = t0 + __builtin_ctzll(bfn);
+      if (cko < 0 && bko) cko = t0 + __builtin_ctzll(bko);
+      if (ckn < 0 && bkn) ckn = t0 + __builtin_ctzll(bkn);
+      xo += lane63(io);
+      xn += lane63(in);
+    }
+    if (lane == 0) {
+      s_cnt[0] = cfo; s_cnt[1] = cfn; s_cnt[2] = cko; s_cnt[3] = ckn;
+      s_lrn = 0; s_lrover = 0;
+    }
+  };
+  // the knee counts of a row folded ahead, from its offsets: chart t's grown
+  // width is Xoff[t + 1] - Xoff[t] (stored up to the full-width count cfn),
+  // and a knee count never exceeds the full-width one
+  auto knee_counts = [&](int kw_f) {
+    const int cfo = uni(s_cnt[0]), cfn = uni(s_cnt[1]);
+    int cko = -1, ckn = -1;
+    if (cfn >= 1 && cfn <= RC) {
+      for (int t0 = 0; ckn < 0; t0 += WAVE) {
+        const int t = t0 + lane;
+        bool po = t >= cfo, pn = t >= cfn;
+        if (t < cfn) {
+          const int x0 = Xoff[t], wd = Xoff[t + 1] - x0;
+          po = po || x0 + wd > kw_f;
+          pn = Xon[t] + wd > kw_f;
+        }
+        const uint64_t bo = ballot64(po), bn = ballot64(pn);
+        if (cko < 0 && bo) cko = t0 + __builtin_ctzll(bo);
+        if (ckn < 0 && bn) ckn = t0 + __builtin_ctzll(bn);
+      }
+    }
+    if (lane == 0) { s_cnt[2] = cko; s_cnt[3] = ckn; }
+  };
+  // 1: the next row is being folded while this row commits; then, after the
+  // opening barrier, 1 if it fitted the other pair
+  int ahead = 0, pre = 0;
+
   PHASE_CLOCK_DECL
   for (;;) {
     __syncthreads();
@@ -479,6 +549,12 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       if (kf > 0) { kdir = uni(s_knee[1]); kl = uni(s_knee[2]); kr = uni(s_knee[3]); }
     }
     if (rs >= n) break;
+    pre = 0;
+    if (ahead) {  // the row folded ahead: into the other pair if it fitted
+      pre = uni(s_cnt[1]) <= RA;
+      if (pre && Xoff == X0) { Xoff = X1; Xon = X1 + (RA + 1); }
+      else { Xoff = X0; Xon = X0 + (RC + 1); }
+    }
     if (rs - wb > FWIN / 2) {
       wb = rs;
       nwin = min(FWIN, n - wb);
@@ -529,38 +605,13 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     const uint32_t* gprof = w.arena + (prof ? pc0 : 0);
     uint32_t* st = reinterpret_cast<uint32_t*>(pool);
     const int kw = kn ? (kdir == DIR_LR ? Wd - kr : kl) : 0;
-    if (wv == 0) {
-      int cfo = -1, cfn = -1, cko = -1, ckn = -1;
-      int xo = 0, xn = 0;
-      for (int t0 = 0; cfn < 0; t0 += WAVE) {
-        const int t = t0 + lane, c = rs + t;
-        int wd = Wd + 1, cdn = 0;
-        if (r0 + t < nwin) {
-          wd = s_wd[r0 + t];
-          cdn = s_cdn[r0 + t];
-        } else if (c < n) {
-          wd = wdv[c];
-          if (c + 1 < n) cdn = cdv[c + 1];
-        }
-        const int ao = wd, an = wd - cdn;
-        const int io = wave_incl_sum(ao), in = wave_incl_sum(an);
-        const int Xo = xo + io - ao, Xn = xn + in - an;
-        if (t <= RC) { Xoff[t] = Xo; Xon[t] = Xn; }
-        const uint64_t bfo = ballot64(Xo + wd > Wd), bfn = ballot64(Xn + wd > Wd);
-        const uint64_t bko = ballot64(Xo + wd > kw), bkn = ballot64(Xn + wd > kw);
-        if (cfo < 0 && bfo) cfo = t0 + __builtin_ctzll(bfo);
-        if (cfn < 0 && bfn) cfn = t0 + __builtin_ctzll(bfn);
-        if (cko < 0 && bko) cko = t0 + __builtin_ctzll(bko);
-        if (ckn < 0 && bkn) ckn = t0 + __builtin_ctzll(bkn);
-        xo += lane63(io);
-        xn += lane63(in);
-      }
-      if (lane == 0) {
-        s_cnt[0] = cfo; s_cnt[1] = cfn; s_cnt[2] = cko; s_cnt[3] = ckn;
-        s_lrn = 0; s_lrover = 0;
-      }
+    if (!pre) {
+      if (wv == 0) fold(rs, r0, Xoff, Xon, RC, kw);
+      __syncthreads();
+    } else if (kn) {
+      if (wv == 0) knee_counts(kw);
+      __syncthreads();
     }
-    __syncthreads();
     PHASE_CLOCK(2);
     const int cfo = uni(s_cnt[0]), cfn = uni(s_cnt[1]), cko = uni(s_cnt[2]), ckn = uni(s_cnt[3]);
     if (cfn == 0) { feasible = 0; break; }  // a chart wider than the atlas
@@ -596,9 +647,12 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     const int E = uni(Xoff[cand]);  // grown texel columns of the candidates
     // pool: (when staged) packed (top, bottom) of texel e at st[e] and its
     // chart at emap[e]; offsets Y of configuration j at the top of the pool
-    int32_t* Yb = pool + PW - ysum;
+    // (the pool's top holds the other pair while the next row is folded,
+    // which happens for rows of at most RA charts)
+    ahead = cand <= RA;
+    int32_t* Yb = pool + (ahead ? PWr : PW) - ysum;
     int16_t* emap = reinterpret_cast<int16_t*>(pool + E);
-    const bool staged = prof && E <= stage_cap && ysum + E + (E + 1) / 2 <= PW;
+    const bool staged = prof && E <= stage_cap && ysum + E + (E + 1) / 2 <= (ahead ? PWr : PW);
     // grown top (tp) / bottom (bt) of texel e and its chart t in the row
     auto texel = [&](int e, int& t, int32_t& tp, int32_t& bt) {
       if (staged) {
@@ -788,9 +842,17 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
     // read of the frontline in this row (push, knee region maximum) happened
     // before the barrier of the score reduction, and the reduction slots and
     // offsets read since are next written after the loop's opening barrier.
-    // (wavefronts 1.. commit while wavefront 0 runs the knee detection below)
+    // (wavefronts 1.. commit while wavefront 0 runs the knee detection below;
+    // with the second offset pair, wavefront 1 folds the next row into it
+    // instead: its counts and pair list are read only after the next opening
+    // barrier)
+    const int cw = ahead ? 2 : 1;  // the first wavefront that commits
+    if (ahead && wv == 1) {
+      if (Xoff == X0) fold(rs + w_cnt, rs + w_cnt - wb, X1, X1 + (RA + 1), RA, 0);
+      else fold(rs + w_cnt, rs + w_cnt - wb, X0, X0 + (RC + 1), RA, 0);
+    }
     const int Ew = Xoff[w_cnt];
-    for (int e = tid - WAVE; wv > 0 && e < Ew; e += PACK_NT - WAVE) {
+    for (int e = tid - cw * WAVE; wv >= cw && e < Ew; e += PACK_NT - cw * WAVE) {
       int t;
       int32_t tp, bt;
       texel(e, t, tp, bt);
@@ -799,7 +861,7 @@ __global__ __launch_bounds__(PACK_NT) __attribute__((amdgpu_waves_per_eu(4))) vo
       const int col = w_dir == DIR_LR ? w_R0 + X + i : w_R1 - 1 - X - i;
       atomicMax(&F[col], Yw[t] + bt);
     }
-    for (int t = tid - WAVE; wv > 0 && t < w_cnt; t += PACK_NT - WAVE) {
+    for (int t = tid - cw * WAVE; wv >= cw && t < w_cnt; t += PACK_NT - cw * WAVE) {
       const int X = w_hc ? Xon[t] : Xoff[t];
       const int wd = Xoff[t + 1] - Xoff[t];
       xs[rs + t] = w_dir == DIR_LR ? w_R0 + X : w_R1 - X - wd;
