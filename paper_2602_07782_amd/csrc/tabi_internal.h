@@ -158,7 +158,9 @@ int pack_static_lds();
 
 // shared-memory plan of the packing kernel: RC charts per row at most, a
 // per-row pool of PW 32-bit words (offsets of every configuration, then the
-// staged texel bounds and the texel -> chart map when they fit)
+// staged texel bounds and the texel -> chart map when they fit; its top also
+// holds the second set of fold offsets, into which the next row is folded
+// while the current one commits, for rows of at most (PW - 2) / 6 charts)
 struct PackLds {
   int RC, PW, bytes;
 };
