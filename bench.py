@@ -576,7 +576,12 @@ def main():
     _, khi_t = tabi.debug_order(xy, off, inp.atlas_w, inp.atlas_h, inp.padding, inp.quality)
     k_top = int(khi_t.cpu()[0])
 
+    # the timed region brackets only the fold-and-push launch with the
+    # library's HIP events (its duration feeds the roofline): every bracketed
+    # stage adds a pair of event records to each pack, so the full stage split
+    # comes from a separate loop after the timed region
     tabi.timing_reset()
+    tabi.timing_stages(["pack"])
     tabi.timing_enable(True)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -589,7 +594,16 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     tabi.timing_enable(False)
+    pack_timed = tabi.timing_read()["pack"]
+    tabi.timing_reset()
+    tabi.timing_stages(None)
+    tabi.timing_enable(True)
+    for _ in range(min(args.steps, 50)):
+        step()
+    torch.cuda.synchronize()
+    tabi.timing_enable(False)
     stages = tabi.timing_read()
+    tabi.timing_reset()
     per = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     p50, p99 = percentile(per, 50), percentile(per, 99)
     ms_per_step = wall * 1000.0 / args.steps
@@ -608,7 +622,7 @@ def main():
     unit_bytes = pack_bytes / max(units, 1)
     dom = max(stages, key=lambda s: stages[s][0])
     dom_ms, dom_launches = stages[dom]
-    pack_ms, pack_launches = stages["pack"]
+    pack_ms, pack_launches = pack_timed
     avg_pack_ms = pack_ms / max(pack_launches, 1)
     achieved = pack_bytes / (avg_pack_ms * 1e-3) / 1e9 if avg_pack_ms > 0 else 0.0
 

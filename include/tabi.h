@@ -472,8 +472,13 @@ const char* tabi_last_hip_error(void);
  * scale bound, 2 per-scale set-up, 3 per-texel profiles and neighbour pairs,
  * 4 fold-and-push, 5 scale selection.  tabi_timing_read waits for the recorded events and writes the
  * summed milliseconds and the number of bracketed launches per stage since
- * the last reset (arrays of nstages entries, either may be NULL). */
+ * the last reset (arrays of nstages entries, either may be NULL).
+ * tabi_timing_stages selects the stages bracketed while timing is enabled
+ * (bit s for stage s; all six by default): each pair of events adds a few
+ * microseconds to the call, so a caller that times whole calls brackets only
+ * the stages it needs.  TABI_EINVAL for an empty mask or bits past stage 5. */
 int tabi_timing_enable(int on);
+int tabi_timing_stages(uint32_t mask);
 int tabi_timing_read(double* ms, int32_t* launches, int32_t nstages);
 void tabi_timing_reset(void);
 

@@ -64,7 +64,7 @@ EXPORTS = ["tabi_pack", "tabi_pack_loops", "tabi_pack_prerotate", "tabi_pack_hyb
            "tabi_record_bytes", "tabi_prep_records", "tabi_splice_records",
            "tabi_pack_many_records", "tabi_debug_order", "tabi_debug_pairs",
            "tabi_debug_feasible", "tabi_debug_phase_clock", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
-           "tabi_timing_enable", "tabi_timing_read", "tabi_timing_reset",
+           "tabi_timing_enable", "tabi_timing_stages", "tabi_timing_read", "tabi_timing_reset",
            "tabi_debug_set_stage_cap", "tabi_debug_set_profile_cap", "tabi_tune_many",
            "tabi_many_shape", "tabi_many_shape_count", "tabi_debug_set_many_shape",
            "tabi_shutdown", "tabi_ctx_create", "tabi_ctx_destroy", "tabi_submit", "tabi_repack",
@@ -113,6 +113,7 @@ def lib():
         L.tabi_pack_lds_bytes.argtypes = [i32, i32, i32]
         L.tabi_pack_lds_bytes.restype = ctypes.c_int64
         L.tabi_timing_enable.argtypes = [ctypes.c_int]
+        L.tabi_timing_stages.argtypes = [ctypes.c_uint32]
         L.tabi_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int32), i32]
         L.tabi_timing_reset.restype = None
@@ -445,6 +446,12 @@ def debug_phase_clock(slots=64):
 
 def timing_enable(on=True):
     lib().tabi_timing_enable(1 if on else 0)
+
+
+def timing_stages(stages=None):
+    """Bracket only these stages (names of STAGES; None: all) while timing is on."""
+    names = STAGES if stages is None else stages
+    _check(lib().tabi_timing_stages(sum(1 << STAGES.index(s) for s in names)))
 
 
 def timing_reset():

@@ -95,6 +95,7 @@ enum Stage { ST_PREP = 0, ST_SORT, ST_SETUP, ST_PROFILE, ST_PACK, ST_SELECT, ST_
 struct Timing {
   std::mutex mu;
   bool on = false;
+  uint32_t mask = (1u << ST_COUNT) - 1;  // the stages bracketed while on
   struct Mark { int stage; hipEvent_t a, b; };
   std::vector<Mark> marks;
   std::vector<hipEvent_t> pool;
@@ -119,7 +120,7 @@ struct StageScope {  // brackets one stage's launches with a pair of events
   hipEvent_t a = nullptr;
   StageScope(int s_, hipStream_t st_) : stage(s_), st(st_) {
     std::lock_guard<std::mutex> lk(g_timing.mu);
-    if (!g_timing.on) return;
+    if (!g_timing.on || !((g_timing.mask >> s_) & 1u)) return;
     a = pool_event();
     if (a) (void)hipEventRecord(a, st);
   }
@@ -1005,6 +1006,13 @@ int tabi_debug_set_profile_cap(int64_t words) {
 int tabi_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_timing.mu);
   g_timing.on = on != 0;
+  return TABI_OK;
+}
+
+int tabi_timing_stages(uint32_t mask) {
+  if (mask == 0 || (mask >> ST_COUNT) != 0) return TABI_EINVAL;
+  std::lock_guard<std::mutex> lk(g_timing.mu);
+  g_timing.mask = mask;
   return TABI_OK;
 }
 

@@ -96,3 +96,20 @@ def test_serving_context_refuses_bad_arguments_on_the_host():
                          ctypes.byref(i64)) == tabi.TABI_EINVAL
     assert L.tabi_poll(None, 0, None, 0, ctypes.byref(i32)) == tabi.TABI_EINVAL
     assert L.tabi_ctx_destroy(None) == tabi.TABI_EINVAL
+
+
+def test_timing_stage_mask_is_checked_on_the_host():
+    """tabi_timing_stages takes a non-empty mask of the six stages (host
+    state only: no device work)."""
+    import paper_2602_07782_amd as tabi
+    if not os.path.exists(tabi.LIB_PATH):
+        pytest.skip("library not built")
+    L = tabi.lib()
+    hdr = open(os.path.join(ROOT, "include", "tabi.h")).read()
+    einval = int(re.search(r"TABI_EINVAL = (-?\d+)", hdr).group(1))
+    assert L.tabi_timing_stages(0) == einval
+    assert L.tabi_timing_stages(1 << 6) == einval
+    assert L.tabi_timing_stages(1 << tabi.STAGES.index("pack")) == 0
+    tabi.timing_stages(None)  # every stage again
+    with pytest.raises(RuntimeError):
+        tabi._check(L.tabi_timing_stages(0))
