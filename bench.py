@@ -434,15 +434,20 @@ TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profile
 
 
 def kernel_sources_sha256():
-    """Digest of the HIP sources the counters were taken from."""
+    """Digest of the HIP sources, and of the build script that holds their
+    compiler flags, that the counters were taken from."""
     import hashlib
-    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2602_07782_amd", "csrc")
+    pkg = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2602_07782_amd")
+    d = os.path.join(pkg, "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".h", ".cpp")):
             h.update(f.encode())
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(fh.read())
+    with open(os.path.join(pkg, "build.py"), "rb") as fh:
+        h.update(b"build.py")
+        h.update(fh.read())
     return h.hexdigest()
 
 
