@@ -367,17 +367,38 @@ __device__ void select_atlas(const Params& P, const Work& w, int round, int last
   else if (best >= 0) { kstar = slot_k(P, d, round, best); scale = (float)kstar / 64.0f; }
   else scale = 0.0f;
   const size_t slot = (size_t)(best >= 0 ? best : 0) * P.N;
-  for (int t = threadIdx.x; t < d.n; t += blockDim.x) {
-    const int c = d.c0 + t;
-    const int dst = d.c0 + w.perm[c];
-    if (kstar > 0 && best >= 0) {
-      out_xy[2 * (size_t)dst] = w.xs[slot + c];
-      out_xy[2 * (size_t)dst + 1] = w.ys[slot + c];
-      out_orient[dst] = (uint8_t)(w.srecs[c].bits | (w.mir[slot + c] << 3));
-    } else {
-      out_xy[2 * (size_t)dst] = -1;
-      out_xy[2 * (size_t)dst + 1] = -1;
-      out_orient[dst] = 0;
+  const bool placed = kstar > 0 && best >= 0;
+  // four charts per thread at a time: all their loads are issued before any
+  // of their stores (a store may alias a later load as far as the compiler
+  // knows, so a chart at a time would wait for its loads once per chart)
+  constexpr int U = 4;
+  for (int t0 = threadIdx.x; t0 < d.n; t0 += U * (int)blockDim.x) {
+    int dst[U];
+    int32_t x[U], y[U];
+    uint8_t o[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x;
+      dst[u] = -1;
+      x[u] = -1;
+      y[u] = -1;
+      o[u] = 0;
+      if (t < d.n) {
+        const int c = d.c0 + t;
+        dst[u] = d.c0 + w.perm[c];
+        if (placed) {
+          x[u] = w.xs[slot + c];
+          y[u] = w.ys[slot + c];
+          o[u] = (uint8_t)(w.srecs[c].bits | (w.mir[slot + c] << 3));
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (dst[u] < 0) continue;
+      out_xy[2 * (size_t)dst[u]] = x[u];
+      out_xy[2 * (size_t)dst[u] + 1] = y[u];
+      out_orient[dst[u]] = o[u];
     }
   }
   if (threadIdx.x == 0) {
