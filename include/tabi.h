@@ -446,6 +446,14 @@ int tabi_debug_phase_clock(int64_t* out, int32_t slots);
  * stored bounds from device memory; results are identical either way. */
 int tabi_debug_set_stage_cap(int32_t entries);
 
+/* Test knob: cap the packing kernel's shared memory for its rows at `bytes`,
+ * but never below the smallest plan (the frontline, one set of fold offsets
+ * and four configurations' offsets of a full row; -1 restores the default,
+ * the device's limit).  A smaller row pool stages fewer rows and folds fewer
+ * rows while the row before them commits (only rows that fit the second set
+ * of offsets at the pool's top are).  Results are identical either way. */
+int tabi_debug_set_pack_lds(int32_t bytes);
+
 /* Test knob: size of the per-call arena of stored per-texel profiles, in
  * 32-bit words (one per grown texel column or row of a chart at a scale;
  * -1 restores the default, 0 stores none).  Charts whose profiles do not fit

@@ -65,7 +65,7 @@ EXPORTS = ["tabi_pack", "tabi_pack_loops", "tabi_pack_prerotate", "tabi_pack_hyb
            "tabi_pack_many_records", "tabi_debug_order", "tabi_debug_pairs",
            "tabi_debug_feasible", "tabi_debug_phase_clock", "tabi_strerror", "tabi_last_hip_error", "tabi_pack_lds_bytes",
            "tabi_timing_enable", "tabi_timing_stages", "tabi_timing_read", "tabi_timing_reset",
-           "tabi_debug_set_stage_cap", "tabi_debug_set_profile_cap", "tabi_tune_many",
+           "tabi_debug_set_stage_cap", "tabi_debug_set_pack_lds", "tabi_debug_set_profile_cap", "tabi_tune_many",
            "tabi_many_shape", "tabi_many_shape_count", "tabi_debug_set_many_shape",
            "tabi_shutdown", "tabi_ctx_create", "tabi_ctx_destroy", "tabi_submit", "tabi_repack",
            "tabi_poll", "tabi_ctx_stats"]
@@ -118,6 +118,7 @@ def lib():
                                        ctypes.POINTER(ctypes.c_int32), i32]
         L.tabi_timing_reset.restype = None
         L.tabi_debug_set_stage_cap.argtypes = [i32]
+        L.tabi_debug_set_pack_lds.argtypes = [i32]
         L.tabi_debug_set_profile_cap.argtypes = [ctypes.c_int64]
         L.tabi_tune_many.argtypes = [vp, vp, vp, i32, vp, i32, i32, i32, i32, i32, vp, vp, vp, i32,
                                      vp, vp, vp]
@@ -516,6 +517,11 @@ def shutdown():
 def debug_set_stage_cap(entries):
     """Cap the pack kernel's per-row staging (-1 = default); results are unchanged."""
     _check(lib().tabi_debug_set_stage_cap(int(entries)))
+
+
+def debug_set_pack_lds(nbytes):
+    """Cap the pack kernel's row shared memory (-1 = default); results are unchanged."""
+    _check(lib().tabi_debug_set_pack_lds(int(nbytes)))
 
 
 def debug_set_profile_cap(words):

@@ -61,6 +61,7 @@ int kPackStaticLds = 32 * 1024;
 // test knobs: upper bound on the row staging area (texel columns) and on the
 // profile arena (32-bit words); < 0 = default
 int g_stage_cap = -1;
+int g_pack_lds = -1;
 int64_t g_profile_cap = -1;
 
 // Per-device set-up, once: the LDS a workgroup may use (the packing kernel is
@@ -299,6 +300,8 @@ int make_job(Job& j, const Params& P, hipStream_t st, void* ws = nullptr, size_t
     const PackLds c = pack_lds_plan(P.nmax, P.Wdmax, lds_cap);
     if (c.bytes <= lds_cap && c.PW >= 4 * c.RC + 3 * P.Wdmax) b = lds_cap;
   }
+  if (g_pack_lds >= 0)  // test knob: at most this much, at least the smallest plan
+    b = std::min(b, std::max(g_pack_lds, pack_lds_plan(P.nmax, P.Wdmax, 0).bytes));
   j.L = pack_lds_plan(P.nmax, P.Wdmax, b);
   if (j.L.bytes > b) return TABI_EINVAL;  // rows of this atlas cannot fit in LDS
   j.stage_cap = g_stage_cap >= 0 ? g_stage_cap : 0x7fffffff;
@@ -991,6 +994,11 @@ int tabi_debug_phase_clock(int64_t* out, int32_t slots) {
   const int r = read_phase_clock(out, slots);
   if (r == -2) return TABI_EINVAL;
   return r < 0 ? hip_fail(hipGetLastError()) : r;
+}
+
+int tabi_debug_set_pack_lds(int32_t bytes) {
+  g_pack_lds = bytes < 0 ? -1 : bytes;
+  return TABI_OK;
 }
 
 int tabi_debug_set_stage_cap(int32_t entries) {

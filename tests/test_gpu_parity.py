@@ -276,6 +276,42 @@ def test_pack_parity_without_row_staging(tabi, orc, cap):
         tabi.debug_set_stage_cap(-1)
 
 
+def test_pack_parity_with_the_smallest_row_pool(tabi, orc):
+    """The packing kernel's shared memory at its smallest plan: the row pool
+    holds four configurations' offsets of a full row and little more, so
+    only rows of at most about two thirds of the row capacity are folded
+    while the row before them commits (into the second set of offsets at the
+    pool's top) and larger ones after their opening barrier, and few rows are
+    staged.  Few charts in wide, low atlases put rows on both sides of that
+    limit.  Same results."""
+    mix = synth.CONFIGS["mixed2k"]["mix"]
+
+    def squares(nbig, ntiny):
+        # big squares sorted first: a row of three, then (with four) a row of
+        # one big and about 30 tiny ones, more than the limit of 29; with
+        # three, six or nine the knee rows after them hold a few tiny ones
+        sq = lambda x, y, s: np.array([[x, y], [x + s, y], [x + s, y + s], [x, y + s]]) * 256
+        polys = [sq(200 * i, 0, 40) for i in range(nbig)]
+        polys += [sq(200 * (nbig + i), 500, 3) for i in range(ntiny)]
+        xy, offs = synth.pack_csr(polys)
+        return synth.AtlasInput(xy, offs, 128, 128, 0, 2)
+
+    tabi.debug_set_pack_lds(0)
+    try:
+        for nbig, ntiny in ((4, 40), (3, 30), (6, 30), (9, 34)):
+            assert_pack_equal(tabi, orc, squares(nbig, ntiny), f"squares {nbig}+{ntiny} smallest pool")
+        for n, a, b in ((12, 60, 10), (16, 24, 6)):
+            inp = synth.rect_input(n, 256 * a, 256 * b, 512, 24, 0, seed=n + a)
+            assert_pack_equal(tabi, orc, inp, f"rects {n} x {a}x{b} smallest pool")
+        for seed in range(6):
+            inp = synth.make_custom(6 + 2 * seed, 256, 32, seed % 3, 2, 1.0, 0.7, mix, 8100 + seed)
+            assert_pack_equal(tabi, orc, inp, f"wide low {seed} smallest pool")
+        assert_pack_equal(tabi, orc, synth.make_input("stars64", 1), "stars64 smallest pool")
+        assert_pack_equal(tabi, orc, synth.make_input("mixed2k", 0), "mixed2k smallest pool")
+    finally:
+        tabi.debug_set_pack_lds(-1)
+
+
 @pytest.mark.parametrize("words", [0, 60000])
 def test_pack_parity_without_stored_profiles(tabi, orc, words):
     """Charts whose profiles do not fit the arena are evaluated from their
